@@ -1,0 +1,158 @@
+"""Throughput benchmark of the decoupled pose search on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batch512]
+
+One step is one pass of the search over one batch of synthetic scan pairs
+already resident in HBM: the forward search and, when the adjoint is built,
+its backward pass (fwd+bwd).  Prints one JSON line with the throughput in
+scan pairs per second, a live roofline entry for the dominant kernel (its
+per-launch algorithmic bytes over its average launch time, from HIP events
+recorded around every library launch in a second timed pass), and the FP64
+oracle timed on the host's cores on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, vendor figure
+FP32_PEAK_TFLOPS = 157.3     # MI355X vector FP32, vendor figure
+
+
+def kernel_bytes(n: int, n_theta: int, n_r: int, batch: int, masked: bool) -> dict:
+    """Algorithmic HBM bytes per launch of each kernel: compulsory reads of its
+    inputs plus writes of its outputs, each touched once (float32 / complex64)."""
+    N2 = n * n
+    nrb = (n_r + 7) // 8
+    hk = n_theta // 2 + 1
+    m = 2 if masked else 1
+    half = 2 * n * (n // 2) * 8            # both half spectra, complex64
+    mag = 2 * n * (n // 2 + 1) * 4          # both magnitude half-planes, float32
+    return {
+        "k_rows1": batch * (m * 2 * 4 * N2 + half),
+        "k_cols1": batch * (half + mag),
+        "k_polar": batch * (mag + nrb * hk * 8),
+        "k_angle_fin": batch * (nrb * hk * 8 + n_theta * 4),
+        "k_rows2": batch * (m * 2 * 4 * N2 + 2 * N2 * 8),
+        "k_cols2": batch * (2 * N2 * 8 + N2 * 8),
+        "k_rows3": batch * (N2 * 8 + N2 * 4),
+        "k_xy_fin": batch * 64,
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="batch512")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-pairs", type=int, default=4)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): each scan pair is "
+              "independent, so the batch would shard across GPUs with no exchange step; this "
+              "build measures the one-GPU share.", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2203_00459_amd import fmbym, synth, workloads
+
+    cfg = workloads.SEARCH[args.workload]
+    kw = workloads.search_kwargs(args.workload)
+    B, n, nt = cfg["batch"], cfg["n"], cfg["n_theta"]
+    dev = torch.device("cuda:0")
+    f_np, g_np, _ = synth.make_batch(args.workload, B, split="bench")
+    f = torch.from_numpy(f_np).to(dev)
+    g = torch.from_numpy(g_np).to(dev)
+    s = fmbym.Search(max_batch=B, **kw)
+    with_bwd = True
+    out = s.forward(f, g)
+    try:
+        s.backward(f, g, None, None, out, torch.ones(B, 3, device=dev))
+    except fmbym.FmbymError as e:
+        if e.code != fmbym.FMBYM_EUNSUPPORTED:
+            raise
+        with_bwd = False
+    d_pose = torch.ones(B, 3, device=dev)
+    torch.cuda.synchronize()
+
+    def step():
+        o = s.forward(f, g)
+        if with_bwd:
+            s.backward(f, g, None, None, o, d_pose)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+
+    # second timed pass: HIP events around every library launch, on its stream
+    fmbym.profile_enable(args.steps * 32)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    prof = fmbym.profile_read()
+    fmbym.profile_enable(0)
+    per_kernel = {k: (t / c) for k, (t, c) in prof.items()}
+    dom = max(prof, key=lambda k: prof[k][0])
+    kb = kernel_bytes(n, nt, n, B, masked=False)
+    achieved = kb[dom] / (per_kernel[dom] * 1e-3) / 1e9 if dom in kb else None
+
+    res = {
+        "metric": "scan-pairs/sec, 512^2 decoupled search fwd+bwd, 1 GPU" if with_bwd
+        else "scan-pairs/sec, decoupled search forward only (adjoint not built), 1 GPU",
+        "value": B / (ms * 1e-3),
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "batch": B, "n": n, "n_theta": nt,
+                   "pass": "fwd+bwd" if with_bwd else "fwd"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": None if achieved is None else achieved / HBM_PEAK_GBS,
+                     "traffic": None},
+        "kernels_ms": {k: round(v, 5) for k, v in sorted(per_kernel.items())},
+    }
+
+    if not args.no_cpu_baseline:
+        from oracle import fmbym_oracle as O
+        p = O.Params(**kw)
+        k = min(args.cpu_pairs, B)
+        t0 = time.perf_counter()
+        for b in range(k):
+            if with_bwd:
+                O.search_grad(f_np[b], g_np[b], [1.0, 1.0, 1.0], p)
+            else:
+                O.search(f_np[b], g_np[b], p)
+        dt = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": k / dt, "unit": "pairs/s", "cores": torch.get_num_threads(),
+                               "kind": "oracle",
+                               "sample": f"{k} of the {B} pairs, FP64 oracle "
+                                         f"{'forward + autograd backward' if with_bwd else 'forward'}"}
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

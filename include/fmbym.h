@@ -1,0 +1,126 @@
+/* fmbym.h - C ABI of the MI355X decoupled correlative pose search (Fast-MbyM).
+ *
+ * The library estimates the SE(2) pose between two Cartesian radar scans f and
+ * g, the problem of Section III-A: find theta, t with f(x) ~= g(R(theta) x + t)
+ * (Eq. 1).  It follows ScanMatch (Algorithm 1): the heading comes from the
+ * circular correlation of polar magnitude spectra along angle (Eq. 5-8), the
+ * translation from the 2-D correlation of f with g rotated by that heading
+ * (Eq. 9), both through temperature soft-argmaxes (Section III-D), optionally
+ * on masked scans f o m_f, g o m_g (Eq. 11).
+ *
+ * Conventions (shared by every entry point)
+ *   - Scans are float32, row-major [n][n]; row i is y = (i - n/2) delta_xy and
+ *     column j is x = (j - n/2) delta_xy metres; the sensor is pixel (n/2, n/2).
+ *   - pose[b] = {theta (rad), t_x (m), t_y (m)} satisfies Eq. 1.
+ *   - c_theta[b][k] is the heading score of lag l = k - n_theta/2, i.e. of the
+ *     candidate theta_l = l pi / n_theta.
+ *   - c_xy[b][i][j] is the translation score of lag (s_y, s_x) = (i - n/2, j - n/2)
+ *     pixels, the linear correlation sum_x f_w[x] g'[x + s].
+ *   - Forward DFTs are unnormalised; correlation values equal their defining sums.
+ *
+ * Memory and errors
+ *   - Every array argument is a DEVICE pointer, allocated and owned by the
+ *     caller; the library never allocates in the search calls and keeps no
+ *     reference after a call returns.  The plan owns only small constant
+ *     tables (twiddles, window) allocated by fmbym_plan_create.
+ *   - Every call is asynchronous on `stream` (a hipStream_t; NULL is the null
+ *     stream).  Arguments are validated on the host before anything is
+ *     enqueued; a call that returns an error has enqueued nothing.
+ *   - Return value: FMBYM_OK or a negative FMBYM_E* code.  Nothing throws or
+ *     prints.  Non-finite inputs propagate to the outputs.
+ *   - Calls on distinct plans/streams may run concurrently from different
+ *     threads; a workspace must not be shared by calls in flight.
+ */
+#ifndef FMBYM_H
+#define FMBYM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FMBYM_API __attribute__((visibility("default")))
+
+#define FMBYM_OK 0
+#define FMBYM_EINVAL (-1)       /* bad parameter or NULL required pointer          */
+#define FMBYM_EUNSUPPORTED (-2) /* size or flag combination not implemented        */
+#define FMBYM_EWORKSPACE (-3)   /* workspace NULL or smaller than required          */
+#define FMBYM_EHIP (-4)         /* HIP runtime error; see fmbym_last_hip_error()    */
+
+/* flags */
+#define FMBYM_HANN 1u           /* periodic Hann window on both scans (Algorithm 1) */
+#define FMBYM_XY_UNWINDOWED 8u  /* translation stage on the unwindowed scans        */
+
+/* floats per pair in the `saved` statistics buffer */
+#define FMBYM_SAVED 16
+
+typedef struct fmbym_plan_s* fmbym_plan;
+
+/* ScanMatch's parameter list (Algorithm 1) plus the band-pass of its stage 1. */
+typedef struct {
+    int32_t n;          /* scan side: 128, 256 or 512                                     */
+    int32_t n_theta;    /* angle bins over [0, pi): power of two, 16..1024; delta_theta = pi/n_theta */
+    int32_t n_r;        /* polar radii over [0, n/2) frequency bins: 1..4096 (the method uses n) */
+    float delta_xy;     /* metres per pixel (> 0)                                         */
+    float temp_theta;   /* heading softmax temperature T_theta (> 0)                      */
+    float temp_xy;      /* translation softmax temperature T_xy (> 0)                     */
+    float band_lo;      /* band-pass: keep lo <= |k|/n <= hi (cycles per pixel) ...       */
+    float band_hi;      /* ... disabled when band_hi <= 0                                  */
+    uint32_t flags;     /* FMBYM_HANN | FMBYM_XY_UNWINDOWED                                */
+} fmbym_params;
+
+/* Validate `p` and build a plan (uploads constant tables to the current device;
+ * this call allocates).  `max_batch` bounds the batch of later calls (>= 1). */
+FMBYM_API int fmbym_plan_create(const fmbym_params* p, int32_t max_batch, fmbym_plan* out);
+FMBYM_API int fmbym_plan_destroy(fmbym_plan plan);
+
+/* Bytes of device workspace needed by fmbym_search (with_backward = 0) or by
+ * fmbym_search_backward (with_backward = 1) for `batch` pairs; 0 on bad input. */
+FMBYM_API size_t fmbym_search_workspace_size(fmbym_plan plan, int32_t batch, int with_backward);
+
+/* Forward search (Algorithm 1 on Eq. 11's masked scans).
+ *   f, g      [batch][n][n]     scans (required)
+ *   m_f, m_g  [batch][n][n]     masks, or both NULL for the unmasked search
+ *   pose      [batch][3]        output (required)
+ *   c_theta   [batch][n_theta]  output heading scores, or NULL
+ *   c_xy      [batch][n][n]     output translation scores, or NULL
+ *   saved     [batch][FMBYM_SAVED]  output softmax statistics, or NULL
+ * c_theta, c_xy and saved are required if fmbym_search_backward will be called. */
+FMBYM_API int fmbym_search(fmbym_plan plan, int32_t batch, const float* f, const float* g,
+                 const float* m_f, const float* m_g, float* pose, float* c_theta, float* c_xy,
+                 float* saved, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Adjoint of fmbym_search: given d_pose = dL/dpose [batch][3], writes
+ * d_f, d_g (required) and d_m_f, d_m_g (required iff masks were given) as
+ * dL/d(input), all [batch][n][n], overwritten.  pose, c_theta, c_xy and saved
+ * are the outputs of the forward call on the same inputs.  The spectra are
+ * recomputed, not stored. */
+FMBYM_API int fmbym_search_backward(fmbym_plan plan, int32_t batch, const float* f, const float* g,
+                          const float* m_f, const float* m_g, const float* pose,
+                          const float* c_theta, const float* c_xy, const float* saved,
+                          const float* d_pose, float* d_f, float* d_g, float* d_m_f, float* d_m_g,
+                          void* workspace, size_t workspace_bytes, void* stream);
+
+/* Diagnostics: per-kernel timing.  fmbym_profile_enable(capacity) with
+ * capacity > 0 pre-creates `capacity` event pairs (it allocates) and brackets
+ * every later kernel launch of the library with two events on the launch's
+ * stream, until the pool is used up; capacity <= 0 switches timing off and
+ * frees the pool.  fmbym_profile_read synchronises the recorded events and
+ * fills, per kernel k < returned count: names[k], total_ms[k] (sum of launch
+ * durations) and launches[k].  Arrays must hold max_kernels >= 32 entries.
+ * Returns the kernel count, FMBYM_EWORKSPACE if the pool overflowed, or an
+ * error code.  Not for concurrent use from several threads. */
+FMBYM_API int fmbym_profile_enable(int32_t capacity);
+FMBYM_API int fmbym_profile_read(int32_t max_kernels, const char** names, double* total_ms,
+                                 int32_t* launches);
+
+FMBYM_API const char* fmbym_strerror(int code);
+/* hipError_t of the last FMBYM_EHIP returned on this thread (0 if none). */
+FMBYM_API int fmbym_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FMBYM_H */

@@ -1,0 +1,164 @@
+// C ABI of the search: plan construction, host-side validation, workspace
+// sizing and dispatch to the kernel launchers.  No call here throws; every
+// argument is checked before anything is enqueued.
+#include <math.h>
+#include <new>
+
+#include "internal.hpp"
+
+using namespace fmbym;
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+int hip_fail(hipError_t e) {
+    g_last_hip = (int)e;
+    return FMBYM_EHIP;
+}
+
+bool pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+int check_params(const fmbym_params* p) {
+    if (!p) return FMBYM_EINVAL;
+    if (!(p->delta_xy > 0.f) || !isfinite(p->delta_xy)) return FMBYM_EINVAL;
+    if (!(p->temp_theta > 0.f) || !isfinite(p->temp_theta)) return FMBYM_EINVAL;
+    if (!(p->temp_xy > 0.f) || !isfinite(p->temp_xy)) return FMBYM_EINVAL;
+    if (!isfinite(p->band_lo) || !isfinite(p->band_hi)) return FMBYM_EINVAL;
+    if (p->band_hi > 0.f && (p->band_lo < 0.f || p->band_lo > p->band_hi)) return FMBYM_EINVAL;
+    if (p->n <= 0 || p->n_theta <= 0 || p->n_r <= 0) return FMBYM_EINVAL;
+    if (p->flags & ~(uint32_t)(FMBYM_HANN | FMBYM_XY_UNWINDOWED)) return FMBYM_EUNSUPPORTED;
+    if (p->n != 128 && p->n != 256 && p->n != 512) return FMBYM_EUNSUPPORTED;
+    if (!pow2(p->n_theta) || p->n_theta < 16 || p->n_theta > 1024) return FMBYM_EUNSUPPORTED;
+    if (p->n_r > 4096) return FMBYM_EUNSUPPORTED;
+    return FMBYM_OK;
+}
+
+int check_call(fmbym_plan plan, int32_t batch) {
+    if (!plan) return FMBYM_EINVAL;
+    if (batch < 1 || batch > plan_cast(plan)->max_batch) return FMBYM_EINVAL;
+    return FMBYM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fmbym_plan_create(const fmbym_params* p, int32_t max_batch, fmbym_plan* out) {
+    if (!out) return FMBYM_EINVAL;
+    *out = nullptr;
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (max_batch < 1 || max_batch > (1 << 20)) return FMBYM_EINVAL;
+    Plan* pl = new (std::nothrow) Plan();
+    if (!pl) return FMBYM_EINVAL;
+    pl->p = *p;
+    pl->max_batch = max_batch;
+    hipError_t e = hipGetDevice(&pl->device);
+    if (e != hipSuccess) {
+        delete pl;
+        return hip_fail(e);
+    }
+    float2 tw[kTwiddleLen];
+    for (int m = 0; m < kTwiddleLen; ++m) {
+        const double a = -2.0 * M_PI * (double)m / (double)kTwiddleLen;
+        tw[m] = make_float2((float)cos(a), (float)sin(a));
+    }
+    float* hann = new (std::nothrow) float[p->n];
+    if (!hann) {
+        delete pl;
+        return FMBYM_EINVAL;
+    }
+    for (int k = 0; k < p->n; ++k) hann[k] = (float)(0.5 * (1.0 - cos(2.0 * M_PI * k / p->n)));
+    pl->band_on = p->band_hi > 0.f ? 1 : 0;
+    if (pl->band_on) {
+        const double lo = (double)p->band_lo * p->n, hi = (double)p->band_hi * p->n;
+        pl->band_lo2 = (int)ceil(lo * lo);
+        pl->band_hi2 = (int)floor(hi * hi);
+    }
+    e = hipMalloc((void**)&pl->twiddle, sizeof(tw));
+    if (e == hipSuccess) e = hipMalloc((void**)&pl->hann, sizeof(float) * p->n);
+    if (e == hipSuccess) e = hipMemcpy(pl->twiddle, tw, sizeof(tw), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(pl->hann, hann, sizeof(float) * p->n, hipMemcpyHostToDevice);
+    delete[] hann;
+    if (e != hipSuccess) {
+        if (pl->twiddle) (void)hipFree(pl->twiddle);
+        if (pl->hann) (void)hipFree(pl->hann);
+        delete pl;
+        return hip_fail(e);
+    }
+    *out = (fmbym_plan)pl;
+    return FMBYM_OK;
+}
+
+int fmbym_plan_destroy(fmbym_plan plan) {
+    if (!plan) return FMBYM_EINVAL;
+    Plan* pl = plan_cast(plan);
+    hipError_t e1 = hipFree(pl->twiddle);
+    hipError_t e2 = hipFree(pl->hann);
+    delete pl;
+    if (e1 != hipSuccess) return hip_fail(e1);
+    if (e2 != hipSuccess) return hip_fail(e2);
+    return FMBYM_OK;
+}
+
+size_t fmbym_search_workspace_size(fmbym_plan plan, int32_t batch, int with_backward) {
+    if (check_call(plan, batch)) return 0;
+    const Plan* pl = plan_cast(plan);
+    const size_t fwd = fwd_layout(pl->p, batch).total;
+    if (!with_backward) return fwd;
+    const size_t bwd = bwd_workspace(pl->p, batch);
+    return bwd > fwd ? bwd : fwd;
+}
+
+int fmbym_search(fmbym_plan plan, int32_t batch, const float* f, const float* g, const float* m_f,
+                 const float* m_g, float* pose, float* c_theta, float* c_xy, float* saved,
+                 void* workspace, size_t workspace_bytes, void* stream) {
+    int rc = check_call(plan, batch);
+    if (rc) return rc;
+    if (!f || !g || !pose) return FMBYM_EINVAL;
+    if ((m_f == nullptr) != (m_g == nullptr)) return FMBYM_EINVAL;
+    const Plan* pl = plan_cast(plan);
+    if (!workspace || workspace_bytes < fwd_layout(pl->p, batch).total) return FMBYM_EWORKSPACE;
+    rc = launch_forward(*pl, batch, f, g, m_f, m_g, pose, c_theta, c_xy, saved, (char*)workspace,
+                        (hipStream_t)stream);
+    if (rc) return rc;
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? FMBYM_OK : hip_fail(e);
+}
+
+int fmbym_search_backward(fmbym_plan plan, int32_t batch, const float* f, const float* g,
+                          const float* m_f, const float* m_g, const float* pose,
+                          const float* c_theta, const float* c_xy, const float* saved,
+                          const float* d_pose, float* d_f, float* d_g, float* d_m_f, float* d_m_g,
+                          void* workspace, size_t workspace_bytes, void* stream) {
+    int rc = check_call(plan, batch);
+    if (rc) return rc;
+    if (!f || !g || !pose || !c_theta || !c_xy || !saved || !d_pose || !d_f || !d_g)
+        return FMBYM_EINVAL;
+    if ((m_f == nullptr) != (m_g == nullptr)) return FMBYM_EINVAL;
+    if ((m_f == nullptr) != (d_m_f == nullptr) || (m_g == nullptr) != (d_m_g == nullptr))
+        return FMBYM_EINVAL;
+    const Plan* pl = plan_cast(plan);
+    if (!workspace || workspace_bytes < bwd_workspace(pl->p, batch)) return FMBYM_EWORKSPACE;
+    rc = launch_backward(*pl, batch, f, g, m_f, m_g, pose, c_theta, c_xy, saved, d_pose, d_f, d_g,
+                         d_m_f, d_m_g, (char*)workspace, (hipStream_t)stream);
+    if (rc) return rc;
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? FMBYM_OK : hip_fail(e);
+}
+
+const char* fmbym_strerror(int code) {
+    switch (code) {
+        case FMBYM_OK: return "success";
+        case FMBYM_EINVAL: return "invalid argument";
+        case FMBYM_EUNSUPPORTED: return "unsupported size or flag";
+        case FMBYM_EWORKSPACE: return "workspace missing or too small";
+        case FMBYM_EHIP: return "HIP runtime error";
+        default: return "unknown error code";
+    }
+}
+
+int fmbym_last_hip_error(void) { return g_last_hip; }
+
+}  // extern "C"

@@ -1,0 +1,224 @@
+// Device-side building blocks of the search kernels: complex helpers, radix-2/4/8
+// butterflies and a Stockham autosort FFT over one "line" held cooperatively by
+// T threads, each owning E = L/T elements in registers.  Lines exchange data
+// between stages through a padded LDS buffer (separate re/im planes).
+//
+// Register layout, on entry and on exit: thread t holds element t + m*T in v[m].
+// This is the layout of a coalesced global load/store of the line, so row
+// kernels load and store directly from/to registers and column kernels only
+// need the LDS transpose that the FFT stages already perform.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fmbym {
+
+constexpr int kTwiddleLen = 2048;   // table holds W_2048^m = exp(-2 pi i m / 2048)
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// conj(a) * b
+__device__ __forceinline__ float2 cmulcj(float2 a, float2 b) {
+    return make_float2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float2 mul_negi(float2 a) { return make_float2(a.y, -a.x); }   // a * (-i)
+
+// Forward butterflies, X[k] = sum_n v[n] exp(-2 pi i k n / R), in place.
+__device__ __forceinline__ void dft2(float2& a, float2& b) {
+    float2 t = a;
+    a = cadd(t, b);
+    b = csub(t, b);
+}
+
+__device__ __forceinline__ void dft4(float2& v0, float2& v1, float2& v2, float2& v3) {
+    float2 a0 = cadd(v0, v2), a1 = csub(v0, v2);
+    float2 a2 = cadd(v1, v3), a3 = mul_negi(csub(v1, v3));
+    v0 = cadd(a0, a2);
+    v2 = csub(a0, a2);
+    v1 = cadd(a1, a3);
+    v3 = csub(a1, a3);
+}
+
+__device__ __forceinline__ void dft8(float2 (&v)[8]) {
+    const float c = 0.70710678118654752440f;
+    float2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    float2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4(e0, e1, e2, e3);
+    dft4(o0, o1, o2, o3);
+    // o_k *= W8^k
+    float2 w1 = make_float2(c * (o1.x + o1.y), c * (o1.y - o1.x));
+    float2 w2 = mul_negi(o2);
+    float2 w3 = make_float2(c * (o3.y - o3.x), -c * (o3.x + o3.y));
+    v[0] = cadd(e0, o0);
+    v[4] = csub(e0, o0);
+    v[1] = cadd(e1, w1);
+    v[5] = csub(e1, w1);
+    v[2] = cadd(e2, w2);
+    v[6] = csub(e2, w2);
+    v[3] = cadd(e3, w3);
+    v[7] = csub(e3, w3);
+}
+
+template <int R>
+__device__ __forceinline__ void dft_r(float2 (&v)[R]);
+template <>
+__device__ __forceinline__ void dft_r<2>(float2 (&v)[2]) { dft2(v[0], v[1]); }
+template <>
+__device__ __forceinline__ void dft_r<4>(float2 (&v)[4]) { dft4(v[0], v[1], v[2], v[3]); }
+template <>
+__device__ __forceinline__ void dft_r<8>(float2 (&v)[8]) { dft8(v); }
+
+// Padded LDS index: one spare word every 32 keeps the strided Stockham
+// accesses spread over the banks.
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 5); }
+__host__ __device__ constexpr int lds_line_words(int L) { return L + L / 32; }
+
+constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
+
+// Radix of stage s for a length-L line with E elements per thread: radix E
+// while it divides what is left, the remainder (2 or 4) last.
+template <int L, int E, int S>
+struct StageRadix {
+    static constexpr int done = StageRadix<L, E, S - 1>::done * StageRadix<L, E, S - 1>::R;
+    static constexpr int left = L / done;
+    static constexpr int R = left >= E ? E : left;
+};
+template <int L, int E>
+struct StageRadix<L, E, 0> {
+    static constexpr int done = 1;
+    static constexpr int left = L;
+    static constexpr int R = L >= E ? E : L;
+};
+template <int L, int E>
+struct NumStages {
+    static constexpr int value = (ilog2c(L) + ilog2c(E) - 1) / ilog2c(E);
+};
+
+// One Stockham stage.  FIRST reads the inputs from registers, LAST writes the
+// outputs to registers; otherwise they go through the LDS line (re, im).
+template <int L, int E, int S, bool FIRST, bool LAST>
+__device__ __forceinline__ void fft_stage(float2 (&v)[E], float* re, float* im, int t,
+                                          const float2* __restrict__ tw) {
+    constexpr int T = L / E;
+    constexpr int R = StageRadix<L, E, S>::R;
+    constexpr int Ns = StageRadix<L, E, S>::done;
+    constexpr int Q = E / R;          // butterflies per thread
+    constexpr int LR = L / R;
+    float2 out[Q][R];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int j = t + q * T;
+        float2 x[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (FIRST) {
+                x[r] = v[q + r * Q];
+            } else {
+                const int idx = lpad(j + r * LR);
+                x[r] = make_float2(re[idx], im[idx]);
+            }
+        }
+        if (Ns > 1) {
+            const int k = j & (Ns - 1);
+            constexpr int step = kTwiddleLen / (Ns * R);
+#pragma unroll
+            for (int r = 1; r < R; ++r) x[r] = cmul(x[r], tw[r * k * step]);
+        }
+        dft_r<R>(x);
+#pragma unroll
+        for (int r = 0; r < R; ++r) out[q][r] = x[r];
+    }
+    if (!LAST) {
+        __syncthreads();   // every read of this stage is done before the line is overwritten
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int j = t + q * T;
+            const int k = j & (Ns - 1);
+            const int base = (j / Ns) * Ns * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int idx = lpad(base + r * Ns);
+                re[idx] = out[q][r].x;
+                im[idx] = out[q][r].y;
+            }
+        }
+        __syncthreads();
+    } else {
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[q + r * Q] = out[q][r];
+    }
+}
+
+template <int L, int E, int S, int NS>
+struct FFTStages {
+    __device__ __forceinline__ static void run(float2 (&v)[E], float* re, float* im, int t,
+                                               const float2* tw) {
+        fft_stage<L, E, S, S == 0, S == NS - 1>(v, re, im, t, tw);
+        FFTStages<L, E, S + 1, NS>::run(v, re, im, t, tw);
+    }
+};
+template <int L, int E, int NS>
+struct FFTStages<L, E, NS, NS> {
+    __device__ __forceinline__ static void run(float2 (&)[E], float*, float*, int, const float2*) {}
+};
+
+// Forward DFT of one line, in registers.  All threads of the block must call
+// it (it contains block barriers) even if their line is padding.
+template <int L, int E>
+__device__ __forceinline__ void fft_line(float2 (&v)[E], float* re, float* im, int t,
+                                         const float2* __restrict__ tw) {
+    static_assert((L & (L - 1)) == 0 && L >= 2 && L <= kTwiddleLen, "power-of-two length");
+    static_assert(E == 2 || E == 4 || E == 8, "elements per thread");
+    FFTStages<L, E, 0, NumStages<L, E>::value>::run(v, re, im, t, tw);
+}
+
+// Inverse (unnormalised) DFT: conj(DFT(conj(x))).
+template <int L, int E>
+__device__ __forceinline__ void ifft_line(float2 (&v)[E], float* re, float* im, int t,
+                                          const float2* __restrict__ tw) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m].y = -v[m].y;
+    fft_line<L, E>(v, re, im, t, tw);
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m].y = -v[m].y;
+}
+
+// Store the register line to LDS in natural order / read the mirror element
+// X[(L - k) mod L] of each held X[k].  Used to split the transforms of two real
+// sequences packed as x + i y.  Barriers included.
+template <int L, int E>
+__device__ __forceinline__ void mirror_line(const float2 (&v)[E], float2 (&mir)[E], float* re,
+                                            float* im, int t) {
+    constexpr int T = L / E;
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int idx = lpad(t + m * T);
+        re[idx] = v[m].x;
+        im[idx] = v[m].y;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int k = t + m * T;
+        const int idx = lpad((L - k) & (L - 1));
+        mir[m] = make_float2(re[idx], im[idx]);
+    }
+}
+
+// Z = DFT(x + i y) with x, y real: X[k] = (Z[k] + conj Z[-k]) / 2, Y[k] = (Z[k] - conj Z[-k]) / 2i.
+__device__ __forceinline__ float2 split_x(float2 z, float2 zm) {
+    return make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y));
+}
+__device__ __forceinline__ float2 split_y(float2 z, float2 zm) {
+    return make_float2(0.5f * (z.y + zm.y), -0.5f * (z.x - zm.x));
+}
+
+}  // namespace fmbym

@@ -1,0 +1,151 @@
+// Internal declarations shared by the search's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/fmbym.h"
+#include "fft_core.hpp"
+
+namespace fmbym {
+
+// Per-pair statistics kept in `saved` (FMBYM_SAVED floats).
+enum SavedSlot {
+    kSavedTheta = 0,      // heading soft-argmax (rad)
+    kSavedCos = 1,        // cos(theta), sin(theta): rounded once, reused by every later kernel
+    kSavedSin = 2,
+    kSavedThetaMax = 3,   // max of c_theta
+    kSavedThetaSum = 4,   // sum exp((c_theta - max) / T_theta)
+    kSavedXyMax = 5,      // max of c_xy
+    kSavedXySum = 6,      // sum exp((c_xy - max) / T_xy)
+    kSavedTpx = 7,        // t' (metres) before the frame change
+    kSavedTpy = 8,
+};
+
+struct Plan {
+    fmbym_params p;
+    int32_t max_batch;
+    int device;
+    float2* twiddle;   // [kTwiddleLen] W_2048^m
+    float* hann;       // [n] periodic Hann, FP64-evaluated, rounded once
+    int band_on;
+    int band_lo2;      // keep ceil((lo n)^2) <= ky^2 + kx^2 <= floor((hi n)^2)
+    int band_hi2;
+};
+
+inline Plan* plan_cast(fmbym_plan p) { return reinterpret_cast<Plan*>(p); }
+
+// Geometry of the polar-gather blocks.
+constexpr int kRadiiPerBlock = 8;
+inline int radius_blocks(int n_r) { return (n_r + kRadiiPerBlock - 1) / kRadiiPerBlock; }
+
+// Column pitch (floats) of the stored half-plane magnitude spectra [n][n/2 + 1].
+inline __host__ __device__ constexpr int mag_pitch(int n) { return n / 2 + 32; }
+
+// Rows per block of the stage-2 inverse-row kernel's softmax partials.
+inline int xy_partials_per_pair(int n) {
+    const int t = (2 * n) / 8;                 // threads per line
+    const int lines = 256 / t < 1 ? 1 : 256 / t;
+    return (n / 2) / lines;
+}
+
+// Workspace carve-up shared by forward and backward launchers.
+struct FwdLayout {
+    size_t r1r2;      // stage-1 row spectra, then stage-2 row spectra   [B][2][n][n]  float2
+    size_t mag_r3;    // magnitudes [B][2][n][pitch] float, then stage-2 columns [B][n][n] float2
+    size_t ptheta;    // [B][radius_blocks][n_theta/2 + 1] float2
+    size_t pxy;       // [B][xy_partials] float4
+    size_t saved;     // [B][FMBYM_SAVED] float (used when the caller passes none)
+    size_t total;
+};
+FwdLayout fwd_layout(const fmbym_params& p, int batch);
+
+int launch_forward(const Plan& pl, int batch, const float* f, const float* g, const float* mf,
+                   const float* mg, float* pose, float* c_theta, float* c_xy, float* saved,
+                   char* ws, hipStream_t s);
+
+size_t bwd_workspace(const fmbym_params& p, int batch);
+int launch_backward(const Plan& pl, int batch, const float* f, const float* g, const float* mf,
+                    const float* mg, const float* pose, const float* c_theta, const float* c_xy,
+                    const float* saved, const float* d_pose, float* d_f, float* d_g, float* d_mf,
+                    float* d_mg, char* ws, hipStream_t s);
+
+// ------------------------------------------------------------------ sampling
+
+// Windowed (and masked) scan value at an integer pixel.
+__device__ __forceinline__ float scan_w(const float* __restrict__ x, const float* __restrict__ m,
+                                        const float* __restrict__ hann, int n, int r, int c,
+                                        bool win) {
+    float v = x[r * n + c];
+    if (m) v *= m[r * n + c];
+    if (win) v *= hann[r] * hann[c];
+    return v;
+}
+
+// Source position of output pixel (i, j) under Rotate: R(theta) y about the centre.
+__device__ __forceinline__ void rot_src(int n, int i, int j, float ct, float st, float& py, float& px) {
+    const float yx = (float)(j - n / 2);
+    const float yy = (float)(i - n / 2);
+    px = ct * yx - st * yy + (float)(n / 2);
+    py = st * yx + ct * yy + (float)(n / 2);
+}
+
+// g'(i, j) = bilinear(g_w)(R(theta) y), lattice points outside the scan read as zero.
+__device__ __forceinline__ float rotate_sample(const float* __restrict__ g, const float* __restrict__ m,
+                                               const float* __restrict__ hann, int n, int i, int j,
+                                               float ct, float st, bool win) {
+    float py, px;
+    rot_src(n, i, j, ct, st, py, px);
+    const float fy = floorf(py), fx = floorf(px);
+    const float wy = py - fy, wx = px - fx;
+    const int y0 = (int)fy, x0 = (int)fx;
+    float acc = 0.f;
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy) {
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx) {
+            const int r = y0 + dy, c = x0 + dx;
+            if (r >= 0 && r < n && c >= 0 && c < n) {
+                const float w = (dy ? wy : 1.f - wy) * (dx ? wx : 1.f - wx);
+                acc += w * scan_w(g, m, hann, n, r, c, win);
+            }
+        }
+    }
+    return acc;
+}
+
+// Polar sample (radius b, angle a): frequency u = rho (cos phi, sin phi) in bins.
+__device__ __forceinline__ void polar_uv(const float2* __restrict__ tw, int n, int n_r, int n_theta,
+                                         int b, int a, float& uy, float& ux) {
+    const float rho = (float)((n / 2) * b) / (float)n_r;
+    const float2 w = tw[a * (kTwiddleLen / (2 * n_theta))];   // exp(-i pi a / n_theta)
+    ux = rho * w.x;
+    uy = rho * (-w.y);
+}
+
+// Bilinear read of a half-plane magnitude spectrum at (uy, ux), using
+// |F(-k)| = |F(k)| for corners with negative column and indices modulo n.
+__device__ __forceinline__ float mag_sample(const float* __restrict__ A, int n, float uy, float ux) {
+    const int P = mag_pitch(n);
+    const float fy = floorf(uy), fx = floorf(ux);
+    const float wy = uy - fy, wx = ux - fx;
+    const int y0 = (int)fy, x0 = (int)fx;
+    float acc = 0.f;
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy) {
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx) {
+            int ky = y0 + dy, kx = x0 + dx;
+            if (kx < 0) {
+                ky = -ky;
+                kx = -kx;
+            }
+            ky &= (n - 1);
+            const float w = (dy ? wy : 1.f - wy) * (dx ? wx : 1.f - wx);
+            acc += w * A[ky * P + kx];
+        }
+    }
+    return acc;
+}
+
+}  // namespace fmbym

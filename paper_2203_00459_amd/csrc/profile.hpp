@@ -1,0 +1,27 @@
+// Optional per-kernel timing: when enabled, every launch of the library is
+// bracketed by two HIP events on its stream.  Events come from a pool created
+// by fmbym_profile_enable, so the search calls still allocate nothing.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace fmbym {
+
+enum KernelId {
+    kKRows1 = 0, kKCols1, kKPolar, kKAngleFin, kKRows2, kKCols2, kKRows3, kKXyFin,
+    kKB0, kKB1, kKB2, kKB3, kKB4, kKB5, kKB6, kKB7, kKB8, kKB9, kKB10, kKB11,
+    kKernelCount
+};
+
+extern const char* const kKernelNames[kKernelCount];
+
+void prof_before(hipStream_t s, int id);
+void prof_after(hipStream_t s, int id);
+
+}  // namespace fmbym
+
+#define FMBYM_LAUNCH(id, kernel, grid, block, stream, ...)                     \
+    do {                                                                      \
+        ::fmbym::prof_before((stream), (id));                                 \
+        hipLaunchKernelGGL(kernel, grid, block, 0, stream, __VA_ARGS__);      \
+        ::fmbym::prof_after((stream), (id));                                  \
+    } while (0)

@@ -1,0 +1,592 @@
+// Forward decoupled search (Algorithm 1) on gfx950.
+//
+// Stage 1 (heading, Eq. 5-8)
+//   k_rows1      Hann (+mask) and row DFTs of f + i g, split into the two
+//                half spectra (one complex FFT serves both real scans).
+//   k_cols1      column DFTs of each half spectrum, band-pass and magnitude.
+//   k_polar      bilinear polar gather of both magnitude spectra, angular DFT
+//                per radius, conj(A_f) A_g summed over a block of radii.
+//   k_angle_fin  sum over radius blocks, inverse angular DFT -> c_theta,
+//                temperature softmax and soft-argmax -> theta (stays on device).
+// Stage 2 (translation, Eq. 9)
+//   k_rows2      f_w and g' = Rotate(g_w, theta) zero-padded to 2n, row DFTs.
+//   k_cols2      column DFTs of both, conj(F) G', inverse column DFT, keeping
+//                the n central lag rows.
+//   k_rows3      inverse row DFTs of two lag rows at a time -> c_xy, and
+//                online-softmax partials.
+//   k_xy_fin     fixed-order merge of the partials -> t' -> t = R(theta) t'.
+//
+// All reductions are in a fixed order; the result is bitwise reproducible.
+#include "internal.hpp"
+#include "profile.hpp"
+
+namespace fmbym {
+
+constexpr int kE = 8;   // elements per thread in every FFT line
+
+// ------------------------------------------------------------------ stage 1
+
+template <int N>
+__global__ __launch_bounds__(256) void k_rows1(const float* __restrict__ f, const float* __restrict__ g,
+                                               const float* __restrict__ mf, const float* __restrict__ mg,
+                                               const float* __restrict__ hann,
+                                               const float2* __restrict__ tw, float2* __restrict__ out,
+                                               int win) {
+    constexpr int L = N, T = L / kE, LPB = 256 / T, H = N / 2;
+    __shared__ float lre[LPB][lds_line_words(L)];
+    __shared__ float lim[LPB][lds_line_words(L)];
+    const int line = threadIdx.x / T, t = threadIdx.x % T;
+    const int grow = blockIdx.x * LPB + line;     // row over the batch
+    const int b = grow / N, i = grow % N;
+    const size_t off = (size_t)grow * N;
+    const float* fr = f + off;
+    const float* gr = g + off;
+    const float* mfr = mf ? mf + off : nullptr;
+    const float* mgr = mg ? mg + off : nullptr;
+    const float hi = win ? hann[i] : 1.f;
+    float2 v[kE];
+#pragma unroll
+    for (int m = 0; m < kE; ++m) {
+        const int x = t + m * T;
+        const float w = win ? hi * hann[x] : 1.f;
+        float a = fr[x], c = gr[x];
+        if (mfr) a *= mfr[x];
+        if (mgr) c *= mgr[x];
+        v[m] = make_float2(a * w, c * w);
+    }
+    fft_line<L, kE>(v, lre[line], lim[line], t, tw);
+    float2 mir[kE];
+    mirror_line<L, kE>(v, mir, lre[line], lim[line], t);
+    float2* of = out + ((size_t)(b * 2 + 0) * N + i) * H;
+    float2* og = out + ((size_t)(b * 2 + 1) * N + i) * H;
+#pragma unroll
+    for (int m = 0; m < kE / 2; ++m) {
+        const int k = t + m * T;
+        float2 X = split_x(v[m], mir[m]);
+        float2 Y = split_y(v[m], mir[m]);
+        if (k == 0) {   // F[0] and F[n/2] are real: pack them in one slot
+            const float2 Xn = split_x(v[kE / 2], mir[kE / 2]);
+            const float2 Yn = split_y(v[kE / 2], mir[kE / 2]);
+            X = make_float2(X.x, Xn.x);
+            Y = make_float2(Y.x, Yn.x);
+        }
+        of[k] = X;
+        og[k] = Y;
+    }
+}
+
+__device__ __forceinline__ float band_gain(int ky_signed, int kx, int on, int lo2, int hi2) {
+    if (!on) return 1.f;
+    const int r2 = ky_signed * ky_signed + kx * kx;
+    return (r2 >= lo2 && r2 <= hi2) ? 1.f : 0.f;
+}
+
+template <int N, int C>
+__global__ __launch_bounds__(C * N / kE) void k_cols1(const float2* __restrict__ in,
+                                                      float* __restrict__ A,
+                                                      const float2* __restrict__ tw, int band_on,
+                                                      int lo2, int hi2) {
+    constexpr int L = N, T = L / kE, H = N / 2, P = mag_pitch(N), TILES = H / C;
+    __shared__ float lre[C][lds_line_words(L)];
+    __shared__ float lim[C][lds_line_words(L)];
+    const int c = threadIdx.x % C, t = threadIdx.x / C;
+    const int tile = blockIdx.x % TILES, bs = blockIdx.x / TILES;   // bs = pair * 2 + scan
+    const int col = tile * C + c;
+    const float2* src = in + (size_t)bs * N * H;
+    float2 v[kE];
+#pragma unroll
+    for (int m = 0; m < kE; ++m) v[m] = src[(size_t)(t + m * T) * H + col];
+    fft_line<L, kE>(v, lre[c], lim[c], t, tw);
+    float* dst = A + (size_t)bs * N * P;
+    if (tile == 0) {   // column 0 packs the real DC and Nyquist columns: split them
+        float2 mir[kE];
+        mirror_line<L, kE>(v, mir, lre[c], lim[c], t);
+#pragma unroll
+        for (int m = 0; m < kE; ++m) {
+            const int ky = t + m * T;
+            const int kys = ky < H ? ky : ky - N;
+            if (c == 0) {
+                const float2 X0 = split_x(v[m], mir[m]);
+                const float2 XN = split_y(v[m], mir[m]);
+                dst[ky * P + 0] = sqrtf(X0.x * X0.x + X0.y * X0.y) * band_gain(kys, 0, band_on, lo2, hi2);
+                dst[ky * P + H] = sqrtf(XN.x * XN.x + XN.y * XN.y) * band_gain(kys, H, band_on, lo2, hi2);
+            } else {
+                dst[ky * P + col] =
+                    sqrtf(v[m].x * v[m].x + v[m].y * v[m].y) * band_gain(kys, col, band_on, lo2, hi2);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m < kE; ++m) {
+            const int ky = t + m * T;
+            const int kys = ky < H ? ky : ky - N;
+            dst[ky * P + col] =
+                sqrtf(v[m].x * v[m].x + v[m].y * v[m].y) * band_gain(kys, col, band_on, lo2, hi2);
+        }
+    }
+}
+
+// One block per (pair, block of kRadiiPerBlock radii); grid is remapped so
+// that all blocks of one pair run on the same XCD (its L2 keeps the pair's
+// magnitude spectra).
+template <int NT, int N>
+__global__ __launch_bounds__(256) void k_polar(const float* __restrict__ A,
+                                               const float2* __restrict__ tw,
+                                               float2* __restrict__ part, int n_r, int batch) {
+    constexpr int L = NT, T = L / kE, LPB = 256 / T, PASSES = (kRadiiPerBlock + LPB - 1) / LPB;
+    constexpr int HK = NT / 2 + 1;
+    __shared__ float lre[LPB][lds_line_words(L)];
+    __shared__ float lim[LPB][lds_line_words(L)];
+    const int nrb = (n_r + kRadiiPerBlock - 1) / kRadiiPerBlock;
+    const int total = batch * nrb;
+    // XCD-aware remap: hardware deals consecutive block ids round-robin over 8 XCDs
+    const int per_xcd = (total + 7) / 8;
+    const int work = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (work >= total) return;   // block-uniform
+    const int b = work / nrb, rb = work % nrb;
+    const int line = threadIdx.x / T, t = threadIdx.x % T;
+    const float* Af = A + (size_t)(b * 2 + 0) * N * mag_pitch(N);
+    const float* Ag = A + (size_t)(b * 2 + 1) * N * mag_pitch(N);
+    float2 acc[kE / 2 + 1];
+#pragma unroll
+    for (int m = 0; m <= kE / 2; ++m) acc[m] = make_float2(0.f, 0.f);
+    for (int pass = 0; pass < PASSES; ++pass) {
+        const int slot = pass * LPB + line;
+        const int rad = rb * kRadiiPerBlock + slot;
+        const bool live = slot < kRadiiPerBlock && rad < n_r;
+        float2 v[kE];
+#pragma unroll
+        for (int m = 0; m < kE; ++m) {
+            if (live) {
+                float uy, ux;
+                polar_uv(tw, N, n_r, NT, rad, t + m * T, uy, ux);
+                v[m] = make_float2(mag_sample(Af, N, uy, ux), mag_sample(Ag, N, uy, ux));
+            } else {
+                v[m] = make_float2(0.f, 0.f);
+            }
+        }
+        fft_line<L, kE>(v, lre[line], lim[line], t, tw);
+        float2 mir[kE];
+        mirror_line<L, kE>(v, mir, lre[line], lim[line], t);
+#pragma unroll
+        for (int m = 0; m <= kE / 2; ++m) {
+            const float2 Xf = split_x(v[m], mir[m]);
+            const float2 Xg = split_y(v[m], mir[m]);
+            acc[m] = cadd(acc[m], cmulcj(Xf, Xg));
+        }
+    }
+    // fixed-order sum over the lines of the block, through LDS
+    __syncthreads();
+    float* sre = &lre[0][0];
+    float* sim = &lim[0][0];
+    for (int m = 0; m <= kE / 2; ++m) {
+        const int k = t + m * T;
+        if (k < HK) {
+            sre[line * HK + k] = acc[m].x;
+            sim[line * HK + k] = acc[m].y;
+        }
+    }
+    __syncthreads();
+    float2* dst = part + ((size_t)b * nrb + rb) * HK;
+    for (int k = threadIdx.x; k < HK; k += blockDim.x) {
+        float2 s = make_float2(0.f, 0.f);
+        for (int l = 0; l < LPB; ++l) s = cadd(s, make_float2(sre[l * HK + k], sim[l * HK + k]));
+        dst[k] = s;
+    }
+}
+
+// Deterministic block reductions over blockDim.x (a power of two) values.
+__device__ __forceinline__ float block_max(float v, float* red) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    const float r = red[0];
+    __syncthreads();
+    return r;
+}
+__device__ __forceinline__ float block_sum(float v, float* red) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    const float r = red[0];
+    __syncthreads();
+    return r;
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT / kE) void k_angle_fin(const float2* __restrict__ part, int n_r,
+                                                       const float2* __restrict__ tw, float temp,
+                                                       float* __restrict__ c_theta,
+                                                       float* __restrict__ pose,
+                                                       float* __restrict__ saved) {
+    constexpr int L = NT, T = L / kE, HK = NT / 2 + 1;
+    __shared__ float lre[lds_line_words(L)];
+    __shared__ float lim[lds_line_words(L)];
+    __shared__ float red[T];
+    const int b = blockIdx.x, t = threadIdx.x;
+    const int nrb = (n_r + kRadiiPerBlock - 1) / kRadiiPerBlock;
+    const float2* src = part + (size_t)b * nrb * HK;
+    float2 v[kE];
+#pragma unroll
+    for (int m = 0; m < kE; ++m) {
+        const int k = t + m * T;
+        const int kk = k < HK ? k : NT - k;
+        float2 s = make_float2(0.f, 0.f);
+        for (int r = 0; r < nrb; ++r) s = cadd(s, src[(size_t)r * HK + kk]);
+        v[m] = k < HK ? s : cconj(s);
+    }
+    ifft_line<L, kE>(v, lre, lim, t, tw);
+    const float scale = 1.f / ((float)NT * (float)n_r);
+    float c[kE];
+    float lmax = -INFINITY;
+#pragma unroll
+    for (int m = 0; m < kE; ++m) {
+        c[m] = v[m].x * scale;
+        lmax = fmaxf(lmax, c[m]);
+    }
+    const float cmax = block_max(lmax, red);
+    const float inv_t = 1.f / temp;
+    float se = 0.f, sl = 0.f;
+#pragma unroll
+    for (int m = 0; m < kE; ++m) {
+        const int n = t + m * T;
+        const int lag = n < NT / 2 ? n : n - NT;
+        const float e = expf((c[m] - cmax) * inv_t);
+        se += e;
+        sl += e * (float)lag;
+        if (c_theta) c_theta[(size_t)b * NT + lag + NT / 2] = c[m];
+    }
+    const float Z = block_sum(se, red);
+    const float SL = block_sum(sl, red);
+    if (t == 0) {
+        const float theta = (SL / Z) * (3.14159265358979323846f / (float)NT);
+        pose[b * 3 + 0] = theta;
+        float* sv = saved + (size_t)b * FMBYM_SAVED;
+        sv[kSavedTheta] = theta;
+        float sn, cs;
+        sincosf(theta, &sn, &cs);
+        sv[kSavedCos] = cs;
+        sv[kSavedSin] = sn;
+        sv[kSavedThetaMax] = cmax;
+        sv[kSavedThetaSum] = Z;
+    }
+}
+
+// ------------------------------------------------------------------ stage 2
+
+template <int N>
+__global__ __launch_bounds__(256) void k_rows2(const float* __restrict__ f, const float* __restrict__ g,
+                                               const float* __restrict__ mf, const float* __restrict__ mg,
+                                               const float* __restrict__ hann,
+                                               const float2* __restrict__ tw,
+                                               const float* __restrict__ saved,
+                                               float2* __restrict__ out, int win) {
+    constexpr int L = 2 * N, T = L / kE, LPB = 256 / T;
+    __shared__ float lre[LPB][lds_line_words(L)];
+    __shared__ float lim[LPB][lds_line_words(L)];
+    const int line = threadIdx.x / T, t = threadIdx.x % T;
+    const int grow = blockIdx.x * LPB + line;
+    const int b = grow / N, i = grow % N;
+    const size_t base = (size_t)b * N * N;
+    const float ct = saved[(size_t)b * FMBYM_SAVED + kSavedCos];
+    const float st = saved[(size_t)b * FMBYM_SAVED + kSavedSin];
+    const float* gb = g + base;
+    const float* mgb = mg ? mg + base : nullptr;
+    float2 v[kE];
+#pragma unroll
+    for (int m = 0; m < kE; ++m) {
+        const int x = t + m * T;
+        if (m < kE / 2) {   // x < n: data; the upper half of the padded row is zero
+            const float a = scan_w(f + base, mf ? mf + base : nullptr, hann, N, i, x, win);
+            const float c = rotate_sample(gb, mgb, hann, N, i, x, ct, st, win);
+            v[m] = make_float2(a, c);
+        } else {
+            v[m] = make_float2(0.f, 0.f);
+        }
+    }
+    fft_line<L, kE>(v, lre[line], lim[line], t, tw);
+    float2 mir[kE];
+    mirror_line<L, kE>(v, mir, lre[line], lim[line], t);
+    float2* of = out + ((size_t)(b * 2 + 0) * N + i) * N;
+    float2* og = out + ((size_t)(b * 2 + 1) * N + i) * N;
+#pragma unroll
+    for (int m = 0; m < kE / 2; ++m) {
+        const int k = t + m * T;
+        float2 X = split_x(v[m], mir[m]);
+        float2 Y = split_y(v[m], mir[m]);
+        if (k == 0) {
+            const float2 Xn = split_x(v[kE / 2], mir[kE / 2]);
+            const float2 Yn = split_y(v[kE / 2], mir[kE / 2]);
+            X = make_float2(X.x, Xn.x);
+            Y = make_float2(Y.x, Yn.x);
+        }
+        of[k] = X;
+        og[k] = Y;
+    }
+}
+
+template <int N, int C>
+__global__ __launch_bounds__(C * 2 * N / kE) void k_cols2(const float2* __restrict__ in,
+                                                          const float2* __restrict__ tw,
+                                                          float2* __restrict__ out, int batch) {
+    constexpr int L = 2 * N, T = L / kE, TILES = N / C;
+    __shared__ float lre[C][lds_line_words(L)];
+    __shared__ float lim[C][lds_line_words(L)];
+    const int total = batch * TILES;
+    const int per_xcd = (total + 7) / 8;
+    const int work = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (work >= total) return;
+    const int c = threadIdx.x % C, t = threadIdx.x / C;
+    const int tile = work % TILES, b = work / TILES;
+    const int col = tile * C + c;
+    const float2* sf = in + (size_t)(b * 2 + 0) * N * N;
+    const float2* sg = in + (size_t)(b * 2 + 1) * N * N;
+    float2 vf[kE], vg[kE];
+#pragma unroll
+    for (int m = 0; m < kE; ++m) {
+        const int row = t + m * T;
+        if (m < kE / 2) {
+            vf[m] = sf[(size_t)row * N + col];
+            vg[m] = sg[(size_t)row * N + col];
+        } else {
+            vf[m] = make_float2(0.f, 0.f);
+            vg[m] = make_float2(0.f, 0.f);
+        }
+    }
+    fft_line<L, kE>(vf, lre[c], lim[c], t, tw);
+    fft_line<L, kE>(vg, lre[c], lim[c], t, tw);
+    float2 p[kE];
+    if (tile == 0) {   // column 0 packs the real DC and Nyquist columns of the padded rows
+        float2 mf_[kE], mg_[kE];
+        mirror_line<L, kE>(vf, mf_, lre[c], lim[c], t);
+        mirror_line<L, kE>(vg, mg_, lre[c], lim[c], t);
+#pragma unroll
+        for (int m = 0; m < kE; ++m) {
+            if (c == 0) {
+                const float2 p0 = cmulcj(split_x(vf[m], mf_[m]), split_x(vg[m], mg_[m]));
+                const float2 pn = cmulcj(split_y(vf[m], mf_[m]), split_y(vg[m], mg_[m]));
+                p[m] = make_float2(p0.x - pn.y, p0.y + pn.x);   // p0 + i pn
+            } else {
+                p[m] = cmulcj(vf[m], vg[m]);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m < kE; ++m) p[m] = cmulcj(vf[m], vg[m]);
+    }
+    ifft_line<L, kE>(p, lre[c], lim[c], t, tw);
+    float2* dst = out + (size_t)b * N * N;
+#pragma unroll
+    for (int m = 0; m < kE; ++m) {
+        const int n = t + m * T;                 // lag row s_y = n (n < N/2) or n - 2N (n >= 3N/2)
+        if (n < N / 2) dst[(size_t)(n + N / 2) * N + col] = p[m];
+        else if (n >= 3 * N / 2) dst[(size_t)(n - 3 * N / 2) * N + col] = p[m];
+    }
+}
+
+// Full 2n-point Hermitian spectrum entry k of a packed half row.
+__device__ __forceinline__ float2 herm_get(const float2* __restrict__ row, int N, int k) {
+    if (k == 0) return make_float2(row[0].x, 0.f);
+    if (k == N) return make_float2(row[0].y, 0.f);
+    if (k < N) return row[k];
+    return cconj(row[2 * N - k]);
+}
+
+template <int N>
+__global__ __launch_bounds__(256) void k_rows3(const float2* __restrict__ in,
+                                               const float2* __restrict__ tw,
+                                               float* __restrict__ c_xy, float4* __restrict__ part,
+                                               float temp) {
+    constexpr int L = 2 * N, T = L / kE, LPB = 256 / T, PPP = (N / 2) / LPB;
+    __shared__ float lre[LPB][lds_line_words(L)];
+    __shared__ float lim[LPB][lds_line_words(L)];
+    __shared__ float4 red[256];
+    const int line = threadIdx.x / T, t = threadIdx.x % T;
+    const int gl = blockIdx.x * LPB + line;       // row pair over the batch
+    const int b = gl / (N / 2), q = gl % (N / 2);
+    const float2* r1 = in + ((size_t)b * N + 2 * q) * N;
+    const float2* r2 = r1 + N;
+    float2 v[kE];
+#pragma unroll
+    for (int m = 0; m < kE; ++m) {
+        const int k = t + m * T;
+        const float2 h1 = herm_get(r1, N, k), h2 = herm_get(r2, N, k);
+        v[m] = make_float2(h1.x - h2.y, h1.y + h2.x);   // h1 + i h2
+    }
+    ifft_line<L, kE>(v, lre[line], lim[line], t, tw);
+    const float scale = 1.f / ((float)L * (float)L);
+    const float inv_t = 1.f / temp;
+    // kept lags: n < N/2 (m < kE/4) and n >= 3N/2 (m >= 3 kE/4)
+    float cv[2][kE / 2];
+    int sx[kE / 2];
+    float lmax = -INFINITY;
+#pragma unroll
+    for (int j = 0; j < kE / 2; ++j) {
+        const int m = j < kE / 4 ? j : j + kE / 2;
+        const int n = t + m * T;
+        const int col = n < N / 2 ? n + N / 2 : n - 3 * N / 2;
+        sx[j] = col - N / 2;
+        cv[0][j] = v[m].x * scale;
+        cv[1][j] = v[m].y * scale;
+        lmax = fmaxf(lmax, fmaxf(cv[0][j], cv[1][j]));
+        if (c_xy) {
+            c_xy[((size_t)b * N + 2 * q) * N + col] = cv[0][j];
+            c_xy[((size_t)b * N + 2 * q + 1) * N + col] = cv[1][j];
+        }
+    }
+    const float sy0 = (float)(2 * q - N / 2), sy1 = sy0 + 1.f;
+    float Z = 0.f, Sx = 0.f, Sy = 0.f;
+#pragma unroll
+    for (int j = 0; j < kE / 2; ++j) {
+        const float e0 = expf((cv[0][j] - lmax) * inv_t);
+        const float e1 = expf((cv[1][j] - lmax) * inv_t);
+        Z += e0 + e1;
+        Sx += (e0 + e1) * (float)sx[j];
+        Sy += e0 * sy0 + e1 * sy1;
+    }
+    red[threadIdx.x] = make_float4(lmax, Z, Sx, Sy);
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            const float4 a = red[threadIdx.x], c = red[threadIdx.x + s];
+            const float M = fmaxf(a.x, c.x);
+            const float ea = expf((a.x - M) * inv_t), ec = expf((c.x - M) * inv_t);
+            red[threadIdx.x] = make_float4(M, a.y * ea + c.y * ec, a.z * ea + c.z * ec, a.w * ea + c.w * ec);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(size_t)b * PPP + (blockIdx.x % PPP)] = red[0];
+}
+
+__global__ __launch_bounds__(64) void k_xy_fin(const float4* __restrict__ part, int ppp, float temp,
+                                               float delta, float* __restrict__ pose,
+                                               float* __restrict__ saved, int batch) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch) return;
+    const float inv_t = 1.f / temp;
+    const float4* p = part + (size_t)b * ppp;
+    float M = -INFINITY;
+    for (int i = 0; i < ppp; ++i) M = fmaxf(M, p[i].x);
+    float Z = 0.f, Sx = 0.f, Sy = 0.f;
+    for (int i = 0; i < ppp; ++i) {
+        const float e = expf((p[i].x - M) * inv_t);
+        Z += p[i].y * e;
+        Sx += p[i].z * e;
+        Sy += p[i].w * e;
+    }
+    float* sv = saved + (size_t)b * FMBYM_SAVED;
+    const float tpx = delta * (Sx / Z), tpy = delta * (Sy / Z);
+    const float ct = sv[kSavedCos], st = sv[kSavedSin];
+    pose[b * 3 + 1] = ct * tpx - st * tpy;
+    pose[b * 3 + 2] = st * tpx + ct * tpy;
+    sv[kSavedXyMax] = M;
+    sv[kSavedXySum] = Z;
+    sv[kSavedTpx] = tpx;
+    sv[kSavedTpy] = tpy;
+}
+
+// ---------------------------------------------------------------- launcher
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+FwdLayout fwd_layout(const fmbym_params& p, int batch) {
+    const size_t n = p.n, B = batch;
+    FwdLayout L{};
+    size_t off = 0;
+    L.r1r2 = off;
+    off = align256(off + B * 2 * n * n * sizeof(float2));
+    L.mag_r3 = off;
+    const size_t mag = B * 2 * n * (size_t)mag_pitch(p.n) * sizeof(float);
+    const size_t r3 = B * n * n * sizeof(float2);
+    off = align256(off + (mag > r3 ? mag : r3));
+    L.ptheta = off;
+    off = align256(off + B * (size_t)radius_blocks(p.n_r) * (p.n_theta / 2 + 1) * sizeof(float2));
+    L.pxy = off;
+    off = align256(off + B * (size_t)xy_partials_per_pair(p.n) * sizeof(float4));
+    L.saved = off;
+    off = align256(off + B * FMBYM_SAVED * sizeof(float));
+    L.total = off;
+    return L;
+}
+
+template <int N>
+static void launch_stage1_rows_cols(const Plan& pl, int B, const float* f, const float* g,
+                                    const float* mf, const float* mg, float2* r1, float* mag,
+                                    hipStream_t s) {
+    const int win = (pl.p.flags & FMBYM_HANN) ? 1 : 0;
+    constexpr int T1 = N / kE, LPB1 = 256 / T1;
+    FMBYM_LAUNCH(kKRows1, k_rows1<N>, dim3(B * N / LPB1), dim3(256), s, f, g, mf, mg, pl.hann,
+                       pl.twiddle, r1, win);
+    constexpr int C = 16;
+    FMBYM_LAUNCH(kKCols1, (k_cols1<N, C>), dim3(B * 2 * (N / 2) / C), dim3(C * N / kE), s, r1, mag,
+                       pl.twiddle, pl.band_on, pl.band_lo2, pl.band_hi2);
+}
+
+template <int N, int NT>
+static void launch_polar(const Plan& pl, int B, const float* mag, float2* pth, float* c_theta,
+                         float* pose, float* saved, hipStream_t s) {
+    const int nrb = radius_blocks(pl.p.n_r);
+    const int total = B * nrb;
+    const int grid = ((total + 7) / 8) * 8;
+    FMBYM_LAUNCH(kKPolar, (k_polar<NT, N>), dim3(grid), dim3(256), s, mag, pl.twiddle, pth, pl.p.n_r, B);
+    FMBYM_LAUNCH(kKAngleFin, k_angle_fin<NT>, dim3(B), dim3(NT / kE), s, pth, pl.p.n_r, pl.twiddle,
+                       pl.p.temp_theta, c_theta, pose, saved);
+}
+
+template <int N>
+static int launch_n(const Plan& pl, int B, const float* f, const float* g, const float* mf,
+                    const float* mg, float* pose, float* c_theta, float* c_xy, float* saved,
+                    char* ws, hipStream_t s) {
+    const FwdLayout lay = fwd_layout(pl.p, B);
+    float2* r1 = (float2*)(ws + lay.r1r2);
+    float* mag = (float*)(ws + lay.mag_r3);
+    float2* pth = (float2*)(ws + lay.ptheta);
+    float4* pxy = (float4*)(ws + lay.pxy);
+    float* sv = saved ? saved : (float*)(ws + lay.saved);
+    launch_stage1_rows_cols<N>(pl, B, f, g, mf, mg, r1, mag, s);
+    switch (pl.p.n_theta) {
+        case 16: launch_polar<N, 16>(pl, B, mag, pth, c_theta, pose, sv, s); break;
+        case 32: launch_polar<N, 32>(pl, B, mag, pth, c_theta, pose, sv, s); break;
+        case 64: launch_polar<N, 64>(pl, B, mag, pth, c_theta, pose, sv, s); break;
+        case 128: launch_polar<N, 128>(pl, B, mag, pth, c_theta, pose, sv, s); break;
+        case 256: launch_polar<N, 256>(pl, B, mag, pth, c_theta, pose, sv, s); break;
+        case 512: launch_polar<N, 512>(pl, B, mag, pth, c_theta, pose, sv, s); break;
+        case 1024: launch_polar<N, 1024>(pl, B, mag, pth, c_theta, pose, sv, s); break;
+        default: return FMBYM_EUNSUPPORTED;
+    }
+    const int win2 = ((pl.p.flags & FMBYM_HANN) && !(pl.p.flags & FMBYM_XY_UNWINDOWED)) ? 1 : 0;
+    float2* r2 = r1;                    // stage-1 rows are dead after k_cols1
+    float2* r3 = (float2*)mag;          // magnitudes are dead after k_polar
+    constexpr int T2 = 2 * N / kE, LPB2 = 256 / T2;
+    FMBYM_LAUNCH(kKRows2, k_rows2<N>, dim3(B * N / LPB2), dim3(256), s, f, g, mf, mg, pl.hann,
+                       pl.twiddle, sv, r2, win2);
+    constexpr int C2 = N >= 512 ? 8 : 16;
+    const int total2 = B * (N / C2);
+    FMBYM_LAUNCH(kKCols2, (k_cols2<N, C2>), dim3(((total2 + 7) / 8) * 8), dim3(C2 * 2 * N / kE), s, r2,
+                       pl.twiddle, r3, B);
+    constexpr int LPB3 = 256 / T2;
+    FMBYM_LAUNCH(kKRows3, k_rows3<N>, dim3(B * (N / 2) / LPB3), dim3(256), s, r3, pl.twiddle, c_xy,
+                       pxy, pl.p.temp_xy);
+    FMBYM_LAUNCH(kKXyFin, k_xy_fin, dim3((B + 63) / 64), dim3(64), s, pxy, xy_partials_per_pair(N),
+                       pl.p.temp_xy, pl.p.delta_xy, pose, sv, B);
+    return FMBYM_OK;
+}
+
+int launch_forward(const Plan& pl, int batch, const float* f, const float* g, const float* mf,
+                   const float* mg, float* pose, float* c_theta, float* c_xy, float* saved,
+                   char* ws, hipStream_t s) {
+    switch (pl.p.n) {
+        case 128: return launch_n<128>(pl, batch, f, g, mf, mg, pose, c_theta, c_xy, saved, ws, s);
+        case 256: return launch_n<256>(pl, batch, f, g, mf, mg, pose, c_theta, c_xy, saved, ws, s);
+        case 512: return launch_n<512>(pl, batch, f, g, mf, mg, pose, c_theta, c_xy, saved, ws, s);
+        default: return FMBYM_EUNSUPPORTED;
+    }
+}
+
+}  // namespace fmbym

@@ -1,0 +1,244 @@
+"""Thin Python binding of libfmbym.so (C ABI in include/fmbym.h).
+
+The functions with the C names only marshal arguments: every step of the
+search runs in the library's HIP kernels.  ``Search`` adds the plumbing a
+PyTorch caller wants (output and workspace tensors on the current stream), and
+``SearchFunction`` exposes the hand-written adjoint to autograd.  There is no
+fallback: if the library is missing this module raises on first use.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfmbym.so")
+
+FMBYM_OK = 0
+FMBYM_EINVAL = -1
+FMBYM_EUNSUPPORTED = -2
+FMBYM_EWORKSPACE = -3
+FMBYM_EHIP = -4
+FMBYM_HANN = 1
+FMBYM_XY_UNWINDOWED = 8
+FMBYM_SAVED = 16
+
+EXPORTS = (
+    "fmbym_plan_create", "fmbym_plan_destroy", "fmbym_search_workspace_size", "fmbym_search",
+    "fmbym_search_backward", "fmbym_strerror", "fmbym_last_hip_error", "fmbym_profile_enable",
+    "fmbym_profile_read",
+)
+
+
+class fmbym_params(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32), ("n_theta", ctypes.c_int32), ("n_r", ctypes.c_int32),
+        ("delta_xy", ctypes.c_float), ("temp_theta", ctypes.c_float), ("temp_xy", ctypes.c_float),
+        ("band_lo", ctypes.c_float), ("band_hi", ctypes.c_float), ("flags", ctypes.c_uint32),
+    ]
+
+
+class FmbymError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = f"{where}: {strerror(code)} ({code})"
+        if code == FMBYM_EHIP:
+            msg += f", hipError {last_hip_error()}"
+        super().__init__(msg)
+        self.code = code
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load the library (torch's HIP runtime is already in the process)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2203_00459_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, VP, SZ, I32 = ctypes.POINTER(fmbym_params), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32
+        L.fmbym_plan_create.argtypes = [P, I32, ctypes.POINTER(VP)]
+        L.fmbym_plan_create.restype = ctypes.c_int
+        L.fmbym_plan_destroy.argtypes = [VP]
+        L.fmbym_plan_destroy.restype = ctypes.c_int
+        L.fmbym_search_workspace_size.argtypes = [VP, I32, ctypes.c_int]
+        L.fmbym_search_workspace_size.restype = SZ
+        L.fmbym_search.argtypes = [VP, I32] + [VP] * 8 + [VP, SZ, VP]
+        L.fmbym_search.restype = ctypes.c_int
+        L.fmbym_search_backward.argtypes = [VP, I32] + [VP] * 13 + [VP, SZ, VP]
+        L.fmbym_search_backward.restype = ctypes.c_int
+        L.fmbym_strerror.argtypes = [ctypes.c_int]
+        L.fmbym_strerror.restype = ctypes.c_char_p
+        L.fmbym_last_hip_error.argtypes = []
+        L.fmbym_last_hip_error.restype = ctypes.c_int
+        L.fmbym_profile_enable.argtypes = [I32]
+        L.fmbym_profile_enable.restype = ctypes.c_int
+        L.fmbym_profile_read.argtypes = [I32, ctypes.POINTER(ctypes.c_char_p),
+                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I32)]
+        L.fmbym_profile_read.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+# ------------------------------------------------------------ C-named calls
+
+def strerror(code: int) -> str:
+    return lib().fmbym_strerror(int(code)).decode()
+
+
+def last_hip_error() -> int:
+    return int(lib().fmbym_last_hip_error())
+
+
+def plan_create(params: fmbym_params, max_batch: int) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    rc = lib().fmbym_plan_create(ctypes.byref(params), int(max_batch), ctypes.byref(h))
+    if rc:
+        raise FmbymError(rc, "fmbym_plan_create")
+    return h
+
+
+def plan_destroy(plan) -> None:
+    rc = lib().fmbym_plan_destroy(plan)
+    if rc:
+        raise FmbymError(rc, "fmbym_plan_destroy")
+
+
+def search_workspace_size(plan, batch: int, with_backward: bool) -> int:
+    return int(lib().fmbym_search_workspace_size(plan, int(batch), int(bool(with_backward))))
+
+
+def search(plan, batch, f, g, m_f, m_g, pose, c_theta, c_xy, saved, workspace, workspace_bytes,
+           stream) -> None:
+    """fmbym_search with raw device addresses (ints or None)."""
+    rc = lib().fmbym_search(plan, int(batch), f, g, m_f, m_g, pose, c_theta, c_xy, saved, workspace,
+                            int(workspace_bytes), stream)
+    if rc:
+        raise FmbymError(rc, "fmbym_search")
+
+
+def search_backward(plan, batch, f, g, m_f, m_g, pose, c_theta, c_xy, saved, d_pose, d_f, d_g,
+                    d_m_f, d_m_g, workspace, workspace_bytes, stream) -> None:
+    rc = lib().fmbym_search_backward(plan, int(batch), f, g, m_f, m_g, pose, c_theta, c_xy, saved,
+                                     d_pose, d_f, d_g, d_m_f, d_m_g, workspace, int(workspace_bytes),
+                                     stream)
+    if rc:
+        raise FmbymError(rc, "fmbym_search_backward")
+
+
+def profile_enable(capacity: int) -> None:
+    rc = lib().fmbym_profile_enable(int(capacity))
+    if rc:
+        raise FmbymError(rc, "fmbym_profile_enable")
+
+
+def profile_read() -> dict:
+    """{kernel name: (total ms, launches)} for kernels launched since profile_enable."""
+    K = 32
+    names = (ctypes.c_char_p * K)()
+    ms = (ctypes.c_double * K)()
+    cnt = (ctypes.c_int32 * K)()
+    rc = lib().fmbym_profile_read(K, names, ms, cnt)
+    if rc < 0:
+        raise FmbymError(rc, "fmbym_profile_read")
+    return {names[k].decode(): (ms[k], cnt[k]) for k in range(rc) if cnt[k] > 0}
+
+
+# ------------------------------------------------------------------ plumbing
+
+def _ptr(t: torch.Tensor | None, shape=None, name=""):
+    if t is None:
+        return None
+    if t.device.type != "cuda" or t.dtype != torch.float32 or not t.is_contiguous():
+        raise ValueError(f"{name}: expected a contiguous float32 device tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t.data_ptr()
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+class Search:
+    """A plan plus torch-allocated outputs and workspace for one parameter set."""
+
+    def __init__(self, n: int, n_theta: int, n_r: int | None = None, delta_xy: float = 1.0,
+                 temp_theta: float = 1.0, temp_xy: float = 1.0, band_lo: float = 0.0,
+                 band_hi: float = 0.0, hann: bool = True, xy_unwindowed: bool = False,
+                 max_batch: int = 64):
+        flags = (FMBYM_HANN if hann else 0) | (FMBYM_XY_UNWINDOWED if xy_unwindowed else 0)
+        self.params = fmbym_params(n, n_theta, n if n_r is None else n_r, delta_xy, temp_theta,
+                                   temp_xy, band_lo, band_hi, flags)
+        self.n, self.n_theta, self.max_batch = n, n_theta, max_batch
+        self.plan = plan_create(self.params, max_batch)
+        self._ws = None
+
+    def close(self):
+        if self.plan is not None:
+            plan_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace(self, batch: int, with_backward: bool, device) -> torch.Tensor:
+        need = search_workspace_size(self.plan, batch, with_backward)
+        if need == 0:
+            raise FmbymError(FMBYM_EINVAL, "fmbym_search_workspace_size")
+        if self._ws is None or self._ws.numel() < need or self._ws.device != device:
+            self._ws = torch.empty(need, dtype=torch.uint8, device=device)
+        return self._ws
+
+    def forward(self, f, g, m_f=None, m_g=None, surfaces: bool = True) -> dict:
+        B, n = f.shape[0], self.n
+        dev = f.device
+        out = dict(pose=torch.empty(B, 3, device=dev),
+                   c_theta=torch.empty(B, self.n_theta, device=dev) if surfaces else None,
+                   c_xy=torch.empty(B, n, n, device=dev) if surfaces else None,
+                   saved=torch.empty(B, FMBYM_SAVED, device=dev))
+        ws = self.workspace(B, False, dev)
+        search(self.plan, B, _ptr(f, (B, n, n), "f"), _ptr(g, (B, n, n), "g"),
+               _ptr(m_f, (B, n, n), "m_f"), _ptr(m_g, (B, n, n), "m_g"), _ptr(out["pose"]),
+               _ptr(out["c_theta"]), _ptr(out["c_xy"]), _ptr(out["saved"]), ws.data_ptr(),
+               ws.numel(), _stream())
+        return out
+
+    def backward(self, f, g, m_f, m_g, fwd: dict, d_pose) -> dict:
+        B, n = f.shape[0], self.n
+        dev = f.device
+        res = dict(d_f=torch.empty(B, n, n, device=dev), d_g=torch.empty(B, n, n, device=dev),
+                   d_m_f=None if m_f is None else torch.empty(B, n, n, device=dev),
+                   d_m_g=None if m_g is None else torch.empty(B, n, n, device=dev))
+        ws = self.workspace(B, True, dev)
+        search_backward(self.plan, B, _ptr(f, (B, n, n), "f"), _ptr(g, (B, n, n), "g"),
+                        _ptr(m_f, (B, n, n), "m_f"), _ptr(m_g, (B, n, n), "m_g"),
+                        _ptr(fwd["pose"]), _ptr(fwd["c_theta"]), _ptr(fwd["c_xy"]),
+                        _ptr(fwd["saved"]), _ptr(d_pose.contiguous(), (B, 3), "d_pose"),
+                        _ptr(res["d_f"]), _ptr(res["d_g"]), _ptr(res["d_m_f"]), _ptr(res["d_m_g"]),
+                        ws.data_ptr(), ws.numel(), _stream())
+        return res
+
+
+class SearchFunction(torch.autograd.Function):
+    """pose = search(f, g[, m_f, m_g]) with the library's hand-written adjoint."""
+
+    @staticmethod
+    def forward(ctx, searcher: Search, f, g, m_f=None, m_g=None):
+        out = searcher.forward(f, g, m_f, m_g, surfaces=True)
+        ctx.searcher = searcher
+        ctx.fwd = out
+        ctx.save_for_backward(f, g, m_f, m_g)
+        return out["pose"]
+
+    @staticmethod
+    def backward(ctx, d_pose):
+        f, g, m_f, m_g = ctx.saved_tensors
+        r = ctx.searcher.backward(f, g, m_f, m_g, ctx.fwd, d_pose)
+        return None, r["d_f"], r["d_g"], r["d_m_f"], r["d_m_g"]

@@ -1,0 +1,25 @@
+"""Search parameter sets of the measured workloads (plain numbers, no arithmetic).
+
+Each entry pairs a scene family of ``synth.WORKLOADS`` with ScanMatch's
+parameters (Algorithm 1).  The band-pass is a hard annulus in cycles per pixel;
+its cut-offs are not given by the method and are a reading of this library.
+"""
+
+SEARCH = {
+    # one pair, 128 x 128, 128 angle bins, both temperatures 1, forward only
+    "pair128": dict(batch=1, n=128, n_theta=128, delta_xy=0.5, temp_theta=1.0, temp_xy=1.0,
+                    band_lo=0.02, band_hi=0.40),
+    # 64 pairs, 256 x 256, 256 angle bins
+    "batch256": dict(batch=64, n=256, n_theta=256, delta_xy=0.35, temp_theta=1.0, temp_xy=1.0,
+                     band_lo=0.02, band_hi=0.40),
+    # 32 pairs, 512 x 512, 512 angle bins, forward and adjoint (the headline workload)
+    "batch512": dict(batch=32, n=512, n_theta=512, delta_xy=0.2, temp_theta=1.0, temp_xy=1.0,
+                     band_lo=0.02, band_hi=0.40),
+}
+
+
+def search_kwargs(name: str) -> dict:
+    """Keyword arguments shared by the library's Search and the oracle's Params."""
+    d = dict(SEARCH[name])
+    d.pop("batch")
+    return d

@@ -1,0 +1,84 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared
+symbol, and rejects bad arguments before touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2203_00459_amd import fmbym
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fmbym.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"FMBYM_API\s+[\w\s\*]+?\b(fmbym_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_binding_names():
+    assert declared_symbols() == sorted(fmbym.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = fmbym.lib()
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+    out = os.popen(f"nm -D --defined-only {fmbym.LIB_PATH}").read()
+    exported = set(re.findall(r"\bT (\w+)", out))
+    assert set(declared_symbols()) <= exported
+    assert all(s.startswith("fmbym_") for s in exported if not s.startswith("_")), \
+        sorted(s for s in exported if not s.startswith("fmbym_"))
+
+
+def test_strerror():
+    assert fmbym.strerror(0) == "success"
+    assert "invalid" in fmbym.strerror(fmbym.FMBYM_EINVAL)
+    assert "workspace" in fmbym.strerror(fmbym.FMBYM_EWORKSPACE)
+    assert fmbym.strerror(12345) == "unknown error code"
+
+
+GOOD = dict(n=128, n_theta=128, n_r=128, delta_xy=0.5, temp_theta=1.0, temp_xy=1.0, band_lo=0.02,
+            band_hi=0.4, flags=fmbym.FMBYM_HANN)
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("n", 100, fmbym.FMBYM_EUNSUPPORTED),
+    ("n", 0, fmbym.FMBYM_EINVAL),
+    ("n_theta", 100, fmbym.FMBYM_EUNSUPPORTED),
+    ("n_theta", 2048, fmbym.FMBYM_EUNSUPPORTED),
+    ("n_r", 0, fmbym.FMBYM_EINVAL),
+    ("n_r", 5000, fmbym.FMBYM_EUNSUPPORTED),
+    ("delta_xy", 0.0, fmbym.FMBYM_EINVAL),
+    ("temp_theta", -1.0, fmbym.FMBYM_EINVAL),
+    ("temp_xy", float("nan"), fmbym.FMBYM_EINVAL),
+    ("band_lo", 0.5, fmbym.FMBYM_EINVAL),
+    ("flags", 1 << 9, fmbym.FMBYM_EUNSUPPORTED),
+])
+def test_plan_create_rejects_bad_parameters(field, value, code):
+    kw = dict(GOOD)
+    kw[field] = value
+    p = fmbym.fmbym_params(*[kw[k] for k, _ in fmbym.fmbym_params._fields_])
+    h = ctypes.c_void_p()
+    rc = fmbym.lib().fmbym_plan_create(ctypes.byref(p), 1, ctypes.byref(h))
+    assert rc == code and not h.value
+
+
+def test_calls_without_a_plan_are_rejected():
+    L = fmbym.lib()
+    assert L.fmbym_search_workspace_size(None, 1, 0) == 0
+    assert L.fmbym_search(None, 1, *([None] * 8), None, 0, None) == fmbym.FMBYM_EINVAL
+    assert L.fmbym_search_backward(None, 1, *([None] * 13), None, 0, None) == fmbym.FMBYM_EINVAL
+    assert L.fmbym_plan_destroy(None) == fmbym.FMBYM_EINVAL
+    p = fmbym.fmbym_params(*[GOOD[k] for k, _ in fmbym.fmbym_params._fields_])
+    assert L.fmbym_plan_create(ctypes.byref(p), 1, None) == fmbym.FMBYM_EINVAL
+    h = ctypes.c_void_p()
+    assert L.fmbym_plan_create(ctypes.byref(p), 0, ctypes.byref(h)) == fmbym.FMBYM_EINVAL
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(fmbym, "_lib", None)
+    monkeypatch.setattr(fmbym, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        fmbym.lib()
