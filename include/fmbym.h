@@ -13,7 +13,12 @@
  *     column j is x = (j - n/2) delta_xy metres; the sensor is pixel (n/2, n/2).
  *   - pose[b] = {theta (rad), t_x (m), t_y (m)} satisfies Eq. 1.
  *   - c_theta[b][k] is the heading score of lag l = k - n_theta/2, i.e. of the
- *     candidate theta_l = l pi / n_theta.
+ *     candidate theta_l = l pi / n_theta, CENTRED: the mean score over all
+ *     lags is subtracted and returned in saved[b][FMBYM_SAVED_THETA_MEAN].  The
+ *     scores are sums of products of non-negative magnitudes, so the mean is
+ *     orders of magnitude larger than the lag-dependent part that the softmax
+ *     sees; computing the centred part without it keeps that part exact to
+ *     FP32 rounding of its own size.  c = c_theta + mean recovers the sums.
  *   - c_xy[b][i][j] is the translation score of lag (s_y, s_x) = (i - n/2, j - n/2)
  *     pixels, the linear correlation sum_x f_w[x] g'[x + s].
  *   - Forward DFTs are unnormalised; correlation values equal their defining sums.
@@ -53,8 +58,20 @@ extern "C" {
 #define FMBYM_HANN 1u           /* periodic Hann window on both scans (Algorithm 1) */
 #define FMBYM_XY_UNWINDOWED 8u  /* translation stage on the unwindowed scans        */
 
-/* floats per pair in the `saved` statistics buffer */
+/* floats per pair in the `saved` statistics buffer, and its slots */
 #define FMBYM_SAVED 16
+#define FMBYM_SAVED_THETA 0       /* heading theta (rad)                                  */
+#define FMBYM_SAVED_COS 1         /* cos(theta), sin(theta) as used by Rotate             */
+#define FMBYM_SAVED_SIN 2
+#define FMBYM_SAVED_THETA_MAX 3   /* max over lags of c_theta (centred scores)            */
+#define FMBYM_SAVED_THETA_SUM 4   /* sum_l exp((c_theta[l] - max) / T_theta)             */
+#define FMBYM_SAVED_XY_MAX 5      /* max of c_xy                                          */
+#define FMBYM_SAVED_XY_SUM 6      /* sum_s exp((c_xy[s] - max) / T_xy)                   */
+#define FMBYM_SAVED_TPX 7         /* t' = (t'_x, t'_y) in metres, before t = R(theta) t' */
+#define FMBYM_SAVED_TPY 8
+#define FMBYM_SAVED_THETA_MEAN 9  /* mean heading score over all lags                     */
+#define FMBYM_SAVED_THETA_ARG 10  /* lag l* of the largest heading score (lowest on ties) */
+#define FMBYM_SAVED_THETA_NU 11   /* sum_l p_l (l - l*): theta = (l* + nu) pi / n_theta   */
 
 typedef struct fmbym_plan_s* fmbym_plan;
 

@@ -11,15 +11,18 @@ namespace fmbym {
 
 // Per-pair statistics kept in `saved` (FMBYM_SAVED floats).
 enum SavedSlot {
-    kSavedTheta = 0,      // heading soft-argmax (rad)
-    kSavedCos = 1,        // cos(theta), sin(theta): rounded once, reused by every later kernel
-    kSavedSin = 2,
-    kSavedThetaMax = 3,   // max of c_theta
-    kSavedThetaSum = 4,   // sum exp((c_theta - max) / T_theta)
-    kSavedXyMax = 5,      // max of c_xy
-    kSavedXySum = 6,      // sum exp((c_xy - max) / T_xy)
-    kSavedTpx = 7,        // t' (metres) before the frame change
-    kSavedTpy = 8,
+    kSavedTheta = FMBYM_SAVED_THETA,         // heading soft-argmax (rad)
+    kSavedCos = FMBYM_SAVED_COS,             // cos/sin(theta): rounded once, reused by later kernels
+    kSavedSin = FMBYM_SAVED_SIN,
+    kSavedThetaMax = FMBYM_SAVED_THETA_MAX,  // max of the centred c_theta
+    kSavedThetaSum = FMBYM_SAVED_THETA_SUM,  // sum exp((c_theta - max) / T_theta)
+    kSavedXyMax = FMBYM_SAVED_XY_MAX,        // max of c_xy
+    kSavedXySum = FMBYM_SAVED_XY_SUM,        // sum exp((c_xy - max) / T_xy)
+    kSavedTpx = FMBYM_SAVED_TPX,             // t' (metres) before the frame change
+    kSavedTpy = FMBYM_SAVED_TPY,
+    kSavedThetaMean = FMBYM_SAVED_THETA_MEAN,  // mean heading score over the lags
+    kSavedThetaArg = FMBYM_SAVED_THETA_ARG,    // lag of the largest heading score
+    kSavedThetaNu = FMBYM_SAVED_THETA_NU,      // sum_l p_l (l - argmax lag)
 };
 
 struct Plan {
@@ -63,6 +66,10 @@ FwdLayout fwd_layout(const fmbym_params& p, int batch);
 int launch_forward(const Plan& pl, int batch, const float* f, const float* g, const float* mf,
                    const float* mg, float* pose, float* c_theta, float* c_xy, float* saved,
                    char* ws, hipStream_t s);
+
+// Stage-1 row DFTs and |F| (k_rows1, k_cols1), shared by forward and adjoint.
+void launch_stage1_spectra(const Plan& pl, int batch, const float* f, const float* g, const float* mf,
+                           const float* mg, float2* r1, float* mag, hipStream_t s);
 
 size_t bwd_workspace(const fmbym_params& p, int batch);
 int launch_backward(const Plan& pl, int batch, const float* f, const float* g, const float* mf,

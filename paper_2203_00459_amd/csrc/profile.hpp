@@ -8,7 +8,7 @@ namespace fmbym {
 
 enum KernelId {
     kKRows1 = 0, kKCols1, kKPolar, kKAngleFin, kKRows2, kKCols2, kKRows3, kKXyFin,
-    kKB0, kKB1, kKB2, kKB3, kKB4, kKB5, kKB6, kKB7, kKB8, kKB9, kKB10, kKB11,
+    kKBRowsFwd2, kKBColsXy, kKBRowsXy, kKBDtheta, kKBPolar, kKBColsMag, kKBRowsFinal,
     kKernelCount
 };
 

@@ -219,6 +219,32 @@ __device__ __forceinline__ float block_sum(float v, float* red) {
     return r;
 }
 
+// Largest value and its lowest index, over the block (deterministic tree).
+__device__ __forceinline__ void block_argmax(float v, int idx, float* rv, int* ri, float& out_v,
+                                             int& out_i) {
+    rv[threadIdx.x] = v;
+    ri[threadIdx.x] = idx;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            const float a = rv[threadIdx.x], b = rv[threadIdx.x + s];
+            const int ia = ri[threadIdx.x], ib = ri[threadIdx.x + s];
+            if (b > a || (b == a && ib < ia)) {
+                rv[threadIdx.x] = b;
+                ri[threadIdx.x] = ib;
+            }
+        }
+        __syncthreads();
+    }
+    out_v = rv[0];
+    out_i = ri[0];
+    __syncthreads();
+}
+
+// Sum over radius blocks, inverse angular DFT without its k = 0 term (the
+// mean over lags, kept apart so that the lag-dependent part is exact to its
+// own rounding), softmax and soft-argmax.  theta is formed as (l* + nu) dtheta
+// with nu = sum p_l (l - l*), which stays accurate when the softmax is sharp.
 template <int NT>
 __global__ __launch_bounds__(NT / kE) void k_angle_fin(const float2* __restrict__ part, int n_r,
                                                        const float2* __restrict__ tw, float temp,
@@ -229,52 +255,71 @@ __global__ __launch_bounds__(NT / kE) void k_angle_fin(const float2* __restrict_
     __shared__ float lre[lds_line_words(L)];
     __shared__ float lim[lds_line_words(L)];
     __shared__ float red[T];
+    __shared__ int redi[T];
     const int b = blockIdx.x, t = threadIdx.x;
     const int nrb = (n_r + kRadiiPerBlock - 1) / kRadiiPerBlock;
     const float2* src = part + (size_t)b * nrb * HK;
     float2 v[kE];
+    float dc = 0.f;
 #pragma unroll
     for (int m = 0; m < kE; ++m) {
         const int k = t + m * T;
         const int kk = k < HK ? k : NT - k;
         float2 s = make_float2(0.f, 0.f);
         for (int r = 0; r < nrb; ++r) s = cadd(s, src[(size_t)r * HK + kk]);
+        if (k == 0) {
+            dc = s.x;
+            s = make_float2(0.f, 0.f);
+        }
         v[m] = k < HK ? s : cconj(s);
     }
     ifft_line<L, kE>(v, lre, lim, t, tw);
     const float scale = 1.f / ((float)NT * (float)n_r);
     float c[kE];
     float lmax = -INFINITY;
+    int larg = 0;
 #pragma unroll
     for (int m = 0; m < kE; ++m) {
+        const int n = t + m * T;
+        const int k = n < NT / 2 ? n + NT / 2 : n - NT / 2;   // storage index of lag n
         c[m] = v[m].x * scale;
-        lmax = fmaxf(lmax, c[m]);
+        if (c[m] > lmax || (c[m] == lmax && k < larg)) {
+            lmax = c[m];
+            larg = k;
+        }
     }
-    const float cmax = block_max(lmax, red);
+    float cmax;
+    int kmax;
+    block_argmax(lmax, larg, red, redi, cmax, kmax);
+    const int lag_star = kmax - NT / 2;
     const float inv_t = 1.f / temp;
-    float se = 0.f, sl = 0.f;
+    float se = 0.f, sn = 0.f;
 #pragma unroll
     for (int m = 0; m < kE; ++m) {
         const int n = t + m * T;
         const int lag = n < NT / 2 ? n : n - NT;
         const float e = expf((c[m] - cmax) * inv_t);
         se += e;
-        sl += e * (float)lag;
+        sn += e * (float)(lag - lag_star);
         if (c_theta) c_theta[(size_t)b * NT + lag + NT / 2] = c[m];
     }
     const float Z = block_sum(se, red);
-    const float SL = block_sum(sl, red);
+    const float SN = block_sum(sn, red);
     if (t == 0) {
-        const float theta = (SL / Z) * (3.14159265358979323846f / (float)NT);
+        const float nu = SN / Z;
+        const float theta = ((float)lag_star + nu) * (3.14159265358979323846f / (float)NT);
         pose[b * 3 + 0] = theta;
         float* sv = saved + (size_t)b * FMBYM_SAVED;
         sv[kSavedTheta] = theta;
-        float sn, cs;
-        sincosf(theta, &sn, &cs);
-        sv[kSavedCos] = cs;
-        sv[kSavedSin] = sn;
+        float snt, cst;
+        sincosf(theta, &snt, &cst);
+        sv[kSavedCos] = cst;
+        sv[kSavedSin] = snt;
         sv[kSavedThetaMax] = cmax;
         sv[kSavedThetaSum] = Z;
+        sv[kSavedThetaMean] = dc * scale;
+        sv[kSavedThetaArg] = (float)lag_star;
+        sv[kSavedThetaNu] = nu;
     }
 }
 
@@ -526,6 +571,16 @@ static void launch_stage1_rows_cols(const Plan& pl, int B, const float* f, const
     constexpr int C = 16;
     FMBYM_LAUNCH(kKCols1, (k_cols1<N, C>), dim3(B * 2 * (N / 2) / C), dim3(C * N / kE), s, r1, mag,
                        pl.twiddle, pl.band_on, pl.band_lo2, pl.band_hi2);
+}
+
+void launch_stage1_spectra(const Plan& pl, int B, const float* f, const float* g, const float* mf,
+                           const float* mg, float2* r1, float* mag, hipStream_t s) {
+    switch (pl.p.n) {
+        case 128: launch_stage1_rows_cols<128>(pl, B, f, g, mf, mg, r1, mag, s); break;
+        case 256: launch_stage1_rows_cols<256>(pl, B, f, g, mf, mg, r1, mag, s); break;
+        case 512: launch_stage1_rows_cols<512>(pl, B, f, g, mf, mg, r1, mag, s); break;
+        default: break;
+    }
 }
 
 template <int N, int NT>

@@ -24,6 +24,18 @@ FMBYM_EHIP = -4
 FMBYM_HANN = 1
 FMBYM_XY_UNWINDOWED = 8
 FMBYM_SAVED = 16
+FMBYM_SAVED_THETA = 0
+FMBYM_SAVED_COS = 1
+FMBYM_SAVED_SIN = 2
+FMBYM_SAVED_THETA_MAX = 3
+FMBYM_SAVED_THETA_SUM = 4
+FMBYM_SAVED_XY_MAX = 5
+FMBYM_SAVED_XY_SUM = 6
+FMBYM_SAVED_TPX = 7
+FMBYM_SAVED_TPY = 8
+FMBYM_SAVED_THETA_MEAN = 9
+FMBYM_SAVED_THETA_ARG = 10
+FMBYM_SAVED_THETA_NU = 11
 
 EXPORTS = (
     "fmbym_plan_create", "fmbym_plan_destroy", "fmbym_search_workspace_size", "fmbym_search",

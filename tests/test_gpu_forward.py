@@ -23,15 +23,22 @@ PX_TOL = 1e-3
 
 
 def _compare(out, b, ref, delta):
+    # c_theta comes back centred (its mean over lags in saved): compare both the
+    # centred scores, which the softmax sees, and the recovered sums
     ct = out["c_theta"][b].double().cpu()
+    mean = float(out["saved"][b, fmbym.FMBYM_SAVED_THETA_MEAN])
+    ro = ref["c_theta"]
+    rc = ro - ro.mean()
+    e_c = float((ct - rc).abs().max() / rc.abs().max().clamp_min(1e-300))
+    e_t = max(e_c, float((ct + mean - ro).abs().max() / ro.abs().max().clamp_min(1e-300)))
     cx = out["c_xy"][b].double().cpu()
-    e_t = float((ct - ref["c_theta"]).abs().max() / ref["c_theta"].abs().max().clamp_min(1e-300))
     e_x = float((cx - ref["c_xy"]).abs().max() / ref["c_xy"].abs().max().clamp_min(1e-300))
     pose = out["pose"][b].double().cpu().numpy()
     rp = ref["pose"].numpy()
     d_th = abs(pose[0] - rp[0])
     d_t = max(abs(pose[1] - rp[1]), abs(pose[2] - rp[2])) / delta
-    msg = f"pair {b}: c_theta {e_t:.2e} c_xy {e_x:.2e} dtheta {d_th:.2e} rad dt {d_t:.2e} px"
+    msg = (f"pair {b}: c_theta {e_t:.2e} (centred {e_c:.2e}) c_xy {e_x:.2e} dtheta {d_th:.2e} rad "
+           f"dt {d_t:.2e} px")
     print(msg, flush=True)
     assert e_t <= SURF_TOL and e_x <= SURF_TOL, msg
     assert d_th <= THETA_TOL and d_t <= PX_TOL, msg
