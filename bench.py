@@ -34,7 +34,9 @@ def kernel_bytes(n: int, n_theta: int, n_r: int, batch: int, masked: bool) -> di
     m = 2 if masked else 1
     half = 2 * n * (n // 2) * 8            # both half spectra, complex64
     mag = 2 * n * (n // 2 + 1) * 4          # both magnitude half-planes, float32
+    polar = 2 * n_r * n_theta * 4           # both polar adjoints, float32
     return {
+        # forward
         "k_rows1": batch * (m * 2 * 4 * N2 + half),
         "k_cols1": batch * (half + mag),
         "k_polar": batch * (mag + nrb * hk * 8),
@@ -43,6 +45,15 @@ def kernel_bytes(n: int, n_theta: int, n_r: int, batch: int, masked: bool) -> di
         "k_cols2": batch * (2 * N2 * 8 + N2 * 8),
         "k_rows3": batch * (N2 * 8 + N2 * 4),
         "k_xy_fin": batch * 64,
+        # adjoint (k_rows1 and k_cols1 run again to recompute the stage-1 spectra)
+        "kb_rows_fwd2": batch * (m * 2 * 4 * N2 + 4 * N2 + 3 * N2 * 8),
+        "kb_cols_xy": batch * (3 * N2 * 8 + 2 * N2 * 8),
+        "kb_rows_xy": batch * (2 * N2 * 8 + m * 4 * N2 + 2 * N2 * 4),
+        "kb_dtheta": batch * (n_theta * 4 + n_theta * 8),
+        "kb_polar": batch * (mag + polar),
+        "kb_dmag": batch * (polar + mag),
+        "kb_cols_mag": batch * (half + mag + half),
+        "kb_rows_final": batch * (half + 2 * N2 * 4 + m * 2 * 4 * N2 + m * 2 * N2 * 4),
     }
 
 

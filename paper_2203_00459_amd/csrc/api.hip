@@ -34,6 +34,17 @@ int check_params(const fmbym_params* p) {
     return FMBYM_OK;
 }
 
+hipError_t free_plan_tables(Plan* pl) {
+    hipError_t first = hipSuccess;
+    void* ptrs[] = {pl->twiddle, pl->hann, pl->csr_ptr, pl->csr_col, pl->csr_val};
+    for (void* q : ptrs) {
+        if (!q) continue;
+        hipError_t e = hipFree(q);
+        if (first == hipSuccess) first = e;
+    }
+    return first;
+}
+
 int check_call(fmbym_plan plan, int32_t batch) {
     if (!plan) return FMBYM_EINVAL;
     if (batch < 1 || batch > plan_cast(plan)->max_batch) return FMBYM_EINVAL;
@@ -81,9 +92,9 @@ int fmbym_plan_create(const fmbym_params* p, int32_t max_batch, fmbym_plan* out)
     if (e == hipSuccess) e = hipMemcpy(pl->twiddle, tw, sizeof(tw), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(pl->hann, hann, sizeof(float) * p->n, hipMemcpyHostToDevice);
     delete[] hann;
+    if (e == hipSuccess) e = (hipError_t)build_polar_csr(*pl);
     if (e != hipSuccess) {
-        if (pl->twiddle) (void)hipFree(pl->twiddle);
-        if (pl->hann) (void)hipFree(pl->hann);
+        free_plan_tables(pl);
         delete pl;
         return hip_fail(e);
     }
@@ -94,12 +105,9 @@ int fmbym_plan_create(const fmbym_params* p, int32_t max_batch, fmbym_plan* out)
 int fmbym_plan_destroy(fmbym_plan plan) {
     if (!plan) return FMBYM_EINVAL;
     Plan* pl = plan_cast(plan);
-    hipError_t e1 = hipFree(pl->twiddle);
-    hipError_t e2 = hipFree(pl->hann);
+    hipError_t e = free_plan_tables(pl);
     delete pl;
-    if (e1 != hipSuccess) return hip_fail(e1);
-    if (e2 != hipSuccess) return hip_fail(e2);
-    return FMBYM_OK;
+    return e == hipSuccess ? FMBYM_OK : hip_fail(e);
 }
 
 size_t fmbym_search_workspace_size(fmbym_plan plan, int32_t batch, int with_backward) {

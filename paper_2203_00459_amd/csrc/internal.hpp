@@ -34,7 +34,13 @@ struct Plan {
     int band_on;
     int band_lo2;      // keep ceil((lo n)^2) <= ky^2 + kx^2 <= floor((hi n)^2)
     int band_hi2;
+    int* csr_ptr;      // transpose of the polar gather: per half-plane bin (ky (n/2+1) + kx),
+    int* csr_col;      // the polar samples (b n_theta + a) reading it
+    float* csr_val;    // and their bilinear weights
 };
+
+// Build the plan's CSR transpose of the polar gather; returns a hipError_t.
+int build_polar_csr(Plan& pl);
 
 inline Plan* plan_cast(fmbym_plan p) { return reinterpret_cast<Plan*>(p); }
 

@@ -1,0 +1,87 @@
+// Plan-time tables: the transpose of the polar gather as a CSR matrix.
+//
+// The polar samples sit at fixed frequencies u(b, a) for a given (n, n_r,
+// n_theta), so the map from sample (b, a) to the half-plane bins its bilinear
+// read touches (Cart2Pol, with the |F(-k)| = |F(k)| fold) is the same for
+// every pair.  A device kernel evaluates the corners and weights with the very
+// arithmetic of the forward gather (polar_uv, floor, weights), the host groups
+// them by bin in sample order, and the adjoint gathers dA = Cart2Pol^T dP with
+// one pass over each bin's row: deterministic, no atomics.
+#include <vector>
+
+#include "internal.hpp"
+
+namespace fmbym {
+
+__global__ void k_polar_corners(const float2* __restrict__ tw, int n, int n_r, int n_theta,
+                                int* __restrict__ bin, float* __restrict__ wgt) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_r * n_theta) return;
+    const int b = s / n_theta, a = s % n_theta;
+    float uy, ux;
+    polar_uv(tw, n, n_r, n_theta, b, a, uy, ux);
+    const float fy = floorf(uy), fx = floorf(ux);
+    const float wy = uy - fy, wx = ux - fx;
+    const int y0 = (int)fy, x0 = (int)fx;
+    const int H1 = n / 2 + 1;
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx) {
+            int ky = y0 + dy, kx = x0 + dx;
+            if (kx < 0) {
+                ky = -ky;
+                kx = -kx;
+            }
+            ky &= (n - 1);
+            bin[4 * s + 2 * dy + dx] = ky * H1 + kx;
+            wgt[4 * s + 2 * dy + dx] = (dy ? wy : 1.f - wy) * (dx ? wx : 1.f - wx);
+        }
+}
+
+int build_polar_csr(Plan& pl) {
+    const int n = pl.p.n, n_r = pl.p.n_r, nt = pl.p.n_theta;
+    const int ns = n_r * nt, nbins = n * (n / 2 + 1);
+    int* d_bin = nullptr;
+    float* d_w = nullptr;
+    hipError_t e = hipMalloc((void**)&d_bin, sizeof(int) * 4 * (size_t)ns);
+    if (e == hipSuccess) e = hipMalloc((void**)&d_w, sizeof(float) * 4 * (size_t)ns);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_polar_corners, dim3((ns + 255) / 256), dim3(256), 0, 0, pl.twiddle, n, n_r,
+                           nt, d_bin, d_w);
+        e = hipGetLastError();
+    }
+    std::vector<int> bin(4 * (size_t)ns);
+    std::vector<float> w(4 * (size_t)ns);
+    if (e == hipSuccess) e = hipMemcpy(bin.data(), d_bin, sizeof(int) * bin.size(), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(w.data(), d_w, sizeof(float) * w.size(), hipMemcpyDeviceToHost);
+    if (d_bin) (void)hipFree(d_bin);
+    if (d_w) (void)hipFree(d_w);
+    if (e != hipSuccess) return (int)e;
+    // counting sort by bin; entries of one bin stay in sample order
+    std::vector<int> ptr(nbins + 1, 0);
+    for (size_t i = 0; i < bin.size(); ++i)
+        if (w[i] != 0.f) ++ptr[bin[i] + 1];
+    for (int i = 0; i < nbins; ++i) ptr[i + 1] += ptr[i];
+    const int nnz = ptr[nbins];
+    std::vector<int> col(nnz);
+    std::vector<float> val(nnz);
+    std::vector<int> fill(ptr.begin(), ptr.end() - 1);
+    for (size_t i = 0; i < bin.size(); ++i) {
+        if (w[i] == 0.f) continue;
+        const int k = fill[bin[i]]++;
+        col[k] = (int)(i / 4);      // sample index b * n_theta + a
+        val[k] = w[i];
+    }
+    e = hipMalloc((void**)&pl.csr_ptr, sizeof(int) * ptr.size());
+    if (e == hipSuccess) e = hipMalloc((void**)&pl.csr_col, sizeof(int) * (nnz > 0 ? nnz : 1));
+    if (e == hipSuccess) e = hipMalloc((void**)&pl.csr_val, sizeof(float) * (nnz > 0 ? nnz : 1));
+    if (e == hipSuccess) e = hipMemcpy(pl.csr_ptr, ptr.data(), sizeof(int) * ptr.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && nnz)
+        e = hipMemcpy(pl.csr_col, col.data(), sizeof(int) * nnz, hipMemcpyHostToDevice);
+    if (e == hipSuccess && nnz)
+        e = hipMemcpy(pl.csr_val, val.data(), sizeof(float) * nnz, hipMemcpyHostToDevice);
+    return (int)e;
+}
+
+}  // namespace fmbym

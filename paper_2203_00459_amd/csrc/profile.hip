@@ -10,7 +10,7 @@ namespace fmbym {
 
 const char* const kKernelNames[kKernelCount] = {
     "k_rows1", "k_cols1", "k_polar", "k_angle_fin", "k_rows2", "k_cols2", "k_rows3", "k_xy_fin",
-    "kb_rows_fwd2", "kb_cols_xy", "kb_rows_xy", "kb_dtheta", "kb_polar", "kb_cols_mag",
+    "kb_rows_fwd2", "kb_cols_xy", "kb_rows_xy", "kb_dtheta", "kb_polar", "kb_dmag", "kb_cols_mag",
     "kb_rows_final",
 };
 

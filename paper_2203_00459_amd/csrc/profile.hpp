@@ -8,7 +8,7 @@ namespace fmbym {
 
 enum KernelId {
     kKRows1 = 0, kKCols1, kKPolar, kKAngleFin, kKRows2, kKCols2, kKRows3, kKXyFin,
-    kKBRowsFwd2, kKBColsXy, kKBRowsXy, kKBDtheta, kKBPolar, kKBColsMag, kKBRowsFinal,
+    kKBRowsFwd2, kKBColsXy, kKBRowsXy, kKBDtheta, kKBPolar, kKBDmag, kKBColsMag, kKBRowsFinal,
     kKernelCount
 };
 

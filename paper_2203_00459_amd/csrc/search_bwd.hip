@@ -23,8 +23,9 @@
 //   kb_dtheta      dtheta_total -> dc_theta -> its angular DFT
 //   k_rows1/k_cols1 (forward kernels) recompute the stage-1 row spectra and |F|
 //   kb_polar       polar gather + angular FFT again, the angular adjoint -> dP
-//   kb_cols_mag    column FFTs again, transposed polar gather, |F| adjoint,
-//                  inverse column DFT (in place over the row spectra)
+//   kb_dmag        transposed polar gather dA = Cart2Pol^T dP (plan's CSR table)
+//   kb_cols_mag    column FFTs again, |F| adjoint, inverse column DFT (in place
+//                  over the row spectra)
 //   kb_rows_final  inverse row DFT -> df_w, dg_w; adds the translation-stage
 //                  terms (Rotate^T gathered here); window and mask adjoints
 #include "internal.hpp"
@@ -402,47 +403,34 @@ __global__ __launch_bounds__(256) void kb_polar(const float* __restrict__ A,
     }
 }
 
-// dA at integer frequency point (py, px) of the polar-sample plane: sum of
-// tent weights times dP over the polar samples within the open unit box.
-__device__ float polar_adjoint_point(const float* __restrict__ dp, const float2* __restrict__ tw,
-                                     int N, int n_r, int NT, float py, float px) {
-    const float r = sqrtf(py * py + px * px);
-    const float drho = (float)(N / 2) / (float)n_r;
-    const int b_lo = max(0, (int)floorf((r - 1.5f) / drho));
-    const int b_hi = min(n_r - 1, (int)ceilf((r + 1.5f) / drho));
-    int a_lo = 0, a_hi = NT - 1;
-    if (r > 2.f) {
-        const float phi = atan2f(py, px);
-        const float half = asinf(1.5f / r) + 1e-3f;
-        const float dth = kPi / (float)NT;
-        a_lo = max(0, (int)floorf((phi - half) / dth));
-        a_hi = min(NT - 1, (int)ceilf((phi + half) / dth));
-    }
-    float acc = 0.f;
-    for (int bb = b_lo; bb <= b_hi; ++bb) {
-        const float* row = dp + (size_t)bb * NT;
-        for (int a = a_lo; a <= a_hi; ++a) {
-            float uy, ux;
-            polar_uv(tw, N, n_r, NT, bb, a, uy, ux);
-            const float ey = fabsf(uy - py), ex = fabsf(ux - px);
-            if (ey < 1.f && ex < 1.f) acc += (1.f - ey) * (1.f - ex) * row[a];
+// dA = band * Cart2Pol^T dP over the half-plane bins, from the plan's CSR
+// transpose of the polar gather.  Bins outside the band get 0 without a gather.
+// blockIdx.y walks groups of kDmagGroup (pair, scan) planes that share the
+// block's CSR rows through the cache.
+constexpr int kDmagGroup = 8;
+__global__ __launch_bounds__(256) void kb_dmag(const int* __restrict__ ptr, const int* __restrict__ col,
+                                               const float* __restrict__ val,
+                                               const float* __restrict__ dpol, float* __restrict__ dA,
+                                               int n, int n_r, int n_theta, int planes, int band_on,
+                                               int lo2, int hi2) {
+    const int h1 = n / 2 + 1;
+    const int bin = blockIdx.x * blockDim.x + threadIdx.x;
+    if (bin >= n * h1) return;
+    const int ky = bin / h1, kx = bin % h1;
+    const int kys = ky < n / 2 ? ky : ky - n;
+    const int r2 = kys * kys + kx * kx;
+    const bool in_band = !band_on || (r2 >= lo2 && r2 <= hi2);
+    const int e0 = ptr[bin], e1 = ptr[bin + 1];
+    const size_t pstride = (size_t)n_r * n_theta;
+    const int p0 = blockIdx.y * kDmagGroup, p1 = min(planes, p0 + kDmagGroup);
+    for (int ps = p0; ps < p1; ++ps) {
+        float acc = 0.f;
+        if (in_band) {
+            const float* src = dpol + (size_t)ps * pstride;
+            for (int e = e0; e < e1; ++e) acc += val[e] * src[col[e]];
         }
+        dA[((size_t)ps * n + ky) * mag_pitch(n) + kx] = acc;
     }
-    return acc;
-}
-
-// dA at stored half-plane bin (ky, kx): direct corners (ky <= n/2) and
-// corners folded from negative columns (|F(-k)| = |F(k)|).
-__device__ __forceinline__ float polar_adjoint_bin(const float* __restrict__ dp,
-                                                   const float2* __restrict__ tw, int N, int n_r,
-                                                   int NT, int ky, int kx) {
-    float acc = 0.f;
-    if (ky <= N / 2) acc += polar_adjoint_point(dp, tw, N, n_r, NT, (float)ky, (float)kx);
-    if (kx > 0) {
-        const int ry = (N - ky) & (N - 1);
-        if (ry <= N / 2) acc += polar_adjoint_point(dp, tw, N, n_r, NT, (float)ry, -(float)kx);
-    }
-    return acc;
 }
 
 __device__ __forceinline__ float2 mag_adjoint(float2 F, float dA) {
@@ -452,26 +440,24 @@ __device__ __forceinline__ float2 mag_adjoint(float2 F, float dA) {
     return make_float2(F.x * s, F.y * s);
 }
 
-__device__ __forceinline__ float band_gain_b(int ky_signed, int kx, int on, int lo2, int hi2) {
-    if (!on) return 1.f;
-    const int r2 = ky_signed * ky_signed + kx * kx;
-    return (r2 >= lo2 && r2 <= hi2) ? 1.f : 0.f;
-}
 
-// Column pass of the rotation adjoint, in place over the stage-1 row spectra.
+// Column pass of the rotation adjoint, in place over the stage-1 row spectra:
+// column DFTs again, dF = dA F / |F| (dA already carries the band gain), and
+// the unnormalised inverse column DFT.  For the packed DC/Nyquist column only
+// the real parts of the inverse are needed: the inverse of the Hermitian part
+// of each, both through one transform.
 template <int N, int C>
 __global__ __launch_bounds__(C * N / kEb) void kb_cols_mag(float2* __restrict__ r1,
-                                                           const float* __restrict__ dpol,
-                                                           const float2* __restrict__ tw, int n_r,
-                                                           int NT, int band_on, int lo2, int hi2) {
-    constexpr int L = N, T = L / kEb, H = N / 2, TILES = H / C;
+                                                           const float* __restrict__ dA,
+                                                           const float2* __restrict__ tw) {
+    constexpr int L = N, T = L / kEb, H = N / 2, TILES = H / C, P = mag_pitch(N);
     __shared__ float lre[C][lds_line_words(L)];
     __shared__ float lim[C][lds_line_words(L)];
     const int c = threadIdx.x % C, t = threadIdx.x / C;
     const int tile = blockIdx.x % TILES, bs = blockIdx.x / TILES;
     const int col = tile * C + c;
     float2* src = r1 + (size_t)bs * N * H;
-    const float* dp = dpol + (size_t)bs * n_r * NT;
+    const float* da = dA + (size_t)bs * N * P;
     float2 v[kEb];
 #pragma unroll
     for (int m = 0; m < kEb; ++m) v[m] = src[(size_t)(t + m * T) * H + col];
@@ -483,24 +469,14 @@ __global__ __launch_bounds__(C * N / kEb) void kb_cols_mag(float2* __restrict__ 
 #pragma unroll
         for (int m = 0; m < kEb; ++m) {
             const int ky = t + m * T;
-            const int kys = ky < H ? ky : ky - N;
             if (c == 0) {
-                const float2 F0 = split_x(v[m], mir[m]), FN = split_y(v[m], mir[m]);
-                const float g0 = band_gain_b(kys, 0, band_on, lo2, hi2);
-                const float gn = band_gain_b(kys, H, band_on, lo2, hi2);
-                const float a0 = g0 != 0.f ? g0 * polar_adjoint_bin(dp, tw, N, n_r, NT, ky, 0) : 0.f;
-                const float an = gn != 0.f ? gn * polar_adjoint_bin(dp, tw, N, n_r, NT, ky, H) : 0.f;
-                d0[m] = mag_adjoint(F0, a0);
-                dn[m] = mag_adjoint(FN, an);
+                d0[m] = mag_adjoint(split_x(v[m], mir[m]), da[ky * P + 0]);
+                dn[m] = mag_adjoint(split_y(v[m], mir[m]), da[ky * P + H]);
             } else {
-                const float gg = band_gain_b(kys, col, band_on, lo2, hi2);
-                const float a = gg != 0.f ? gg * polar_adjoint_bin(dp, tw, N, n_r, NT, ky, col) : 0.f;
-                d0[m] = mag_adjoint(v[m], a);
+                d0[m] = mag_adjoint(v[m], da[ky * P + col]);
                 dn[m] = make_float2(0.f, 0.f);
             }
         }
-        // Re of the inverse column DFT = inverse DFT of the Hermitian part;
-        // the two real results of the packed column share one transform.
         float2 m0[kEb], mn[kEb];
         mirror_line<L, kEb>(d0, m0, lre[c], lim[c], t);
         mirror_line<L, kEb>(dn, mn, lre[c], lim[c], t);
@@ -516,13 +492,7 @@ __global__ __launch_bounds__(C * N / kEb) void kb_cols_mag(float2* __restrict__ 
         }
     } else {
 #pragma unroll
-        for (int m = 0; m < kEb; ++m) {
-            const int ky = t + m * T;
-            const int kys = ky < H ? ky : ky - N;
-            const float gg = band_gain_b(kys, col, band_on, lo2, hi2);
-            const float a = gg != 0.f ? gg * polar_adjoint_bin(dp, tw, N, n_r, NT, ky, col) : 0.f;
-            v[m] = mag_adjoint(v[m], a);
-        }
+        for (int m = 0; m < kEb; ++m) v[m] = mag_adjoint(v[m], da[(t + m * T) * P + col]);
     }
     ifft_line<L, kEb>(v, lre[c], lim[c], t, tw);
 #pragma unroll
@@ -726,9 +696,14 @@ static int launch_bwd_n(const Plan& pl, int B, const float* f, const float* g, c
         case 1024: launch_bwd_polar<N, 1024>(pl, B, mag, dspec, dpol, s); break;
         default: return FMBYM_EUNSUPPORTED;
     }
-    constexpr int C = N >= 512 ? 8 : 16;
-    FMBYM_LAUNCH(kKBColsMag, (kb_cols_mag<N, C>), dim3(B * 2 * (N / 2) / C), dim3(C * N / kEb), s, r1, dpol,
-                 pl.twiddle, pl.p.n_r, pl.p.n_theta, pl.band_on, pl.band_lo2, pl.band_hi2);
+    float* dA = mag;                    // the recomputed magnitudes are dead after kb_polar
+    const int nbins = N * (N / 2 + 1);
+    FMBYM_LAUNCH(kKBDmag, kb_dmag, dim3((nbins + 255) / 256, (2 * B + kDmagGroup - 1) / kDmagGroup),
+                 dim3(256), s, pl.csr_ptr, pl.csr_col, pl.csr_val, dpol, dA, N, pl.p.n_r, pl.p.n_theta,
+                 2 * B, pl.band_on, pl.band_lo2, pl.band_hi2);
+    constexpr int C = 16;
+    FMBYM_LAUNCH(kKBColsMag, (kb_cols_mag<N, C>), dim3(B * 2 * (N / 2) / C), dim3(C * N / kEb), s, r1, dA,
+                 pl.twiddle);
     constexpr int T1 = N / kEb, LPB1 = 256 / T1;
     FMBYM_LAUNCH(kKBRowsFinal, kb_rows_final<N>, dim3(B * N / LPB1), dim3(256), s, r1, df2, dgp, f, g, mf, mg,
                  pl.hann, pl.twiddle, saved, d_f, d_g, d_mf, d_mg, win, win2);

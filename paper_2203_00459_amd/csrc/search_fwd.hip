@@ -195,11 +195,12 @@ __global__ __launch_bounds__(256) void k_polar(const float* __restrict__ A,
     }
 }
 
-// Deterministic block reductions over blockDim.x (a power of two) values.
-__device__ __forceinline__ float block_max(float v, float* red) {
-    red[threadIdx.x] = v;
+// Deterministic reductions over the first `cnt` threads (a power of two) of
+// the block; every thread of the block must call them (they hold barriers).
+__device__ __forceinline__ float block_max(float v, float* red, int cnt) {
+    if ((int)threadIdx.x < cnt) red[threadIdx.x] = v;
     __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    for (int s = cnt / 2; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
         __syncthreads();
     }
@@ -207,10 +208,10 @@ __device__ __forceinline__ float block_max(float v, float* red) {
     __syncthreads();
     return r;
 }
-__device__ __forceinline__ float block_sum(float v, float* red) {
-    red[threadIdx.x] = v;
+__device__ __forceinline__ float block_sum(float v, float* red, int cnt) {
+    if ((int)threadIdx.x < cnt) red[threadIdx.x] = v;
     __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    for (int s = cnt / 2; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
@@ -220,12 +221,14 @@ __device__ __forceinline__ float block_sum(float v, float* red) {
 }
 
 // Largest value and its lowest index, over the block (deterministic tree).
-__device__ __forceinline__ void block_argmax(float v, int idx, float* rv, int* ri, float& out_v,
-                                             int& out_i) {
-    rv[threadIdx.x] = v;
-    ri[threadIdx.x] = idx;
+__device__ __forceinline__ void block_argmax(float v, int idx, float* rv, int* ri, int cnt,
+                                             float& out_v, int& out_i) {
+    if ((int)threadIdx.x < cnt) {
+        rv[threadIdx.x] = v;
+        ri[threadIdx.x] = idx;
+    }
     __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    for (int s = cnt / 2; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) {
             const float a = rv[threadIdx.x], b = rv[threadIdx.x + s];
             const int ia = ri[threadIdx.x], ib = ri[threadIdx.x + s];
@@ -245,35 +248,50 @@ __device__ __forceinline__ void block_argmax(float v, int idx, float* rv, int* r
 // mean over lags, kept apart so that the lag-dependent part is exact to its
 // own rounding), softmax and soft-argmax.  theta is formed as (l* + nu) dtheta
 // with nu = sum p_l (l - l*), which stays accurate when the softmax is sharp.
+constexpr int kAngleGroups = 4;   // thread groups that share the radius-block sum
+
 template <int NT>
-__global__ __launch_bounds__(NT / kE) void k_angle_fin(const float2* __restrict__ part, int n_r,
-                                                       const float2* __restrict__ tw, float temp,
-                                                       float* __restrict__ c_theta,
-                                                       float* __restrict__ pose,
-                                                       float* __restrict__ saved) {
+__global__ __launch_bounds__(kAngleGroups * NT / kE) void k_angle_fin(
+    const float2* __restrict__ part, int n_r, const float2* __restrict__ tw, float temp,
+    float* __restrict__ c_theta, float* __restrict__ pose, float* __restrict__ saved) {
     constexpr int L = NT, T = L / kE, HK = NT / 2 + 1;
-    __shared__ float lre[lds_line_words(L)];
-    __shared__ float lim[lds_line_words(L)];
+    __shared__ float lre[kAngleGroups][lds_line_words(L)];   // one line per group: the groups
+    __shared__ float lim[kAngleGroups][lds_line_words(L)];   // repeat the transform, race-free
+    __shared__ float2 psum[kAngleGroups][HK];
     __shared__ float red[T];
     __shared__ int redi[T];
-    const int b = blockIdx.x, t = threadIdx.x;
+    const int b = blockIdx.x;
     const int nrb = (n_r + kRadiiPerBlock - 1) / kRadiiPerBlock;
     const float2* src = part + (size_t)b * nrb * HK;
+    {   // group q sums radius blocks q, q + G, ... ; the groups are then added in order
+        const int q = threadIdx.x / T, tt = threadIdx.x % T;
+        for (int k = tt; k < HK; k += T) {
+            float2 s = make_float2(0.f, 0.f);
+            for (int r = q; r < nrb; r += kAngleGroups) s = cadd(s, src[(size_t)r * HK + k]);
+            psum[q][k] = s;
+        }
+    }
+    __syncthreads();
+    // the transform and softmax run on the first group; the others idle through
+    // the barriers (their values are never stored)
+    const int t = threadIdx.x % T;
+    const bool lead = (int)threadIdx.x < T;
     float2 v[kE];
     float dc = 0.f;
 #pragma unroll
     for (int m = 0; m < kE; ++m) {
         const int k = t + m * T;
         const int kk = k < HK ? k : NT - k;
-        float2 s = make_float2(0.f, 0.f);
-        for (int r = 0; r < nrb; ++r) s = cadd(s, src[(size_t)r * HK + kk]);
+        float2 s = psum[0][kk];
+#pragma unroll
+        for (int q = 1; q < kAngleGroups; ++q) s = cadd(s, psum[q][kk]);
         if (k == 0) {
             dc = s.x;
             s = make_float2(0.f, 0.f);
         }
         v[m] = k < HK ? s : cconj(s);
     }
-    ifft_line<L, kE>(v, lre, lim, t, tw);
+    ifft_line<L, kE>(v, lre[threadIdx.x / T], lim[threadIdx.x / T], t, tw);
     const float scale = 1.f / ((float)NT * (float)n_r);
     float c[kE];
     float lmax = -INFINITY;
@@ -290,7 +308,7 @@ __global__ __launch_bounds__(NT / kE) void k_angle_fin(const float2* __restrict_
     }
     float cmax;
     int kmax;
-    block_argmax(lmax, larg, red, redi, cmax, kmax);
+    block_argmax(lmax, larg, red, redi, T, cmax, kmax);
     const int lag_star = kmax - NT / 2;
     const float inv_t = 1.f / temp;
     float se = 0.f, sn = 0.f;
@@ -301,11 +319,11 @@ __global__ __launch_bounds__(NT / kE) void k_angle_fin(const float2* __restrict_
         const float e = expf((c[m] - cmax) * inv_t);
         se += e;
         sn += e * (float)(lag - lag_star);
-        if (c_theta) c_theta[(size_t)b * NT + lag + NT / 2] = c[m];
+        if (c_theta && lead) c_theta[(size_t)b * NT + lag + NT / 2] = c[m];
     }
-    const float Z = block_sum(se, red);
-    const float SN = block_sum(sn, red);
-    if (t == 0) {
+    const float Z = block_sum(se, red, T);
+    const float SN = block_sum(sn, red, T);
+    if (threadIdx.x == 0) {
         const float nu = SN / Z;
         const float theta = ((float)lag_star + nu) * (3.14159265358979323846f / (float)NT);
         pose[b * 3 + 0] = theta;
@@ -509,31 +527,43 @@ __global__ __launch_bounds__(256) void k_rows3(const float2* __restrict__ in,
     if (threadIdx.x == 0) part[(size_t)b * PPP + (blockIdx.x % PPP)] = red[0];
 }
 
+// Merge of the online-softmax partials of one pair: 64 threads, each folds a
+// strided subset, then a fixed-order tree.
+__device__ __forceinline__ float4 softmax_merge(float4 a, float4 c, float inv_t) {
+    if (c.x == -INFINITY) return a;   // empty partials (threads past the end)
+    if (a.x == -INFINITY) return c;
+    const float M = fmaxf(a.x, c.x);
+    const float ea = expf((a.x - M) * inv_t), ec = expf((c.x - M) * inv_t);
+    return make_float4(M, a.y * ea + c.y * ec, a.z * ea + c.z * ec, a.w * ea + c.w * ec);
+}
+
 __global__ __launch_bounds__(64) void k_xy_fin(const float4* __restrict__ part, int ppp, float temp,
                                                float delta, float* __restrict__ pose,
-                                               float* __restrict__ saved, int batch) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= batch) return;
+                                               float* __restrict__ saved) {
+    __shared__ float4 red[64];
+    const int b = blockIdx.x, t = threadIdx.x;
     const float inv_t = 1.f / temp;
     const float4* p = part + (size_t)b * ppp;
-    float M = -INFINITY;
-    for (int i = 0; i < ppp; ++i) M = fmaxf(M, p[i].x);
-    float Z = 0.f, Sx = 0.f, Sy = 0.f;
-    for (int i = 0; i < ppp; ++i) {
-        const float e = expf((p[i].x - M) * inv_t);
-        Z += p[i].y * e;
-        Sx += p[i].z * e;
-        Sy += p[i].w * e;
+    float4 acc = make_float4(-INFINITY, 0.f, 0.f, 0.f);
+    for (int i = t; i < ppp; i += 64) acc = softmax_merge(acc, p[i], inv_t);
+    red[t] = acc;
+    __syncthreads();
+    for (int s = 32; s > 0; s >>= 1) {
+        if (t < s) red[t] = softmax_merge(red[t], red[t + s], inv_t);
+        __syncthreads();
     }
-    float* sv = saved + (size_t)b * FMBYM_SAVED;
-    const float tpx = delta * (Sx / Z), tpy = delta * (Sy / Z);
-    const float ct = sv[kSavedCos], st = sv[kSavedSin];
-    pose[b * 3 + 1] = ct * tpx - st * tpy;
-    pose[b * 3 + 2] = st * tpx + ct * tpy;
-    sv[kSavedXyMax] = M;
-    sv[kSavedXySum] = Z;
-    sv[kSavedTpx] = tpx;
-    sv[kSavedTpy] = tpy;
+    if (t == 0) {
+        const float4 r = red[0];
+        float* sv = saved + (size_t)b * FMBYM_SAVED;
+        const float tpx = delta * (r.z / r.y), tpy = delta * (r.w / r.y);
+        const float ct = sv[kSavedCos], st = sv[kSavedSin];
+        pose[b * 3 + 1] = ct * tpx - st * tpy;
+        pose[b * 3 + 2] = st * tpx + ct * tpy;
+        sv[kSavedXyMax] = r.x;
+        sv[kSavedXySum] = r.y;
+        sv[kSavedTpx] = tpx;
+        sv[kSavedTpy] = tpy;
+    }
 }
 
 // ---------------------------------------------------------------- launcher
@@ -590,7 +620,7 @@ static void launch_polar(const Plan& pl, int B, const float* mag, float2* pth, f
     const int total = B * nrb;
     const int grid = ((total + 7) / 8) * 8;
     FMBYM_LAUNCH(kKPolar, (k_polar<NT, N>), dim3(grid), dim3(256), s, mag, pl.twiddle, pth, pl.p.n_r, B);
-    FMBYM_LAUNCH(kKAngleFin, k_angle_fin<NT>, dim3(B), dim3(NT / kE), s, pth, pl.p.n_r, pl.twiddle,
+    FMBYM_LAUNCH(kKAngleFin, k_angle_fin<NT>, dim3(B), dim3(kAngleGroups * NT / kE), s, pth, pl.p.n_r, pl.twiddle,
                        pl.p.temp_theta, c_theta, pose, saved);
 }
 
@@ -628,8 +658,8 @@ static int launch_n(const Plan& pl, int B, const float* f, const float* g, const
     constexpr int LPB3 = 256 / T2;
     FMBYM_LAUNCH(kKRows3, k_rows3<N>, dim3(B * (N / 2) / LPB3), dim3(256), s, r3, pl.twiddle, c_xy,
                        pxy, pl.p.temp_xy);
-    FMBYM_LAUNCH(kKXyFin, k_xy_fin, dim3((B + 63) / 64), dim3(64), s, pxy, xy_partials_per_pair(N),
-                       pl.p.temp_xy, pl.p.delta_xy, pose, sv, B);
+    FMBYM_LAUNCH(kKXyFin, k_xy_fin, dim3(B), dim3(64), s, pxy, xy_partials_per_pair(N), pl.p.temp_xy,
+                 pl.p.delta_xy, pose, sv);
     return FMBYM_OK;
 }
 
