@@ -74,9 +74,11 @@ template <>
 __device__ __forceinline__ void dft_r<8>(float2 (&v)[8]) { dft8(v); }
 
 // Padded LDS index: one spare word every 32 keeps the strided Stockham
-// accesses spread over the banks.
+// accesses spread over the banks; one more word per line makes consecutive
+// lines (the columns of a column tile, accessed by neighbouring lanes) start
+// on different banks.
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 5); }
-__host__ __device__ constexpr int lds_line_words(int L) { return L + L / 32; }
+__host__ __device__ constexpr int lds_line_words(int L) { return L + L / 32 + 1; }
 
 constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
 
@@ -123,11 +125,15 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[E], float* re, float* im, 
                 x[r] = make_float2(re[idx], im[idx]);
             }
         }
-        if (Ns > 1) {
+        if (Ns > 1) {   // W^r for r < R from one table read, products at most 3 deep
             const int k = j & (Ns - 1);
             constexpr int step = kTwiddleLen / (Ns * R);
+            float2 w[R];
+            w[1] = tw[k * step];
 #pragma unroll
-            for (int r = 1; r < R; ++r) x[r] = cmul(x[r], tw[r * k * step]);
+            for (int r = 2; r < R; ++r) w[r] = cmul(w[r / 2], w[r - r / 2]);
+#pragma unroll
+            for (int r = 1; r < R; ++r) x[r] = cmul(x[r], w[r]);
         }
         dft_r<R>(x);
 #pragma unroll

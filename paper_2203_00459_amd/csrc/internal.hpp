@@ -48,8 +48,14 @@ inline Plan* plan_cast(fmbym_plan p) { return reinterpret_cast<Plan*>(p); }
 constexpr int kRadiiPerBlock = 8;
 inline int radius_blocks(int n_r) { return (n_r + kRadiiPerBlock - 1) / kRadiiPerBlock; }
 
-// Column pitch (floats) of the stored half-plane magnitude spectra [n][n/2 + 1].
-inline __host__ __device__ constexpr int mag_pitch(int n) { return n / 2 + 32; }
+// Row pitches, in elements.  Every row array keeps its unique columns
+// (n/2 + 1 in stage 1, n + 1 in stage 2) plus room for the last, partial
+// column tile of the column kernels (at most kPitchPad columns wide).
+constexpr int kPitchPad = 16;
+__host__ __device__ constexpr int pitch_rows1(int n) { return n / 2 + kPitchPad; }  // float4 (F_f, F_g)
+__host__ __device__ constexpr int pitch_mag(int n) { return n / 2 + kPitchPad; }    // float2 (A_f, A_g)
+__host__ __device__ constexpr int pitch_rows2(int n) { return n + kPitchPad; }      // float4 (F, G')
+__host__ __device__ constexpr int pitch_lag(int n) { return n + kPitchPad; }        // float2
 
 // Rows per block of the stage-2 inverse-row kernel's softmax partials.
 inline int xy_partials_per_pair(int n) {
@@ -60,8 +66,8 @@ inline int xy_partials_per_pair(int n) {
 
 // Workspace carve-up shared by forward and backward launchers.
 struct FwdLayout {
-    size_t r1r2;      // stage-1 row spectra, then stage-2 row spectra   [B][2][n][n]  float2
-    size_t mag_r3;    // magnitudes [B][2][n][pitch] float, then stage-2 columns [B][n][n] float2
+    size_t r1r2;      // stage-1 row spectra [B][n][pitch_rows1] float4, then stage-2 [B][n][pitch_rows2] float4
+    size_t mag_r3;    // magnitudes [B][n][pitch_mag] float2, then stage-2 columns [B][n][pitch_lag] float2
     size_t ptheta;    // [B][radius_blocks][n_theta/2 + 1] float2
     size_t pxy;       // [B][xy_partials] float4
     size_t saved;     // [B][FMBYM_SAVED] float (used when the caller passes none)
@@ -75,7 +81,7 @@ int launch_forward(const Plan& pl, int batch, const float* f, const float* g, co
 
 // Stage-1 row DFTs and |F| (k_rows1, k_cols1), shared by forward and adjoint.
 void launch_stage1_spectra(const Plan& pl, int batch, const float* f, const float* g, const float* mf,
-                           const float* mg, float2* r1, float* mag, hipStream_t s);
+                           const float* mg, float4* r1, float2* mag, hipStream_t s);
 
 size_t bwd_workspace(const fmbym_params& p, int batch);
 int launch_backward(const Plan& pl, int batch, const float* f, const float* g, const float* mf,
@@ -136,14 +142,15 @@ __device__ __forceinline__ void polar_uv(const float2* __restrict__ tw, int n, i
     uy = rho * (-w.y);
 }
 
-// Bilinear read of a half-plane magnitude spectrum at (uy, ux), using
-// |F(-k)| = |F(k)| for corners with negative column and indices modulo n.
-__device__ __forceinline__ float mag_sample(const float* __restrict__ A, int n, float uy, float ux) {
-    const int P = mag_pitch(n);
+// Bilinear read of both half-plane magnitude spectra (interleaved) at
+// (uy, ux), using |F(-k)| = |F(k)| for corners with negative column and
+// indices modulo n.
+__device__ __forceinline__ float2 mag_sample(const float2* __restrict__ A, int n, float uy, float ux) {
+    const int P = pitch_mag(n);
     const float fy = floorf(uy), fx = floorf(ux);
     const float wy = uy - fy, wx = ux - fx;
     const int y0 = (int)fy, x0 = (int)fx;
-    float acc = 0.f;
+    float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
     for (int dy = 0; dy < 2; ++dy) {
 #pragma unroll
@@ -155,7 +162,9 @@ __device__ __forceinline__ float mag_sample(const float* __restrict__ A, int n, 
             }
             ky &= (n - 1);
             const float w = (dy ? wy : 1.f - wy) * (dx ? wx : 1.f - wx);
-            acc += w * A[ky * P + kx];
+            const float2 a = A[ky * P + kx];
+            acc.x += w * a.x;
+            acc.y += w * a.y;
         }
     }
     return acc;

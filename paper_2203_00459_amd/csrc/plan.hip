@@ -6,7 +6,8 @@
 // every pair.  A device kernel evaluates the corners and weights with the very
 // arithmetic of the forward gather (polar_uv, floor, weights), the host groups
 // them by bin in sample order, and the adjoint gathers dA = Cart2Pol^T dP with
-// one pass over each bin's row: deterministic, no atomics.
+// one pass over each bin's row: deterministic, no atomics.  Bins outside the
+// band-pass get empty rows (the adjoint multiplies their dA by 0 anyway).
 #include <vector>
 
 #include "internal.hpp"
@@ -58,6 +59,17 @@ int build_polar_csr(Plan& pl) {
     if (d_bin) (void)hipFree(d_bin);
     if (d_w) (void)hipFree(d_w);
     if (e != hipSuccess) return (int)e;
+    // bins outside the band-pass get empty rows: their dA is multiplied by 0
+    const int h1 = n / 2 + 1;
+    auto in_band = [&](int b) {
+        if (!pl.band_on) return true;
+        const int ky = b / h1, kx = b % h1;
+        const int kys = ky < n / 2 ? ky : ky - n;
+        const int r2 = kys * kys + kx * kx;
+        return r2 >= pl.band_lo2 && r2 <= pl.band_hi2;
+    };
+    for (size_t i = 0; i < bin.size(); ++i)
+        if (!in_band(bin[i])) w[i] = 0.f;
     // counting sort by bin; entries of one bin stay in sample order
     std::vector<int> ptr(nbins + 1, 0);
     for (size_t i = 0; i < bin.size(); ++i)

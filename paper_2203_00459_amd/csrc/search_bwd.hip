@@ -19,6 +19,7 @@
 // Kernels, in launch order:
 //   kb_rows_fwd2   rows of f2 and g' (2n-padded) and of dc_xy, paired complex FFTs
 //   kb_cols_xy     column FFTs, conj(DC) G' and F DC, inverse columns (rows < n kept)
+//                  (layouts as in the forward: interleaved spectra, all unique columns)
 //   kb_rows_xy     inverse rows -> df2, dg'; partial sums of dtheta_2
 //   kb_dtheta      dtheta_total -> dc_theta -> its angular DFT
 //   k_rows1/k_cols1 (forward kernels) recompute the stage-1 row spectra and |F|
@@ -62,25 +63,27 @@ __device__ __forceinline__ XyAdj make_xy_adj(const float* sv, const float* dp, f
 
 // ------------------------------------------------------ translation adjoint
 
-// Blocks [0, B n / LPB) transform rows of f2 + i g'; the rest transform pairs
-// of dc_xy lag rows.  Outputs are packed half spectra of the 2n-point rows.
+// Blocks [0, B n / LPB) transform rows of f2 + i g' (-> rf, float4 (F, G'));
+// the rest transform pairs of dc_xy lag rows (-> rdc, float2).  Columns 0 .. n
+// of the 2n-point row spectra are kept.
 template <int N>
 __global__ __launch_bounds__(256) void kb_rows_fwd2(
     const float* __restrict__ f, const float* __restrict__ g, const float* __restrict__ mf,
     const float* __restrict__ mg, const float* __restrict__ hann, const float2* __restrict__ tw,
     const float* __restrict__ saved, const float* __restrict__ c_xy, const float* __restrict__ d_pose,
-    float2* __restrict__ rf, float2* __restrict__ rg, float2* __restrict__ rdc, int win, int batch,
-    float temp, float delta) {
-    constexpr int L = 2 * N, T = L / kEb, LPB = 256 / T;
+    float4* __restrict__ rf, float2* __restrict__ rdc, int win, int batch, float temp, float delta) {
+    constexpr int L = 2 * N, T = L / kEb, LPB = 256 / T, P2 = pitch_rows2(N), P3 = pitch_lag(N);
     __shared__ float lre[LPB][lds_line_words(L)];
     __shared__ float lim[LPB][lds_line_words(L)];
     const int line = threadIdx.x / T, t = threadIdx.x % T;
     const int nscan_blocks = batch * N / LPB;
+    const bool scan_rows = (int)blockIdx.x < nscan_blocks;   // block-uniform
     float2 v[kEb];
-    float2 *o1, *o2;
-    if ((int)blockIdx.x < nscan_blocks) {
-        const int grow = blockIdx.x * LPB + line;
-        const int b = grow / N, i = grow % N;
+    int grow = 0, gl = 0, b = 0, q = 0;
+    if (scan_rows) {
+        grow = blockIdx.x * LPB + line;
+        b = grow / N;
+        const int i = grow % N;
         const size_t base = (size_t)b * N * N;
         const float* sv = saved + (size_t)b * FMBYM_SAVED;
         const float ct = sv[kSavedCos], st = sv[kSavedSin];
@@ -95,11 +98,10 @@ __global__ __launch_bounds__(256) void kb_rows_fwd2(
                 v[m] = make_float2(0.f, 0.f);
             }
         }
-        o1 = rf + ((size_t)b * N + i) * N;
-        o2 = rg + ((size_t)b * N + i) * N;
     } else {
-        const int gl = (blockIdx.x - nscan_blocks) * LPB + line;   // lag-row pair
-        const int b = gl / (N / 2), q = gl % (N / 2);
+        gl = (blockIdx.x - nscan_blocks) * LPB + line;   // lag-row pair
+        b = gl / (N / 2);
+        q = gl % (N / 2);
         const XyAdj adj = make_xy_adj(saved + (size_t)b * FMBYM_SAVED, d_pose + b * 3, temp, delta);
         const float* c1 = c_xy + ((size_t)b * N + 2 * q) * N;
         const float* c2 = c1 + N;
@@ -115,38 +117,34 @@ __global__ __launch_bounds__(256) void kb_rows_fwd2(
                 v[m] = make_float2(0.f, 0.f);
             }
         }
-        o1 = rdc + ((size_t)b * N + 2 * q) * N;
-        o2 = o1 + N;
     }
     fft_line<L, kEb>(v, lre[line], lim[line], t, tw);
     float2 mir[kEb];
     mirror_line<L, kEb>(v, mir, lre[line], lim[line], t);
 #pragma unroll
-    for (int m = 0; m < kEb / 2; ++m) {
+    for (int m = 0; m <= kEb / 2; ++m) {
         const int k = t + m * T;
-        float2 X = split_x(v[m], mir[m]);
-        float2 Y = split_y(v[m], mir[m]);
-        if (k == 0) {
-            const float2 Xn = split_x(v[kEb / 2], mir[kEb / 2]);
-            const float2 Yn = split_y(v[kEb / 2], mir[kEb / 2]);
-            X = make_float2(X.x, Xn.x);
-            Y = make_float2(Y.x, Yn.x);
+        if (k > N) continue;
+        const float2 X = split_x(v[m], mir[m]), Y = split_y(v[m], mir[m]);
+        if (scan_rows) {
+            rf[(size_t)grow * P2 + k] = make_float4(X.x, X.y, Y.x, Y.y);
+        } else {
+            float2* o = rdc + ((size_t)b * N + 2 * q) * P3;
+            o[k] = X;
+            o[P3 + k] = Y;
         }
-        o1[k] = X;
-        o2[k] = Y;
     }
 }
 
-// Column pass of the translation adjoint.  Column col of the packed half
-// spectra (2n-point transforms along the padded rows); writes the n data rows
-// of the two inverse transforms in place of the F and G' inputs.
+// Column pass of the translation adjoint over columns 0 .. n: forward 2n-point
+// column DFTs of F, G' and DC, then X1 = conj(DC) G' and X2 = F DC, inverse
+// column DFTs; the n data rows of (X1, X2) overwrite (F, G') in place.
 template <int N, int C>
-__global__ __launch_bounds__(C * 2 * N / kEb) void kb_cols_xy(float2* __restrict__ rf,
-                                                              float2* __restrict__ rg,
+__global__ __launch_bounds__(C * 2 * N / kEb) void kb_cols_xy(float4* __restrict__ rf,
                                                               const float2* __restrict__ rdc,
                                                               const float2* __restrict__ tw,
                                                               int batch) {
-    constexpr int L = 2 * N, T = L / kEb, TILES = N / C;
+    constexpr int L = 2 * N, T = L / kEb, TILES = N / C + 1, P2 = pitch_rows2(N), P3 = pitch_lag(N);
     __shared__ float lre[C][lds_line_words(L)];
     __shared__ float lim[C][lds_line_words(L)];
     const int total = batch * TILES;
@@ -156,77 +154,57 @@ __global__ __launch_bounds__(C * 2 * N / kEb) void kb_cols_xy(float2* __restrict
     const int c = threadIdx.x % C, t = threadIdx.x / C;
     const int tile = work % TILES, b = work / TILES;
     const int col = tile * C + c;
-    float2* sf = rf + (size_t)b * N * N;
-    float2* sg = rg + (size_t)b * N * N;
-    const float2* sd = rdc + (size_t)b * N * N;
-    float2 vf[kEb], vg[kEb], vd[kEb];
+    float4* sf = rf + (size_t)b * N * P2;
+    const float2* sd = rdc + (size_t)b * N * P3;
+    float2 vd[kEb];
 #pragma unroll
     for (int m = 0; m < kEb; ++m) {
         const int n = t + m * T;
-        if (m < kEb / 2) {
-            vf[m] = sf[(size_t)n * N + col];
-            vg[m] = sg[(size_t)n * N + col];
-        } else {
-            vf[m] = vg[m] = make_float2(0.f, 0.f);
-        }
         // dc lag row o holds s_y = o - n/2, placed at padded row s_y mod 2n
-        if (m < kEb / 4) vd[m] = sd[(size_t)(n + N / 2) * N + col];
-        else if (m >= 3 * kEb / 4) vd[m] = sd[(size_t)(n - 3 * N / 2) * N + col];
+        if (m < kEb / 4) vd[m] = sd[(size_t)(n + N / 2) * P3 + col];
+        else if (m >= 3 * kEb / 4) vd[m] = sd[(size_t)(n - 3 * N / 2) * P3 + col];
         else vd[m] = make_float2(0.f, 0.f);
     }
     fft_line<L, kEb>(vd, lre[c], lim[c], t, tw);
+    float2 vf[kEb], vg[kEb];
+#pragma unroll
+    for (int m = 0; m < kEb; ++m) {
+        if (m < kEb / 2) {
+            const float4 q = sf[(size_t)(t + m * T) * P2 + col];
+            vf[m] = make_float2(q.x, q.y);
+            vg[m] = make_float2(q.z, q.w);
+        } else {
+            vf[m] = vg[m] = make_float2(0.f, 0.f);
+        }
+    }
     fft_line<L, kEb>(vf, lre[c], lim[c], t, tw);
+#pragma unroll
+    for (int m = 0; m < kEb; ++m) vf[m] = cmul(vf[m], vd[m]);          // X2 = F DC
     fft_line<L, kEb>(vg, lre[c], lim[c], t, tw);
-    float2 x1[kEb], x2[kEb];
-    if (tile == 0) {   // packed DC / Nyquist column: split, multiply, repack
-        float2 mf_[kEb], mg_[kEb], md_[kEb];
-        mirror_line<L, kEb>(vf, mf_, lre[c], lim[c], t);
-        mirror_line<L, kEb>(vg, mg_, lre[c], lim[c], t);
-        mirror_line<L, kEb>(vd, md_, lre[c], lim[c], t);
 #pragma unroll
-        for (int m = 0; m < kEb; ++m) {
-            if (c == 0) {
-                const float2 f0 = split_x(vf[m], mf_[m]), fn = split_y(vf[m], mf_[m]);
-                const float2 g0 = split_x(vg[m], mg_[m]), gn = split_y(vg[m], mg_[m]);
-                const float2 d0 = split_x(vd[m], md_[m]), dn = split_y(vd[m], md_[m]);
-                const float2 a0 = cmulcj(d0, g0), an = cmulcj(dn, gn);
-                const float2 b0 = cmul(f0, d0), bn = cmul(fn, dn);
-                x1[m] = make_float2(a0.x - an.y, a0.y + an.x);
-                x2[m] = make_float2(b0.x - bn.y, b0.y + bn.x);
-            } else {
-                x1[m] = cmulcj(vd[m], vg[m]);
-                x2[m] = cmul(vf[m], vd[m]);
-            }
-        }
-    } else {
+    for (int m = 0; m < kEb; ++m) vg[m] = cmulcj(vd[m], vg[m]);        // X1 = conj(DC) G'
+    ifft_line<L, kEb>(vg, lre[c], lim[c], t, tw);
+    ifft_line<L, kEb>(vf, lre[c], lim[c], t, tw);
+    if (col > N) return;
 #pragma unroll
-        for (int m = 0; m < kEb; ++m) {
-            x1[m] = cmulcj(vd[m], vg[m]);
-            x2[m] = cmul(vf[m], vd[m]);
-        }
-    }
-    ifft_line<L, kEb>(x1, lre[c], lim[c], t, tw);
-    ifft_line<L, kEb>(x2, lre[c], lim[c], t, tw);
-#pragma unroll
-    for (int m = 0; m < kEb / 2; ++m) {
-        const int n = t + m * T;
-        sf[(size_t)n * N + col] = x1[m];
-        sg[(size_t)n * N + col] = x2[m];
-    }
+    for (int m = 0; m < kEb / 2; ++m)
+        sf[(size_t)(t + m * T) * P2 + col] = make_float4(vg[m].x, vg[m].y, vf[m].x, vf[m].y);
 }
 
-__device__ __forceinline__ float2 herm_get2(const float2* __restrict__ row, int N, int k) {
-    if (k == 0) return make_float2(row[0].x, 0.f);
-    if (k == N) return make_float2(row[0].y, 0.f);
-    if (k < N) return row[k];
-    return cconj(row[2 * N - k]);
+// Entry k of the full 2n-point Hermitian spectrum from stored columns 0 .. n.
+__device__ __forceinline__ float2 herm_get2(float2 (*get)(const float4*, int), const float4* row,
+                                            int N, int k) {
+    if (k == 0 || k == N) return make_float2(get(row, k).x, 0.f);
+    if (k < N) return get(row, k);
+    return cconj(get(row, 2 * N - k));
 }
+__device__ __forceinline__ float2 get_lo(const float4* row, int k) { return make_float2(row[k].x, row[k].y); }
+__device__ __forceinline__ float2 get_hi(const float4* row, int k) { return make_float2(row[k].z, row[k].w); }
 
 // Inverse rows of the translation adjoint -> df2, dg' (rows < n, columns < n),
 // and the Rotate-path heading gradient dtheta_2 summed per block.
 template <int N>
-__global__ __launch_bounds__(256) void kb_rows_xy(const float2* __restrict__ q1,
-                                                  const float2* __restrict__ q2,
+__global__ __launch_bounds__(256) void kb_rows_xy(const float4* __restrict__ q12,
                                                   const float* __restrict__ g,
                                                   const float* __restrict__ mg,
                                                   const float* __restrict__ hann,
@@ -234,20 +212,19 @@ __global__ __launch_bounds__(256) void kb_rows_xy(const float2* __restrict__ q1,
                                                   const float* __restrict__ saved,
                                                   float* __restrict__ df2, float* __restrict__ dgp,
                                                   float* __restrict__ dth_part, int win) {
-    constexpr int L = 2 * N, T = L / kEb, LPB = 256 / T, PPB = N / LPB;
+    constexpr int L = 2 * N, T = L / kEb, LPB = 256 / T, PPB = N / LPB, P2 = pitch_rows2(N);
     __shared__ float lre[LPB][lds_line_words(L)];
     __shared__ float lim[LPB][lds_line_words(L)];
     __shared__ float red[256];
     const int line = threadIdx.x / T, t = threadIdx.x % T;
     const int grow = blockIdx.x * LPB + line;
     const int b = grow / N, i = grow % N;
-    const float2* r1 = q1 + ((size_t)b * N + i) * N;
-    const float2* r2 = q2 + ((size_t)b * N + i) * N;
+    const float4* row = q12 + (size_t)grow * P2;
     float2 v[kEb];
 #pragma unroll
     for (int m = 0; m < kEb; ++m) {
         const int k = t + m * T;
-        const float2 h1 = herm_get2(r1, N, k), h2 = herm_get2(r2, N, k);
+        const float2 h1 = herm_get2(get_lo, row, N, k), h2 = herm_get2(get_hi, row, N, k);
         v[m] = make_float2(h1.x - h2.y, h1.y + h2.x);
     }
     ifft_line<L, kEb>(v, lre[line], lim[line], t, tw);
@@ -343,12 +320,13 @@ __global__ __launch_bounds__(NT / kEb) void kb_dtheta(const float* __restrict__ 
 // ---------------------------------------------------------- rotation adjoint
 
 // Polar gather + angular DFT of both magnitude spectra (as in the forward),
-// then the angular adjoint: dP_f = IDFT(conj(D) Pg^) / n_r, dP_g = IDFT(Pf^ D) / n_r.
+// then the angular adjoint: dP_f = IDFT(conj(D) Pg^) / n_r, dP_g = IDFT(Pf^ D) / n_r,
+// written interleaved per polar sample.
 template <int NT, int N>
-__global__ __launch_bounds__(256) void kb_polar(const float* __restrict__ A,
+__global__ __launch_bounds__(256) void kb_polar(const float2* __restrict__ A,
                                                 const float2* __restrict__ tw,
                                                 const float2* __restrict__ dspec,
-                                                float* __restrict__ dpol, int n_r, int batch) {
+                                                float2* __restrict__ dpol, int n_r, int batch) {
     constexpr int L = NT, T = L / kEb, LPB = 256 / T, PASSES = (kRadiiPerBlock + LPB - 1) / LPB;
     __shared__ float lre[LPB][lds_line_words(L)];
     __shared__ float lim[LPB][lds_line_words(L)];
@@ -359,8 +337,7 @@ __global__ __launch_bounds__(256) void kb_polar(const float* __restrict__ A,
     if (work >= total) return;
     const int b = work / nrb, rb = work % nrb;
     const int line = threadIdx.x / T, t = threadIdx.x % T;
-    const float* Af = A + (size_t)(b * 2 + 0) * N * mag_pitch(N);
-    const float* Ag = A + (size_t)(b * 2 + 1) * N * mag_pitch(N);
+    const float2* Ab = A + (size_t)b * N * pitch_mag(N);
     float2 D[kEb];
 #pragma unroll
     for (int m = 0; m < kEb; ++m) D[m] = dspec[(size_t)b * NT + t + m * T];
@@ -375,7 +352,7 @@ __global__ __launch_bounds__(256) void kb_polar(const float* __restrict__ A,
             if (live) {
                 float uy, ux;
                 polar_uv(tw, N, n_r, NT, rad, t + m * T, uy, ux);
-                v[m] = make_float2(mag_sample(Af, N, uy, ux), mag_sample(Ag, N, uy, ux));
+                v[m] = mag_sample(Ab, N, uy, ux);
             } else {
                 v[m] = make_float2(0.f, 0.f);
             }
@@ -391,45 +368,69 @@ __global__ __launch_bounds__(256) void kb_polar(const float* __restrict__ A,
             v[m] = make_float2(a.x - c.y, a.y + c.x);   // a + i c
         }
         ifft_line<L, kEb>(v, lre[line], lim[line], t, tw);
-        if (live) {
-            float* of = dpol + ((size_t)(b * 2 + 0) * n_r + rad) * NT;
-            float* og = dpol + ((size_t)(b * 2 + 1) * n_r + rad) * NT;
+        if (live) {   // (dP_f, dP_g) interleaved: the transpose gathers both at once
+            float2* o = dpol + ((size_t)b * n_r + rad) * NT;
 #pragma unroll
-            for (int m = 0; m < kEb; ++m) {
-                of[t + m * T] = v[m].x * scale;
-                og[t + m * T] = v[m].y * scale;
-            }
+            for (int m = 0; m < kEb; ++m) o[t + m * T] = cscale(v[m], scale);
         }
     }
 }
 
-// dA = band * Cart2Pol^T dP over the half-plane bins, from the plan's CSR
-// transpose of the polar gather.  Bins outside the band get 0 without a gather.
-// blockIdx.y walks groups of kDmagGroup (pair, scan) planes that share the
-// block's CSR rows through the cache.
-constexpr int kDmagGroup = 8;
+// dA = Cart2Pol^T dP over the half-plane bins, from the plan's CSR transpose
+// of the polar gather (rows of bins outside the band are empty, so they come
+// out 0).  A block owns 256 consecutive bins and kDmagPairs pairs.  Its CSR
+// slice is staged in LDS once; for each pair every thread forms the products
+// w * (dP_f, dP_g) of a strided set of entries (independent, coalesced
+// gathers), then each bin sums its own segment from LDS in entry order.
+// Slices longer than the LDS stage are processed in chunks, still in order.
+constexpr int kDmagPairs = 4;
+constexpr int kDmagStage = 4096;
 __global__ __launch_bounds__(256) void kb_dmag(const int* __restrict__ ptr, const int* __restrict__ col,
                                                const float* __restrict__ val,
-                                               const float* __restrict__ dpol, float* __restrict__ dA,
-                                               int n, int n_r, int n_theta, int planes, int band_on,
-                                               int lo2, int hi2) {
-    const int h1 = n / 2 + 1;
-    const int bin = blockIdx.x * blockDim.x + threadIdx.x;
-    if (bin >= n * h1) return;
-    const int ky = bin / h1, kx = bin % h1;
-    const int kys = ky < n / 2 ? ky : ky - n;
-    const int r2 = kys * kys + kx * kx;
-    const bool in_band = !band_on || (r2 >= lo2 && r2 <= hi2);
-    const int e0 = ptr[bin], e1 = ptr[bin + 1];
+                                               const float2* __restrict__ dpol, float2* __restrict__ dA,
+                                               int n, int n_r, int n_theta, int batch) {
+    __shared__ int lcol[kDmagStage];
+    __shared__ float lval[kDmagStage];
+    __shared__ float2 prod[kDmagStage];
+    __shared__ int lptr[257];
+    const int h1 = n / 2 + 1, nbins = n * h1;
+    const int bin0 = blockIdx.x * 256;
+    const int nb = min(256, nbins - bin0);
+    const int tid = threadIdx.x;
+    for (int i = tid; i <= nb; i += 256) lptr[i] = ptr[bin0 + i];
+    __syncthreads();
+    const int e_begin = lptr[0], e_end = lptr[nb];
     const size_t pstride = (size_t)n_r * n_theta;
-    const int p0 = blockIdx.y * kDmagGroup, p1 = min(planes, p0 + kDmagGroup);
-    for (int ps = p0; ps < p1; ++ps) {
-        float acc = 0.f;
-        if (in_band) {
-            const float* src = dpol + (size_t)ps * pstride;
-            for (int e = e0; e < e1; ++e) acc += val[e] * src[col[e]];
+    const int p0 = blockIdx.y * kDmagPairs, p1 = min(batch, p0 + kDmagPairs);
+    const bool staged = e_end - e_begin <= kDmagStage;
+    if (staged) {
+        for (int e = e_begin + tid; e < e_end; e += 256) {
+            lcol[e - e_begin] = col[e];
+            lval[e - e_begin] = val[e];
         }
-        dA[((size_t)ps * n + ky) * mag_pitch(n) + kx] = acc;
+    }
+    __syncthreads();
+    const int my0 = tid < nb ? lptr[tid] : 0, my1 = tid < nb ? lptr[tid + 1] : 0;
+    for (int pr = p0; pr < p1; ++pr) {
+        const float2* src = dpol + (size_t)pr * pstride;
+        float2 acc = make_float2(0.f, 0.f);
+        for (int c0 = e_begin; c0 < e_end; c0 += kDmagStage) {
+            const int c1 = min(e_end, c0 + kDmagStage);
+            for (int e = c0 + tid; e < c1; e += 256) {
+                const int k = e - c0;
+                const int cc = staged ? lcol[k] : col[e];
+                const float w = staged ? lval[k] : val[e];
+                prod[k] = cscale(src[cc], w);
+            }
+            __syncthreads();
+            const int a = max(my0, c0), z = min(my1, c1);
+            for (int e = a; e < z; ++e) acc = cadd(acc, prod[e - c0]);
+            __syncthreads();
+        }
+        if (tid < nb) {
+            const int bin = bin0 + tid, ky = bin / h1, kx = bin % h1;
+            dA[((size_t)pr * n + ky) * pitch_mag(n) + kx] = acc;
+        }
     }
 }
 
@@ -446,57 +447,43 @@ __device__ __forceinline__ float2 mag_adjoint(float2 F, float dA) {
 // the unnormalised inverse column DFT.  For the packed DC/Nyquist column only
 // the real parts of the inverse are needed: the inverse of the Hermitian part
 // of each, both through one transform.
+// Column pass of the rotation adjoint over columns 0 .. n/2, in place over the
+// stage-1 row spectra: column DFTs again, dF = dA F / |F| (dA already
+// carries the band gain), unnormalised inverse column DFT.  For columns 0 and
+// n/2 the row pass uses only the real part of the result.
 template <int N, int C>
-__global__ __launch_bounds__(C * N / kEb) void kb_cols_mag(float2* __restrict__ r1,
-                                                           const float* __restrict__ dA,
+__global__ __launch_bounds__(C * N / kEb) void kb_cols_mag(float4* __restrict__ r1,
+                                                           const float2* __restrict__ dA,
                                                            const float2* __restrict__ tw) {
-    constexpr int L = N, T = L / kEb, H = N / 2, TILES = H / C, P = mag_pitch(N);
+    constexpr int L = N, T = L / kEb, H = N / 2, TILES = H / C + 1, P1 = pitch_rows1(N), PA = pitch_mag(N);
     __shared__ float lre[C][lds_line_words(L)];
     __shared__ float lim[C][lds_line_words(L)];
     const int c = threadIdx.x % C, t = threadIdx.x / C;
-    const int tile = blockIdx.x % TILES, bs = blockIdx.x / TILES;
+    const int tile = blockIdx.x % TILES, b = blockIdx.x / TILES;
     const int col = tile * C + c;
-    float2* src = r1 + (size_t)bs * N * H;
-    const float* da = dA + (size_t)bs * N * P;
-    float2 v[kEb];
+    float4* src = r1 + (size_t)b * N * P1;
+    const float2* da = dA + (size_t)b * N * PA;
+    float2 vf[kEb], vg[kEb];
 #pragma unroll
-    for (int m = 0; m < kEb; ++m) v[m] = src[(size_t)(t + m * T) * H + col];
-    fft_line<L, kEb>(v, lre[c], lim[c], t, tw);
-    if (tile == 0) {
-        float2 mir[kEb];
-        mirror_line<L, kEb>(v, mir, lre[c], lim[c], t);
-        float2 d0[kEb], dn[kEb];
-#pragma unroll
-        for (int m = 0; m < kEb; ++m) {
-            const int ky = t + m * T;
-            if (c == 0) {
-                d0[m] = mag_adjoint(split_x(v[m], mir[m]), da[ky * P + 0]);
-                dn[m] = mag_adjoint(split_y(v[m], mir[m]), da[ky * P + H]);
-            } else {
-                d0[m] = mag_adjoint(v[m], da[ky * P + col]);
-                dn[m] = make_float2(0.f, 0.f);
-            }
-        }
-        float2 m0[kEb], mn[kEb];
-        mirror_line<L, kEb>(d0, m0, lre[c], lim[c], t);
-        mirror_line<L, kEb>(dn, mn, lre[c], lim[c], t);
-#pragma unroll
-        for (int m = 0; m < kEb; ++m) {
-            if (c == 0) {
-                const float2 s0 = make_float2(0.5f * (d0[m].x + m0[m].x), 0.5f * (d0[m].y - m0[m].y));
-                const float2 sn = make_float2(0.5f * (dn[m].x + mn[m].x), 0.5f * (dn[m].y - mn[m].y));
-                v[m] = make_float2(s0.x - sn.y, s0.y + sn.x);
-            } else {
-                v[m] = d0[m];
-            }
-        }
-    } else {
-#pragma unroll
-        for (int m = 0; m < kEb; ++m) v[m] = mag_adjoint(v[m], da[(t + m * T) * P + col]);
+    for (int m = 0; m < kEb; ++m) {
+        const float4 q = src[(size_t)(t + m * T) * P1 + col];
+        vf[m] = make_float2(q.x, q.y);
+        vg[m] = make_float2(q.z, q.w);
     }
-    ifft_line<L, kEb>(v, lre[c], lim[c], t, tw);
+    fft_line<L, kEb>(vf, lre[c], lim[c], t, tw);
+    fft_line<L, kEb>(vg, lre[c], lim[c], t, tw);
 #pragma unroll
-    for (int m = 0; m < kEb; ++m) src[(size_t)(t + m * T) * H + col] = v[m];
+    for (int m = 0; m < kEb; ++m) {
+        const float2 d = col <= H ? da[(t + m * T) * PA + col] : make_float2(0.f, 0.f);
+        vf[m] = mag_adjoint(vf[m], d.x);
+        vg[m] = mag_adjoint(vg[m], d.y);
+    }
+    ifft_line<L, kEb>(vf, lre[c], lim[c], t, tw);
+    ifft_line<L, kEb>(vg, lre[c], lim[c], t, tw);
+    if (col > H) return;
+#pragma unroll
+    for (int m = 0; m < kEb; ++m)
+        src[(size_t)(t + m * T) * P1 + col] = make_float4(vf[m].x, vf[m].y, vg[m].x, vg[m].y);
 }
 
 // Rotate^T of dg' at scan pixel (qr, qc): sum over output pixels whose
@@ -520,37 +507,39 @@ __device__ __forceinline__ float rotate_adjoint(const float* __restrict__ dgp, i
     return acc;
 }
 
-// Inverse row DFT of the rotation adjoint (Re part via the Hermitian
-// extension, f and g paired), plus the translation-stage terms, then the
-// window and mask adjoints.
+// Inverse row DFT of the rotation adjoint: df_w[x] = Re sum_{k <= n/2} Q[k] e^{+2 pi i k x / n},
+// formed as the inverse DFT of the Hermitian extension (Re Q at k = 0, n/2;
+// Q/2 and conj(Q)/2 elsewhere), f and g paired in one transform.  Adds the
+// translation-stage terms (Rotate^T gathered here), then the window and mask
+// adjoints.
 template <int N>
 __global__ __launch_bounds__(256) void kb_rows_final(
-    const float2* __restrict__ r1, const float* __restrict__ df2, const float* __restrict__ dgp,
+    const float4* __restrict__ r1, const float* __restrict__ df2, const float* __restrict__ dgp,
     const float* __restrict__ f, const float* __restrict__ g, const float* __restrict__ mf,
     const float* __restrict__ mg, const float* __restrict__ hann, const float2* __restrict__ tw,
     const float* __restrict__ saved, float* __restrict__ d_f, float* __restrict__ d_g,
     float* __restrict__ d_mf, float* __restrict__ d_mg, int win, int win2) {
-    constexpr int L = N, T = L / kEb, LPB = 256 / T, H = N / 2;
+    constexpr int L = N, T = L / kEb, LPB = 256 / T, H = N / 2, P1 = pitch_rows1(N);
     __shared__ float lre[LPB][lds_line_words(L)];
     __shared__ float lim[LPB][lds_line_words(L)];
     const int line = threadIdx.x / T, t = threadIdx.x % T;
     const int grow = blockIdx.x * LPB + line;
     const int b = grow / N, i = grow % N;
-    const float2* qf = r1 + ((size_t)(b * 2 + 0) * N + i) * H;
-    const float2* qg = r1 + ((size_t)(b * 2 + 1) * N + i) * H;
+    const float4* q = r1 + (size_t)grow * P1;
     float2 v[kEb];
 #pragma unroll
     for (int m = 0; m < kEb; ++m) {
         const int k = t + m * T;
         float2 z;
-        if (k == 0) z = make_float2(qf[0].x, qg[0].x);
-        else if (k == H) z = make_float2(qf[0].y, qg[0].y);
-        else if (k < H) {
-            const float2 a = qf[k], c = qg[k];
-            z = make_float2(0.5f * (a.x - c.y), 0.5f * (a.y + c.x));
+        if (k == 0 || k == H) {
+            const float4 a = q[k];
+            z = make_float2(a.x, a.z);
+        } else if (k < H) {
+            const float4 a = q[k];                       // (Qf, Qg)
+            z = make_float2(0.5f * (a.x - a.w), 0.5f * (a.y + a.z));
         } else {
-            const float2 a = qf[N - k], c = qg[N - k];
-            z = make_float2(0.5f * (a.x + c.y), 0.5f * (c.x - a.y));
+            const float4 a = q[N - k];
+            z = make_float2(0.5f * (a.x + a.w), 0.5f * (a.z - a.y));
         }
         v[m] = z;
     }
@@ -590,28 +579,26 @@ __global__ __launch_bounds__(256) void kb_rows_final(
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct BwdLayout {
-    size_t fwd_end;   // stage-1 recomputation reuses the forward layout's first regions
-    size_t rf, rg, rdc, df2, dgp, dpol, dth, dspec, total;
+    size_t rf, rdc, df2, dgp, dpol, dth, dspec, total;
 };
 
+// The stage-1 recomputation reuses the forward layout's first two regions;
+// the adjoint's own buffers follow it.
 static BwdLayout bwd_layout(const fmbym_params& p, int batch) {
     const size_t n = p.n, B = batch;
     const FwdLayout f = fwd_layout(p, batch);
     BwdLayout L{};
     size_t off = f.total;
-    L.fwd_end = off;
     L.rf = off;
-    off = al256(off + B * n * n * sizeof(float2));
-    L.rg = off;
-    off = al256(off + B * n * n * sizeof(float2));
+    off = al256(off + B * n * (size_t)pitch_rows2(p.n) * sizeof(float4));
     L.rdc = off;
-    off = al256(off + B * n * n * sizeof(float2));
+    off = al256(off + B * n * (size_t)pitch_lag(p.n) * sizeof(float2));
     L.df2 = off;
     off = al256(off + B * n * n * sizeof(float));
     L.dgp = off;
     off = al256(off + B * n * n * sizeof(float));
     L.dpol = off;
-    off = al256(off + B * 2 * (size_t)p.n_r * p.n_theta * sizeof(float));
+    off = al256(off + B * (size_t)p.n_r * p.n_theta * sizeof(float2));
     L.dth = off;
     off = al256(off + B * n * sizeof(float));
     L.dspec = off;
@@ -623,7 +610,7 @@ static BwdLayout bwd_layout(const fmbym_params& p, int batch) {
 size_t bwd_workspace(const fmbym_params& p, int batch) { return bwd_layout(p, batch).total; }
 
 template <int N, int NT>
-static void launch_bwd_polar(const Plan& pl, int B, const float* A, const float2* dspec, float* dpol,
+static void launch_bwd_polar(const Plan& pl, int B, const float2* A, const float2* dspec, float2* dpol,
                              hipStream_t s) {
     const int nrb = radius_blocks(pl.p.n_r);
     const int total = B * nrb;
@@ -638,6 +625,9 @@ static void launch_dtheta(const Plan& pl, int B, int ppb, const float* dth, cons
                  pl.twiddle, pl.p.temp_theta, dspec);
 }
 
+template <int N> constexpr int bcols_xy_tile() { return N >= 256 ? 8 : 16; }
+template <int N> constexpr int bcols_mag_tile() { return N >= 512 ? 8 : 16; }
+
 template <int N>
 static int launch_bwd_n(const Plan& pl, int B, const float* f, const float* g, const float* mf,
                         const float* mg, const float* c_theta, const float* c_xy, const float* saved,
@@ -645,16 +635,15 @@ static int launch_bwd_n(const Plan& pl, int B, const float* f, const float* g, c
                         char* ws, hipStream_t s) {
     const FwdLayout fl = fwd_layout(pl.p, B);
     const BwdLayout bl = bwd_layout(pl.p, B);
-    float2* rf = (float2*)(ws + bl.rf);
-    float2* rg = (float2*)(ws + bl.rg);
+    float4* rf = (float4*)(ws + bl.rf);
     float2* rdc = (float2*)(ws + bl.rdc);
     float* df2 = (float*)(ws + bl.df2);
     float* dgp = (float*)(ws + bl.dgp);
-    float* dpol = (float*)(ws + bl.dpol);
+    float2* dpol = (float2*)(ws + bl.dpol);
     float* dth = (float*)(ws + bl.dth);
     float2* dspec = (float2*)(ws + bl.dspec);
-    float2* r1 = (float2*)(ws + fl.r1r2);
-    float* mag = (float*)(ws + fl.mag_r3);
+    float4* r1 = (float4*)(ws + fl.r1r2);
+    float2* mag = (float2*)(ws + fl.mag_r3);
     const int win = (pl.p.flags & FMBYM_HANN) ? 1 : 0;
     const int win2 = (win && !(pl.p.flags & FMBYM_XY_UNWINDOWED)) ? 1 : 0;
 
@@ -662,15 +651,13 @@ static int launch_bwd_n(const Plan& pl, int B, const float* f, const float* g, c
     constexpr int T2 = 2 * N / kEb, LPB2 = 256 / T2;
     const int scan_blocks = B * N / LPB2, dc_blocks = B * (N / 2) / LPB2;
     FMBYM_LAUNCH(kKBRowsFwd2, kb_rows_fwd2<N>, dim3(scan_blocks + dc_blocks), dim3(256), s, f, g, mf, mg,
-                 pl.hann, pl.twiddle, saved, c_xy, d_pose, rf, rg, rdc, win2, B, pl.p.temp_xy,
+                 pl.hann, pl.twiddle, saved, c_xy, d_pose, rf, rdc, win2, B, pl.p.temp_xy,
                  pl.p.delta_xy);
-    // 512-thread blocks: the three transforms per column need more than the
-    // 128 registers a 1024-thread block leaves each lane
-    constexpr int C2 = N >= 512 ? 4 : (N >= 256 ? 8 : 16);
-    const int total2 = B * (N / C2);
+    constexpr int C2 = bcols_xy_tile<N>();
+    const int total2 = B * (N / C2 + 1);
     FMBYM_LAUNCH(kKBColsXy, (kb_cols_xy<N, C2>), dim3(((total2 + 7) / 8) * 8), dim3(C2 * 2 * N / kEb), s,
-                 rf, rg, rdc, pl.twiddle, B);
-    FMBYM_LAUNCH(kKBRowsXy, kb_rows_xy<N>, dim3(B * N / LPB2), dim3(256), s, rf, rg, g, mg, pl.hann,
+                 rf, rdc, pl.twiddle, B);
+    FMBYM_LAUNCH(kKBRowsXy, kb_rows_xy<N>, dim3(B * N / LPB2), dim3(256), s, rf, g, mg, pl.hann,
                  pl.twiddle, saved, df2, dgp, dth, win2);
     const int ppb = N / LPB2;
     switch (pl.p.n_theta) {
@@ -696,17 +683,17 @@ static int launch_bwd_n(const Plan& pl, int B, const float* f, const float* g, c
         case 1024: launch_bwd_polar<N, 1024>(pl, B, mag, dspec, dpol, s); break;
         default: return FMBYM_EUNSUPPORTED;
     }
-    float* dA = mag;                    // the recomputed magnitudes are dead after kb_polar
+    float2* dA = mag;                   // the recomputed magnitudes are dead after kb_polar
     const int nbins = N * (N / 2 + 1);
-    FMBYM_LAUNCH(kKBDmag, kb_dmag, dim3((nbins + 255) / 256, (2 * B + kDmagGroup - 1) / kDmagGroup),
+    FMBYM_LAUNCH(kKBDmag, kb_dmag, dim3((nbins + 255) / 256, (B + kDmagPairs - 1) / kDmagPairs),
                  dim3(256), s, pl.csr_ptr, pl.csr_col, pl.csr_val, dpol, dA, N, pl.p.n_r, pl.p.n_theta,
-                 2 * B, pl.band_on, pl.band_lo2, pl.band_hi2);
-    constexpr int C = 16;
-    FMBYM_LAUNCH(kKBColsMag, (kb_cols_mag<N, C>), dim3(B * 2 * (N / 2) / C), dim3(C * N / kEb), s, r1, dA,
-                 pl.twiddle);
+                 B);
+    constexpr int C = bcols_mag_tile<N>();
+    FMBYM_LAUNCH(kKBColsMag, (kb_cols_mag<N, C>), dim3(B * ((N / 2) / C + 1)), dim3(C * N / kEb), s, r1,
+                 dA, pl.twiddle);
     constexpr int T1 = N / kEb, LPB1 = 256 / T1;
-    FMBYM_LAUNCH(kKBRowsFinal, kb_rows_final<N>, dim3(B * N / LPB1), dim3(256), s, r1, df2, dgp, f, g, mf, mg,
-                 pl.hann, pl.twiddle, saved, d_f, d_g, d_mf, d_mg, win, win2);
+    FMBYM_LAUNCH(kKBRowsFinal, kb_rows_final<N>, dim3(B * N / LPB1), dim3(256), s, r1, df2, dgp, f, g, mf,
+                 mg, pl.hann, pl.twiddle, saved, d_f, d_g, d_mf, d_mg, win, win2);
     return FMBYM_OK;
 }
 

@@ -1,9 +1,9 @@
 // Forward decoupled search (Algorithm 1) on gfx950.
 //
 // Stage 1 (heading, Eq. 5-8)
-//   k_rows1      Hann (+mask) and row DFTs of f + i g, split into the two
-//                half spectra (one complex FFT serves both real scans).
-//   k_cols1      column DFTs of each half spectrum, band-pass and magnitude.
+//   k_rows1      Hann (+mask) and row DFTs of f + i g (one complex FFT serves
+//                both real scans), split into the two spectra, n/2 + 1 columns.
+//   k_cols1      column DFTs of both spectra, band-pass and magnitude.
 //   k_polar      bilinear polar gather of both magnitude spectra, angular DFT
 //                per radius, conj(A_f) A_g summed over a block of radii.
 //   k_angle_fin  sum over radius blocks, inverse angular DFT -> c_theta,
@@ -16,7 +16,11 @@
 //                online-softmax partials.
 //   k_xy_fin     fixed-order merge of the partials -> t' -> t = R(theta) t'.
 //
-// All reductions are in a fixed order; the result is bitwise reproducible.
+// Data between passes: row kernels write the two spectra they produce
+// interleaved (float4 per column), so a column tile of 8 reads 128-byte
+// segments; every row keeps all its unique columns (0 .. n/2 or 0 .. n), so
+// column kernels treat every column alike.  All reductions are in a fixed
+// order; results are bitwise reproducible.
 #include "internal.hpp"
 #include "profile.hpp"
 
@@ -30,14 +34,14 @@ template <int N>
 __global__ __launch_bounds__(256) void k_rows1(const float* __restrict__ f, const float* __restrict__ g,
                                                const float* __restrict__ mf, const float* __restrict__ mg,
                                                const float* __restrict__ hann,
-                                               const float2* __restrict__ tw, float2* __restrict__ out,
+                                               const float2* __restrict__ tw, float4* __restrict__ out,
                                                int win) {
-    constexpr int L = N, T = L / kE, LPB = 256 / T, H = N / 2;
+    constexpr int L = N, T = L / kE, LPB = 256 / T, H = N / 2, P = pitch_rows1(N);
     __shared__ float lre[LPB][lds_line_words(L)];
     __shared__ float lim[LPB][lds_line_words(L)];
     const int line = threadIdx.x / T, t = threadIdx.x % T;
     const int grow = blockIdx.x * LPB + line;     // row over the batch
-    const int b = grow / N, i = grow % N;
+    const int i = grow % N;
     const size_t off = (size_t)grow * N;
     const float* fr = f + off;
     const float* gr = g + off;
@@ -57,21 +61,14 @@ __global__ __launch_bounds__(256) void k_rows1(const float* __restrict__ f, cons
     fft_line<L, kE>(v, lre[line], lim[line], t, tw);
     float2 mir[kE];
     mirror_line<L, kE>(v, mir, lre[line], lim[line], t);
-    float2* of = out + ((size_t)(b * 2 + 0) * N + i) * H;
-    float2* og = out + ((size_t)(b * 2 + 1) * N + i) * H;
+    float4* o = out + (size_t)grow * P;
 #pragma unroll
-    for (int m = 0; m < kE / 2; ++m) {
+    for (int m = 0; m <= kE / 2; ++m) {
         const int k = t + m * T;
-        float2 X = split_x(v[m], mir[m]);
-        float2 Y = split_y(v[m], mir[m]);
-        if (k == 0) {   // F[0] and F[n/2] are real: pack them in one slot
-            const float2 Xn = split_x(v[kE / 2], mir[kE / 2]);
-            const float2 Yn = split_y(v[kE / 2], mir[kE / 2]);
-            X = make_float2(X.x, Xn.x);
-            Y = make_float2(Y.x, Yn.x);
+        if (k <= H) {
+            const float2 X = split_x(v[m], mir[m]), Y = split_y(v[m], mir[m]);
+            o[k] = make_float4(X.x, X.y, Y.x, Y.y);
         }
-        of[k] = X;
-        og[k] = Y;
     }
 }
 
@@ -81,48 +78,39 @@ __device__ __forceinline__ float band_gain(int ky_signed, int kx, int on, int lo
     return (r2 >= lo2 && r2 <= hi2) ? 1.f : 0.f;
 }
 
+// Column DFTs of both stage-1 spectra and their band-passed magnitudes,
+// written interleaved.  Tiles of C columns cover 0 .. n/2; the last tile has
+// one live column.
 template <int N, int C>
-__global__ __launch_bounds__(C * N / kE) void k_cols1(const float2* __restrict__ in,
-                                                      float* __restrict__ A,
+__global__ __launch_bounds__(C * N / kE) void k_cols1(const float4* __restrict__ in,
+                                                      float2* __restrict__ A,
                                                       const float2* __restrict__ tw, int band_on,
                                                       int lo2, int hi2) {
-    constexpr int L = N, T = L / kE, H = N / 2, P = mag_pitch(N), TILES = H / C;
+    constexpr int L = N, T = L / kE, H = N / 2, P1 = pitch_rows1(N), PA = pitch_mag(N);
+    constexpr int TILES = H / C + 1;
     __shared__ float lre[C][lds_line_words(L)];
     __shared__ float lim[C][lds_line_words(L)];
     const int c = threadIdx.x % C, t = threadIdx.x / C;
-    const int tile = blockIdx.x % TILES, bs = blockIdx.x / TILES;   // bs = pair * 2 + scan
+    const int tile = blockIdx.x % TILES, b = blockIdx.x / TILES;
     const int col = tile * C + c;
-    const float2* src = in + (size_t)bs * N * H;
-    float2 v[kE];
+    const float4* src = in + (size_t)b * N * P1;
+    float2 vf[kE], vg[kE];
 #pragma unroll
-    for (int m = 0; m < kE; ++m) v[m] = src[(size_t)(t + m * T) * H + col];
-    fft_line<L, kE>(v, lre[c], lim[c], t, tw);
-    float* dst = A + (size_t)bs * N * P;
-    if (tile == 0) {   // column 0 packs the real DC and Nyquist columns: split them
-        float2 mir[kE];
-        mirror_line<L, kE>(v, mir, lre[c], lim[c], t);
+    for (int m = 0; m < kE; ++m) {
+        const float4 q = src[(size_t)(t + m * T) * P1 + col];
+        vf[m] = make_float2(q.x, q.y);
+        vg[m] = make_float2(q.z, q.w);
+    }
+    fft_line<L, kE>(vf, lre[c], lim[c], t, tw);
+    fft_line<L, kE>(vg, lre[c], lim[c], t, tw);
+    if (col > H) return;   // padding lane of the last tile (no barriers follow)
+    float2* dst = A + (size_t)b * N * PA;
 #pragma unroll
-        for (int m = 0; m < kE; ++m) {
-            const int ky = t + m * T;
-            const int kys = ky < H ? ky : ky - N;
-            if (c == 0) {
-                const float2 X0 = split_x(v[m], mir[m]);
-                const float2 XN = split_y(v[m], mir[m]);
-                dst[ky * P + 0] = sqrtf(X0.x * X0.x + X0.y * X0.y) * band_gain(kys, 0, band_on, lo2, hi2);
-                dst[ky * P + H] = sqrtf(XN.x * XN.x + XN.y * XN.y) * band_gain(kys, H, band_on, lo2, hi2);
-            } else {
-                dst[ky * P + col] =
-                    sqrtf(v[m].x * v[m].x + v[m].y * v[m].y) * band_gain(kys, col, band_on, lo2, hi2);
-            }
-        }
-    } else {
-#pragma unroll
-        for (int m = 0; m < kE; ++m) {
-            const int ky = t + m * T;
-            const int kys = ky < H ? ky : ky - N;
-            dst[ky * P + col] =
-                sqrtf(v[m].x * v[m].x + v[m].y * v[m].y) * band_gain(kys, col, band_on, lo2, hi2);
-        }
+    for (int m = 0; m < kE; ++m) {
+        const int ky = t + m * T;
+        const float gain = band_gain(ky < H ? ky : ky - N, col, band_on, lo2, hi2);
+        dst[ky * PA + col] = make_float2(sqrtf(vf[m].x * vf[m].x + vf[m].y * vf[m].y) * gain,
+                                         sqrtf(vg[m].x * vg[m].x + vg[m].y * vg[m].y) * gain);
     }
 }
 
@@ -130,7 +118,7 @@ __global__ __launch_bounds__(C * N / kE) void k_cols1(const float2* __restrict__
 // that all blocks of one pair run on the same XCD (its L2 keeps the pair's
 // magnitude spectra).
 template <int NT, int N>
-__global__ __launch_bounds__(256) void k_polar(const float* __restrict__ A,
+__global__ __launch_bounds__(256) void k_polar(const float2* __restrict__ A,
                                                const float2* __restrict__ tw,
                                                float2* __restrict__ part, int n_r, int batch) {
     constexpr int L = NT, T = L / kE, LPB = 256 / T, PASSES = (kRadiiPerBlock + LPB - 1) / LPB;
@@ -145,8 +133,7 @@ __global__ __launch_bounds__(256) void k_polar(const float* __restrict__ A,
     if (work >= total) return;   // block-uniform
     const int b = work / nrb, rb = work % nrb;
     const int line = threadIdx.x / T, t = threadIdx.x % T;
-    const float* Af = A + (size_t)(b * 2 + 0) * N * mag_pitch(N);
-    const float* Ag = A + (size_t)(b * 2 + 1) * N * mag_pitch(N);
+    const float2* Ab = A + (size_t)b * N * pitch_mag(N);
     float2 acc[kE / 2 + 1];
 #pragma unroll
     for (int m = 0; m <= kE / 2; ++m) acc[m] = make_float2(0.f, 0.f);
@@ -160,7 +147,7 @@ __global__ __launch_bounds__(256) void k_polar(const float* __restrict__ A,
             if (live) {
                 float uy, ux;
                 polar_uv(tw, N, n_r, NT, rad, t + m * T, uy, ux);
-                v[m] = make_float2(mag_sample(Af, N, uy, ux), mag_sample(Ag, N, uy, ux));
+                v[m] = mag_sample(Ab, N, uy, ux);
             } else {
                 v[m] = make_float2(0.f, 0.f);
             }
@@ -349,8 +336,8 @@ __global__ __launch_bounds__(256) void k_rows2(const float* __restrict__ f, cons
                                                const float* __restrict__ hann,
                                                const float2* __restrict__ tw,
                                                const float* __restrict__ saved,
-                                               float2* __restrict__ out, int win) {
-    constexpr int L = 2 * N, T = L / kE, LPB = 256 / T;
+                                               float4* __restrict__ out, int win) {
+    constexpr int L = 2 * N, T = L / kE, LPB = 256 / T, P2 = pitch_rows2(N);
     __shared__ float lre[LPB][lds_line_words(L)];
     __shared__ float lim[LPB][lds_line_words(L)];
     const int line = threadIdx.x / T, t = threadIdx.x % T;
@@ -376,29 +363,25 @@ __global__ __launch_bounds__(256) void k_rows2(const float* __restrict__ f, cons
     fft_line<L, kE>(v, lre[line], lim[line], t, tw);
     float2 mir[kE];
     mirror_line<L, kE>(v, mir, lre[line], lim[line], t);
-    float2* of = out + ((size_t)(b * 2 + 0) * N + i) * N;
-    float2* og = out + ((size_t)(b * 2 + 1) * N + i) * N;
+    float4* o = out + (size_t)grow * P2;
 #pragma unroll
-    for (int m = 0; m < kE / 2; ++m) {
+    for (int m = 0; m <= kE / 2; ++m) {
         const int k = t + m * T;
-        float2 X = split_x(v[m], mir[m]);
-        float2 Y = split_y(v[m], mir[m]);
-        if (k == 0) {
-            const float2 Xn = split_x(v[kE / 2], mir[kE / 2]);
-            const float2 Yn = split_y(v[kE / 2], mir[kE / 2]);
-            X = make_float2(X.x, Xn.x);
-            Y = make_float2(Y.x, Yn.x);
+        if (k <= N) {
+            const float2 X = split_x(v[m], mir[m]), Y = split_y(v[m], mir[m]);
+            o[k] = make_float4(X.x, X.y, Y.x, Y.y);
         }
-        of[k] = X;
-        og[k] = Y;
     }
 }
 
+// Column pass of stage 2 over columns 0 .. n of the padded row spectra:
+// forward column DFTs of F and G' (n data rows, n zero rows), conj(F) G',
+// inverse column DFT; the n central lag rows are kept.
 template <int N, int C>
-__global__ __launch_bounds__(C * 2 * N / kE) void k_cols2(const float2* __restrict__ in,
+__global__ __launch_bounds__(C * 2 * N / kE) void k_cols2(const float4* __restrict__ in,
                                                           const float2* __restrict__ tw,
                                                           float2* __restrict__ out, int batch) {
-    constexpr int L = 2 * N, T = L / kE, TILES = N / C;
+    constexpr int L = 2 * N, T = L / kE, TILES = N / C + 1, P2 = pitch_rows2(N), P3 = pitch_lag(N);
     __shared__ float lre[C][lds_line_words(L)];
     __shared__ float lim[C][lds_line_words(L)];
     const int total = batch * TILES;
@@ -408,55 +391,37 @@ __global__ __launch_bounds__(C * 2 * N / kE) void k_cols2(const float2* __restri
     const int c = threadIdx.x % C, t = threadIdx.x / C;
     const int tile = work % TILES, b = work / TILES;
     const int col = tile * C + c;
-    const float2* sf = in + (size_t)(b * 2 + 0) * N * N;
-    const float2* sg = in + (size_t)(b * 2 + 1) * N * N;
+    const float4* src = in + (size_t)b * N * P2;
     float2 vf[kE], vg[kE];
 #pragma unroll
     for (int m = 0; m < kE; ++m) {
-        const int row = t + m * T;
         if (m < kE / 2) {
-            vf[m] = sf[(size_t)row * N + col];
-            vg[m] = sg[(size_t)row * N + col];
+            const float4 q = src[(size_t)(t + m * T) * P2 + col];
+            vf[m] = make_float2(q.x, q.y);
+            vg[m] = make_float2(q.z, q.w);
         } else {
-            vf[m] = make_float2(0.f, 0.f);
-            vg[m] = make_float2(0.f, 0.f);
+            vf[m] = vg[m] = make_float2(0.f, 0.f);
         }
     }
     fft_line<L, kE>(vf, lre[c], lim[c], t, tw);
     fft_line<L, kE>(vg, lre[c], lim[c], t, tw);
-    float2 p[kE];
-    if (tile == 0) {   // column 0 packs the real DC and Nyquist columns of the padded rows
-        float2 mf_[kE], mg_[kE];
-        mirror_line<L, kE>(vf, mf_, lre[c], lim[c], t);
-        mirror_line<L, kE>(vg, mg_, lre[c], lim[c], t);
 #pragma unroll
-        for (int m = 0; m < kE; ++m) {
-            if (c == 0) {
-                const float2 p0 = cmulcj(split_x(vf[m], mf_[m]), split_x(vg[m], mg_[m]));
-                const float2 pn = cmulcj(split_y(vf[m], mf_[m]), split_y(vg[m], mg_[m]));
-                p[m] = make_float2(p0.x - pn.y, p0.y + pn.x);   // p0 + i pn
-            } else {
-                p[m] = cmulcj(vf[m], vg[m]);
-            }
-        }
-    } else {
-#pragma unroll
-        for (int m = 0; m < kE; ++m) p[m] = cmulcj(vf[m], vg[m]);
-    }
-    ifft_line<L, kE>(p, lre[c], lim[c], t, tw);
-    float2* dst = out + (size_t)b * N * N;
+    for (int m = 0; m < kE; ++m) vf[m] = cmulcj(vf[m], vg[m]);
+    ifft_line<L, kE>(vf, lre[c], lim[c], t, tw);
+    if (col > N) return;
+    float2* dst = out + (size_t)b * N * P3;
 #pragma unroll
     for (int m = 0; m < kE; ++m) {
         const int n = t + m * T;                 // lag row s_y = n (n < N/2) or n - 2N (n >= 3N/2)
-        if (n < N / 2) dst[(size_t)(n + N / 2) * N + col] = p[m];
-        else if (n >= 3 * N / 2) dst[(size_t)(n - 3 * N / 2) * N + col] = p[m];
+        if (n < N / 2) dst[(size_t)(n + N / 2) * P3 + col] = vf[m];
+        else if (n >= 3 * N / 2) dst[(size_t)(n - 3 * N / 2) * P3 + col] = vf[m];
     }
 }
 
-// Full 2n-point Hermitian spectrum entry k of a packed half row.
+// Entry k of the full 2n-point Hermitian spectrum of a lag row whose columns
+// 0 .. n are stored (the DC and Nyquist entries are real by symmetry).
 __device__ __forceinline__ float2 herm_get(const float2* __restrict__ row, int N, int k) {
-    if (k == 0) return make_float2(row[0].x, 0.f);
-    if (k == N) return make_float2(row[0].y, 0.f);
+    if (k == 0 || k == N) return make_float2(row[k].x, 0.f);
     if (k < N) return row[k];
     return cconj(row[2 * N - k]);
 }
@@ -466,15 +431,15 @@ __global__ __launch_bounds__(256) void k_rows3(const float2* __restrict__ in,
                                                const float2* __restrict__ tw,
                                                float* __restrict__ c_xy, float4* __restrict__ part,
                                                float temp) {
-    constexpr int L = 2 * N, T = L / kE, LPB = 256 / T, PPP = (N / 2) / LPB;
+    constexpr int L = 2 * N, T = L / kE, LPB = 256 / T, PPP = (N / 2) / LPB, P3 = pitch_lag(N);
     __shared__ float lre[LPB][lds_line_words(L)];
     __shared__ float lim[LPB][lds_line_words(L)];
     __shared__ float4 red[256];
     const int line = threadIdx.x / T, t = threadIdx.x % T;
     const int gl = blockIdx.x * LPB + line;       // row pair over the batch
     const int b = gl / (N / 2), q = gl % (N / 2);
-    const float2* r1 = in + ((size_t)b * N + 2 * q) * N;
-    const float2* r2 = r1 + N;
+    const float2* r1 = in + ((size_t)b * N + 2 * q) * P3;
+    const float2* r2 = r1 + P3;
     float2 v[kE];
 #pragma unroll
     for (int m = 0; m < kE; ++m) {
@@ -575,10 +540,12 @@ FwdLayout fwd_layout(const fmbym_params& p, int batch) {
     FwdLayout L{};
     size_t off = 0;
     L.r1r2 = off;
-    off = align256(off + B * 2 * n * n * sizeof(float2));
+    const size_t r1 = B * n * (size_t)pitch_rows1(p.n) * sizeof(float4);
+    const size_t r2 = B * n * (size_t)pitch_rows2(p.n) * sizeof(float4);
+    off = align256(off + (r1 > r2 ? r1 : r2));
     L.mag_r3 = off;
-    const size_t mag = B * 2 * n * (size_t)mag_pitch(p.n) * sizeof(float);
-    const size_t r3 = B * n * n * sizeof(float2);
+    const size_t mag = B * n * (size_t)pitch_mag(p.n) * sizeof(float2);
+    const size_t r3 = B * n * (size_t)pitch_lag(p.n) * sizeof(float2);
     off = align256(off + (mag > r3 ? mag : r3));
     L.ptheta = off;
     off = align256(off + B * (size_t)radius_blocks(p.n_r) * (p.n_theta / 2 + 1) * sizeof(float2));
@@ -590,21 +557,25 @@ FwdLayout fwd_layout(const fmbym_params& p, int batch) {
     return L;
 }
 
+// Column-tile widths: 8 interleaved columns read 128-byte segments.
+template <int N> constexpr int cols1_tile() { return N >= 512 ? 8 : 16; }
+template <int N> constexpr int cols2_tile() { return N >= 256 ? 8 : 16; }
+
 template <int N>
 static void launch_stage1_rows_cols(const Plan& pl, int B, const float* f, const float* g,
-                                    const float* mf, const float* mg, float2* r1, float* mag,
+                                    const float* mf, const float* mg, float4* r1, float2* mag,
                                     hipStream_t s) {
     const int win = (pl.p.flags & FMBYM_HANN) ? 1 : 0;
     constexpr int T1 = N / kE, LPB1 = 256 / T1;
     FMBYM_LAUNCH(kKRows1, k_rows1<N>, dim3(B * N / LPB1), dim3(256), s, f, g, mf, mg, pl.hann,
-                       pl.twiddle, r1, win);
-    constexpr int C = 16;
-    FMBYM_LAUNCH(kKCols1, (k_cols1<N, C>), dim3(B * 2 * (N / 2) / C), dim3(C * N / kE), s, r1, mag,
-                       pl.twiddle, pl.band_on, pl.band_lo2, pl.band_hi2);
+                 pl.twiddle, r1, win);
+    constexpr int C = cols1_tile<N>();
+    FMBYM_LAUNCH(kKCols1, (k_cols1<N, C>), dim3(B * ((N / 2) / C + 1)), dim3(C * N / kE), s, r1, mag,
+                 pl.twiddle, pl.band_on, pl.band_lo2, pl.band_hi2);
 }
 
 void launch_stage1_spectra(const Plan& pl, int B, const float* f, const float* g, const float* mf,
-                           const float* mg, float2* r1, float* mag, hipStream_t s) {
+                           const float* mg, float4* r1, float2* mag, hipStream_t s) {
     switch (pl.p.n) {
         case 128: launch_stage1_rows_cols<128>(pl, B, f, g, mf, mg, r1, mag, s); break;
         case 256: launch_stage1_rows_cols<256>(pl, B, f, g, mf, mg, r1, mag, s); break;
@@ -614,14 +585,14 @@ void launch_stage1_spectra(const Plan& pl, int B, const float* f, const float* g
 }
 
 template <int N, int NT>
-static void launch_polar(const Plan& pl, int B, const float* mag, float2* pth, float* c_theta,
+static void launch_polar(const Plan& pl, int B, const float2* mag, float2* pth, float* c_theta,
                          float* pose, float* saved, hipStream_t s) {
     const int nrb = radius_blocks(pl.p.n_r);
     const int total = B * nrb;
     const int grid = ((total + 7) / 8) * 8;
     FMBYM_LAUNCH(kKPolar, (k_polar<NT, N>), dim3(grid), dim3(256), s, mag, pl.twiddle, pth, pl.p.n_r, B);
-    FMBYM_LAUNCH(kKAngleFin, k_angle_fin<NT>, dim3(B), dim3(kAngleGroups * NT / kE), s, pth, pl.p.n_r, pl.twiddle,
-                       pl.p.temp_theta, c_theta, pose, saved);
+    FMBYM_LAUNCH(kKAngleFin, k_angle_fin<NT>, dim3(B), dim3(kAngleGroups * NT / kE), s, pth, pl.p.n_r,
+                 pl.twiddle, pl.p.temp_theta, c_theta, pose, saved);
 }
 
 template <int N>
@@ -629,8 +600,8 @@ static int launch_n(const Plan& pl, int B, const float* f, const float* g, const
                     const float* mg, float* pose, float* c_theta, float* c_xy, float* saved,
                     char* ws, hipStream_t s) {
     const FwdLayout lay = fwd_layout(pl.p, B);
-    float2* r1 = (float2*)(ws + lay.r1r2);
-    float* mag = (float*)(ws + lay.mag_r3);
+    float4* r1 = (float4*)(ws + lay.r1r2);
+    float2* mag = (float2*)(ws + lay.mag_r3);
     float2* pth = (float2*)(ws + lay.ptheta);
     float4* pxy = (float4*)(ws + lay.pxy);
     float* sv = saved ? saved : (float*)(ws + lay.saved);
@@ -646,18 +617,18 @@ static int launch_n(const Plan& pl, int B, const float* f, const float* g, const
         default: return FMBYM_EUNSUPPORTED;
     }
     const int win2 = ((pl.p.flags & FMBYM_HANN) && !(pl.p.flags & FMBYM_XY_UNWINDOWED)) ? 1 : 0;
-    float2* r2 = r1;                    // stage-1 rows are dead after k_cols1
-    float2* r3 = (float2*)mag;          // magnitudes are dead after k_polar
+    float4* r2 = r1;                    // stage-1 rows are dead after k_cols1
+    float2* r3 = mag;                   // magnitudes are dead after k_polar
     constexpr int T2 = 2 * N / kE, LPB2 = 256 / T2;
     FMBYM_LAUNCH(kKRows2, k_rows2<N>, dim3(B * N / LPB2), dim3(256), s, f, g, mf, mg, pl.hann,
-                       pl.twiddle, sv, r2, win2);
-    constexpr int C2 = N >= 512 ? 8 : 16;
-    const int total2 = B * (N / C2);
+                 pl.twiddle, sv, r2, win2);
+    constexpr int C2 = cols2_tile<N>();
+    const int total2 = B * (N / C2 + 1);
     FMBYM_LAUNCH(kKCols2, (k_cols2<N, C2>), dim3(((total2 + 7) / 8) * 8), dim3(C2 * 2 * N / kE), s, r2,
-                       pl.twiddle, r3, B);
+                 pl.twiddle, r3, B);
     constexpr int LPB3 = 256 / T2;
     FMBYM_LAUNCH(kKRows3, k_rows3<N>, dim3(B * (N / 2) / LPB3), dim3(256), s, r3, pl.twiddle, c_xy,
-                       pxy, pl.p.temp_xy);
+                 pxy, pl.p.temp_xy);
     FMBYM_LAUNCH(kKXyFin, k_xy_fin, dim3(B), dim3(64), s, pxy, xy_partials_per_pair(N), pl.p.temp_xy,
                  pl.p.delta_xy, pose, sv);
     return FMBYM_OK;
