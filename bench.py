@@ -65,6 +65,8 @@ def main() -> int:
     ap.add_argument("--workload", default="batch512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pairs", type=int, default=4)
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (calibrates HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): each scan pair is "
@@ -95,6 +97,14 @@ def main() -> int:
         with_bwd = False
     d_pose = torch.ones(B, 3, device=dev)
     torch.cuda.synchronize()
+
+    if args.copy_probe_mb:
+        src = torch.empty(args.copy_probe_mb << 18, device=dev)        # MiB of float32
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step():
         o = s.forward(f, g)

@@ -73,12 +73,26 @@ __device__ __forceinline__ void dft_r<4>(float2 (&v)[4]) { dft4(v[0], v[1], v[2]
 template <>
 __device__ __forceinline__ void dft_r<8>(float2 (&v)[8]) { dft8(v); }
 
-// Padded LDS index: one spare word every 32 keeps the strided Stockham
-// accesses spread over the banks; one more word per line makes consecutive
-// lines (the columns of a column tile, accessed by neighbouring lanes) start
-// on different banks.
-__device__ __forceinline__ int lpad(int i) { return i + (i >> 5); }
-__host__ __device__ constexpr int lds_line_words(int L) { return L + L / 32 + 1; }
+// LDS layouts of a line (separate re/im planes, 32 banks of 4 bytes).  The
+// Stockham stages read unit-stride and write stride-Ns patterns, the mirror
+// reads reversed; these layouts keep those patterns near one cycle per
+// half-wave access (chosen with a bank simulator of exactly these patterns):
+//   rows (one line per T threads, lanes vary the element): XOR swizzle of the
+//     low five bits by bits 3..7; short lines (several per wave) are spaced by
+//     16 words mod 32;
+//   column tiles (lanes vary the column fastest, C columns per tile): one
+//     spare word per 8 elements and a line stride of 32/C words mod 32.
+struct LdsRows {
+    __device__ __forceinline__ static int at(int i) { return i ^ ((i >> 3) & 31); }
+    __host__ __device__ static constexpr int words(int L) { return L <= 128 ? L + 16 : L; }
+};
+template <int C>
+struct LdsCols {
+    __device__ __forceinline__ static int at(int i) { return i + (i >> 3); }
+    __host__ __device__ static constexpr int words(int L) {
+        return L + L / 8 + ((32 / C - (L + L / 8)) % 32 + 32) % 32;
+    }
+};
 
 constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
 
@@ -103,7 +117,7 @@ struct NumStages {
 
 // One Stockham stage.  FIRST reads the inputs from registers, LAST writes the
 // outputs to registers; otherwise they go through the LDS line (re, im).
-template <int L, int E, int S, bool FIRST, bool LAST>
+template <int L, int E, int S, bool FIRST, bool LAST, class Lay>
 __device__ __forceinline__ void fft_stage(float2 (&v)[E], float* re, float* im, int t,
                                           const float2* __restrict__ tw) {
     constexpr int T = L / E;
@@ -121,7 +135,7 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[E], float* re, float* im, 
             if (FIRST) {
                 x[r] = v[q + r * Q];
             } else {
-                const int idx = lpad(j + r * LR);
+                const int idx = Lay::at(j + r * LR);
                 x[r] = make_float2(re[idx], im[idx]);
             }
         }
@@ -148,7 +162,7 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[E], float* re, float* im, 
             const int base = (j / Ns) * Ns * R + k;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const int idx = lpad(base + r * Ns);
+                const int idx = Lay::at(base + r * Ns);
                 re[idx] = out[q][r].x;
                 im[idx] = out[q][r].y;
             }
@@ -162,36 +176,36 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[E], float* re, float* im, 
     }
 }
 
-template <int L, int E, int S, int NS>
+template <int L, int E, int S, int NS, class Lay>
 struct FFTStages {
     __device__ __forceinline__ static void run(float2 (&v)[E], float* re, float* im, int t,
                                                const float2* tw) {
-        fft_stage<L, E, S, S == 0, S == NS - 1>(v, re, im, t, tw);
-        FFTStages<L, E, S + 1, NS>::run(v, re, im, t, tw);
+        fft_stage<L, E, S, S == 0, S == NS - 1, Lay>(v, re, im, t, tw);
+        FFTStages<L, E, S + 1, NS, Lay>::run(v, re, im, t, tw);
     }
 };
-template <int L, int E, int NS>
-struct FFTStages<L, E, NS, NS> {
+template <int L, int E, int NS, class Lay>
+struct FFTStages<L, E, NS, NS, Lay> {
     __device__ __forceinline__ static void run(float2 (&)[E], float*, float*, int, const float2*) {}
 };
 
 // Forward DFT of one line, in registers.  All threads of the block must call
 // it (it contains block barriers) even if their line is padding.
-template <int L, int E>
+template <int L, int E, class Lay = LdsRows>
 __device__ __forceinline__ void fft_line(float2 (&v)[E], float* re, float* im, int t,
                                          const float2* __restrict__ tw) {
     static_assert((L & (L - 1)) == 0 && L >= 2 && L <= kTwiddleLen, "power-of-two length");
     static_assert(E == 2 || E == 4 || E == 8, "elements per thread");
-    FFTStages<L, E, 0, NumStages<L, E>::value>::run(v, re, im, t, tw);
+    FFTStages<L, E, 0, NumStages<L, E>::value, Lay>::run(v, re, im, t, tw);
 }
 
 // Inverse (unnormalised) DFT: conj(DFT(conj(x))).
-template <int L, int E>
+template <int L, int E, class Lay = LdsRows>
 __device__ __forceinline__ void ifft_line(float2 (&v)[E], float* re, float* im, int t,
                                           const float2* __restrict__ tw) {
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m].y = -v[m].y;
-    fft_line<L, E>(v, re, im, t, tw);
+    fft_line<L, E, Lay>(v, re, im, t, tw);
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m].y = -v[m].y;
 }
@@ -199,14 +213,14 @@ __device__ __forceinline__ void ifft_line(float2 (&v)[E], float* re, float* im, 
 // Store the register line to LDS in natural order / read the mirror element
 // X[(L - k) mod L] of each held X[k].  Used to split the transforms of two real
 // sequences packed as x + i y.  Barriers included.
-template <int L, int E>
+template <int L, int E, class Lay = LdsRows>
 __device__ __forceinline__ void mirror_line(const float2 (&v)[E], float2 (&mir)[E], float* re,
                                             float* im, int t) {
     constexpr int T = L / E;
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-        const int idx = lpad(t + m * T);
+        const int idx = Lay::at(t + m * T);
         re[idx] = v[m].x;
         im[idx] = v[m].y;
     }
@@ -214,7 +228,7 @@ __device__ __forceinline__ void mirror_line(const float2 (&v)[E], float2 (&mir)[
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         const int k = t + m * T;
-        const int idx = lpad((L - k) & (L - 1));
+        const int idx = Lay::at((L - k) & (L - 1));
         mir[m] = make_float2(re[idx], im[idx]);
     }
 }

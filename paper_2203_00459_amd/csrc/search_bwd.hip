@@ -73,8 +73,8 @@ __global__ __launch_bounds__(256) void kb_rows_fwd2(
     const float* __restrict__ saved, const float* __restrict__ c_xy, const float* __restrict__ d_pose,
     float4* __restrict__ rf, float2* __restrict__ rdc, int win, int batch, float temp, float delta) {
     constexpr int L = 2 * N, T = L / kEb, LPB = 256 / T, P2 = pitch_rows2(N), P3 = pitch_lag(N);
-    __shared__ float lre[LPB][lds_line_words(L)];
-    __shared__ float lim[LPB][lds_line_words(L)];
+    __shared__ float lre[LPB][LdsRows::words(L)];
+    __shared__ float lim[LPB][LdsRows::words(L)];
     const int line = threadIdx.x / T, t = threadIdx.x % T;
     const int nscan_blocks = batch * N / LPB;
     const bool scan_rows = (int)blockIdx.x < nscan_blocks;   // block-uniform
@@ -145,8 +145,8 @@ __global__ __launch_bounds__(C * 2 * N / kEb) void kb_cols_xy(float4* __restrict
                                                               const float2* __restrict__ tw,
                                                               int batch) {
     constexpr int L = 2 * N, T = L / kEb, TILES = N / C + 1, P2 = pitch_rows2(N), P3 = pitch_lag(N);
-    __shared__ float lre[C][lds_line_words(L)];
-    __shared__ float lim[C][lds_line_words(L)];
+    __shared__ float lre[C][LdsCols<C>::words(L)];
+    __shared__ float lim[C][LdsCols<C>::words(L)];
     const int total = batch * TILES;
     const int per_xcd = (total + 7) / 8;
     const int work = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
@@ -165,7 +165,7 @@ __global__ __launch_bounds__(C * 2 * N / kEb) void kb_cols_xy(float4* __restrict
         else if (m >= 3 * kEb / 4) vd[m] = sd[(size_t)(n - 3 * N / 2) * P3 + col];
         else vd[m] = make_float2(0.f, 0.f);
     }
-    fft_line<L, kEb>(vd, lre[c], lim[c], t, tw);
+    fft_line<L, kEb, LdsCols<C>>(vd, lre[c], lim[c], t, tw);
     float2 vf[kEb], vg[kEb];
 #pragma unroll
     for (int m = 0; m < kEb; ++m) {
@@ -177,14 +177,14 @@ __global__ __launch_bounds__(C * 2 * N / kEb) void kb_cols_xy(float4* __restrict
             vf[m] = vg[m] = make_float2(0.f, 0.f);
         }
     }
-    fft_line<L, kEb>(vf, lre[c], lim[c], t, tw);
+    fft_line<L, kEb, LdsCols<C>>(vf, lre[c], lim[c], t, tw);
 #pragma unroll
     for (int m = 0; m < kEb; ++m) vf[m] = cmul(vf[m], vd[m]);          // X2 = F DC
-    fft_line<L, kEb>(vg, lre[c], lim[c], t, tw);
+    fft_line<L, kEb, LdsCols<C>>(vg, lre[c], lim[c], t, tw);
 #pragma unroll
     for (int m = 0; m < kEb; ++m) vg[m] = cmulcj(vd[m], vg[m]);        // X1 = conj(DC) G'
-    ifft_line<L, kEb>(vg, lre[c], lim[c], t, tw);
-    ifft_line<L, kEb>(vf, lre[c], lim[c], t, tw);
+    ifft_line<L, kEb, LdsCols<C>>(vg, lre[c], lim[c], t, tw);
+    ifft_line<L, kEb, LdsCols<C>>(vf, lre[c], lim[c], t, tw);
     if (col > N) return;
 #pragma unroll
     for (int m = 0; m < kEb / 2; ++m)
@@ -213,8 +213,8 @@ __global__ __launch_bounds__(256) void kb_rows_xy(const float4* __restrict__ q12
                                                   float* __restrict__ df2, float* __restrict__ dgp,
                                                   float* __restrict__ dth_part, int win) {
     constexpr int L = 2 * N, T = L / kEb, LPB = 256 / T, PPB = N / LPB, P2 = pitch_rows2(N);
-    __shared__ float lre[LPB][lds_line_words(L)];
-    __shared__ float lim[LPB][lds_line_words(L)];
+    __shared__ float lre[LPB][LdsRows::words(L)];
+    __shared__ float lim[LPB][LdsRows::words(L)];
     __shared__ float red[256];
     const int line = threadIdx.x / T, t = threadIdx.x % T;
     const int grow = blockIdx.x * LPB + line;
@@ -278,8 +278,8 @@ __global__ __launch_bounds__(NT / kEb) void kb_dtheta(const float* __restrict__ 
                                                       const float2* __restrict__ tw, float temp,
                                                       float2* __restrict__ dspec) {
     constexpr int L = NT, T = L / kEb;
-    __shared__ float lre[lds_line_words(L)];
-    __shared__ float lim[lds_line_words(L)];
+    __shared__ float lre[LdsRows::words(L)];
+    __shared__ float lim[LdsRows::words(L)];
     __shared__ float red[T];
     const int b = blockIdx.x, t = threadIdx.x;
     float s = 0.f;
@@ -328,8 +328,8 @@ __global__ __launch_bounds__(256) void kb_polar(const float2* __restrict__ A,
                                                 const float2* __restrict__ dspec,
                                                 float2* __restrict__ dpol, int n_r, int batch) {
     constexpr int L = NT, T = L / kEb, LPB = 256 / T, PASSES = (kRadiiPerBlock + LPB - 1) / LPB;
-    __shared__ float lre[LPB][lds_line_words(L)];
-    __shared__ float lim[LPB][lds_line_words(L)];
+    __shared__ float lre[LPB][LdsRows::words(L)];
+    __shared__ float lim[LPB][LdsRows::words(L)];
     const int nrb = (n_r + kRadiiPerBlock - 1) / kRadiiPerBlock;
     const int total = batch * nrb;
     const int per_xcd = (total + 7) / 8;
@@ -456,8 +456,8 @@ __global__ __launch_bounds__(C * N / kEb) void kb_cols_mag(float4* __restrict__ 
                                                            const float2* __restrict__ dA,
                                                            const float2* __restrict__ tw) {
     constexpr int L = N, T = L / kEb, H = N / 2, TILES = H / C + 1, P1 = pitch_rows1(N), PA = pitch_mag(N);
-    __shared__ float lre[C][lds_line_words(L)];
-    __shared__ float lim[C][lds_line_words(L)];
+    __shared__ float lre[C][LdsCols<C>::words(L)];
+    __shared__ float lim[C][LdsCols<C>::words(L)];
     const int c = threadIdx.x % C, t = threadIdx.x / C;
     const int tile = blockIdx.x % TILES, b = blockIdx.x / TILES;
     const int col = tile * C + c;
@@ -470,16 +470,16 @@ __global__ __launch_bounds__(C * N / kEb) void kb_cols_mag(float4* __restrict__ 
         vf[m] = make_float2(q.x, q.y);
         vg[m] = make_float2(q.z, q.w);
     }
-    fft_line<L, kEb>(vf, lre[c], lim[c], t, tw);
-    fft_line<L, kEb>(vg, lre[c], lim[c], t, tw);
+    fft_line<L, kEb, LdsCols<C>>(vf, lre[c], lim[c], t, tw);
+    fft_line<L, kEb, LdsCols<C>>(vg, lre[c], lim[c], t, tw);
 #pragma unroll
     for (int m = 0; m < kEb; ++m) {
         const float2 d = col <= H ? da[(t + m * T) * PA + col] : make_float2(0.f, 0.f);
         vf[m] = mag_adjoint(vf[m], d.x);
         vg[m] = mag_adjoint(vg[m], d.y);
     }
-    ifft_line<L, kEb>(vf, lre[c], lim[c], t, tw);
-    ifft_line<L, kEb>(vg, lre[c], lim[c], t, tw);
+    ifft_line<L, kEb, LdsCols<C>>(vf, lre[c], lim[c], t, tw);
+    ifft_line<L, kEb, LdsCols<C>>(vg, lre[c], lim[c], t, tw);
     if (col > H) return;
 #pragma unroll
     for (int m = 0; m < kEb; ++m)
@@ -520,8 +520,8 @@ __global__ __launch_bounds__(256) void kb_rows_final(
     const float* __restrict__ saved, float* __restrict__ d_f, float* __restrict__ d_g,
     float* __restrict__ d_mf, float* __restrict__ d_mg, int win, int win2) {
     constexpr int L = N, T = L / kEb, LPB = 256 / T, H = N / 2, P1 = pitch_rows1(N);
-    __shared__ float lre[LPB][lds_line_words(L)];
-    __shared__ float lim[LPB][lds_line_words(L)];
+    __shared__ float lre[LPB][LdsRows::words(L)];
+    __shared__ float lim[LPB][LdsRows::words(L)];
     const int line = threadIdx.x / T, t = threadIdx.x % T;
     const int grow = blockIdx.x * LPB + line;
     const int b = grow / N, i = grow % N;

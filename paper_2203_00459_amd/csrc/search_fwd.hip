@@ -37,8 +37,8 @@ __global__ __launch_bounds__(256) void k_rows1(const float* __restrict__ f, cons
                                                const float2* __restrict__ tw, float4* __restrict__ out,
                                                int win) {
     constexpr int L = N, T = L / kE, LPB = 256 / T, H = N / 2, P = pitch_rows1(N);
-    __shared__ float lre[LPB][lds_line_words(L)];
-    __shared__ float lim[LPB][lds_line_words(L)];
+    __shared__ float lre[LPB][LdsRows::words(L)];
+    __shared__ float lim[LPB][LdsRows::words(L)];
     const int line = threadIdx.x / T, t = threadIdx.x % T;
     const int grow = blockIdx.x * LPB + line;     // row over the batch
     const int i = grow % N;
@@ -88,8 +88,8 @@ __global__ __launch_bounds__(C * N / kE) void k_cols1(const float4* __restrict__
                                                       int lo2, int hi2) {
     constexpr int L = N, T = L / kE, H = N / 2, P1 = pitch_rows1(N), PA = pitch_mag(N);
     constexpr int TILES = H / C + 1;
-    __shared__ float lre[C][lds_line_words(L)];
-    __shared__ float lim[C][lds_line_words(L)];
+    __shared__ float lre[C][LdsCols<C>::words(L)];
+    __shared__ float lim[C][LdsCols<C>::words(L)];
     const int c = threadIdx.x % C, t = threadIdx.x / C;
     const int tile = blockIdx.x % TILES, b = blockIdx.x / TILES;
     const int col = tile * C + c;
@@ -101,8 +101,8 @@ __global__ __launch_bounds__(C * N / kE) void k_cols1(const float4* __restrict__
         vf[m] = make_float2(q.x, q.y);
         vg[m] = make_float2(q.z, q.w);
     }
-    fft_line<L, kE>(vf, lre[c], lim[c], t, tw);
-    fft_line<L, kE>(vg, lre[c], lim[c], t, tw);
+    fft_line<L, kE, LdsCols<C>>(vf, lre[c], lim[c], t, tw);
+    fft_line<L, kE, LdsCols<C>>(vg, lre[c], lim[c], t, tw);
     if (col > H) return;   // padding lane of the last tile (no barriers follow)
     float2* dst = A + (size_t)b * N * PA;
 #pragma unroll
@@ -123,8 +123,8 @@ __global__ __launch_bounds__(256) void k_polar(const float2* __restrict__ A,
                                                float2* __restrict__ part, int n_r, int batch) {
     constexpr int L = NT, T = L / kE, LPB = 256 / T, PASSES = (kRadiiPerBlock + LPB - 1) / LPB;
     constexpr int HK = NT / 2 + 1;
-    __shared__ float lre[LPB][lds_line_words(L)];
-    __shared__ float lim[LPB][lds_line_words(L)];
+    __shared__ float lre[LPB][LdsRows::words(L)];
+    __shared__ float lim[LPB][LdsRows::words(L)];
     const int nrb = (n_r + kRadiiPerBlock - 1) / kRadiiPerBlock;
     const int total = batch * nrb;
     // XCD-aware remap: hardware deals consecutive block ids round-robin over 8 XCDs
@@ -242,8 +242,8 @@ __global__ __launch_bounds__(kAngleGroups * NT / kE) void k_angle_fin(
     const float2* __restrict__ part, int n_r, const float2* __restrict__ tw, float temp,
     float* __restrict__ c_theta, float* __restrict__ pose, float* __restrict__ saved) {
     constexpr int L = NT, T = L / kE, HK = NT / 2 + 1;
-    __shared__ float lre[kAngleGroups][lds_line_words(L)];   // one line per group: the groups
-    __shared__ float lim[kAngleGroups][lds_line_words(L)];   // repeat the transform, race-free
+    __shared__ float lre[kAngleGroups][LdsRows::words(L)];   // one line per group: the groups
+    __shared__ float lim[kAngleGroups][LdsRows::words(L)];   // repeat the transform, race-free
     __shared__ float2 psum[kAngleGroups][HK];
     __shared__ float red[T];
     __shared__ int redi[T];
@@ -338,8 +338,8 @@ __global__ __launch_bounds__(256) void k_rows2(const float* __restrict__ f, cons
                                                const float* __restrict__ saved,
                                                float4* __restrict__ out, int win) {
     constexpr int L = 2 * N, T = L / kE, LPB = 256 / T, P2 = pitch_rows2(N);
-    __shared__ float lre[LPB][lds_line_words(L)];
-    __shared__ float lim[LPB][lds_line_words(L)];
+    __shared__ float lre[LPB][LdsRows::words(L)];
+    __shared__ float lim[LPB][LdsRows::words(L)];
     const int line = threadIdx.x / T, t = threadIdx.x % T;
     const int grow = blockIdx.x * LPB + line;
     const int b = grow / N, i = grow % N;
@@ -382,8 +382,8 @@ __global__ __launch_bounds__(C * 2 * N / kE) void k_cols2(const float4* __restri
                                                           const float2* __restrict__ tw,
                                                           float2* __restrict__ out, int batch) {
     constexpr int L = 2 * N, T = L / kE, TILES = N / C + 1, P2 = pitch_rows2(N), P3 = pitch_lag(N);
-    __shared__ float lre[C][lds_line_words(L)];
-    __shared__ float lim[C][lds_line_words(L)];
+    __shared__ float lre[C][LdsCols<C>::words(L)];
+    __shared__ float lim[C][LdsCols<C>::words(L)];
     const int total = batch * TILES;
     const int per_xcd = (total + 7) / 8;
     const int work = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
@@ -403,11 +403,11 @@ __global__ __launch_bounds__(C * 2 * N / kE) void k_cols2(const float4* __restri
             vf[m] = vg[m] = make_float2(0.f, 0.f);
         }
     }
-    fft_line<L, kE>(vf, lre[c], lim[c], t, tw);
-    fft_line<L, kE>(vg, lre[c], lim[c], t, tw);
+    fft_line<L, kE, LdsCols<C>>(vf, lre[c], lim[c], t, tw);
+    fft_line<L, kE, LdsCols<C>>(vg, lre[c], lim[c], t, tw);
 #pragma unroll
     for (int m = 0; m < kE; ++m) vf[m] = cmulcj(vf[m], vg[m]);
-    ifft_line<L, kE>(vf, lre[c], lim[c], t, tw);
+    ifft_line<L, kE, LdsCols<C>>(vf, lre[c], lim[c], t, tw);
     if (col > N) return;
     float2* dst = out + (size_t)b * N * P3;
 #pragma unroll
@@ -432,8 +432,8 @@ __global__ __launch_bounds__(256) void k_rows3(const float2* __restrict__ in,
                                                float* __restrict__ c_xy, float4* __restrict__ part,
                                                float temp) {
     constexpr int L = 2 * N, T = L / kE, LPB = 256 / T, PPP = (N / 2) / LPB, P3 = pitch_lag(N);
-    __shared__ float lre[LPB][lds_line_words(L)];
-    __shared__ float lim[LPB][lds_line_words(L)];
+    __shared__ float lre[LPB][LdsRows::words(L)];
+    __shared__ float lim[LPB][LdsRows::words(L)];
     __shared__ float4 red[256];
     const int line = threadIdx.x / T, t = threadIdx.x % T;
     const int gl = blockIdx.x * LPB + line;       // row pair over the batch
