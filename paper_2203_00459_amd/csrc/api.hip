@@ -36,7 +36,7 @@ int check_params(const fmbym_params* p) {
 
 hipError_t free_plan_tables(Plan* pl) {
     hipError_t first = hipSuccess;
-    void* ptrs[] = {pl->twiddle, pl->hann, pl->csr_ptr, pl->csr_col, pl->csr_val};
+    void* ptrs[] = {pl->twiddle, pl->hann, pl->csr_ptr, pl->csr_col, pl->csr_val, pl->csr_dst, pl->dmag_part};
     for (void* q : ptrs) {
         if (!q) continue;
         hipError_t e = hipFree(q);

@@ -34,10 +34,22 @@ struct Plan {
     int band_on;
     int band_lo2;      // keep ceil((lo n)^2) <= ky^2 + kx^2 <= floor((hi n)^2)
     int band_hi2;
-    int* csr_ptr;      // transpose of the polar gather: per half-plane bin (ky (n/2+1) + kx),
-    int* csr_col;      // the polar samples (b n_theta + a) reading it
-    float* csr_val;    // and their bilinear weights
+    // Transpose of the polar gather as a CSR matrix whose rows are the
+    // half-plane bins in tile order (16 x 16 tiles of kx < n/2, then the
+    // column kx = n/2): row p is bin csr_dst[p] (offset ky pitch_mag + kx in
+    // a magnitude plane) and reads the polar samples csr_col (b n_theta + a)
+    // with the bilinear weights csr_val.
+    int* csr_ptr;
+    int* csr_col;
+    float* csr_val;
+    int* csr_dst;
+    int* dmag_part;    // [dmag_nparts + 1] first CSR row of each adjoint block
+    int dmag_nparts;
 };
+
+constexpr int kDmagTile = 16;     // bins per side of one tile of the CSR row order
+constexpr int kDmagRows = 256;    // at most this many CSR rows per adjoint block
+constexpr int kDmagChunk = 1024;  // and about this many entries (more only for a single row)
 
 // Build the plan's CSR transpose of the polar gather; returns a hipError_t.
 int build_polar_csr(Plan& pl);

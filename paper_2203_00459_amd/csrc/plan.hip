@@ -70,10 +70,27 @@ int build_polar_csr(Plan& pl) {
     };
     for (size_t i = 0; i < bin.size(); ++i)
         if (!in_band(bin[i])) w[i] = 0.f;
-    // counting sort by bin; entries of one bin stay in sample order
+    // Row order: 16 x 16 tiles of the bins kx < n/2 (tile rows outer), then
+    // the column kx = n/2.  A block of 256 consecutive rows covers one tile,
+    // whose polar samples form a compact patch of the (r, theta) grid, so the
+    // adjoint's gather reads whole cache lines of dP.
+    std::vector<int> order;
+    order.reserve(nbins);
+    for (int ty = 0; ty < n / kDmagTile; ++ty)
+        for (int tx = 0; tx < (n / 2) / kDmagTile; ++tx)
+            for (int y = 0; y < kDmagTile; ++y)
+                for (int x = 0; x < kDmagTile; ++x)
+                    order.push_back((ty * kDmagTile + y) * h1 + tx * kDmagTile + x);
+    for (int ky = 0; ky < n; ++ky) order.push_back(ky * h1 + n / 2);
+    std::vector<int> rank(nbins), dst(nbins);
+    for (int q = 0; q < nbins; ++q) {
+        rank[order[q]] = q;
+        dst[q] = (order[q] / h1) * pitch_mag(n) + order[q] % h1;
+    }
+    // counting sort by row; entries of one row stay in sample order
     std::vector<int> ptr(nbins + 1, 0);
     for (size_t i = 0; i < bin.size(); ++i)
-        if (w[i] != 0.f) ++ptr[bin[i] + 1];
+        if (w[i] != 0.f) ++ptr[rank[bin[i]] + 1];
     for (int i = 0; i < nbins; ++i) ptr[i + 1] += ptr[i];
     const int nnz = ptr[nbins];
     std::vector<int> col(nnz);
@@ -81,14 +98,30 @@ int build_polar_csr(Plan& pl) {
     std::vector<int> fill(ptr.begin(), ptr.end() - 1);
     for (size_t i = 0; i < bin.size(); ++i) {
         if (w[i] == 0.f) continue;
-        const int k = fill[bin[i]]++;
+        const int k = fill[rank[bin[i]]]++;
         col[k] = (int)(i / 4);      // sample index b * n_theta + a
         val[k] = w[i];
     }
+    // Blocks of the adjoint: runs of consecutive rows, at most kDmagRows rows
+    // and kDmagChunk entries each (a longer single row gets a block alone), so
+    // the dense rows near the centre do not pile up in one block.
+    std::vector<int> part{0};
+    for (int r = 0; r < nbins;) {
+        int r1 = r + 1;
+        while (r1 < nbins && r1 - r < kDmagRows && ptr[r1 + 1] - ptr[r] <= kDmagChunk) ++r1;
+        part.push_back(r1);
+        r = r1;
+    }
+    pl.dmag_nparts = (int)part.size() - 1;
     e = hipMalloc((void**)&pl.csr_ptr, sizeof(int) * ptr.size());
     if (e == hipSuccess) e = hipMalloc((void**)&pl.csr_col, sizeof(int) * (nnz > 0 ? nnz : 1));
     if (e == hipSuccess) e = hipMalloc((void**)&pl.csr_val, sizeof(float) * (nnz > 0 ? nnz : 1));
+    if (e == hipSuccess) e = hipMalloc((void**)&pl.csr_dst, sizeof(int) * nbins);
     if (e == hipSuccess) e = hipMemcpy(pl.csr_ptr, ptr.data(), sizeof(int) * ptr.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc((void**)&pl.dmag_part, sizeof(int) * part.size());
+    if (e == hipSuccess) e = hipMemcpy(pl.csr_dst, dst.data(), sizeof(int) * nbins, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(pl.dmag_part, part.data(), sizeof(int) * part.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && nnz)
         e = hipMemcpy(pl.csr_col, col.data(), sizeof(int) * nnz, hipMemcpyHostToDevice);
     if (e == hipSuccess && nnz)

@@ -378,59 +378,69 @@ __global__ __launch_bounds__(256) void kb_polar(const float2* __restrict__ A,
 
 // dA = Cart2Pol^T dP over the half-plane bins, from the plan's CSR transpose
 // of the polar gather (rows of bins outside the band are empty, so they come
-// out 0).  A block owns 256 consecutive bins and kDmagPairs pairs.  Its CSR
-// slice is staged in LDS once; for each pair every thread forms the products
-// w * (dP_f, dP_g) of a strided set of entries (independent, coalesced
-// gathers), then each bin sums its own segment from LDS in entry order.
-// Slices longer than the LDS stage are processed in chunks, still in order.
+// out 0).  Block x owns the CSR rows [part[x], part[x+1]) (at most kDmagRows
+// rows, about kDmagChunk entries: a balanced share of the entries, whatever
+// the density of polar samples) and kDmagPairs pairs.  Every thread forms the
+// products w * (dP_f, dP_g) of a strided set of entries for all the pairs at
+// once (independent gathers, many in flight), then each row sums its own
+// segment from LDS in entry order and lands at dst[row] of the magnitude
+// plane.  A row longer than kDmagChunk is processed in chunks, still in order.
 constexpr int kDmagPairs = 4;
-constexpr int kDmagStage = 4096;
+constexpr int kDmagPer = kDmagChunk / 256;
+static_assert(kDmagChunk % 256 == 0 && kDmagRows <= 256, "one row per thread, whole strides of entries");
 __global__ __launch_bounds__(256) void kb_dmag(const int* __restrict__ ptr, const int* __restrict__ col,
-                                               const float* __restrict__ val,
+                                               const float* __restrict__ val, const int* __restrict__ dst,
+                                               const int* __restrict__ part,
                                                const float2* __restrict__ dpol, float2* __restrict__ dA,
                                                int n, int n_r, int n_theta, int batch) {
-    __shared__ int lcol[kDmagStage];
-    __shared__ float lval[kDmagStage];
-    __shared__ float2 prod[kDmagStage];
-    __shared__ int lptr[257];
-    const int h1 = n / 2 + 1, nbins = n * h1;
-    const int bin0 = blockIdx.x * 256;
-    const int nb = min(256, nbins - bin0);
+    __shared__ float4 prod[kDmagChunk][kDmagPairs / 2];
+    __shared__ int lptr[kDmagRows + 1];
     const int tid = threadIdx.x;
-    for (int i = tid; i <= nb; i += 256) lptr[i] = ptr[bin0 + i];
+    const int r0 = part[blockIdx.x], nrow = part[blockIdx.x + 1] - r0;
+    for (int i = tid; i <= nrow; i += 256) lptr[i] = ptr[r0 + i];
     __syncthreads();
-    const int e_begin = lptr[0], e_end = lptr[nb];
+    const int e_begin = lptr[0], e_end = lptr[nrow];
     const size_t pstride = (size_t)n_r * n_theta;
-    const int p0 = blockIdx.y * kDmagPairs, p1 = min(batch, p0 + kDmagPairs);
-    const bool staged = e_end - e_begin <= kDmagStage;
-    if (staged) {
-        for (int e = e_begin + tid; e < e_end; e += 256) {
-            lcol[e - e_begin] = col[e];
-            lval[e - e_begin] = val[e];
+    const int p0 = blockIdx.y * kDmagPairs, np = min(kDmagPairs, batch - p0);
+    const float2* src = dpol + (size_t)p0 * pstride;
+    const int my0 = tid < nrow ? lptr[tid] : 0, my1 = tid < nrow ? lptr[tid + 1] : 0;
+    float2 acc[kDmagPairs];
+#pragma unroll
+    for (int p = 0; p < kDmagPairs; ++p) acc[p] = make_float2(0.f, 0.f);
+    for (int c0 = e_begin; c0 < e_end; c0 += kDmagChunk) {
+        const int c1 = min(e_end, c0 + kDmagChunk);
+#pragma unroll
+        for (int j = 0; j < kDmagPer; ++j) {
+            const int e = c0 + tid + 256 * j;
+            if (e >= c1) break;
+            const int cc = col[e];
+            const float w = val[e];
+            float2 x[kDmagPairs];
+#pragma unroll
+            for (int p = 0; p < kDmagPairs; ++p)
+                x[p] = p < np ? cscale(src[p * pstride + cc], w) : make_float2(0.f, 0.f);
+#pragma unroll
+            for (int h = 0; h < kDmagPairs / 2; ++h)
+                prod[e - c0][h] = make_float4(x[2 * h].x, x[2 * h].y, x[2 * h + 1].x, x[2 * h + 1].y);
         }
-    }
-    __syncthreads();
-    const int my0 = tid < nb ? lptr[tid] : 0, my1 = tid < nb ? lptr[tid + 1] : 0;
-    for (int pr = p0; pr < p1; ++pr) {
-        const float2* src = dpol + (size_t)pr * pstride;
-        float2 acc = make_float2(0.f, 0.f);
-        for (int c0 = e_begin; c0 < e_end; c0 += kDmagStage) {
-            const int c1 = min(e_end, c0 + kDmagStage);
-            for (int e = c0 + tid; e < c1; e += 256) {
-                const int k = e - c0;
-                const int cc = staged ? lcol[k] : col[e];
-                const float w = staged ? lval[k] : val[e];
-                prod[k] = cscale(src[cc], w);
+        __syncthreads();
+        const int a = max(my0, c0), z = min(my1, c1);
+        for (int e = a; e < z; ++e) {
+#pragma unroll
+            for (int h = 0; h < kDmagPairs / 2; ++h) {
+                const float4 q = prod[e - c0][h];
+                acc[2 * h] = cadd(acc[2 * h], make_float2(q.x, q.y));
+                acc[2 * h + 1] = cadd(acc[2 * h + 1], make_float2(q.z, q.w));
             }
-            __syncthreads();
-            const int a = max(my0, c0), z = min(my1, c1);
-            for (int e = a; e < z; ++e) acc = cadd(acc, prod[e - c0]);
-            __syncthreads();
         }
-        if (tid < nb) {
-            const int bin = bin0 + tid, ky = bin / h1, kx = bin % h1;
-            dA[((size_t)pr * n + ky) * pitch_mag(n) + kx] = acc;
-        }
+        __syncthreads();
+    }
+    if (tid < nrow) {
+        const int o = dst[r0 + tid];
+        const size_t plane = (size_t)n * pitch_mag(n);
+#pragma unroll
+        for (int p = 0; p < kDmagPairs; ++p)
+            if (p < np) dA[(p0 + p) * plane + o] = acc[p];
     }
 }
 
@@ -442,11 +452,6 @@ __device__ __forceinline__ float2 mag_adjoint(float2 F, float dA) {
 }
 
 
-// Column pass of the rotation adjoint, in place over the stage-1 row spectra:
-// column DFTs again, dF = dA F / |F| (dA already carries the band gain), and
-// the unnormalised inverse column DFT.  For the packed DC/Nyquist column only
-// the real parts of the inverse are needed: the inverse of the Hermitian part
-// of each, both through one transform.
 // Column pass of the rotation adjoint over columns 0 .. n/2, in place over the
 // stage-1 row spectra: column DFTs again, dF = dA F / |F| (dA already
 // carries the band gain), unnormalised inverse column DFT.  For columns 0 and
@@ -684,10 +689,9 @@ static int launch_bwd_n(const Plan& pl, int B, const float* f, const float* g, c
         default: return FMBYM_EUNSUPPORTED;
     }
     float2* dA = mag;                   // the recomputed magnitudes are dead after kb_polar
-    const int nbins = N * (N / 2 + 1);
-    FMBYM_LAUNCH(kKBDmag, kb_dmag, dim3((nbins + 255) / 256, (B + kDmagPairs - 1) / kDmagPairs),
-                 dim3(256), s, pl.csr_ptr, pl.csr_col, pl.csr_val, dpol, dA, N, pl.p.n_r, pl.p.n_theta,
-                 B);
+    FMBYM_LAUNCH(kKBDmag, kb_dmag, dim3(pl.dmag_nparts, (B + kDmagPairs - 1) / kDmagPairs), dim3(256), s,
+                 pl.csr_ptr, pl.csr_col, pl.csr_val, pl.csr_dst, pl.dmag_part, dpol, dA, N, pl.p.n_r,
+                 pl.p.n_theta, B);
     constexpr int C = bcols_mag_tile<N>();
     FMBYM_LAUNCH(kKBColsMag, (kb_cols_mag<N, C>), dim3(B * ((N / 2) / C + 1)), dim3(C * N / kEb), s, r1,
                  dA, pl.twiddle);
