@@ -73,7 +73,89 @@ def main() -> int:
               "independent, so the batch would shard across GPUs with no exchange step; this "
               "build measures the one-GPU share.", file=sys.stderr)
         return 2
+    from paper_2203_00459_amd import workloads
+    if args.workload in workloads.RAGGED:
+        return ragged_bench(args)
+    return search_bench(args)
 
+
+def ragged_bench(args) -> int:
+    """One step = one captured launch of a ragged work list (forward search of
+    every pair at its own size); reports pairs/s and per-pair latency."""
+    import numpy as np
+    import torch
+
+    from paper_2203_00459_amd import fmbym, synth, workloads
+
+    cfg = workloads.RAGGED[args.workload]
+    names = synth.ragged_mix(cfg["n_pairs"], cfg["mix"])
+    sizes = [name for name, _ in cfg["mix"]]
+    dev = torch.device("cuda:0")
+    counts = {k: names.count(k) for k in sizes}
+    scans = {}
+    for k in sizes:
+        f, g, _ = synth.make_batch(k, counts[k], split="bench")
+        scans[k] = (torch.from_numpy(f).to(dev), torch.from_numpy(g).to(dev))
+    seen = {k: 0 for k in sizes}
+    pairs = []
+    for k in names:
+        j = seen[k]
+        seen[k] += 1
+        pairs.append((scans[k][0][j], scans[k][1][j]))
+    searches = [fmbym.Search(max_batch=counts[k], **workloads.search_kwargs(k)) for k in sizes]
+    r = fmbym.Ragged(searches, pairs)
+    for _ in range(args.warmup):
+        r.launch()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.steps):
+        r.launch()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    lat = r.latencies_us().numpy()
+    fwd = ("k_rows1", "k_cols1", "k_polar", "k_angle_fin", "k_rows2", "k_cols2", "k_rows3", "k_xy_fin")
+    nbytes = 0
+    for k in sizes:
+        kw = workloads.search_kwargs(k)
+        kb = kernel_bytes(kw["n"], kw["n_theta"], kw["n"], counts[k], masked=False)
+        nbytes += sum(kb[x] for x in fwd)
+    achieved = nbytes / (ms * 1e-3) / 1e9
+    res = {
+        "metric": f"scan-pairs/sec, ragged {cfg['n_pairs']}-pair forward search (mixed sizes), 1 GPU",
+        "value": cfg["n_pairs"] / (ms * 1e-3),
+        "unit": "pairs/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "pairs": counts, "pass": "fwd",
+                   "launch": "one captured graph per work list"},
+        "latency_us": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "max": float(lat.max())},
+        "roofline": {"bound": "hbm", "kernel": "whole launch", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        from oracle import fmbym_oracle as O
+        t_pair = {}
+        for k in sizes:
+            p = O.Params(**workloads.search_kwargs(k))
+            f, g = scans[k][0][0].cpu().numpy(), scans[k][1][0].cpu().numpy()
+            t0 = time.perf_counter()
+            O.search(f, g, p)
+            t_pair[k] = time.perf_counter() - t0
+        mean_t = sum(counts[k] * t_pair[k] for k in sizes) / cfg["n_pairs"]
+        res["cpu_baseline"] = {"value": 1.0 / mean_t, "unit": "pairs/s", "cores": torch.get_num_threads(),
+                               "kind": "oracle",
+                               "sample": "one pair of each size, FP64 oracle forward, weighted by the mix"}
+    print(json.dumps(res), flush=True)
+    r.close()
+    return 0
+
+
+def search_bench(args) -> int:
     import numpy as np
     import torch
 

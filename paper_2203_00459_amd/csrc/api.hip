@@ -8,14 +8,20 @@
 
 using namespace fmbym;
 
-namespace {
+namespace fmbym {
 
+namespace {
 thread_local int g_last_hip = 0;
+}
 
 int hip_fail(hipError_t e) {
     g_last_hip = (int)e;
     return FMBYM_EHIP;
 }
+
+}  // namespace fmbym
+
+namespace {
 
 bool pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 

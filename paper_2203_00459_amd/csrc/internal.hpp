@@ -56,6 +56,9 @@ int build_polar_csr(Plan& pl);
 
 inline Plan* plan_cast(fmbym_plan p) { return reinterpret_cast<Plan*>(p); }
 
+// Record e as this thread's last HIP error (fmbym_last_hip_error); returns FMBYM_EHIP.
+int hip_fail(hipError_t e);
+
 // Geometry of the polar-gather blocks.
 constexpr int kRadiiPerBlock = 8;
 inline int radius_blocks(int n_r) { return (n_r + kRadiiPerBlock - 1) / kRadiiPerBlock; }
@@ -87,9 +90,11 @@ struct FwdLayout {
 };
 FwdLayout fwd_layout(const fmbym_params& p, int batch);
 
+// tab: null for packed batches (scan b at x + b n^2), else a device table of
+// 4 pointers per pair, (f, g, m_f, m_g), for a ragged work list.
 int launch_forward(const Plan& pl, int batch, const float* f, const float* g, const float* mf,
                    const float* mg, float* pose, float* c_theta, float* c_xy, float* saved,
-                   char* ws, hipStream_t s);
+                   char* ws, hipStream_t s, const float* const* tab = nullptr);
 
 // Stage-1 row DFTs and |F| (k_rows1, k_cols1), shared by forward and adjoint.
 void launch_stage1_spectra(const Plan& pl, int batch, const float* f, const float* g, const float* mf,
@@ -102,6 +107,21 @@ int launch_backward(const Plan& pl, int batch, const float* f, const float* g, c
                     float* d_mg, char* ws, hipStream_t s);
 
 // ------------------------------------------------------------------ sampling
+
+// The scans of pair b: packed batches, or row b of a ragged pointer table.
+struct PairScans {
+    const float* f;
+    const float* g;
+    const float* mf;
+    const float* mg;
+};
+__device__ __forceinline__ PairScans pair_scans(const float* const* __restrict__ tab, int b, int n,
+                                                const float* f, const float* g, const float* mf,
+                                                const float* mg) {
+    if (tab) return PairScans{tab[4 * b], tab[4 * b + 1], tab[4 * b + 2], tab[4 * b + 3]};
+    const size_t o = (size_t)b * n * n;
+    return PairScans{f + o, g + o, mf ? mf + o : nullptr, mg ? mg + o : nullptr};
+}
 
 // Windowed (and masked) scan value at an integer pixel.
 __device__ __forceinline__ float scan_w(const float* __restrict__ x, const float* __restrict__ m,

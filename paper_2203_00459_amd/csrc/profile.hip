@@ -27,11 +27,15 @@ std::vector<Rec> g_pool;   // pre-created events
 size_t g_used = 0;
 int g_open_id = -1;
 bool g_overflow = false;
+thread_local int g_paused = 0;
 
 }  // namespace
 
+ProfilePause::ProfilePause() { ++g_paused; }
+ProfilePause::~ProfilePause() { --g_paused; }
+
 void prof_before(hipStream_t s, int id) {
-    if (!g_on.load(std::memory_order_relaxed)) return;
+    if (g_paused || !g_on.load(std::memory_order_relaxed)) return;
     std::lock_guard<std::mutex> lk(g_mu);
     if (g_used >= g_pool.size()) {
         g_overflow = true;
@@ -44,7 +48,7 @@ void prof_before(hipStream_t s, int id) {
 }
 
 void prof_after(hipStream_t s, int id) {
-    if (!g_on.load(std::memory_order_relaxed)) return;
+    if (g_paused || !g_on.load(std::memory_order_relaxed)) return;
     std::lock_guard<std::mutex> lk(g_mu);
     if (g_open_id != id) return;
     (void)hipEventRecord(g_pool[g_used].b, s);

@@ -17,6 +17,12 @@ extern const char* const kKernelNames[kKernelCount];
 void prof_before(hipStream_t s, int id);
 void prof_after(hipStream_t s, int id);
 
+// While alive, launches on this thread are not timed (used around graph capture).
+struct ProfilePause {
+    ProfilePause();
+    ~ProfilePause();
+};
+
 }  // namespace fmbym
 
 #define FMBYM_LAUNCH(id, kernel, grid, block, stream, ...)                     \

@@ -1,0 +1,253 @@
+// Ragged work lists: pairs of mixed scan sizes searched as one replayable
+// launch.  Pairs are grouped by (n, masked) in size order; each group is the
+// batched forward search of its plan reading its scans through a per-pair
+// pointer table, followed by a small kernel that moves the group's poses to
+// the caller's order and stamps the device wall clock.  The groups are
+// independent branches of one HIP graph captured at creation, so the small
+// sizes do not wait behind the large ones and a replay costs one launch call.
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "internal.hpp"
+#include "profile.hpp"
+
+namespace fmbym {
+
+namespace {
+
+struct Group {
+    const Plan* plan;
+    bool masked;
+    int first;          // first slot (row of the pointer table)
+    int count;
+    size_t ws_off;      // forward workspace of the group
+    size_t pose_off;    // [count][3] float poses of the group
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Validate the work list and lay out its groups; slots[] lists the pairs in
+// group order.  Returns FMBYM_OK or an error code; sets *bytes to the workspace.
+int plan_groups(const fmbym_plan* plans, int n_plans, const fmbym_pair* pairs, int n_pairs,
+                std::vector<Group>& groups, std::vector<int>& slots, size_t* bytes) {
+    if (!plans || n_plans < 1 || n_plans > 64 || !pairs || n_pairs < 1 || n_pairs > (1 << 20))
+        return FMBYM_EINVAL;
+    for (int k = 0; k < n_plans; ++k) {
+        if (!plans[k]) return FMBYM_EINVAL;
+        for (int j = 0; j < k; ++j)
+            if (plan_cast(plans[j])->p.n == plan_cast(plans[k])->p.n) return FMBYM_EINVAL;
+    }
+    std::vector<int> plan_of(n_pairs);
+    for (int i = 0; i < n_pairs; ++i) {
+        const fmbym_pair& q = pairs[i];
+        if (q.reserved != 0 || !q.f || !q.g || (q.m_f == nullptr) != (q.m_g == nullptr))
+            return FMBYM_EINVAL;
+        plan_of[i] = -1;
+        for (int k = 0; k < n_plans; ++k)
+            if (plan_cast(plans[k])->p.n == q.n) plan_of[i] = k;
+        if (plan_of[i] < 0) return FMBYM_EINVAL;
+    }
+    // groups in increasing n, unmasked before masked; pairs keep their order
+    std::vector<int> key(n_pairs);
+    for (int i = 0; i < n_pairs; ++i) key[i] = pairs[i].n * 2 + (pairs[i].m_f ? 1 : 0);
+    slots.resize(n_pairs);
+    for (int i = 0; i < n_pairs; ++i) slots[i] = i;
+    std::stable_sort(slots.begin(), slots.end(), [&](int a, int b) { return key[a] < key[b]; });
+    groups.clear();
+    size_t off = 0;
+    for (int s = 0; s < n_pairs;) {
+        int e = s;
+        while (e < n_pairs && key[slots[e]] == key[slots[s]]) ++e;
+        Group gr{};
+        gr.plan = plan_cast(plans[plan_of[slots[s]]]);
+        gr.masked = pairs[slots[s]].m_f != nullptr;
+        gr.first = s;
+        gr.count = e - s;
+        gr.ws_off = off;
+        off = align256(off + fwd_layout(gr.plan->p, gr.count).total);
+        gr.pose_off = off;
+        off = align256(off + (size_t)gr.count * 3 * sizeof(float));
+        groups.push_back(gr);
+        s = e;
+    }
+    *bytes = off;
+    return FMBYM_OK;
+}
+
+__global__ void k_ragged_start(unsigned long long* __restrict__ stamps, int n_pairs) {
+    if (threadIdx.x == 0) stamps[n_pairs] = (unsigned long long)wall_clock64();
+}
+
+// Poses of one group to the caller's order, then the time they were written.
+__global__ void k_ragged_poses(const float* __restrict__ pose_g, const int* __restrict__ slot_pair,
+                               int count, float* __restrict__ pose,
+                               unsigned long long* __restrict__ stamps) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= count) return;
+    const int i = slot_pair[b];
+    pose[3 * i] = pose_g[3 * b];
+    pose[3 * i + 1] = pose_g[3 * b + 1];
+    pose[3 * i + 2] = pose_g[3 * b + 2];
+    if (stamps) stamps[i] = (unsigned long long)wall_clock64();
+}
+
+}  // namespace
+
+struct Ragged {
+    int device = 0;
+    int n_pairs = 0;
+    const float** tab = nullptr;    // device [n_pairs][4] (f, g, m_f, m_g) in slot order
+    int* slot_pair = nullptr;       // device [n_pairs] pair index of each slot
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> events;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+static hipError_t ragged_free(Ragged* r) {
+    hipError_t first = hipSuccess;
+    auto keep = [&](hipError_t e) {
+        if (first == hipSuccess) first = e;
+    };
+    if (r->exec) keep(hipGraphExecDestroy(r->exec));
+    if (r->graph) keep(hipGraphDestroy(r->graph));
+    for (hipEvent_t e : r->events) keep(hipEventDestroy(e));
+    for (hipStream_t s : r->streams) keep(hipStreamDestroy(s));
+    if (r->tab) keep(hipFree(r->tab));
+    if (r->slot_pair) keep(hipFree(r->slot_pair));
+    delete r;
+    return first;
+}
+
+// Enqueue the work list on s0, forking one branch per group (used under capture).
+static int record_launch(Ragged& r, const std::vector<Group>& groups, float* pose,
+                         unsigned long long* stamps, char* ws) {
+    hipStream_t s0 = r.streams[0];
+    if (stamps) hipLaunchKernelGGL(k_ragged_start, dim3(1), dim3(64), 0, s0, stamps, r.n_pairs);
+    hipError_t e = hipEventRecord(r.events[0], s0);
+    for (size_t k = 0; k < groups.size() && e == hipSuccess; ++k) {
+        const Group& gr = groups[k];
+        hipStream_t sg = r.streams[1 + k];
+        e = hipStreamWaitEvent(sg, r.events[0], 0);
+        if (e != hipSuccess) break;
+        float* pose_g = (float*)(ws + gr.pose_off);
+        const int rc = launch_forward(*gr.plan, gr.count, nullptr, nullptr, nullptr, nullptr, pose_g,
+                                      nullptr, nullptr, nullptr, ws + gr.ws_off, sg,
+                                      r.tab + 4 * (size_t)gr.first);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_ragged_poses, dim3((gr.count + 63) / 64), dim3(64), 0, sg, pose_g,
+                           r.slot_pair + gr.first, gr.count, pose, stamps);
+        e = hipEventRecord(r.events[1 + k], sg);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s0, r.events[1 + k], 0);
+    }
+    if (e == hipSuccess) e = hipGetLastError();
+    return e == hipSuccess ? FMBYM_OK : hip_fail(e);
+}
+
+}  // namespace fmbym
+
+using namespace fmbym;
+
+extern "C" {
+
+size_t fmbym_ragged_workspace_size(const fmbym_plan* plans, int32_t n_plans, const fmbym_pair* pairs,
+                                   int32_t n_pairs) {
+    std::vector<Group> groups;
+    std::vector<int> slots;
+    size_t bytes = 0;
+    if (plan_groups(plans, n_plans, pairs, n_pairs, groups, slots, &bytes)) return 0;
+    return bytes;
+}
+
+int fmbym_ragged_create(const fmbym_plan* plans, int32_t n_plans, const fmbym_pair* pairs,
+                        int32_t n_pairs, float* pose, uint64_t* stamps, void* workspace,
+                        size_t workspace_bytes, fmbym_ragged* out) {
+    if (!out) return FMBYM_EINVAL;
+    *out = nullptr;
+    std::vector<Group> groups;
+    std::vector<int> slots;
+    size_t bytes = 0;
+    int rc = plan_groups(plans, n_plans, pairs, n_pairs, groups, slots, &bytes);
+    if (rc) return rc;
+    if (!pose) return FMBYM_EINVAL;
+    if (!workspace || workspace_bytes < bytes) return FMBYM_EWORKSPACE;
+
+    Ragged* r = new (std::nothrow) Ragged();
+    if (!r) return FMBYM_EINVAL;
+    r->n_pairs = n_pairs;
+    std::vector<const float*> tab(4 * (size_t)n_pairs);
+    for (int s = 0; s < n_pairs; ++s) {
+        const fmbym_pair& q = pairs[slots[s]];
+        tab[4 * s] = q.f;
+        tab[4 * s + 1] = q.g;
+        tab[4 * s + 2] = q.m_f;
+        tab[4 * s + 3] = q.m_g;
+    }
+    hipError_t e = hipGetDevice(&r->device);
+    if (e == hipSuccess) e = hipMalloc((void**)&r->tab, sizeof(const float*) * tab.size());
+    if (e == hipSuccess) e = hipMalloc((void**)&r->slot_pair, sizeof(int) * n_pairs);
+    if (e == hipSuccess)
+        e = hipMemcpy(r->tab, tab.data(), sizeof(const float*) * tab.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(r->slot_pair, slots.data(), sizeof(int) * n_pairs, hipMemcpyHostToDevice);
+    for (size_t k = 0; k <= groups.size() && e == hipSuccess; ++k) {
+        hipStream_t st = nullptr;
+        hipEvent_t ev = nullptr;
+        e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (e == hipSuccess) r->streams.push_back(st);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess) r->events.push_back(ev);
+    }
+    if (e != hipSuccess) {
+        ragged_free(r);
+        return hip_fail(e);
+    }
+    // capture: the profiling hooks stay out of the graph
+    ProfilePause pause;
+    e = hipStreamBeginCapture(r->streams[0], hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        ragged_free(r);
+        return hip_fail(e);
+    }
+    rc = record_launch(*r, groups, pose, (unsigned long long*)stamps, (char*)workspace);
+    hipGraph_t graph = nullptr;
+    hipError_t e_end = hipStreamEndCapture(r->streams[0], &graph);
+    r->graph = graph;
+    if (rc == FMBYM_OK && e_end != hipSuccess) rc = hip_fail(e_end);
+    if (rc == FMBYM_OK) {
+        e = hipGraphInstantiate(&r->exec, r->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) rc = hip_fail(e);
+    }
+    if (rc) {
+        ragged_free(r);
+        return rc;
+    }
+    *out = (fmbym_ragged)r;
+    return FMBYM_OK;
+}
+
+int fmbym_ragged_launch(fmbym_ragged rg, void* stream) {
+    if (!rg) return FMBYM_EINVAL;
+    Ragged* r = reinterpret_cast<Ragged*>(rg);
+    hipError_t e = hipGraphLaunch(r->exec, (hipStream_t)stream);
+    return e == hipSuccess ? FMBYM_OK : hip_fail(e);
+}
+
+int fmbym_wall_clock_khz(int32_t* khz) {
+    if (!khz) return FMBYM_EINVAL;
+    int dev = 0, v = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&v, hipDeviceAttributeWallClockRate, dev);
+    if (e != hipSuccess) return hip_fail(e);
+    *khz = v;
+    return FMBYM_OK;
+}
+
+int fmbym_ragged_destroy(fmbym_ragged rg) {
+    if (!rg) return FMBYM_EINVAL;
+    hipError_t e = ragged_free(reinterpret_cast<Ragged*>(rg));
+    return e == hipSuccess ? FMBYM_OK : hip_fail(e);
+}
+
+}  // extern "C"

@@ -35,18 +35,19 @@ __global__ __launch_bounds__(256) void k_rows1(const float* __restrict__ f, cons
                                                const float* __restrict__ mf, const float* __restrict__ mg,
                                                const float* __restrict__ hann,
                                                const float2* __restrict__ tw, float4* __restrict__ out,
-                                               int win) {
+                                               int win, const float* const* __restrict__ tab) {
     constexpr int L = N, T = L / kE, LPB = 256 / T, H = N / 2, P = pitch_rows1(N);
     __shared__ float lre[LPB][LdsRows::words(L)];
     __shared__ float lim[LPB][LdsRows::words(L)];
     const int line = threadIdx.x / T, t = threadIdx.x % T;
     const int grow = blockIdx.x * LPB + line;     // row over the batch
     const int i = grow % N;
-    const size_t off = (size_t)grow * N;
-    const float* fr = f + off;
-    const float* gr = g + off;
-    const float* mfr = mf ? mf + off : nullptr;
-    const float* mgr = mg ? mg + off : nullptr;
+    const PairScans sc = pair_scans(tab, grow / N, N, f, g, mf, mg);
+    const size_t off = (size_t)i * N;
+    const float* fr = sc.f + off;
+    const float* gr = sc.g + off;
+    const float* mfr = sc.mf ? sc.mf + off : nullptr;
+    const float* mgr = sc.mg ? sc.mg + off : nullptr;
     const float hi = win ? hann[i] : 1.f;
     float2 v[kE];
 #pragma unroll
@@ -336,25 +337,24 @@ __global__ __launch_bounds__(256) void k_rows2(const float* __restrict__ f, cons
                                                const float* __restrict__ hann,
                                                const float2* __restrict__ tw,
                                                const float* __restrict__ saved,
-                                               float4* __restrict__ out, int win) {
+                                               float4* __restrict__ out, int win,
+                                               const float* const* __restrict__ tab) {
     constexpr int L = 2 * N, T = L / kE, LPB = 256 / T, P2 = pitch_rows2(N);
     __shared__ float lre[LPB][LdsRows::words(L)];
     __shared__ float lim[LPB][LdsRows::words(L)];
     const int line = threadIdx.x / T, t = threadIdx.x % T;
     const int grow = blockIdx.x * LPB + line;
     const int b = grow / N, i = grow % N;
-    const size_t base = (size_t)b * N * N;
+    const PairScans sc = pair_scans(tab, b, N, f, g, mf, mg);
     const float ct = saved[(size_t)b * FMBYM_SAVED + kSavedCos];
     const float st = saved[(size_t)b * FMBYM_SAVED + kSavedSin];
-    const float* gb = g + base;
-    const float* mgb = mg ? mg + base : nullptr;
     float2 v[kE];
 #pragma unroll
     for (int m = 0; m < kE; ++m) {
         const int x = t + m * T;
         if (m < kE / 2) {   // x < n: data; the upper half of the padded row is zero
-            const float a = scan_w(f + base, mf ? mf + base : nullptr, hann, N, i, x, win);
-            const float c = rotate_sample(gb, mgb, hann, N, i, x, ct, st, win);
+            const float a = scan_w(sc.f, sc.mf, hann, N, i, x, win);
+            const float c = rotate_sample(sc.g, sc.mg, hann, N, i, x, ct, st, win);
             v[m] = make_float2(a, c);
         } else {
             v[m] = make_float2(0.f, 0.f);
@@ -564,11 +564,11 @@ template <int N> constexpr int cols2_tile() { return N >= 256 ? 8 : 16; }
 template <int N>
 static void launch_stage1_rows_cols(const Plan& pl, int B, const float* f, const float* g,
                                     const float* mf, const float* mg, float4* r1, float2* mag,
-                                    hipStream_t s) {
+                                    hipStream_t s, const float* const* tab) {
     const int win = (pl.p.flags & FMBYM_HANN) ? 1 : 0;
     constexpr int T1 = N / kE, LPB1 = 256 / T1;
     FMBYM_LAUNCH(kKRows1, k_rows1<N>, dim3(B * N / LPB1), dim3(256), s, f, g, mf, mg, pl.hann,
-                 pl.twiddle, r1, win);
+                 pl.twiddle, r1, win, tab);
     constexpr int C = cols1_tile<N>();
     FMBYM_LAUNCH(kKCols1, (k_cols1<N, C>), dim3(B * ((N / 2) / C + 1)), dim3(C * N / kE), s, r1, mag,
                  pl.twiddle, pl.band_on, pl.band_lo2, pl.band_hi2);
@@ -577,9 +577,9 @@ static void launch_stage1_rows_cols(const Plan& pl, int B, const float* f, const
 void launch_stage1_spectra(const Plan& pl, int B, const float* f, const float* g, const float* mf,
                            const float* mg, float4* r1, float2* mag, hipStream_t s) {
     switch (pl.p.n) {
-        case 128: launch_stage1_rows_cols<128>(pl, B, f, g, mf, mg, r1, mag, s); break;
-        case 256: launch_stage1_rows_cols<256>(pl, B, f, g, mf, mg, r1, mag, s); break;
-        case 512: launch_stage1_rows_cols<512>(pl, B, f, g, mf, mg, r1, mag, s); break;
+        case 128: launch_stage1_rows_cols<128>(pl, B, f, g, mf, mg, r1, mag, s, nullptr); break;
+        case 256: launch_stage1_rows_cols<256>(pl, B, f, g, mf, mg, r1, mag, s, nullptr); break;
+        case 512: launch_stage1_rows_cols<512>(pl, B, f, g, mf, mg, r1, mag, s, nullptr); break;
         default: break;
     }
 }
@@ -598,14 +598,14 @@ static void launch_polar(const Plan& pl, int B, const float2* mag, float2* pth, 
 template <int N>
 static int launch_n(const Plan& pl, int B, const float* f, const float* g, const float* mf,
                     const float* mg, float* pose, float* c_theta, float* c_xy, float* saved,
-                    char* ws, hipStream_t s) {
+                    char* ws, hipStream_t s, const float* const* tab) {
     const FwdLayout lay = fwd_layout(pl.p, B);
     float4* r1 = (float4*)(ws + lay.r1r2);
     float2* mag = (float2*)(ws + lay.mag_r3);
     float2* pth = (float2*)(ws + lay.ptheta);
     float4* pxy = (float4*)(ws + lay.pxy);
     float* sv = saved ? saved : (float*)(ws + lay.saved);
-    launch_stage1_rows_cols<N>(pl, B, f, g, mf, mg, r1, mag, s);
+    launch_stage1_rows_cols<N>(pl, B, f, g, mf, mg, r1, mag, s, tab);
     switch (pl.p.n_theta) {
         case 16: launch_polar<N, 16>(pl, B, mag, pth, c_theta, pose, sv, s); break;
         case 32: launch_polar<N, 32>(pl, B, mag, pth, c_theta, pose, sv, s); break;
@@ -621,7 +621,7 @@ static int launch_n(const Plan& pl, int B, const float* f, const float* g, const
     float2* r3 = mag;                   // magnitudes are dead after k_polar
     constexpr int T2 = 2 * N / kE, LPB2 = 256 / T2;
     FMBYM_LAUNCH(kKRows2, k_rows2<N>, dim3(B * N / LPB2), dim3(256), s, f, g, mf, mg, pl.hann,
-                 pl.twiddle, sv, r2, win2);
+                 pl.twiddle, sv, r2, win2, tab);
     constexpr int C2 = cols2_tile<N>();
     const int total2 = B * (N / C2 + 1);
     FMBYM_LAUNCH(kKCols2, (k_cols2<N, C2>), dim3(((total2 + 7) / 8) * 8), dim3(C2 * 2 * N / kE), s, r2,
@@ -636,11 +636,11 @@ static int launch_n(const Plan& pl, int B, const float* f, const float* g, const
 
 int launch_forward(const Plan& pl, int batch, const float* f, const float* g, const float* mf,
                    const float* mg, float* pose, float* c_theta, float* c_xy, float* saved,
-                   char* ws, hipStream_t s) {
+                   char* ws, hipStream_t s, const float* const* tab) {
     switch (pl.p.n) {
-        case 128: return launch_n<128>(pl, batch, f, g, mf, mg, pose, c_theta, c_xy, saved, ws, s);
-        case 256: return launch_n<256>(pl, batch, f, g, mf, mg, pose, c_theta, c_xy, saved, ws, s);
-        case 512: return launch_n<512>(pl, batch, f, g, mf, mg, pose, c_theta, c_xy, saved, ws, s);
+        case 128: return launch_n<128>(pl, batch, f, g, mf, mg, pose, c_theta, c_xy, saved, ws, s, tab);
+        case 256: return launch_n<256>(pl, batch, f, g, mf, mg, pose, c_theta, c_xy, saved, ws, s, tab);
+        case 512: return launch_n<512>(pl, batch, f, g, mf, mg, pose, c_theta, c_xy, saved, ws, s, tab);
         default: return FMBYM_EUNSUPPORTED;
     }
 }

@@ -40,7 +40,8 @@ FMBYM_SAVED_THETA_NU = 11
 EXPORTS = (
     "fmbym_plan_create", "fmbym_plan_destroy", "fmbym_search_workspace_size", "fmbym_search",
     "fmbym_search_backward", "fmbym_strerror", "fmbym_last_hip_error", "fmbym_profile_enable",
-    "fmbym_profile_read",
+    "fmbym_profile_read", "fmbym_ragged_workspace_size", "fmbym_ragged_create",
+    "fmbym_ragged_launch", "fmbym_ragged_destroy", "fmbym_wall_clock_khz",
 )
 
 
@@ -49,6 +50,13 @@ class fmbym_params(ctypes.Structure):
         ("n", ctypes.c_int32), ("n_theta", ctypes.c_int32), ("n_r", ctypes.c_int32),
         ("delta_xy", ctypes.c_float), ("temp_theta", ctypes.c_float), ("temp_xy", ctypes.c_float),
         ("band_lo", ctypes.c_float), ("band_hi", ctypes.c_float), ("flags", ctypes.c_uint32),
+    ]
+
+
+class fmbym_pair(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32), ("reserved", ctypes.c_int32), ("f", ctypes.c_void_p),
+        ("g", ctypes.c_void_p), ("m_f", ctypes.c_void_p), ("m_g", ctypes.c_void_p),
     ]
 
 
@@ -91,6 +99,18 @@ def lib() -> ctypes.CDLL:
         L.fmbym_profile_read.argtypes = [I32, ctypes.POINTER(ctypes.c_char_p),
                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I32)]
         L.fmbym_profile_read.restype = ctypes.c_int
+        PP = ctypes.POINTER(fmbym_pair)
+        L.fmbym_ragged_workspace_size.argtypes = [ctypes.POINTER(VP), I32, PP, I32]
+        L.fmbym_ragged_workspace_size.restype = SZ
+        L.fmbym_ragged_create.argtypes = [ctypes.POINTER(VP), I32, PP, I32, VP, VP, VP, SZ,
+                                          ctypes.POINTER(VP)]
+        L.fmbym_ragged_create.restype = ctypes.c_int
+        L.fmbym_ragged_launch.argtypes = [VP, VP]
+        L.fmbym_ragged_launch.restype = ctypes.c_int
+        L.fmbym_ragged_destroy.argtypes = [VP]
+        L.fmbym_ragged_destroy.restype = ctypes.c_int
+        L.fmbym_wall_clock_khz.argtypes = [ctypes.POINTER(I32)]
+        L.fmbym_wall_clock_khz.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -157,6 +177,47 @@ def profile_read() -> dict:
     if rc < 0:
         raise FmbymError(rc, "fmbym_profile_read")
     return {names[k].decode(): (ms[k], cnt[k]) for k in range(rc) if cnt[k] > 0}
+
+
+def _plan_array(plans):
+    arr = (ctypes.c_void_p * len(plans))()
+    for k, p in enumerate(plans):
+        arr[k] = p.value if isinstance(p, ctypes.c_void_p) else p
+    return arr
+
+
+def ragged_workspace_size(plans, pairs) -> int:
+    """plans: plan handles; pairs: a ctypes array of fmbym_pair."""
+    return int(lib().fmbym_ragged_workspace_size(_plan_array(plans), len(plans), pairs, len(pairs)))
+
+
+def ragged_create(plans, pairs, pose, stamps, workspace, workspace_bytes) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    rc = lib().fmbym_ragged_create(_plan_array(plans), len(plans), pairs, len(pairs), pose, stamps,
+                                   workspace, int(workspace_bytes), ctypes.byref(h))
+    if rc:
+        raise FmbymError(rc, "fmbym_ragged_create")
+    return h
+
+
+def ragged_launch(ragged, stream) -> None:
+    rc = lib().fmbym_ragged_launch(ragged, stream)
+    if rc:
+        raise FmbymError(rc, "fmbym_ragged_launch")
+
+
+def ragged_destroy(ragged) -> None:
+    rc = lib().fmbym_ragged_destroy(ragged)
+    if rc:
+        raise FmbymError(rc, "fmbym_ragged_destroy")
+
+
+def wall_clock_khz() -> int:
+    v = ctypes.c_int32()
+    rc = lib().fmbym_wall_clock_khz(ctypes.byref(v))
+    if rc:
+        raise FmbymError(rc, "fmbym_wall_clock_khz")
+    return int(v.value)
 
 
 # ------------------------------------------------------------------ plumbing
@@ -254,3 +315,58 @@ class SearchFunction(torch.autograd.Function):
         f, g, m_f, m_g = ctx.saved_tensors
         r = ctx.searcher.backward(f, g, m_f, m_g, ctx.fwd, d_pose)
         return None, r["d_f"], r["d_g"], r["d_m_f"], r["d_m_g"]
+
+
+class Ragged:
+    """A ragged work list (pairs of mixed sizes) as one replayable launch.
+
+    ``searches`` are Search objects with distinct n; ``pairs`` is a list of
+    (f, g) or (f, g, m_f, m_g) device tensors, each [n, n] for one of those n.
+    The tensors must stay alive and in place: every launch reads them anew.
+    ``pose`` [P, 3] and ``stamps`` [P + 1] (int64 wall-clock ticks, the last one
+    the launch start) are refreshed by every launch.
+    """
+
+    def __init__(self, searches, pairs, stamps: bool = True):
+        self.searches = list(searches)
+        self._keep = []
+        arr = (fmbym_pair * len(pairs))()
+        dev = None
+        for i, q in enumerate(pairs):
+            f, g = q[0], q[1]
+            m_f, m_g = (q[2], q[3]) if len(q) > 2 else (None, None)
+            n = f.shape[-1]
+            arr[i] = fmbym_pair(n, 0, _ptr(f, (n, n), "f"), _ptr(g, (n, n), "g"),
+                                _ptr(m_f, (n, n), "m_f"), _ptr(m_g, (n, n), "m_g"))
+            self._keep.append(q)
+            dev = f.device
+        plans = [s.plan for s in self.searches]
+        need = ragged_workspace_size(plans, arr)
+        if need == 0:
+            raise FmbymError(FMBYM_EINVAL, "fmbym_ragged_workspace_size")
+        self.workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+        self.pose = torch.zeros(len(pairs), 3, device=dev)
+        self.stamps = torch.zeros(len(pairs) + 1, dtype=torch.int64, device=dev) if stamps else None
+        self.handle = ragged_create(plans, arr, self.pose.data_ptr(),
+                                    None if self.stamps is None else self.stamps.data_ptr(),
+                                    self.workspace.data_ptr(), need)
+
+    def launch(self) -> torch.Tensor:
+        ragged_launch(self.handle, _stream())
+        return self.pose
+
+    def latencies_us(self) -> torch.Tensor:
+        """Per-pair time from the launch start to its pose write, in microseconds."""
+        s = self.stamps.cpu()
+        return (s[:-1] - s[-1]).double() * 1e3 / wall_clock_khz()
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            ragged_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -222,3 +222,14 @@ def noise_batch(n: int, batch: int, seed: int = 0):
     """Uniform-noise scans, the input used for the method's timing runs (Section IV-C)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return (rng.random((batch, n, n), dtype=np.float32), rng.random((batch, n, n), dtype=np.float32))
+
+
+def ragged_mix(n_pairs: int, mix, seed: int = 0) -> list[str]:
+    """Workload names for a ragged work list: ``mix`` is ((name, fraction), ...);
+    counts are rounded down, the remainder goes to the first entry, and the
+    order is a seeded shuffle."""
+    counts = [int(math.floor(frac * n_pairs)) for _, frac in mix]
+    counts[0] += n_pairs - sum(counts)
+    names = [name for (name, _), c in zip(mix, counts) for _ in range(c)]
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return [names[i] for i in rng.permutation(n_pairs)]

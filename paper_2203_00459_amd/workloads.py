@@ -17,6 +17,12 @@ SEARCH = {
                      band_lo=0.02, band_hi=0.40),
 }
 
+# Ragged serving batches: pairs of the three sizes above in one launch.
+RAGGED = {
+    # 1024 pairs: half 128 x 128, 30 % 256 x 256, 20 % 512 x 512, each with its size's parameters
+    "ragged1024": dict(n_pairs=1024, mix=(("pair128", 0.5), ("batch256", 0.3), ("batch512", 0.2))),
+}
+
 
 def search_kwargs(name: str) -> dict:
     """Keyword arguments shared by the library's Search and the oracle's Params."""

@@ -77,6 +77,32 @@ def test_calls_without_a_plan_are_rejected():
     assert L.fmbym_plan_create(ctypes.byref(p), 0, ctypes.byref(h)) == fmbym.FMBYM_EINVAL
 
 
+def test_ragged_calls_reject_bad_arguments():
+    L = fmbym.lib()
+    pairs = (fmbym.fmbym_pair * 1)()
+    assert L.fmbym_ragged_workspace_size(None, 1, pairs, 1) == 0
+    plans = (ctypes.c_void_p * 1)()
+    assert L.fmbym_ragged_workspace_size(plans, 1, pairs, 1) == 0        # null plan
+    assert L.fmbym_ragged_workspace_size(plans, 0, pairs, 1) == 0
+    h = ctypes.c_void_p()
+    assert L.fmbym_ragged_create(None, 1, pairs, 1, None, None, None, 0,
+                                 ctypes.byref(h)) == fmbym.FMBYM_EINVAL
+    assert L.fmbym_ragged_create(plans, 1, pairs, 1, None, None, None, 0, None) == fmbym.FMBYM_EINVAL
+    assert L.fmbym_ragged_launch(None, None) == fmbym.FMBYM_EINVAL
+    assert L.fmbym_ragged_destroy(None) == fmbym.FMBYM_EINVAL
+    assert L.fmbym_wall_clock_khz(None) == fmbym.FMBYM_EINVAL
+
+
+def test_ragged_mix_counts_and_order():
+    from paper_2203_00459_amd import synth, workloads
+    cfg = workloads.RAGGED["ragged1024"]
+    names = synth.ragged_mix(cfg["n_pairs"], cfg["mix"])
+    assert len(names) == 1024
+    assert (names.count("pair128"), names.count("batch256"), names.count("batch512")) == (513, 307, 204)
+    assert names == synth.ragged_mix(cfg["n_pairs"], cfg["mix"])
+    assert names[:8] != sorted(names[:8]) or names[8:16] != sorted(names[8:16])
+
+
 def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
     monkeypatch.setattr(fmbym, "_lib", None)
     monkeypatch.setattr(fmbym, "LIB_PATH", str(tmp_path / "missing.so"))
