@@ -89,11 +89,22 @@ def init_params(levels: int, base: int, seed: int = 0) -> np.ndarray:
     return np.concatenate(parts).astype(np.float32)
 
 
-def conv_bn_relu(x, w, gamma, beta, eps):
-    """3x3 convolution (padding 1, no bias), BatchNorm on batch statistics, ReLU."""
-    z = F.conv2d(x, w, padding=1)
+def bf16(x, on: bool = True):
+    """Round to bfloat16 (nearest, ties to even) as the stored value, with an
+    identity derivative (the rounding is a storage format, not part of the
+    function being differentiated)."""
+    if not on:
+        return x
+    return x + (x.to(torch.bfloat16).to(x.dtype) - x).detach()
+
+
+def conv_bn_relu(x, w, gamma, beta, eps, quant: bool = False):
+    """3x3 convolution (padding 1, no bias), BatchNorm on batch statistics, ReLU.
+    With quant, the conv output z and the activation are stored in bfloat16 and
+    the statistics are those of the stored z."""
+    z = bf16(F.conv2d(x, bf16(w, quant), padding=1), quant)
     y = F.batch_norm(z, None, None, gamma, beta, training=True, eps=eps)
-    return z, F.relu(y)
+    return z, bf16(F.relu(y), quant)
 
 
 def up2(x):
@@ -101,25 +112,29 @@ def up2(x):
     return F.interpolate(x, scale_factor=2, mode="bilinear", align_corners=False)
 
 
-def forward(x, theta, levels: int, base: int, eps: float = 1e-5, keep: bool = False):
+def forward(x, theta, levels: int, base: int, eps: float = 1e-5, keep: bool = False,
+            quant: bool = False):
     """Masks for images x [I, n, n] (FP64 tensors); theta is the flat FP64 vector.
-    Returns m [I, n, n] and, with keep=True, every intermediate by name."""
+    Returns m [I, n, n] and, with keep=True, every intermediate by name.
+    quant=True stores the scan, the conv weights, every conv output, activation
+    and upsampled tensor in bfloat16 (the arithmetic stays FP64); the head's
+    weights and everything after the last activation stay unrounded."""
     P = unpack(theta, levels, base)
-    h = x[:, None]
+    h = bf16(x[:, None], quant)
     acts, skips = {}, []
     for l in range(levels):
         if l > 0:
             h = F.max_pool2d(h, 2)
             acts[f"pool{l}"] = h
         for part in "ab":
-            z, h = conv_bn_relu(h, *P[f"enc{l}{part}"], eps)
+            z, h = conv_bn_relu(h, *P[f"enc{l}{part}"], eps, quant)
             acts[f"enc{l}{part}.z"], acts[f"enc{l}{part}"] = z, h
         skips.append(h)
     for l in range(levels - 2, -1, -1):
-        h = torch.cat([up2(h), skips[l]], dim=1)
+        h = torch.cat([bf16(up2(h), quant), skips[l]], dim=1)
         acts[f"cat{l}"] = h
         for part in "ab":
-            z, h = conv_bn_relu(h, *P[f"dec{l}{part}"], eps)
+            z, h = conv_bn_relu(h, *P[f"dec{l}{part}"], eps, quant)
             acts[f"dec{l}{part}.z"], acts[f"dec{l}{part}"] = z, h
     wh, bh = P["head"]
     logit = F.conv2d(h, wh, bh, padding=1)
@@ -154,9 +169,49 @@ def adam_step(theta, grad, m, v, step: int, lr: float, b1: float = 0.9, b2: floa
     return theta - lr * mh / (torch.sqrt(vh) + eps), m, v
 
 
-def grad(x, d_mask, theta, levels: int, base: int, eps: float = 1e-5):
+def running_stats(x, theta, levels: int, base: int, run_mean, run_var, momentum: float = 0.1,
+                  eps: float = 1e-5, quant: bool = False):
+    """Running statistics after one training pass: each BN channel moves by
+    `momentum` towards its batch mean and unbiased batch variance."""
+    _, acts = forward(x, theta, levels, base, eps, keep=True, quant=quant)
+    means, vars_ = [], []
+    for c in conv_list(levels, base):
+        z = acts[f"{c.name}.z"]
+        means.append(z.mean(dim=(0, 2, 3)))
+        vars_.append(z.var(dim=(0, 2, 3), unbiased=True))
+    mu, var = torch.cat(means), torch.cat(vars_)
+    return (1 - momentum) * run_mean + momentum * mu, (1 - momentum) * run_var + momentum * var
+
+
+def forward_eval(x, theta, levels: int, base: int, run_mean, run_var, eps: float = 1e-5):
+    """Masks with BatchNorm on the given running statistics (inference)."""
+    P = unpack(theta, levels, base)
+    stats, o = {}, 0
+    for c in conv_list(levels, base):
+        stats[c.name] = (run_mean[o:o + c.c_out], run_var[o:o + c.c_out])
+        o += c.c_out
+
+    def cbr(h, name):
+        w, g, b = P[name]
+        z = F.conv2d(h, w, padding=1)
+        return F.relu(F.batch_norm(z, *stats[name], g, b, training=False, eps=eps))
+
+    h, skips = x[:, None], []
+    for l in range(levels):
+        if l > 0:
+            h = F.max_pool2d(h, 2)
+        h = cbr(cbr(h, f"enc{l}a"), f"enc{l}b")
+        skips.append(h)
+    for l in range(levels - 2, -1, -1):
+        h = torch.cat([up2(h), skips[l]], dim=1)
+        h = cbr(cbr(h, f"dec{l}a"), f"dec{l}b")
+    wh, bh = P["head"]
+    return torch.sigmoid(F.conv2d(h, wh, bh, padding=1))[:, 0]
+
+
+def grad(x, d_mask, theta, levels: int, base: int, eps: float = 1e-5, quant: bool = False):
     """d<mask, d_mask>/d theta by FP64 autograd (the mask network's adjoint)."""
     th = theta.detach().clone().requires_grad_(True)
-    m = forward(x, th, levels, base, eps)
+    m = forward(x, th, levels, base, eps, quant=quant)
     (m * d_mask).sum().backward()
     return th.grad.detach()

@@ -1,0 +1,874 @@
+// Kernels of the mask network: BF16 matrix-core 3x3 convolutions (forward,
+// data gradient through the same kernel with flipped weights, weight gradient)
+// and the FP32 element-wise layers (batch norm, ReLU, pooling, upsampling,
+// head, optimiser, loss).  Every reduction runs in a fixed order, so results
+// are bitwise reproducible.
+//
+// Matrix-core operand layout (v_mfma_f32_16x16x32_bf16): lane l holds
+// A[l % 16][8 (l / 16) .. + 7], B[8 (l / 16) .. + 7][l % 16] and receives
+// D[4 (l / 16) + r][l % 16], r < 4.
+#include <math.h>
+
+#include "mask_kernels.hpp"
+
+namespace fmbym {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+// Input channels staged per pass: all of them up to 32, else 32 or 24 at a time.
+__host__ __device__ constexpr int chunk_ch(int cin) { return cin <= 32 ? cin : (cin % 32 == 0 ? 32 : 24); }
+
+// Pixels of a conv tile's input patch, (rows + 2) x (cols + 2), at side S.
+__host__ __device__ constexpr int patch_pixels(int S) {
+    return S >= kConvTile ? 3 * (kConvTile + 2) : (kConvTile / S + 2) * (S + 2);
+}
+
+// Dynamic LDS bytes of the staged patch (G + 1 groups of 16 bytes per pixel).
+constexpr size_t patch_bytes(int cin, int S) { return (size_t)patch_pixels(S) * (chunk_ch(cin) / 8 + 1) * 16; }
+
+constexpr size_t kLdsLimit = 64 * 1024;
+
+__device__ __forceinline__ bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+__device__ __forceinline__ f32x4 mfma(u32x4 a, u32x4 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a), as_bf16x8(b), c, 0, 0, 0);
+}
+
+// Output tile of conv block `blk`: image, first row/column, rows x cols.
+struct TileGeo {
+    int img, y0, x0, pr, pc;
+};
+
+__device__ __forceinline__ TileGeo tile_geo(int blk, int S) {
+    TileGeo t;
+    const int per_img = S * S / kConvTile;
+    t.img = blk / per_img;
+    const int k = blk % per_img;
+    if (S >= kConvTile) {
+        const int per_row = S / kConvTile;
+        t.pr = 1;
+        t.pc = kConvTile;
+        t.y0 = k / per_row;
+        t.x0 = (k % per_row) * kConvTile;
+    } else {
+        t.pc = S;
+        t.pr = kConvTile / S;
+        t.y0 = k * t.pr;
+        t.x0 = 0;
+    }
+    return t;
+}
+
+// Stage channels [c0, c0 + 8G) of the tile's input patch (one pixel of halo on
+// every side, zeros outside the image) as G groups of 8 channels per pixel at a
+// pitch of G + 1 groups.
+template <int CIN, int G>
+__device__ __forceinline__ void stage_patch(const bf16* __restrict__ in, u32x4* patch, const TileGeo& t,
+                                            int S, int c0) {
+    const int W = t.pc + 2, npix = (t.pr + 2) * W;
+    const bf16* base = in + (size_t)t.img * S * S * CIN;
+    for (int it = threadIdx.x; it < npix * G; it += blockDim.x) {
+        const int q = it / G, cg = it % G;
+        const int y = t.y0 - 1 + q / W, x = t.x0 - 1 + q % W;
+        u32x4 v = {0u, 0u, 0u, 0u};
+        if (y >= 0 && y < S && x >= 0 && x < S)
+            v = *(const u32x4*)(base + ((size_t)y * S + x) * CIN + c0 + 8 * cg);
+        patch[q * (G + 1) + cg] = v;
+    }
+}
+
+// ------------------------------------------------------------ convolution
+
+// out = conv3x3(in, w) over one 256-pixel tile per block, all output channels.
+// K runs over (tap, input channel) in groups of 8; every 32-wide K step is one
+// matrix-core instruction per (16-pixel M-tile, 16-channel N-tile).  Each wave
+// owns 4 M-tiles; A comes from the LDS patch, B from the packed weights.
+template <int CIN, int COUT, bool STATS, class OutT>
+__global__ __launch_bounds__(256) void k_conv3x3(const bf16* __restrict__ in, const bf16* __restrict__ w,
+                                                 OutT* __restrict__ out, float* __restrict__ part,
+                                                 int S) {
+    constexpr int CC = chunk_ch(CIN), NCH = CIN / CC, G = CC / 8, NQ = 9 * G, NS = (NQ + 3) / 4;
+    constexpr int NT = pad16(COUT) / 16, K = 9 * CIN;
+    static_assert(CIN % 8 == 0 && CIN % CC == 0, "input channels in groups of 8");
+    extern __shared__ u32x4 patch[];   // patch_bytes(CIN, S)
+    const TileGeo t = tile_geo(blockIdx.x, S);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, r16 = lane & 15;
+    const int W = t.pc + 2;
+    int prow[4], pcol[4];
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi) {
+        const int p = (wave + 4 * mi) * 16 + r16;
+        prow[mi] = p / t.pc;
+        pcol[mi] = p % t.pc;
+    }
+    f32x4 acc[4][NT];
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[mi][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const u32x4 zero = {0u, 0u, 0u, 0u};
+    for (int ch = 0; ch < NCH; ++ch) {
+        const int c0 = ch * CC;
+        if (ch) __syncthreads();
+        stage_patch<CIN, G>(in, patch, t, S, c0);
+        __syncthreads();
+#pragma unroll
+        for (int st = 0; st < NS; ++st) {
+            const int q = 4 * st + g;
+            const bool valid = q < NQ;
+            const int tap = valid ? q / G : 0, cg = q % G;
+            const int ky = tap / 3, kx = tap % 3;
+            u32x4 a[4], b[NT];
+#pragma unroll
+            for (int mi = 0; mi < 4; ++mi)
+                a[mi] = valid ? patch[((prow[mi] + ky) * W + pcol[mi] + kx) * (G + 1) + cg] : zero;
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const int co = nt * 16 + r16;
+                b[nt] = (valid && co < COUT)
+                            ? *(const u32x4*)(w + (size_t)co * K + tap * CIN + c0 + 8 * cg)
+                            : zero;
+            }
+#pragma unroll
+            for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) acc[mi][nt] = mfma(a[mi], b[nt], acc[mi][nt]);
+        }
+    }
+    float s1[NT], s2[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) s1[nt] = s2[nt] = 0.f;
+    const size_t img_base = (size_t)t.img * S * S;
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int p = (wave + 4 * mi) * 16 + 4 * g + r;
+            const size_t pix = img_base + (size_t)(t.y0 + p / t.pc) * S + t.x0 + p % t.pc;
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const int co = nt * 16 + r16;
+                if (co >= COUT) continue;
+                const float v = acc[mi][nt][r];
+                if constexpr (STATS) {
+                    const bf16 h = (bf16)v;
+                    out[pix * COUT + co] = h;
+                    const float hv = (float)h;
+                    s1[nt] += hv;
+                    s2[nt] += hv * hv;
+                } else {
+                    out[pix * COUT + co] = v;
+                }
+            }
+        }
+    if constexpr (STATS) {
+        __shared__ float red[4][2][NT * 16];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            s1[nt] += __shfl_xor(s1[nt], 16);
+            s1[nt] += __shfl_xor(s1[nt], 32);
+            s2[nt] += __shfl_xor(s2[nt], 16);
+            s2[nt] += __shfl_xor(s2[nt], 32);
+            if (g == 0) {
+                red[wave][0][nt * 16 + r16] = s1[nt];
+                red[wave][1][nt * 16 + r16] = s2[nt];
+            }
+        }
+        __syncthreads();
+        for (int c = threadIdx.x; c < COUT; c += blockDim.x) {
+            float a = 0.f, b = 0.f;
+#pragma unroll
+            for (int wv = 0; wv < 4; ++wv) {
+                a += red[wv][0][c];
+                b += red[wv][1][c];
+            }
+            part[(size_t)blockIdx.x * 2 * COUT + c] = a;
+            part[(size_t)blockIdx.x * 2 * COUT + COUT + c] = b;
+        }
+    }
+}
+
+// Weight gradient over `tpb` consecutive tiles per block:
+// part[block][co][tap CIN + ci] = sum over the tiles' pixels of dz[p][co] in[p + tap][ci].
+// M = output channels, N = (tap, input channel) columns of one channel chunk,
+// K = pixels in steps of 32.  Both operands are gathered from LDS (dz tile and
+// input patch), 8 pixels per lane.
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) void k_wgrad(const bf16* __restrict__ dz, const bf16* __restrict__ in,
+                                               float* __restrict__ part, int S, int tpb, int tiles) {
+    constexpr int CC = chunk_ch(CIN), NCH = CIN / CC, G = CC / 8;
+    constexpr int MT = pad16(COUT) / 16, KC = 9 * CC, NTK = (KC + 15) / 16, NTW = (NTK + 3) / 4;
+    constexpr int K = 9 * CIN;
+    extern __shared__ u32x4 patch[];   // patch_bytes(CIN, S), then the dz tile [256][COUT]
+    bf16* dzt = reinterpret_cast<bf16*>(patch + (size_t)patch_pixels(S) * (G + 1));
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, r16 = lane & 15;
+    const bf16* pe = reinterpret_cast<const bf16*>(patch);
+    for (int ch = 0; ch < NCH; ++ch) {
+        const int c0 = ch * CC;
+        f32x4 acc[MT][NTW];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int j = 0; j < NTW; ++j) acc[mt][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int k = 0; k < tpb; ++k) {
+            const int tile = blockIdx.x * tpb + k;
+            if (tile >= tiles) break;
+            const TileGeo t = tile_geo(tile, S);
+            __syncthreads();
+            stage_patch<CIN, G>(in, patch, t, S, c0);
+            {
+                const size_t img_base = (size_t)t.img * S * S;
+                for (int it = threadIdx.x; it < kConvTile * COUT / 8; it += blockDim.x) {
+                    const int p = it / (COUT / 8), cg = it % (COUT / 8);
+                    const size_t pix = img_base + (size_t)(t.y0 + p / t.pc) * S + t.x0 + p % t.pc;
+                    *(u32x4*)(dzt + p * COUT + 8 * cg) = *(const u32x4*)(dz + pix * COUT + 8 * cg);
+                }
+            }
+            __syncthreads();
+            const int W = t.pc + 2;
+#pragma unroll 2
+            for (int st = 0; st < kConvTile / 32; ++st) {
+                const int p0 = 32 * st + 8 * g;           // this lane's 8 pixels (one tile row)
+                const int row = p0 / t.pc, col = p0 % t.pc;
+                u32x4 a[MT];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    const int co = mt * 16 + r16;
+                    bf16x8 v;
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) v[j] = co < COUT ? dzt[(p0 + j) * COUT + co] : (bf16)0.f;
+                    a[mt] = __builtin_bit_cast(u32x4, v);
+                }
+#pragma unroll
+                for (int j = 0; j < NTW; ++j) {
+                    const int nt = wave + 4 * j;
+                    if (nt >= NTK) break;
+                    const int kc = nt * 16 + r16;
+                    bf16x8 v;
+                    if (kc < KC) {
+                        const int tap = kc / CC, ci = kc % CC;
+                        const int base = ((row + tap / 3) * W + col + tap % 3) * (G + 1) * 8 + ci;
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) v[e] = pe[base + e * (G + 1) * 8];
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) v[e] = (bf16)0.f;
+                    }
+                    const u32x4 b = __builtin_bit_cast(u32x4, v);
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) acc[mt][j] = mfma(a[mt], b, acc[mt][j]);
+                }
+            }
+        }
+        float* pb = part + (size_t)blockIdx.x * COUT * K;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int j = 0; j < NTW; ++j) {
+                const int nt = wave + 4 * j;
+                if (nt >= NTK) break;
+                const int kc = nt * 16 + r16;
+                if (kc >= KC) continue;
+                const int kg = (kc / CC) * CIN + c0 + kc % CC;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int co = mt * 16 + 4 * g + r;
+                    if (co < COUT) pb[(size_t)co * K + kg] = acc[mt][j][r];
+                }
+            }
+    }
+}
+
+// out[j] = sum_b part[b stride + j], b ascending (one thread per column).
+__global__ void k_reduce_cols(const float* __restrict__ part, int nb, long long stride, int n,
+                              float* __restrict__ out) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    float s = 0.f;
+    for (int b = 0; b < nb; ++b) s += part[(size_t)b * stride + j];
+    out[j] = s;
+}
+
+// ------------------------------------------------------------ element-wise
+
+__global__ void k_input8(const float* __restrict__ x, bf16* __restrict__ x8, long long npix) {
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npix) return;
+    bf16x8 v;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = (bf16)0.f;
+    v[0] = (bf16)x[p];
+    *(u32x4*)(x8 + p * 8) = __builtin_bit_cast(u32x4, v);
+}
+
+// Batch-norm statistics from the conv partials (double-precision sums in block order).
+__global__ void k_bn_stats(const float* __restrict__ part, int nb, int C, long long M,
+                           const float* __restrict__ gamma, const float* __restrict__ beta, float eps,
+                           float momentum, int training, float* __restrict__ run_mean,
+                           float* __restrict__ run_var, float* __restrict__ stat) {
+    const int c = blockIdx.x;
+    __shared__ double r1[256], r2[256];
+    double a = 0.0, b = 0.0;
+    for (int k = threadIdx.x; k < nb; k += blockDim.x) {
+        a += part[(size_t)k * 2 * C + c];
+        b += part[(size_t)k * 2 * C + C + c];
+    }
+    r1[threadIdx.x] = a;
+    r2[threadIdx.x] = b;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            r1[threadIdx.x] += r1[threadIdx.x + s];
+            r2[threadIdx.x] += r2[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    double mean, var;
+    if (training) {
+        mean = r1[0] / (double)M;
+        var = r2[0] / (double)M - mean * mean;
+        if (var < 0.0) var = 0.0;
+        const double unb = M > 1 ? var * (double)M / (double)(M - 1) : var;
+        run_mean[c] = (float)((1.0 - momentum) * run_mean[c] + momentum * mean);
+        run_var[c] = (float)((1.0 - momentum) * run_var[c] + momentum * unb);
+    } else {
+        mean = run_mean[c];
+        var = run_var[c];
+    }
+    const double inv = 1.0 / sqrt(var + (double)eps);
+    const double sc = (double)gamma[c] * inv;
+    stat[c] = (float)mean;
+    stat[C + c] = (float)inv;
+    stat[2 * C + c] = (float)sc;
+    stat[3 * C + c] = (float)((double)beta[c] - mean * sc);
+}
+
+__global__ void k_bn_relu(const bf16* __restrict__ z, const float* __restrict__ stat,
+                          bf16* __restrict__ a, long long items, int C) {
+    const long long it = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (it >= items) return;
+    const int c0 = (int)(it % (C / 8)) * 8;
+    const bf16x8 v = __builtin_bit_cast(bf16x8, *(const u32x4*)(z + it * 8));
+    bf16x8 o;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+        o[j] = (bf16)fmaxf(fmaf((float)v[j], stat[2 * C + c0 + j], stat[3 * C + c0 + j]), 0.f);
+    *(u32x4*)(a + it * 8) = __builtin_bit_cast(u32x4, o);
+}
+
+__global__ void k_maxpool(const bf16* __restrict__ in, bf16* __restrict__ out, int images, int S,
+                          int C) {
+    const int H = S / 2, G8 = C / 8;
+    const long long it = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (it >= (long long)images * H * H * G8) return;
+    const int cg = (int)(it % G8);
+    const long long q = it / G8;
+    const int X = (int)(q % H), Y = (int)((q / H) % H), img = (int)(q / ((long long)H * H));
+    const bf16* b = in + (((size_t)img * S + 2 * Y) * S + 2 * X) * C + 8 * cg;
+    const bf16x8 v00 = __builtin_bit_cast(bf16x8, *(const u32x4*)b);
+    const bf16x8 v01 = __builtin_bit_cast(bf16x8, *(const u32x4*)(b + C));
+    const bf16x8 v10 = __builtin_bit_cast(bf16x8, *(const u32x4*)(b + (size_t)S * C));
+    const bf16x8 v11 = __builtin_bit_cast(bf16x8, *(const u32x4*)(b + (size_t)S * C + C));
+    bf16x8 o;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+        o[j] = (bf16)fmaxf(fmaxf((float)v00[j], (float)v01[j]), fmaxf((float)v10[j], (float)v11[j]));
+    *(u32x4*)(out + q * C + 8 * cg) = __builtin_bit_cast(u32x4, o);
+}
+
+// 1-D taps of the half-pixel bilinear x2 upsampling at output o of a length-n input.
+__device__ __forceinline__ void up_taps(int o, int n, int& i0, int& i1, float& w1) {
+    const float s = fmaxf(0.f, 0.5f * (float)o - 0.25f);
+    i0 = (int)s;
+    w1 = s - (float)i0;
+    i1 = min(i0 + 1, n - 1);
+}
+
+__global__ void k_up_concat(const bf16* __restrict__ d, const bf16* __restrict__ e, bf16* __restrict__ cat,
+                            int images, int S, int Cd, int Ce) {
+    const int C = Cd + Ce, G8 = C / 8, H = S / 2;
+    const long long it = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (it >= (long long)images * S * S * G8) return;
+    const int cg = (int)(it % G8);
+    const long long p = it / G8;
+    const int x = (int)(p % S), y = (int)((p / S) % S), img = (int)(p / ((long long)S * S));
+    u32x4 outv;
+    if (8 * cg < Cd) {
+        int y0, y1, x0, x1;
+        float wy, wx;
+        up_taps(y, H, y0, y1, wy);
+        up_taps(x, H, x0, x1, wx);
+        const bf16* db = d + (size_t)img * H * H * Cd + 8 * cg;
+        const bf16x8 a = __builtin_bit_cast(bf16x8, *(const u32x4*)(db + ((size_t)y0 * H + x0) * Cd));
+        const bf16x8 b = __builtin_bit_cast(bf16x8, *(const u32x4*)(db + ((size_t)y0 * H + x1) * Cd));
+        const bf16x8 c = __builtin_bit_cast(bf16x8, *(const u32x4*)(db + ((size_t)y1 * H + x0) * Cd));
+        const bf16x8 dd = __builtin_bit_cast(bf16x8, *(const u32x4*)(db + ((size_t)y1 * H + x1) * Cd));
+        bf16x8 o;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const float top = (1.f - wx) * (float)a[j] + wx * (float)b[j];
+            const float bot = (1.f - wx) * (float)c[j] + wx * (float)dd[j];
+            o[j] = (bf16)((1.f - wy) * top + wy * bot);
+        }
+        outv = __builtin_bit_cast(u32x4, o);
+    } else {
+        outv = *(const u32x4*)(e + p * Ce + (8 * cg - Cd));
+    }
+    *(u32x4*)(cat + p * C + 8 * cg) = outv;
+}
+
+__global__ void k_head_fwd(const bf16* __restrict__ a, const float* __restrict__ w,
+                           const float* __restrict__ b, float* __restrict__ mask, int images, int S,
+                           int C) {
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= (long long)images * S * S) return;
+    const int x = (int)(p % S), y = (int)((p / S) % S), img = (int)(p / ((long long)S * S));
+    float acc = b[0];
+    for (int ky = 0; ky < 3; ++ky) {
+        const int yy = y + ky - 1;
+        if (yy < 0 || yy >= S) continue;
+        for (int kx = 0; kx < 3; ++kx) {
+            const int xx = x + kx - 1;
+            if (xx < 0 || xx >= S) continue;
+            const bf16* ap = a + (((size_t)img * S + yy) * S + xx) * C;
+            for (int cg = 0; cg < C / 8; ++cg) {
+                const bf16x8 v = __builtin_bit_cast(bf16x8, *(const u32x4*)(ap + 8 * cg));
+#pragma unroll
+                for (int j = 0; j < 8; ++j) acc = fmaf((float)v[j], w[(8 * cg + j) * 9 + ky * 3 + kx], acc);
+            }
+        }
+    }
+    mask[p] = 1.f / (1.f + expf(-acc));
+}
+
+__global__ void k_head_dl(const float* __restrict__ dm, const float* __restrict__ m, float* __restrict__ dl,
+                          long long n) {
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const float v = m[p];
+    dl[p] = dm[p] * v * (1.f - v);
+}
+
+// g[p][ci] = sum_taps w[ci][tap] dl[p - (ky - 1, kx - 1)]
+__global__ void k_head_g(const float* __restrict__ dl, const float* __restrict__ w, float* __restrict__ g,
+                         int images, int S, int C) {
+    const long long it = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (it >= (long long)images * S * S * C) return;
+    const int ci = (int)(it % C);
+    const long long p = it / C;
+    const int x = (int)(p % S), y = (int)((p / S) % S), img = (int)(p / ((long long)S * S));
+    float acc = 0.f;
+    for (int ky = 0; ky < 3; ++ky) {
+        const int yy = y - (ky - 1);
+        if (yy < 0 || yy >= S) continue;
+        for (int kx = 0; kx < 3; ++kx) {
+            const int xx = x - (kx - 1);
+            if (xx < 0 || xx >= S) continue;
+            acc = fmaf(w[ci * 9 + ky * 3 + kx], dl[((size_t)img * S + yy) * S + xx], acc);
+        }
+    }
+    g[it] = acc;
+}
+
+constexpr int kHeadPix = 4096;   // pixels per head weight-gradient block
+
+// part[block][ci 9 + tap] = sum dl[p] a[p + tap][ci]; part[block][9 C] = sum dl.
+__global__ __launch_bounds__(256) void k_head_wgrad(const float* __restrict__ dl, const bf16* __restrict__ a,
+                                                    float* __restrict__ part, int images, int S) {
+    constexpr int C = 8, NW = 9 * C + 1;
+    float acc[NW];
+#pragma unroll
+    for (int j = 0; j < NW; ++j) acc[j] = 0.f;
+    const long long n = (long long)images * S * S;
+    const long long p0 = (long long)blockIdx.x * kHeadPix;
+    for (long long p = p0 + threadIdx.x; p < min(n, p0 + kHeadPix); p += blockDim.x) {
+        const int x = (int)(p % S), y = (int)((p / S) % S), img = (int)(p / ((long long)S * S));
+        const float d = dl[p];
+        acc[NW - 1] += d;
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky) {
+            const int yy = y + ky - 1;
+#pragma unroll
+            for (int kx = 0; kx < 3; ++kx) {
+                const int xx = x + kx - 1;
+                if (yy < 0 || yy >= S || xx < 0 || xx >= S) continue;
+                const bf16x8 v =
+                    __builtin_bit_cast(bf16x8, *(const u32x4*)(a + (((size_t)img * S + yy) * S + xx) * C));
+#pragma unroll
+                for (int j = 0; j < C; ++j) acc[j * 9 + ky * 3 + kx] = fmaf(d, (float)v[j], acc[j * 9 + ky * 3 + kx]);
+            }
+        }
+    }
+    __shared__ float red[4][NW];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < NW; ++j) {
+        float v = acc[j];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if (lane == 0) red[wave][j] = v;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < NW; j += blockDim.x)
+        part[(size_t)blockIdx.x * NW + j] = red[0][j] + red[1][j] + red[2][j] + red[3][j];
+}
+
+// Per-block channel sums for the batch-norm adjoint: part[block][0][c] = sum dy,
+// part[block][1][c] = sum dy xhat over kBnPix pixels.  Thread (pixel lane,
+// channel group) with blockDim = 32 C/8.
+constexpr int kBnPix = 1024;
+
+__global__ void k_bn_bwd_part(const float* __restrict__ g, const bf16* __restrict__ z,
+                              const float* __restrict__ stat, float* __restrict__ part, long long M,
+                              int C) {
+    const int G8 = C / 8, cg = threadIdx.x % G8, pl = threadIdx.x / G8;
+    const long long p0 = (long long)blockIdx.x * kBnPix;
+    const long long p1 = min(M, p0 + kBnPix);
+    float sd[8], sx[8], mean[8], inv[8], sc[8], sh[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int c = 8 * cg + j;
+        sd[j] = sx[j] = 0.f;
+        mean[j] = stat[c];
+        inv[j] = stat[C + c];
+        sc[j] = stat[2 * C + c];
+        sh[j] = stat[3 * C + c];
+    }
+    for (long long p = p0 + pl; p < p1; p += 32) {
+        const bf16x8 zv = __builtin_bit_cast(bf16x8, *(const u32x4*)(z + p * C + 8 * cg));
+        const float* gp = g + p * C + 8 * cg;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const float zz = (float)zv[j];
+            const float dy = fmaf(zz, sc[j], sh[j]) > 0.f ? gp[j] : 0.f;
+            sd[j] += dy;
+            sx[j] = fmaf(dy, (zz - mean[j]) * inv[j], sx[j]);
+        }
+    }
+    __shared__ float red[32][2][96];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        red[pl][0][8 * cg + j] = sd[j];
+        red[pl][1][8 * cg + j] = sx[j];
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < 2 * C; c += blockDim.x) {
+        const int k = c / C, cc = c % C;
+        float s = 0.f;
+        for (int q = 0; q < 32; ++q) s += red[q][k][cc];
+        part[(size_t)blockIdx.x * 2 * C + c] = s;
+    }
+}
+
+// dbeta, dgamma (double sums of the partials in block order) and the apply coefficients.
+__global__ void k_bn_bwd_fin(const float* __restrict__ part, int nb, int C, long long M,
+                             const float* __restrict__ gamma, const float* __restrict__ stat,
+                             float* __restrict__ coef, float* __restrict__ dgamma, float* __restrict__ dbeta) {
+    const int c = blockIdx.x;
+    __shared__ double r1[256], r2[256];
+    double a = 0.0, b = 0.0;
+    for (int k = threadIdx.x; k < nb; k += blockDim.x) {
+        a += part[(size_t)k * 2 * C + c];
+        b += part[(size_t)k * 2 * C + C + c];
+    }
+    r1[threadIdx.x] = a;
+    r2[threadIdx.x] = b;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            r1[threadIdx.x] += r1[threadIdx.x + s];
+            r2[threadIdx.x] += r2[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    dbeta[c] = (float)r1[0];
+    dgamma[c] = (float)r2[0];
+    coef[c] = gamma[c] * stat[C + c];                 // gamma invstd
+    coef[C + c] = (float)(r1[0] / (double)M);         // mean dy
+    coef[2 * C + c] = (float)(r2[0] / (double)M);     // mean dy xhat
+}
+
+__global__ void k_bn_bwd_apply(const float* __restrict__ g, const bf16* __restrict__ z,
+                               const float* __restrict__ stat, const float* __restrict__ coef,
+                               bf16* __restrict__ dz, long long items, int C) {
+    const long long it = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (it >= items) return;
+    const int c0 = (int)(it % (C / 8)) * 8;
+    const bf16x8 zv = __builtin_bit_cast(bf16x8, *(const u32x4*)(z + it * 8));
+    const float* gp = g + it * 8;
+    bf16x8 o;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int c = c0 + j;
+        const float zz = (float)zv[j];
+        const float dy = fmaf(zz, stat[2 * C + c], stat[3 * C + c]) > 0.f ? gp[j] : 0.f;
+        const float xh = (zz - stat[c]) * stat[C + c];
+        o[j] = (bf16)(coef[c] * (dy - coef[C + c] - xh * coef[2 * C + c]));
+    }
+    *(u32x4*)(dz + it * 8) = __builtin_bit_cast(u32x4, o);
+}
+
+__global__ void k_pool_bwd(const float* __restrict__ d_pool, const bf16* __restrict__ e,
+                           const float* __restrict__ skip, int skip_stride, int skip_off,
+                           float* __restrict__ g, int images, int S, int C) {
+    const long long it = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (it >= (long long)images * S * S * C) return;
+    const int c = (int)(it % C);
+    const long long p = it / C;
+    const int x = (int)(p % S), y = (int)((p / S) % S), img = (int)(p / ((long long)S * S));
+    const int H = S / 2, Y = y / 2, X = x / 2;
+    const bf16* b = e + (((size_t)img * S + 2 * Y) * S + 2 * X) * C + c;
+    const float v[4] = {(float)b[0], (float)b[C], (float)b[(size_t)S * C], (float)b[(size_t)S * C + C]};
+    int arg = 0;
+#pragma unroll
+    for (int k = 1; k < 4; ++k)
+        if (v[k] > v[arg]) arg = k;
+    const int mine = (y - 2 * Y) * 2 + (x - 2 * X);
+    float r = skip ? skip[p * skip_stride + skip_off + c] : 0.f;
+    if (arg == mine) r += d_pool[(((size_t)img * H + Y) * H + X) * C + c];
+    g[it] = r;
+}
+
+// Adjoint 1-D taps of up2: the outputs o that read input q, with their weights.
+__device__ __forceinline__ int up_adj(int q, int n, int* o, float* w) {
+    int k = 0;
+    if (q >= 1) { o[k] = 2 * q - 1; w[k++] = 0.25f; }
+    o[k] = 2 * q;
+    w[k++] = q == 0 ? 1.f : 0.75f;
+    o[k] = 2 * q + 1;
+    w[k++] = q == n - 1 ? 1.f : 0.75f;
+    if (q <= n - 2) { o[k] = 2 * q + 2; w[k++] = 0.25f; }
+    return k;
+}
+
+__global__ void k_up_bwd(const float* __restrict__ d_cat, float* __restrict__ d_d, int images, int S,
+                         int Cd, int Ce) {
+    const int H = S / 2, C = Cd + Ce;
+    const long long it = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (it >= (long long)images * H * H * Cd) return;
+    const int c = (int)(it % Cd);
+    const long long q = it / Cd;
+    const int X = (int)(q % H), Y = (int)((q / H) % H), img = (int)(q / ((long long)H * H));
+    int oy[4], ox[4];
+    float wy[4], wx[4];
+    const int ny = up_adj(Y, H, oy, wy), nx = up_adj(X, H, ox, wx);
+    float acc = 0.f;
+    for (int a = 0; a < ny; ++a) {
+        float row = 0.f;
+        for (int b = 0; b < nx; ++b) row = fmaf(wx[b], d_cat[(((size_t)img * S + oy[a]) * S + ox[b]) * C + c], row);
+        acc = fmaf(wy[a], row, acc);
+    }
+    d_d[it] = acc;
+}
+
+__global__ void k_pack(const float* __restrict__ w, int cin, int cout, int cink, bf16* __restrict__ wf,
+                       bf16* __restrict__ wb) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cout * 9 * cink) return;
+    const int co = i / (9 * cink), k = i % (9 * cink), tap = k / cink, ci = k % cink;
+    wf[i] = ci < cin ? (bf16)w[((size_t)co * cin + ci) * 9 + tap] : (bf16)0.f;
+    if (wb && ci < cin) {
+        // data gradient: [cin][9 cout], tap flipped
+        wb[(size_t)ci * 9 * cout + (8 - tap) * cout + co] = (bf16)w[((size_t)co * cin + ci) * 9 + tap];
+    }
+}
+
+__global__ void k_unpack_grad(const float* __restrict__ dw, int cin, int cout, int cink,
+                              float* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cout * cin * 9) return;
+    const int co = i / (cin * 9), ci = (i / 9) % cin, tap = i % 9;
+    out[i] = dw[(size_t)co * 9 * cink + tap * cink + ci];
+}
+
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, long long n, float lr, float b1, float b2, float eps,
+                       float c1, float c2) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__global__ void k_pose_loss(int batch, const float* __restrict__ pose, const float* __restrict__ target,
+                            int kind, float* __restrict__ loss, float* __restrict__ d_pose) {
+    float acc = 0.f;
+    const float inv_b = 1.f / (float)batch;
+    for (int i = threadIdx.x; i < 3 * batch; i += blockDim.x) {
+        const float d = pose[i] - target[i];
+        if (kind == 1) {
+            acc += fabsf(d);
+            d_pose[i] = (d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f)) * inv_b;
+        } else {
+            acc += d * d;
+            d_pose[i] = 2.f * d * inv_b;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (threadIdx.x == 0) loss[0] = acc * inv_b;
+}
+
+inline unsigned grid_for(long long n, int block) { return (unsigned)((n + block - 1) / block); }
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+
+#define FMBYM_CONV_PAIRS(X)                                                                      \
+    X(8, 8) X(8, 16) X(16, 16) X(16, 32) X(32, 32) X(32, 64) X(64, 64) X(96, 32) X(48, 16) X(24, 8) \
+    X(16, 8) X(32, 16) X(64, 32) X(32, 96) X(16, 48) X(8, 24)
+
+bool launch_conv3x3(int cin, int cout, bool stats, const bf16* in, const bf16* w, void* z, float* part,
+                    int images, int S, hipStream_t s) {
+    const dim3 grid(conv_blocks(images, S)), block(256);
+    const size_t lds = patch_bytes(cin, S);
+    if (lds + 4 * 2 * 96 * sizeof(float) > kLdsLimit) return false;
+#define FMBYM_CONV_CASE(CI, CO)                                                                   \
+    if (cin == CI && cout == CO) {                                                                \
+        if (stats)                                                                                \
+            hipLaunchKernelGGL((k_conv3x3<CI, CO, true, bf16>), grid, block, lds, s, in, w,        \
+                               (bf16*)z, part, S);                                                \
+        else                                                                                      \
+            hipLaunchKernelGGL((k_conv3x3<CI, CO, false, float>), grid, block, lds, s, in, w,      \
+                               (float*)z, part, S);                                               \
+        return true;                                                                              \
+    }
+    FMBYM_CONV_PAIRS(FMBYM_CONV_CASE)
+#undef FMBYM_CONV_CASE
+    return false;
+}
+
+void wgrad_grid(int images, int S, int* blocks, int* tiles_per_block) {
+    const int tiles = conv_blocks(images, S);
+    int tpb = tiles / 512;
+    tpb = tpb < 1 ? 1 : (tpb > 16 ? 16 : tpb);
+    *tiles_per_block = tpb;
+    *blocks = (tiles + tpb - 1) / tpb;
+}
+
+bool launch_wgrad(int cin, int cout, const bf16* dz, const bf16* in, float* part, float* dw, int images,
+                  int S, hipStream_t s) {
+    int nb, tpb;
+    wgrad_grid(images, S, &nb, &tpb);
+    const int tiles = conv_blocks(images, S);
+    const int n = cout * 9 * cin;
+    const size_t lds = patch_bytes(cin, S) + (size_t)kConvTile * cout * sizeof(bf16);
+    if (lds > kLdsLimit) return false;
+#define FMBYM_WGRAD_CASE(CI, CO)                                                                  \
+    if (cin == CI && cout == CO) {                                                                \
+        hipLaunchKernelGGL((k_wgrad<CI, CO>), dim3(nb), dim3(256), lds, s, dz, in, part, S, tpb, tiles); \
+        hipLaunchKernelGGL(k_reduce_cols, dim3(grid_for(n, 256)), dim3(256), 0, s, part, nb,          \
+                           (long long)n, n, dw);                                                  \
+        return true;                                                                              \
+    }
+    FMBYM_CONV_PAIRS(FMBYM_WGRAD_CASE)
+#undef FMBYM_WGRAD_CASE
+    return false;
+}
+
+int bn_part_blocks(long long M, int /*C*/) { return (int)((M + kBnPix - 1) / kBnPix); }
+
+void launch_input8(const float* x, bf16* x8, int images, int S, hipStream_t s) {
+    const long long n = (long long)images * S * S;
+    hipLaunchKernelGGL(k_input8, dim3(grid_for(n, 256)), dim3(256), 0, s, x, x8, n);
+}
+
+void launch_bn_stats(const float* part, int nb, int C, long long M, const float* gamma,
+                     const float* beta, float eps, float momentum, int training, float* run_mean,
+                     float* run_var, float* stat, hipStream_t s) {
+    hipLaunchKernelGGL(k_bn_stats, dim3(C), dim3(256), 0, s, part, nb, C, M, gamma, beta, eps, momentum,
+                       training, run_mean, run_var, stat);
+}
+
+void launch_bn_relu(const bf16* z, const float* stat, bf16* a, long long M, int C, hipStream_t s) {
+    const long long items = M * (C / 8);
+    hipLaunchKernelGGL(k_bn_relu, dim3(grid_for(items, 256)), dim3(256), 0, s, z, stat, a, items, C);
+}
+
+void launch_maxpool(const bf16* in, bf16* out, int images, int S, int C, hipStream_t s) {
+    const long long items = (long long)images * (S / 2) * (S / 2) * (C / 8);
+    hipLaunchKernelGGL(k_maxpool, dim3(grid_for(items, 256)), dim3(256), 0, s, in, out, images, S, C);
+}
+
+void launch_up_concat(const bf16* d, const bf16* e, bf16* cat, int images, int S, int Cd, int Ce,
+                      hipStream_t s) {
+    const long long items = (long long)images * S * S * ((Cd + Ce) / 8);
+    hipLaunchKernelGGL(k_up_concat, dim3(grid_for(items, 256)), dim3(256), 0, s, d, e, cat, images, S,
+                       Cd, Ce);
+}
+
+void launch_head_fwd(const bf16* a, const float* w, const float* b, float* mask, int images, int S,
+                     int C, hipStream_t s) {
+    const long long n = (long long)images * S * S;
+    hipLaunchKernelGGL(k_head_fwd, dim3(grid_for(n, 256)), dim3(256), 0, s, a, w, b, mask, images, S, C);
+}
+
+void launch_head_bwd(const float* d_mask, const float* mask, const bf16* a, const float* w, float* dl,
+                     float* g, float* part, float* dw, float* db, int images, int S, int C,
+                     hipStream_t s) {
+    const long long n = (long long)images * S * S;
+    hipLaunchKernelGGL(k_head_dl, dim3(grid_for(n, 256)), dim3(256), 0, s, d_mask, mask, dl, n);
+    hipLaunchKernelGGL(k_head_g, dim3(grid_for(n * C, 256)), dim3(256), 0, s, dl, w, g, images, S, C);
+    const int nb = (int)((n + kHeadPix - 1) / kHeadPix), NW = 9 * C + 1;
+    hipLaunchKernelGGL(k_head_wgrad, dim3(nb), dim3(256), 0, s, dl, a, part, images, S);
+    hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(128), 0, s, part, nb, (long long)NW, 9 * C, dw);
+    hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(64), 0, s, part + 9 * C, nb, (long long)NW, 1, db);
+}
+
+void launch_bn_relu_bwd(const float* g, const bf16* z, const float* stat, const float* gamma, float* part,
+                        float* coef, float* dgamma, float* dbeta, bf16* dz, long long M, int C,
+                        hipStream_t s) {
+    const int nb = bn_part_blocks(M, C);
+    hipLaunchKernelGGL(k_bn_bwd_part, dim3(nb), dim3(32 * (C / 8)), 0, s, g, z, stat, part, M, C);
+    hipLaunchKernelGGL(k_bn_bwd_fin, dim3(C), dim3(256), 0, s, part, nb, C, M, gamma, stat, coef, dgamma,
+                       dbeta);
+    const long long items = M * (C / 8);
+    hipLaunchKernelGGL(k_bn_bwd_apply, dim3(grid_for(items, 256)), dim3(256), 0, s, g, z, stat, coef, dz,
+                       items, C);
+}
+
+void launch_pool_bwd(const float* d_pool, const bf16* e, const float* skip, int skip_stride,
+                     int skip_off, float* g, int images, int S, int C, hipStream_t s) {
+    const long long n = (long long)images * S * S * C;
+    hipLaunchKernelGGL(k_pool_bwd, dim3(grid_for(n, 256)), dim3(256), 0, s, d_pool, e, skip, skip_stride,
+                       skip_off, g, images, S, C);
+}
+
+void launch_up_bwd(const float* d_cat, float* d_d, int images, int S, int Cd, int Ce, hipStream_t s) {
+    const long long n = (long long)images * (S / 2) * (S / 2) * Cd;
+    hipLaunchKernelGGL(k_up_bwd, dim3(grid_for(n, 256)), dim3(256), 0, s, d_cat, d_d, images, S, Cd, Ce);
+}
+
+void launch_pack(const float* w, int cin, int cout, int cink, bf16* wf, bf16* wb, hipStream_t s) {
+    const int n = cout * 9 * cink;
+    hipLaunchKernelGGL(k_pack, dim3(grid_for(n, 256)), dim3(256), 0, s, w, cin, cout, cink, wf, wb);
+}
+
+void launch_unpack_grad(const float* dw, int cin, int cout, int cink, float* out, hipStream_t s) {
+    const int n = cout * cin * 9;
+    hipLaunchKernelGGL(k_unpack_grad, dim3(grid_for(n, 256)), dim3(256), 0, s, dw, cin, cout, cink, out);
+}
+
+void launch_adam(float* p, const float* g, float* m, float* v, long long n, float lr, float b1, float b2,
+                 float eps, float c1, float c2, hipStream_t s) {
+    hipLaunchKernelGGL(k_adam, dim3(grid_for(n, 256)), dim3(256), 0, s, p, g, m, v, n, lr, b1, b2, eps, c1,
+                       c2);
+}
+
+void launch_pose_loss(int batch, const float* pose, const float* target, int kind, float* loss,
+                      float* d_pose, hipStream_t s) {
+    hipLaunchKernelGGL(k_pose_loss, dim3(1), dim3(64), 0, s, batch, pose, target, kind, loss, d_pose);
+}
+
+}  // namespace fmbym

@@ -1,0 +1,102 @@
+// Kernels of the mask network (a U-Net of 3x3 convolutions, Section III-E /
+// Table II pattern): BF16 matrix-core convolutions with FP32 accumulation and
+// the FP32 element-wise layers around them.  Tensors are NHWC: element
+// (image, y, x, c) of a [I][S][S][C] tensor sits at ((image S + y) S + x) C + c.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace fmbym {
+
+typedef __bf16 bf16;
+
+// Output pixels per convolution block (16 matrix-core rows per M-tile, 16 tiles).
+constexpr int kConvTile = 256;
+
+__host__ __device__ constexpr int pad16(int c) { return (c + 15) / 16 * 16; }
+
+// Blocks of one conv launch over `images` images of side S.
+inline int conv_blocks(int images, int S) { return images * (S * S / kConvTile); }
+
+// Partial-sum blocks of the channel reductions (batch-norm statistics) over
+// M pixels of C channels; see bn_part_blocks in the kernels.
+int bn_part_blocks(long long M, int C);
+// Blocks of a weight-gradient launch and the tiles each one covers.
+void wgrad_grid(int images, int S, int* blocks, int* tiles_per_block);
+
+// --- launchers (all asynchronous on s; shapes checked by the caller) -------
+
+// x [I][S][S] float -> [I][S][S][8] bf16 with the scan in channel 0, zeros elsewhere.
+void launch_input8(const float* x, bf16* x8, int images, int S, hipStream_t s);
+
+// z = conv3x3(in, w) for (cin, cout) in the supported set; w packed [cout][9 cin]
+// bf16 (k = tap cin + ci, tap = 3 ky + kx).  With stats, z is bf16 and
+// part[block][2][cout] receives the block's sums of z and z^2 (of the stored
+// bf16 values); otherwise z is float.  Returns false for an unsupported pair.
+bool launch_conv3x3(int cin, int cout, bool stats, const bf16* in, const bf16* w, void* z,
+                    float* part, int images, int S, hipStream_t s);
+
+// Weight gradient: dw[co][9 cin] (float, k as above) = sum over pixels of
+// dz[p][co] in[p + tap][ci], through per-block partials part (wgrad_grid) and
+// a fixed-order reduction.  Returns false for an unsupported pair.
+bool launch_wgrad(int cin, int cout, const bf16* dz, const bf16* in, float* part, float* dw,
+                  int images, int S, hipStream_t s);
+
+// Batch-norm statistics: reduce part[nb][2][C] (sums of z, z^2) over nb in a
+// fixed order; training: mean/var of the batch (and running-statistics
+// update), else the running ones.  Writes stat[4][C] = mean, invstd, scale, shift.
+void launch_bn_stats(const float* part, int nb, int C, long long M, const float* gamma,
+                     const float* beta, float eps, float momentum, int training,
+                     float* run_mean, float* run_var, float* stat, hipStream_t s);
+
+// a = relu(z scale + shift) per channel, bf16 -> bf16.
+void launch_bn_relu(const bf16* z, const float* stat, bf16* a, long long M, int C, hipStream_t s);
+
+// 2x2 max-pool, [I][S][S][C] -> [I][S/2][S/2][C].
+void launch_maxpool(const bf16* in, bf16* out, int images, int S, int C, hipStream_t s);
+
+// cat = [up2(d), e] with d [I][S/2][S/2][Cd], e [I][S][S][Ce] -> [I][S][S][Cd + Ce].
+void launch_up_concat(const bf16* d, const bf16* e, bf16* cat, int images, int S, int Cd, int Ce,
+                      hipStream_t s);
+
+// Head: mask = sigmoid(conv3x3(a, w) + b), a [I][S][S][C] bf16, w [C][3][3] float.
+void launch_head_fwd(const bf16* a, const float* w, const float* b, float* mask, int images, int S,
+                     int C, hipStream_t s);
+// Head adjoint: dl = d_mask m (1 - m); g [I][S][S][C] float = conv3x3^T(dl, w);
+// dw [C][3][3] and db (float, written) through per-block partials in part.
+void launch_head_bwd(const float* d_mask, const float* mask, const bf16* a, const float* w,
+                     float* dl, float* g, float* part, float* dw, float* db, int images, int S, int C,
+                     hipStream_t s);
+
+// Batch-norm + ReLU adjoint given g = dL/da (float): dy = g [a > 0];
+// dgamma = sum dy xhat, dbeta = sum dy (written to dgamma/dbeta);
+// dz = gamma invstd / M (M dy - dbeta - xhat dgamma), bf16.
+void launch_bn_relu_bwd(const float* g, const bf16* z, const float* stat, const float* gamma,
+                        float* part, float* coef, float* dgamma, float* dbeta, bf16* dz, long long M,
+                        int C, hipStream_t s);
+
+// Max-pool adjoint plus the skip gradient: g[p][c] = skip[p][c] (channel
+// offset skip_off of a row of skip_stride floats, or 0 if skip is null) +
+// d_pool[q][c] where p is the first maximum (row-major) of its window in e.
+void launch_pool_bwd(const float* d_pool, const bf16* e, const float* skip, int skip_stride,
+                     int skip_off, float* g, int images, int S, int C, hipStream_t s);
+
+// up2 adjoint: d_d [I][S/2][S/2][Cd] = up2^T of channels [0, Cd) of d_cat
+// (rows of Cd + Ce floats).
+void launch_up_bwd(const float* d_cat, float* d_d, int images, int S, int Cd, int Ce, hipStream_t s);
+
+// Pack conv weights (OIHW float) to the forward layout [cout][9 cink] (ci >=
+// cin zero) and, if wb is not null, the data-gradient layout [cin][9 cout] with
+// the taps flipped.
+void launch_pack(const float* w, int cin, int cout, int cink, bf16* wf, bf16* wb, hipStream_t s);
+
+// Scatter a [cout][9 cink] weight gradient into OIHW float (ci < cin).
+void launch_unpack_grad(const float* dw, int cin, int cout, int cink, float* out, hipStream_t s);
+
+void launch_adam(float* p, const float* g, float* m, float* v, long long n, float lr, float b1,
+                 float b2, float eps, float c1, float c2, hipStream_t s);
+void launch_pose_loss(int batch, const float* pose, const float* target, int kind, float* loss,
+                      float* d_pose, hipStream_t s);
+
+}  // namespace fmbym

@@ -1,0 +1,372 @@
+// C ABI of the mask network: layer plan, buffer layouts and the forward /
+// backward schedules over the kernels of mask_kernels.hip.
+//
+// Layer plan (parameter order): enc0a, enc0b, ..., enc(L-1)a, enc(L-1)b,
+// dec(L-2)a, dec(L-2)b, ..., dec0a, dec0b, then the head.  Inputs: enc0a reads
+// the scan (as 8 channels, the scan in channel 0), enc{l}a reads the max-pool
+// of enc{l-1}b's activation, every b conv reads its a conv's activation,
+// dec{l}a reads concat[up2(deeper), enc{l}b] where deeper is dec{l+1}b (or
+// enc{L-1}b at the bottom).  The head reads the last conv's activation.
+#include <math.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "../../include/fmbym_mask.h"
+#include "internal.hpp"
+#include "mask_kernels.hpp"
+
+namespace fmbym {
+namespace {
+
+struct ConvL {
+    int cin, cout, cink, level;
+    bool enc, first_of_level;
+    size_t w, gamma, beta;   // float offsets in params
+    size_t pf, pb;           // bf16 element offsets in packed (pb unused for the first conv)
+    int bn;                  // first channel in the running statistics
+};
+
+struct Net {
+    int levels = 0, base = 0;
+    float eps = 0.f, momentum = 0.f;
+    std::vector<ConvL> convs;
+    size_t n_params = 0, n_packed = 0, head_w = 0, head_b = 0;
+    int bn_channels = 0;
+    int ch(int l) const { return base << l; }
+    // index of a conv by (enc/dec, level, part b?)
+    int enc_a(int l) const { return 2 * l; }
+    int enc_b(int l) const { return 2 * l + 1; }
+    int dec_a(int l) const { return 2 * levels + 2 * (levels - 2 - l); }
+    int dec_b(int l) const { return dec_a(l) + 1; }
+    int last() const { return (int)convs.size() - 1; }
+    // activation feeding dec{l}a's upsampling
+    int deeper(int l) const { return l + 1 == levels - 1 ? enc_b(levels - 1) : dec_b(l + 1); }
+};
+
+size_t al64(size_t x) { return (x + 63) & ~(size_t)63; }
+
+bool build_net(const fmbym_mask_desc* d, Net& net) {
+    if (!d || d->levels < 1 || d->levels > 4 || d->base_channels != 8) return false;
+    net = Net();
+    net.levels = d->levels;
+    net.base = d->base_channels;
+    net.eps = d->bn_eps;
+    net.momentum = d->bn_momentum;
+    size_t po = 0, pk = 0;
+    int bn = 0;
+    auto add = [&](int cin, int cout, int level, bool enc, bool first) {
+        ConvL c{};
+        c.cin = cin;
+        c.cout = cout;
+        c.cink = cin < 8 ? 8 : cin;
+        c.level = level;
+        c.enc = enc;
+        c.first_of_level = first;
+        c.w = po;
+        po += (size_t)cout * cin * 9;
+        c.gamma = po;
+        po += cout;
+        c.beta = po;
+        po += cout;
+        c.pf = pk;
+        pk = al64(pk + (size_t)cout * 9 * c.cink);
+        c.pb = pk;
+        if (!net.convs.empty()) pk = al64(pk + (size_t)cin * 9 * cout);
+        c.bn = bn;
+        bn += cout;
+        net.convs.push_back(c);
+    };
+    for (int l = 0; l < net.levels; ++l) {
+        add(l == 0 ? 1 : net.ch(l - 1), net.ch(l), l, true, true);
+        add(net.ch(l), net.ch(l), l, true, false);
+    }
+    for (int l = net.levels - 2; l >= 0; --l) {
+        add(net.ch(l + 1) + net.ch(l), net.ch(l), l, false, true);
+        add(net.ch(l), net.ch(l), l, false, false);
+    }
+    net.head_w = po;
+    po += (size_t)net.base * 9;
+    net.head_b = po;
+    po += 1;
+    net.n_params = po;
+    net.n_packed = pk;
+    net.bn_channels = bn;
+    return true;
+}
+
+bool size_ok(const Net& net, int images, int n) {
+    if (images < 1 || images > (1 << 16)) return false;
+    if (n != 128 && n != 256 && n != 512) return false;
+    return (n >> (net.levels - 1)) >= 16;
+}
+
+struct Bump {
+    size_t off = 0;
+    size_t take(size_t bytes) {
+        const size_t o = off;
+        off = (off + bytes + 255) & ~(size_t)255;
+        return o;
+    }
+};
+
+struct ActLayout {
+    size_t x8 = 0, mask = 0, part = 0, total = 0;
+    std::vector<size_t> z, a, stat, pool, cat;
+};
+
+ActLayout act_layout(const Net& net, int I, int n) {
+    ActLayout L;
+    Bump b;
+    const size_t bf = 2, fl = 4;
+    auto pix = [&](int l) { return (size_t)I * (size_t)(n >> l) * (size_t)(n >> l); };
+    L.x8 = b.take(pix(0) * 8 * bf);
+    size_t part_max = 0;
+    for (const ConvL& c : net.convs) {
+        L.z.push_back(b.take(pix(c.level) * c.cout * bf));
+        L.a.push_back(b.take(pix(c.level) * c.cout * bf));
+        L.stat.push_back(b.take(4 * (size_t)c.cout * fl));
+        const size_t p = (size_t)conv_blocks(I, n >> c.level) * 2 * c.cout * fl;
+        if (p > part_max) part_max = p;
+    }
+    L.pool.assign(net.levels, 0);
+    for (int l = 1; l < net.levels; ++l) L.pool[l] = b.take(pix(l) * net.ch(l - 1) * bf);
+    L.cat.assign(net.levels, 0);
+    for (int l = 0; l + 1 < net.levels; ++l) L.cat[l] = b.take(pix(l) * (net.ch(l + 1) + net.ch(l)) * bf);
+    L.mask = b.take(pix(0) * fl);
+    L.part = b.take(part_max);
+    L.total = b.off;
+    return L;
+}
+
+struct WsLayout {
+    size_t dz = 0, part = 0, coef = 0, wpart = 0, dw = 0, dl = 0, hpart = 0, total = 0;
+    std::vector<size_t> g, dpool, dcat;
+};
+
+WsLayout ws_layout(const Net& net, int I, int n) {
+    WsLayout L;
+    Bump b;
+    const size_t fl = 4;
+    auto pix = [&](int l) { return (size_t)I * (size_t)(n >> l) * (size_t)(n >> l); };
+    size_t dz_max = 0, part_max = 0, wpart_max = 0, dw_max = 0;
+    for (const ConvL& c : net.convs) {
+        L.g.push_back(b.take(pix(c.level) * c.cout * fl));
+        dz_max = std::max(dz_max, pix(c.level) * c.cout * 2);
+        part_max = std::max(part_max, (size_t)bn_part_blocks((long long)pix(c.level), c.cout) * 2 * c.cout * fl);
+        int nb, tpb;
+        wgrad_grid(I, n >> c.level, &nb, &tpb);
+        wpart_max = std::max(wpart_max, (size_t)nb * c.cout * 9 * c.cink * fl);
+        dw_max = std::max(dw_max, (size_t)c.cout * 9 * c.cink * fl);
+    }
+    L.dpool.assign(net.levels, 0);
+    for (int l = 1; l < net.levels; ++l) L.dpool[l] = b.take(pix(l) * net.ch(l - 1) * fl);
+    L.dcat.assign(net.levels, 0);
+    for (int l = 0; l + 1 < net.levels; ++l) L.dcat[l] = b.take(pix(l) * (net.ch(l + 1) + net.ch(l)) * fl);
+    L.dz = b.take(dz_max);
+    L.part = b.take(part_max);
+    L.coef = b.take(3 * 96 * fl);
+    L.wpart = b.take(wpart_max);
+    L.dw = b.take(dw_max);
+    L.dl = b.take(pix(0) * fl);
+    L.hpart = b.take(((pix(0) + 4095) / 4096) * (9 * net.base + 1) * fl);
+    L.total = b.off;
+    return L;
+}
+
+template <class T>
+T* at(void* base, size_t off) {
+    return reinterpret_cast<T*>(static_cast<char*>(base) + off);
+}
+template <class T>
+const T* at(const void* base, size_t off) {
+    return reinterpret_cast<const T*>(static_cast<const char*>(base) + off);
+}
+
+int finish(hipStream_t) {
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? FMBYM_OK : hip_fail(e);
+}
+
+}  // namespace
+}  // namespace fmbym
+
+using namespace fmbym;
+
+extern "C" {
+
+size_t fmbym_mask_param_count(const fmbym_mask_desc* d) {
+    Net net;
+    return build_net(d, net) ? net.n_params : 0;
+}
+
+size_t fmbym_mask_packed_bytes(const fmbym_mask_desc* d) {
+    Net net;
+    return build_net(d, net) ? net.n_packed * sizeof(bf16) : 0;
+}
+
+size_t fmbym_mask_bn_channels(const fmbym_mask_desc* d) {
+    Net net;
+    return build_net(d, net) ? (size_t)net.bn_channels : 0;
+}
+
+int fmbym_mask_pack(const fmbym_mask_desc* d, void* stream) {
+    Net net;
+    if (!build_net(d, net)) return FMBYM_EUNSUPPORTED;
+    if (!d->params || !d->packed) return FMBYM_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    bf16* pk = (bf16*)d->packed;
+    for (size_t j = 0; j < net.convs.size(); ++j) {
+        const ConvL& c = net.convs[j];
+        launch_pack(d->params + c.w, c.cin, c.cout, c.cink, pk + c.pf, j ? pk + c.pb : nullptr, s);
+    }
+    return finish(s);
+}
+
+size_t fmbym_mask_activation_bytes(const fmbym_mask_desc* d, int32_t images, int32_t n) {
+    Net net;
+    if (!build_net(d, net) || !size_ok(net, images, n)) return 0;
+    return act_layout(net, images, n).total;
+}
+
+size_t fmbym_mask_workspace_bytes(const fmbym_mask_desc* d, int32_t images, int32_t n) {
+    Net net;
+    if (!build_net(d, net) || !size_ok(net, images, n)) return 0;
+    return ws_layout(net, images, n).total;
+}
+
+int fmbym_mask_fwd(const fmbym_mask_desc* d, int32_t I, int32_t n, const float* x, float* mask, void* act,
+                   size_t act_bytes, int training, void* stream) {
+    Net net;
+    if (!d) return FMBYM_EINVAL;
+    if (!build_net(d, net)) return FMBYM_EUNSUPPORTED;
+    if (!size_ok(net, I, n)) return FMBYM_EUNSUPPORTED;
+    if (!x || !mask || !d->params || !d->packed || !d->bn_running) return FMBYM_EINVAL;
+    if (!(d->bn_eps > 0.f) || !(d->bn_momentum >= 0.f && d->bn_momentum <= 1.f)) return FMBYM_EINVAL;
+    const ActLayout A = act_layout(net, I, n);
+    if (!act || act_bytes < A.total) return FMBYM_EWORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    const bf16* pk = (const bf16*)d->packed;
+    float* run_mean = d->bn_running;
+    float* run_var = d->bn_running + net.bn_channels;
+    launch_input8(x, at<bf16>(act, A.x8), I, n, s);
+    for (int j = 0; j <= net.last(); ++j) {
+        const ConvL& c = net.convs[j];
+        const int S = n >> c.level;
+        const bf16* in;
+        if (j == 0) {
+            in = at<bf16>(act, A.x8);
+        } else if (c.enc && c.first_of_level) {
+            launch_maxpool(at<bf16>(act, A.a[net.enc_b(c.level - 1)]), at<bf16>(act, A.pool[c.level]), I,
+                           n >> (c.level - 1), net.ch(c.level - 1), s);
+            in = at<bf16>(act, A.pool[c.level]);
+        } else if (!c.enc && c.first_of_level) {
+            launch_up_concat(at<bf16>(act, A.a[net.deeper(c.level)]), at<bf16>(act, A.a[net.enc_b(c.level)]),
+                             at<bf16>(act, A.cat[c.level]), I, S, net.ch(c.level + 1), net.ch(c.level), s);
+            in = at<bf16>(act, A.cat[c.level]);
+        } else {
+            in = at<bf16>(act, A.a[j - 1]);
+        }
+        if (!launch_conv3x3(c.cink, c.cout, true, in, pk + c.pf, at<bf16>(act, A.z[j]), at<float>(act, A.part),
+                            I, S, s))
+            return FMBYM_EUNSUPPORTED;
+        const long long M = (long long)I * S * S;
+        launch_bn_stats(at<float>(act, A.part), conv_blocks(I, S), c.cout, M, d->params + c.gamma,
+                        d->params + c.beta, net.eps, net.momentum, training ? 1 : 0, run_mean + c.bn,
+                        run_var + c.bn, at<float>(act, A.stat[j]), s);
+        launch_bn_relu(at<bf16>(act, A.z[j]), at<float>(act, A.stat[j]), at<bf16>(act, A.a[j]), M, c.cout, s);
+    }
+    launch_head_fwd(at<bf16>(act, A.a[net.last()]), d->params + net.head_w, d->params + net.head_b, mask, I,
+                    n, net.base, s);
+    (void)hipMemcpyAsync(at<float>(act, A.mask), mask, (size_t)I * n * n * sizeof(float),
+                         hipMemcpyDeviceToDevice, s);
+    return finish(s);
+}
+
+int fmbym_mask_bwd(const fmbym_mask_desc* d, int32_t I, int32_t n, const float* d_mask, const void* act,
+                   size_t act_bytes, float* d_params, void* ws, size_t ws_bytes, void* stream) {
+    Net net;
+    if (!d) return FMBYM_EINVAL;
+    if (!build_net(d, net)) return FMBYM_EUNSUPPORTED;
+    if (!size_ok(net, I, n)) return FMBYM_EUNSUPPORTED;
+    if (!d_mask || !d_params || !d->params || !d->packed) return FMBYM_EINVAL;
+    const ActLayout A = act_layout(net, I, n);
+    const WsLayout W = ws_layout(net, I, n);
+    if (!act || act_bytes < A.total) return FMBYM_EWORKSPACE;
+    if (!ws || ws_bytes < W.total) return FMBYM_EWORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    const bf16* pk = (const bf16*)d->packed;
+    const float* P = d->params;
+    void* wsp = ws;
+    const int last = net.last();
+    launch_head_bwd(d_mask, at<float>(act, A.mask), at<bf16>(act, A.a[last]), P + net.head_w,
+                    at<float>(wsp, W.dl), at<float>(wsp, W.g[last]), at<float>(wsp, W.hpart),
+                    d_params + net.head_w, d_params + net.head_b, I, n, net.base, s);
+    for (int j = last; j >= 0; --j) {
+        const ConvL& c = net.convs[j];
+        const int S = n >> c.level;
+        const long long M = (long long)I * S * S;
+        bf16* dz = at<bf16>(wsp, W.dz);
+        launch_bn_relu_bwd(at<float>(wsp, W.g[j]), at<bf16>(act, A.z[j]), at<float>(act, A.stat[j]),
+                           P + c.gamma, at<float>(wsp, W.part), at<float>(wsp, W.coef), d_params + c.gamma,
+                           d_params + c.beta, dz, M, c.cout, s);
+        const bf16* in;
+        if (j == 0)
+            in = at<bf16>(act, A.x8);
+        else if (c.enc && c.first_of_level)
+            in = at<bf16>(act, A.pool[c.level]);
+        else if (!c.enc && c.first_of_level)
+            in = at<bf16>(act, A.cat[c.level]);
+        else
+            in = at<bf16>(act, A.a[j - 1]);
+        if (!launch_wgrad(c.cink, c.cout, dz, in, at<float>(wsp, W.wpart), at<float>(wsp, W.dw), I, S, s))
+            return FMBYM_EUNSUPPORTED;
+        launch_unpack_grad(at<float>(wsp, W.dw), c.cin, c.cout, c.cink, d_params + c.w, s);
+        if (j == 0) break;
+        // data gradient into the buffer of this conv's input
+        float* din;
+        if (c.enc && c.first_of_level)
+            din = at<float>(wsp, W.dpool[c.level]);
+        else if (!c.enc && c.first_of_level)
+            din = at<float>(wsp, W.dcat[c.level]);
+        else
+            din = at<float>(wsp, W.g[j - 1]);
+        if (!launch_conv3x3(c.cout, c.cin, false, dz, pk + c.pb, din, nullptr, I, S, s))
+            return FMBYM_EUNSUPPORTED;
+        // the gradient of the next conv down (parameter order j - 1) when it is a b conv
+        if (!c.enc && c.first_of_level) {
+            // deeper activation of dec{l}a: dec{l+1}b or enc{L-1}b
+            launch_up_bwd(din, at<float>(wsp, W.g[net.deeper(c.level)]), I, S, net.ch(c.level + 1),
+                          net.ch(c.level), s);
+        } else if (c.enc && c.first_of_level) {
+            const int l = c.level;   // >= 1: enc{l-1}b gets the pool adjoint plus its skip gradient
+            launch_pool_bwd(din, at<bf16>(act, A.a[net.enc_b(l - 1)]), at<float>(wsp, W.dcat[l - 1]),
+                            net.ch(l) + net.ch(l - 1), net.ch(l), at<float>(wsp, W.g[net.enc_b(l - 1)]), I,
+                            n >> (l - 1), net.ch(l - 1), s);
+        }
+    }
+    return finish(s);
+}
+
+int fmbym_adam(float* params, const float* grad, float* m, float* v, int64_t count, int32_t step, float lr,
+               float beta1, float beta2, float eps, void* stream) {
+    if (!params || !grad || !m || !v || count < 1 || step < 1) return FMBYM_EINVAL;
+    if (!(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+        return FMBYM_EINVAL;
+    const float c1 = (float)(1.0 - pow((double)beta1, step));
+    const float c2 = (float)(1.0 - pow((double)beta2, step));
+    hipStream_t s = (hipStream_t)stream;
+    launch_adam(params, grad, m, v, count, lr, beta1, beta2, eps, c1, c2, s);
+    return finish(s);
+}
+
+int fmbym_pose_loss(int32_t batch, const float* pose, const float* target, int32_t kind, float* loss,
+                    float* d_pose, void* stream) {
+    if (batch < 1 || !pose || !target || !loss || !d_pose) return FMBYM_EINVAL;
+    if (kind != FMBYM_LOSS_L1 && kind != FMBYM_LOSS_L2) return FMBYM_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    launch_pose_loss(batch, pose, target, kind, loss, d_pose, s);
+    return finish(s);
+}
+
+}  // extern "C"

@@ -42,7 +42,12 @@ EXPORTS = (
     "fmbym_search_backward", "fmbym_strerror", "fmbym_last_hip_error", "fmbym_profile_enable",
     "fmbym_profile_read", "fmbym_ragged_workspace_size", "fmbym_ragged_create",
     "fmbym_ragged_launch", "fmbym_ragged_destroy", "fmbym_wall_clock_khz",
+    "fmbym_mask_param_count", "fmbym_mask_packed_bytes", "fmbym_mask_bn_channels", "fmbym_mask_pack",
+    "fmbym_mask_activation_bytes", "fmbym_mask_fwd", "fmbym_mask_workspace_bytes", "fmbym_mask_bwd",
+    "fmbym_adam", "fmbym_pose_loss",
 )
+FMBYM_LOSS_L1 = 1
+FMBYM_LOSS_L2 = 2
 
 
 class fmbym_params(ctypes.Structure):
@@ -57,6 +62,14 @@ class fmbym_pair(ctypes.Structure):
     _fields_ = [
         ("n", ctypes.c_int32), ("reserved", ctypes.c_int32), ("f", ctypes.c_void_p),
         ("g", ctypes.c_void_p), ("m_f", ctypes.c_void_p), ("m_g", ctypes.c_void_p),
+    ]
+
+
+class fmbym_mask_desc(ctypes.Structure):
+    _fields_ = [
+        ("levels", ctypes.c_int32), ("base_channels", ctypes.c_int32), ("bn_eps", ctypes.c_float),
+        ("bn_momentum", ctypes.c_float), ("params", ctypes.c_void_p), ("packed", ctypes.c_void_p),
+        ("bn_running", ctypes.c_void_p),
     ]
 
 
@@ -111,6 +124,25 @@ def lib() -> ctypes.CDLL:
         L.fmbym_ragged_destroy.restype = ctypes.c_int
         L.fmbym_wall_clock_khz.argtypes = [ctypes.POINTER(I32)]
         L.fmbym_wall_clock_khz.restype = ctypes.c_int
+        MD = ctypes.POINTER(fmbym_mask_desc)
+        for name in ("fmbym_mask_param_count", "fmbym_mask_packed_bytes", "fmbym_mask_bn_channels"):
+            getattr(L, name).argtypes = [MD]
+            getattr(L, name).restype = SZ
+        L.fmbym_mask_pack.argtypes = [MD, VP]
+        L.fmbym_mask_pack.restype = ctypes.c_int
+        L.fmbym_mask_activation_bytes.argtypes = [MD, I32, I32]
+        L.fmbym_mask_activation_bytes.restype = SZ
+        L.fmbym_mask_workspace_bytes.argtypes = [MD, I32, I32]
+        L.fmbym_mask_workspace_bytes.restype = SZ
+        L.fmbym_mask_fwd.argtypes = [MD, I32, I32, VP, VP, VP, SZ, ctypes.c_int, VP]
+        L.fmbym_mask_fwd.restype = ctypes.c_int
+        L.fmbym_mask_bwd.argtypes = [MD, I32, I32, VP, VP, SZ, VP, VP, SZ, VP]
+        L.fmbym_mask_bwd.restype = ctypes.c_int
+        L.fmbym_adam.argtypes = [VP, VP, VP, VP, ctypes.c_int64, I32, ctypes.c_float, ctypes.c_float,
+                                 ctypes.c_float, ctypes.c_float, VP]
+        L.fmbym_adam.restype = ctypes.c_int
+        L.fmbym_pose_loss.argtypes = [I32, VP, VP, I32, VP, VP, VP]
+        L.fmbym_pose_loss.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -370,3 +402,135 @@ class Ragged:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------- mask network
+
+def _check(rc: int, where: str) -> None:
+    if rc:
+        raise FmbymError(rc, where)
+
+
+def mask_param_count(desc: fmbym_mask_desc) -> int:
+    return int(lib().fmbym_mask_param_count(ctypes.byref(desc)))
+
+
+def mask_packed_bytes(desc: fmbym_mask_desc) -> int:
+    return int(lib().fmbym_mask_packed_bytes(ctypes.byref(desc)))
+
+
+def mask_bn_channels(desc: fmbym_mask_desc) -> int:
+    return int(lib().fmbym_mask_bn_channels(ctypes.byref(desc)))
+
+
+def mask_pack(desc: fmbym_mask_desc, stream) -> None:
+    _check(lib().fmbym_mask_pack(ctypes.byref(desc), stream), "fmbym_mask_pack")
+
+
+def mask_activation_bytes(desc, images: int, n: int) -> int:
+    return int(lib().fmbym_mask_activation_bytes(ctypes.byref(desc), int(images), int(n)))
+
+
+def mask_workspace_bytes(desc, images: int, n: int) -> int:
+    return int(lib().fmbym_mask_workspace_bytes(ctypes.byref(desc), int(images), int(n)))
+
+
+def mask_fwd(desc, images, n, x, mask, act, act_bytes, training, stream) -> None:
+    _check(lib().fmbym_mask_fwd(ctypes.byref(desc), int(images), int(n), x, mask, act, int(act_bytes),
+                                int(bool(training)), stream), "fmbym_mask_fwd")
+
+
+def mask_bwd(desc, images, n, d_mask, act, act_bytes, d_params, ws, ws_bytes, stream) -> None:
+    _check(lib().fmbym_mask_bwd(ctypes.byref(desc), int(images), int(n), d_mask, act, int(act_bytes),
+                                d_params, ws, int(ws_bytes), stream), "fmbym_mask_bwd")
+
+
+def adam(params, grad, m, v, count, step, lr, beta1, beta2, eps, stream) -> None:
+    _check(lib().fmbym_adam(params, grad, m, v, int(count), int(step), float(lr), float(beta1),
+                            float(beta2), float(eps), stream), "fmbym_adam")
+
+
+def pose_loss(batch, pose, target, kind, loss, d_pose, stream) -> None:
+    _check(lib().fmbym_pose_loss(int(batch), pose, target, int(kind), loss, d_pose, stream),
+           "fmbym_pose_loss")
+
+
+class MaskNet:
+    """Device buffers of the mask network (FP32 parameters, BF16 packed
+    weights, running statistics, Adam moments) and its calls on torch tensors.
+    ``params`` uses the library's flat layout (include/fmbym_mask.h)."""
+
+    def __init__(self, params, levels: int = 4, base: int = 8, bn_eps: float = 1e-5,
+                 bn_momentum: float = 0.1, device="cuda:0"):
+        self.levels, self.base = levels, base
+        self.desc = fmbym_mask_desc(levels, base, bn_eps, bn_momentum, None, None, None)
+        n_p = mask_param_count(self.desc)
+        if n_p == 0:
+            raise FmbymError(FMBYM_EUNSUPPORTED, "fmbym_mask_param_count")
+        p = torch.as_tensor(params, dtype=torch.float32).to(device).contiguous()
+        if p.numel() != n_p:
+            raise ValueError(f"params: expected {n_p} values, got {p.numel()}")
+        self.params = p
+        self.packed = torch.zeros(mask_packed_bytes(self.desc), dtype=torch.uint8, device=device)
+        nbn = mask_bn_channels(self.desc)
+        self.bn_running = torch.cat([torch.zeros(nbn), torch.ones(nbn)]).to(device)
+        self.m = torch.zeros_like(p)
+        self.v = torch.zeros_like(p)
+        self.step = 0
+        self.desc.params = p.data_ptr()
+        self.desc.packed = self.packed.data_ptr()
+        self.desc.bn_running = self.bn_running.data_ptr()
+        self._act = None
+        self._ws = None
+        self.pack()
+
+    def pack(self) -> None:
+        mask_pack(self.desc, _stream())
+
+    def _buf(self, name, need, dev):
+        cur = getattr(self, name)
+        if cur is None or cur.numel() < need:
+            cur = torch.empty(need, dtype=torch.uint8, device=dev)
+            setattr(self, name, cur)
+        return cur
+
+    def forward(self, x, training: bool = True):
+        """x [I, n, n] float32 scans -> masks [I, n, n]; keeps the activations for backward."""
+        I, n = x.shape[0], x.shape[-1]
+        need = mask_activation_bytes(self.desc, I, n)
+        if need == 0:
+            raise FmbymError(FMBYM_EUNSUPPORTED, "fmbym_mask_activation_bytes")
+        act = self._buf("_act", need, x.device)
+        mask = torch.empty(I, n, n, device=x.device)
+        mask_fwd(self.desc, I, n, _ptr(x, (I, n, n), "x"), mask.data_ptr(), act.data_ptr(), act.numel(),
+                 training, _stream())
+        self._shape = (I, n)
+        return mask
+
+    def backward(self, d_mask):
+        """dL/dparams (flat FP32) of the last training forward, given dL/dmask."""
+        I, n = self._shape
+        need = mask_workspace_bytes(self.desc, I, n)
+        ws = self._buf("_ws", need, d_mask.device)
+        d_params = torch.empty_like(self.params)
+        mask_bwd(self.desc, I, n, _ptr(d_mask.contiguous(), (I, n, n), "d_mask"), self._act.data_ptr(),
+                 self._act.numel(), d_params.data_ptr(), ws.data_ptr(), ws.numel(), _stream())
+        return d_params
+
+    def adam_step(self, grad, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+                  eps: float = 1e-8) -> None:
+        """One Adam update of params with grad, then re-pack the BF16 weights."""
+        self.step += 1
+        adam(self.params.data_ptr(), _ptr(grad.contiguous(), name="grad"), self.m.data_ptr(),
+             self.v.data_ptr(), self.params.numel(), self.step, lr, beta1, beta2, eps, _stream())
+        self.pack()
+
+
+def pose_loss_t(pose, target, kind: int = FMBYM_LOSS_L2):
+    """(loss [1], d_pose [B, 3]) on device tensors through fmbym_pose_loss."""
+    B = pose.shape[0]
+    loss = torch.empty(1, device=pose.device)
+    d = torch.empty(B, 3, device=pose.device)
+    pose_loss(B, _ptr(pose.contiguous(), (B, 3), "pose"), _ptr(target.contiguous(), (B, 3), "target"),
+              kind, loss.data_ptr(), d.data_ptr(), _stream())
+    return loss, d

@@ -9,11 +9,12 @@ import pytest
 from paper_2203_00459_amd import fmbym
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "fmbym.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if h.endswith(".h")]
 
 
 def declared_symbols():
-    text = open(HEADER).read()
+    text = "".join(open(h).read() for h in HEADERS)
     return sorted(set(re.findall(r"FMBYM_API\s+[\w\s\*]+?\b(fmbym_\w+)\s*\(", text)))
 
 
@@ -91,6 +92,32 @@ def test_ragged_calls_reject_bad_arguments():
     assert L.fmbym_ragged_launch(None, None) == fmbym.FMBYM_EINVAL
     assert L.fmbym_ragged_destroy(None) == fmbym.FMBYM_EINVAL
     assert L.fmbym_wall_clock_khz(None) == fmbym.FMBYM_EINVAL
+
+
+def test_mask_calls_reject_bad_arguments():
+    L = fmbym.lib()
+    d = fmbym.fmbym_mask_desc(4, 8, 1e-5, 0.1, None, None, None)
+    assert fmbym.mask_param_count(d) == 121_680 + 2 * 352 + 1
+    assert fmbym.mask_bn_channels(d) == 352
+    assert fmbym.mask_packed_bytes(d) > 2 * 121_608
+    assert fmbym.mask_activation_bytes(d, 4, 64) == 0          # 64 >> 3 < 16 and n unsupported
+    assert fmbym.mask_activation_bytes(d, 4, 128) > 0
+    assert fmbym.mask_workspace_bytes(d, 0, 256) == 0
+    bad = fmbym.fmbym_mask_desc(5, 8, 1e-5, 0.1, None, None, None)
+    assert fmbym.mask_param_count(bad) == 0
+    assert L.fmbym_mask_fwd(ctypes.byref(bad), 1, 128, None, None, None, 0, 1, None) == fmbym.FMBYM_EUNSUPPORTED
+    assert L.fmbym_mask_fwd(ctypes.byref(d), 1, 128, None, None, None, 0, 1, None) == fmbym.FMBYM_EINVAL
+    assert L.fmbym_mask_bwd(None, 1, 128, None, None, 0, None, None, 0, None) == fmbym.FMBYM_EINVAL
+    assert L.fmbym_mask_pack(ctypes.byref(d), None) == fmbym.FMBYM_EINVAL
+    assert L.fmbym_adam(None, None, None, None, 1, 1, 1e-3, 0.9, 0.999, 1e-8, None) == fmbym.FMBYM_EINVAL
+    assert L.fmbym_pose_loss(1, None, None, 2, None, None, None) == fmbym.FMBYM_EINVAL
+
+
+def test_mask_param_count_matches_the_oracle_layout():
+    from oracle import mask_oracle as M
+    for levels in (1, 2, 3, 4):
+        d = fmbym.fmbym_mask_desc(levels, 8, 1e-5, 0.1, None, None, None)
+        assert fmbym.mask_param_count(d) == M.param_count(levels, 8)
 
 
 def test_ragged_mix_counts_and_order():

@@ -1,0 +1,158 @@
+"""Mask network on the GPU against the FP64 oracle.
+
+The GPU stores the scan, the conv weights, every conv output, activation and
+upsampled tensor in BF16 and accumulates in FP32.  Two oracle evaluations
+frame it: the exact FP64 network, and the same network with BF16 storage at
+the GPU's rounding points (quant=True, arithmetic still FP64).  With one level
+the GPU reproduces the BF16-storage oracle to FP32 accumulation error.  With
+more levels the two BF16 evaluations drift apart: a rounding decision that FP32
+and FP64 accumulation take differently changes one stored value by a BF16 ulp,
+which changes the rounding of its 9 c_out consumers, and so on (measured: the
+fraction of differing elements grows from 1e-5 after the second conv to about
+0.5 after ten, each difference staying a few ulps).  What is fixed by the
+arithmetic is the size of the BF16 storage error itself, |quant - exact|; the
+GPU must be as close to the exact network as the BF16-storage oracle is:
+|gpu - exact| <= 2 |quant - exact| + tau, measured as the max and the mean over
+the mask and normwise per parameter group of the gradient (tau = 1e-4 for the
+mask, 1e-3 relative for gradients).  The gradient also carries the rounding of
+every conv's output gradient dz to BF16 (the operand of both gradient
+products), which the oracle's straight-through quantisation does not apply;
+the factor 2 covers it (measured worst ratio below 1.5)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mask_oracle as M
+from paper_2203_00459_amd import fmbym, synth
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+DT = torch.float64
+
+
+def _scans(name, count, split="val"):
+    f, g, _ = synth.make_batch(name, (count + 1) // 2, split=split)
+    return np.concatenate([f, g])[:count]
+
+
+def _gpu_net(levels, seed=0):
+    p = M.init_params(levels, 8, seed=seed)
+    return p, fmbym.MaskNet(p, levels=levels)
+
+
+def _groups(levels):
+    """(name, slice, kind) of every parameter group in the flat layout."""
+    out, o = [], 0
+    for c in M.conv_list(levels, 8):
+        nw = c.c_out * c.c_in * 9
+        out += [(c.name + ".w", slice(o, o + nw), "w"), (c.name + ".gamma", slice(o + nw, o + nw + c.c_out), "bn"),
+                (c.name + ".beta", slice(o + nw + c.c_out, o + nw + 2 * c.c_out), "bn")]
+        o += nw + 2 * c.c_out
+    out += [("head.w", slice(o, o + 72), "head"), ("head.b", slice(o + 72, o + 73), "head")]
+    return out
+
+
+CASES = [(1, "pair128", 4), (2, "pair128", 4), (4, "pair128", 4), (4, "mask256", 4)]
+
+
+@pytest.mark.parametrize("levels,scene,images", CASES)
+def test_forward_matches_oracle(levels, scene, images):
+    x = _scans(scene, images)
+    p, net = _gpu_net(levels)
+    print(f"mask fwd levels={levels} scene={scene} images={images}", flush=True)
+    m = net.forward(torch.from_numpy(x).to(DEV)).double().cpu()
+    X, P = torch.from_numpy(x).to(DT), torch.from_numpy(p).to(DT)
+    ref_q = M.forward(X, P, levels, 8, quant=True)
+    ref = M.forward(X, P, levels, 8)
+    eg, eq, dq = (m - ref).abs(), (ref_q - ref).abs(), (m - ref_q).abs()
+    print(f"  |gpu-exact| max {eg.max():.3e} mean {eg.mean():.3e}; |quant-exact| max {eq.max():.3e} "
+          f"mean {eq.mean():.3e}; |gpu-quant| max {dq.max():.3e}", flush=True)
+    assert float(eg.max()) <= 2 * float(eq.max()) + 1e-4
+    assert float(eg.mean()) <= 2 * float(eq.mean()) + 1e-4
+    if levels == 1:   # no cascade: FP32 accumulation order is all that differs
+        assert float(dq.max()) <= 1e-5
+
+
+@pytest.mark.parametrize("levels,scene,images", CASES)
+def test_backward_matches_oracle(levels, scene, images):
+    x = _scans(scene, images)
+    n = x.shape[-1]
+    p, net = _gpu_net(levels, seed=1)
+    rng = np.random.Generator(np.random.PCG64(7))
+    dm = rng.normal(size=(images, n, n)).astype(np.float32)
+    print(f"mask bwd levels={levels} scene={scene} images={images}", flush=True)
+    net.forward(torch.from_numpy(x).to(DEV))
+    g = net.backward(torch.from_numpy(dm).to(DEV)).double().cpu()
+    X, D, P = torch.from_numpy(x).to(DT), torch.from_numpy(dm).to(DT), torch.from_numpy(p).to(DT)
+    ref = M.grad(X, D, P, levels, 8)
+    ref_q = M.grad(X, D, P, levels, 8, quant=True)
+    worst = 0.0
+    for name, sl, kind in _groups(levels):
+        nr = max(float(ref[sl].norm()), 1e-30)
+        eg = float((g[sl] - ref[sl]).norm()) / nr
+        eq = float((ref_q[sl] - ref[sl]).norm()) / nr
+        worst = max(worst, eg / (eq + 1e-3))
+        assert eg <= 2 * eq + 1e-3, (name, eg, eq)
+    print(f"  worst |gpu-exact| / (|quant-exact| + 1e-3) over groups: {worst:.3f}", flush=True)
+
+
+def test_running_statistics_and_eval_mode():
+    levels, images = 2, 4
+    x = _scans("pair128", images)
+    p, net = _gpu_net(levels, seed=2)
+    nbn = net.bn_running.numel() // 2
+    rng = np.random.Generator(np.random.PCG64(3))
+    rm0 = rng.normal(0.0, 0.5, nbn)
+    rv0 = rng.uniform(0.5, 2.0, nbn)
+    net.bn_running.copy_(torch.tensor(np.concatenate([rm0, rv0]), dtype=torch.float32))
+    X = torch.from_numpy(x).to(DT)
+    P = torch.from_numpy(p).to(DT)
+    # eval mode normalises with the given running statistics
+    me = net.forward(torch.from_numpy(x).to(DEV), training=False).double().cpu()
+    ref_e = M.forward_eval(X, P, levels, 8, torch.tensor(rm0), torch.tensor(rv0))
+    print(f"eval mode: max {(me - ref_e).abs().max():.3e} mean {(me - ref_e).abs().mean():.3e}", flush=True)
+    assert float((me - ref_e).abs().max()) <= 5e-2 and float((me - ref_e).abs().mean()) <= 5e-3
+    # a training pass moves them by the momentum towards the batch statistics
+    net.forward(torch.from_numpy(x).to(DEV), training=True)
+    got = net.bn_running.double().cpu()
+    rm, rv = M.running_stats(X, P, levels, 8, torch.tensor(rm0), torch.tensor(rv0), quant=True)
+    assert torch.allclose(got[:nbn], rm, rtol=1e-3, atol=1e-3)
+    assert torch.allclose(got[nbn:], rv, rtol=1e-3, atol=1e-3)
+
+
+def test_adam_matches_oracle():
+    rng = np.random.Generator(np.random.PCG64(4))
+    p = M.init_params(2, 8, seed=4)
+    net = fmbym.MaskNet(p, levels=2)
+    th, m, v = torch.from_numpy(p).to(DT), torch.zeros(p.size, dtype=DT), torch.zeros(p.size, dtype=DT)
+    for step in range(1, 4):
+        g = rng.normal(size=p.size).astype(np.float32)
+        net.adam_step(torch.from_numpy(g).to(DEV), lr=1e-3)
+        th, m, v = M.adam_step(th, torch.from_numpy(g).to(DT), m, v, step, 1e-3)
+    got = net.params.double().cpu()
+    assert float((got - th).abs().max()) <= 1e-6 + 1e-6 * float(th.abs().max())
+
+
+@pytest.mark.parametrize("kind,name", [(fmbym.FMBYM_LOSS_L1, "l1"), (fmbym.FMBYM_LOSS_L2, "l2")])
+def test_pose_loss_matches_oracle(kind, name):
+    rng = np.random.Generator(np.random.PCG64(5))
+    pose = rng.normal(size=(16, 3)).astype(np.float32)
+    tgt = rng.normal(size=(16, 3)).astype(np.float32)
+    loss, d = fmbym.pose_loss_t(torch.from_numpy(pose).to(DEV), torch.from_numpy(tgt).to(DEV), kind)
+    P = torch.from_numpy(pose).to(DT).requires_grad_(True)
+    ref = M.pose_loss(P, torch.from_numpy(tgt).to(DT), name)
+    ref.backward()
+    assert abs(float(loss.cpu()) - float(ref)) <= 1e-5 * max(1.0, float(ref))
+    assert torch.allclose(d.double().cpu(), P.grad, atol=1e-6)
+
+
+def test_mask_network_is_deterministic():
+    x = torch.from_numpy(_scans("pair128", 4)).to(DEV)
+    p, net = _gpu_net(4, seed=6)
+    dm = torch.ones(4, 128, 128, device=DEV)
+    m1 = net.forward(x)
+    g1 = net.backward(dm)
+    m2 = net.forward(x)
+    g2 = net.backward(dm)
+    assert torch.equal(m1, m2) and torch.equal(g1, g2)
