@@ -1,0 +1,112 @@
+"""Training of the mask network through the differentiable search (Section III-E).
+
+One step (Eq. 10-13): masks m = h_alpha(scan) for both scans of every pair
+(one batched network call, shared weights), the search on the masked scans,
+the pose loss against the known poses, the search's adjoint down to the masks,
+the network's adjoint down to its parameters, and an Adam update.  Every
+stage runs in the library's kernels; this module only sequences the calls.
+
+The unmasked search is the fallback and the judge: ``evaluate`` reports the
+pose error of both searches on held-out pairs, and ``use_mask`` is only set
+once the masked search has beaten the unmasked one there.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+import torch
+
+from . import fmbym
+
+
+def he_init(levels: int, base: int, seed: int) -> np.ndarray:
+    """Flat parameters in the library's layout: He-normal conv weights
+    (std sqrt(2 / (9 c_in))), BatchNorm gamma 1 and beta 0, head weights with
+    std sqrt(1 / (9 base)) and a zero bias."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ch = [base << l for l in range(levels)]
+    convs = []
+    for l in range(levels):
+        convs += [(1 if l == 0 else ch[l - 1], ch[l]), (ch[l], ch[l])]
+    for l in range(levels - 2, -1, -1):
+        convs += [(ch[l + 1] + ch[l], ch[l]), (ch[l], ch[l])]
+    parts = []
+    for cin, cout in convs:
+        parts += [rng.normal(0.0, math.sqrt(2.0 / (9 * cin)), cout * cin * 9), np.ones(cout),
+                  np.zeros(cout)]
+    parts += [rng.normal(0.0, math.sqrt(1.0 / (9 * base)), base * 9), np.zeros(1)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+@dataclasses.dataclass
+class TrainConfig:
+    levels: int = 4
+    base: int = 8
+    lr: float = 1e-3
+    loss: int = fmbym.FMBYM_LOSS_L2
+    seed: int = 0
+
+
+class MaskedSearchTrainer:
+    """Mask network + masked search + loss + adjoints + Adam on one GPU."""
+
+    def __init__(self, search_kwargs: dict, batch: int, cfg: TrainConfig = TrainConfig(),
+                 params: np.ndarray | None = None):
+        self.cfg = cfg
+        self.batch = batch
+        self.search = fmbym.Search(max_batch=batch, **search_kwargs)
+        p = he_init(cfg.levels, cfg.base, cfg.seed) if params is None else params
+        self.net = fmbym.MaskNet(p, levels=cfg.levels, base=cfg.base)
+        self.use_mask = False
+
+    def masks(self, f, g, training: bool):
+        B = f.shape[0]
+        m = self.net.forward(torch.cat([f, g]), training=training)
+        return m[:B].contiguous(), m[B:].contiguous()
+
+    def step(self, f, g, target):
+        """One training step on device tensors f, g [B, n, n] and target [B, 3];
+        returns (loss tensor [1], pose [B, 3])."""
+        m_f, m_g = self.masks(f, g, training=True)
+        out = self.search.forward(f, g, m_f, m_g, surfaces=True)
+        loss, d_pose = fmbym.pose_loss_t(out["pose"], target, self.cfg.loss)
+        gr = self.search.backward(f, g, m_f, m_g, out, d_pose)
+        d_params = self.net.backward(torch.cat([gr["d_m_f"], gr["d_m_g"]]))
+        self.net.adam_step(d_params, self.cfg.lr)
+        return loss, out["pose"]
+
+    def gradient(self, f, g, target):
+        """dL/dparams of the chain without updating (for checks)."""
+        m_f, m_g = self.masks(f, g, training=True)
+        out = self.search.forward(f, g, m_f, m_g, surfaces=True)
+        loss, d_pose = fmbym.pose_loss_t(out["pose"], target, self.cfg.loss)
+        gr = self.search.backward(f, g, m_f, m_g, out, d_pose)
+        return loss, self.net.backward(torch.cat([gr["d_m_f"], gr["d_m_g"]]))
+
+    @torch.no_grad()
+    def evaluate(self, f, g, target) -> dict:
+        """Mean |theta| error (rad) and mean translation error (m) of the masked
+        (network in inference mode) and the unmasked search; sets use_mask."""
+        m_f, m_g = self.masks(f, g, training=False)
+        pm = self.search.forward(f, g, m_f, m_g, surfaces=False)["pose"]
+        pu = self.search.forward(f, g, surfaces=False)["pose"]
+
+        def err(p):
+            d = (p - target).double()
+            return float(d[:, 0].abs().mean()), float(d[:, 1:].norm(dim=1).mean())
+
+        em, eu = err(pm), err(pu)
+        # the judge: translation error first (the paper's drift metric), heading as a tie-break
+        self.use_mask = (em[1], em[0]) < (eu[1], eu[0])
+        return {"masked_theta": em[0], "masked_t": em[1], "unmasked_theta": eu[0], "unmasked_t": eu[1],
+                "use_mask": self.use_mask}
+
+    @torch.no_grad()
+    def predict(self, f, g):
+        """Poses with the policy: the masked search once it has won, else the unmasked one."""
+        if self.use_mask:
+            m_f, m_g = self.masks(f, g, training=False)
+            return self.search.forward(f, g, m_f, m_g, surfaces=False)["pose"]
+        return self.search.forward(f, g, surfaces=False)["pose"]

@@ -1,0 +1,102 @@
+"""End-to-end training through the search on the GPU (Section III-E, Eq. 10-13).
+
+1. The gradient of the whole chain (mask network -> masked search -> pose loss)
+   with respect to the network parameters, against FP64 autograd of the oracle
+   chain.  Criterion as for the network alone: the GPU is as close to the exact
+   chain as the chain with the network's BF16 storage (quant oracle) is, plus a
+   term for the search's FP32 adjoint (normwise 1e-3 in its own tests) carried
+   through the network: |gpu - exact| <= 2 |quant - exact| + 1e-2 per group.
+2. Training on synthetic pairs with distractors (moving clutter, multipath
+   ghosts) makes the masked search beat the unmasked one on held-out pairs, and
+   the fallback policy switches to the mask only then.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import fmbym_oracle as O
+from oracle import mask_oracle as M
+from paper_2203_00459_amd import fmbym, synth
+from paper_2203_00459_amd.train import MaskedSearchTrainer, TrainConfig, he_init
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+DT = torch.float64
+KW256 = dict(n=256, n_theta=256, delta_xy=0.35, temp_theta=1.0, temp_xy=1.0, band_lo=0.02, band_hi=0.40)
+
+
+def test_he_init_matches_the_documented_layout():
+    for levels in (1, 2, 4):
+        p = he_init(levels, 8, seed=0)
+        assert p.size == M.param_count(levels, 8)
+        P = M.unpack(torch.from_numpy(p).to(DT), levels, 8)
+        for name, (w, g, b) in ((k, v) for k, v in P.items() if k != "head"):
+            assert torch.all(g == 1) and torch.all(b == 0), name
+            std = float(w.std())
+            assert 0.5 < std / np.sqrt(2.0 / (9 * w.shape[1])) < 1.6, name
+
+
+def test_chain_gradient_matches_oracle():
+    levels, B = 2, 2
+    kw = dict(n=128, n_theta=128, delta_xy=0.5, temp_theta=5.0, temp_xy=2.0, band_lo=0.02, band_hi=0.40)
+    f, g, pose = synth.make_batch("pair128", B, split="val")
+    p = he_init(levels, 8, seed=3)
+    tr = MaskedSearchTrainer(kw, batch=B, cfg=TrainConfig(levels=levels), params=p)
+    target = torch.from_numpy(pose).float().to(DEV)
+    loss, g_gpu = tr.gradient(torch.from_numpy(f).to(DEV), torch.from_numpy(g).to(DEV), target)
+    g_gpu = g_gpu.double().cpu()
+
+    def oracle_grad(quant):
+        th = torch.from_numpy(p).to(DT).requires_grad_(True)
+        X = torch.from_numpy(np.concatenate([f, g])).to(DT)
+        m = M.forward(X, th, levels, 8, quant=quant)
+        op = O.Params(**kw)
+        poses = torch.stack([O.search(f[b], g[b], op, m[b], m[B + b])["pose"] for b in range(B)])
+        L = M.pose_loss(poses, torch.from_numpy(pose).to(DT), "l2")
+        L.backward()
+        return float(L), th.grad.detach()
+
+    L_ref, ref = oracle_grad(False)
+    _, ref_q = oracle_grad(True)
+    print(f"chain loss gpu {float(loss.cpu()):.6f} oracle {L_ref:.6f}", flush=True)
+    assert abs(float(loss.cpu()) - L_ref) <= 1e-2 * max(1.0, L_ref)
+    o, worst = 0, 0.0
+    for c in M.conv_list(levels, 8) + [None]:
+        n_w = 8 * 9 + 1 if c is None else c.c_out * c.c_in * 9 + 2 * c.c_out
+        sl = slice(o, o + n_w)
+        o += n_w
+        nr = max(float(ref[sl].norm()), 1e-30)
+        eg = float((g_gpu[sl] - ref[sl]).norm()) / nr
+        eq = float((ref_q[sl] - ref[sl]).norm()) / nr
+        worst = max(worst, eg / (2 * eq + 1e-2))
+        assert eg <= 2 * eq + 1e-2, ("head" if c is None else c.name, eg, eq)
+    print(f"chain gradient: worst |gpu-exact| / bound {worst:.3f}", flush=True)
+
+
+def test_training_makes_the_mask_beat_the_unmasked_search():
+    ntrain, steps, B = 1024, 600, 16
+    f, g, p = synth.make_batch("mask256", ntrain, split="train")
+    ft, gt, pt = synth.make_batch("mask256", 64, split="test")
+    F, G, P = (torch.from_numpy(a).to(DEV) for a in (f, g, p.astype(np.float32)))
+    Ft, Gt, Pt = (torch.from_numpy(a).to(DEV) for a in (ft, gt, pt.astype(np.float32)))
+    tr = MaskedSearchTrainer(KW256, batch=64, cfg=TrainConfig(lr=1e-3))
+    before = tr.evaluate(Ft, Gt, Pt)
+    print("before", before, flush=True)
+    assert not before["use_mask"]
+    rng = np.random.Generator(np.random.PCG64(0))
+    first, last = [], []
+    for s in range(steps):
+        idx = torch.from_numpy(rng.choice(ntrain, B, replace=False)).to(DEV)
+        loss, _ = tr.step(F[idx].contiguous(), G[idx].contiguous(), P[idx].contiguous())
+        (first if s < 50 else last if s >= steps - 50 else []).append(loss)
+    l0, l1 = float(torch.stack(first).mean()), float(torch.stack(last).mean())
+    after = tr.evaluate(Ft, Gt, Pt)
+    print(f"loss {l0:.3f} -> {l1:.3f}; after {after}", flush=True)
+    assert l1 < 0.25 * l0
+    assert after["use_mask"]
+    assert after["masked_t"] < 0.5 * after["unmasked_t"]
+    assert after["masked_theta"] < after["unmasked_theta"]
+    m_f, m_g = tr.masks(Ft, Gt, training=False)
+    ref = tr.search.forward(Ft, Gt, m_f, m_g, surfaces=False)["pose"]
+    assert torch.equal(tr.predict(Ft, Gt), ref)
