@@ -23,6 +23,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, vendor figure
 FP32_PEAK_TFLOPS = 157.3     # MI355X vector FP32, vendor figure
+BF16_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 matrix cores, vendor figure
 
 
 def kernel_bytes(n: int, n_theta: int, n_r: int, batch: int, masked: bool) -> dict:
@@ -76,7 +77,126 @@ def main() -> int:
     from paper_2203_00459_amd import workloads
     if args.workload in workloads.RAGGED:
         return ragged_bench(args)
+    if args.workload in workloads.TRAIN:
+        return train_bench(args)
     return search_bench(args)
+
+
+def mask_layers(levels: int, base: int):
+    """(c_in, c_out, level) of the mask network's convolutions in order."""
+    ch = [base << l for l in range(levels)]
+    out = []
+    for l in range(levels):
+        out += [(1 if l == 0 else ch[l - 1], ch[l], l), (ch[l], ch[l], l)]
+    for l in range(levels - 2, -1, -1):
+        out += [(ch[l + 1] + ch[l], ch[l], l), (ch[l], ch[l], l)]
+    return out
+
+
+def mask_kernel_model(images: int, n: int, levels: int = 4, base: int = 8) -> dict:
+    """Algorithmic HBM bytes and flops per training step of the mask network's
+    kernel groups: every tensor read and written once (BF16 activations, FP32
+    gradients), convolution flops 2 * pixels * 9 * c_in * c_out."""
+    m = {}
+
+    def add(k, b, f=0.0):
+        bb, ff = m.get(k, (0.0, 0.0))
+        m[k] = (bb + b, ff + f)
+
+    for j, (ci, co, l) in enumerate(mask_layers(levels, base)):
+        px = images * (n >> l) ** 2
+        cik = max(ci, 8)
+        add("m_conv_fwd", px * (cik + co) * 2, 2.0 * px * 9 * ci * co)
+        add("m_bn_relu", px * co * 4)
+        add("m_bn_bwd", px * co * (4 + 2) * 2 + px * co * 2)
+        add("m_wgrad", px * (co + cik) * 2, 2.0 * px * 9 * ci * co)
+        if j:
+            add("m_conv_dgrad", px * (co * 2 + ci * 4), 2.0 * px * 9 * ci * co)
+    return m
+
+
+def train_bench(args) -> int:
+    """One step = one training step of the masked search (Eq. 10-13): mask
+    network forward on both scans of every pair, masked search forward, pose
+    loss, search adjoint, network adjoint, Adam."""
+    import numpy as np
+    import torch
+
+    from paper_2203_00459_amd import fmbym, synth, workloads
+    from paper_2203_00459_amd.train import MaskedSearchTrainer, TrainConfig
+
+    cfg = workloads.TRAIN[args.workload]
+    B, n, levels = cfg["batch"], cfg["n"], cfg["levels"]
+    kw = workloads.search_kwargs(cfg["search"])
+    dev = torch.device("cuda:0")
+    pool = 4 * B
+    f, g, p = synth.make_batch(cfg["scenes"], pool, split="bench")
+    F, G, P = (torch.from_numpy(a).to(dev) for a in (f, g, p.astype(np.float32)))
+    tr = MaskedSearchTrainer(kw, batch=B, cfg=TrainConfig(levels=levels, lr=1e-4))
+    batches = [(F[k * B:(k + 1) * B].contiguous(), G[k * B:(k + 1) * B].contiguous(),
+                P[k * B:(k + 1) * B].contiguous()) for k in range(pool // B)]
+
+    def step(i):
+        tr.step(*batches[i % len(batches)])
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for i in range(args.steps):
+        step(i)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    fmbym.profile_enable(args.steps * 600)
+    for i in range(args.steps):
+        step(i)
+    torch.cuda.synchronize()
+    prof = fmbym.profile_read()
+    fmbym.profile_enable(0)
+    per_step = {k: t / args.steps for k, (t, c) in prof.items()}
+    dom = max(per_step, key=per_step.get)
+    mk = mask_kernel_model(2 * B, n, levels)
+    sb = kernel_bytes(n, kw["n_theta"], n, B, masked=True)
+    if dom in mk:
+        byts, flops = mk[dom]
+    else:
+        byts, flops = sb.get(dom, 0), 0.0
+    t_dom = per_step[dom] * 1e-3
+    achieved = byts / t_dom / 1e9
+    conv_t = per_step.get("m_conv_fwd", 0.0) * 1e-3
+    res = {
+        "metric": f"scan-pairs/sec, {n}^2 masked-search training step (mask net fwd+bwd, search fwd+bwd, Adam), 1 GPU",
+        "value": B / (ms * 1e-3),
+        "unit": "pairs/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 conv (fp32 accumulate), f32 search", "data": "synthetic",
+        "config": {"workload": args.workload, "batch": B, "n": n, "levels": levels, "images_per_step": 2 * B},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "conv_fwd_mfma": None if not conv_t else {
+            "achieved": mk["m_conv_fwd"][1] / conv_t / 1e12, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": mk["m_conv_fwd"][1] / conv_t / 1e12 / BF16_PEAK_TFLOPS},
+        "kernels_ms_per_step": {k: round(v, 5) for k, v in sorted(per_step.items())},
+    }
+    if not args.no_cpu_baseline:
+        from oracle import fmbym_oracle as O
+        from oracle import mask_oracle as M
+        from paper_2203_00459_amd.train import he_init
+        th = torch.from_numpy(he_init(levels, 8, 0)).double().requires_grad_(True)
+        t0 = time.perf_counter()
+        X = torch.from_numpy(np.stack([f[0], g[0]])).double()
+        m = M.forward(X, th, levels, 8)
+        pose = O.search(f[0], g[0], O.Params(**kw), m[0], m[1])["pose"]
+        M.pose_loss(pose[None], torch.from_numpy(p[:1]).double(), "l2").backward()
+        dt = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": 1.0 / dt, "unit": "pairs/s", "cores": torch.get_num_threads(),
+                               "kind": "oracle",
+                               "sample": "1 pair: FP64 oracle mask network + masked search + L2 loss, autograd"}
+    print(json.dumps(res), flush=True)
+    return 0
 
 
 def ragged_bench(args) -> int:

@@ -172,7 +172,7 @@ FMBYM_API int fmbym_wall_clock_khz(int32_t* khz);
  * stream, until the pool is used up; capacity <= 0 switches timing off and
  * frees the pool.  fmbym_profile_read synchronises the recorded events and
  * fills, per kernel k < returned count: names[k], total_ms[k] (sum of launch
- * durations) and launches[k].  Arrays must hold max_kernels >= 32 entries.
+ * durations) and launches[k].  Arrays must hold max_kernels >= 64 entries.
  * Returns the kernel count, FMBYM_EWORKSPACE if the pool overflowed, or an
  * error code.  Not for concurrent use from several threads. */
 FMBYM_API int fmbym_profile_enable(int32_t capacity);

@@ -10,6 +10,7 @@
 #include <math.h>
 
 #include "mask_kernels.hpp"
+#include "profile.hpp"
 
 namespace fmbym {
 
@@ -285,14 +286,16 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16* __restrict__ dz, cons
     }
 }
 
-// out[j] = sum_b part[b stride + j], b ascending (one thread per column).
-__global__ void k_reduce_cols(const float* __restrict__ part, int nb, long long stride, int n,
-                              float* __restrict__ out) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
+// out[j] = sum_b part[b stride + j]: one wave per column, lane l summing
+// b = l, l + 64, ... and a fixed butterfly across the lanes (deterministic).
+__global__ __launch_bounds__(256) void k_reduce_cols(const float* __restrict__ part, int nb,
+                                                     long long stride, int n, float* __restrict__ out) {
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (j >= n) return;   // the whole wave leaves together
     float s = 0.f;
-    for (int b = 0; b < nb; ++b) s += part[(size_t)b * stride + j];
-    out[j] = s;
+    for (int b = lane; b < nb; b += 64) s += part[(size_t)b * stride + j];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) out[j] = s;
 }
 
 // ------------------------------------------------------------ element-wise
@@ -456,25 +459,30 @@ __global__ void k_head_dl(const float* __restrict__ dm, const float* __restrict_
     dl[p] = dm[p] * v * (1.f - v);
 }
 
-// g[p][ci] = sum_taps w[ci][tap] dl[p - (ky - 1, kx - 1)]
+// g[p][ci] = sum_taps w[ci][tap] dl[p - (ky - 1, kx - 1)], one pixel (8 channels) per thread.
 __global__ void k_head_g(const float* __restrict__ dl, const float* __restrict__ w, float* __restrict__ g,
-                         int images, int S, int C) {
-    const long long it = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (it >= (long long)images * S * S * C) return;
-    const int ci = (int)(it % C);
-    const long long p = it / C;
+                         int images, int S) {
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= (long long)images * S * S) return;
     const int x = (int)(p % S), y = (int)((p / S) % S), img = (int)(p / ((long long)S * S));
-    float acc = 0.f;
+    float acc[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[j] = 0.f;
+#pragma unroll
     for (int ky = 0; ky < 3; ++ky) {
         const int yy = y - (ky - 1);
-        if (yy < 0 || yy >= S) continue;
+#pragma unroll
         for (int kx = 0; kx < 3; ++kx) {
             const int xx = x - (kx - 1);
-            if (xx < 0 || xx >= S) continue;
-            acc = fmaf(w[ci * 9 + ky * 3 + kx], dl[((size_t)img * S + yy) * S + xx], acc);
+            if (yy < 0 || yy >= S || xx < 0 || xx >= S) continue;
+            const float d = dl[((size_t)img * S + yy) * S + xx];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) acc[j] = fmaf(w[j * 9 + ky * 3 + kx], d, acc[j]);
         }
     }
-    g[it] = acc;
+    float4* o = reinterpret_cast<float4*>(g + p * 8);
+    o[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+    o[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
 }
 
 constexpr int kHeadPix = 4096;   // pixels per head weight-gradient block
@@ -521,13 +529,14 @@ __global__ __launch_bounds__(256) void k_head_wgrad(const float* __restrict__ dl
 
 // Per-block channel sums for the batch-norm adjoint: part[block][0][c] = sum dy,
 // part[block][1][c] = sum dy xhat over kBnPix pixels.  Thread (pixel lane,
-// channel group) with blockDim = 32 C/8.
+// 8-channel group) with blockDim = (C/8) (256 / (C/8)); the pixel lanes are
+// summed in order through LDS.
 constexpr int kBnPix = 1024;
 
-__global__ void k_bn_bwd_part(const float* __restrict__ g, const bf16* __restrict__ z,
-                              const float* __restrict__ stat, float* __restrict__ part, long long M,
-                              int C) {
-    const int G8 = C / 8, cg = threadIdx.x % G8, pl = threadIdx.x / G8;
+__global__ __launch_bounds__(256) void k_bn_bwd_part(const float* __restrict__ g, const bf16* __restrict__ z,
+                                                     const float* __restrict__ stat, float* __restrict__ part,
+                                                     long long M, int C) {
+    const int G8 = C / 8, PL = blockDim.x / G8, cg = threadIdx.x % G8, pl = threadIdx.x / G8;
     const long long p0 = (long long)blockIdx.x * kBnPix;
     const long long p1 = min(M, p0 + kBnPix);
     float sd[8], sx[8], mean[8], inv[8], sc[8], sh[8];
@@ -540,28 +549,30 @@ __global__ void k_bn_bwd_part(const float* __restrict__ g, const bf16* __restric
         sc[j] = stat[2 * C + c];
         sh[j] = stat[3 * C + c];
     }
-    for (long long p = p0 + pl; p < p1; p += 32) {
+    for (long long p = p0 + pl; p < p1; p += PL) {
         const bf16x8 zv = __builtin_bit_cast(bf16x8, *(const u32x4*)(z + p * C + 8 * cg));
-        const float* gp = g + p * C + 8 * cg;
+        const float4 g0 = *(const float4*)(g + p * C + 8 * cg);
+        const float4 g1 = *(const float4*)(g + p * C + 8 * cg + 4);
+        const float gv[8] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w};
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const float zz = (float)zv[j];
-            const float dy = fmaf(zz, sc[j], sh[j]) > 0.f ? gp[j] : 0.f;
+            const float dy = fmaf(zz, sc[j], sh[j]) > 0.f ? gv[j] : 0.f;
             sd[j] += dy;
             sx[j] = fmaf(dy, (zz - mean[j]) * inv[j], sx[j]);
         }
     }
-    __shared__ float red[32][2][96];
+    __shared__ float red[2][256 * 8];   // [sum][pixel lane][channel]
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-        red[pl][0][8 * cg + j] = sd[j];
-        red[pl][1][8 * cg + j] = sx[j];
+        red[0][pl * C + 8 * cg + j] = sd[j];
+        red[1][pl * C + 8 * cg + j] = sx[j];
     }
     __syncthreads();
     for (int c = threadIdx.x; c < 2 * C; c += blockDim.x) {
         const int k = c / C, cc = c % C;
         float s = 0.f;
-        for (int q = 0; q < 32; ++q) s += red[q][k][cc];
+        for (int q = 0; q < PL; ++q) s += red[k][q * C + cc];
         part[(size_t)blockIdx.x * 2 * C + c] = s;
     }
 }
@@ -618,22 +629,33 @@ __global__ void k_bn_bwd_apply(const float* __restrict__ g, const bf16* __restri
 __global__ void k_pool_bwd(const float* __restrict__ d_pool, const bf16* __restrict__ e,
                            const float* __restrict__ skip, int skip_stride, int skip_off,
                            float* __restrict__ g, int images, int S, int C) {
+    const int G8 = C / 8;
     const long long it = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (it >= (long long)images * S * S * C) return;
-    const int c = (int)(it % C);
-    const long long p = it / C;
+    if (it >= (long long)images * S * S * G8) return;
+    const int cg = (int)(it % G8);
+    const long long p = it / G8;
     const int x = (int)(p % S), y = (int)((p / S) % S), img = (int)(p / ((long long)S * S));
     const int H = S / 2, Y = y / 2, X = x / 2;
-    const bf16* b = e + (((size_t)img * S + 2 * Y) * S + 2 * X) * C + c;
-    const float v[4] = {(float)b[0], (float)b[C], (float)b[(size_t)S * C], (float)b[(size_t)S * C + C]};
-    int arg = 0;
-#pragma unroll
-    for (int k = 1; k < 4; ++k)
-        if (v[k] > v[arg]) arg = k;
+    const bf16* b = e + (((size_t)img * S + 2 * Y) * S + 2 * X) * C + 8 * cg;
+    const bf16x8 w0 = __builtin_bit_cast(bf16x8, *(const u32x4*)b);
+    const bf16x8 w1 = __builtin_bit_cast(bf16x8, *(const u32x4*)(b + C));
+    const bf16x8 w2 = __builtin_bit_cast(bf16x8, *(const u32x4*)(b + (size_t)S * C));
+    const bf16x8 w3 = __builtin_bit_cast(bf16x8, *(const u32x4*)(b + (size_t)S * C + C));
     const int mine = (y - 2 * Y) * 2 + (x - 2 * X);
-    float r = skip ? skip[p * skip_stride + skip_off + c] : 0.f;
-    if (arg == mine) r += d_pool[(((size_t)img * H + Y) * H + X) * C + c];
-    g[it] = r;
+    const float* dp = d_pool + (((size_t)img * H + Y) * H + X) * C + 8 * cg;
+    float r[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const float v[4] = {(float)w0[j], (float)w1[j], (float)w2[j], (float)w3[j]};
+        int arg = 0;
+#pragma unroll
+        for (int k = 1; k < 4; ++k)
+            if (v[k] > v[arg]) arg = k;
+        r[j] = (skip ? skip[p * skip_stride + skip_off + 8 * cg + j] : 0.f) + (arg == mine ? dp[j] : 0.f);
+    }
+    float4* o = reinterpret_cast<float4*>(g + p * C + 8 * cg);
+    o[0] = make_float4(r[0], r[1], r[2], r[3]);
+    o[1] = make_float4(r[4], r[5], r[6], r[7]);
 }
 
 // Adjoint 1-D taps of up2: the outputs o that read input q, with their weights.
@@ -650,22 +672,35 @@ __device__ __forceinline__ int up_adj(int q, int n, int* o, float* w) {
 
 __global__ void k_up_bwd(const float* __restrict__ d_cat, float* __restrict__ d_d, int images, int S,
                          int Cd, int Ce) {
-    const int H = S / 2, C = Cd + Ce;
+    const int H = S / 2, C = Cd + Ce, G8 = Cd / 8;
     const long long it = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (it >= (long long)images * H * H * Cd) return;
-    const int c = (int)(it % Cd);
-    const long long q = it / Cd;
+    if (it >= (long long)images * H * H * G8) return;
+    const int cg = (int)(it % G8);
+    const long long q = it / G8;
     const int X = (int)(q % H), Y = (int)((q / H) % H), img = (int)(q / ((long long)H * H));
     int oy[4], ox[4];
     float wy[4], wx[4];
     const int ny = up_adj(Y, H, oy, wy), nx = up_adj(X, H, ox, wx);
-    float acc = 0.f;
+    float acc[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[j] = 0.f;
     for (int a = 0; a < ny; ++a) {
-        float row = 0.f;
-        for (int b = 0; b < nx; ++b) row = fmaf(wx[b], d_cat[(((size_t)img * S + oy[a]) * S + ox[b]) * C + c], row);
-        acc = fmaf(wy[a], row, acc);
+        float row[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) row[j] = 0.f;
+        for (int b = 0; b < nx; ++b) {
+            const float* src = d_cat + (((size_t)img * S + oy[a]) * S + ox[b]) * C + 8 * cg;
+            const float4 u = *(const float4*)src, v = *(const float4*)(src + 4);
+            const float vals[8] = {u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int j = 0; j < 8; ++j) row[j] = fmaf(wx[b], vals[j], row[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[j] = fmaf(wy[a], row[j], acc[j]);
     }
-    d_d[it] = acc;
+    float4* o = reinterpret_cast<float4*>(d_d + q * Cd + 8 * cg);
+    o[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+    o[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
 }
 
 __global__ void k_pack(const float* __restrict__ w, int cin, int cout, int cink, bf16* __restrict__ wf,
@@ -737,10 +772,10 @@ bool launch_conv3x3(int cin, int cout, bool stats, const bf16* in, const bf16* w
 #define FMBYM_CONV_CASE(CI, CO)                                                                   \
     if (cin == CI && cout == CO) {                                                                \
         if (stats)                                                                                \
-            hipLaunchKernelGGL((k_conv3x3<CI, CO, true, bf16>), grid, block, lds, s, in, w,        \
+            FMBYM_LAUNCH_LDS(kMConvFwd, (k_conv3x3<CI, CO, true, bf16>), grid, block, lds, s, in, w, \
                                (bf16*)z, part, S);                                                \
         else                                                                                      \
-            hipLaunchKernelGGL((k_conv3x3<CI, CO, false, float>), grid, block, lds, s, in, w,      \
+            FMBYM_LAUNCH_LDS(kMConvDgrad, (k_conv3x3<CI, CO, false, float>), grid, block, lds, s, in, w, \
                                (float*)z, part, S);                                               \
         return true;                                                                              \
     }
@@ -767,8 +802,8 @@ bool launch_wgrad(int cin, int cout, const bf16* dz, const bf16* in, float* part
     if (lds > kLdsLimit) return false;
 #define FMBYM_WGRAD_CASE(CI, CO)                                                                  \
     if (cin == CI && cout == CO) {                                                                \
-        hipLaunchKernelGGL((k_wgrad<CI, CO>), dim3(nb), dim3(256), lds, s, dz, in, part, S, tpb, tiles); \
-        hipLaunchKernelGGL(k_reduce_cols, dim3(grid_for(n, 256)), dim3(256), 0, s, part, nb,          \
+        FMBYM_LAUNCH_LDS(kMWgrad, (k_wgrad<CI, CO>), dim3(nb), dim3(256), lds, s, dz, in, part, S, tpb, tiles); \
+        FMBYM_LAUNCH(kMWgrad, k_reduce_cols, dim3(grid_for(n, 4)), dim3(256), s, part, nb,            \
                            (long long)n, n, dw);                                                  \
         return true;                                                                              \
     }
@@ -781,94 +816,95 @@ int bn_part_blocks(long long M, int /*C*/) { return (int)((M + kBnPix - 1) / kBn
 
 void launch_input8(const float* x, bf16* x8, int images, int S, hipStream_t s) {
     const long long n = (long long)images * S * S;
-    hipLaunchKernelGGL(k_input8, dim3(grid_for(n, 256)), dim3(256), 0, s, x, x8, n);
+    FMBYM_LAUNCH(kMInput, k_input8, dim3(grid_for(n, 256)), dim3(256), s, x, x8, n);
 }
 
 void launch_bn_stats(const float* part, int nb, int C, long long M, const float* gamma,
                      const float* beta, float eps, float momentum, int training, float* run_mean,
                      float* run_var, float* stat, hipStream_t s) {
-    hipLaunchKernelGGL(k_bn_stats, dim3(C), dim3(256), 0, s, part, nb, C, M, gamma, beta, eps, momentum,
+    FMBYM_LAUNCH(kMBnStats, k_bn_stats, dim3(C), dim3(256), s, part, nb, C, M, gamma, beta, eps, momentum,
                        training, run_mean, run_var, stat);
 }
 
 void launch_bn_relu(const bf16* z, const float* stat, bf16* a, long long M, int C, hipStream_t s) {
     const long long items = M * (C / 8);
-    hipLaunchKernelGGL(k_bn_relu, dim3(grid_for(items, 256)), dim3(256), 0, s, z, stat, a, items, C);
+    FMBYM_LAUNCH(kMBnRelu, k_bn_relu, dim3(grid_for(items, 256)), dim3(256), s, z, stat, a, items, C);
 }
 
 void launch_maxpool(const bf16* in, bf16* out, int images, int S, int C, hipStream_t s) {
     const long long items = (long long)images * (S / 2) * (S / 2) * (C / 8);
-    hipLaunchKernelGGL(k_maxpool, dim3(grid_for(items, 256)), dim3(256), 0, s, in, out, images, S, C);
+    FMBYM_LAUNCH(kMPool, k_maxpool, dim3(grid_for(items, 256)), dim3(256), s, in, out, images, S, C);
 }
 
 void launch_up_concat(const bf16* d, const bf16* e, bf16* cat, int images, int S, int Cd, int Ce,
                       hipStream_t s) {
     const long long items = (long long)images * S * S * ((Cd + Ce) / 8);
-    hipLaunchKernelGGL(k_up_concat, dim3(grid_for(items, 256)), dim3(256), 0, s, d, e, cat, images, S,
+    FMBYM_LAUNCH(kMUpCat, k_up_concat, dim3(grid_for(items, 256)), dim3(256), s, d, e, cat, images, S,
                        Cd, Ce);
 }
 
 void launch_head_fwd(const bf16* a, const float* w, const float* b, float* mask, int images, int S,
                      int C, hipStream_t s) {
     const long long n = (long long)images * S * S;
-    hipLaunchKernelGGL(k_head_fwd, dim3(grid_for(n, 256)), dim3(256), 0, s, a, w, b, mask, images, S, C);
+    FMBYM_LAUNCH(kMHeadFwd, k_head_fwd, dim3(grid_for(n, 256)), dim3(256), s, a, w, b, mask, images, S, C);
 }
 
 void launch_head_bwd(const float* d_mask, const float* mask, const bf16* a, const float* w, float* dl,
                      float* g, float* part, float* dw, float* db, int images, int S, int C,
                      hipStream_t s) {
     const long long n = (long long)images * S * S;
-    hipLaunchKernelGGL(k_head_dl, dim3(grid_for(n, 256)), dim3(256), 0, s, d_mask, mask, dl, n);
-    hipLaunchKernelGGL(k_head_g, dim3(grid_for(n * C, 256)), dim3(256), 0, s, dl, w, g, images, S, C);
+    FMBYM_LAUNCH(kMHeadBwd, k_head_dl, dim3(grid_for(n, 256)), dim3(256), s, d_mask, mask, dl, n);
+    FMBYM_LAUNCH(kMHeadBwd, k_head_g, dim3(grid_for(n, 256)), dim3(256), s, dl, w, g, images, S);
     const int nb = (int)((n + kHeadPix - 1) / kHeadPix), NW = 9 * C + 1;
-    hipLaunchKernelGGL(k_head_wgrad, dim3(nb), dim3(256), 0, s, dl, a, part, images, S);
-    hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(128), 0, s, part, nb, (long long)NW, 9 * C, dw);
-    hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(64), 0, s, part + 9 * C, nb, (long long)NW, 1, db);
+    FMBYM_LAUNCH(kMHeadBwd, k_head_wgrad, dim3(nb), dim3(256), s, dl, a, part, images, S);
+    FMBYM_LAUNCH(kMHeadBwd, k_reduce_cols, dim3(grid_for(9 * C, 4)), dim3(256), s, part, nb, (long long)NW,
+                 9 * C, dw);
+    FMBYM_LAUNCH(kMHeadBwd, k_reduce_cols, dim3(1), dim3(256), s, part + 9 * C, nb, (long long)NW, 1, db);
 }
 
 void launch_bn_relu_bwd(const float* g, const bf16* z, const float* stat, const float* gamma, float* part,
                         float* coef, float* dgamma, float* dbeta, bf16* dz, long long M, int C,
                         hipStream_t s) {
     const int nb = bn_part_blocks(M, C);
-    hipLaunchKernelGGL(k_bn_bwd_part, dim3(nb), dim3(32 * (C / 8)), 0, s, g, z, stat, part, M, C);
-    hipLaunchKernelGGL(k_bn_bwd_fin, dim3(C), dim3(256), 0, s, part, nb, C, M, gamma, stat, coef, dgamma,
+    FMBYM_LAUNCH(kMBnBwd, k_bn_bwd_part, dim3(nb), dim3((C / 8) * (256 / (C / 8))), s, g, z, stat, part, M, C);
+    FMBYM_LAUNCH(kMBnBwd, k_bn_bwd_fin, dim3(C), dim3(256), s, part, nb, C, M, gamma, stat, coef, dgamma,
                        dbeta);
     const long long items = M * (C / 8);
-    hipLaunchKernelGGL(k_bn_bwd_apply, dim3(grid_for(items, 256)), dim3(256), 0, s, g, z, stat, coef, dz,
+    FMBYM_LAUNCH(kMBnBwd, k_bn_bwd_apply, dim3(grid_for(items, 256)), dim3(256), s, g, z, stat, coef, dz,
                        items, C);
 }
 
 void launch_pool_bwd(const float* d_pool, const bf16* e, const float* skip, int skip_stride,
                      int skip_off, float* g, int images, int S, int C, hipStream_t s) {
-    const long long n = (long long)images * S * S * C;
-    hipLaunchKernelGGL(k_pool_bwd, dim3(grid_for(n, 256)), dim3(256), 0, s, d_pool, e, skip, skip_stride,
+    const long long n = (long long)images * S * S * (C / 8);
+    FMBYM_LAUNCH(kMPoolBwd, k_pool_bwd, dim3(grid_for(n, 256)), dim3(256), s, d_pool, e, skip, skip_stride,
                        skip_off, g, images, S, C);
 }
 
 void launch_up_bwd(const float* d_cat, float* d_d, int images, int S, int Cd, int Ce, hipStream_t s) {
-    const long long n = (long long)images * (S / 2) * (S / 2) * Cd;
-    hipLaunchKernelGGL(k_up_bwd, dim3(grid_for(n, 256)), dim3(256), 0, s, d_cat, d_d, images, S, Cd, Ce);
+    const long long n = (long long)images * (S / 2) * (S / 2) * (Cd / 8);
+    FMBYM_LAUNCH(kMUpBwd, k_up_bwd, dim3(grid_for(n, 256)), dim3(256), s, d_cat, d_d, images, S, Cd, Ce);
 }
 
 void launch_pack(const float* w, int cin, int cout, int cink, bf16* wf, bf16* wb, hipStream_t s) {
     const int n = cout * 9 * cink;
-    hipLaunchKernelGGL(k_pack, dim3(grid_for(n, 256)), dim3(256), 0, s, w, cin, cout, cink, wf, wb);
+    FMBYM_LAUNCH(kMPack, k_pack, dim3(grid_for(n, 256)), dim3(256), s, w, cin, cout, cink, wf, wb);
 }
 
 void launch_unpack_grad(const float* dw, int cin, int cout, int cink, float* out, hipStream_t s) {
     const int n = cout * cin * 9;
-    hipLaunchKernelGGL(k_unpack_grad, dim3(grid_for(n, 256)), dim3(256), 0, s, dw, cin, cout, cink, out);
+    FMBYM_LAUNCH(kMWgrad, k_unpack_grad, dim3(grid_for(n, 256)), dim3(256), s, dw, cin, cout, cink, out);
 }
 
 void launch_adam(float* p, const float* g, float* m, float* v, long long n, float lr, float b1, float b2,
                  float eps, float c1, float c2, hipStream_t s) {
-    hipLaunchKernelGGL(k_adam, dim3(grid_for(n, 256)), dim3(256), 0, s, p, g, m, v, n, lr, b1, b2, eps, c1,
+    FMBYM_LAUNCH(kMAdam, k_adam, dim3(grid_for(n, 256)), dim3(256), s, p, g, m, v, n, lr, b1, b2, eps, c1,
                        c2);
 }
 
 void launch_pose_loss(int batch, const float* pose, const float* target, int kind, float* loss,
                       float* d_pose, hipStream_t s) {
-    hipLaunchKernelGGL(k_pose_loss, dim3(1), dim3(64), 0, s, batch, pose, target, kind, loss, d_pose);
+    FMBYM_LAUNCH(kMLoss, k_pose_loss, dim3(1), dim3(64), s, batch, pose, target, kind, loss, d_pose);
 }
 
 }  // namespace fmbym

@@ -8,10 +8,15 @@
 
 namespace fmbym {
 
+static_assert(kKernelCount <= 64, "profile_read hands out at most 64 entries");
+
 const char* const kKernelNames[kKernelCount] = {
     "k_rows1", "k_cols1", "k_polar", "k_angle_fin", "k_rows2", "k_cols2", "k_rows3", "k_xy_fin",
     "kb_rows_fwd2", "kb_cols_xy", "kb_rows_xy", "kb_dtheta", "kb_polar", "kb_dmag", "kb_cols_mag",
     "kb_rows_final",
+    "m_input8", "m_conv_fwd", "m_bn_stats", "m_bn_relu", "m_maxpool", "m_up_concat", "m_head_fwd",
+    "m_head_bwd", "m_bn_bwd", "m_wgrad", "m_conv_dgrad", "m_pool_bwd", "m_up_bwd", "m_pack", "m_adam",
+    "m_pose_loss",
 };
 
 namespace {
@@ -89,7 +94,7 @@ FMBYM_API int fmbym_profile_enable(int32_t capacity) {
 
 FMBYM_API int fmbym_profile_read(int32_t max_kernels, const char** names, double* total_ms,
                                  int32_t* launches) {
-    if (max_kernels < (int32_t)kKernelCount || !names || !total_ms || !launches) return FMBYM_EINVAL;
+    if (max_kernels < 64 || !names || !total_ms || !launches) return FMBYM_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
     for (int k = 0; k < kKernelCount; ++k) {
         names[k] = kKernelNames[k];

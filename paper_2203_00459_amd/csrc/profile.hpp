@@ -9,6 +9,8 @@ namespace fmbym {
 enum KernelId {
     kKRows1 = 0, kKCols1, kKPolar, kKAngleFin, kKRows2, kKCols2, kKRows3, kKXyFin,
     kKBRowsFwd2, kKBColsXy, kKBRowsXy, kKBDtheta, kKBPolar, kKBDmag, kKBColsMag, kKBRowsFinal,
+    kMInput, kMConvFwd, kMBnStats, kMBnRelu, kMPool, kMUpCat, kMHeadFwd, kMHeadBwd, kMBnBwd, kMWgrad,
+    kMConvDgrad, kMPoolBwd, kMUpBwd, kMPack, kMAdam, kMLoss,
     kKernelCount
 };
 
@@ -26,8 +28,11 @@ struct ProfilePause {
 }  // namespace fmbym
 
 #define FMBYM_LAUNCH(id, kernel, grid, block, stream, ...)                     \
+    FMBYM_LAUNCH_LDS(id, kernel, grid, block, 0, stream, __VA_ARGS__)
+
+#define FMBYM_LAUNCH_LDS(id, kernel, grid, block, lds, stream, ...)            \
     do {                                                                      \
         ::fmbym::prof_before((stream), (id));                                 \
-        hipLaunchKernelGGL(kernel, grid, block, 0, stream, __VA_ARGS__);      \
+        hipLaunchKernelGGL(kernel, grid, block, lds, stream, __VA_ARGS__);    \
         ::fmbym::prof_after((stream), (id));                                  \
     } while (0)

@@ -201,7 +201,7 @@ def profile_enable(capacity: int) -> None:
 
 def profile_read() -> dict:
     """{kernel name: (total ms, launches)} for kernels launched since profile_enable."""
-    K = 32
+    K = 64
     names = (ctypes.c_char_p * K)()
     ms = (ctypes.c_double * K)()
     cnt = (ctypes.c_int32 * K)()

@@ -23,6 +23,12 @@ RAGGED = {
     "ragged1024": dict(n_pairs=1024, mix=(("pair128", 0.5), ("batch256", 0.3), ("batch512", 0.2))),
 }
 
+# Mask-network training: batch of pairs with distractors, the 4-level network.
+TRAIN = {
+    # 16 pairs of 256 x 256 scans with moving clutter and multipath ghosts; search as batch256
+    "mask256": dict(batch=16, n=256, levels=4, scenes="mask256", search="batch256"),
+}
+
 
 def search_kwargs(name: str) -> dict:
     """Keyword arguments shared by the library's Search and the oracle's Params."""
