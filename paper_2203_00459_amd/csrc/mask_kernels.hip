@@ -194,108 +194,192 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16* __restrict__ in, co
     }
 }
 
+// Weight-gradient geometry.  N runs over base columns (ky, ci) of one channel
+// chunk, in groups of 16; each group feeds three N-tiles, one per kx, whose B
+// fragments come from the same two aligned LDS reads (the kx shift is a
+// 16-bit funnel shift).  With fewer than 4 groups the 4 waves split the
+// pixel steps instead and their accumulators are summed in wave order.
+template <int CIN, int COUT>
+struct WgradGeo {
+    static constexpr int CC = chunk_ch(CIN), NCH = CIN / CC;
+    static constexpr int MT = pad16(COUT) / 16, NB = 3 * CC, NG = (NB + 15) / 16;
+    static constexpr int WG = NG >= 4 ? 4 : 1;            // waves across groups
+    static constexpr int GPW = (NG + WG - 1) / WG;        // groups per wave
+    static constexpr int KPW = (kConvTile / 32) * WG / 4; // pixel steps per wave
+    static constexpr size_t red_bytes = WG == 1 ? (size_t)MT * GPW * 3 * 64 * 16 : 0;
+};
+
+__host__ __device__ constexpr int wg_pitch(int S) { return (S >= kConvTile ? kConvTile : S) + 8; }
+__host__ __device__ constexpr int wg_rows(int S) { return (S >= kConvTile ? 1 : kConvTile / S) + 2; }
+
 // Weight gradient over `tpb` consecutive tiles per block:
 // part[block][co][tap CIN + ci] = sum over the tiles' pixels of dz[p][co] in[p + tap][ci].
-// M = output channels, N = (tap, input channel) columns of one channel chunk,
-// K = pixels in steps of 32.  Both operands are gathered from LDS (dz tile and
-// input patch), 8 pixels per lane.
+// M = output channels, K = pixels (8 per lane: one tile row), N = (tap, ci).
+// LDS: dz tile transposed [COUT][256], the input patch transposed per channel
+// [CC][rows][pitch] (pixels contiguous), and the wave-reduction area.
 template <int CIN, int COUT>
 __global__ __launch_bounds__(256) void k_wgrad(const bf16* __restrict__ dz, const bf16* __restrict__ in,
                                                float* __restrict__ part, int S, int tpb, int tiles) {
-    constexpr int CC = chunk_ch(CIN), NCH = CIN / CC, G = CC / 8;
-    constexpr int MT = pad16(COUT) / 16, KC = 9 * CC, NTK = (KC + 15) / 16, NTW = (NTK + 3) / 4;
+    using Geo = WgradGeo<CIN, COUT>;
+    constexpr int CC = Geo::CC, MT = Geo::MT, NB = Geo::NB, NG = Geo::NG, WG = Geo::WG, GPW = Geo::GPW,
+                  KPW = Geo::KPW;
     constexpr int K = 9 * CIN;
-    extern __shared__ u32x4 patch[];   // patch_bytes(CIN, S), then the dz tile [256][COUT]
-    bf16* dzt = reinterpret_cast<bf16*>(patch + (size_t)patch_pixels(S) * (G + 1));
+    extern __shared__ u32x4 smem[];
+    bf16* dzt = reinterpret_cast<bf16*>(smem);                       // [COUT][256]
+    bf16* pt = dzt + COUT * kConvTile;                               // [CC][rows][pitch]
+    const int PW = wg_pitch(S), PRW = wg_rows(S);
+    f32x4* red = reinterpret_cast<f32x4*>(pt + (size_t)CC * PRW * PW);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, r16 = lane & 15;
-    const bf16* pe = reinterpret_cast<const bf16*>(patch);
-    for (int ch = 0; ch < NCH; ++ch) {
+    const u32x4 zero = {0u, 0u, 0u, 0u};
+    for (int ch = 0; ch < Geo::NCH; ++ch) {
         const int c0 = ch * CC;
-        f32x4 acc[MT][NTW];
+        f32x4 acc[MT][GPW][3];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-            for (int j = 0; j < NTW; ++j) acc[mt][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int gi = 0; gi < GPW; ++gi)
+#pragma unroll
+                for (int kx = 0; kx < 3; ++kx) acc[mt][gi][kx] = f32x4{0.f, 0.f, 0.f, 0.f};
         for (int k = 0; k < tpb; ++k) {
             const int tile = blockIdx.x * tpb + k;
             if (tile >= tiles) break;
             const TileGeo t = tile_geo(tile, S);
+            const size_t img_base = (size_t)t.img * S * S;
             __syncthreads();
-            stage_patch<CIN, G>(in, patch, t, S, c0);
+            // dz tile, transposed
+            for (int it = threadIdx.x; it < kConvTile * COUT / 8; it += blockDim.x) {
+                const int p = it / (COUT / 8), cg = it % (COUT / 8);
+                const size_t pix = img_base + (size_t)(t.y0 + p / t.pc) * S + t.x0 + p % t.pc;
+                const bf16x8 v = __builtin_bit_cast(bf16x8, *(const u32x4*)(dz + pix * COUT + 8 * cg));
+#pragma unroll
+                for (int j = 0; j < 8; ++j) dzt[(8 * cg + j) * kConvTile + p] = v[j];
+            }
+            // input patch of the chunk, transposed per channel
             {
-                const size_t img_base = (size_t)t.img * S * S;
-                for (int it = threadIdx.x; it < kConvTile * COUT / 8; it += blockDim.x) {
-                    const int p = it / (COUT / 8), cg = it % (COUT / 8);
-                    const size_t pix = img_base + (size_t)(t.y0 + p / t.pc) * S + t.x0 + p % t.pc;
-                    *(u32x4*)(dzt + p * COUT + 8 * cg) = *(const u32x4*)(dz + pix * COUT + 8 * cg);
+                const int W = t.pc + 2, npix = (t.pr + 2) * W;
+                const bf16* base = in + (size_t)t.img * S * S * CIN;
+                for (int it = threadIdx.x; it < npix * (CC / 8); it += blockDim.x) {
+                    const int q = it / (CC / 8), cg = it % (CC / 8);
+                    const int r = q / W, c = q % W;
+                    const int y = t.y0 - 1 + r, x = t.x0 - 1 + c;
+                    u32x4 u = zero;
+                    if (y >= 0 && y < S && x >= 0 && x < S)
+                        u = *(const u32x4*)(base + ((size_t)y * S + x) * CIN + c0 + 8 * cg);
+                    const bf16x8 v = __builtin_bit_cast(bf16x8, u);
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) pt[((size_t)(8 * cg + j) * PRW + r) * PW + c] = v[j];
                 }
             }
             __syncthreads();
-            const int W = t.pc + 2;
-#pragma unroll 2
-            for (int st = 0; st < kConvTile / 32; ++st) {
-                const int p0 = 32 * st + 8 * g;           // this lane's 8 pixels (one tile row)
+#pragma unroll
+            for (int kk = 0; kk < KPW; ++kk) {
+                const int st = WG == 4 ? kk : wave * KPW + kk;
+                const int p0 = 32 * st + 8 * g;
                 const int row = p0 / t.pc, col = p0 % t.pc;
                 u32x4 a[MT];
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt) {
                     const int co = mt * 16 + r16;
-                    bf16x8 v;
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) v[j] = co < COUT ? dzt[(p0 + j) * COUT + co] : (bf16)0.f;
-                    a[mt] = __builtin_bit_cast(u32x4, v);
+                    a[mt] = co < COUT ? *(const u32x4*)(dzt + co * kConvTile + p0) : zero;
                 }
 #pragma unroll
-                for (int j = 0; j < NTW; ++j) {
-                    const int nt = wave + 4 * j;
-                    if (nt >= NTK) break;
-                    const int kc = nt * 16 + r16;
-                    bf16x8 v;
-                    if (kc < KC) {
-                        const int tap = kc / CC, ci = kc % CC;
-                        const int base = ((row + tap / 3) * W + col + tap % 3) * (G + 1) * 8 + ci;
-#pragma unroll
-                        for (int e = 0; e < 8; ++e) v[e] = pe[base + e * (G + 1) * 8];
-                    } else {
-#pragma unroll
-                        for (int e = 0; e < 8; ++e) v[e] = (bf16)0.f;
+                for (int gi = 0; gi < GPW; ++gi) {
+                    const int gp = WG == 4 ? wave + 4 * gi : gi;
+                    if (gp >= NG) break;
+                    const int bc = gp * 16 + r16;
+                    u32x4 b0 = zero, b1 = zero, b2 = zero;
+                    if (bc < NB) {
+                        const int ky = bc / CC, ci = bc % CC;
+                        const bf16* src = pt + ((size_t)ci * PRW + row + ky) * PW + col;
+                        const u32x4 w = *(const u32x4*)src;
+                        const unsigned w4 = *(const unsigned*)(src + 8);
+                        b0 = w;
+                        b1 = u32x4{__builtin_amdgcn_alignbyte(w[1], w[0], 2), __builtin_amdgcn_alignbyte(w[2], w[1], 2),
+                                   __builtin_amdgcn_alignbyte(w[3], w[2], 2), __builtin_amdgcn_alignbyte(w4, w[3], 2)};
+                        b2 = u32x4{w[1], w[2], w[3], w4};
                     }
-                    const u32x4 b = __builtin_bit_cast(u32x4, v);
 #pragma unroll
-                    for (int mt = 0; mt < MT; ++mt) acc[mt][j] = mfma(a[mt], b, acc[mt][j]);
+                    for (int mt = 0; mt < MT; ++mt) {
+                        acc[mt][gi][0] = mfma(a[mt], b0, acc[mt][gi][0]);
+                        acc[mt][gi][1] = mfma(a[mt], b1, acc[mt][gi][1]);
+                        acc[mt][gi][2] = mfma(a[mt], b2, acc[mt][gi][2]);
+                    }
                 }
             }
+        }
+        if constexpr (WG == 1) {
+            // waves hold partial sums over their pixel steps: add them in wave order
+            for (int wv = 0; wv < 4; ++wv) {
+                __syncthreads();
+                if (wave == wv) {
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                        for (int gi = 0; gi < GPW; ++gi)
+#pragma unroll
+                            for (int kx = 0; kx < 3; ++kx) {
+                                f32x4& r = red[((mt * GPW + gi) * 3 + kx) * 64 + lane];
+                                if (wv == 0)
+                                    r = acc[mt][gi][kx];
+                                else
+                                    r = r + acc[mt][gi][kx];
+                                acc[mt][gi][kx] = r;
+                            }
+                }
+            }
+            if (wave != 3) continue;   // wave 3 now holds the block's sums (block-uniform per wave)
         }
         float* pb = part + (size_t)blockIdx.x * COUT * K;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-            for (int j = 0; j < NTW; ++j) {
-                const int nt = wave + 4 * j;
-                if (nt >= NTK) break;
-                const int kc = nt * 16 + r16;
-                if (kc >= KC) continue;
-                const int kg = (kc / CC) * CIN + c0 + kc % CC;
+            for (int gi = 0; gi < GPW; ++gi) {
+                const int gp = WG == 4 ? wave + 4 * gi : gi;
+                if (gp >= NG) break;
+                const int bc = gp * 16 + r16;
+                if (bc >= NB) continue;
+                const int ky = bc / CC, ci = bc % CC;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int co = mt * 16 + 4 * g + r;
-                    if (co < COUT) pb[(size_t)co * K + kg] = acc[mt][j][r];
+                for (int kx = 0; kx < 3; ++kx) {
+                    const int kg = (ky * 3 + kx) * CIN + c0 + ci;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int co = mt * 16 + 4 * g + r;
+                        if (co < COUT) pb[(size_t)co * K + kg] = acc[mt][gi][kx][r];
+                    }
                 }
             }
     }
 }
 
-// out[j] = sum_b part[b stride + j]: one wave per column, lane l summing
-// b = l, l + 64, ... and a fixed butterfly across the lanes (deterministic).
-__global__ __launch_bounds__(256) void k_reduce_cols(const float* __restrict__ part, int nb,
-                                                     long long stride, int n, float* __restrict__ out) {
-    const int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-    if (j >= n) return;   // the whole wave leaves together
+// Column sums of a [nb][stride] partial array, in two fixed-order stages so
+// that both read coalesced rows: stage 1 gives tmp[c][j] = sum over the rows of
+// chunk c (`per` rows, 4 interleaved lanes added in lane order), stage 2 adds
+// the chunks in order (in double precision).
+constexpr int kColChunks = 64;
+
+__global__ __launch_bounds__(256) void k_colsum1(const float* __restrict__ part, int nb, long long stride,
+                                                 int n, int per, float* __restrict__ tmp) {
+    const int t = threadIdx.x & 63, bl = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + t;
+    const int b0 = blockIdx.y * per, b1 = min(nb, b0 + per);
     float s = 0.f;
-    for (int b = lane; b < nb; b += 64) s += part[(size_t)b * stride + j];
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    if (lane == 0) out[j] = s;
+    if (j < n)
+        for (int b = b0 + bl; b < b1; b += 4) s += part[(size_t)b * stride + j];
+    __shared__ float r[4][64];
+    r[bl][t] = s;
+    __syncthreads();
+    if (bl == 0 && j < n) tmp[(size_t)blockIdx.y * n + j] = ((r[0][t] + r[1][t]) + r[2][t]) + r[3][t];
+}
+
+__global__ void k_colsum2(const float* __restrict__ tmp, int nbc, int n, int j0, int count,
+                          float* __restrict__ out) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= count) return;
+    double s = 0.0;
+    for (int c = 0; c < nbc; ++c) s += tmp[(size_t)c * n + j0 + j];
+    out[j] = (float)s;
 }
 
 // ------------------------------------------------------------ element-wise
@@ -756,7 +840,18 @@ __global__ void k_pose_loss(int batch, const float* __restrict__ pose, const flo
 
 inline unsigned grid_for(long long n, int block) { return (unsigned)((n + block - 1) / block); }
 
+// Stage 1 of the column sums; returns the number of chunks written to tmp.
+int colsum1(int id, const float* part, int nb, long long stride, int n, float* tmp, hipStream_t s) {
+    const int nbc = nb < kColChunks ? nb : kColChunks;
+    const int per = (nb + nbc - 1) / nbc;
+    const int used = (nb + per - 1) / per;
+    FMBYM_LAUNCH(id, k_colsum1, dim3(grid_for(n, 64), used), dim3(256), s, part, nb, stride, n, per, tmp);
+    return used;
+}
+
 }  // namespace
+
+size_t colsum_tmp_floats(int n) { return (size_t)kColChunks * n; }
 
 // ------------------------------------------------------------------ launchers
 
@@ -786,25 +881,27 @@ bool launch_conv3x3(int cin, int cout, bool stats, const bf16* in, const bf16* w
 
 void wgrad_grid(int images, int S, int* blocks, int* tiles_per_block) {
     const int tiles = conv_blocks(images, S);
-    int tpb = tiles / 512;
+    int tpb = tiles / 2048;
     tpb = tpb < 1 ? 1 : (tpb > 16 ? 16 : tpb);
     *tiles_per_block = tpb;
     *blocks = (tiles + tpb - 1) / tpb;
 }
 
-bool launch_wgrad(int cin, int cout, const bf16* dz, const bf16* in, float* part, float* dw, int images,
-                  int S, hipStream_t s) {
+bool launch_wgrad(int cin, int cout, const bf16* dz, const bf16* in, float* part, float* tmp, float* dw,
+                  int images, int S, hipStream_t s) {
     int nb, tpb;
     wgrad_grid(images, S, &nb, &tpb);
     const int tiles = conv_blocks(images, S);
     const int n = cout * 9 * cin;
-    const size_t lds = patch_bytes(cin, S) + (size_t)kConvTile * cout * sizeof(bf16);
-    if (lds > kLdsLimit) return false;
 #define FMBYM_WGRAD_CASE(CI, CO)                                                                  \
     if (cin == CI && cout == CO) {                                                                \
+        using Geo = WgradGeo<CI, CO>;                                                             \
+        const size_t lds = (size_t)CO * kConvTile * 2 + (size_t)Geo::CC * wg_rows(S) * wg_pitch(S) * 2 + \
+                           Geo::red_bytes;                                                        \
+        if (lds > kLdsLimit) return false;                                                        \
         FMBYM_LAUNCH_LDS(kMWgrad, (k_wgrad<CI, CO>), dim3(nb), dim3(256), lds, s, dz, in, part, S, tpb, tiles); \
-        FMBYM_LAUNCH(kMWgrad, k_reduce_cols, dim3(grid_for(n, 4)), dim3(256), s, part, nb,            \
-                           (long long)n, n, dw);                                                  \
+        const int nbc = colsum1(kMWgrad, part, nb, (long long)n, n, tmp, s);                       \
+        FMBYM_LAUNCH(kMWgrad, k_colsum2, dim3(grid_for(n, 256)), dim3(256), s, tmp, nbc, n, 0, n, dw); \
         return true;                                                                              \
     }
     FMBYM_CONV_PAIRS(FMBYM_WGRAD_CASE)
@@ -821,9 +918,10 @@ void launch_input8(const float* x, bf16* x8, int images, int S, hipStream_t s) {
 
 void launch_bn_stats(const float* part, int nb, int C, long long M, const float* gamma,
                      const float* beta, float eps, float momentum, int training, float* run_mean,
-                     float* run_var, float* stat, hipStream_t s) {
+                     float* run_var, float* stat, float* tmp, hipStream_t s) {
+    (void)tmp;
     FMBYM_LAUNCH(kMBnStats, k_bn_stats, dim3(C), dim3(256), s, part, nb, C, M, gamma, beta, eps, momentum,
-                       training, run_mean, run_var, stat);
+                 training, run_mean, run_var, stat);
 }
 
 void launch_bn_relu(const bf16* z, const float* stat, bf16* a, long long M, int C, hipStream_t s) {
@@ -850,23 +948,24 @@ void launch_head_fwd(const bf16* a, const float* w, const float* b, float* mask,
 }
 
 void launch_head_bwd(const float* d_mask, const float* mask, const bf16* a, const float* w, float* dl,
-                     float* g, float* part, float* dw, float* db, int images, int S, int C,
+                     float* g, float* part, float* tmp, float* dw, float* db, int images, int S, int C,
                      hipStream_t s) {
     const long long n = (long long)images * S * S;
     FMBYM_LAUNCH(kMHeadBwd, k_head_dl, dim3(grid_for(n, 256)), dim3(256), s, d_mask, mask, dl, n);
     FMBYM_LAUNCH(kMHeadBwd, k_head_g, dim3(grid_for(n, 256)), dim3(256), s, dl, w, g, images, S);
     const int nb = (int)((n + kHeadPix - 1) / kHeadPix), NW = 9 * C + 1;
     FMBYM_LAUNCH(kMHeadBwd, k_head_wgrad, dim3(nb), dim3(256), s, dl, a, part, images, S);
-    FMBYM_LAUNCH(kMHeadBwd, k_reduce_cols, dim3(grid_for(9 * C, 4)), dim3(256), s, part, nb, (long long)NW,
-                 9 * C, dw);
-    FMBYM_LAUNCH(kMHeadBwd, k_reduce_cols, dim3(1), dim3(256), s, part + 9 * C, nb, (long long)NW, 1, db);
+    const int nbc = colsum1(kMHeadBwd, part, nb, (long long)NW, NW, tmp, s);
+    FMBYM_LAUNCH(kMHeadBwd, k_colsum2, dim3(1), dim3(128), s, tmp, nbc, NW, 0, 9 * C, dw);
+    FMBYM_LAUNCH(kMHeadBwd, k_colsum2, dim3(1), dim3(64), s, tmp, nbc, NW, 9 * C, 1, db);
 }
 
 void launch_bn_relu_bwd(const float* g, const bf16* z, const float* stat, const float* gamma, float* part,
-                        float* coef, float* dgamma, float* dbeta, bf16* dz, long long M, int C,
+                        float* tmp, float* coef, float* dgamma, float* dbeta, bf16* dz, long long M, int C,
                         hipStream_t s) {
     const int nb = bn_part_blocks(M, C);
     FMBYM_LAUNCH(kMBnBwd, k_bn_bwd_part, dim3(nb), dim3((C / 8) * (256 / (C / 8))), s, g, z, stat, part, M, C);
+    (void)tmp;
     FMBYM_LAUNCH(kMBnBwd, k_bn_bwd_fin, dim3(C), dim3(256), s, part, nb, C, M, gamma, stat, coef, dgamma,
                        dbeta);
     const long long items = M * (C / 8);

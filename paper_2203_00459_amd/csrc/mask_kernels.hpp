@@ -39,16 +39,20 @@ bool launch_conv3x3(int cin, int cout, bool stats, const bf16* in, const bf16* w
 
 // Weight gradient: dw[co][9 cin] (float, k as above) = sum over pixels of
 // dz[p][co] in[p + tap][ci], through per-block partials part (wgrad_grid) and
-// a fixed-order reduction.  Returns false for an unsupported pair.
-bool launch_wgrad(int cin, int cout, const bf16* dz, const bf16* in, float* part, float* dw,
+// a fixed-order reduction (tmp: colsum_tmp_floats(cout 9 cin)).  Returns false
+// for an unsupported pair.
+bool launch_wgrad(int cin, int cout, const bf16* dz, const bf16* in, float* part, float* tmp, float* dw,
                   int images, int S, hipStream_t s);
+
+// Floats of the scratch `tmp` that the two-stage column sums of n columns need.
+size_t colsum_tmp_floats(int n);
 
 // Batch-norm statistics: reduce part[nb][2][C] (sums of z, z^2) over nb in a
 // fixed order; training: mean/var of the batch (and running-statistics
 // update), else the running ones.  Writes stat[4][C] = mean, invstd, scale, shift.
 void launch_bn_stats(const float* part, int nb, int C, long long M, const float* gamma,
                      const float* beta, float eps, float momentum, int training,
-                     float* run_mean, float* run_var, float* stat, hipStream_t s);
+                     float* run_mean, float* run_var, float* stat, float* tmp, hipStream_t s);
 
 // a = relu(z scale + shift) per channel, bf16 -> bf16.
 void launch_bn_relu(const bf16* z, const float* stat, bf16* a, long long M, int C, hipStream_t s);
@@ -66,15 +70,15 @@ void launch_head_fwd(const bf16* a, const float* w, const float* b, float* mask,
 // Head adjoint: dl = d_mask m (1 - m); g [I][S][S][C] float = conv3x3^T(dl, w);
 // dw [C][3][3] and db (float, written) through per-block partials in part.
 void launch_head_bwd(const float* d_mask, const float* mask, const bf16* a, const float* w,
-                     float* dl, float* g, float* part, float* dw, float* db, int images, int S, int C,
-                     hipStream_t s);
+                     float* dl, float* g, float* part, float* tmp, float* dw, float* db, int images, int S,
+                     int C, hipStream_t s);
 
 // Batch-norm + ReLU adjoint given g = dL/da (float): dy = g [a > 0];
 // dgamma = sum dy xhat, dbeta = sum dy (written to dgamma/dbeta);
 // dz = gamma invstd / M (M dy - dbeta - xhat dgamma), bf16.
 void launch_bn_relu_bwd(const float* g, const bf16* z, const float* stat, const float* gamma,
-                        float* part, float* coef, float* dgamma, float* dbeta, bf16* dz, long long M,
-                        int C, hipStream_t s);
+                        float* part, float* tmp, float* coef, float* dgamma, float* dbeta, bf16* dz,
+                        long long M, int C, hipStream_t s);
 
 // Max-pool adjoint plus the skip gradient: g[p][c] = skip[p][c] (channel
 // offset skip_off of a row of skip_stride floats, or 0 if skip is null) +

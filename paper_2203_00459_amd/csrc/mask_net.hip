@@ -111,7 +111,7 @@ struct Bump {
 };
 
 struct ActLayout {
-    size_t x8 = 0, mask = 0, part = 0, total = 0;
+    size_t x8 = 0, mask = 0, part = 0, tmp = 0, total = 0;
     std::vector<size_t> z, a, stat, pool, cat;
 };
 
@@ -135,12 +135,13 @@ ActLayout act_layout(const Net& net, int I, int n) {
     for (int l = 0; l + 1 < net.levels; ++l) L.cat[l] = b.take(pix(l) * (net.ch(l + 1) + net.ch(l)) * bf);
     L.mask = b.take(pix(0) * fl);
     L.part = b.take(part_max);
+    L.tmp = b.take(colsum_tmp_floats(2 * 96) * fl);
     L.total = b.off;
     return L;
 }
 
 struct WsLayout {
-    size_t dz = 0, part = 0, coef = 0, wpart = 0, dw = 0, dl = 0, hpart = 0, total = 0;
+    size_t dz = 0, part = 0, coef = 0, wpart = 0, dw = 0, dl = 0, hpart = 0, tmp = 0, total = 0;
     std::vector<size_t> g, dpool, dcat;
 };
 
@@ -170,6 +171,9 @@ WsLayout ws_layout(const Net& net, int I, int n) {
     L.dw = b.take(dw_max);
     L.dl = b.take(pix(0) * fl);
     L.hpart = b.take(((pix(0) + 4095) / 4096) * (9 * net.base + 1) * fl);
+    size_t cols = 2 * 96;
+    for (const ConvL& c : net.convs) cols = std::max(cols, (size_t)c.cout * 9 * c.cink);
+    L.tmp = b.take(colsum_tmp_floats((int)cols) * fl);
     L.total = b.off;
     return L;
 }
@@ -273,7 +277,7 @@ int fmbym_mask_fwd(const fmbym_mask_desc* d, int32_t I, int32_t n, const float* 
         const long long M = (long long)I * S * S;
         launch_bn_stats(at<float>(act, A.part), conv_blocks(I, S), c.cout, M, d->params + c.gamma,
                         d->params + c.beta, net.eps, net.momentum, training ? 1 : 0, run_mean + c.bn,
-                        run_var + c.bn, at<float>(act, A.stat[j]), s);
+                        run_var + c.bn, at<float>(act, A.stat[j]), at<float>(act, A.tmp), s);
         launch_bn_relu(at<bf16>(act, A.z[j]), at<float>(act, A.stat[j]), at<bf16>(act, A.a[j]), M, c.cout, s);
     }
     launch_head_fwd(at<bf16>(act, A.a[net.last()]), d->params + net.head_w, d->params + net.head_b, mask, I,
@@ -301,14 +305,15 @@ int fmbym_mask_bwd(const fmbym_mask_desc* d, int32_t I, int32_t n, const float* 
     const int last = net.last();
     launch_head_bwd(d_mask, at<float>(act, A.mask), at<bf16>(act, A.a[last]), P + net.head_w,
                     at<float>(wsp, W.dl), at<float>(wsp, W.g[last]), at<float>(wsp, W.hpart),
-                    d_params + net.head_w, d_params + net.head_b, I, n, net.base, s);
+                    at<float>(wsp, W.tmp), d_params + net.head_w, d_params + net.head_b, I, n, net.base, s);
     for (int j = last; j >= 0; --j) {
         const ConvL& c = net.convs[j];
         const int S = n >> c.level;
         const long long M = (long long)I * S * S;
         bf16* dz = at<bf16>(wsp, W.dz);
         launch_bn_relu_bwd(at<float>(wsp, W.g[j]), at<bf16>(act, A.z[j]), at<float>(act, A.stat[j]),
-                           P + c.gamma, at<float>(wsp, W.part), at<float>(wsp, W.coef), d_params + c.gamma,
+                           P + c.gamma, at<float>(wsp, W.part), at<float>(wsp, W.tmp), at<float>(wsp, W.coef),
+                           d_params + c.gamma,
                            d_params + c.beta, dz, M, c.cout, s);
         const bf16* in;
         if (j == 0)
@@ -319,7 +324,8 @@ int fmbym_mask_bwd(const fmbym_mask_desc* d, int32_t I, int32_t n, const float* 
             in = at<bf16>(act, A.cat[c.level]);
         else
             in = at<bf16>(act, A.a[j - 1]);
-        if (!launch_wgrad(c.cink, c.cout, dz, in, at<float>(wsp, W.wpart), at<float>(wsp, W.dw), I, S, s))
+        if (!launch_wgrad(c.cink, c.cout, dz, in, at<float>(wsp, W.wpart), at<float>(wsp, W.tmp),
+                          at<float>(wsp, W.dw), I, S, s))
             return FMBYM_EUNSUPPORTED;
         launch_unpack_grad(at<float>(wsp, W.dw), c.cin, c.cout, c.cink, d_params + c.w, s);
         if (j == 0) break;
