@@ -128,38 +128,48 @@ FMBYM_API int fmbym_search_backward(fmbym_plan plan, int32_t batch, const float*
  * with the plan of its size; the batch runs as ONE replayable launch: pairs are
  * grouped by (n, masked), every group is a batched forward search, and the
  * groups are concurrent branches of a HIP graph captured at creation. */
+#define FMBYM_PAIR_NET_MASK 1u   /* masks of this pair come from the mask network (fmbym_mask.h) */
+
 typedef struct {
-    int32_t n;          /* scan side of this pair; one of the plans must have this n */
-    int32_t reserved;   /* must be 0                                                 */
-    const float* f;     /* [n][n] device scans (required)                            */
+    int32_t n;          /* scan side of this pair; one of the plans must have this n              */
+    uint32_t flags;     /* 0 or FMBYM_PAIR_NET_MASK                                               */
+    const float* f;     /* [n][n] device scans (required)                                         */
     const float* g;
-    const float* m_f;   /* [n][n] device masks, or both NULL                         */
+    const float* m_f;   /* [n][n] device masks, or both NULL (must be NULL with FMBYM_PAIR_NET_MASK) */
     const float* m_g;
 } fmbym_pair;
 
 typedef struct fmbym_ragged_s* fmbym_ragged;
+struct fmbym_mask_desc_s;   /* fmbym_mask_desc of fmbym_mask.h */
 
 /* Bytes of device workspace fmbym_ragged_create needs for this work list
- * (pairs is a HOST array of n_pairs entries); 0 on bad input. */
+ * (pairs is a HOST array of n_pairs entries; net as for create); 0 on bad input. */
 FMBYM_API size_t fmbym_ragged_workspace_size(const fmbym_plan* plans, int32_t n_plans,
-                                             const fmbym_pair* pairs, int32_t n_pairs);
+                                             const fmbym_pair* pairs, int32_t n_pairs,
+                                             const struct fmbym_mask_desc_s* net);
 
 /* Build the launch (this call allocates: pointer tables, streams, the graph).
  *   plans     n_plans plans with distinct n; each pair uses the one of its n
  *             (their max_batch does not bound the group sizes)
  *   pairs     HOST array; the device pointers in it are baked into the launch:
  *             every fmbym_ragged_launch reads what they hold at that time
+ *   net       mask network for the pairs flagged FMBYM_PAIR_NET_MASK (NULL if
+ *             none is): each such group first runs the network in inference
+ *             mode (running statistics) on its 2 x count scans, then the search
+ *             on the masked scans; the descriptor is copied, the buffers it
+ *             points to are read at every launch
  *   pose      [n_pairs][3] device output, in the order of `pairs`
  *   stamps    [n_pairs + 1] device output or NULL: stamps[i] is the device wall
  *             clock when pose[i] was written, stamps[n_pairs] when the launch
  *             started (ticks of hipDeviceAttributeWallClockRate, in kHz)
  *   workspace fmbym_ragged_workspace_size() bytes, owned by the caller, used by
  *             every launch and by nothing else until fmbym_ragged_destroy
- * Plans, pose, stamps and workspace must outlive the object.  Launches of one
- * object must not overlap (they share the workspace). */
+ * Plans, the network's buffers, pose, stamps and workspace must outlive the
+ * object.  Launches of one object must not overlap (they share the workspace). */
 FMBYM_API int fmbym_ragged_create(const fmbym_plan* plans, int32_t n_plans, const fmbym_pair* pairs,
-                                  int32_t n_pairs, float* pose, uint64_t* stamps, void* workspace,
-                                  size_t workspace_bytes, fmbym_ragged* out);
+                                  int32_t n_pairs, const struct fmbym_mask_desc_s* net, float* pose,
+                                  uint64_t* stamps, void* workspace, size_t workspace_bytes,
+                                  fmbym_ragged* out);
 /* Enqueue one replay of the whole work list on `stream`. */
 FMBYM_API int fmbym_ragged_launch(fmbym_ragged r, void* stream);
 FMBYM_API int fmbym_ragged_destroy(fmbym_ragged r);

@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-typedef struct {
+typedef struct fmbym_mask_desc_s {
     int32_t levels;          /* 1..4                                                      */
     int32_t base_channels;   /* 8                                                         */
     float bn_eps;            /* BatchNorm epsilon, > 0 (1e-5)                             */

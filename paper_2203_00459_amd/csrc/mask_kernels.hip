@@ -384,13 +384,15 @@ __global__ void k_colsum2(const float* __restrict__ tmp, int nbc, int n, int j0,
 
 // ------------------------------------------------------------ element-wise
 
-__global__ void k_input8(const float* __restrict__ x, bf16* __restrict__ x8, long long npix) {
+// Scan -> 8-channel BF16 input; image i is x + i S^2, or x_tab[i] for a table of scans.
+__global__ void k_input8(const float* __restrict__ x, const float* const* __restrict__ x_tab,
+                         bf16* __restrict__ x8, long long npix, int S2) {
     const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npix) return;
     bf16x8 v;
 #pragma unroll
     for (int j = 0; j < 8; ++j) v[j] = (bf16)0.f;
-    v[0] = (bf16)x[p];
+    v[0] = (bf16)(x_tab ? x_tab[p / S2][p % S2] : x[p]);
     *(u32x4*)(x8 + p * 8) = __builtin_bit_cast(u32x4, v);
 }
 
@@ -911,9 +913,9 @@ bool launch_wgrad(int cin, int cout, const bf16* dz, const bf16* in, float* part
 
 int bn_part_blocks(long long M, int /*C*/) { return (int)((M + kBnPix - 1) / kBnPix); }
 
-void launch_input8(const float* x, bf16* x8, int images, int S, hipStream_t s) {
+void launch_input8(const float* x, const float* const* x_tab, bf16* x8, int images, int S, hipStream_t s) {
     const long long n = (long long)images * S * S;
-    FMBYM_LAUNCH(kMInput, k_input8, dim3(grid_for(n, 256)), dim3(256), s, x, x8, n);
+    FMBYM_LAUNCH(kMInput, k_input8, dim3(grid_for(n, 256)), dim3(256), s, x, x_tab, x8, n, S * S);
 }
 
 void launch_bn_stats(const float* part, int nb, int C, long long M, const float* gamma,

@@ -27,8 +27,9 @@ void wgrad_grid(int images, int S, int* blocks, int* tiles_per_block);
 
 // --- launchers (all asynchronous on s; shapes checked by the caller) -------
 
-// x [I][S][S] float -> [I][S][S][8] bf16 with the scan in channel 0, zeros elsewhere.
-void launch_input8(const float* x, bf16* x8, int images, int S, hipStream_t s);
+// x [I][S][S] float (or image i at x_tab[i] when x_tab is not null) -> [I][S][S][8]
+// bf16 with the scan in channel 0, zeros elsewhere.
+void launch_input8(const float* x, const float* const* x_tab, bf16* x8, int images, int S, hipStream_t s);
 
 // z = conv3x3(in, w) for (cin, cout) in the supported set; w packed [cout][9 cin]
 // bf16 (k = tap cin + ci, tap = 3 ky + kx).  With stats, z is bf16 and

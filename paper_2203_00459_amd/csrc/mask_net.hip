@@ -12,9 +12,9 @@
 #include <algorithm>
 #include <vector>
 
-#include "../../include/fmbym_mask.h"
 #include "internal.hpp"
 #include "mask_kernels.hpp"
+#include "mask_net.hpp"
 
 namespace fmbym {
 namespace {
@@ -241,50 +241,7 @@ size_t fmbym_mask_workspace_bytes(const fmbym_mask_desc* d, int32_t images, int3
 
 int fmbym_mask_fwd(const fmbym_mask_desc* d, int32_t I, int32_t n, const float* x, float* mask, void* act,
                    size_t act_bytes, int training, void* stream) {
-    Net net;
-    if (!d) return FMBYM_EINVAL;
-    if (!build_net(d, net)) return FMBYM_EUNSUPPORTED;
-    if (!size_ok(net, I, n)) return FMBYM_EUNSUPPORTED;
-    if (!x || !mask || !d->params || !d->packed || !d->bn_running) return FMBYM_EINVAL;
-    if (!(d->bn_eps > 0.f) || !(d->bn_momentum >= 0.f && d->bn_momentum <= 1.f)) return FMBYM_EINVAL;
-    const ActLayout A = act_layout(net, I, n);
-    if (!act || act_bytes < A.total) return FMBYM_EWORKSPACE;
-    hipStream_t s = (hipStream_t)stream;
-    const bf16* pk = (const bf16*)d->packed;
-    float* run_mean = d->bn_running;
-    float* run_var = d->bn_running + net.bn_channels;
-    launch_input8(x, at<bf16>(act, A.x8), I, n, s);
-    for (int j = 0; j <= net.last(); ++j) {
-        const ConvL& c = net.convs[j];
-        const int S = n >> c.level;
-        const bf16* in;
-        if (j == 0) {
-            in = at<bf16>(act, A.x8);
-        } else if (c.enc && c.first_of_level) {
-            launch_maxpool(at<bf16>(act, A.a[net.enc_b(c.level - 1)]), at<bf16>(act, A.pool[c.level]), I,
-                           n >> (c.level - 1), net.ch(c.level - 1), s);
-            in = at<bf16>(act, A.pool[c.level]);
-        } else if (!c.enc && c.first_of_level) {
-            launch_up_concat(at<bf16>(act, A.a[net.deeper(c.level)]), at<bf16>(act, A.a[net.enc_b(c.level)]),
-                             at<bf16>(act, A.cat[c.level]), I, S, net.ch(c.level + 1), net.ch(c.level), s);
-            in = at<bf16>(act, A.cat[c.level]);
-        } else {
-            in = at<bf16>(act, A.a[j - 1]);
-        }
-        if (!launch_conv3x3(c.cink, c.cout, true, in, pk + c.pf, at<bf16>(act, A.z[j]), at<float>(act, A.part),
-                            I, S, s))
-            return FMBYM_EUNSUPPORTED;
-        const long long M = (long long)I * S * S;
-        launch_bn_stats(at<float>(act, A.part), conv_blocks(I, S), c.cout, M, d->params + c.gamma,
-                        d->params + c.beta, net.eps, net.momentum, training ? 1 : 0, run_mean + c.bn,
-                        run_var + c.bn, at<float>(act, A.stat[j]), at<float>(act, A.tmp), s);
-        launch_bn_relu(at<bf16>(act, A.z[j]), at<float>(act, A.stat[j]), at<bf16>(act, A.a[j]), M, c.cout, s);
-    }
-    launch_head_fwd(at<bf16>(act, A.a[net.last()]), d->params + net.head_w, d->params + net.head_b, mask, I,
-                    n, net.base, s);
-    (void)hipMemcpyAsync(at<float>(act, A.mask), mask, (size_t)I * n * n * sizeof(float),
-                         hipMemcpyDeviceToDevice, s);
-    return finish(s);
+    return mask_forward(d, I, n, x, nullptr, mask, act, act_bytes, training, (hipStream_t)stream);
 }
 
 int fmbym_mask_bwd(const fmbym_mask_desc* d, int32_t I, int32_t n, const float* d_mask, const void* act,
@@ -376,3 +333,54 @@ int fmbym_pose_loss(int32_t batch, const float* pose, const float* target, int32
 }
 
 }  // extern "C"
+
+namespace fmbym {
+
+int mask_forward(const fmbym_mask_desc* d, int I, int n, const float* x, const float* const* x_tab,
+                 float* mask, void* act, size_t act_bytes, int training, hipStream_t s) {
+    Net net;
+    if (!d) return FMBYM_EINVAL;
+    if (!build_net(d, net)) return FMBYM_EUNSUPPORTED;
+    if (!size_ok(net, I, n)) return FMBYM_EUNSUPPORTED;
+    if ((!x && !x_tab) || !mask || !d->params || !d->packed || !d->bn_running) return FMBYM_EINVAL;
+    if (!(d->bn_eps > 0.f) || !(d->bn_momentum >= 0.f && d->bn_momentum <= 1.f)) return FMBYM_EINVAL;
+    const ActLayout A = act_layout(net, I, n);
+    if (!act || act_bytes < A.total) return FMBYM_EWORKSPACE;
+    const bf16* pk = (const bf16*)d->packed;
+    float* run_mean = d->bn_running;
+    float* run_var = d->bn_running + net.bn_channels;
+    launch_input8(x, x_tab, at<bf16>(act, A.x8), I, n, s);
+    for (int j = 0; j <= net.last(); ++j) {
+        const ConvL& c = net.convs[j];
+        const int S = n >> c.level;
+        const bf16* in;
+        if (j == 0) {
+            in = at<bf16>(act, A.x8);
+        } else if (c.enc && c.first_of_level) {
+            launch_maxpool(at<bf16>(act, A.a[net.enc_b(c.level - 1)]), at<bf16>(act, A.pool[c.level]), I,
+                           n >> (c.level - 1), net.ch(c.level - 1), s);
+            in = at<bf16>(act, A.pool[c.level]);
+        } else if (!c.enc && c.first_of_level) {
+            launch_up_concat(at<bf16>(act, A.a[net.deeper(c.level)]), at<bf16>(act, A.a[net.enc_b(c.level)]),
+                             at<bf16>(act, A.cat[c.level]), I, S, net.ch(c.level + 1), net.ch(c.level), s);
+            in = at<bf16>(act, A.cat[c.level]);
+        } else {
+            in = at<bf16>(act, A.a[j - 1]);
+        }
+        if (!launch_conv3x3(c.cink, c.cout, true, in, pk + c.pf, at<bf16>(act, A.z[j]), at<float>(act, A.part),
+                            I, S, s))
+            return FMBYM_EUNSUPPORTED;
+        const long long M = (long long)I * S * S;
+        launch_bn_stats(at<float>(act, A.part), conv_blocks(I, S), c.cout, M, d->params + c.gamma,
+                        d->params + c.beta, net.eps, net.momentum, training ? 1 : 0, run_mean + c.bn,
+                        run_var + c.bn, at<float>(act, A.stat[j]), at<float>(act, A.tmp), s);
+        launch_bn_relu(at<bf16>(act, A.z[j]), at<float>(act, A.stat[j]), at<bf16>(act, A.a[j]), M, c.cout, s);
+    }
+    launch_head_fwd(at<bf16>(act, A.a[net.last()]), d->params + net.head_w, d->params + net.head_b, mask, I,
+                    n, net.base, s);
+    (void)hipMemcpyAsync(at<float>(act, A.mask), mask, (size_t)I * n * n * sizeof(float),
+                         hipMemcpyDeviceToDevice, s);
+    return finish(s);
+}
+
+}  // namespace fmbym

@@ -1,8 +1,11 @@
 // Ragged work lists: pairs of mixed scan sizes searched as one replayable
-// launch.  Pairs are grouped by (n, masked) in size order; each group is the
-// batched forward search of its plan reading its scans through a per-pair
-// pointer table, followed by a small kernel that moves the group's poses to
-// the caller's order and stamps the device wall clock.  The groups are
+// launch.  Pairs are grouped by (n, mask kind) in size order, the kinds being
+// unmasked, caller masks and network masks; each group is the batched forward
+// search of its plan reading its scans through a per-pair pointer table
+// (network-masked groups first run the mask network in inference mode on
+// their 2 count scans, read through a second table), followed by a small kernel
+// that moves the group's poses to the caller's order and stamps the device
+// wall clock.  The groups are
 // independent branches of one HIP graph captured at creation, so the small
 // sizes do not wait behind the large ones and a replay costs one launch call.
 #include <algorithm>
@@ -10,19 +13,24 @@
 #include <vector>
 
 #include "internal.hpp"
+#include "mask_net.hpp"
 #include "profile.hpp"
 
 namespace fmbym {
 
 namespace {
 
+enum MaskKind { kUnmasked = 0, kGiven = 1, kNet = 2 };
+
 struct Group {
     const Plan* plan;
-    bool masked;
+    int kind;
     int first;          // first slot (row of the pointer table)
     int count;
     size_t ws_off;      // forward workspace of the group
     size_t pose_off;    // [count][3] float poses of the group
+    size_t act_off, act_bytes, mask_off;   // network groups: activations, masks [2 count][n][n]
+    int xtab_first;     // network groups: first row of the scan table (2 count rows)
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -30,7 +38,8 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // Validate the work list and lay out its groups; slots[] lists the pairs in
 // group order.  Returns FMBYM_OK or an error code; sets *bytes to the workspace.
 int plan_groups(const fmbym_plan* plans, int n_plans, const fmbym_pair* pairs, int n_pairs,
-                std::vector<Group>& groups, std::vector<int>& slots, size_t* bytes) {
+                const fmbym_mask_desc* net, std::vector<Group>& groups, std::vector<int>& slots,
+                size_t* bytes) {
     if (!plans || n_plans < 1 || n_plans > 64 || !pairs || n_pairs < 1 || n_pairs > (1 << 20))
         return FMBYM_EINVAL;
     for (int k = 0; k < n_plans; ++k) {
@@ -38,36 +47,54 @@ int plan_groups(const fmbym_plan* plans, int n_plans, const fmbym_pair* pairs, i
         for (int j = 0; j < k; ++j)
             if (plan_cast(plans[j])->p.n == plan_cast(plans[k])->p.n) return FMBYM_EINVAL;
     }
-    std::vector<int> plan_of(n_pairs);
+    std::vector<int> plan_of(n_pairs), kind(n_pairs);
     for (int i = 0; i < n_pairs; ++i) {
         const fmbym_pair& q = pairs[i];
-        if (q.reserved != 0 || !q.f || !q.g || (q.m_f == nullptr) != (q.m_g == nullptr))
+        if ((q.flags & ~FMBYM_PAIR_NET_MASK) || !q.f || !q.g || (q.m_f == nullptr) != (q.m_g == nullptr))
             return FMBYM_EINVAL;
+        if (q.flags & FMBYM_PAIR_NET_MASK) {
+            if (!net || q.m_f) return FMBYM_EINVAL;
+            kind[i] = kNet;
+        } else {
+            kind[i] = q.m_f ? kGiven : kUnmasked;
+        }
         plan_of[i] = -1;
         for (int k = 0; k < n_plans; ++k)
             if (plan_cast(plans[k])->p.n == q.n) plan_of[i] = k;
         if (plan_of[i] < 0) return FMBYM_EINVAL;
     }
-    // groups in increasing n, unmasked before masked; pairs keep their order
+    // groups in increasing n, then by mask kind; pairs keep their order
     std::vector<int> key(n_pairs);
-    for (int i = 0; i < n_pairs; ++i) key[i] = pairs[i].n * 2 + (pairs[i].m_f ? 1 : 0);
+    for (int i = 0; i < n_pairs; ++i) key[i] = pairs[i].n * 4 + kind[i];
     slots.resize(n_pairs);
     for (int i = 0; i < n_pairs; ++i) slots[i] = i;
     std::stable_sort(slots.begin(), slots.end(), [&](int a, int b) { return key[a] < key[b]; });
     groups.clear();
     size_t off = 0;
+    int xrows = 0;
     for (int s = 0; s < n_pairs;) {
         int e = s;
         while (e < n_pairs && key[slots[e]] == key[slots[s]]) ++e;
         Group gr{};
         gr.plan = plan_cast(plans[plan_of[slots[s]]]);
-        gr.masked = pairs[slots[s]].m_f != nullptr;
+        gr.kind = kind[slots[s]];
         gr.first = s;
         gr.count = e - s;
         gr.ws_off = off;
         off = align256(off + fwd_layout(gr.plan->p, gr.count).total);
         gr.pose_off = off;
         off = align256(off + (size_t)gr.count * 3 * sizeof(float));
+        if (gr.kind == kNet) {
+            const int n = gr.plan->p.n;
+            gr.act_bytes = fmbym_mask_activation_bytes(net, 2 * gr.count, n);
+            if (gr.act_bytes == 0) return FMBYM_EUNSUPPORTED;
+            gr.act_off = off;
+            off = align256(off + gr.act_bytes);
+            gr.mask_off = off;
+            off = align256(off + (size_t)2 * gr.count * n * n * sizeof(float));
+            gr.xtab_first = xrows;
+            xrows += 2 * gr.count;
+        }
         groups.push_back(gr);
         s = e;
     }
@@ -97,7 +124,9 @@ __global__ void k_ragged_poses(const float* __restrict__ pose_g, const int* __re
 struct Ragged {
     int device = 0;
     int n_pairs = 0;
-    const float** tab = nullptr;    // device [n_pairs][4] (f, g, m_f, m_g) in slot order
+    fmbym_mask_desc net{};          // copy of the network descriptor (network groups)
+    const float** tab = nullptr;    // device [n_pairs][4] (f, g, m_f, m_g) in slot order,
+                                    // then the network groups' scan rows
     int* slot_pair = nullptr;       // device [n_pairs] pair index of each slot
     std::vector<hipStream_t> streams;
     std::vector<hipEvent_t> events;
@@ -132,6 +161,12 @@ static int record_launch(Ragged& r, const std::vector<Group>& groups, float* pos
         e = hipStreamWaitEvent(sg, r.events[0], 0);
         if (e != hipSuccess) break;
         float* pose_g = (float*)(ws + gr.pose_off);
+        if (gr.kind == kNet) {
+            const int rc = mask_forward(&r.net, 2 * gr.count, gr.plan->p.n, nullptr,
+                                        r.tab + 4 * (size_t)r.n_pairs + gr.xtab_first,
+                                        (float*)(ws + gr.mask_off), ws + gr.act_off, gr.act_bytes, 0, sg);
+            if (rc) return rc;
+        }
         const int rc = launch_forward(*gr.plan, gr.count, nullptr, nullptr, nullptr, nullptr, pose_g,
                                       nullptr, nullptr, nullptr, ws + gr.ws_off, sg,
                                       r.tab + 4 * (size_t)gr.first);
@@ -152,23 +187,23 @@ using namespace fmbym;
 extern "C" {
 
 size_t fmbym_ragged_workspace_size(const fmbym_plan* plans, int32_t n_plans, const fmbym_pair* pairs,
-                                   int32_t n_pairs) {
+                                   int32_t n_pairs, const fmbym_mask_desc* net) {
     std::vector<Group> groups;
     std::vector<int> slots;
     size_t bytes = 0;
-    if (plan_groups(plans, n_plans, pairs, n_pairs, groups, slots, &bytes)) return 0;
+    if (plan_groups(plans, n_plans, pairs, n_pairs, net, groups, slots, &bytes)) return 0;
     return bytes;
 }
 
 int fmbym_ragged_create(const fmbym_plan* plans, int32_t n_plans, const fmbym_pair* pairs,
-                        int32_t n_pairs, float* pose, uint64_t* stamps, void* workspace,
-                        size_t workspace_bytes, fmbym_ragged* out) {
+                        int32_t n_pairs, const fmbym_mask_desc* net, float* pose, uint64_t* stamps,
+                        void* workspace, size_t workspace_bytes, fmbym_ragged* out) {
     if (!out) return FMBYM_EINVAL;
     *out = nullptr;
     std::vector<Group> groups;
     std::vector<int> slots;
     size_t bytes = 0;
-    int rc = plan_groups(plans, n_plans, pairs, n_pairs, groups, slots, &bytes);
+    int rc = plan_groups(plans, n_plans, pairs, n_pairs, net, groups, slots, &bytes);
     if (rc) return rc;
     if (!pose) return FMBYM_EINVAL;
     if (!workspace || workspace_bytes < bytes) return FMBYM_EWORKSPACE;
@@ -176,13 +211,28 @@ int fmbym_ragged_create(const fmbym_plan* plans, int32_t n_plans, const fmbym_pa
     Ragged* r = new (std::nothrow) Ragged();
     if (!r) return FMBYM_EINVAL;
     r->n_pairs = n_pairs;
-    std::vector<const float*> tab(4 * (size_t)n_pairs);
-    for (int s = 0; s < n_pairs; ++s) {
-        const fmbym_pair& q = pairs[slots[s]];
-        tab[4 * s] = q.f;
-        tab[4 * s + 1] = q.g;
-        tab[4 * s + 2] = q.m_f;
-        tab[4 * s + 3] = q.m_g;
+    if (net) r->net = *net;
+    size_t xrows = 0;
+    for (const Group& gr : groups)
+        if (gr.kind == kNet) xrows += 2 * (size_t)gr.count;
+    std::vector<const float*> tab(4 * (size_t)n_pairs + xrows);
+    for (const Group& gr : groups) {
+        const int n = gr.plan->p.n;
+        for (int b = 0; b < gr.count; ++b) {
+            const int s = gr.first + b;
+            const fmbym_pair& q = pairs[slots[s]];
+            tab[4 * s] = q.f;
+            tab[4 * s + 1] = q.g;
+            tab[4 * s + 2] = q.m_f;
+            tab[4 * s + 3] = q.m_g;
+            if (gr.kind == kNet) {
+                const float* masks = (const float*)((const char*)workspace + gr.mask_off);
+                tab[4 * s + 2] = masks + (size_t)b * n * n;                 // network mask of f
+                tab[4 * s + 3] = masks + (size_t)(gr.count + b) * n * n;    // and of g
+                tab[4 * (size_t)n_pairs + gr.xtab_first + b] = q.f;
+                tab[4 * (size_t)n_pairs + gr.xtab_first + gr.count + b] = q.g;
+            }
+        }
     }
     hipError_t e = hipGetDevice(&r->device);
     if (e == hipSuccess) e = hipMalloc((void**)&r->tab, sizeof(const float*) * tab.size());

@@ -58,9 +58,12 @@ class fmbym_params(ctypes.Structure):
     ]
 
 
+FMBYM_PAIR_NET_MASK = 1
+
+
 class fmbym_pair(ctypes.Structure):
     _fields_ = [
-        ("n", ctypes.c_int32), ("reserved", ctypes.c_int32), ("f", ctypes.c_void_p),
+        ("n", ctypes.c_int32), ("flags", ctypes.c_uint32), ("f", ctypes.c_void_p),
         ("g", ctypes.c_void_p), ("m_f", ctypes.c_void_p), ("m_g", ctypes.c_void_p),
     ]
 
@@ -113,9 +116,9 @@ def lib() -> ctypes.CDLL:
                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I32)]
         L.fmbym_profile_read.restype = ctypes.c_int
         PP = ctypes.POINTER(fmbym_pair)
-        L.fmbym_ragged_workspace_size.argtypes = [ctypes.POINTER(VP), I32, PP, I32]
+        L.fmbym_ragged_workspace_size.argtypes = [ctypes.POINTER(VP), I32, PP, I32, VP]
         L.fmbym_ragged_workspace_size.restype = SZ
-        L.fmbym_ragged_create.argtypes = [ctypes.POINTER(VP), I32, PP, I32, VP, VP, VP, SZ,
+        L.fmbym_ragged_create.argtypes = [ctypes.POINTER(VP), I32, PP, I32, VP, VP, VP, VP, SZ,
                                           ctypes.POINTER(VP)]
         L.fmbym_ragged_create.restype = ctypes.c_int
         L.fmbym_ragged_launch.argtypes = [VP, VP]
@@ -218,14 +221,16 @@ def _plan_array(plans):
     return arr
 
 
-def ragged_workspace_size(plans, pairs) -> int:
-    """plans: plan handles; pairs: a ctypes array of fmbym_pair."""
-    return int(lib().fmbym_ragged_workspace_size(_plan_array(plans), len(plans), pairs, len(pairs)))
+def ragged_workspace_size(plans, pairs, net=None) -> int:
+    """plans: plan handles; pairs: a ctypes array of fmbym_pair; net: fmbym_mask_desc or None."""
+    return int(lib().fmbym_ragged_workspace_size(_plan_array(plans), len(plans), pairs, len(pairs),
+                                                 None if net is None else ctypes.addressof(net)))
 
 
-def ragged_create(plans, pairs, pose, stamps, workspace, workspace_bytes) -> ctypes.c_void_p:
+def ragged_create(plans, pairs, pose, stamps, workspace, workspace_bytes, net=None) -> ctypes.c_void_p:
     h = ctypes.c_void_p()
-    rc = lib().fmbym_ragged_create(_plan_array(plans), len(plans), pairs, len(pairs), pose, stamps,
+    rc = lib().fmbym_ragged_create(_plan_array(plans), len(plans), pairs, len(pairs),
+                                   None if net is None else ctypes.addressof(net), pose, stamps,
                                    workspace, int(workspace_bytes), ctypes.byref(h))
     if rc:
         raise FmbymError(rc, "fmbym_ragged_create")
@@ -353,27 +358,37 @@ class Ragged:
     """A ragged work list (pairs of mixed sizes) as one replayable launch.
 
     ``searches`` are Search objects with distinct n; ``pairs`` is a list of
-    (f, g) or (f, g, m_f, m_g) device tensors, each [n, n] for one of those n.
-    The tensors must stay alive and in place: every launch reads them anew.
-    ``pose`` [P, 3] and ``stamps`` [P + 1] (int64 wall-clock ticks, the last one
-    the launch start) are refreshed by every launch.
+    (f, g), (f, g, m_f, m_g) or (f, g, "net") device tensors, each [n, n] for
+    one of those n; "net" takes the masks from ``net`` (a MaskNet, run in
+    inference mode inside the launch).  The tensors must stay alive and in
+    place: every launch reads them anew.  ``pose`` [P, 3] and ``stamps`` [P + 1]
+    (int64 wall-clock ticks, the last one the launch start) are refreshed by
+    every launch.
     """
 
-    def __init__(self, searches, pairs, stamps: bool = True):
+    def __init__(self, searches, pairs, stamps: bool = True, net: "MaskNet | None" = None):
         self.searches = list(searches)
+        self.net = net
         self._keep = []
         arr = (fmbym_pair * len(pairs))()
         dev = None
         for i, q in enumerate(pairs):
             f, g = q[0], q[1]
-            m_f, m_g = (q[2], q[3]) if len(q) > 2 else (None, None)
             n = f.shape[-1]
-            arr[i] = fmbym_pair(n, 0, _ptr(f, (n, n), "f"), _ptr(g, (n, n), "g"),
-                                _ptr(m_f, (n, n), "m_f"), _ptr(m_g, (n, n), "m_g"))
+            if len(q) == 3 and isinstance(q[2], str):
+                if q[2] != "net" or net is None:
+                    raise ValueError("a (f, g, 'net') pair needs the net argument")
+                arr[i] = fmbym_pair(n, FMBYM_PAIR_NET_MASK, _ptr(f, (n, n), "f"), _ptr(g, (n, n), "g"),
+                                    None, None)
+            else:
+                m_f, m_g = (q[2], q[3]) if len(q) > 2 else (None, None)
+                arr[i] = fmbym_pair(n, 0, _ptr(f, (n, n), "f"), _ptr(g, (n, n), "g"),
+                                    _ptr(m_f, (n, n), "m_f"), _ptr(m_g, (n, n), "m_g"))
             self._keep.append(q)
             dev = f.device
         plans = [s.plan for s in self.searches]
-        need = ragged_workspace_size(plans, arr)
+        desc = None if net is None else net.desc
+        need = ragged_workspace_size(plans, arr, desc)
         if need == 0:
             raise FmbymError(FMBYM_EINVAL, "fmbym_ragged_workspace_size")
         self.workspace = torch.empty(need, dtype=torch.uint8, device=dev)
@@ -381,7 +396,7 @@ class Ragged:
         self.stamps = torch.zeros(len(pairs) + 1, dtype=torch.int64, device=dev) if stamps else None
         self.handle = ragged_create(plans, arr, self.pose.data_ptr(),
                                     None if self.stamps is None else self.stamps.data_ptr(),
-                                    self.workspace.data_ptr(), need)
+                                    self.workspace.data_ptr(), need, desc)
 
     def launch(self) -> torch.Tensor:
         ragged_launch(self.handle, _stream())

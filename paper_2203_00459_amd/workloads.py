@@ -21,6 +21,9 @@ SEARCH = {
 RAGGED = {
     # 1024 pairs: half 128 x 128, 30 % 256 x 256, 20 % 512 x 512, each with its size's parameters
     "ragged1024": dict(n_pairs=1024, mix=(("pair128", 0.5), ("batch256", 0.3), ("batch512", 0.2))),
+    # the same list with every pair masked by the 4-level mask network inside the launch
+    "ragged1024_masked": dict(n_pairs=1024, mix=(("pair128", 0.5), ("batch256", 0.3), ("batch512", 0.2)),
+                              mask="net"),
 }
 
 # Mask-network training: batch of pairs with distractors, the 4-level network.

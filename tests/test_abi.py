@@ -81,14 +81,14 @@ def test_calls_without_a_plan_are_rejected():
 def test_ragged_calls_reject_bad_arguments():
     L = fmbym.lib()
     pairs = (fmbym.fmbym_pair * 1)()
-    assert L.fmbym_ragged_workspace_size(None, 1, pairs, 1) == 0
+    assert L.fmbym_ragged_workspace_size(None, 1, pairs, 1, None) == 0
     plans = (ctypes.c_void_p * 1)()
-    assert L.fmbym_ragged_workspace_size(plans, 1, pairs, 1) == 0        # null plan
-    assert L.fmbym_ragged_workspace_size(plans, 0, pairs, 1) == 0
+    assert L.fmbym_ragged_workspace_size(plans, 1, pairs, 1, None) == 0        # null plan
+    assert L.fmbym_ragged_workspace_size(plans, 0, pairs, 1, None) == 0
     h = ctypes.c_void_p()
-    assert L.fmbym_ragged_create(None, 1, pairs, 1, None, None, None, 0,
+    assert L.fmbym_ragged_create(None, 1, pairs, 1, None, None, None, None, 0,
                                  ctypes.byref(h)) == fmbym.FMBYM_EINVAL
-    assert L.fmbym_ragged_create(plans, 1, pairs, 1, None, None, None, 0, None) == fmbym.FMBYM_EINVAL
+    assert L.fmbym_ragged_create(plans, 1, pairs, 1, None, None, None, None, 0, None) == fmbym.FMBYM_EINVAL
     assert L.fmbym_ragged_launch(None, None) == fmbym.FMBYM_EINVAL
     assert L.fmbym_ragged_destroy(None) == fmbym.FMBYM_EINVAL
     assert L.fmbym_wall_clock_khz(None) == fmbym.FMBYM_EINVAL

@@ -117,6 +117,39 @@ def test_ragged_pair_against_the_oracle():
     r.close()
 
 
+def test_ragged_network_masks_equal_the_eager_chain():
+    """Pairs flagged for network masks: the mask network (inference mode) runs
+    inside the launch and the search uses its masks; the pose equals the eager
+    MaskNet forward + masked search bit for bit, next to unmasked pairs."""
+    from paper_2203_00459_amd.train import he_init
+    searches = _searches()
+    net = fmbym.MaskNet(he_init(4, 8, seed=4), levels=4)
+    nbn = net.bn_running.numel() // 2
+    rng = np.random.Generator(np.random.PCG64(8))
+    net.bn_running.copy_(torch.tensor(np.concatenate([rng.normal(0, 0.3, nbn), rng.uniform(0.5, 2, nbn)]),
+                                      dtype=torch.float32))
+    names = ["pair128", "batch256", "pair128", "batch512", "pair128", "batch256"]
+    base = _work_list(names)
+    pairs = [(q[0], q[1], "net") if i % 2 == 0 else (q[0], q[1]) for i, q in enumerate(base)]
+    r = fmbym.Ragged([searches[k] for k in SIZES], pairs, net=net)
+    for rep in range(2):
+        pose = r.launch().clone()
+        torch.cuda.synchronize()
+        ref = torch.empty_like(pose)
+        for i, (name, q) in enumerate(zip(names, base)):
+            s = searches[name]
+            if i % 2 == 0:
+                m = net.forward(torch.stack([q[0], q[1]]), training=False)
+                ref[i] = s.forward(q[0][None], q[1][None], m[0:1].contiguous(), m[1:2].contiguous(),
+                                   surfaces=False)["pose"][0]
+            else:
+                ref[i] = s.forward(q[0][None], q[1][None], surfaces=False)["pose"][0]
+        torch.cuda.synchronize()
+        print(f"net-masked ragged replay {rep}: max |diff| {(pose - ref).abs().max().item()}", flush=True)
+        assert torch.equal(pose, ref)
+    r.close()
+
+
 def test_ragged_rejects_a_size_without_a_plan():
     searches = _searches()
     pairs = _work_list(["pair128", "batch256"])
