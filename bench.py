@@ -36,25 +36,31 @@ def kernel_bytes(n: int, n_theta: int, n_r: int, batch: int, masked: bool) -> di
     half = 2 * n * (n // 2) * 8            # both half spectra, complex64
     mag = 2 * n * (n // 2 + 1) * 4          # both magnitude half-planes, float32
     polar = 2 * n_r * n_theta * 4           # both polar adjoints, float32
+    h2 = 3 * n // 4 + 1                     # unique columns of the 3n/2-point stage-2 rows
+    rows2 = n * h2 * 16                     # stage-2 row spectra (F, G'), complex64 pairs
+    lag = n * h2 * 8                        # stage-2 lag rows, complex64
     return {
         # forward
         "k_rows1": batch * (m * 2 * 4 * N2 + half),
         "k_cols1": batch * (half + mag),
         "k_polar": batch * (mag + nrb * hk * 8),
         "k_angle_fin": batch * (nrb * hk * 8 + n_theta * 4),
-        "k_rows2": batch * (m * 2 * 4 * N2 + 2 * N2 * 8),
-        "k_cols2": batch * (2 * N2 * 8 + N2 * 8),
-        "k_rows3": batch * (N2 * 8 + N2 * 4),
+        # k_rotate runs twice per step: forward (g' only) and adjoint (g' and d g'/d theta)
+        "k_rotate": batch * (m * 4 * N2 + 6 * N2),
+        "k_rows2": batch * (m * 4 * N2 + 4 * N2 + rows2),
+        "k_cols2": batch * (rows2 + lag),
+        "k_rows3": batch * (lag + N2 * 4),
         "k_xy_fin": batch * 64,
         # adjoint (k_rows1 and k_cols1 run again to recompute the stage-1 spectra)
-        "kb_rows_fwd2": batch * (m * 2 * 4 * N2 + 4 * N2 + 3 * N2 * 8),
-        "kb_cols_xy": batch * (3 * N2 * 8 + 2 * N2 * 8),
-        "kb_rows_xy": batch * (2 * N2 * 8 + m * 4 * N2 + 2 * N2 * 4),
+        "kb_rows_fwd2": batch * (m * 4 * N2 + 4 * N2 + 4 * N2 + rows2 + lag),
+        "kb_cols_xy": batch * (rows2 + lag + rows2),
+        "kb_rows_xy": batch * (rows2 + 4 * N2 + 2 * N2 * 4),
+        "kb_rotate_adj": batch * (4 * N2 + 4 * N2),
         "kb_dtheta": batch * (n_theta * 4 + n_theta * 8),
         "kb_polar": batch * (mag + polar),
         "kb_dmag": batch * (polar + mag),
         "kb_cols_mag": batch * (half + mag + half),
-        "kb_rows_final": batch * (half + 2 * N2 * 4 + m * 2 * 4 * N2 + m * 2 * N2 * 4),
+        "kb_rows_final": batch * (half + 2 * N2 * 4 + m * 2 * 4 * N2 + 2 * N2 * 4 + (m - 1) * 2 * N2 * 4),
     }
 
 
@@ -240,7 +246,8 @@ def ragged_bench(args) -> int:
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / args.steps
     lat = r.latencies_us().numpy()
-    fwd = ("k_rows1", "k_cols1", "k_polar", "k_angle_fin", "k_rows2", "k_cols2", "k_rows3", "k_xy_fin")
+    fwd = ("k_rows1", "k_cols1", "k_polar", "k_angle_fin", "k_rows2", "k_cols2", "k_rows3", "k_xy_fin",
+           "k_rotate")
     nbytes = 0
     for k in sizes:
         kw = workloads.search_kwargs(k)
@@ -312,7 +319,7 @@ def search_bench(args) -> int:
         src = torch.empty(args.copy_probe_mb << 18, device=dev)        # MiB of float32
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.mul(src, 1.0, out=dst)   # a plain read+write kernel of known size
         torch.cuda.synchronize()
         del src, dst
 

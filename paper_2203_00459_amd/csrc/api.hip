@@ -42,7 +42,7 @@ int check_params(const fmbym_params* p) {
 
 hipError_t free_plan_tables(Plan* pl) {
     hipError_t first = hipSuccess;
-    void* ptrs[] = {pl->twiddle, pl->hann, pl->csr_ptr, pl->csr_col, pl->csr_val, pl->csr_dst, pl->dmag_part};
+    void* ptrs[] = {pl->twiddle, pl->twiddle3, pl->hann, pl->csr_ptr, pl->csr_col, pl->csr_val, pl->csr_dst, pl->dmag_part};
     for (void* q : ptrs) {
         if (!q) continue;
         hipError_t e = hipFree(q);
@@ -76,10 +76,14 @@ int fmbym_plan_create(const fmbym_params* p, int32_t max_batch, fmbym_plan* out)
         delete pl;
         return hip_fail(e);
     }
-    float2 tw[kTwiddleLen];
+    float2 tw[kTwiddleLen], tw3[kTwiddleLen3];
     for (int m = 0; m < kTwiddleLen; ++m) {
         const double a = -2.0 * M_PI * (double)m / (double)kTwiddleLen;
         tw[m] = make_float2((float)cos(a), (float)sin(a));
+    }
+    for (int m = 0; m < kTwiddleLen3; ++m) {
+        const double a = -2.0 * M_PI * (double)m / (double)kTwiddleLen3;
+        tw3[m] = make_float2((float)cos(a), (float)sin(a));
     }
     float* hann = new (std::nothrow) float[p->n];
     if (!hann) {
@@ -94,6 +98,8 @@ int fmbym_plan_create(const fmbym_params* p, int32_t max_batch, fmbym_plan* out)
         pl->band_hi2 = (int)floor(hi * hi);
     }
     e = hipMalloc((void**)&pl->twiddle, sizeof(tw));
+    if (e == hipSuccess) e = hipMalloc((void**)&pl->twiddle3, sizeof(tw3));
+    if (e == hipSuccess) e = hipMemcpy(pl->twiddle3, tw3, sizeof(tw3), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMalloc((void**)&pl->hann, sizeof(float) * p->n);
     if (e == hipSuccess) e = hipMemcpy(pl->twiddle, tw, sizeof(tw), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(pl->hann, hann, sizeof(float) * p->n, hipMemcpyHostToDevice);

@@ -1,7 +1,8 @@
-// Device-side building blocks of the search kernels: complex helpers, radix-2/4/8
-// butterflies and a Stockham autosort FFT over one "line" held cooperatively by
-// T threads, each owning E = L/T elements in registers.  Lines exchange data
-// between stages through a padded LDS buffer (separate re/im planes).
+// Device-side building blocks of the search kernels: complex helpers, radix-2/3/4/8
+// butterflies and a Stockham autosort FFT over one "line" of L = 2^a or 3 2^a
+// points held cooperatively by T threads, each owning E = L/T elements in
+// registers.  Lines exchange data between stages through a padded LDS buffer
+// (separate re/im planes).
 //
 // Register layout, on entry and on exit: thread t holds element t + m*T in v[m].
 // This is the layout of a coalesced global load/store of the line, so row
@@ -13,7 +14,12 @@
 
 namespace fmbym {
 
-constexpr int kTwiddleLen = 2048;   // table holds W_2048^m = exp(-2 pi i m / 2048)
+// Twiddle tables: W_2048^m for lines of 2^a points and W_3072^m for lines of
+// 3 2^a points (each small enough to stay in the vector L1 cache).
+constexpr int kTwiddleLen = 2048;
+constexpr int kTwiddleLen3 = 3072;
+template <int L>
+constexpr int twiddle_len() { return (L & (L - 1)) == 0 ? kTwiddleLen : kTwiddleLen3; }
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
@@ -64,8 +70,22 @@ __device__ __forceinline__ void dft8(float2 (&v)[8]) {
     v[7] = csub(e3, w3);
 }
 
+// X1 = a + W b + W^2 c, X2 = a + W^2 b + W c with W = exp(-2 pi i / 3).
+__device__ __forceinline__ void dft3(float2& a, float2& b, float2& c) {
+    const float h = 0.86602540378443864676f;   // sqrt(3) / 2
+    const float2 s = cadd(b, c);
+    const float2 m = make_float2(a.x - 0.5f * s.x, a.y - 0.5f * s.y);
+    const float2 d = csub(b, c);
+    const float2 r = make_float2(h * d.y, -h * d.x);   // -i (sqrt(3)/2) (b - c)
+    a = cadd(a, s);
+    b = cadd(m, r);
+    c = csub(m, r);
+}
+
 template <int R>
 __device__ __forceinline__ void dft_r(float2 (&v)[R]);
+template <>
+__device__ __forceinline__ void dft_r<3>(float2 (&v)[3]) { dft3(v[0], v[1], v[2]); }
 template <>
 __device__ __forceinline__ void dft_r<2>(float2 (&v)[2]) { dft2(v[0], v[1]); }
 template <>
@@ -94,25 +114,39 @@ struct LdsCols {
     }
 };
 
-constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
+// Power-of-two factor of x = 2^a or 3 2^a.
+constexpr int pow2_part(int x) { return (x & (x - 1)) == 0 ? x : pow2_part(x / 3); }
+// Largest power-of-two radix (at most 8) that divides the per-thread count E.
+constexpr int max_pow2_radix(int E) { return E % 8 == 0 ? 8 : (E % 4 == 0 ? 4 : 2); }
 
-// Radix of stage s for a length-L line with E elements per thread: radix E
-// while it divides what is left, the remainder (2 or 4) last.
+// Radix plan of a length-L line with E elements per thread: power-of-two
+// stages of radix min(max_pow2_radix(E), what is left of 2^a), then one radix-3
+// stage for lengths 3 2^a.  Every radix divides E.
 template <int L, int E, int S>
 struct StageRadix {
     static constexpr int done = StageRadix<L, E, S - 1>::done * StageRadix<L, E, S - 1>::R;
     static constexpr int left = L / done;
-    static constexpr int R = left >= E ? E : left;
+    static constexpr int p2 = pow2_part(left);
+    static constexpr int R = p2 > 1 ? (p2 < max_pow2_radix(E) ? p2 : max_pow2_radix(E)) : left;
 };
 template <int L, int E>
 struct StageRadix<L, E, 0> {
     static constexpr int done = 1;
     static constexpr int left = L;
-    static constexpr int R = L >= E ? E : L;
+    static constexpr int p2 = pow2_part(L);
+    static constexpr int R = p2 > 1 ? (p2 < max_pow2_radix(E) ? p2 : max_pow2_radix(E)) : L;
+};
+template <int L, int E, int S = 0, bool END = (StageRadix<L, E, S>::done == L)>
+struct NumStagesFrom {
+    static constexpr int value = 1 + NumStagesFrom<L, E, S + 1>::value;
+};
+template <int L, int E, int S>
+struct NumStagesFrom<L, E, S, true> {
+    static constexpr int value = 0;
 };
 template <int L, int E>
 struct NumStages {
-    static constexpr int value = (ilog2c(L) + ilog2c(E) - 1) / ilog2c(E);
+    static constexpr int value = NumStagesFrom<L, E>::value;
 };
 
 // One Stockham stage.  FIRST reads the inputs from registers, LAST writes the
@@ -125,6 +159,7 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[E], float* re, float* im, 
     constexpr int Ns = StageRadix<L, E, S>::done;
     constexpr int Q = E / R;          // butterflies per thread
     constexpr int LR = L / R;
+    static_assert(E % R == 0 && (Ns & (Ns - 1)) == 0, "radix divides E; the radix-3 stage comes last");
     float2 out[Q][R];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -141,7 +176,7 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[E], float* re, float* im, 
         }
         if (Ns > 1) {   // W^r for r < R from one table read, products at most 3 deep
             const int k = j & (Ns - 1);
-            constexpr int step = kTwiddleLen / (Ns * R);
+            constexpr int step = twiddle_len<L>() / (Ns * R);
             float2 w[R];
             w[1] = tw[k * step];
 #pragma unroll
@@ -190,12 +225,14 @@ struct FFTStages<L, E, NS, NS, Lay> {
 };
 
 // Forward DFT of one line, in registers.  All threads of the block must call
-// it (it contains block barriers) even if their line is padding.
+// it (it contains block barriers) even if their line is padding.  tw is the
+// table of twiddle_len<L>() entries.
 template <int L, int E, class Lay = LdsRows>
 __device__ __forceinline__ void fft_line(float2 (&v)[E], float* re, float* im, int t,
                                          const float2* __restrict__ tw) {
-    static_assert((L & (L - 1)) == 0 && L >= 2 && L <= kTwiddleLen, "power-of-two length");
-    static_assert(E == 2 || E == 4 || E == 8, "elements per thread");
+    static_assert(pow2_part(L) * (pow2_part(L) == L ? 1 : 3) == L && L >= 2 && twiddle_len<L>() % L == 0,
+                  "length 2^a or 3 2^a dividing its twiddle table");
+    static_assert(E == 2 || E == 4 || E == 8 || E == 12 || E == 24, "elements per thread");
     FFTStages<L, E, 0, NumStages<L, E>::value, Lay>::run(v, re, im, t, tw);
 }
 
@@ -228,7 +265,7 @@ __device__ __forceinline__ void mirror_line(const float2 (&v)[E], float2 (&mir)[
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         const int k = t + m * T;
-        const int idx = Lay::at((L - k) & (L - 1));
+        const int idx = Lay::at(k == 0 ? 0 : L - k);
         mir[m] = make_float2(re[idx], im[idx]);
     }
 }

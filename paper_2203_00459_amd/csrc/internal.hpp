@@ -30,6 +30,7 @@ struct Plan {
     int32_t max_batch;
     int device;
     float2* twiddle;   // [kTwiddleLen] W_2048^m
+    float2* twiddle3;  // [kTwiddleLen3] W_3072^m (stage-2 lines of 3n/2 points)
     float* hann;       // [n] periodic Hann, FP64-evaluated, rounded once
     int band_on;
     int band_lo2;      // keep ceil((lo n)^2) <= ky^2 + kx^2 <= floor((hi n)^2)
@@ -63,21 +64,26 @@ int hip_fail(hipError_t e);
 constexpr int kRadiiPerBlock = 8;
 inline int radius_blocks(int n_r) { return (n_r + kRadiiPerBlock - 1) / kRadiiPerBlock; }
 
+// Stage 2 correlates zero-padded scans of length pad2(n) = 3n/2 per axis: the
+// smallest length at which the circular correlation equals the linear one for
+// every lag of the window [-n/2, n/2) (a wrapped index lands in the zero
+// padding).  Its lines use kE2 = 12 elements per thread: radix 4, 4, ..., 3.
+__host__ __device__ constexpr int pad2(int n) { return 3 * n / 2; }
+constexpr int kE2 = 12;
+
 // Row pitches, in elements.  Every row array keeps its unique columns
-// (n/2 + 1 in stage 1, n + 1 in stage 2) plus room for the last, partial
+// (n/2 + 1 in stage 1, 3n/4 + 1 in stage 2) plus room for the last, partial
 // column tile of the column kernels (at most kPitchPad columns wide).
 constexpr int kPitchPad = 16;
-__host__ __device__ constexpr int pitch_rows1(int n) { return n / 2 + kPitchPad; }  // float4 (F_f, F_g)
-__host__ __device__ constexpr int pitch_mag(int n) { return n / 2 + kPitchPad; }    // float2 (A_f, A_g)
-__host__ __device__ constexpr int pitch_rows2(int n) { return n + kPitchPad; }      // float4 (F, G')
-__host__ __device__ constexpr int pitch_lag(int n) { return n + kPitchPad; }        // float2
+__host__ __device__ constexpr int pitch_rows1(int n) { return n / 2 + kPitchPad; }      // float4 (F_f, F_g)
+__host__ __device__ constexpr int pitch_mag(int n) { return n / 2 + kPitchPad; }        // float2 (A_f, A_g)
+__host__ __device__ constexpr int pitch_rows2(int n) { return 3 * n / 4 + kPitchPad; }  // float4 (F, G')
+__host__ __device__ constexpr int pitch_lag(int n) { return 3 * n / 4 + kPitchPad; }    // float2
 
-// Rows per block of the stage-2 inverse-row kernel's softmax partials.
-inline int xy_partials_per_pair(int n) {
-    const int t = (2 * n) / 8;                 // threads per line
-    const int lines = 256 / t < 1 ? 1 : 256 / t;
-    return (n / 2) / lines;
-}
+// Lines per 256-thread block of a stage-2 row kernel, and the softmax
+// partials per pair of the inverse-row kernel (one per block of lag-row pairs).
+__host__ __device__ constexpr int rows2_lines(int n) { return 256 / (pad2(n) / kE2); }
+inline int xy_partials_per_pair(int n) { return (n / 2) / rows2_lines(n); }
 
 // Workspace carve-up shared by forward and backward launchers.
 struct FwdLayout {
@@ -86,6 +92,7 @@ struct FwdLayout {
     size_t ptheta;    // [B][radius_blocks][n_theta/2 + 1] float2
     size_t pxy;       // [B][xy_partials] float4
     size_t saved;     // [B][FMBYM_SAVED] float (used when the caller passes none)
+    size_t grot;      // [B][n][n] float: g' = Rotate(g_w), the rotated stage-2 scan
     size_t total;
 };
 FwdLayout fwd_layout(const fmbym_params& p, int batch);
@@ -164,6 +171,41 @@ __device__ __forceinline__ float rotate_sample(const float* __restrict__ g, cons
     }
     return acc;
 }
+
+// d g'(i, j) / d theta: the bilinear gradient of g_w at the sample position
+// times the derivative of the position, R'(theta) y.
+__device__ __forceinline__ float rotate_dtheta(const float* __restrict__ g, const float* __restrict__ m,
+                                               const float* __restrict__ hann, int n, int i, int j,
+                                               float ct, float st, bool win) {
+    float py, px;
+    rot_src(n, i, j, ct, st, py, px);
+    const float fy = floorf(py), fx = floorf(px);
+    const float wy = py - fy, wx = px - fx;
+    const int y0 = (int)fy, x0 = (int)fx;
+    float G[2][2];
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx) {
+            const int r = y0 + dy, c = x0 + dx;
+            G[dy][dx] = (r >= 0 && r < n && c >= 0 && c < n) ? scan_w(g, m, hann, n, r, c, win) : 0.f;
+        }
+    const float gx = (1.f - wy) * (G[0][1] - G[0][0]) + wy * (G[1][1] - G[1][0]);
+    const float gy = (1.f - wx) * (G[1][0] - G[0][0]) + wx * (G[1][1] - G[0][1]);
+    const float yx = (float)(j - n / 2), yy = (float)(i - n / 2);
+    return gx * (-st * yx - ct * yy) + gy * (ct * yx - st * yy);
+}
+
+// Output tiles of the rotation kernels and the side of the LDS box that holds
+// the source pixels of one tile at any angle.
+constexpr int kRotTY = 16, kRotTX = 64;
+constexpr int kRotBox = 72;   // > sqrt(kRotTX^2 + kRotTY^2) + 6
+
+// Rotate g_w by the pair's heading into gr (and its theta derivative into jac
+// when not null), one pixel per thread: the gathers run in a kernel of their
+// own so that their latency is hidden by many light waves.
+void launch_rotate(const Plan& pl, int batch, const float* g, const float* mg, const float* saved,
+                   float* gr, float* jac, int win, hipStream_t s, const float* const* tab);
 
 // Polar sample (radius b, angle a): frequency u = rho (cos phi, sin phi) in bins.
 __device__ __forceinline__ void polar_uv(const float2* __restrict__ tw, int n, int n_r, int n_theta,

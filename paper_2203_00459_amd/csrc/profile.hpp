@@ -10,7 +10,7 @@ enum KernelId {
     kKRows1 = 0, kKCols1, kKPolar, kKAngleFin, kKRows2, kKCols2, kKRows3, kKXyFin,
     kKBRowsFwd2, kKBColsXy, kKBRowsXy, kKBDtheta, kKBPolar, kKBDmag, kKBColsMag, kKBRowsFinal,
     kMInput, kMConvFwd, kMBnStats, kMBnRelu, kMPool, kMUpCat, kMHeadFwd, kMHeadBwd, kMBnBwd, kMWgrad,
-    kMConvDgrad, kMPoolBwd, kMUpBwd, kMPack, kMAdam, kMLoss,
+    kMConvDgrad, kMPoolBwd, kMUpBwd, kMPack, kMAdam, kMLoss, kKRotate, kKBRotateAdj,
     kKernelCount
 };
 

@@ -63,37 +63,37 @@ __device__ __forceinline__ XyAdj make_xy_adj(const float* sv, const float* dp, f
 
 // ------------------------------------------------------ translation adjoint
 
-// Blocks [0, B n / LPB) transform rows of f2 + i g' (-> rf, float4 (F, G'));
-// the rest transform pairs of dc_xy lag rows (-> rdc, float2).  Columns 0 .. n
-// of the 2n-point row spectra are kept.
+// Blocks [0, B n / LPB) transform rows of f2 + i g' (g' read from gr; -> rf, float4 (F, G'));
+// the rest transform pairs of dc_xy lag rows (-> rdc, float2).  Columns 0 .. 3n/4
+// of the 3n/2-point row spectra are kept.
 template <int N>
 __global__ __launch_bounds__(256) void kb_rows_fwd2(
     const float* __restrict__ f, const float* __restrict__ g, const float* __restrict__ mf,
     const float* __restrict__ mg, const float* __restrict__ hann, const float2* __restrict__ tw,
     const float* __restrict__ saved, const float* __restrict__ c_xy, const float* __restrict__ d_pose,
-    float4* __restrict__ rf, float2* __restrict__ rdc, int win, int batch, float temp, float delta) {
-    constexpr int L = 2 * N, T = L / kEb, LPB = 256 / T, P2 = pitch_rows2(N), P3 = pitch_lag(N);
+    const float* __restrict__ gr, float4* __restrict__ rf, float2* __restrict__ rdc, int win, int batch,
+    float temp, float delta) {
+    constexpr int L = pad2(N), E = kE2, T = L / E, LPB = 256 / T, H = L / 2, P2 = pitch_rows2(N),
+                  P3 = pitch_lag(N);
     __shared__ float lre[LPB][LdsRows::words(L)];
     __shared__ float lim[LPB][LdsRows::words(L)];
     const int line = threadIdx.x / T, t = threadIdx.x % T;
     const int nscan_blocks = batch * N / LPB;
     const bool scan_rows = (int)blockIdx.x < nscan_blocks;   // block-uniform
-    float2 v[kEb];
+    float2 v[E];
     int grow = 0, gl = 0, b = 0, q = 0;
     if (scan_rows) {
         grow = blockIdx.x * LPB + line;
         b = grow / N;
         const int i = grow % N;
         const size_t base = (size_t)b * N * N;
-        const float* sv = saved + (size_t)b * FMBYM_SAVED;
-        const float ct = sv[kSavedCos], st = sv[kSavedSin];
+        const float* grow_g = gr + (size_t)grow * N;
 #pragma unroll
-        for (int m = 0; m < kEb; ++m) {
+        for (int m = 0; m < E; ++m) {
             const int x = t + m * T;
-            if (m < kEb / 2) {
+            if (m < 2 * E / 3) {
                 const float a = scan_w(f + base, mf ? mf + base : nullptr, hann, N, i, x, win);
-                const float c = rotate_sample(g + base, mg ? mg + base : nullptr, hann, N, i, x, ct, st, win);
-                v[m] = make_float2(a, c);
+                v[m] = make_float2(a, grow_g[x]);
             } else {
                 v[m] = make_float2(0.f, 0.f);
             }
@@ -107,10 +107,10 @@ __global__ __launch_bounds__(256) void kb_rows_fwd2(
         const float* c2 = c1 + N;
         const int sy1 = 2 * q - N / 2, sy2 = sy1 + 1;
 #pragma unroll
-        for (int m = 0; m < kEb; ++m) {
-            const int x = t + m * T;                 // padded position s_x mod 2n
-            if (m < kEb / 4 || m >= 3 * kEb / 4) {
-                const int sx = m < kEb / 4 ? x : x - L;
+        for (int m = 0; m < E; ++m) {
+            const int x = t + m * T;                 // padded position s_x mod 3n/2
+            if (m < E / 3 || m >= 2 * E / 3) {
+                const int sx = m < E / 3 ? x : x - L;
                 const int j = sx + N / 2;
                 v[m] = make_float2(adj(c1[j], sx, sy1), adj(c2[j], sx, sy2));
             } else {
@@ -118,13 +118,13 @@ __global__ __launch_bounds__(256) void kb_rows_fwd2(
             }
         }
     }
-    fft_line<L, kEb>(v, lre[line], lim[line], t, tw);
-    float2 mir[kEb];
-    mirror_line<L, kEb>(v, mir, lre[line], lim[line], t);
+    fft_line<L, E>(v, lre[line], lim[line], t, tw);
+    float2 mir[E];
+    mirror_line<L, E>(v, mir, lre[line], lim[line], t);
 #pragma unroll
-    for (int m = 0; m <= kEb / 2; ++m) {
+    for (int m = 0; m <= E / 2; ++m) {
         const int k = t + m * T;
-        if (k > N) continue;
+        if (k > H) continue;
         const float2 X = split_x(v[m], mir[m]), Y = split_y(v[m], mir[m]);
         if (scan_rows) {
             rf[(size_t)grow * P2 + k] = make_float4(X.x, X.y, Y.x, Y.y);
@@ -136,15 +136,16 @@ __global__ __launch_bounds__(256) void kb_rows_fwd2(
     }
 }
 
-// Column pass of the translation adjoint over columns 0 .. n: forward 2n-point
-// column DFTs of F, G' and DC, then X1 = conj(DC) G' and X2 = F DC, inverse
-// column DFTs; the n data rows of (X1, X2) overwrite (F, G') in place.
+// Column pass of the translation adjoint over columns 0 .. 3n/4: forward
+// 3n/2-point column DFTs of F, G' and DC, then X1 = conj(DC) G' and X2 = F DC,
+// inverse column DFTs; the n data rows of (X1, X2) overwrite (F, G') in place.
 template <int N, int C>
-__global__ __launch_bounds__(C * 2 * N / kEb) void kb_cols_xy(float4* __restrict__ rf,
-                                                              const float2* __restrict__ rdc,
-                                                              const float2* __restrict__ tw,
-                                                              int batch) {
-    constexpr int L = 2 * N, T = L / kEb, TILES = N / C + 1, P2 = pitch_rows2(N), P3 = pitch_lag(N);
+__global__ __launch_bounds__(C * pad2(N) / kE2) void kb_cols_xy(float4* __restrict__ rf,
+                                                                const float2* __restrict__ rdc,
+                                                                const float2* __restrict__ tw,
+                                                                int batch) {
+    constexpr int L = pad2(N), E = kE2, T = L / E, H = L / 2, TILES = H / C + 1, P2 = pitch_rows2(N),
+                  P3 = pitch_lag(N);
     __shared__ float lre[C][LdsCols<C>::words(L)];
     __shared__ float lim[C][LdsCols<C>::words(L)];
     const int total = batch * TILES;
@@ -156,20 +157,20 @@ __global__ __launch_bounds__(C * 2 * N / kEb) void kb_cols_xy(float4* __restrict
     const int col = tile * C + c;
     float4* sf = rf + (size_t)b * N * P2;
     const float2* sd = rdc + (size_t)b * N * P3;
-    float2 vd[kEb];
+    float2 vd[E];
 #pragma unroll
-    for (int m = 0; m < kEb; ++m) {
+    for (int m = 0; m < E; ++m) {
         const int n = t + m * T;
-        // dc lag row o holds s_y = o - n/2, placed at padded row s_y mod 2n
-        if (m < kEb / 4) vd[m] = sd[(size_t)(n + N / 2) * P3 + col];
-        else if (m >= 3 * kEb / 4) vd[m] = sd[(size_t)(n - 3 * N / 2) * P3 + col];
+        // dc lag row o holds s_y = o - n/2, placed at padded row s_y mod 3n/2
+        if (m < E / 3) vd[m] = sd[(size_t)(n + N / 2) * P3 + col];
+        else if (m >= 2 * E / 3) vd[m] = sd[(size_t)(n - N) * P3 + col];
         else vd[m] = make_float2(0.f, 0.f);
     }
-    fft_line<L, kEb, LdsCols<C>>(vd, lre[c], lim[c], t, tw);
-    float2 vf[kEb], vg[kEb];
+    fft_line<L, E, LdsCols<C>>(vd, lre[c], lim[c], t, tw);
+    float2 vf[E], vg[E];
 #pragma unroll
-    for (int m = 0; m < kEb; ++m) {
-        if (m < kEb / 2) {
+    for (int m = 0; m < E; ++m) {
+        if (m < 2 * E / 3) {
             const float4 q = sf[(size_t)(t + m * T) * P2 + col];
             vf[m] = make_float2(q.x, q.y);
             vg[m] = make_float2(q.z, q.w);
@@ -177,26 +178,26 @@ __global__ __launch_bounds__(C * 2 * N / kEb) void kb_cols_xy(float4* __restrict
             vf[m] = vg[m] = make_float2(0.f, 0.f);
         }
     }
-    fft_line<L, kEb, LdsCols<C>>(vf, lre[c], lim[c], t, tw);
+    fft_line<L, E, LdsCols<C>>(vf, lre[c], lim[c], t, tw);
 #pragma unroll
-    for (int m = 0; m < kEb; ++m) vf[m] = cmul(vf[m], vd[m]);          // X2 = F DC
-    fft_line<L, kEb, LdsCols<C>>(vg, lre[c], lim[c], t, tw);
+    for (int m = 0; m < E; ++m) vf[m] = cmul(vf[m], vd[m]);          // X2 = F DC
+    fft_line<L, E, LdsCols<C>>(vg, lre[c], lim[c], t, tw);
 #pragma unroll
-    for (int m = 0; m < kEb; ++m) vg[m] = cmulcj(vd[m], vg[m]);        // X1 = conj(DC) G'
-    ifft_line<L, kEb, LdsCols<C>>(vg, lre[c], lim[c], t, tw);
-    ifft_line<L, kEb, LdsCols<C>>(vf, lre[c], lim[c], t, tw);
-    if (col > N) return;
+    for (int m = 0; m < E; ++m) vg[m] = cmulcj(vd[m], vg[m]);        // X1 = conj(DC) G'
+    ifft_line<L, E, LdsCols<C>>(vg, lre[c], lim[c], t, tw);
+    ifft_line<L, E, LdsCols<C>>(vf, lre[c], lim[c], t, tw);
+    if (col > H) return;
 #pragma unroll
-    for (int m = 0; m < kEb / 2; ++m)
+    for (int m = 0; m < 2 * E / 3; ++m)
         sf[(size_t)(t + m * T) * P2 + col] = make_float4(vg[m].x, vg[m].y, vf[m].x, vf[m].y);
 }
 
-// Entry k of the full 2n-point Hermitian spectrum from stored columns 0 .. n.
+// Entry k of the full L-point Hermitian spectrum from stored columns 0 .. L/2.
 __device__ __forceinline__ float2 herm_get2(float2 (*get)(const float4*, int), const float4* row,
-                                            int N, int k) {
-    if (k == 0 || k == N) return make_float2(get(row, k).x, 0.f);
-    if (k < N) return get(row, k);
-    return cconj(get(row, 2 * N - k));
+                                            int L, int k) {
+    if (k == 0 || k == L / 2) return make_float2(get(row, k).x, 0.f);
+    if (k < L / 2) return get(row, k);
+    return cconj(get(row, L - k));
 }
 __device__ __forceinline__ float2 get_lo(const float4* row, int k) { return make_float2(row[k].x, row[k].y); }
 __device__ __forceinline__ float2 get_hi(const float4* row, int k) { return make_float2(row[k].z, row[k].w); }
@@ -205,14 +206,11 @@ __device__ __forceinline__ float2 get_hi(const float4* row, int k) { return make
 // and the Rotate-path heading gradient dtheta_2 summed per block.
 template <int N>
 __global__ __launch_bounds__(256) void kb_rows_xy(const float4* __restrict__ q12,
-                                                  const float* __restrict__ g,
-                                                  const float* __restrict__ mg,
-                                                  const float* __restrict__ hann,
+                                                  const float* __restrict__ jac,
                                                   const float2* __restrict__ tw,
-                                                  const float* __restrict__ saved,
                                                   float* __restrict__ df2, float* __restrict__ dgp,
-                                                  float* __restrict__ dth_part, int win) {
-    constexpr int L = 2 * N, T = L / kEb, LPB = 256 / T, PPB = N / LPB, P2 = pitch_rows2(N);
+                                                  float* __restrict__ dth_part) {
+    constexpr int L = pad2(N), E = kE2, T = L / E, LPB = 256 / T, PPB = N / LPB, P2 = pitch_rows2(N);
     __shared__ float lre[LPB][LdsRows::words(L)];
     __shared__ float lim[LPB][LdsRows::words(L)];
     __shared__ float red[256];
@@ -220,45 +218,25 @@ __global__ __launch_bounds__(256) void kb_rows_xy(const float4* __restrict__ q12
     const int grow = blockIdx.x * LPB + line;
     const int b = grow / N, i = grow % N;
     const float4* row = q12 + (size_t)grow * P2;
-    float2 v[kEb];
+    float2 v[E];
 #pragma unroll
-    for (int m = 0; m < kEb; ++m) {
+    for (int m = 0; m < E; ++m) {
         const int k = t + m * T;
-        const float2 h1 = herm_get2(get_lo, row, N, k), h2 = herm_get2(get_hi, row, N, k);
+        const float2 h1 = herm_get2(get_lo, row, L, k), h2 = herm_get2(get_hi, row, L, k);
         v[m] = make_float2(h1.x - h2.y, h1.y + h2.x);
     }
-    ifft_line<L, kEb>(v, lre[line], lim[line], t, tw);
+    ifft_line<L, E>(v, lre[line], lim[line], t, tw);
     const float scale = 1.f / ((float)L * (float)L);
     const size_t base = (size_t)b * N * N;
-    const float* sv = saved + (size_t)b * FMBYM_SAVED;
-    const float ct = sv[kSavedCos], st = sv[kSavedSin];
-    const float* gb = g + base;
-    const float* mgb = mg ? mg + base : nullptr;
     float dth = 0.f;
 #pragma unroll
-    for (int m = 0; m < kEb / 2; ++m) {
+    for (int m = 0; m < 2 * E / 3; ++m) {
         const int x = t + m * T;
         const float a = v[m].x * scale, d = v[m].y * scale;
-        df2[base + (size_t)i * N + x] = a;
-        dgp[base + (size_t)i * N + x] = d;
-        // d g'(i, x) / d theta through the bilinear sample position
-        float py, px;
-        rot_src(N, i, x, ct, st, py, px);
-        const float fy = floorf(py), fx = floorf(px);
-        const float wy = py - fy, wx = px - fx;
-        const int y0 = (int)fy, x0 = (int)fx;
-        float G[2][2];
-#pragma unroll
-        for (int dy = 0; dy < 2; ++dy)
-#pragma unroll
-            for (int dx = 0; dx < 2; ++dx) {
-                const int r = y0 + dy, cc = x0 + dx;
-                G[dy][dx] = (r >= 0 && r < N && cc >= 0 && cc < N) ? scan_w(gb, mgb, hann, N, r, cc, win) : 0.f;
-            }
-        const float gx = (1.f - wy) * (G[0][1] - G[0][0]) + wy * (G[1][1] - G[1][0]);
-        const float gy = (1.f - wx) * (G[1][0] - G[0][0]) + wx * (G[1][1] - G[0][1]);
-        const float yx = (float)(x - N / 2), yy = (float)(i - N / 2);
-        dth += d * (gx * (-st * yx - ct * yy) + gy * (ct * yx - st * yy));
+        const size_t o = base + (size_t)i * N + x;
+        df2[o] = a;
+        dgp[o] = d;
+        dth += d * jac[o];   // d g'(i, x) / d theta through the bilinear sample position
     }
     red[threadIdx.x] = dth;
     __syncthreads();
@@ -512,6 +490,68 @@ __device__ __forceinline__ float rotate_adjoint(const float* __restrict__ dgp, i
     return acc;
 }
 
+// Rotate^T of dg' on its own, one scan pixel per thread (a gather over the few
+// output pixels whose sample position falls within a unit box of it).
+template <int N>
+__global__ __launch_bounds__(256) void kb_rotate_adj(const float* __restrict__ dgp,
+                                                     const float* __restrict__ saved,
+                                                     float* __restrict__ dgr) {
+    constexpr int TPR = N / kRotTX, TPP = TPR * (N / kRotTY);
+    __shared__ float box[kRotBox * kRotBox];
+    const int b = blockIdx.x / TPP, tile = blockIdx.x % TPP;
+    const int q0 = (tile / TPR) * kRotTY, c0 = (tile % TPR) * kRotTX;
+    const float* sv = saved + (size_t)b * FMBYM_SAVED;
+    const float ct = sv[kSavedCos], st = sv[kSavedSin];
+    const float e = fabsf(ct) + fabsf(st) + 1e-3f;
+    // box of the output pixels that any scan pixel of the tile gathers from
+    float ymin = 1e30f, ymax = -1e30f, xmin = 1e30f, xmax = -1e30f;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const float ox = (float)(c0 + (c >> 1) * (kRotTX - 1) - N / 2);
+        const float oy = (float)(q0 + (c & 1) * (kRotTY - 1) - N / 2);
+        const float cx = ct * ox + st * oy + (float)(N / 2);
+        const float cy = -st * ox + ct * oy + (float)(N / 2);
+        ymin = fminf(ymin, cy); ymax = fmaxf(ymax, cy);
+        xmin = fminf(xmin, cx); xmax = fmaxf(xmax, cx);
+    }
+    const int by0 = (int)floorf(ymin - e) - 1, bx0 = (int)floorf(xmin - e) - 1;
+    const int bh = min(kRotBox, (int)floorf(ymax + e) + 2 - by0), bw = min(kRotBox, (int)floorf(xmax + e) + 2 - bx0);
+    const float* src = dgp + (size_t)b * N * N;
+    for (int k = threadIdx.x; k < bh * bw; k += 256) {
+        const int r = by0 + k / bw, c = bx0 + k % bw;
+        box[k] = (r >= 0 && r < N && c >= 0 && c < N) ? src[(size_t)r * N + c] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kRotTY * kRotTX / 256; ++k) {
+        const int p = threadIdx.x + 256 * k;
+        const int qr = q0 + p / kRotTX, qc = c0 + p % kRotTX;
+        // the gather of rotate_adjoint, reading the box: every output pixel whose
+        // sample position lies within the unit box of q is within one lattice step
+        // of round(R^T (q - c) + c), so a fixed 3 x 3 window in row order visits
+        // the same contributors in the same order
+        const float ox = (float)(qc - N / 2), oy = (float)(qr - N / 2);
+        const float cx = ct * ox + st * oy + (float)(N / 2);
+        const float cy = -st * ox + ct * oy + (float)(N / 2);
+        const int ic = (int)rintf(cy), jc = (int)rintf(cx);
+        float acc = 0.f;
+#pragma unroll
+        for (int di = -1; di <= 1; ++di)
+#pragma unroll
+            for (int dj = -1; dj <= 1; ++dj) {
+                const int i = ic + di, j = jc + dj;
+                float py, px;
+                rot_src(N, i, j, ct, st, py, px);
+                const float ey = fabsf(py - (float)qr), ex = fabsf(px - (float)qc);
+                const int r = i - by0, c = j - bx0;
+                if (ey < 1.f && ex < 1.f && i >= 0 && i < N && j >= 0 && j < N && r >= 0 && r < bh && c >= 0 &&
+                    c < bw)
+                    acc += (1.f - ey) * (1.f - ex) * box[r * bw + c];
+            }
+        dgr[(size_t)b * N * N + (size_t)qr * N + qc] = acc;
+    }
+}
+
 // Inverse row DFT of the rotation adjoint: df_w[x] = Re sum_{k <= n/2} Q[k] e^{+2 pi i k x / n},
 // formed as the inverse DFT of the Hermitian extension (Re Q at k = 0, n/2;
 // Q/2 and conj(Q)/2 elsewhere), f and g paired in one transform.  Adds the
@@ -519,7 +559,7 @@ __device__ __forceinline__ float rotate_adjoint(const float* __restrict__ dgp, i
 // adjoints.
 template <int N>
 __global__ __launch_bounds__(256) void kb_rows_final(
-    const float4* __restrict__ r1, const float* __restrict__ df2, const float* __restrict__ dgp,
+    const float4* __restrict__ r1, const float* __restrict__ df2, const float* __restrict__ dgr,
     const float* __restrict__ f, const float* __restrict__ g, const float* __restrict__ mf,
     const float* __restrict__ mg, const float* __restrict__ hann, const float2* __restrict__ tw,
     const float* __restrict__ saved, float* __restrict__ d_f, float* __restrict__ d_g,
@@ -550,8 +590,6 @@ __global__ __launch_bounds__(256) void kb_rows_final(
     }
     ifft_line<L, kEb>(v, lre[line], lim[line], t, tw);
     const size_t base = (size_t)b * N * N;
-    const float* sv = saved + (size_t)b * FMBYM_SAVED;
-    const float ct = sv[kSavedCos], st = sv[kSavedSin];
     const float hi = win ? hann[i] : 1.f;
 #pragma unroll
     for (int m = 0; m < kEb; ++m) {
@@ -560,7 +598,7 @@ __global__ __launch_bounds__(256) void kb_rows_final(
         const float w = win ? hi * hann[x] : 1.f;
         const float w2 = win2 ? w : 1.f;
         const float s2f = df2[o];
-        const float s2g = rotate_adjoint(dgp + base, N, i, x, ct, st);
+        const float s2g = dgr[o];
         // stage 1 always sees the window; stage 2 sees it unless unwindowed
         const float dft = w * v[m].x + w2 * s2f;
         const float dgt = w * v[m].y + w2 * s2g;
@@ -584,7 +622,7 @@ __global__ __launch_bounds__(256) void kb_rows_final(
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct BwdLayout {
-    size_t rf, rdc, df2, dgp, dpol, dth, dspec, total;
+    size_t rf, rdc, df2, dgp, dpol, dth, dspec, jac, total;
 };
 
 // The stage-1 recomputation reuses the forward layout's first two regions;
@@ -608,6 +646,8 @@ static BwdLayout bwd_layout(const fmbym_params& p, int batch) {
     off = al256(off + B * n * sizeof(float));
     L.dspec = off;
     off = al256(off + B * (size_t)p.n_theta * sizeof(float2));
+    L.jac = off;
+    off = al256(off + B * n * n * sizeof(float));
     L.total = off;
     return L;
 }
@@ -647,23 +687,26 @@ static int launch_bwd_n(const Plan& pl, int B, const float* f, const float* g, c
     float2* dpol = (float2*)(ws + bl.dpol);
     float* dth = (float*)(ws + bl.dth);
     float2* dspec = (float2*)(ws + bl.dspec);
+    float* jac = (float*)(ws + bl.jac);
+    float* gr = (float*)(ws + fl.grot);     // g' for kb_rows_fwd2, later Rotate^T dg'
     float4* r1 = (float4*)(ws + fl.r1r2);
     float2* mag = (float2*)(ws + fl.mag_r3);
     const int win = (pl.p.flags & FMBYM_HANN) ? 1 : 0;
     const int win2 = (win && !(pl.p.flags & FMBYM_XY_UNWINDOWED)) ? 1 : 0;
 
     // translation-stage adjoint
-    constexpr int T2 = 2 * N / kEb, LPB2 = 256 / T2;
+    constexpr int T2 = pad2(N) / kE2, LPB2 = rows2_lines(N);
     const int scan_blocks = B * N / LPB2, dc_blocks = B * (N / 2) / LPB2;
+    launch_rotate(pl, B, g, mg, saved, gr, jac, win2, s, nullptr);
     FMBYM_LAUNCH(kKBRowsFwd2, kb_rows_fwd2<N>, dim3(scan_blocks + dc_blocks), dim3(256), s, f, g, mf, mg,
-                 pl.hann, pl.twiddle, saved, c_xy, d_pose, rf, rdc, win2, B, pl.p.temp_xy,
+                 pl.hann, pl.twiddle3, saved, c_xy, d_pose, gr, rf, rdc, win2, B, pl.p.temp_xy,
                  pl.p.delta_xy);
     constexpr int C2 = bcols_xy_tile<N>();
-    const int total2 = B * (N / C2 + 1);
-    FMBYM_LAUNCH(kKBColsXy, (kb_cols_xy<N, C2>), dim3(((total2 + 7) / 8) * 8), dim3(C2 * 2 * N / kEb), s,
-                 rf, rdc, pl.twiddle, B);
-    FMBYM_LAUNCH(kKBRowsXy, kb_rows_xy<N>, dim3(B * N / LPB2), dim3(256), s, rf, g, mg, pl.hann,
-                 pl.twiddle, saved, df2, dgp, dth, win2);
+    const int total2 = B * ((pad2(N) / 2) / C2 + 1);
+    FMBYM_LAUNCH(kKBColsXy, (kb_cols_xy<N, C2>), dim3(((total2 + 7) / 8) * 8), dim3(C2 * T2), s,
+                 rf, rdc, pl.twiddle3, B);
+    FMBYM_LAUNCH(kKBRowsXy, kb_rows_xy<N>, dim3(B * N / LPB2), dim3(256), s, rf, jac, pl.twiddle3, df2,
+                 dgp, dth);
     const int ppb = N / LPB2;
     switch (pl.p.n_theta) {
         case 16: launch_dtheta<16>(pl, B, ppb, dth, c_theta, saved, d_pose, dspec, s); break;
@@ -695,8 +738,10 @@ static int launch_bwd_n(const Plan& pl, int B, const float* f, const float* g, c
     constexpr int C = bcols_mag_tile<N>();
     FMBYM_LAUNCH(kKBColsMag, (kb_cols_mag<N, C>), dim3(B * ((N / 2) / C + 1)), dim3(C * N / kEb), s, r1,
                  dA, pl.twiddle);
+    FMBYM_LAUNCH(kKBRotateAdj, kb_rotate_adj<N>, dim3(B * (N / kRotTY) * (N / kRotTX)), dim3(256), s, dgp,
+                 saved, gr);
     constexpr int T1 = N / kEb, LPB1 = 256 / T1;
-    FMBYM_LAUNCH(kKBRowsFinal, kb_rows_final<N>, dim3(B * N / LPB1), dim3(256), s, r1, df2, dgp, f, g, mf,
+    FMBYM_LAUNCH(kKBRowsFinal, kb_rows_final<N>, dim3(B * N / LPB1), dim3(256), s, r1, df2, gr, f, g, mf,
                  mg, pl.hann, pl.twiddle, saved, d_f, d_g, d_mf, d_mg, win, win2);
     return FMBYM_OK;
 }

@@ -336,52 +336,122 @@ __global__ __launch_bounds__(256) void k_rows2(const float* __restrict__ f, cons
                                                const float* __restrict__ mf, const float* __restrict__ mg,
                                                const float* __restrict__ hann,
                                                const float2* __restrict__ tw,
-                                               const float* __restrict__ saved,
+                                               const float* __restrict__ gr,
                                                float4* __restrict__ out, int win,
                                                const float* const* __restrict__ tab) {
-    constexpr int L = 2 * N, T = L / kE, LPB = 256 / T, P2 = pitch_rows2(N);
+    constexpr int L = pad2(N), E = kE2, T = L / E, LPB = 256 / T, H = L / 2, P2 = pitch_rows2(N);
     __shared__ float lre[LPB][LdsRows::words(L)];
     __shared__ float lim[LPB][LdsRows::words(L)];
     const int line = threadIdx.x / T, t = threadIdx.x % T;
     const int grow = blockIdx.x * LPB + line;
     const int b = grow / N, i = grow % N;
     const PairScans sc = pair_scans(tab, b, N, f, g, mf, mg);
-    const float ct = saved[(size_t)b * FMBYM_SAVED + kSavedCos];
-    const float st = saved[(size_t)b * FMBYM_SAVED + kSavedSin];
-    float2 v[kE];
+    const float* grow_g = gr + (size_t)grow * N;
+    float2 v[E];
 #pragma unroll
-    for (int m = 0; m < kE; ++m) {
+    for (int m = 0; m < E; ++m) {
         const int x = t + m * T;
-        if (m < kE / 2) {   // x < n: data; the upper half of the padded row is zero
+        if (m < 2 * E / 3) {   // x < n: data; the padding up to 3n/2 is zero
             const float a = scan_w(sc.f, sc.mf, hann, N, i, x, win);
-            const float c = rotate_sample(sc.g, sc.mg, hann, N, i, x, ct, st, win);
-            v[m] = make_float2(a, c);
+            v[m] = make_float2(a, grow_g[x]);
         } else {
             v[m] = make_float2(0.f, 0.f);
         }
     }
-    fft_line<L, kE>(v, lre[line], lim[line], t, tw);
-    float2 mir[kE];
-    mirror_line<L, kE>(v, mir, lre[line], lim[line], t);
+    fft_line<L, E>(v, lre[line], lim[line], t, tw);
+    float2 mir[E];
+    mirror_line<L, E>(v, mir, lre[line], lim[line], t);
     float4* o = out + (size_t)grow * P2;
 #pragma unroll
-    for (int m = 0; m <= kE / 2; ++m) {
+    for (int m = 0; m <= E / 2; ++m) {
         const int k = t + m * T;
-        if (k <= N) {
+        if (k <= H) {
             const float2 X = split_x(v[m], mir[m]), Y = split_y(v[m], mir[m]);
             o[k] = make_float4(X.x, X.y, Y.x, Y.y);
         }
     }
 }
 
-// Column pass of stage 2 over columns 0 .. n of the padded row spectra:
-// forward column DFTs of F and G' (n data rows, n zero rows), conj(F) G',
-// inverse column DFT; the n central lag rows are kept.
+// Rotate g_w into gr (and d g' / d theta into jac when not null).  A block
+// owns a kRotTY x kRotTX tile of output pixels; the source positions of the
+// tile lie in the rotated tile's bounding box, which is staged in LDS (windowed
+// and masked, zeros outside the scan) with coalesced row reads, and every
+// bilinear corner is then read from LDS.  The arithmetic (positions, weights,
+// summation order) is that of rotate_sample / rotate_dtheta.
+
+template <int N>
+__global__ __launch_bounds__(256) void k_rotate(const float* __restrict__ g, const float* __restrict__ mg,
+                                                const float* __restrict__ hann,
+                                                const float* __restrict__ saved, float* __restrict__ gr,
+                                                float* __restrict__ jac, int win,
+                                                const float* const* __restrict__ tab) {
+    static_assert(N % kRotTX == 0 && N % kRotTY == 0, "tiles cover the scan");
+    constexpr int TPR = N / kRotTX, TPP = TPR * (N / kRotTY);   // tiles per tile row, per pair
+    __shared__ float box[kRotBox * kRotBox];
+    const int b = blockIdx.x / TPP, tile = blockIdx.x % TPP;
+    const int i0 = (tile / TPR) * kRotTY, j0 = (tile % TPR) * kRotTX;
+    const PairScans sc = pair_scans(tab, b, N, g, g, mg, mg);
+    const float ct = saved[(size_t)b * FMBYM_SAVED + kSavedCos];
+    const float st = saved[(size_t)b * FMBYM_SAVED + kSavedSin];
+    // bounding box of the tile's source positions (corners of the tile map to its extremes)
+    float ymin = 1e30f, ymax = -1e30f, xmin = 1e30f, xmax = -1e30f;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        float py, px;
+        rot_src(N, i0 + (c & 1) * (kRotTY - 1), j0 + (c >> 1) * (kRotTX - 1), ct, st, py, px);
+        ymin = fminf(ymin, py); ymax = fmaxf(ymax, py);
+        xmin = fminf(xmin, px); xmax = fmaxf(xmax, px);
+    }
+    const int by0 = (int)floorf(ymin) - 1, bx0 = (int)floorf(xmin) - 1;
+    const int bh = min(kRotBox, (int)floorf(ymax) + 3 - by0), bw = min(kRotBox, (int)floorf(xmax) + 3 - bx0);
+    for (int k = threadIdx.x; k < bh * bw; k += 256) {
+        const int r = by0 + k / bw, c = bx0 + k % bw;
+        box[k] = (r >= 0 && r < N && c >= 0 && c < N) ? scan_w(sc.g, sc.mg, hann, N, r, c, win) : 0.f;
+    }
+    __syncthreads();
+    float* go = gr + (size_t)b * N * N;
+    float* jo = jac ? jac + (size_t)b * N * N : nullptr;
+#pragma unroll
+    for (int k = 0; k < kRotTY * kRotTX / 256; ++k) {
+        const int e = threadIdx.x + 256 * k;
+        const int i = i0 + e / kRotTX, j = j0 + e % kRotTX;
+        float py, px;
+        rot_src(N, i, j, ct, st, py, px);
+        const float fy = floorf(py), fx = floorf(px);
+        const float wy = py - fy, wx = px - fx;
+        const int y0 = (int)fy - by0, x0 = (int)fx - bx0;
+        float G[2][2];
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 2; ++dx) {
+                const int r = y0 + dy, c = x0 + dx;
+                G[dy][dx] = (r >= 0 && r < bh && c >= 0 && c < bw) ? box[r * bw + c] : 0.f;
+            }
+        float acc = 0.f;
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 2; ++dx) acc += (dy ? wy : 1.f - wy) * (dx ? wx : 1.f - wx) * G[dy][dx];
+        go[(size_t)i * N + j] = acc;
+        if (jo) {
+            const float gx = (1.f - wy) * (G[0][1] - G[0][0]) + wy * (G[1][1] - G[1][0]);
+            const float gy = (1.f - wx) * (G[1][0] - G[0][0]) + wx * (G[1][1] - G[0][1]);
+            const float yx = (float)(j - N / 2), yy = (float)(i - N / 2);
+            jo[(size_t)i * N + j] = gx * (-st * yx - ct * yy) + gy * (ct * yx - st * yy);
+        }
+    }
+}
+
+// Column pass of stage 2 over columns 0 .. 3n/4 of the padded row spectra:
+// forward column DFTs of F and G' (n data rows, n/2 zero rows), conj(F) G',
+// inverse column DFT; the n lag rows of the window are kept.
 template <int N, int C>
-__global__ __launch_bounds__(C * 2 * N / kE) void k_cols2(const float4* __restrict__ in,
-                                                          const float2* __restrict__ tw,
-                                                          float2* __restrict__ out, int batch) {
-    constexpr int L = 2 * N, T = L / kE, TILES = N / C + 1, P2 = pitch_rows2(N), P3 = pitch_lag(N);
+__global__ __launch_bounds__(C * pad2(N) / kE2) void k_cols2(const float4* __restrict__ in,
+                                                             const float2* __restrict__ tw,
+                                                             float2* __restrict__ out, int batch) {
+    constexpr int L = pad2(N), E = kE2, T = L / E, H = L / 2, TILES = H / C + 1, P2 = pitch_rows2(N),
+                  P3 = pitch_lag(N);
     __shared__ float lre[C][LdsCols<C>::words(L)];
     __shared__ float lim[C][LdsCols<C>::words(L)];
     const int total = batch * TILES;
@@ -392,10 +462,10 @@ __global__ __launch_bounds__(C * 2 * N / kE) void k_cols2(const float4* __restri
     const int tile = work % TILES, b = work / TILES;
     const int col = tile * C + c;
     const float4* src = in + (size_t)b * N * P2;
-    float2 vf[kE], vg[kE];
+    float2 vf[E], vg[E];
 #pragma unroll
-    for (int m = 0; m < kE; ++m) {
-        if (m < kE / 2) {
+    for (int m = 0; m < E; ++m) {
+        if (m < 2 * E / 3) {
             const float4 q = src[(size_t)(t + m * T) * P2 + col];
             vf[m] = make_float2(q.x, q.y);
             vg[m] = make_float2(q.z, q.w);
@@ -403,27 +473,27 @@ __global__ __launch_bounds__(C * 2 * N / kE) void k_cols2(const float4* __restri
             vf[m] = vg[m] = make_float2(0.f, 0.f);
         }
     }
-    fft_line<L, kE, LdsCols<C>>(vf, lre[c], lim[c], t, tw);
-    fft_line<L, kE, LdsCols<C>>(vg, lre[c], lim[c], t, tw);
+    fft_line<L, E, LdsCols<C>>(vf, lre[c], lim[c], t, tw);
+    fft_line<L, E, LdsCols<C>>(vg, lre[c], lim[c], t, tw);
 #pragma unroll
-    for (int m = 0; m < kE; ++m) vf[m] = cmulcj(vf[m], vg[m]);
-    ifft_line<L, kE, LdsCols<C>>(vf, lre[c], lim[c], t, tw);
-    if (col > N) return;
+    for (int m = 0; m < E; ++m) vf[m] = cmulcj(vf[m], vg[m]);
+    ifft_line<L, E, LdsCols<C>>(vf, lre[c], lim[c], t, tw);
+    if (col > H) return;
     float2* dst = out + (size_t)b * N * P3;
 #pragma unroll
-    for (int m = 0; m < kE; ++m) {
-        const int n = t + m * T;                 // lag row s_y = n (n < N/2) or n - 2N (n >= 3N/2)
-        if (n < N / 2) dst[(size_t)(n + N / 2) * P3 + col] = vf[m];
-        else if (n >= 3 * N / 2) dst[(size_t)(n - 3 * N / 2) * P3 + col] = vf[m];
+    for (int m = 0; m < E; ++m) {
+        const int n = t + m * T;        // lag row s_y = n (n < N/2) or n - 3N/2 (n >= N)
+        if (m < E / 3) dst[(size_t)(n + N / 2) * P3 + col] = vf[m];
+        else if (m >= 2 * E / 3) dst[(size_t)(n - N) * P3 + col] = vf[m];
     }
 }
 
-// Entry k of the full 2n-point Hermitian spectrum of a lag row whose columns
-// 0 .. n are stored (the DC and Nyquist entries are real by symmetry).
-__device__ __forceinline__ float2 herm_get(const float2* __restrict__ row, int N, int k) {
-    if (k == 0 || k == N) return make_float2(row[k].x, 0.f);
-    if (k < N) return row[k];
-    return cconj(row[2 * N - k]);
+// Entry k of the full L-point Hermitian spectrum of a lag row whose columns
+// 0 .. L/2 are stored (the DC and Nyquist entries are real by symmetry).
+__device__ __forceinline__ float2 herm_get(const float2* __restrict__ row, int L, int k) {
+    if (k == 0 || k == L / 2) return make_float2(row[k].x, 0.f);
+    if (k < L / 2) return row[k];
+    return cconj(row[L - k]);
 }
 
 template <int N>
@@ -431,7 +501,8 @@ __global__ __launch_bounds__(256) void k_rows3(const float2* __restrict__ in,
                                                const float2* __restrict__ tw,
                                                float* __restrict__ c_xy, float4* __restrict__ part,
                                                float temp) {
-    constexpr int L = 2 * N, T = L / kE, LPB = 256 / T, PPP = (N / 2) / LPB, P3 = pitch_lag(N);
+    constexpr int L = pad2(N), E = kE2, T = L / E, LPB = 256 / T, PPP = (N / 2) / LPB, P3 = pitch_lag(N);
+    constexpr int K = 2 * E / 3;    // kept lags per thread
     __shared__ float lre[LPB][LdsRows::words(L)];
     __shared__ float lim[LPB][LdsRows::words(L)];
     __shared__ float4 red[256];
@@ -440,25 +511,25 @@ __global__ __launch_bounds__(256) void k_rows3(const float2* __restrict__ in,
     const int b = gl / (N / 2), q = gl % (N / 2);
     const float2* r1 = in + ((size_t)b * N + 2 * q) * P3;
     const float2* r2 = r1 + P3;
-    float2 v[kE];
+    float2 v[E];
 #pragma unroll
-    for (int m = 0; m < kE; ++m) {
+    for (int m = 0; m < E; ++m) {
         const int k = t + m * T;
-        const float2 h1 = herm_get(r1, N, k), h2 = herm_get(r2, N, k);
+        const float2 h1 = herm_get(r1, L, k), h2 = herm_get(r2, L, k);
         v[m] = make_float2(h1.x - h2.y, h1.y + h2.x);   // h1 + i h2
     }
-    ifft_line<L, kE>(v, lre[line], lim[line], t, tw);
+    ifft_line<L, E>(v, lre[line], lim[line], t, tw);
     const float scale = 1.f / ((float)L * (float)L);
     const float inv_t = 1.f / temp;
-    // kept lags: n < N/2 (m < kE/4) and n >= 3N/2 (m >= 3 kE/4)
-    float cv[2][kE / 2];
-    int sx[kE / 2];
+    // kept lags: n < N/2 (m < E/3) and n >= N (m >= 2E/3)
+    float cv[2][K];
+    int sx[K];
     float lmax = -INFINITY;
 #pragma unroll
-    for (int j = 0; j < kE / 2; ++j) {
-        const int m = j < kE / 4 ? j : j + kE / 2;
+    for (int j = 0; j < K; ++j) {
+        const int m = j < E / 3 ? j : j + E / 3;
         const int n = t + m * T;
-        const int col = n < N / 2 ? n + N / 2 : n - 3 * N / 2;
+        const int col = n < N / 2 ? n + N / 2 : n - N;
         sx[j] = col - N / 2;
         cv[0][j] = v[m].x * scale;
         cv[1][j] = v[m].y * scale;
@@ -471,7 +542,7 @@ __global__ __launch_bounds__(256) void k_rows3(const float2* __restrict__ in,
     const float sy0 = (float)(2 * q - N / 2), sy1 = sy0 + 1.f;
     float Z = 0.f, Sx = 0.f, Sy = 0.f;
 #pragma unroll
-    for (int j = 0; j < kE / 2; ++j) {
+    for (int j = 0; j < K; ++j) {
         const float e0 = expf((cv[0][j] - lmax) * inv_t);
         const float e1 = expf((cv[1][j] - lmax) * inv_t);
         Z += e0 + e1;
@@ -553,6 +624,8 @@ FwdLayout fwd_layout(const fmbym_params& p, int batch) {
     off = align256(off + B * (size_t)xy_partials_per_pair(p.n) * sizeof(float4));
     L.saved = off;
     off = align256(off + B * FMBYM_SAVED * sizeof(float));
+    L.grot = off;
+    off = align256(off + B * n * n * sizeof(float));
     L.total = off;
     return L;
 }
@@ -619,19 +692,44 @@ static int launch_n(const Plan& pl, int B, const float* f, const float* g, const
     const int win2 = ((pl.p.flags & FMBYM_HANN) && !(pl.p.flags & FMBYM_XY_UNWINDOWED)) ? 1 : 0;
     float4* r2 = r1;                    // stage-1 rows are dead after k_cols1
     float2* r3 = mag;                   // magnitudes are dead after k_polar
-    constexpr int T2 = 2 * N / kE, LPB2 = 256 / T2;
+    constexpr int T2 = pad2(N) / kE2, LPB2 = rows2_lines(N);
+    float* gr = (float*)(ws + lay.grot);
+    FMBYM_LAUNCH(kKRotate, k_rotate<N>, dim3(B * (N / kRotTY) * (N / kRotTX)), dim3(256), s, g, mg, pl.hann,
+                 sv, gr, nullptr, win2, tab);
     FMBYM_LAUNCH(kKRows2, k_rows2<N>, dim3(B * N / LPB2), dim3(256), s, f, g, mf, mg, pl.hann,
-                 pl.twiddle, sv, r2, win2, tab);
+                 pl.twiddle3, gr, r2, win2, tab);
     constexpr int C2 = cols2_tile<N>();
-    const int total2 = B * (N / C2 + 1);
-    FMBYM_LAUNCH(kKCols2, (k_cols2<N, C2>), dim3(((total2 + 7) / 8) * 8), dim3(C2 * 2 * N / kE), s, r2,
-                 pl.twiddle, r3, B);
-    constexpr int LPB3 = 256 / T2;
-    FMBYM_LAUNCH(kKRows3, k_rows3<N>, dim3(B * (N / 2) / LPB3), dim3(256), s, r3, pl.twiddle, c_xy,
+    const int total2 = B * ((pad2(N) / 2) / C2 + 1);
+    FMBYM_LAUNCH(kKCols2, (k_cols2<N, C2>), dim3(((total2 + 7) / 8) * 8), dim3(C2 * T2), s, r2,
+                 pl.twiddle3, r3, B);
+    FMBYM_LAUNCH(kKRows3, k_rows3<N>, dim3(B * (N / 2) / LPB2), dim3(256), s, r3, pl.twiddle3, c_xy,
                  pxy, pl.p.temp_xy);
     FMBYM_LAUNCH(kKXyFin, k_xy_fin, dim3(B), dim3(64), s, pxy, xy_partials_per_pair(N), pl.p.temp_xy,
                  pl.p.delta_xy, pose, sv);
     return FMBYM_OK;
+}
+
+void launch_rotate(const Plan& pl, int B, const float* g, const float* mg, const float* saved, float* gr,
+                   float* jac, int win, hipStream_t s, const float* const* tab) {
+    const int N = pl.p.n;
+    switch (N) {
+        case 128:
+            FMBYM_LAUNCH(kKRotate, k_rotate<128>, dim3(B * (128 / kRotTY) * (128 / kRotTX)), dim3(256), s, g, mg,
+                         pl.hann,
+                         saved, gr, jac, win, tab);
+            break;
+        case 256:
+            FMBYM_LAUNCH(kKRotate, k_rotate<256>, dim3(B * (256 / kRotTY) * (256 / kRotTX)), dim3(256), s, g, mg,
+                         pl.hann,
+                         saved, gr, jac, win, tab);
+            break;
+        case 512:
+            FMBYM_LAUNCH(kKRotate, k_rotate<512>, dim3(B * (512 / kRotTY) * (512 / kRotTX)), dim3(256), s, g, mg,
+                         pl.hann,
+                         saved, gr, jac, win, tab);
+            break;
+        default: break;
+    }
 }
 
 int launch_forward(const Plan& pl, int batch, const float* f, const float* g, const float* mf,
