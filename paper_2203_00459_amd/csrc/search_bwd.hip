@@ -670,8 +670,8 @@ static void launch_dtheta(const Plan& pl, int B, int ppb, const float* dth, cons
                  pl.twiddle, pl.p.temp_theta, dspec);
 }
 
-template <int N> constexpr int bcols_xy_tile() { return N >= 256 ? 8 : 16; }
-template <int N> constexpr int bcols_mag_tile() { return N >= 512 ? 8 : 16; }
+template <int N> constexpr int bcols_xy_tile() { return N >= 512 ? 4 : (N >= 256 ? 8 : 16); }
+template <int N> constexpr int bcols_mag_tile() { return N >= 512 ? 4 : 16; }
 
 template <int N>
 static int launch_bwd_n(const Plan& pl, int B, const float* f, const float* g, const float* mf,

@@ -630,9 +630,10 @@ FwdLayout fwd_layout(const fmbym_params& p, int batch) {
     return L;
 }
 
-// Column-tile widths: 8 interleaved columns read 128-byte segments.
+// Column-tile widths (measured at 512 x 512): 8 float4 columns read whole 128-byte
+// lines; the 3n/2-point stage-2 columns run better 4 wide (more blocks per CU).
 template <int N> constexpr int cols1_tile() { return N >= 512 ? 8 : 16; }
-template <int N> constexpr int cols2_tile() { return N >= 256 ? 8 : 16; }
+template <int N> constexpr int cols2_tile() { return N >= 512 ? 4 : (N >= 256 ? 8 : 16); }
 
 template <int N>
 static void launch_stage1_rows_cols(const Plan& pl, int B, const float* f, const float* g,
