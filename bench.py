@@ -26,6 +26,51 @@ FP32_PEAK_TFLOPS = 157.3     # MI355X vector FP32, vendor figure
 BF16_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 matrix cores, vendor figure
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_batch512.txt")
+
+
+def source_digest() -> str:
+    """sha256 over the library's HIP sources (names and contents, sorted)."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_2203_00459_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(src)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(f.encode())
+            with open(os.path.join(src, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE/WRITE_SIZE
+    summary (scaled by its copy-kernel calibration), or None when the summary is
+    missing or was taken on other sources than the ones built here."""
+    try:
+        lines = open(TRAFFIC_FILE).read().splitlines()
+    except OSError:
+        return None
+    meta = {}
+    for ln in lines:
+        if ln.startswith("# source-digest "):
+            meta["digest"] = ln.split()[2]
+        elif ln.startswith("# calibration-fetch "):
+            meta["ff"] = float(ln.split()[2])
+        elif ln.startswith("# calibration-write "):
+            meta["fw"] = float(ln.split()[2])
+    if meta.get("digest") != source_digest() or "ff" not in meta or "fw" not in meta:
+        return None
+    for ln in lines:
+        if ln.startswith("#") or not ln.strip():
+            continue
+        parts = ln.split()
+        name = ln[:34].strip().split("<")[0]
+        if name == kernel and len(parts) >= 4:
+            fetch, write = float(parts[-4]), float(parts[-3])
+            return (fetch * meta["ff"] + write * meta["fw"]) * 1024.0
+    return None
+
+
 def kernel_bytes(n: int, n_theta: int, n_r: int, batch: int, masked: bool) -> dict:
     """Algorithmic HBM bytes per launch of each kernel: compulsory reads of its
     inputs plus writes of its outputs, each touched once (float32 / complex64)."""
@@ -369,7 +414,8 @@ def search_bench(args) -> int:
                    "pass": "fwd+bwd" if with_bwd else "fwd"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": None if achieved is None else achieved / HBM_PEAK_GBS,
-                     "traffic": None},
+                     "traffic": measured_traffic(dom) if args.workload == "batch512" else None,
+                     "algorithmic_bytes": kb.get(dom)},
         "kernels_ms": {k: round(v, 5) for k, v in sorted(per_kernel.items())},
     }
 

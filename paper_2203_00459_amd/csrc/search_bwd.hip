@@ -437,12 +437,15 @@ __device__ __forceinline__ float2 mag_adjoint(float2 F, float dA) {
 template <int N, int C>
 __global__ __launch_bounds__(C * N / kEb) void kb_cols_mag(float4* __restrict__ r1,
                                                            const float2* __restrict__ dA,
-                                                           const float2* __restrict__ tw) {
+                                                           const float2* __restrict__ tw, int batch) {
     constexpr int L = N, T = L / kEb, H = N / 2, TILES = H / C + 1, P1 = pitch_rows1(N), PA = pitch_mag(N);
     __shared__ float lre[C][LdsCols<C>::words(L)];
     __shared__ float lim[C][LdsCols<C>::words(L)];
     const int c = threadIdx.x % C, t = threadIdx.x / C;
-    const int tile = blockIdx.x % TILES, b = blockIdx.x / TILES;
+    const int total = gridDim.x, per_xcd = total / 8;   // grid is a multiple of 8
+    const int work = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;   // adjacent tiles on one XCD
+    if (work >= batch * TILES) return;
+    const int tile = work % TILES, b = work / TILES;
     const int col = tile * C + c;
     float4* src = r1 + (size_t)b * N * P1;
     const float2* da = dA + (size_t)b * N * PA;
@@ -736,8 +739,9 @@ static int launch_bwd_n(const Plan& pl, int B, const float* f, const float* g, c
                  pl.csr_ptr, pl.csr_col, pl.csr_val, pl.csr_dst, pl.dmag_part, dpol, dA, N, pl.p.n_r,
                  pl.p.n_theta, B);
     constexpr int C = bcols_mag_tile<N>();
-    FMBYM_LAUNCH(kKBColsMag, (kb_cols_mag<N, C>), dim3(B * ((N / 2) / C + 1)), dim3(C * N / kEb), s, r1,
-                 dA, pl.twiddle);
+    const int tiles_mag = B * ((N / 2) / C + 1);
+    FMBYM_LAUNCH(kKBColsMag, (kb_cols_mag<N, C>), dim3(((tiles_mag + 7) / 8) * 8), dim3(C * N / kEb), s, r1,
+                 dA, pl.twiddle, B);
     FMBYM_LAUNCH(kKBRotateAdj, kb_rotate_adj<N>, dim3(B * (N / kRotTY) * (N / kRotTX)), dim3(256), s, dgp,
                  saved, gr);
     constexpr int T1 = N / kEb, LPB1 = 256 / T1;

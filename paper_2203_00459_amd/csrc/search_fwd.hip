@@ -86,13 +86,16 @@ template <int N, int C>
 __global__ __launch_bounds__(C * N / kE) void k_cols1(const float4* __restrict__ in,
                                                       float2* __restrict__ A,
                                                       const float2* __restrict__ tw, int band_on,
-                                                      int lo2, int hi2) {
+                                                      int lo2, int hi2, int batch) {
     constexpr int L = N, T = L / kE, H = N / 2, P1 = pitch_rows1(N), PA = pitch_mag(N);
     constexpr int TILES = H / C + 1;
     __shared__ float lre[C][LdsCols<C>::words(L)];
     __shared__ float lim[C][LdsCols<C>::words(L)];
     const int c = threadIdx.x % C, t = threadIdx.x / C;
-    const int tile = blockIdx.x % TILES, b = blockIdx.x / TILES;
+    const int per_xcd = gridDim.x / 8;   // grid is a multiple of 8
+    const int work = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;   // adjacent tiles on one XCD
+    if (work >= batch * TILES) return;
+    const int tile = work % TILES, b = work / TILES;
     const int col = tile * C + c;
     const float4* src = in + (size_t)b * N * P1;
     float2 vf[kE], vg[kE];
@@ -255,7 +258,8 @@ __global__ __launch_bounds__(kAngleGroups * NT / kE) void k_angle_fin(
         const int q = threadIdx.x / T, tt = threadIdx.x % T;
         for (int k = tt; k < HK; k += T) {
             float2 s = make_float2(0.f, 0.f);
-            for (int r = q; r < nrb; r += kAngleGroups) s = cadd(s, src[(size_t)r * HK + k]);
+#pragma unroll 8
+            for (int r = q; r < nrb; r += kAngleGroups) s = cadd(s, src[(size_t)r * HK + k]);   // loads overlap
             psum[q][k] = s;
         }
     }
@@ -644,8 +648,9 @@ static void launch_stage1_rows_cols(const Plan& pl, int B, const float* f, const
     FMBYM_LAUNCH(kKRows1, k_rows1<N>, dim3(B * N / LPB1), dim3(256), s, f, g, mf, mg, pl.hann,
                  pl.twiddle, r1, win, tab);
     constexpr int C = cols1_tile<N>();
-    FMBYM_LAUNCH(kKCols1, (k_cols1<N, C>), dim3(B * ((N / 2) / C + 1)), dim3(C * N / kE), s, r1, mag,
-                 pl.twiddle, pl.band_on, pl.band_lo2, pl.band_hi2);
+    const int tiles1 = B * ((N / 2) / C + 1);
+    FMBYM_LAUNCH(kKCols1, (k_cols1<N, C>), dim3(((tiles1 + 7) / 8) * 8), dim3(C * N / kE), s, r1, mag,
+                 pl.twiddle, pl.band_on, pl.band_lo2, pl.band_hi2, B);
 }
 
 void launch_stage1_spectra(const Plan& pl, int B, const float* f, const float* g, const float* mf,
