@@ -224,6 +224,17 @@ struct FFTStages<L, E, NS, NS, Lay> {
     __device__ __forceinline__ static void run(float2 (&)[E], float*, float*, int, const float2*) {}
 };
 
+// The thread index under a fresh name.  Kernels that run several transforms
+// pass each one its own fresh index: the LDS addresses of a transform are
+// functions of t alone, and when transforms share them the compiler computes
+// them once and keeps them all live in registers from the first transform to
+// the last (about 80 VGPRs for 12 elements per thread).  With a fresh index
+// they are recomputed per transform, a few integer instructions per stage.
+__device__ __forceinline__ int fresh_index(int t) {
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
 // Forward DFT of one line, in registers.  All threads of the block must call
 // it (it contains block barriers) even if their line is padding.  tw is the
 // table of twiddle_len<L>() entries.

@@ -201,6 +201,37 @@ __device__ __forceinline__ float rotate_dtheta(const float* __restrict__ g, cons
 constexpr int kRotTY = 16, kRotTX = 64;
 constexpr int kRotBox = 72;   // > sqrt(kRotTX^2 + kRotTY^2) + 6
 
+// Stage rows by0 .. by0+bh-1, columns bx0 .. bx0+bw-1 of x (times m if MASKED,
+// times the separable window if WIN) into box at a pitch of kRotBox words,
+// lattice points outside the n x n scan as zero.  For blocks of 256 threads.
+// The loads are unconditional at clamped addresses (hann has n entries), so
+// four of them per thread are in flight before the LDS stores.
+template <bool MASKED, bool WIN>
+__device__ __forceinline__ void stage_box(float* __restrict__ box, const float* __restrict__ x,
+                                          const float* __restrict__ m, const float* __restrict__ hann,
+                                          int n, int by0, int bx0, int bh, int bw) {
+    const int lim = bh * kRotBox;
+    for (int k0 = threadIdx.x; k0 < lim; k0 += 4 * 256) {
+        float val[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 + 256 * u, cc = k % kRotBox;
+            const int r = by0 + k / kRotBox, c = bx0 + cc;
+            const int rc = min(max(r, 0), n - 1), ccl = min(max(c, 0), n - 1);
+            float v = x[(size_t)rc * n + ccl];
+            if (MASKED) v *= m[(size_t)rc * n + ccl];
+            if (WIN) v *= hann[rc] * hann[ccl];
+            // a factor rather than a branch: the load stays unconditional (scans are finite)
+            val[u] = v * (float)((r == rc) & (c == ccl));
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 + 256 * u;
+            if (k < lim && k % kRotBox < bw) box[k] = val[u];
+        }
+    }
+}
+
 // Rotate g_w by the pair's heading into gr (and its theta derivative into jac
 // when not null), one pixel per thread: the gathers run in a kernel of their
 // own so that their latency is hidden by many light waves.

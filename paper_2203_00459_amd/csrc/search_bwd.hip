@@ -166,7 +166,7 @@ __global__ __launch_bounds__(C * pad2(N) / kE2) void kb_cols_xy(float4* __restri
         else if (m >= 2 * E / 3) vd[m] = sd[(size_t)(n - N) * P3 + col];
         else vd[m] = make_float2(0.f, 0.f);
     }
-    fft_line<L, E, LdsCols<C>>(vd, lre[c], lim[c], t, tw);
+    fft_line<L, E, LdsCols<C>>(vd, lre[c], lim[c], fresh_index(t), tw);
     float2 vf[E], vg[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
@@ -178,14 +178,14 @@ __global__ __launch_bounds__(C * pad2(N) / kE2) void kb_cols_xy(float4* __restri
             vf[m] = vg[m] = make_float2(0.f, 0.f);
         }
     }
-    fft_line<L, E, LdsCols<C>>(vf, lre[c], lim[c], t, tw);
+    fft_line<L, E, LdsCols<C>>(vf, lre[c], lim[c], fresh_index(t), tw);
 #pragma unroll
     for (int m = 0; m < E; ++m) vf[m] = cmul(vf[m], vd[m]);          // X2 = F DC
-    fft_line<L, E, LdsCols<C>>(vg, lre[c], lim[c], t, tw);
+    fft_line<L, E, LdsCols<C>>(vg, lre[c], lim[c], fresh_index(t), tw);
 #pragma unroll
     for (int m = 0; m < E; ++m) vg[m] = cmulcj(vd[m], vg[m]);        // X1 = conj(DC) G'
-    ifft_line<L, E, LdsCols<C>>(vg, lre[c], lim[c], t, tw);
-    ifft_line<L, E, LdsCols<C>>(vf, lre[c], lim[c], t, tw);
+    ifft_line<L, E, LdsCols<C>>(vg, lre[c], lim[c], fresh_index(t), tw);
+    ifft_line<L, E, LdsCols<C>>(vf, lre[c], lim[c], fresh_index(t), tw);
     if (col > H) return;
 #pragma unroll
     for (int m = 0; m < 2 * E / 3; ++m)
@@ -335,9 +335,9 @@ __global__ __launch_bounds__(256) void kb_polar(const float2* __restrict__ A,
                 v[m] = make_float2(0.f, 0.f);
             }
         }
-        fft_line<L, kEb>(v, lre[line], lim[line], t, tw);
+        fft_line<L, kEb>(v, lre[line], lim[line], fresh_index(t), tw);
         float2 mir[kEb];
-        mirror_line<L, kEb>(v, mir, lre[line], lim[line], t);
+        mirror_line<L, kEb>(v, mir, lre[line], lim[line], fresh_index(t));
 #pragma unroll
         for (int m = 0; m < kEb; ++m) {
             const float2 Pf = split_x(v[m], mir[m]), Pg = split_y(v[m], mir[m]);
@@ -345,7 +345,7 @@ __global__ __launch_bounds__(256) void kb_polar(const float2* __restrict__ A,
             const float2 c = cmul(Pf, D[m]);
             v[m] = make_float2(a.x - c.y, a.y + c.x);   // a + i c
         }
-        ifft_line<L, kEb>(v, lre[line], lim[line], t, tw);
+        ifft_line<L, kEb>(v, lre[line], lim[line], fresh_index(t), tw);
         if (live) {   // (dP_f, dP_g) interleaved: the transpose gathers both at once
             float2* o = dpol + ((size_t)b * n_r + rad) * NT;
 #pragma unroll
@@ -456,16 +456,16 @@ __global__ __launch_bounds__(C * N / kEb) void kb_cols_mag(float4* __restrict__ 
         vf[m] = make_float2(q.x, q.y);
         vg[m] = make_float2(q.z, q.w);
     }
-    fft_line<L, kEb, LdsCols<C>>(vf, lre[c], lim[c], t, tw);
-    fft_line<L, kEb, LdsCols<C>>(vg, lre[c], lim[c], t, tw);
+    fft_line<L, kEb, LdsCols<C>>(vf, lre[c], lim[c], fresh_index(t), tw);
+    fft_line<L, kEb, LdsCols<C>>(vg, lre[c], lim[c], fresh_index(t), tw);
 #pragma unroll
     for (int m = 0; m < kEb; ++m) {
         const float2 d = col <= H ? da[(t + m * T) * PA + col] : make_float2(0.f, 0.f);
         vf[m] = mag_adjoint(vf[m], d.x);
         vg[m] = mag_adjoint(vg[m], d.y);
     }
-    ifft_line<L, kEb, LdsCols<C>>(vf, lre[c], lim[c], t, tw);
-    ifft_line<L, kEb, LdsCols<C>>(vg, lre[c], lim[c], t, tw);
+    ifft_line<L, kEb, LdsCols<C>>(vf, lre[c], lim[c], fresh_index(t), tw);
+    ifft_line<L, kEb, LdsCols<C>>(vg, lre[c], lim[c], fresh_index(t), tw);
     if (col > H) return;
 #pragma unroll
     for (int m = 0; m < kEb; ++m)
@@ -519,11 +519,7 @@ __global__ __launch_bounds__(256) void kb_rotate_adj(const float* __restrict__ d
     }
     const int by0 = (int)floorf(ymin - e) - 1, bx0 = (int)floorf(xmin - e) - 1;
     const int bh = min(kRotBox, (int)floorf(ymax + e) + 2 - by0), bw = min(kRotBox, (int)floorf(xmax + e) + 2 - bx0);
-    const float* src = dgp + (size_t)b * N * N;
-    for (int k = threadIdx.x; k < bh * bw; k += 256) {
-        const int r = by0 + k / bw, c = bx0 + k % bw;
-        box[k] = (r >= 0 && r < N && c >= 0 && c < N) ? src[(size_t)r * N + c] : 0.f;
-    }
+    stage_box<false, false>(box, dgp + (size_t)b * N * N, nullptr, nullptr, N, by0, bx0, bh, bw);
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kRotTY * kRotTX / 256; ++k) {
@@ -549,7 +545,7 @@ __global__ __launch_bounds__(256) void kb_rotate_adj(const float* __restrict__ d
                 const int r = i - by0, c = j - bx0;
                 if (ey < 1.f && ex < 1.f && i >= 0 && i < N && j >= 0 && j < N && r >= 0 && r < bh && c >= 0 &&
                     c < bw)
-                    acc += (1.f - ey) * (1.f - ex) * box[r * bw + c];
+                    acc += (1.f - ey) * (1.f - ex) * box[r * kRotBox + c];
             }
         dgr[(size_t)b * N * N + (size_t)qr * N + qc] = acc;
     }

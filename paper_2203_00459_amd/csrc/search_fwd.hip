@@ -105,8 +105,8 @@ __global__ __launch_bounds__(C * N / kE) void k_cols1(const float4* __restrict__
         vf[m] = make_float2(q.x, q.y);
         vg[m] = make_float2(q.z, q.w);
     }
-    fft_line<L, kE, LdsCols<C>>(vf, lre[c], lim[c], t, tw);
-    fft_line<L, kE, LdsCols<C>>(vg, lre[c], lim[c], t, tw);
+    fft_line<L, kE, LdsCols<C>>(vf, lre[c], lim[c], fresh_index(t), tw);
+    fft_line<L, kE, LdsCols<C>>(vg, lre[c], lim[c], fresh_index(t), tw);
     if (col > H) return;   // padding lane of the last tile (no barriers follow)
     float2* dst = A + (size_t)b * N * PA;
 #pragma unroll
@@ -156,9 +156,9 @@ __global__ __launch_bounds__(256) void k_polar(const float2* __restrict__ A,
                 v[m] = make_float2(0.f, 0.f);
             }
         }
-        fft_line<L, kE>(v, lre[line], lim[line], t, tw);
+        fft_line<L, kE>(v, lre[line], lim[line], fresh_index(t), tw);
         float2 mir[kE];
-        mirror_line<L, kE>(v, mir, lre[line], lim[line], t);
+        mirror_line<L, kE>(v, mir, lre[line], lim[line], fresh_index(t));
 #pragma unroll
         for (int m = 0; m <= kE / 2; ++m) {
             const float2 Xf = split_x(v[m], mir[m]);
@@ -408,9 +408,12 @@ __global__ __launch_bounds__(256) void k_rotate(const float* __restrict__ g, con
     }
     const int by0 = (int)floorf(ymin) - 1, bx0 = (int)floorf(xmin) - 1;
     const int bh = min(kRotBox, (int)floorf(ymax) + 3 - by0), bw = min(kRotBox, (int)floorf(xmax) + 3 - bx0);
-    for (int k = threadIdx.x; k < bh * bw; k += 256) {
-        const int r = by0 + k / bw, c = bx0 + k % bw;
-        box[k] = (r >= 0 && r < N && c >= 0 && c < N) ? scan_w(sc.g, sc.mg, hann, N, r, c, win) : 0.f;
+    if (sc.mg) {
+        if (win) stage_box<true, true>(box, sc.g, sc.mg, hann, N, by0, bx0, bh, bw);
+        else stage_box<true, false>(box, sc.g, sc.mg, hann, N, by0, bx0, bh, bw);
+    } else {
+        if (win) stage_box<false, true>(box, sc.g, nullptr, hann, N, by0, bx0, bh, bw);
+        else stage_box<false, false>(box, sc.g, nullptr, hann, N, by0, bx0, bh, bw);
     }
     __syncthreads();
     float* go = gr + (size_t)b * N * N;
@@ -430,7 +433,7 @@ __global__ __launch_bounds__(256) void k_rotate(const float* __restrict__ g, con
 #pragma unroll
             for (int dx = 0; dx < 2; ++dx) {
                 const int r = y0 + dy, c = x0 + dx;
-                G[dy][dx] = (r >= 0 && r < bh && c >= 0 && c < bw) ? box[r * bw + c] : 0.f;
+                G[dy][dx] = (r >= 0 && r < bh && c >= 0 && c < bw) ? box[r * kRotBox + c] : 0.f;
             }
         float acc = 0.f;
 #pragma unroll
@@ -477,11 +480,11 @@ __global__ __launch_bounds__(C * pad2(N) / kE2) void k_cols2(const float4* __res
             vf[m] = vg[m] = make_float2(0.f, 0.f);
         }
     }
-    fft_line<L, E, LdsCols<C>>(vf, lre[c], lim[c], t, tw);
-    fft_line<L, E, LdsCols<C>>(vg, lre[c], lim[c], t, tw);
+    fft_line<L, E, LdsCols<C>>(vf, lre[c], lim[c], fresh_index(t), tw);
+    fft_line<L, E, LdsCols<C>>(vg, lre[c], lim[c], fresh_index(t), tw);
 #pragma unroll
     for (int m = 0; m < E; ++m) vf[m] = cmulcj(vf[m], vg[m]);
-    ifft_line<L, E, LdsCols<C>>(vf, lre[c], lim[c], t, tw);
+    ifft_line<L, E, LdsCols<C>>(vf, lre[c], lim[c], fresh_index(t), tw);
     if (col > H) return;
     float2* dst = out + (size_t)b * N * P3;
 #pragma unroll
