@@ -103,11 +103,17 @@ __device__ __forceinline__ void dft_r<8>(float2 (&v)[8]) { dft8(v); }
 //   column tiles (lanes vary the column fastest, C columns per tile): one
 //     spare word per 8 elements and a line stride of 32/C words mod 32.
 struct LdsRows {
+    static constexpr bool kLinear = false;
     __device__ __forceinline__ static int at(int i) { return i ^ ((i >> 3) & 31); }
     __host__ __device__ static constexpr int words(int L) { return L <= 128 ? L + 16 : L; }
 };
 template <int C>
 struct LdsCols {
+    // at(b + c) = at(b) + lin(c) for b >= 0 and c a multiple of 8 (more
+    // generally whenever (b mod 8) + (c mod 8) < 8): a stage's addresses are
+    // one per-thread base plus constants (LDS immediate offsets).
+    static constexpr bool kLinear = true;
+    __host__ __device__ static constexpr int lin(int c) { return c + (c >> 3); }
     __device__ __forceinline__ static int at(int i) { return i + (i >> 3); }
     __host__ __device__ static constexpr int words(int L) {
         return L + L / 8 + ((32 / C - (L + L / 8)) % 32 + 32) % 32;
@@ -149,6 +155,14 @@ struct NumStages {
     static constexpr int value = NumStagesFrom<L, E>::value;
 };
 
+// LDS word of line element i = b + c (b per thread, c a compile-time constant
+// after unrolling): at(b) + lin(c) for layouts that allow it, else at(i).
+template <class Lay>
+__device__ __forceinline__ int lds_index(int b, int i, int c) {
+    if constexpr (Lay::kLinear) return Lay::at(b) + Lay::lin(c);
+    else return Lay::at(i);
+}
+
 // One Stockham stage.  FIRST reads the inputs from registers, LAST writes the
 // outputs to registers; otherwise they go through the LDS line (re, im).
 template <int L, int E, int S, bool FIRST, bool LAST, class Lay>
@@ -160,6 +174,8 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[E], float* re, float* im, 
     constexpr int Q = E / R;          // butterflies per thread
     constexpr int LR = L / R;
     static_assert(E % R == 0 && (Ns & (Ns - 1)) == 0, "radix divides E; the radix-3 stage comes last");
+    static_assert(!Lay::kLinear || (T % 8 == 0 && LR % 8 == 0 && (T & (T - 1)) == 0),
+                  "linear LDS addressing needs T and L/R multiples of 8 and T a power of two");
     float2 out[Q][R];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -170,7 +186,7 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[E], float* re, float* im, 
             if (FIRST) {
                 x[r] = v[q + r * Q];
             } else {
-                const int idx = Lay::at(j + r * LR);
+                const int idx = lds_index<Lay>(t, j + r * LR, q * T + r * LR);
                 x[r] = make_float2(re[idx], im[idx]);
             }
         }
@@ -190,6 +206,13 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[E], float* re, float* im, 
     }
     if (!LAST) {
         __syncthreads();   // every read of this stage is done before the line is overwritten
+        // write index (j / Ns) Ns R + (j mod Ns) + r Ns with j = t + q T, as a
+        // per-thread base w0 plus a constant: for Ns <= T (Ns | T) it is
+        // w0 = (t / Ns) Ns R + (t mod Ns) plus q T R + r Ns; for Ns > T (T | Ns)
+        // it is t plus (q T / Ns) Ns R + (q T mod Ns) + r Ns.  In both cases
+        // (w0 mod 8) + (constant mod 8) < 8, so LdsCols stays linear.
+        constexpr bool small = Ns <= T;
+        const int w0 = small ? (t / Ns) * Ns * R + (t & (Ns - 1)) : t;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int j = t + q * T;
@@ -197,7 +220,8 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[E], float* re, float* im, 
             const int base = (j / Ns) * Ns * R + k;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const int idx = Lay::at(base + r * Ns);
+                const int c = small ? q * T * R + r * Ns : (q * T / Ns) * Ns * R + (q * T) % Ns + r * Ns;
+                const int idx = lds_index<Lay>(w0, base + r * Ns, c);
                 re[idx] = out[q][r].x;
                 im[idx] = out[q][r].y;
             }
@@ -232,7 +256,7 @@ struct FFTStages<L, E, NS, NS, Lay> {
 // they are recomputed per transform, a few integer instructions per stage.
 __device__ __forceinline__ int fresh_index(int t) {
     asm volatile("" : "+v"(t));
-    return t;
+    return t & 1023;   // restores the known range (t < 1024): unsigned index arithmetic
 }
 
 // Forward DFT of one line, in registers.  All threads of the block must call
