@@ -521,6 +521,15 @@ __global__ __launch_bounds__(256) void kb_rotate_adj(const float* __restrict__ d
     const int bh = min(kRotBox, (int)floorf(ymax + e) + 2 - by0), bw = min(kRotBox, (int)floorf(xmax + e) + 2 - bx0);
     stage_box<false, false>(box, dgp + (size_t)b * N * N, nullptr, nullptr, N, by0, bx0, bh, bw);
     __syncthreads();
+    // sample-position offsets of the 3 x 3 window, the same for every pixel of the pair
+    float ky[3][3], kx[3][3];
+#pragma unroll
+    for (int di = -1; di <= 1; ++di)
+#pragma unroll
+        for (int dj = -1; dj <= 1; ++dj) {
+            ky[di + 1][dj + 1] = (float)di * ct + (float)dj * st;
+            kx[di + 1][dj + 1] = (float)dj * ct - (float)di * st;
+        }
 #pragma unroll
     for (int k = 0; k < kRotTY * kRotTX / 256; ++k) {
         const int p = threadIdx.x + 256 * k;
@@ -528,25 +537,28 @@ __global__ __launch_bounds__(256) void kb_rotate_adj(const float* __restrict__ d
         // the gather of rotate_adjoint, reading the box: every output pixel whose
         // sample position lies within the unit box of q is within one lattice step
         // of round(R^T (q - c) + c), so a fixed 3 x 3 window in row order visits
-        // the same contributors in the same order
+        // the same contributors in the same order.  The window lies inside the
+        // box (its margins cover a rounding step and a lattice step), and the
+        // box holds zeros for output positions outside the scan.
         const float ox = (float)(qc - N / 2), oy = (float)(qr - N / 2);
         const float cx = ct * ox + st * oy + (float)(N / 2);
         const float cy = -st * ox + ct * oy + (float)(N / 2);
         const int ic = (int)rintf(cy), jc = (int)rintf(cx);
+        float py0, px0;
+        rot_src(N, ic, jc, ct, st, py0, px0);
+        const int r0 = ic - 1 - by0, c0w = jc - 1 - bx0;
+        const bool inside = (unsigned)r0 <= (unsigned)(bh - 3) && (unsigned)c0w <= (unsigned)(bw - 3);
+        const float* w = box + (inside ? r0 * kRotBox + c0w : 0);
         float acc = 0.f;
 #pragma unroll
-        for (int di = -1; di <= 1; ++di)
+        for (int di = 0; di < 3; ++di)
 #pragma unroll
-            for (int dj = -1; dj <= 1; ++dj) {
-                const int i = ic + di, j = jc + dj;
-                float py, px;
-                rot_src(N, i, j, ct, st, py, px);
-                const float ey = fabsf(py - (float)qr), ex = fabsf(px - (float)qc);
-                const int r = i - by0, c = j - bx0;
-                if (ey < 1.f && ex < 1.f && i >= 0 && i < N && j >= 0 && j < N && r >= 0 && r < bh && c >= 0 &&
-                    c < bw)
-                    acc += (1.f - ey) * (1.f - ex) * box[r * kRotBox + c];
+            for (int dj = 0; dj < 3; ++dj) {
+                const float ey = fabsf(py0 + ky[di][dj] - (float)qr), ex = fabsf(px0 + kx[di][dj] - (float)qc);
+                const float v = w[di * kRotBox + dj];
+                if (ey < 1.f && ex < 1.f) acc += (1.f - ey) * (1.f - ex) * v;
             }
+        if (!inside) acc = 0.f;   // unreachable by the box bounds; keeps every LDS read in the box
         dgr[(size_t)b * N * N + (size_t)qr * N + qc] = acc;
     }
 }

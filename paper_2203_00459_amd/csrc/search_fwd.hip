@@ -427,14 +427,16 @@ __global__ __launch_bounds__(256) void k_rotate(const float* __restrict__ g, con
         const float fy = floorf(py), fx = floorf(px);
         const float wy = py - fy, wx = px - fx;
         const int y0 = (int)fy - by0, x0 = (int)fx - bx0;
+        // the 2 x 2 cell lies inside the box (its margins cover the tile's
+        // extreme sample positions); one check keeps every LDS read in it
+        const bool inside = (unsigned)y0 <= (unsigned)(bh - 2) && (unsigned)x0 <= (unsigned)(bw - 2);
+        const float* cell = box + (inside ? y0 * kRotBox + x0 : 0);
+        const float s = inside ? 1.f : 0.f;
         float G[2][2];
 #pragma unroll
         for (int dy = 0; dy < 2; ++dy)
 #pragma unroll
-            for (int dx = 0; dx < 2; ++dx) {
-                const int r = y0 + dy, c = x0 + dx;
-                G[dy][dx] = (r >= 0 && r < bh && c >= 0 && c < bw) ? box[r * kRotBox + c] : 0.f;
-            }
+            for (int dx = 0; dx < 2; ++dx) G[dy][dx] = s * cell[dy * kRotBox + dx];
         float acc = 0.f;
 #pragma unroll
         for (int dy = 0; dy < 2; ++dy)
