@@ -71,9 +71,12 @@ def measured_traffic(kernel: str):
     return None
 
 
-def kernel_bytes(n: int, n_theta: int, n_r: int, batch: int, masked: bool) -> dict:
+def kernel_bytes(n: int, n_theta: int, n_r: int, batch: int, masked: bool, keep: bool = False) -> dict:
     """Algorithmic HBM bytes per launch of each kernel: compulsory reads of its
-    inputs plus writes of its outputs, each touched once (float32 / complex64)."""
+    inputs plus writes of its outputs, each touched once (float32 / complex64).
+    keep: the training forward keeps its intermediates for the adjoint (k_rotate
+    runs once and also writes d g'/d theta; kb_rows_fwd2 transforms only the
+    d c_xy lag rows; k_rows1 / k_cols1 run once)."""
     N2 = n * n
     nrb = (n_r + 7) // 8
     hk = n_theta // 2 + 1
@@ -90,14 +93,14 @@ def kernel_bytes(n: int, n_theta: int, n_r: int, batch: int, masked: bool) -> di
         "k_cols1": batch * (half + mag),
         "k_polar": batch * (mag + nrb * hk * 8),
         "k_angle_fin": batch * (nrb * hk * 8 + n_theta * 4),
-        # k_rotate runs twice per step: forward (g' only) and adjoint (g' and d g'/d theta)
-        "k_rotate": batch * (m * 4 * N2 + 6 * N2),
+        # without keep k_rotate runs twice per step: forward (g') and adjoint (g', d g'/d theta)
+        "k_rotate": batch * (m * 4 * N2 + (8 * N2 if keep else 6 * N2)),
         "k_rows2": batch * (m * 4 * N2 + 4 * N2 + rows2),
         "k_cols2": batch * (rows2 + lag),
         "k_rows3": batch * (lag + N2 * 4),
         "k_xy_fin": batch * 64,
-        # adjoint (k_rows1 and k_cols1 run again to recompute the stage-1 spectra)
-        "kb_rows_fwd2": batch * (m * 4 * N2 + 4 * N2 + 4 * N2 + rows2 + lag),
+        # adjoint (without keep, k_rows1 and k_cols1 run again to recompute the stage-1 spectra)
+        "kb_rows_fwd2": batch * (4 * N2 + lag) if keep else batch * (m * 4 * N2 + 4 * N2 + 4 * N2 + rows2 + lag),
         "kb_cols_xy": batch * (rows2 + lag + rows2),
         "kb_rows_xy": batch * (rows2 + 4 * N2 + 2 * N2 * 4),
         "kb_rotate_adj": batch * (4 * N2 + 4 * N2),
@@ -209,7 +212,7 @@ def train_bench(args) -> int:
     per_step = {k: t / args.steps for k, (t, c) in prof.items()}
     dom = max(per_step, key=per_step.get)
     mk = mask_kernel_model(2 * B, n, levels)
-    sb = kernel_bytes(n, kw["n_theta"], n, B, masked=True)
+    sb = kernel_bytes(n, kw["n_theta"], n, B, masked=True, keep=True)
     if dom in mk:
         byts, flops = mk[dom]
     else:
@@ -369,7 +372,8 @@ def search_bench(args) -> int:
         del src, dst
 
     def step():
-        o = s.forward(f, g)
+        # the training pair: the forward keeps its intermediates, the adjoint reads them
+        o = s.forward(f, g, keep=with_bwd)
         if with_bwd:
             s.backward(f, g, None, None, o, d_pose)
 
@@ -393,7 +397,7 @@ def search_bench(args) -> int:
     fmbym.profile_enable(0)
     per_kernel = {k: (t / c) for k, (t, c) in prof.items()}
     dom = max(prof, key=lambda k: prof[k][0])
-    kb = kernel_bytes(n, nt, n, B, masked=False)
+    kb = kernel_bytes(n, nt, n, B, masked=False, keep=with_bwd)
     achieved = kb[dom] / (per_kernel[dom] * 1e-3) / 1e9 if dom in kb else None
 
     res = {
@@ -411,7 +415,7 @@ def search_bench(args) -> int:
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "batch": B, "n": n, "n_theta": nt,
-                   "pass": "fwd+bwd" if with_bwd else "fwd"},
+                   "pass": "fwd+bwd (forward keeps its intermediates for the adjoint)" if with_bwd else "fwd"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": None if achieved is None else achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(dom) if args.workload == "batch512" else None,

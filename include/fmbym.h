@@ -120,6 +120,34 @@ FMBYM_API int fmbym_search_backward(fmbym_plan plan, int32_t batch, const float*
                           const float* d_pose, float* d_f, float* d_g, float* d_m_f, float* d_m_g,
                           void* workspace, size_t workspace_bytes, void* stream);
 
+/* ---------------------------------------------------------------- training pair
+ *
+ * A forward that keeps its intermediates for the adjoint: the stage-1 row
+ * spectra and magnitudes |F| (Eq. 5-7), the rotated scan g' = Rotate(g_w)
+ * with its heading derivative dg'/dtheta, and the stage-2 row spectra (Eq. 9).
+ * fmbym_search_backward_state reads them instead of recomputing them, which
+ * removes the stage-1 transforms and the rotation from the adjoint.  Results
+ * are those of fmbym_search / fmbym_search_backward up to FP32 rounding order.
+ *   state  device buffer of fmbym_search_state_size() bytes, owned by the
+ *          caller; written by fmbym_search_train, only read by the adjoint (which
+ *          may be called on it any number of times); layout private.
+ * Same memory, stream and error rules as above; c_theta, c_xy and saved are
+ * required. */
+FMBYM_API size_t fmbym_search_state_size(fmbym_plan plan, int32_t batch);
+FMBYM_API int fmbym_search_train(fmbym_plan plan, int32_t batch, const float* f, const float* g,
+                                 const float* m_f, const float* m_g, float* pose, float* c_theta,
+                                 float* c_xy, float* saved, void* state, size_t state_bytes,
+                                 void* workspace, size_t workspace_bytes, void* stream);
+/* Adjoint of fmbym_search_train (same inputs, its outputs and state); the
+ * workspace is that of fmbym_search_workspace_size(plan, batch, 1). */
+FMBYM_API int fmbym_search_backward_state(fmbym_plan plan, int32_t batch, const float* f,
+                                          const float* g, const float* m_f, const float* m_g,
+                                          const float* pose, const float* c_theta, const float* c_xy,
+                                          const float* saved, const void* state, size_t state_bytes,
+                                          const float* d_pose, float* d_f, float* d_g, float* d_m_f,
+                                          float* d_m_g, void* workspace, size_t workspace_bytes,
+                                          void* stream);
+
 /* ---------------------------------------------------------------- ragged work lists
  *
  * A serving batch whose pairs come at several scan sizes (the method is timed

@@ -97,21 +97,35 @@ struct FwdLayout {
 };
 FwdLayout fwd_layout(const fmbym_params& p, int batch);
 
+// Intermediates a training forward keeps in the caller's state buffer, so that
+// its adjoint reads them instead of recomputing them.
+struct Keep {
+    float4* r1;    // stage-1 row spectra [B][n][pitch_rows1] float4
+    float2* mag;   // stage-1 magnitudes [B][n][pitch_mag] float2
+    float* gr;     // g' = Rotate(g_w) [B][n][n]
+    float* jac;    // d g' / d theta [B][n][n]
+    float4* r2;    // stage-2 row spectra [B][n][pitch_rows2] float4
+};
+size_t keep_bytes(const fmbym_params& p, int batch);
+Keep keep_pointers(const fmbym_params& p, int batch, void* state);
+
 // tab: null for packed batches (scan b at x + b n^2), else a device table of
-// 4 pointers per pair, (f, g, m_f, m_g), for a ragged work list.
+// 4 pointers per pair, (f, g, m_f, m_g), for a ragged work list.  keep: null,
+// or where the forward leaves its intermediates for the adjoint.
 int launch_forward(const Plan& pl, int batch, const float* f, const float* g, const float* mf,
                    const float* mg, float* pose, float* c_theta, float* c_xy, float* saved,
-                   char* ws, hipStream_t s, const float* const* tab = nullptr);
+                   char* ws, hipStream_t s, const float* const* tab = nullptr, const Keep* keep = nullptr);
 
 // Stage-1 row DFTs and |F| (k_rows1, k_cols1), shared by forward and adjoint.
 void launch_stage1_spectra(const Plan& pl, int batch, const float* f, const float* g, const float* mf,
                            const float* mg, float4* r1, float2* mag, hipStream_t s);
 
 size_t bwd_workspace(const fmbym_params& p, int batch);
+// keep: null (recompute the spectra and g'), or the state of a training forward.
 int launch_backward(const Plan& pl, int batch, const float* f, const float* g, const float* mf,
                     const float* mg, const float* pose, const float* c_theta, const float* c_xy,
                     const float* saved, const float* d_pose, float* d_f, float* d_g, float* d_mf,
-                    float* d_mg, char* ws, hipStream_t s);
+                    float* d_mg, char* ws, hipStream_t s, const Keep* keep = nullptr);
 
 // ------------------------------------------------------------------ sampling
 

@@ -72,18 +72,19 @@ __global__ __launch_bounds__(256) void kb_rows_fwd2(
     const float* __restrict__ mg, const float* __restrict__ hann, const float2* __restrict__ tw,
     const float* __restrict__ saved, const float* __restrict__ c_xy, const float* __restrict__ d_pose,
     const float* __restrict__ gr, float4* __restrict__ rf, float2* __restrict__ rdc, int win, int batch,
-    float temp, float delta) {
+    float temp, float delta, int block0) {
     constexpr int L = pad2(N), E = kE2, T = L / E, LPB = 256 / T, H = L / 2, P2 = pitch_rows2(N),
                   P3 = pitch_lag(N);
     __shared__ float lre[LPB][LdsRows::words(L)];
     __shared__ float lim[LPB][LdsRows::words(L)];
     const int line = threadIdx.x / T, t = threadIdx.x % T;
     const int nscan_blocks = batch * N / LPB;
-    const bool scan_rows = (int)blockIdx.x < nscan_blocks;   // block-uniform
+    const int bid = (int)blockIdx.x + block0;   // block0 > 0 skips the scan rows
+    const bool scan_rows = bid < nscan_blocks;   // block-uniform
     float2 v[E];
     int grow = 0, gl = 0, b = 0, q = 0;
     if (scan_rows) {
-        grow = blockIdx.x * LPB + line;
+        grow = bid * LPB + line;
         b = grow / N;
         const int i = grow % N;
         const size_t base = (size_t)b * N * N;
@@ -99,7 +100,7 @@ __global__ __launch_bounds__(256) void kb_rows_fwd2(
             }
         }
     } else {
-        gl = (blockIdx.x - nscan_blocks) * LPB + line;   // lag-row pair
+        gl = (bid - nscan_blocks) * LPB + line;   // lag-row pair
         b = gl / (N / 2);
         q = gl % (N / 2);
         const XyAdj adj = make_xy_adj(saved + (size_t)b * FMBYM_SAVED, d_pose + b * 3, temp, delta);
@@ -138,9 +139,9 @@ __global__ __launch_bounds__(256) void kb_rows_fwd2(
 
 // Column pass of the translation adjoint over columns 0 .. 3n/4: forward
 // 3n/2-point column DFTs of F, G' and DC, then X1 = conj(DC) G' and X2 = F DC,
-// inverse column DFTs; the n data rows of (X1, X2) overwrite (F, G') in place.
+// inverse column DFTs; the n data rows of (X1, X2) go to out (which may be rf).
 template <int N, int C>
-__global__ __launch_bounds__(C * pad2(N) / kE2) void kb_cols_xy(float4* __restrict__ rf,
+__global__ __launch_bounds__(C * pad2(N) / kE2) void kb_cols_xy(const float4* rf, float4* out,
                                                                 const float2* __restrict__ rdc,
                                                                 const float2* __restrict__ tw,
                                                                 int batch) {
@@ -155,7 +156,8 @@ __global__ __launch_bounds__(C * pad2(N) / kE2) void kb_cols_xy(float4* __restri
     const int c = threadIdx.x % C, t = threadIdx.x / C;
     const int tile = work % TILES, b = work / TILES;
     const int col = tile * C + c;
-    float4* sf = rf + (size_t)b * N * P2;
+    const float4* sf = rf + (size_t)b * N * P2;   // may equal out: a block reads its columns first
+    float4* so = out + (size_t)b * N * P2;
     const float2* sd = rdc + (size_t)b * N * P3;
     float2 vd[E];
 #pragma unroll
@@ -189,7 +191,7 @@ __global__ __launch_bounds__(C * pad2(N) / kE2) void kb_cols_xy(float4* __restri
     if (col > H) return;
 #pragma unroll
     for (int m = 0; m < 2 * E / 3; ++m)
-        sf[(size_t)(t + m * T) * P2 + col] = make_float4(vg[m].x, vg[m].y, vf[m].x, vf[m].y);
+        so[(size_t)(t + m * T) * P2 + col] = make_float4(vg[m].x, vg[m].y, vf[m].x, vf[m].y);
 }
 
 // Entry k of the full L-point Hermitian spectrum from stored columns 0 .. L/2.
@@ -402,15 +404,41 @@ __global__ __launch_bounds__(256) void kb_dmag(const int* __restrict__ ptr, cons
                 prod[e - c0][h] = make_float4(x[2 * h].x, x[2 * h].y, x[2 * h + 1].x, x[2 * h + 1].y);
         }
         __syncthreads();
+        // this thread's row segment within the chunk, summed by four interleaved
+        // partial sums (entries e = a + 4 i + u into part u), then part 0 + 1 + 2 + 3:
+        // a fixed order, with four independent LDS reads in flight for the long
+        // rows near the spectrum's centre
         const int a = max(my0, c0), z = min(my1, c1);
-        for (int e = a; e < z; ++e) {
+        float2 part[4][kDmagPairs];
 #pragma unroll
-            for (int h = 0; h < kDmagPairs / 2; ++h) {
-                const float4 q = prod[e - c0][h];
-                acc[2 * h] = cadd(acc[2 * h], make_float2(q.x, q.y));
-                acc[2 * h + 1] = cadd(acc[2 * h + 1], make_float2(q.z, q.w));
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int p = 0; p < kDmagPairs; ++p) part[u][p] = make_float2(0.f, 0.f);
+        int e = a;
+        for (; e + 4 <= z; e += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int h = 0; h < kDmagPairs / 2; ++h) {
+                    const float4 q = prod[e + u - c0][h];
+                    part[u][2 * h] = cadd(part[u][2 * h], make_float2(q.x, q.y));
+                    part[u][2 * h + 1] = cadd(part[u][2 * h + 1], make_float2(q.z, q.w));
+                }
+        }
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+            if (e + u < z) {
+#pragma unroll
+                for (int h = 0; h < kDmagPairs / 2; ++h) {
+                    const float4 q = prod[e + u - c0][h];
+                    part[u][2 * h] = cadd(part[u][2 * h], make_float2(q.x, q.y));
+                    part[u][2 * h + 1] = cadd(part[u][2 * h + 1], make_float2(q.z, q.w));
+                }
             }
         }
+#pragma unroll
+        for (int p = 0; p < kDmagPairs; ++p)
+            acc[p] = cadd(acc[p], cadd(cadd(part[0][p], part[1][p]), cadd(part[2][p], part[3][p])));
         __syncthreads();
     }
     if (tid < nrow) {
@@ -435,7 +463,7 @@ __device__ __forceinline__ float2 mag_adjoint(float2 F, float dA) {
 // carries the band gain), unnormalised inverse column DFT.  For columns 0 and
 // n/2 the row pass uses only the real part of the result.
 template <int N, int C>
-__global__ __launch_bounds__(C * N / kEb) void kb_cols_mag(float4* __restrict__ r1,
+__global__ __launch_bounds__(C * N / kEb) void kb_cols_mag(const float4* r1, float4* out,
                                                            const float2* __restrict__ dA,
                                                            const float2* __restrict__ tw, int batch) {
     constexpr int L = N, T = L / kEb, H = N / 2, TILES = H / C + 1, P1 = pitch_rows1(N), PA = pitch_mag(N);
@@ -447,7 +475,8 @@ __global__ __launch_bounds__(C * N / kEb) void kb_cols_mag(float4* __restrict__ 
     if (work >= batch * TILES) return;
     const int tile = work % TILES, b = work / TILES;
     const int col = tile * C + c;
-    float4* src = r1 + (size_t)b * N * P1;
+    const float4* src = r1 + (size_t)b * N * P1;   // may equal out: a block reads its columns first
+    float4* dst = out + (size_t)b * N * P1;
     const float2* da = dA + (size_t)b * N * PA;
     float2 vf[kEb], vg[kEb];
 #pragma unroll
@@ -469,7 +498,7 @@ __global__ __launch_bounds__(C * N / kEb) void kb_cols_mag(float4* __restrict__ 
     if (col > H) return;
 #pragma unroll
     for (int m = 0; m < kEb; ++m)
-        src[(size_t)(t + m * T) * P1 + col] = make_float4(vf[m].x, vf[m].y, vg[m].x, vg[m].y);
+        dst[(size_t)(t + m * T) * P1 + col] = make_float4(vf[m].x, vf[m].y, vg[m].x, vg[m].y);
 }
 
 // Rotate^T of dg' at scan pixel (qr, qc): sum over output pixels whose
@@ -688,7 +717,7 @@ template <int N>
 static int launch_bwd_n(const Plan& pl, int B, const float* f, const float* g, const float* mf,
                         const float* mg, const float* c_theta, const float* c_xy, const float* saved,
                         const float* d_pose, float* d_f, float* d_g, float* d_mf, float* d_mg,
-                        char* ws, hipStream_t s) {
+                        char* ws, hipStream_t s, const Keep* keep) {
     const FwdLayout fl = fwd_layout(pl.p, B);
     const BwdLayout bl = bwd_layout(pl.p, B);
     float4* rf = (float4*)(ws + bl.rf);
@@ -698,24 +727,32 @@ static int launch_bwd_n(const Plan& pl, int B, const float* f, const float* g, c
     float2* dpol = (float2*)(ws + bl.dpol);
     float* dth = (float*)(ws + bl.dth);
     float2* dspec = (float2*)(ws + bl.dspec);
-    float* jac = (float*)(ws + bl.jac);
-    float* gr = (float*)(ws + fl.grot);     // g' for kb_rows_fwd2, later Rotate^T dg'
-    float4* r1 = (float4*)(ws + fl.r1r2);
-    float2* mag = (float2*)(ws + fl.mag_r3);
+    // With keep, the forward's g', J, stage-1 spectra and stage-2 rows are read
+    // from the state (never written); otherwise they are recomputed into the
+    // workspace.  Rotate^T dg', dA and the |F| adjoint's columns go to the workspace.
+    float* jac = keep ? keep->jac : (float*)(ws + bl.jac);
+    float* dgr = (float*)(ws + fl.grot);    // Rotate^T dg' (without keep, g' before it)
+    const float* gr = keep ? keep->gr : dgr;
+    float4* r1w = (float4*)(ws + fl.r1r2);
+    const float4* r1 = keep ? keep->r1 : r1w;
+    float2* magw = (float2*)(ws + fl.mag_r3);
+    const float2* mag = keep ? keep->mag : magw;
+    const float4* rows2 = keep ? keep->r2 : rf;
     const int win = (pl.p.flags & FMBYM_HANN) ? 1 : 0;
     const int win2 = (win && !(pl.p.flags & FMBYM_XY_UNWINDOWED)) ? 1 : 0;
 
     // translation-stage adjoint
     constexpr int T2 = pad2(N) / kE2, LPB2 = rows2_lines(N);
     const int scan_blocks = B * N / LPB2, dc_blocks = B * (N / 2) / LPB2;
-    launch_rotate(pl, B, g, mg, saved, gr, jac, win2, s, nullptr);
-    FMBYM_LAUNCH(kKBRowsFwd2, kb_rows_fwd2<N>, dim3(scan_blocks + dc_blocks), dim3(256), s, f, g, mf, mg,
-                 pl.hann, pl.twiddle3, saved, c_xy, d_pose, gr, rf, rdc, win2, B, pl.p.temp_xy,
-                 pl.p.delta_xy);
+    if (!keep) launch_rotate(pl, B, g, mg, saved, dgr, jac, win2, s, nullptr);
+    const int skip = keep ? scan_blocks : 0;   // with keep only the dc_xy lag rows are transformed
+    FMBYM_LAUNCH(kKBRowsFwd2, kb_rows_fwd2<N>, dim3(scan_blocks + dc_blocks - skip), dim3(256), s, f, g, mf,
+                 mg, pl.hann, pl.twiddle3, saved, c_xy, d_pose, gr, rf, rdc, win2, B, pl.p.temp_xy,
+                 pl.p.delta_xy, skip);
     constexpr int C2 = bcols_xy_tile<N>();
     const int total2 = B * ((pad2(N) / 2) / C2 + 1);
     FMBYM_LAUNCH(kKBColsXy, (kb_cols_xy<N, C2>), dim3(((total2 + 7) / 8) * 8), dim3(C2 * T2), s,
-                 rf, rdc, pl.twiddle3, B);
+                 rows2, rf, rdc, pl.twiddle3, B);
     FMBYM_LAUNCH(kKBRowsXy, kb_rows_xy<N>, dim3(B * N / LPB2), dim3(256), s, rf, jac, pl.twiddle3, df2,
                  dgp, dth);
     const int ppb = N / LPB2;
@@ -731,7 +768,7 @@ static int launch_bwd_n(const Plan& pl, int B, const float* f, const float* g, c
     }
 
     // rotation-stage adjoint: recompute the stage-1 spectra, then transpose
-    launch_stage1_spectra(pl, B, f, g, mf, mg, r1, mag, s);
+    if (!keep) launch_stage1_spectra(pl, B, f, g, mf, mg, r1w, magw, s);
     switch (pl.p.n_theta) {
         case 16: launch_bwd_polar<N, 16>(pl, B, mag, dspec, dpol, s); break;
         case 32: launch_bwd_polar<N, 32>(pl, B, mag, dspec, dpol, s); break;
@@ -742,18 +779,18 @@ static int launch_bwd_n(const Plan& pl, int B, const float* f, const float* g, c
         case 1024: launch_bwd_polar<N, 1024>(pl, B, mag, dspec, dpol, s); break;
         default: return FMBYM_EUNSUPPORTED;
     }
-    float2* dA = mag;                   // the recomputed magnitudes are dead after kb_polar
+    float2* dA = magw;                  // (recomputed magnitudes are dead after kb_polar)
     FMBYM_LAUNCH(kKBDmag, kb_dmag, dim3(pl.dmag_nparts, (B + kDmagPairs - 1) / kDmagPairs), dim3(256), s,
                  pl.csr_ptr, pl.csr_col, pl.csr_val, pl.csr_dst, pl.dmag_part, dpol, dA, N, pl.p.n_r,
                  pl.p.n_theta, B);
     constexpr int C = bcols_mag_tile<N>();
     const int tiles_mag = B * ((N / 2) / C + 1);
     FMBYM_LAUNCH(kKBColsMag, (kb_cols_mag<N, C>), dim3(((tiles_mag + 7) / 8) * 8), dim3(C * N / kEb), s, r1,
-                 dA, pl.twiddle, B);
+                 r1w, dA, pl.twiddle, B);
     FMBYM_LAUNCH(kKBRotateAdj, kb_rotate_adj<N>, dim3(B * (N / kRotTY) * (N / kRotTX)), dim3(256), s, dgp,
-                 saved, gr);
+                 saved, dgr);
     constexpr int T1 = N / kEb, LPB1 = 256 / T1;
-    FMBYM_LAUNCH(kKBRowsFinal, kb_rows_final<N>, dim3(B * N / LPB1), dim3(256), s, r1, df2, gr, f, g, mf,
+    FMBYM_LAUNCH(kKBRowsFinal, kb_rows_final<N>, dim3(B * N / LPB1), dim3(256), s, r1w, df2, dgr, f, g, mf,
                  mg, pl.hann, pl.twiddle, saved, d_f, d_g, d_mf, d_mg, win, win2);
     return FMBYM_OK;
 }
@@ -761,17 +798,17 @@ static int launch_bwd_n(const Plan& pl, int B, const float* f, const float* g, c
 int launch_backward(const Plan& pl, int batch, const float* f, const float* g, const float* mf,
                     const float* mg, const float* /*pose*/, const float* c_theta, const float* c_xy,
                     const float* saved, const float* d_pose, float* d_f, float* d_g, float* d_mf,
-                    float* d_mg, char* ws, hipStream_t s) {
+                    float* d_mg, char* ws, hipStream_t s, const Keep* keep) {
     switch (pl.p.n) {
         case 128:
             return launch_bwd_n<128>(pl, batch, f, g, mf, mg, c_theta, c_xy, saved, d_pose, d_f, d_g,
-                                     d_mf, d_mg, ws, s);
+                                     d_mf, d_mg, ws, s, keep);
         case 256:
             return launch_bwd_n<256>(pl, batch, f, g, mf, mg, c_theta, c_xy, saved, d_pose, d_f, d_g,
-                                     d_mf, d_mg, ws, s);
+                                     d_mf, d_mg, ws, s, keep);
         case 512:
             return launch_bwd_n<512>(pl, batch, f, g, mf, mg, c_theta, c_xy, saved, d_pose, d_f, d_g,
-                                     d_mf, d_mg, ws, s);
+                                     d_mf, d_mg, ws, s, keep);
         default: return FMBYM_EUNSUPPORTED;
     }
 }

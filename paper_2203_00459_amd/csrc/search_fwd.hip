@@ -639,6 +639,29 @@ FwdLayout fwd_layout(const fmbym_params& p, int batch) {
     return L;
 }
 
+size_t keep_bytes(const fmbym_params& p, int batch) {
+    const size_t n = p.n, B = batch;
+    return align256(B * n * (size_t)pitch_rows1(p.n) * sizeof(float4)) +
+           align256(B * n * (size_t)pitch_mag(p.n) * sizeof(float2)) + 2 * align256(B * n * n * sizeof(float)) +
+           align256(B * n * (size_t)pitch_rows2(p.n) * sizeof(float4));
+}
+
+Keep keep_pointers(const fmbym_params& p, int batch, void* state) {
+    const size_t n = p.n, B = batch;
+    char* c = (char*)state;
+    Keep k;
+    k.r1 = (float4*)c;
+    c += align256(B * n * (size_t)pitch_rows1(p.n) * sizeof(float4));
+    k.mag = (float2*)c;
+    c += align256(B * n * (size_t)pitch_mag(p.n) * sizeof(float2));
+    k.gr = (float*)c;
+    c += align256(B * n * n * sizeof(float));
+    k.jac = (float*)c;
+    c += align256(B * n * n * sizeof(float));
+    k.r2 = (float4*)c;
+    return k;
+}
+
 // Column-tile widths (measured at 512 x 512): 8 float4 columns read whole 128-byte
 // lines; the 3n/2-point stage-2 columns run better 4 wide (more blocks per CU).
 template <int N> constexpr int cols1_tile() { return N >= 512 ? 8 : 16; }
@@ -682,10 +705,10 @@ static void launch_polar(const Plan& pl, int B, const float2* mag, float2* pth, 
 template <int N>
 static int launch_n(const Plan& pl, int B, const float* f, const float* g, const float* mf,
                     const float* mg, float* pose, float* c_theta, float* c_xy, float* saved,
-                    char* ws, hipStream_t s, const float* const* tab) {
+                    char* ws, hipStream_t s, const float* const* tab, const Keep* keep) {
     const FwdLayout lay = fwd_layout(pl.p, B);
-    float4* r1 = (float4*)(ws + lay.r1r2);
-    float2* mag = (float2*)(ws + lay.mag_r3);
+    float4* r1 = keep ? keep->r1 : (float4*)(ws + lay.r1r2);
+    float2* mag = keep ? keep->mag : (float2*)(ws + lay.mag_r3);
     float2* pth = (float2*)(ws + lay.ptheta);
     float4* pxy = (float4*)(ws + lay.pxy);
     float* sv = saved ? saved : (float*)(ws + lay.saved);
@@ -701,12 +724,13 @@ static int launch_n(const Plan& pl, int B, const float* f, const float* g, const
         default: return FMBYM_EUNSUPPORTED;
     }
     const int win2 = ((pl.p.flags & FMBYM_HANN) && !(pl.p.flags & FMBYM_XY_UNWINDOWED)) ? 1 : 0;
-    float4* r2 = r1;                    // stage-1 rows are dead after k_cols1
-    float2* r3 = mag;                   // magnitudes are dead after k_polar
+    // without keep, stage-1 rows are dead after k_cols1 and magnitudes after k_polar
+    float4* r2 = keep ? keep->r2 : r1;
+    float2* r3 = (float2*)(ws + lay.mag_r3);
     constexpr int T2 = pad2(N) / kE2, LPB2 = rows2_lines(N);
-    float* gr = (float*)(ws + lay.grot);
+    float* gr = keep ? keep->gr : (float*)(ws + lay.grot);
     FMBYM_LAUNCH(kKRotate, k_rotate<N>, dim3(B * (N / kRotTY) * (N / kRotTX)), dim3(256), s, g, mg, pl.hann,
-                 sv, gr, nullptr, win2, tab);
+                 sv, gr, keep ? keep->jac : nullptr, win2, tab);
     FMBYM_LAUNCH(kKRows2, k_rows2<N>, dim3(B * N / LPB2), dim3(256), s, f, g, mf, mg, pl.hann,
                  pl.twiddle3, gr, r2, win2, tab);
     constexpr int C2 = cols2_tile<N>();
@@ -745,11 +769,11 @@ void launch_rotate(const Plan& pl, int B, const float* g, const float* mg, const
 
 int launch_forward(const Plan& pl, int batch, const float* f, const float* g, const float* mf,
                    const float* mg, float* pose, float* c_theta, float* c_xy, float* saved,
-                   char* ws, hipStream_t s, const float* const* tab) {
+                   char* ws, hipStream_t s, const float* const* tab, const Keep* keep) {
     switch (pl.p.n) {
-        case 128: return launch_n<128>(pl, batch, f, g, mf, mg, pose, c_theta, c_xy, saved, ws, s, tab);
-        case 256: return launch_n<256>(pl, batch, f, g, mf, mg, pose, c_theta, c_xy, saved, ws, s, tab);
-        case 512: return launch_n<512>(pl, batch, f, g, mf, mg, pose, c_theta, c_xy, saved, ws, s, tab);
+        case 128: return launch_n<128>(pl, batch, f, g, mf, mg, pose, c_theta, c_xy, saved, ws, s, tab, keep);
+        case 256: return launch_n<256>(pl, batch, f, g, mf, mg, pose, c_theta, c_xy, saved, ws, s, tab, keep);
+        case 512: return launch_n<512>(pl, batch, f, g, mf, mg, pose, c_theta, c_xy, saved, ws, s, tab, keep);
         default: return FMBYM_EUNSUPPORTED;
     }
 }

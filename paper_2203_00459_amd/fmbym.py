@@ -44,7 +44,8 @@ EXPORTS = (
     "fmbym_ragged_launch", "fmbym_ragged_destroy", "fmbym_wall_clock_khz",
     "fmbym_mask_param_count", "fmbym_mask_packed_bytes", "fmbym_mask_bn_channels", "fmbym_mask_pack",
     "fmbym_mask_activation_bytes", "fmbym_mask_fwd", "fmbym_mask_workspace_bytes", "fmbym_mask_bwd",
-    "fmbym_adam", "fmbym_pose_loss",
+    "fmbym_adam", "fmbym_pose_loss", "fmbym_search_state_size", "fmbym_search_train",
+    "fmbym_search_backward_state",
 )
 FMBYM_LOSS_L1 = 1
 FMBYM_LOSS_L2 = 2
@@ -106,6 +107,12 @@ def lib() -> ctypes.CDLL:
         L.fmbym_search.restype = ctypes.c_int
         L.fmbym_search_backward.argtypes = [VP, I32] + [VP] * 13 + [VP, SZ, VP]
         L.fmbym_search_backward.restype = ctypes.c_int
+        L.fmbym_search_state_size.argtypes = [VP, I32]
+        L.fmbym_search_state_size.restype = SZ
+        L.fmbym_search_train.argtypes = [VP, I32] + [VP] * 8 + [VP, SZ, VP, SZ, VP]
+        L.fmbym_search_train.restype = ctypes.c_int
+        L.fmbym_search_backward_state.argtypes = [VP, I32] + [VP] * 8 + [VP, SZ] + [VP] * 5 + [VP, SZ, VP]
+        L.fmbym_search_backward_state.restype = ctypes.c_int
         L.fmbym_strerror.argtypes = [ctypes.c_int]
         L.fmbym_strerror.restype = ctypes.c_char_p
         L.fmbym_last_hip_error.argtypes = []
@@ -194,6 +201,28 @@ def search_backward(plan, batch, f, g, m_f, m_g, pose, c_theta, c_xy, saved, d_p
                                      stream)
     if rc:
         raise FmbymError(rc, "fmbym_search_backward")
+
+
+def search_state_size(plan, batch) -> int:
+    return int(lib().fmbym_search_state_size(plan, int(batch)))
+
+
+def search_train(plan, batch, f, g, m_f, m_g, pose, c_theta, c_xy, saved, state, state_bytes, workspace,
+                 workspace_bytes, stream) -> None:
+    """fmbym_search_train with raw device addresses (ints or None)."""
+    rc = lib().fmbym_search_train(plan, int(batch), f, g, m_f, m_g, pose, c_theta, c_xy, saved, state,
+                                  int(state_bytes), workspace, int(workspace_bytes), stream)
+    if rc:
+        raise FmbymError(rc, "fmbym_search_train")
+
+
+def search_backward_state(plan, batch, f, g, m_f, m_g, pose, c_theta, c_xy, saved, state, state_bytes,
+                          d_pose, d_f, d_g, d_m_f, d_m_g, workspace, workspace_bytes, stream) -> None:
+    rc = lib().fmbym_search_backward_state(plan, int(batch), f, g, m_f, m_g, pose, c_theta, c_xy, saved,
+                                           state, int(state_bytes), d_pose, d_f, d_g, d_m_f, d_m_g,
+                                           workspace, int(workspace_bytes), stream)
+    if rc:
+        raise FmbymError(rc, "fmbym_search_backward_state")
 
 
 def profile_enable(capacity: int) -> None:
@@ -306,9 +335,13 @@ class Search:
             self._ws = torch.empty(need, dtype=torch.uint8, device=device)
         return self._ws
 
-    def forward(self, f, g, m_f=None, m_g=None, surfaces: bool = True) -> dict:
+    def forward(self, f, g, m_f=None, m_g=None, surfaces: bool = True, keep: bool = False) -> dict:
+        """keep=True: the training forward, which also returns ``state`` (the
+        intermediates the adjoint then reads instead of recomputing)."""
         B, n = f.shape[0], self.n
         dev = f.device
+        if keep:
+            return self._forward_keep(f, g, m_f, m_g)
         out = dict(pose=torch.empty(B, 3, device=dev),
                    c_theta=torch.empty(B, self.n_theta, device=dev) if surfaces else None,
                    c_xy=torch.empty(B, n, n, device=dev) if surfaces else None,
@@ -320,13 +353,38 @@ class Search:
                ws.numel(), _stream())
         return out
 
+    def _forward_keep(self, f, g, m_f, m_g) -> dict:
+        B, n = f.shape[0], self.n
+        dev = f.device
+        need = search_state_size(self.plan, B)
+        out = dict(pose=torch.empty(B, 3, device=dev), c_theta=torch.empty(B, self.n_theta, device=dev),
+                   c_xy=torch.empty(B, n, n, device=dev), saved=torch.empty(B, FMBYM_SAVED, device=dev),
+                   state=torch.empty(need, dtype=torch.uint8, device=dev))
+        ws = self.workspace(B, False, dev)
+        search_train(self.plan, B, _ptr(f, (B, n, n), "f"), _ptr(g, (B, n, n), "g"),
+                     _ptr(m_f, (B, n, n), "m_f"), _ptr(m_g, (B, n, n), "m_g"), _ptr(out["pose"]),
+                     _ptr(out["c_theta"]), _ptr(out["c_xy"]), _ptr(out["saved"]), out["state"].data_ptr(),
+                     need, ws.data_ptr(), ws.numel(), _stream())
+        return out
+
     def backward(self, f, g, m_f, m_g, fwd: dict, d_pose) -> dict:
+        """The adjoint; reads fwd["state"] when the forward kept one."""
         B, n = f.shape[0], self.n
         dev = f.device
         res = dict(d_f=torch.empty(B, n, n, device=dev), d_g=torch.empty(B, n, n, device=dev),
                    d_m_f=None if m_f is None else torch.empty(B, n, n, device=dev),
                    d_m_g=None if m_g is None else torch.empty(B, n, n, device=dev))
         ws = self.workspace(B, True, dev)
+        st = fwd.get("state")
+        if st is not None:
+            search_backward_state(self.plan, B, _ptr(f, (B, n, n), "f"), _ptr(g, (B, n, n), "g"),
+                                  _ptr(m_f, (B, n, n), "m_f"), _ptr(m_g, (B, n, n), "m_g"),
+                                  _ptr(fwd["pose"]), _ptr(fwd["c_theta"]), _ptr(fwd["c_xy"]),
+                                  _ptr(fwd["saved"]), st.data_ptr(), st.numel(),
+                                  _ptr(d_pose.contiguous(), (B, 3), "d_pose"), _ptr(res["d_f"]),
+                                  _ptr(res["d_g"]), _ptr(res["d_m_f"]), _ptr(res["d_m_g"]), ws.data_ptr(),
+                                  ws.numel(), _stream())
+            return res
         search_backward(self.plan, B, _ptr(f, (B, n, n), "f"), _ptr(g, (B, n, n), "g"),
                         _ptr(m_f, (B, n, n), "m_f"), _ptr(m_g, (B, n, n), "m_g"),
                         _ptr(fwd["pose"]), _ptr(fwd["c_theta"]), _ptr(fwd["c_xy"]),

@@ -1,7 +1,8 @@
 """Training of the mask network through the differentiable search (Section III-E).
 
 One step (Eq. 10-13): masks m = h_alpha(scan) for both scans of every pair
-(one batched network call, shared weights), the search on the masked scans,
+(one batched network call, shared weights), the search on the masked scans
+(the training forward, which keeps its intermediates for the adjoint),
 the pose loss against the known poses, the search's adjoint down to the masks,
 the network's adjoint down to its parameters, and an Adam update.  Every
 stage runs in the library's kernels; this module only sequences the calls.
@@ -70,7 +71,7 @@ class MaskedSearchTrainer:
         """One training step on device tensors f, g [B, n, n] and target [B, 3];
         returns (loss tensor [1], pose [B, 3])."""
         m_f, m_g = self.masks(f, g, training=True)
-        out = self.search.forward(f, g, m_f, m_g, surfaces=True)
+        out = self.search.forward(f, g, m_f, m_g, keep=True)
         loss, d_pose = fmbym.pose_loss_t(out["pose"], target, self.cfg.loss)
         gr = self.search.backward(f, g, m_f, m_g, out, d_pose)
         d_params = self.net.backward(torch.cat([gr["d_m_f"], gr["d_m_g"]]))
@@ -80,7 +81,7 @@ class MaskedSearchTrainer:
     def gradient(self, f, g, target):
         """dL/dparams of the chain without updating (for checks)."""
         m_f, m_g = self.masks(f, g, training=True)
-        out = self.search.forward(f, g, m_f, m_g, surfaces=True)
+        out = self.search.forward(f, g, m_f, m_g, keep=True)
         loss, d_pose = fmbym.pose_loss_t(out["pose"], target, self.cfg.loss)
         gr = self.search.backward(f, g, m_f, m_g, out, d_pose)
         return loss, self.net.backward(torch.cat([gr["d_m_f"], gr["d_m_g"]]))
