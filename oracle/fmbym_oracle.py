@@ -361,6 +361,43 @@ def search_grad(f, g, d_pose, p: Params, m_f=None, m_g=None) -> dict:
 
 # ------------------------------------------------- plain joint search (Eq. 2)
 
+def joint_headings(n_angles: int) -> torch.Tensor:
+    """Candidate headings of the joint comparator: -pi/2 + k pi / n_angles, k < n_angles
+    (the range of the decoupled search's lag grid, R3, at a coarser step)."""
+    return -math.pi / 2 + torch.arange(n_angles, dtype=F64) * (math.pi / n_angles)
+
+
+def joint_search_rotated(f, g, p: Params, thetas, m_f=None, m_g=None) -> dict:
+    """Brute-force joint search on the translation stage's lag grid (Eq. 2-3 with
+    the search over headings done exhaustively instead of by Eq. 8).
+
+    For every candidate heading theta_k, the stage-2 correlation at that fixed
+    heading, J_k(s') = sum_x fw(x) Rotate(gw, theta_k)(x + s') (Eq. 9); the pose
+    is the hard argmax over (k, s') with t = R(theta_k) s' delta (R9), first
+    maximum in (k, s_y, s_x) order.  J_k(s') = S_k(R(theta_k) s') in the
+    notation of ``joint_scores``.
+    """
+    f = torch.as_tensor(f).to(F64)
+    g = torch.as_tensor(g).to(F64)
+    if m_f is not None:
+        f = f * torch.as_tensor(m_f).to(F64)
+    if m_g is not None:
+        g = g * torch.as_tensor(m_g).to(F64)
+    w = hann2d(p.n) if p.hann else torch.ones(p.n, p.n, dtype=F64)
+    fw, gw = (f, g) if p.xy_unwindowed else (w * f, w * g)
+    thetas = torch.as_tensor(thetas).to(F64)
+    scores = torch.stack([xy_correlation(fw, rotate(gw, th)) for th in thetas])
+    flat = int(torch.argmax(scores.reshape(-1)))
+    k, rem = divmod(flat, p.n * p.n)
+    iy, ix = divmod(rem, p.n)
+    th = thetas[k]
+    tpx, tpy = (ix - p.n // 2) * p.delta_xy, (iy - p.n // 2) * p.delta_xy
+    ct, st = math.cos(float(th)), math.sin(float(th))
+    return dict(scores=scores, peak=scores.reshape(len(thetas), -1).max(dim=1).values, theta=float(th),
+                tx=ct * tpx - st * tpy, ty=st * tpx + ct * tpy, index=(k, iy, ix),
+                pose=torch.tensor([float(th), ct * tpx - st * tpy, st * tpx + ct * tpy], dtype=F64))
+
+
 def joint_scores(fw: torch.Tensor, gw: torch.Tensor, thetas, n_lag: int) -> torch.Tensor:
     """S[k, s_y, s_x] = sum_x fw(x) g(R(theta_k) x + s), the correlative search of Eq. 2-3.
 

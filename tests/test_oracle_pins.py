@@ -344,6 +344,51 @@ def test_decoupled_search_agrees_with_joint_brute_force():
         assert abs(float(dec["ty"]) - joint["ty"]) <= 1.0 + 1e-9
 
 
+def test_rotated_joint_matches_the_direct_joint_sums():
+    """The comparator's scores J_k(s') (rotate g, FFT correlation) against the
+    direct sums of Eq. 2, S_k(s) = sum_x fw(x) gw(R x + s): equal at s' = 0 for
+    any heading, and entry for entry (s = R s') at the headings that map the
+    lattice onto itself (-pi/2 and 0 among joint_headings(4))."""
+    n = 12
+    rng = np.random.Generator(np.random.PCG64(21))
+    f = rng.uniform(0, 1, (n, n))
+    g = rng.uniform(0, 1, (n, n))
+    p = O.Params(n=n, n_theta=16, delta_xy=1.0, hann=True)
+    th = O.joint_headings(4)
+    j = O.joint_search_rotated(f, g, p, th)
+    w = O.hann2d(n)
+    fw, gw = w * torch.from_numpy(f), w * torch.from_numpy(g)
+    S = O.joint_scores(fw, gw, [float(t) for t in th], n + 4)   # lags -n/2-2 .. n/2+1
+    off = n // 2 + 2
+    for k in range(4):
+        assert abs(float(j["scores"][k, n // 2, n // 2] - S[k, off, off])) <= 1e-9 * float(S[k].abs().max())
+    for k in (0, 2):                       # theta = -pi/2 and 0
+        ct, st = round(math.cos(float(th[k]))), round(math.sin(float(th[k])))
+        for iy in range(n):
+            for ix in range(n):
+                sy, sx = iy - n // 2, ix - n // 2
+                rx, ry = ct * sx - st * sy, st * sx + ct * sy
+                ref = S[k, ry + off, rx + off]
+                assert abs(float(j["scores"][k, iy, ix] - ref)) <= 1e-9 * float(S[k].abs().max()), (k, iy, ix)
+
+
+def test_rotated_joint_recovers_a_lattice_pose():
+    """Sparse scene moved by an integer shift at a candidate heading of zero:
+    the comparator's argmax is that heading and shift (Cauchy-Schwarz makes the
+    true alignment the unique maximum)."""
+    n = 16
+    f = np.zeros((n, n))
+    rng = np.random.Generator(np.random.PCG64(5))
+    for _ in range(6):
+        f[rng.integers(5, 11), rng.integers(5, 11)] += rng.uniform(0.5, 1.0)
+    ty, tx = 2, -3
+    g = np.roll(np.roll(f, ty, axis=0), tx, axis=1)       # g(y) = f(y - t): f(x) = g(x + t)
+    p = O.Params(n=n, n_theta=16, delta_xy=0.5, hann=False)
+    j = O.joint_search_rotated(f, g, p, O.joint_headings(8))
+    assert j["theta"] == 0.0
+    assert (j["tx"], j["ty"]) == (tx * 0.5, ty * 0.5)
+
+
 # -------------------------------------------------------------------- gradients
 
 def test_gradient_matches_finite_differences():
