@@ -148,6 +148,23 @@ FMBYM_API int fmbym_search_backward_state(fmbym_plan plan, int32_t batch, const 
                                           float* d_m_g, void* workspace, size_t workspace_bytes,
                                           void* stream);
 
+/* ---------------------------------------------------------------- joint comparator
+ *
+ * The exhaustive search that the decoupling replaces (Eq. 2-3 with the heading
+ * searched by brute force instead of by Eq. 8): for each of n_angles headings
+ * theta_k = -pi/2 + k pi / n_angles, the translation stage's correlation at
+ * that heading, J_k(s') = sum_x f_w(x) Rotate(g_w, theta_k)(x + s') over the
+ * lags s' of c_xy; the pose is the hard argmax over (k, s') (first maximum in
+ * k, then row-major s'), with t = R(theta_k) s' delta_xy.  n_angles times the
+ * stage-2 work of fmbym_search.
+ *   pose  [batch][3] output (required)
+ *   peak  [batch][n_angles] output, max over s' of J_k, or NULL
+ * Windowing and masks as in fmbym_search; 1 <= n_angles <= 4096. */
+FMBYM_API size_t fmbym_joint_workspace_size(fmbym_plan plan, int32_t batch, int32_t n_angles);
+FMBYM_API int fmbym_search_joint(fmbym_plan plan, int32_t batch, int32_t n_angles, const float* f,
+                                 const float* g, const float* m_f, const float* m_g, float* pose,
+                                 float* peak, void* workspace, size_t workspace_bytes, void* stream);
+
 /* ---------------------------------------------------------------- ragged work lists
  *
  * A serving batch whose pairs come at several scan sizes (the method is timed

@@ -168,6 +168,27 @@ int fmbym_search_backward(fmbym_plan plan, int32_t batch, const float* f, const 
     return e == hipSuccess ? FMBYM_OK : hip_fail(e);
 }
 
+size_t fmbym_joint_workspace_size(fmbym_plan plan, int32_t batch, int32_t n_angles) {
+    if (check_call(plan, batch) || n_angles < 1 || n_angles > 4096) return 0;
+    return joint_workspace(plan_cast(plan)->p, batch, n_angles);
+}
+
+int fmbym_search_joint(fmbym_plan plan, int32_t batch, int32_t n_angles, const float* f, const float* g,
+                       const float* m_f, const float* m_g, float* pose, float* peak, void* workspace,
+                       size_t workspace_bytes, void* stream) {
+    int rc = check_call(plan, batch);
+    if (rc) return rc;
+    if (n_angles < 1 || n_angles > 4096 || !f || !g || !pose) return FMBYM_EINVAL;
+    if ((m_f == nullptr) != (m_g == nullptr)) return FMBYM_EINVAL;
+    const Plan* pl = plan_cast(plan);
+    if (!workspace || workspace_bytes < joint_workspace(pl->p, batch, n_angles)) return FMBYM_EWORKSPACE;
+    rc = launch_joint(*pl, batch, n_angles, f, g, m_f, m_g, pose, peak, (char*)workspace,
+                      (hipStream_t)stream);
+    if (rc) return rc;
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? FMBYM_OK : hip_fail(e);
+}
+
 size_t fmbym_search_state_size(fmbym_plan plan, int32_t batch) {
     if (check_call(plan, batch)) return 0;
     return keep_bytes(plan_cast(plan)->p, batch);

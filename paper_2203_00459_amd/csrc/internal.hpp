@@ -116,6 +116,18 @@ int launch_forward(const Plan& pl, int batch, const float* f, const float* g, co
                    const float* mg, float* pose, float* c_theta, float* c_xy, float* saved,
                    char* ws, hipStream_t s, const float* const* tab = nullptr, const Keep* keep = nullptr);
 
+// Stage 2 alone (k_rotate, k_rows2, k_cols2, k_rows3) for `batch` pairs whose
+// heading is in saved[b] (cos, sin); writes c_xy [batch][n][n] and the
+// softmax partials into the forward layout of ws.  tab as for launch_forward.
+void launch_stage2(const Plan& pl, int batch, const float* f, const float* g, const float* mf,
+                   const float* mg, const float* saved, float* c_xy, char* ws, hipStream_t s,
+                   const float* const* tab);
+
+// Joint comparator: K headings -pi/2 + k pi / K, stage 2 at each, hard argmax.
+size_t joint_workspace(const fmbym_params& p, int batch, int n_angles);
+int launch_joint(const Plan& pl, int batch, int n_angles, const float* f, const float* g, const float* mf,
+                 const float* mg, float* pose, float* peak, char* ws, hipStream_t s);
+
 // Stage-1 row DFTs and |F| (k_rows1, k_cols1), shared by forward and adjoint.
 void launch_stage1_spectra(const Plan& pl, int batch, const float* f, const float* g, const float* mf,
                            const float* mg, float4* r1, float2* mag, hipStream_t s);

@@ -702,6 +702,33 @@ static void launch_polar(const Plan& pl, int B, const float2* mag, float2* pth, 
                  pl.twiddle, pl.p.temp_theta, c_theta, pose, saved);
 }
 
+// Stage 2 up to the lag rows: Rotate, the 3n/2-point rows of f_w + i g', the
+// column correlation and the inverse rows (c_xy and the softmax partials in
+// the layout's pxy region).  The heading is read from saved[b].
+template <int N>
+static void stage2_n(const Plan& pl, int B, const float* f, const float* g, const float* mf,
+                     const float* mg, const float* sv, float* c_xy, char* ws, hipStream_t s,
+                     const float* const* tab, const Keep* keep) {
+    const FwdLayout lay = fwd_layout(pl.p, B);
+    const int win2 = ((pl.p.flags & FMBYM_HANN) && !(pl.p.flags & FMBYM_XY_UNWINDOWED)) ? 1 : 0;
+    // without keep, stage-1 rows are dead after k_cols1 and magnitudes after k_polar
+    float4* r2 = keep ? keep->r2 : (float4*)(ws + lay.r1r2);
+    float2* r3 = (float2*)(ws + lay.mag_r3);
+    float4* pxy = (float4*)(ws + lay.pxy);
+    constexpr int T2 = pad2(N) / kE2, LPB2 = rows2_lines(N);
+    float* gr = keep ? keep->gr : (float*)(ws + lay.grot);
+    FMBYM_LAUNCH(kKRotate, k_rotate<N>, dim3(B * (N / kRotTY) * (N / kRotTX)), dim3(256), s, g, mg, pl.hann,
+                 sv, gr, keep ? keep->jac : nullptr, win2, tab);
+    FMBYM_LAUNCH(kKRows2, k_rows2<N>, dim3(B * N / LPB2), dim3(256), s, f, g, mf, mg, pl.hann,
+                 pl.twiddle3, gr, r2, win2, tab);
+    constexpr int C2 = cols2_tile<N>();
+    const int total2 = B * ((pad2(N) / 2) / C2 + 1);
+    FMBYM_LAUNCH(kKCols2, (k_cols2<N, C2>), dim3(((total2 + 7) / 8) * 8), dim3(C2 * T2), s, r2,
+                 pl.twiddle3, r3, B);
+    FMBYM_LAUNCH(kKRows3, k_rows3<N>, dim3(B * (N / 2) / LPB2), dim3(256), s, r3, pl.twiddle3, c_xy,
+                 pxy, pl.p.temp_xy);
+}
+
 template <int N>
 static int launch_n(const Plan& pl, int B, const float* f, const float* g, const float* mf,
                     const float* mg, float* pose, float* c_theta, float* c_xy, float* saved,
@@ -723,25 +750,21 @@ static int launch_n(const Plan& pl, int B, const float* f, const float* g, const
         case 1024: launch_polar<N, 1024>(pl, B, mag, pth, c_theta, pose, sv, s); break;
         default: return FMBYM_EUNSUPPORTED;
     }
-    const int win2 = ((pl.p.flags & FMBYM_HANN) && !(pl.p.flags & FMBYM_XY_UNWINDOWED)) ? 1 : 0;
-    // without keep, stage-1 rows are dead after k_cols1 and magnitudes after k_polar
-    float4* r2 = keep ? keep->r2 : r1;
-    float2* r3 = (float2*)(ws + lay.mag_r3);
-    constexpr int T2 = pad2(N) / kE2, LPB2 = rows2_lines(N);
-    float* gr = keep ? keep->gr : (float*)(ws + lay.grot);
-    FMBYM_LAUNCH(kKRotate, k_rotate<N>, dim3(B * (N / kRotTY) * (N / kRotTX)), dim3(256), s, g, mg, pl.hann,
-                 sv, gr, keep ? keep->jac : nullptr, win2, tab);
-    FMBYM_LAUNCH(kKRows2, k_rows2<N>, dim3(B * N / LPB2), dim3(256), s, f, g, mf, mg, pl.hann,
-                 pl.twiddle3, gr, r2, win2, tab);
-    constexpr int C2 = cols2_tile<N>();
-    const int total2 = B * ((pad2(N) / 2) / C2 + 1);
-    FMBYM_LAUNCH(kKCols2, (k_cols2<N, C2>), dim3(((total2 + 7) / 8) * 8), dim3(C2 * T2), s, r2,
-                 pl.twiddle3, r3, B);
-    FMBYM_LAUNCH(kKRows3, k_rows3<N>, dim3(B * (N / 2) / LPB2), dim3(256), s, r3, pl.twiddle3, c_xy,
-                 pxy, pl.p.temp_xy);
+    stage2_n<N>(pl, B, f, g, mf, mg, sv, c_xy, ws, s, tab, keep);
     FMBYM_LAUNCH(kKXyFin, k_xy_fin, dim3(B), dim3(64), s, pxy, xy_partials_per_pair(N), pl.p.temp_xy,
                  pl.p.delta_xy, pose, sv);
     return FMBYM_OK;
+}
+
+void launch_stage2(const Plan& pl, int batch, const float* f, const float* g, const float* mf,
+                   const float* mg, const float* saved, float* c_xy, char* ws, hipStream_t s,
+                   const float* const* tab) {
+    switch (pl.p.n) {
+        case 128: stage2_n<128>(pl, batch, f, g, mf, mg, saved, c_xy, ws, s, tab, nullptr); break;
+        case 256: stage2_n<256>(pl, batch, f, g, mf, mg, saved, c_xy, ws, s, tab, nullptr); break;
+        case 512: stage2_n<512>(pl, batch, f, g, mf, mg, saved, c_xy, ws, s, tab, nullptr); break;
+        default: break;
+    }
 }
 
 void launch_rotate(const Plan& pl, int B, const float* g, const float* mg, const float* saved, float* gr,

@@ -45,7 +45,7 @@ EXPORTS = (
     "fmbym_mask_param_count", "fmbym_mask_packed_bytes", "fmbym_mask_bn_channels", "fmbym_mask_pack",
     "fmbym_mask_activation_bytes", "fmbym_mask_fwd", "fmbym_mask_workspace_bytes", "fmbym_mask_bwd",
     "fmbym_adam", "fmbym_pose_loss", "fmbym_search_state_size", "fmbym_search_train",
-    "fmbym_search_backward_state",
+    "fmbym_search_backward_state", "fmbym_joint_workspace_size", "fmbym_search_joint",
 )
 FMBYM_LOSS_L1 = 1
 FMBYM_LOSS_L2 = 2
@@ -107,6 +107,10 @@ def lib() -> ctypes.CDLL:
         L.fmbym_search.restype = ctypes.c_int
         L.fmbym_search_backward.argtypes = [VP, I32] + [VP] * 13 + [VP, SZ, VP]
         L.fmbym_search_backward.restype = ctypes.c_int
+        L.fmbym_joint_workspace_size.argtypes = [VP, I32, I32]
+        L.fmbym_joint_workspace_size.restype = SZ
+        L.fmbym_search_joint.argtypes = [VP, I32, I32] + [VP] * 6 + [VP, SZ, VP]
+        L.fmbym_search_joint.restype = ctypes.c_int
         L.fmbym_search_state_size.argtypes = [VP, I32]
         L.fmbym_search_state_size.restype = SZ
         L.fmbym_search_train.argtypes = [VP, I32] + [VP] * 8 + [VP, SZ, VP, SZ, VP]
@@ -201,6 +205,18 @@ def search_backward(plan, batch, f, g, m_f, m_g, pose, c_theta, c_xy, saved, d_p
                                      stream)
     if rc:
         raise FmbymError(rc, "fmbym_search_backward")
+
+
+def joint_workspace_size(plan, batch, n_angles) -> int:
+    return int(lib().fmbym_joint_workspace_size(plan, int(batch), int(n_angles)))
+
+
+def search_joint(plan, batch, n_angles, f, g, m_f, m_g, pose, peak, workspace, workspace_bytes, stream) -> None:
+    """fmbym_search_joint with raw device addresses (ints or None)."""
+    rc = lib().fmbym_search_joint(plan, int(batch), int(n_angles), f, g, m_f, m_g, pose, peak, workspace,
+                                  int(workspace_bytes), stream)
+    if rc:
+        raise FmbymError(rc, "fmbym_search_joint")
 
 
 def search_state_size(plan, batch) -> int:
@@ -315,6 +331,7 @@ class Search:
         self.n, self.n_theta, self.max_batch = n, n_theta, max_batch
         self.plan = plan_create(self.params, max_batch)
         self._ws = None
+        self._jws = None
 
     def close(self):
         if self.plan is not None:
@@ -351,6 +368,21 @@ class Search:
                _ptr(m_f, (B, n, n), "m_f"), _ptr(m_g, (B, n, n), "m_g"), _ptr(out["pose"]),
                _ptr(out["c_theta"]), _ptr(out["c_xy"]), _ptr(out["saved"]), ws.data_ptr(),
                ws.numel(), _stream())
+        return out
+
+    def joint(self, f, g, n_angles: int, m_f=None, m_g=None) -> dict:
+        """The brute-force joint comparator: pose [B, 3] and peak [B, n_angles]."""
+        B, n = f.shape[0], self.n
+        dev = f.device
+        need = joint_workspace_size(self.plan, B, n_angles)
+        if need == 0:
+            raise FmbymError(FMBYM_EINVAL, "fmbym_joint_workspace_size")
+        if self._jws is None or self._jws.numel() < need or self._jws.device != dev:
+            self._jws = torch.empty(need, dtype=torch.uint8, device=dev)
+        out = dict(pose=torch.empty(B, 3, device=dev), peak=torch.empty(B, n_angles, device=dev))
+        search_joint(self.plan, B, n_angles, _ptr(f, (B, n, n), "f"), _ptr(g, (B, n, n), "g"),
+                     _ptr(m_f, (B, n, n), "m_f"), _ptr(m_g, (B, n, n), "m_g"), _ptr(out["pose"]),
+                     _ptr(out["peak"]), self._jws.data_ptr(), need, _stream())
         return out
 
     def _forward_keep(self, f, g, m_f, m_g) -> dict:
