@@ -348,18 +348,20 @@ def search_bench(args) -> int:
     kw = workloads.search_kwargs(args.workload)
     B, n, nt = cfg["batch"], cfg["n"], cfg["n_theta"]
     dev = torch.device("cuda:0")
-    f_np, g_np, _ = synth.make_batch(args.workload, B, split="bench")
+    mode = workloads.PASS.get(args.workload, "fwd+bwd")
+    f_np, g_np, gt_pose = synth.make_batch(args.workload, B, split="bench")
     f = torch.from_numpy(f_np).to(dev)
     g = torch.from_numpy(g_np).to(dev)
     s = fmbym.Search(max_batch=B, **kw)
-    with_bwd = True
+    with_bwd = mode == "fwd+bwd"
     out = s.forward(f, g)
-    try:
-        s.backward(f, g, None, None, out, torch.ones(B, 3, device=dev))
-    except fmbym.FmbymError as e:
-        if e.code != fmbym.FMBYM_EUNSUPPORTED:
-            raise
-        with_bwd = False
+    if with_bwd:
+        try:
+            s.backward(f, g, None, None, out, torch.ones(B, 3, device=dev))
+        except fmbym.FmbymError as e:
+            if e.code != fmbym.FMBYM_EUNSUPPORTED:
+                raise
+            with_bwd = False
     d_pose = torch.ones(B, 3, device=dev)
     torch.cuda.synchronize()
 
@@ -371,22 +373,71 @@ def search_bench(args) -> int:
         torch.cuda.synchronize()
         del src, dst
 
-    def step():
+    def step(keep=with_bwd):
         # the training pair: the forward keeps its intermediates, the adjoint reads them
-        o = s.forward(f, g, keep=with_bwd)
+        o = s.forward(f, g, keep=keep)
         if with_bwd:
             s.backward(f, g, None, None, o, d_pose)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(args.steps):
-        step()
-    ev1.record()
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / args.steps
+    def timed(keep):
+        for _ in range(args.warmup):
+            step(keep)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(args.steps):
+            step(keep)
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / args.steps
+
+    ms = timed(with_bwd)
+    # the adjoint that recomputes the spectra (fmbym_search + fmbym_search_backward), same step
+    ms_recompute = timed(False) if with_bwd else None
+    extra = {}
+    if mode == "fwd" and B == 1:
+        # one pair: a captured launch (one HIP graph replay per pair)
+        r = fmbym.Ragged([s], [(f[0], g[0])], stamps=False)
+        for _ in range(max(args.warmup, 50)):
+            r.launch()
+        torch.cuda.synchronize()
+        iters = max(args.steps, 2000)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(iters):
+            r.launch()
+        e1.record()
+        torch.cuda.synchronize()
+        extra["eager_ms_per_pair"] = ms
+        ms = e0.elapsed_time(e1) / iters
+        extra["latency_us"] = ms * 1e3
+        r.close()
+    if mode.startswith("fwd+joint"):
+        K = workloads.JOINT_ANGLES
+        jo = s.joint(f, g, K)
+        for _ in range(2):
+            jo = s.joint(f, g, K)
+        torch.cuda.synchronize()
+        jsteps = max(3, args.steps // 10)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(jsteps):
+            jo = s.joint(f, g, K)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_j = e0.elapsed_time(e1) / jsteps
+        dec = s.forward(f, g, surfaces=False)["pose"].double().cpu().numpy()
+        jp = jo["pose"].double().cpu().numpy()
+
+        def errs(pz):
+            return (float(np.median(np.abs(pz[:, 0] - gt_pose[:, 0]))),
+                    float(np.median(np.hypot(pz[:, 1] - gt_pose[:, 1], pz[:, 2] - gt_pose[:, 2]))))
+        (td, xd), (tj, xj) = errs(dec), errs(jp)
+        extra["joint_comparator"] = {
+            "n_angles": K, "ms_per_step": ms_j, "value": B / (ms_j * 1e-3), "unit": "pairs/s",
+            "decoupled_speedup": ms_j / ms,
+            "median_theta_err_rad": {"decoupled": td, "joint": tj},
+            "median_t_err_m": {"decoupled": xd, "joint": xj}}
 
     # second timed pass: HIP events around every library launch, on its stream
     fmbym.profile_enable(args.steps * 32)
@@ -400,9 +451,17 @@ def search_bench(args) -> int:
     kb = kernel_bytes(n, nt, n, B, masked=False, keep=with_bwd)
     achieved = kb[dom] / (per_kernel[dom] * 1e-3) / 1e9 if dom in kb else None
 
+    if with_bwd:
+        metric = "scan-pairs/sec, 512^2 decoupled search fwd+bwd, 1 GPU"
+    elif mode == "fwd" and B == 1:
+        metric = f"scan-pairs/sec, {n}^2 decoupled search forward, one pair per captured launch, 1 GPU"
+    elif mode.startswith("fwd+joint"):
+        metric = (f"scan-pairs/sec, {n}^2 decoupled search forward (beside the "
+                  f"{workloads.JOINT_ANGLES}-heading joint comparator), 1 GPU")
+    else:
+        metric = f"scan-pairs/sec, {n}^2 decoupled search forward, 1 GPU"
     res = {
-        "metric": "scan-pairs/sec, 512^2 decoupled search fwd+bwd, 1 GPU" if with_bwd
-        else "scan-pairs/sec, decoupled search forward only (adjoint not built), 1 GPU",
+        "metric": metric,
         "value": B / (ms * 1e-3),
         "unit": "pairs/s",
         "n_gpus": 1,
@@ -415,13 +474,23 @@ def search_bench(args) -> int:
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "batch": B, "n": n, "n_theta": nt,
-                   "pass": "fwd+bwd (forward keeps its intermediates for the adjoint)" if with_bwd else "fwd"},
+                   "pass": "fwd+bwd (forward keeps its intermediates for the adjoint)" if with_bwd else mode},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": None if achieved is None else achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(dom) if args.workload == "batch512" else None,
                      "algorithmic_bytes": kb.get(dom)},
         "kernels_ms": {k: round(v, 5) for k, v in sorted(per_kernel.items())},
     }
+    # whole path against the pass model's bytes per pair (304 n^2 fwd+bwd, 92 n^2 fwd)
+    pass_bytes = (304 if with_bwd else 92) * n * n * B
+    res["roofline_path"] = {"bound": "hbm", "bytes_per_step": pass_bytes,
+                            "achieved": pass_bytes / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": pass_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    res.update(extra)
+    if ms_recompute is not None:
+        res["recompute_path"] = {"ms_per_step": ms_recompute, "value": B / (ms_recompute * 1e-3),
+                                 "unit": "pairs/s",
+                                 "frac": pass_bytes / (ms_recompute * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
     if not args.no_cpu_baseline:
         from oracle import fmbym_oracle as O

@@ -17,6 +17,12 @@ SEARCH = {
                      band_lo=0.02, band_hi=0.40),
 }
 
+# What one bench step of each search workload runs: the forward alone (one pair,
+# timed as a captured launch), the forward beside the joint comparator over
+# 64 headings, or the forward and the adjoint.
+PASS = {"pair128": "fwd", "batch256": "fwd+joint64", "batch512": "fwd+bwd"}
+JOINT_ANGLES = 64
+
 # Ragged serving batches: pairs of the three sizes above in one launch.
 RAGGED = {
     # 1024 pairs: half 128 x 128, 30 % 256 x 256, 20 % 512 x 512, each with its size's parameters
