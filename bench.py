@@ -363,6 +363,8 @@ def search_bench(args) -> int:
                 raise
             with_bwd = False
     d_pose = torch.ones(B, 3, device=dev)
+    # column-tile widths measured on this GPU for this workload (untimed; results do not depend on them)
+    tuning, _ = fmbym.plan_autotune(s.plan, B, with_bwd, dev)
     torch.cuda.synchronize()
 
     if args.copy_probe_mb:
@@ -487,6 +489,7 @@ def search_bench(args) -> int:
                             "achieved": pass_bytes / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                             "frac": pass_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
     res.update(extra)
+    res["tuning"] = tuning
     if ms_recompute is not None:
         res["recompute_path"] = {"ms_per_step": ms_recompute, "value": B / (ms_recompute * 1e-3),
                                  "unit": "pairs/s",

@@ -88,6 +88,17 @@ typedef struct {
     uint32_t flags;     /* FMBYM_HANN | FMBYM_XY_UNWINDOWED                                */
 } fmbym_params;
 
+/* Column-tile widths of the column passes: how many float4 columns one block
+ * transforms (4, 8 or 16).  They change speed, never results: every width runs
+ * the same arithmetic on every column.  A new plan starts from defaults for its
+ * n; fmbym_autotune measures and sets the fastest. */
+typedef struct {
+    int32_t cols1;      /* stage-1 column FFTs and |F|                      */
+    int32_t cols2;      /* stage-2 column correlation                       */
+    int32_t cols_xy;    /* adjoint of the stage-2 column correlation        */
+    int32_t cols_mag;   /* adjoint of |F| and the stage-1 columns            */
+} fmbym_tuning;
+
 /* Validate `p` and build a plan (uploads constant tables to the current device;
  * this call allocates).  `max_batch` bounds the batch of later calls (>= 1). */
 FMBYM_API int fmbym_plan_create(const fmbym_params* p, int32_t max_batch, fmbym_plan* out);
@@ -119,6 +130,26 @@ FMBYM_API int fmbym_search_backward(fmbym_plan plan, int32_t batch, const float*
                           const float* c_theta, const float* c_xy, const float* saved,
                           const float* d_pose, float* d_f, float* d_g, float* d_m_f, float* d_m_g,
                           void* workspace, size_t workspace_bytes, void* stream);
+
+/* ---------------------------------------------------------------- tuning
+ *
+ * fmbym_plan_get_tuning / fmbym_plan_set_tuning read and replace the plan's
+ * column-tile widths (set: FMBYM_EINVAL unless every width is 4, 8 or 16).
+ * Not to be called while searches on the plan are in flight.
+ *
+ * fmbym_autotune times whole search steps on synthetic inputs it writes into
+ * its workspace (fmbym_autotune_workspace_size bytes) and picks the widths one
+ * pass at a time (coordinate search over 4, 8, 16, in the order cols1, cols2,
+ * cols_xy, cols_mag; with_backward = 0 times the forward alone and leaves the
+ * adjoint's widths as they are).  It synchronises `stream`, creates and
+ * destroys two HIP events, sets the result on the plan and writes it to *best;
+ * ms_per_step (or NULL) receives the best step time.  Results of the searches
+ * do not depend on the choice. */
+FMBYM_API int fmbym_plan_get_tuning(fmbym_plan plan, fmbym_tuning* out);
+FMBYM_API int fmbym_plan_set_tuning(fmbym_plan plan, const fmbym_tuning* t);
+FMBYM_API size_t fmbym_autotune_workspace_size(fmbym_plan plan, int32_t batch, int with_backward);
+FMBYM_API int fmbym_autotune(fmbym_plan plan, int32_t batch, int with_backward, void* workspace,
+                             size_t workspace_bytes, void* stream, fmbym_tuning* best, float* ms_per_step);
 
 /* ---------------------------------------------------------------- training pair
  *

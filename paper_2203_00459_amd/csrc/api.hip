@@ -19,6 +19,12 @@ int hip_fail(hipError_t e) {
     return FMBYM_EHIP;
 }
 
+int check_call(fmbym_plan plan, int32_t batch) {
+    if (!plan) return FMBYM_EINVAL;
+    if (batch < 1 || batch > plan_cast(plan)->max_batch) return FMBYM_EINVAL;
+    return FMBYM_OK;
+}
+
 }  // namespace fmbym
 
 namespace {
@@ -51,12 +57,6 @@ hipError_t free_plan_tables(Plan* pl) {
     return first;
 }
 
-int check_call(fmbym_plan plan, int32_t batch) {
-    if (!plan) return FMBYM_EINVAL;
-    if (batch < 1 || batch > plan_cast(plan)->max_batch) return FMBYM_EINVAL;
-    return FMBYM_OK;
-}
-
 }  // namespace
 
 extern "C" {
@@ -71,6 +71,7 @@ int fmbym_plan_create(const fmbym_params* p, int32_t max_batch, fmbym_plan* out)
     if (!pl) return FMBYM_EINVAL;
     pl->p = *p;
     pl->max_batch = max_batch;
+    pl->tune = default_tuning(p->n);
     hipError_t e = hipGetDevice(&pl->device);
     if (e != hipSuccess) {
         delete pl;
@@ -166,6 +167,20 @@ int fmbym_search_backward(fmbym_plan plan, int32_t batch, const float* f, const 
     if (rc) return rc;
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? FMBYM_OK : hip_fail(e);
+}
+
+int fmbym_plan_get_tuning(fmbym_plan plan, fmbym_tuning* out) {
+    if (!plan || !out) return FMBYM_EINVAL;
+    *out = plan_cast(plan)->tune;
+    return FMBYM_OK;
+}
+
+int fmbym_plan_set_tuning(fmbym_plan plan, const fmbym_tuning* t) {
+    if (!plan || !t) return FMBYM_EINVAL;
+    if (!valid_tile(t->cols1) || !valid_tile(t->cols2) || !valid_tile(t->cols_xy) || !valid_tile(t->cols_mag))
+        return FMBYM_EINVAL;
+    plan_cast(plan)->tune = *t;
+    return FMBYM_OK;
 }
 
 size_t fmbym_joint_workspace_size(fmbym_plan plan, int32_t batch, int32_t n_angles) {

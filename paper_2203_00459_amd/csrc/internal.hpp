@@ -46,7 +46,13 @@ struct Plan {
     int* csr_dst;
     int* dmag_part;    // [dmag_nparts + 1] first CSR row of each adjoint block
     int dmag_nparts;
+    fmbym_tuning tune; // column-tile widths of the column passes
 };
+
+// Widths measured best at 512 x 512 before tuning (8 float4 columns read whole
+// 128-byte lines in stage 1; the 3n/2-point columns run 4 wide at 512).
+fmbym_tuning default_tuning(int n);
+bool valid_tile(int c);
 
 constexpr int kDmagTile = 16;     // bins per side of one tile of the CSR row order
 constexpr int kDmagRows = 256;    // at most this many CSR rows per adjoint block
@@ -56,6 +62,9 @@ constexpr int kDmagChunk = 1024;  // and about this many entries (more only for 
 int build_polar_csr(Plan& pl);
 
 inline Plan* plan_cast(fmbym_plan p) { return reinterpret_cast<Plan*>(p); }
+
+// FMBYM_EINVAL unless plan is set and 1 <= batch <= its max_batch.
+int check_call(fmbym_plan plan, int32_t batch);
 
 // Record e as this thread's last HIP error (fmbym_last_hip_error); returns FMBYM_EHIP.
 int hip_fail(hipError_t e);

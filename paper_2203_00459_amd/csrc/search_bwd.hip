@@ -710,8 +710,43 @@ static void launch_dtheta(const Plan& pl, int B, int ppb, const float* dth, cons
                  pl.twiddle, pl.p.temp_theta, dspec);
 }
 
-template <int N> constexpr int bcols_xy_tile() { return N >= 512 ? 4 : (N >= 256 ? 8 : 16); }
-template <int N> constexpr int bcols_mag_tile() { return N >= 512 ? 4 : 16; }
+// Column-tile widths from the plan's tuning (same arithmetic for every width).
+template <int N, int C>
+static void launch_cols_xy_c(const Plan& pl, int B, const float4* rows2, float4* rf, const float2* rdc,
+                             hipStream_t s) {
+    constexpr int T2 = pad2(N) / kE2;
+    const int total2 = B * ((pad2(N) / 2) / C + 1);
+    FMBYM_LAUNCH(kKBColsXy, (kb_cols_xy<N, C>), dim3(((total2 + 7) / 8) * 8), dim3(C * T2), s, rows2, rf,
+                 rdc, pl.twiddle3, B);
+}
+
+template <int N>
+static void launch_cols_xy(const Plan& pl, int B, const float4* rows2, float4* rf, const float2* rdc,
+                           hipStream_t s) {
+    switch (pl.tune.cols_xy) {
+        case 4: launch_cols_xy_c<N, 4>(pl, B, rows2, rf, rdc, s); break;
+        case 8: launch_cols_xy_c<N, 8>(pl, B, rows2, rf, rdc, s); break;
+        default: launch_cols_xy_c<N, 16>(pl, B, rows2, rf, rdc, s); break;
+    }
+}
+
+template <int N, int C>
+static void launch_cols_mag_c(const Plan& pl, int B, const float4* r1, float4* out, const float2* dA,
+                              hipStream_t s) {
+    const int tiles_mag = B * ((N / 2) / C + 1);
+    FMBYM_LAUNCH(kKBColsMag, (kb_cols_mag<N, C>), dim3(((tiles_mag + 7) / 8) * 8), dim3(C * N / kEb), s, r1,
+                 out, dA, pl.twiddle, B);
+}
+
+template <int N>
+static void launch_cols_mag(const Plan& pl, int B, const float4* r1, float4* out, const float2* dA,
+                            hipStream_t s) {
+    switch (pl.tune.cols_mag) {
+        case 4: launch_cols_mag_c<N, 4>(pl, B, r1, out, dA, s); break;
+        case 8: launch_cols_mag_c<N, 8>(pl, B, r1, out, dA, s); break;
+        default: launch_cols_mag_c<N, 16>(pl, B, r1, out, dA, s); break;
+    }
+}
 
 template <int N>
 static int launch_bwd_n(const Plan& pl, int B, const float* f, const float* g, const float* mf,
@@ -749,10 +784,7 @@ static int launch_bwd_n(const Plan& pl, int B, const float* f, const float* g, c
     FMBYM_LAUNCH(kKBRowsFwd2, kb_rows_fwd2<N>, dim3(scan_blocks + dc_blocks - skip), dim3(256), s, f, g, mf,
                  mg, pl.hann, pl.twiddle3, saved, c_xy, d_pose, gr, rf, rdc, win2, B, pl.p.temp_xy,
                  pl.p.delta_xy, skip);
-    constexpr int C2 = bcols_xy_tile<N>();
-    const int total2 = B * ((pad2(N) / 2) / C2 + 1);
-    FMBYM_LAUNCH(kKBColsXy, (kb_cols_xy<N, C2>), dim3(((total2 + 7) / 8) * 8), dim3(C2 * T2), s,
-                 rows2, rf, rdc, pl.twiddle3, B);
+    launch_cols_xy<N>(pl, B, rows2, rf, rdc, s);
     FMBYM_LAUNCH(kKBRowsXy, kb_rows_xy<N>, dim3(B * N / LPB2), dim3(256), s, rf, jac, pl.twiddle3, df2,
                  dgp, dth);
     const int ppb = N / LPB2;
@@ -783,10 +815,7 @@ static int launch_bwd_n(const Plan& pl, int B, const float* f, const float* g, c
     FMBYM_LAUNCH(kKBDmag, kb_dmag, dim3(pl.dmag_nparts, (B + kDmagPairs - 1) / kDmagPairs), dim3(256), s,
                  pl.csr_ptr, pl.csr_col, pl.csr_val, pl.csr_dst, pl.dmag_part, dpol, dA, N, pl.p.n_r,
                  pl.p.n_theta, B);
-    constexpr int C = bcols_mag_tile<N>();
-    const int tiles_mag = B * ((N / 2) / C + 1);
-    FMBYM_LAUNCH(kKBColsMag, (kb_cols_mag<N, C>), dim3(((tiles_mag + 7) / 8) * 8), dim3(C * N / kEb), s, r1,
-                 r1w, dA, pl.twiddle, B);
+    launch_cols_mag<N>(pl, B, r1, r1w, dA, s);
     FMBYM_LAUNCH(kKBRotateAdj, kb_rotate_adj<N>, dim3(B * (N / kRotTY) * (N / kRotTX)), dim3(256), s, dgp,
                  saved, dgr);
     constexpr int T1 = N / kEb, LPB1 = 256 / T1;

@@ -662,10 +662,40 @@ Keep keep_pointers(const fmbym_params& p, int batch, void* state) {
     return k;
 }
 
-// Column-tile widths (measured at 512 x 512): 8 float4 columns read whole 128-byte
-// lines; the 3n/2-point stage-2 columns run better 4 wide (more blocks per CU).
-template <int N> constexpr int cols1_tile() { return N >= 512 ? 8 : 16; }
-template <int N> constexpr int cols2_tile() { return N >= 512 ? 4 : (N >= 256 ? 8 : 16); }
+// Column-tile widths are the plan's tuning (fmbym_tuning: 4, 8 or 16 columns
+// per block); every width gives the same arithmetic per column.
+template <int N, int C>
+static void launch_cols1_c(const Plan& pl, int B, const float4* r1, float2* mag, hipStream_t s) {
+    const int tiles1 = B * ((N / 2) / C + 1);
+    FMBYM_LAUNCH(kKCols1, (k_cols1<N, C>), dim3(((tiles1 + 7) / 8) * 8), dim3(C * N / kE), s, r1, mag,
+                 pl.twiddle, pl.band_on, pl.band_lo2, pl.band_hi2, B);
+}
+
+template <int N>
+static void launch_cols1(const Plan& pl, int B, const float4* r1, float2* mag, hipStream_t s) {
+    switch (pl.tune.cols1) {
+        case 4: launch_cols1_c<N, 4>(pl, B, r1, mag, s); break;
+        case 8: launch_cols1_c<N, 8>(pl, B, r1, mag, s); break;
+        default: launch_cols1_c<N, 16>(pl, B, r1, mag, s); break;
+    }
+}
+
+template <int N, int C>
+static void launch_cols2_c(const Plan& pl, int B, const float4* r2, float2* r3, hipStream_t s) {
+    constexpr int T2 = pad2(N) / kE2;
+    const int total2 = B * ((pad2(N) / 2) / C + 1);
+    FMBYM_LAUNCH(kKCols2, (k_cols2<N, C>), dim3(((total2 + 7) / 8) * 8), dim3(C * T2), s, r2, pl.twiddle3,
+                 r3, B);
+}
+
+template <int N>
+static void launch_cols2(const Plan& pl, int B, const float4* r2, float2* r3, hipStream_t s) {
+    switch (pl.tune.cols2) {
+        case 4: launch_cols2_c<N, 4>(pl, B, r2, r3, s); break;
+        case 8: launch_cols2_c<N, 8>(pl, B, r2, r3, s); break;
+        default: launch_cols2_c<N, 16>(pl, B, r2, r3, s); break;
+    }
+}
 
 template <int N>
 static void launch_stage1_rows_cols(const Plan& pl, int B, const float* f, const float* g,
@@ -675,10 +705,7 @@ static void launch_stage1_rows_cols(const Plan& pl, int B, const float* f, const
     constexpr int T1 = N / kE, LPB1 = 256 / T1;
     FMBYM_LAUNCH(kKRows1, k_rows1<N>, dim3(B * N / LPB1), dim3(256), s, f, g, mf, mg, pl.hann,
                  pl.twiddle, r1, win, tab);
-    constexpr int C = cols1_tile<N>();
-    const int tiles1 = B * ((N / 2) / C + 1);
-    FMBYM_LAUNCH(kKCols1, (k_cols1<N, C>), dim3(((tiles1 + 7) / 8) * 8), dim3(C * N / kE), s, r1, mag,
-                 pl.twiddle, pl.band_on, pl.band_lo2, pl.band_hi2, B);
+    launch_cols1<N>(pl, B, r1, mag, s);
 }
 
 void launch_stage1_spectra(const Plan& pl, int B, const float* f, const float* g, const float* mf,
@@ -721,10 +748,7 @@ static void stage2_n(const Plan& pl, int B, const float* f, const float* g, cons
                  sv, gr, keep ? keep->jac : nullptr, win2, tab);
     FMBYM_LAUNCH(kKRows2, k_rows2<N>, dim3(B * N / LPB2), dim3(256), s, f, g, mf, mg, pl.hann,
                  pl.twiddle3, gr, r2, win2, tab);
-    constexpr int C2 = cols2_tile<N>();
-    const int total2 = B * ((pad2(N) / 2) / C2 + 1);
-    FMBYM_LAUNCH(kKCols2, (k_cols2<N, C2>), dim3(((total2 + 7) / 8) * 8), dim3(C2 * T2), s, r2,
-                 pl.twiddle3, r3, B);
+    launch_cols2<N>(pl, B, r2, r3, s);
     FMBYM_LAUNCH(kKRows3, k_rows3<N>, dim3(B * (N / 2) / LPB2), dim3(256), s, r3, pl.twiddle3, c_xy,
                  pxy, pl.p.temp_xy);
 }

@@ -46,6 +46,7 @@ EXPORTS = (
     "fmbym_mask_activation_bytes", "fmbym_mask_fwd", "fmbym_mask_workspace_bytes", "fmbym_mask_bwd",
     "fmbym_adam", "fmbym_pose_loss", "fmbym_search_state_size", "fmbym_search_train",
     "fmbym_search_backward_state", "fmbym_joint_workspace_size", "fmbym_search_joint",
+    "fmbym_plan_get_tuning", "fmbym_plan_set_tuning", "fmbym_autotune_workspace_size", "fmbym_autotune",
 )
 FMBYM_LOSS_L1 = 1
 FMBYM_LOSS_L2 = 2
@@ -67,6 +68,11 @@ class fmbym_pair(ctypes.Structure):
         ("n", ctypes.c_int32), ("flags", ctypes.c_uint32), ("f", ctypes.c_void_p),
         ("g", ctypes.c_void_p), ("m_f", ctypes.c_void_p), ("m_g", ctypes.c_void_p),
     ]
+
+
+class fmbym_tuning(ctypes.Structure):
+    _fields_ = [("cols1", ctypes.c_int32), ("cols2", ctypes.c_int32), ("cols_xy", ctypes.c_int32),
+                ("cols_mag", ctypes.c_int32)]
 
 
 class fmbym_mask_desc(ctypes.Structure):
@@ -107,6 +113,15 @@ def lib() -> ctypes.CDLL:
         L.fmbym_search.restype = ctypes.c_int
         L.fmbym_search_backward.argtypes = [VP, I32] + [VP] * 13 + [VP, SZ, VP]
         L.fmbym_search_backward.restype = ctypes.c_int
+        TP = ctypes.POINTER(fmbym_tuning)
+        L.fmbym_plan_get_tuning.argtypes = [VP, TP]
+        L.fmbym_plan_get_tuning.restype = ctypes.c_int
+        L.fmbym_plan_set_tuning.argtypes = [VP, TP]
+        L.fmbym_plan_set_tuning.restype = ctypes.c_int
+        L.fmbym_autotune_workspace_size.argtypes = [VP, I32, ctypes.c_int]
+        L.fmbym_autotune_workspace_size.restype = SZ
+        L.fmbym_autotune.argtypes = [VP, I32, ctypes.c_int, VP, SZ, VP, TP, ctypes.POINTER(ctypes.c_float)]
+        L.fmbym_autotune.restype = ctypes.c_int
         L.fmbym_joint_workspace_size.argtypes = [VP, I32, I32]
         L.fmbym_joint_workspace_size.restype = SZ
         L.fmbym_search_joint.argtypes = [VP, I32, I32] + [VP] * 6 + [VP, SZ, VP]
@@ -205,6 +220,39 @@ def search_backward(plan, batch, f, g, m_f, m_g, pose, c_theta, c_xy, saved, d_p
                                      stream)
     if rc:
         raise FmbymError(rc, "fmbym_search_backward")
+
+
+TUNING_FIELDS = ("cols1", "cols2", "cols_xy", "cols_mag")
+
+
+def plan_get_tuning(plan) -> dict:
+    t = fmbym_tuning()
+    rc = lib().fmbym_plan_get_tuning(plan, ctypes.byref(t))
+    if rc:
+        raise FmbymError(rc, "fmbym_plan_get_tuning")
+    return {k: int(getattr(t, k)) for k in TUNING_FIELDS}
+
+
+def plan_set_tuning(plan, tuning: dict) -> None:
+    t = fmbym_tuning(*[int(tuning[k]) for k in TUNING_FIELDS])
+    rc = lib().fmbym_plan_set_tuning(plan, ctypes.byref(t))
+    if rc:
+        raise FmbymError(rc, "fmbym_plan_set_tuning")
+
+
+def plan_autotune(plan, batch: int, with_backward: bool, device) -> tuple[dict, float]:
+    """Native autotune of the plan's column-tile widths; returns (widths, ms per step)."""
+    need = int(lib().fmbym_autotune_workspace_size(plan, int(batch), int(with_backward)))
+    if need == 0:
+        raise FmbymError(FMBYM_EINVAL, "fmbym_autotune_workspace_size")
+    ws = torch.empty(need, dtype=torch.uint8, device=device)
+    t = fmbym_tuning()
+    ms = ctypes.c_float()
+    rc = lib().fmbym_autotune(plan, int(batch), int(with_backward), ws.data_ptr(), need, _stream(),
+                              ctypes.byref(t), ctypes.byref(ms))
+    if rc:
+        raise FmbymError(rc, "fmbym_autotune")
+    return {k: int(getattr(t, k)) for k in TUNING_FIELDS}, float(ms.value)
 
 
 def joint_workspace_size(plan, batch, n_angles) -> int:

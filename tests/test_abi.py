@@ -73,6 +73,11 @@ def test_calls_without_a_plan_are_rejected():
     assert L.fmbym_search_backward(None, 1, *([None] * 13), None, 0, None) == fmbym.FMBYM_EINVAL
     assert L.fmbym_search_state_size(None, 1) == 0
     assert L.fmbym_joint_workspace_size(None, 1, 64) == 0
+    t = fmbym.fmbym_tuning(8, 8, 8, 8)
+    assert L.fmbym_plan_get_tuning(None, ctypes.byref(t)) == fmbym.FMBYM_EINVAL
+    assert L.fmbym_plan_set_tuning(None, ctypes.byref(t)) == fmbym.FMBYM_EINVAL
+    assert L.fmbym_autotune_workspace_size(None, 1, 1) == 0
+    assert L.fmbym_autotune(None, 1, 1, None, 0, None, ctypes.byref(t), None) == fmbym.FMBYM_EINVAL
     assert L.fmbym_search_joint(None, 1, 64, *([None] * 6), None, 0, None) == fmbym.FMBYM_EINVAL
     assert L.fmbym_search_train(None, 1, *([None] * 8), None, 0, None, 0, None) == fmbym.FMBYM_EINVAL
     assert L.fmbym_search_backward_state(None, 1, *([None] * 8), None, 0, *([None] * 5), None, 0,

@@ -1,0 +1,66 @@
+"""Column-tile widths (the plan's tuning) change speed, never results: the
+forward and the adjoint are bitwise identical under every width for every
+supported n; the autotuner returns widths from the supported set, sets them
+on the plan, and its JSON cache gives them back without measuring again."""
+import itertools
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2203_00459_amd import fmbym, synth, tune, workloads
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+TUNINGS = [dict(cols1=c, cols2=c, cols_xy=c, cols_mag=c) for c in (4, 8, 16)] + [
+    dict(cols1=16, cols2=4, cols_xy=8, cols_mag=4)]
+
+
+@pytest.mark.parametrize("name", ["pair128", "batch256", "batch512"])
+def test_every_width_gives_the_same_bits(name):
+    B = 2
+    print(f"case {name}", flush=True)
+    s = fmbym.Search(max_batch=B, **workloads.search_kwargs(name))
+    f, g, _ = synth.make_batch(name, B, split="val")
+    f, g = torch.from_numpy(f).to(DEV), torch.from_numpy(g).to(DEV)
+    rng = np.random.Generator(np.random.PCG64(2))
+    mf, mg = (torch.from_numpy(rng.uniform(0.3, 1.0, f.shape).astype(np.float32)).to(DEV) for _ in range(2))
+    d_pose = torch.from_numpy(rng.normal(size=(B, 3)).astype(np.float32)).to(DEV)
+    ref = None
+    for t in TUNINGS:
+        fmbym.plan_set_tuning(s.plan, t)
+        assert fmbym.plan_get_tuning(s.plan) == t
+        out = s.forward(f, g, mf, mg, keep=True)
+        gr = s.backward(f, g, mf, mg, out, d_pose)
+        torch.cuda.synchronize()
+        res = {k: out[k].clone() for k in ("pose", "c_theta", "c_xy")}
+        res.update({k: v.clone() for k, v in gr.items()})
+        if ref is None:
+            ref = res
+            continue
+        for k, v in res.items():
+            assert torch.equal(v, ref[k]), (t, k)
+    s.close()
+
+
+def test_set_tuning_rejects_unsupported_widths():
+    s = fmbym.Search(max_batch=1, **workloads.search_kwargs("pair128"))
+    with pytest.raises(fmbym.FmbymError):
+        fmbym.plan_set_tuning(s.plan, dict(cols1=4, cols2=6, cols_xy=4, cols_mag=4))
+    s.close()
+
+
+def test_autotune_sets_supported_widths_and_caches(tmp_path):
+    s = fmbym.Search(max_batch=8, **workloads.search_kwargs("batch256"))
+    path = str(tmp_path / "tuning.json")
+    r = tune.autotune(s, 8, with_backward=True, cache_path=path)
+    print("autotune", r, flush=True)
+    assert not r["from_cache"] and r["ms_per_step"] > 0
+    assert all(v in (4, 8, 16) for v in r["tuning"].values())
+    assert fmbym.plan_get_tuning(s.plan) == r["tuning"]
+    fmbym.plan_set_tuning(s.plan, dict(cols1=4, cols2=4, cols_xy=4, cols_mag=4))
+    r2 = tune.autotune(s, 8, with_backward=True, cache_path=path)
+    assert r2["from_cache"] and r2["tuning"] == r["tuning"]
+    assert fmbym.plan_get_tuning(s.plan) == r["tuning"]
+    s.close()
