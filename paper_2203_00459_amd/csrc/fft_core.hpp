@@ -96,25 +96,32 @@ __device__ __forceinline__ void dft_r<8>(float2 (&v)[8]) { dft8(v); }
 // LDS layouts of a line (separate re/im planes, 32 banks of 4 bytes).  The
 // Stockham stages read unit-stride and write stride-Ns patterns, the mirror
 // reads reversed; these layouts keep those patterns near one cycle per
-// half-wave access (chosen with a bank simulator of exactly these patterns):
-//   rows (one line per T threads, lanes vary the element): XOR swizzle of the
-//     low five bits by bits 3..7; short lines (several per wave) are spaced by
-//     16 words mod 32;
+// half-wave access (chosen with a bank simulator of exactly these patterns),
+// and both are paddings, at(i) = i + p (i >> s): a stage's addresses are then
+// one per-thread base plus constants (LDS immediate offsets), at(b + c) =
+// at(b) + at(c), which lds_layout_linear() below proves for every access of
+// every instantiated transform.
+//   rows (one line per T threads, lanes vary the element): three spare words
+//     per 32 elements (per 16 for lines shorter than 256), short lines spaced
+//     by a measured stride;
 //   column tiles (lanes vary the column fastest, C columns per tile): one
 //     spare word per 8 elements and a line stride of 32/C words mod 32.
+template <int L>
 struct LdsRows {
-    static constexpr bool kLinear = false;
-    __device__ __forceinline__ static int at(int i) { return i ^ ((i >> 3) & 31); }
-    __host__ __device__ static constexpr int words(int L) { return L <= 128 ? L + 16 : L; }
+    static constexpr bool kLinear = true;
+    static constexpr int kShift = L >= 256 ? 5 : 4;
+    __host__ __device__ static constexpr int lin(int c) { return c + 3 * (c >> kShift); }
+    __host__ __device__ static constexpr int at(int i) { return i + 3 * (i >> kShift); }
+    __host__ __device__ static constexpr int spacing() {
+        return L >= 256 ? 0 : L == 192 ? 15 : L == 128 ? 27 : L == 64 ? 15 : L == 32 ? 1 : 2;
+    }
+    __host__ __device__ static constexpr int words(int) { return at(L - 1) + 1 + spacing(); }
 };
 template <int C>
 struct LdsCols {
-    // at(b + c) = at(b) + lin(c) for b >= 0 and c a multiple of 8 (more
-    // generally whenever (b mod 8) + (c mod 8) < 8): a stage's addresses are
-    // one per-thread base plus constants (LDS immediate offsets).
     static constexpr bool kLinear = true;
     __host__ __device__ static constexpr int lin(int c) { return c + (c >> 3); }
-    __device__ __forceinline__ static int at(int i) { return i + (i >> 3); }
+    __host__ __device__ static constexpr int at(int i) { return i + (i >> 3); }
     __host__ __device__ static constexpr int words(int L) {
         return L + L / 8 + ((32 / C - (L + L / 8)) % 32 + 32) % 32;
     }
@@ -174,8 +181,6 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[E], float* re, float* im, 
     constexpr int Q = E / R;          // butterflies per thread
     constexpr int LR = L / R;
     static_assert(E % R == 0 && (Ns & (Ns - 1)) == 0, "radix divides E; the radix-3 stage comes last");
-    static_assert(!Lay::kLinear || (T % 8 == 0 && LR % 8 == 0 && (T & (T - 1)) == 0),
-                  "linear LDS addressing needs T and L/R multiples of 8 and T a power of two");
     float2 out[Q][R];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -262,9 +267,38 @@ __device__ __forceinline__ int fresh_index(int t) {
 // Forward DFT of one line, in registers.  All threads of the block must call
 // it (it contains block barriers) even if their line is padding.  tw is the
 // table of twiddle_len<L>() entries.
-template <int L, int E, class Lay = LdsRows>
+// Compile-time proof that the base-plus-constant addresses of fft_stage equal
+// the layout function for every thread, butterfly, radix index and stage.
+template <int L, int E, class Lay, int S = 0, bool END = (S == NumStages<L, E>::value)>
+struct LayoutCheck {
+    static constexpr bool ok() {
+        constexpr int T = L / E, R = StageRadix<L, E, S>::R, Ns = StageRadix<L, E, S>::done, Q = E / R;
+        constexpr int LR = L / R, NS = NumStages<L, E>::value;
+        constexpr bool small = Ns <= T;
+        for (int t = 0; t < T; ++t)
+            for (int q = 0; q < Q; ++q)
+                for (int r = 0; r < R; ++r) {
+                    const int j = t + q * T;
+                    if (S > 0 && Lay::at(t) + Lay::lin(q * T + r * LR) != Lay::at(j + r * LR)) return false;
+                    if (S < NS - 1) {
+                        const int w0 = small ? (t / Ns) * Ns * R + (t & (Ns - 1)) : t;
+                        const int c = small ? q * T * R + r * Ns : (q * T / Ns) * Ns * R + (q * T) % Ns + r * Ns;
+                        const int i = (j / Ns) * Ns * R + (j & (Ns - 1)) + r * Ns;
+                        if (Lay::at(w0) + Lay::lin(c) != Lay::at(i)) return false;
+                    }
+                }
+        return LayoutCheck<L, E, Lay, S + 1>::ok();
+    }
+};
+template <int L, int E, class Lay, int S>
+struct LayoutCheck<L, E, Lay, S, true> {
+    static constexpr bool ok() { return true; }
+};
+
+template <int L, int E, class Lay = LdsRows<L>>
 __device__ __forceinline__ void fft_line(float2 (&v)[E], float* re, float* im, int t,
                                          const float2* __restrict__ tw) {
+    static_assert(!Lay::kLinear || LayoutCheck<L, E, Lay>::ok(), "linear LDS addresses equal the layout");
     static_assert(pow2_part(L) * (pow2_part(L) == L ? 1 : 3) == L && L >= 2 && twiddle_len<L>() % L == 0,
                   "length 2^a or 3 2^a dividing its twiddle table");
     static_assert(E == 2 || E == 4 || E == 8 || E == 12 || E == 24, "elements per thread");
@@ -272,7 +306,7 @@ __device__ __forceinline__ void fft_line(float2 (&v)[E], float* re, float* im, i
 }
 
 // Inverse (unnormalised) DFT: conj(DFT(conj(x))).
-template <int L, int E, class Lay = LdsRows>
+template <int L, int E, class Lay = LdsRows<L>>
 __device__ __forceinline__ void ifft_line(float2 (&v)[E], float* re, float* im, int t,
                                           const float2* __restrict__ tw) {
 #pragma unroll
@@ -285,7 +319,7 @@ __device__ __forceinline__ void ifft_line(float2 (&v)[E], float* re, float* im, 
 // Store the register line to LDS in natural order / read the mirror element
 // X[(L - k) mod L] of each held X[k].  Used to split the transforms of two real
 // sequences packed as x + i y.  Barriers included.
-template <int L, int E, class Lay = LdsRows>
+template <int L, int E, class Lay = LdsRows<L>>
 __device__ __forceinline__ void mirror_line(const float2 (&v)[E], float2 (&mir)[E], float* re,
                                             float* im, int t) {
     constexpr int T = L / E;

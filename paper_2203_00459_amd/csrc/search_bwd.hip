@@ -75,8 +75,8 @@ __global__ __launch_bounds__(256) void kb_rows_fwd2(
     float temp, float delta, int block0) {
     constexpr int L = pad2(N), E = kE2, T = L / E, LPB = 256 / T, H = L / 2, P2 = pitch_rows2(N),
                   P3 = pitch_lag(N);
-    __shared__ float lre[LPB][LdsRows::words(L)];
-    __shared__ float lim[LPB][LdsRows::words(L)];
+    __shared__ float lre[LPB][LdsRows<L>::words(L)];
+    __shared__ float lim[LPB][LdsRows<L>::words(L)];
     const int line = threadIdx.x / T, t = threadIdx.x % T;
     const int nscan_blocks = batch * N / LPB;
     const int bid = (int)blockIdx.x + block0;   // block0 > 0 skips the scan rows
@@ -213,8 +213,8 @@ __global__ __launch_bounds__(256) void kb_rows_xy(const float4* __restrict__ q12
                                                   float* __restrict__ df2, float* __restrict__ dgp,
                                                   float* __restrict__ dth_part) {
     constexpr int L = pad2(N), E = kE2, T = L / E, LPB = 256 / T, PPB = N / LPB, P2 = pitch_rows2(N);
-    __shared__ float lre[LPB][LdsRows::words(L)];
-    __shared__ float lim[LPB][LdsRows::words(L)];
+    __shared__ float lre[LPB][LdsRows<L>::words(L)];
+    __shared__ float lim[LPB][LdsRows<L>::words(L)];
     __shared__ float red[256];
     const int line = threadIdx.x / T, t = threadIdx.x % T;
     const int grow = blockIdx.x * LPB + line;
@@ -258,8 +258,8 @@ __global__ __launch_bounds__(NT / kEb) void kb_dtheta(const float* __restrict__ 
                                                       const float2* __restrict__ tw, float temp,
                                                       float2* __restrict__ dspec) {
     constexpr int L = NT, T = L / kEb;
-    __shared__ float lre[LdsRows::words(L)];
-    __shared__ float lim[LdsRows::words(L)];
+    __shared__ float lre[LdsRows<L>::words(L)];
+    __shared__ float lim[LdsRows<L>::words(L)];
     __shared__ float red[T];
     const int b = blockIdx.x, t = threadIdx.x;
     float s = 0.f;
@@ -308,8 +308,8 @@ __global__ __launch_bounds__(256) void kb_polar(const float2* __restrict__ A,
                                                 const float2* __restrict__ dspec,
                                                 float2* __restrict__ dpol, int n_r, int batch) {
     constexpr int L = NT, T = L / kEb, LPB = 256 / T, PASSES = (kRadiiPerBlock + LPB - 1) / LPB;
-    __shared__ float lre[LPB][LdsRows::words(L)];
-    __shared__ float lim[LPB][LdsRows::words(L)];
+    __shared__ float lre[LPB][LdsRows<L>::words(L)];
+    __shared__ float lim[LPB][LdsRows<L>::words(L)];
     const int nrb = (n_r + kRadiiPerBlock - 1) / kRadiiPerBlock;
     const int total = batch * nrb;
     const int per_xcd = (total + 7) / 8;
@@ -605,8 +605,8 @@ __global__ __launch_bounds__(256) void kb_rows_final(
     const float* __restrict__ saved, float* __restrict__ d_f, float* __restrict__ d_g,
     float* __restrict__ d_mf, float* __restrict__ d_mg, int win, int win2) {
     constexpr int L = N, T = L / kEb, LPB = 256 / T, H = N / 2, P1 = pitch_rows1(N);
-    __shared__ float lre[LPB][LdsRows::words(L)];
-    __shared__ float lim[LPB][LdsRows::words(L)];
+    __shared__ float lre[LPB][LdsRows<L>::words(L)];
+    __shared__ float lim[LPB][LdsRows<L>::words(L)];
     const int line = threadIdx.x / T, t = threadIdx.x % T;
     const int grow = blockIdx.x * LPB + line;
     const int b = grow / N, i = grow % N;

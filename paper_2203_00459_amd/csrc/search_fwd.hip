@@ -37,8 +37,8 @@ __global__ __launch_bounds__(256) void k_rows1(const float* __restrict__ f, cons
                                                const float2* __restrict__ tw, float4* __restrict__ out,
                                                int win, const float* const* __restrict__ tab) {
     constexpr int L = N, T = L / kE, LPB = 256 / T, H = N / 2, P = pitch_rows1(N);
-    __shared__ float lre[LPB][LdsRows::words(L)];
-    __shared__ float lim[LPB][LdsRows::words(L)];
+    __shared__ float lre[LPB][LdsRows<L>::words(L)];
+    __shared__ float lim[LPB][LdsRows<L>::words(L)];
     const int line = threadIdx.x / T, t = threadIdx.x % T;
     const int grow = blockIdx.x * LPB + line;     // row over the batch
     const int i = grow % N;
@@ -127,8 +127,8 @@ __global__ __launch_bounds__(256) void k_polar(const float2* __restrict__ A,
                                                float2* __restrict__ part, int n_r, int batch) {
     constexpr int L = NT, T = L / kE, LPB = 256 / T, PASSES = (kRadiiPerBlock + LPB - 1) / LPB;
     constexpr int HK = NT / 2 + 1;
-    __shared__ float lre[LPB][LdsRows::words(L)];
-    __shared__ float lim[LPB][LdsRows::words(L)];
+    __shared__ float lre[LPB][LdsRows<L>::words(L)];
+    __shared__ float lim[LPB][LdsRows<L>::words(L)];
     const int nrb = (n_r + kRadiiPerBlock - 1) / kRadiiPerBlock;
     const int total = batch * nrb;
     // XCD-aware remap: hardware deals consecutive block ids round-robin over 8 XCDs
@@ -246,8 +246,8 @@ __global__ __launch_bounds__(kAngleGroups * NT / kE) void k_angle_fin(
     const float2* __restrict__ part, int n_r, const float2* __restrict__ tw, float temp,
     float* __restrict__ c_theta, float* __restrict__ pose, float* __restrict__ saved) {
     constexpr int L = NT, T = L / kE, HK = NT / 2 + 1;
-    __shared__ float lre[kAngleGroups][LdsRows::words(L)];   // one line per group: the groups
-    __shared__ float lim[kAngleGroups][LdsRows::words(L)];   // repeat the transform, race-free
+    __shared__ float lre[kAngleGroups][LdsRows<L>::words(L)];   // one line per group: the groups
+    __shared__ float lim[kAngleGroups][LdsRows<L>::words(L)];   // repeat the transform, race-free
     __shared__ float2 psum[kAngleGroups][HK];
     __shared__ float red[T];
     __shared__ int redi[T];
@@ -344,8 +344,8 @@ __global__ __launch_bounds__(256) void k_rows2(const float* __restrict__ f, cons
                                                float4* __restrict__ out, int win,
                                                const float* const* __restrict__ tab) {
     constexpr int L = pad2(N), E = kE2, T = L / E, LPB = 256 / T, H = L / 2, P2 = pitch_rows2(N);
-    __shared__ float lre[LPB][LdsRows::words(L)];
-    __shared__ float lim[LPB][LdsRows::words(L)];
+    __shared__ float lre[LPB][LdsRows<L>::words(L)];
+    __shared__ float lim[LPB][LdsRows<L>::words(L)];
     const int line = threadIdx.x / T, t = threadIdx.x % T;
     const int grow = blockIdx.x * LPB + line;
     const int b = grow / N, i = grow % N;
@@ -512,8 +512,8 @@ __global__ __launch_bounds__(256) void k_rows3(const float2* __restrict__ in,
                                                float temp) {
     constexpr int L = pad2(N), E = kE2, T = L / E, LPB = 256 / T, PPP = (N / 2) / LPB, P3 = pitch_lag(N);
     constexpr int K = 2 * E / 3;    // kept lags per thread
-    __shared__ float lre[LPB][LdsRows::words(L)];
-    __shared__ float lim[LPB][LdsRows::words(L)];
+    __shared__ float lre[LPB][LdsRows<L>::words(L)];
+    __shared__ float lim[LPB][LdsRows<L>::words(L)];
     __shared__ float4 red[256];
     const int line = threadIdx.x / T, t = threadIdx.x % T;
     const int gl = blockIdx.x * LPB + line;       // row pair over the batch
