@@ -88,15 +88,21 @@ typedef struct {
     uint32_t flags;     /* FMBYM_HANN | FMBYM_XY_UNWINDOWED                                */
 } fmbym_params;
 
-/* Column-tile widths of the column passes: how many float4 columns one block
- * transforms (4, 8 or 16).  They change speed, never results: every width runs
- * the same arithmetic on every column.  A new plan starts from defaults for its
- * n; fmbym_autotune measures and sets the fastest. */
+/* Launch choices of a plan: column-tile widths of the column passes (how many
+ * float4 columns one block transforms: 4, 8 or 16) and the batch split.  They
+ * change speed, never results: every choice runs the same arithmetic on every
+ * pair and column.  A new plan starts from defaults for its n; fmbym_autotune
+ * measures and sets the fastest.  Because of the split's stream and events,
+ * calls on one plan must not be issued concurrently from several host threads. */
 typedef struct {
     int32_t cols1;      /* stage-1 column FFTs and |F|                      */
     int32_t cols2;      /* stage-2 column correlation                       */
     int32_t cols_xy;    /* adjoint of the stage-2 column correlation        */
     int32_t cols_mag;   /* adjoint of |F| and the stage-1 columns            */
+    int32_t split;      /* 1, or 2: the search calls run the two halves of a
+                           batch concurrently, the second on a stream the plan
+                           owns (joined back to the caller's stream by events;
+                           still capturable into a graph)                   */
 } fmbym_tuning;
 
 /* Validate `p` and build a plan (uploads constant tables to the current device;
@@ -134,14 +140,15 @@ FMBYM_API int fmbym_search_backward(fmbym_plan plan, int32_t batch, const float*
 /* ---------------------------------------------------------------- tuning
  *
  * fmbym_plan_get_tuning / fmbym_plan_set_tuning read and replace the plan's
- * column-tile widths (set: FMBYM_EINVAL unless every width is 4, 8 or 16).
+ * launch choices (set: FMBYM_EINVAL unless every width is 4, 8 or 16 and
+ * split is 1 or 2).
  * Not to be called while searches on the plan are in flight.
  *
  * fmbym_autotune times whole search steps on synthetic inputs it writes into
- * its workspace (fmbym_autotune_workspace_size bytes) and picks the widths one
- * pass at a time (coordinate search over 4, 8, 16, in the order cols1, cols2,
- * cols_xy, cols_mag; with_backward = 0 times the forward alone and leaves the
- * adjoint's widths as they are).  It synchronises `stream`, creates and
+ * its workspace (fmbym_autotune_workspace_size bytes) and picks the choices one
+ * at a time (split over 1, 2, then the widths over 4, 8, 16 in the order cols1,
+ * cols2, cols_xy, cols_mag; with_backward = 0 times the forward alone and
+ * leaves the adjoint's widths as they are).  It synchronises `stream`, creates and
  * destroys two HIP events, sets the result on the plan and writes it to *best;
  * ms_per_step (or NULL) receives the best step time.  Results of the searches
  * do not depend on the choice. */

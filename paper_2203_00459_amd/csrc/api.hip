@@ -48,6 +48,15 @@ int check_params(const fmbym_params* p) {
 
 hipError_t free_plan_tables(Plan* pl) {
     hipError_t first = hipSuccess;
+    if (pl->join) first = hipEventDestroy(pl->join);
+    if (pl->fork) {
+        hipError_t e = hipEventDestroy(pl->fork);
+        if (first == hipSuccess) first = e;
+    }
+    if (pl->aux) {
+        hipError_t e = hipStreamDestroy(pl->aux);
+        if (first == hipSuccess) first = e;
+    }
     void* ptrs[] = {pl->twiddle, pl->twiddle3, pl->hann, pl->csr_ptr, pl->csr_col, pl->csr_val, pl->csr_dst, pl->dmag_part};
     for (void* q : ptrs) {
         if (!q) continue;
@@ -106,6 +115,9 @@ int fmbym_plan_create(const fmbym_params* p, int32_t max_batch, fmbym_plan* out)
     if (e == hipSuccess) e = hipMemcpy(pl->hann, hann, sizeof(float) * p->n, hipMemcpyHostToDevice);
     delete[] hann;
     if (e == hipSuccess) e = (hipError_t)build_polar_csr(*pl);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&pl->aux, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->join, hipEventDisableTiming);
     if (e != hipSuccess) {
         free_plan_tables(pl);
         delete pl;
@@ -126,9 +138,9 @@ int fmbym_plan_destroy(fmbym_plan plan) {
 size_t fmbym_search_workspace_size(fmbym_plan plan, int32_t batch, int with_backward) {
     if (check_call(plan, batch)) return 0;
     const Plan* pl = plan_cast(plan);
-    const size_t fwd = fwd_layout(pl->p, batch).total;
+    const size_t fwd = run_fwd_workspace(*pl, batch);
     if (!with_backward) return fwd;
-    const size_t bwd = bwd_workspace(pl->p, batch);
+    const size_t bwd = run_bwd_workspace(*pl, batch);
     return bwd > fwd ? bwd : fwd;
 }
 
@@ -140,9 +152,9 @@ int fmbym_search(fmbym_plan plan, int32_t batch, const float* f, const float* g,
     if (!f || !g || !pose) return FMBYM_EINVAL;
     if ((m_f == nullptr) != (m_g == nullptr)) return FMBYM_EINVAL;
     const Plan* pl = plan_cast(plan);
-    if (!workspace || workspace_bytes < fwd_layout(pl->p, batch).total) return FMBYM_EWORKSPACE;
-    rc = launch_forward(*pl, batch, f, g, m_f, m_g, pose, c_theta, c_xy, saved, (char*)workspace,
-                        (hipStream_t)stream);
+    if (!workspace || workspace_bytes < run_fwd_workspace(*pl, batch)) return FMBYM_EWORKSPACE;
+    rc = run_forward(*pl, batch, f, g, m_f, m_g, pose, c_theta, c_xy, saved, (char*)workspace,
+                     (hipStream_t)stream, nullptr);
     if (rc) return rc;
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? FMBYM_OK : hip_fail(e);
@@ -161,9 +173,9 @@ int fmbym_search_backward(fmbym_plan plan, int32_t batch, const float* f, const 
     if ((m_f == nullptr) != (d_m_f == nullptr) || (m_g == nullptr) != (d_m_g == nullptr))
         return FMBYM_EINVAL;
     const Plan* pl = plan_cast(plan);
-    if (!workspace || workspace_bytes < bwd_workspace(pl->p, batch)) return FMBYM_EWORKSPACE;
-    rc = launch_backward(*pl, batch, f, g, m_f, m_g, pose, c_theta, c_xy, saved, d_pose, d_f, d_g,
-                         d_m_f, d_m_g, (char*)workspace, (hipStream_t)stream);
+    if (!workspace || workspace_bytes < run_bwd_workspace(*pl, batch)) return FMBYM_EWORKSPACE;
+    rc = run_backward(*pl, batch, f, g, m_f, m_g, pose, c_theta, c_xy, saved, d_pose, d_f, d_g, d_m_f,
+                      d_m_g, (char*)workspace, (hipStream_t)stream, nullptr);
     if (rc) return rc;
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? FMBYM_OK : hip_fail(e);
@@ -179,6 +191,7 @@ int fmbym_plan_set_tuning(fmbym_plan plan, const fmbym_tuning* t) {
     if (!plan || !t) return FMBYM_EINVAL;
     if (!valid_tile(t->cols1) || !valid_tile(t->cols2) || !valid_tile(t->cols_xy) || !valid_tile(t->cols_mag))
         return FMBYM_EINVAL;
+    if (t->split != 1 && t->split != 2) return FMBYM_EINVAL;
     plan_cast(plan)->tune = *t;
     return FMBYM_OK;
 }
@@ -219,10 +232,10 @@ int fmbym_search_train(fmbym_plan plan, int32_t batch, const float* f, const flo
     if ((m_f == nullptr) != (m_g == nullptr)) return FMBYM_EINVAL;
     const Plan* pl = plan_cast(plan);
     if (!state || state_bytes < keep_bytes(pl->p, batch)) return FMBYM_EWORKSPACE;
-    if (!workspace || workspace_bytes < fwd_layout(pl->p, batch).total) return FMBYM_EWORKSPACE;
+    if (!workspace || workspace_bytes < run_fwd_workspace(*pl, batch)) return FMBYM_EWORKSPACE;
     const Keep keep = keep_pointers(pl->p, batch, state);
-    rc = launch_forward(*pl, batch, f, g, m_f, m_g, pose, c_theta, c_xy, saved, (char*)workspace,
-                        (hipStream_t)stream, nullptr, &keep);
+    rc = run_forward(*pl, batch, f, g, m_f, m_g, pose, c_theta, c_xy, saved, (char*)workspace,
+                     (hipStream_t)stream, &keep);
     if (rc) return rc;
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? FMBYM_OK : hip_fail(e);
@@ -243,10 +256,10 @@ int fmbym_search_backward_state(fmbym_plan plan, int32_t batch, const float* f, 
         return FMBYM_EINVAL;
     const Plan* pl = plan_cast(plan);
     if (!state || state_bytes < keep_bytes(pl->p, batch)) return FMBYM_EWORKSPACE;
-    if (!workspace || workspace_bytes < bwd_workspace(pl->p, batch)) return FMBYM_EWORKSPACE;
+    if (!workspace || workspace_bytes < run_bwd_workspace(*pl, batch)) return FMBYM_EWORKSPACE;
     const Keep keep = keep_pointers(pl->p, batch, (void*)state);
-    rc = launch_backward(*pl, batch, f, g, m_f, m_g, pose, c_theta, c_xy, saved, d_pose, d_f, d_g,
-                         d_m_f, d_m_g, (char*)workspace, (hipStream_t)stream, &keep);
+    rc = run_backward(*pl, batch, f, g, m_f, m_g, pose, c_theta, c_xy, saved, d_pose, d_f, d_g, d_m_f,
+                      d_m_g, (char*)workspace, (hipStream_t)stream, &keep);
     if (rc) return rc;
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? FMBYM_OK : hip_fail(e);

@@ -46,7 +46,9 @@ struct Plan {
     int* csr_dst;
     int* dmag_part;    // [dmag_nparts + 1] first CSR row of each adjoint block
     int dmag_nparts;
-    fmbym_tuning tune; // column-tile widths of the column passes
+    fmbym_tuning tune; // column-tile widths of the column passes, batch split
+    hipStream_t aux;   // second stream of a split batch (default priority)
+    hipEvent_t fork, join;
 };
 
 // Widths measured best at 512 x 512 before tuning (8 float4 columns read whole
@@ -142,6 +144,22 @@ void launch_stage1_spectra(const Plan& pl, int batch, const float* f, const floa
                            const float* mg, float4* r1, float2* mag, hipStream_t s);
 
 size_t bwd_workspace(const fmbym_params& p, int batch);
+// The pairs [b0, b0 + ...) of a full-batch state (every kept array is batch-major).
+Keep keep_slice(const Keep& k, const fmbym_params& p, int b0);
+
+// Search calls with the plan's batch split: the halves run on the caller's
+// stream and the plan's aux stream (fork/join by events), each in its own
+// region of the workspace; keep_full is the state of the whole batch or null.
+size_t run_fwd_workspace(const Plan& pl, int batch);
+size_t run_bwd_workspace(const Plan& pl, int batch);
+int run_forward(const Plan& pl, int batch, const float* f, const float* g, const float* mf, const float* mg,
+                float* pose, float* c_theta, float* c_xy, float* saved, char* ws, hipStream_t s,
+                const Keep* keep_full);
+int run_backward(const Plan& pl, int batch, const float* f, const float* g, const float* mf,
+                 const float* mg, const float* pose, const float* c_theta, const float* c_xy,
+                 const float* saved, const float* d_pose, float* d_f, float* d_g, float* d_mf, float* d_mg,
+                 char* ws, hipStream_t s, const Keep* keep_full);
+
 // keep: null (recompute the spectra and g'), or the state of a training forward.
 int launch_backward(const Plan& pl, int batch, const float* f, const float* g, const float* mf,
                     const float* mg, const float* pose, const float* c_theta, const float* c_xy,

@@ -662,6 +662,17 @@ Keep keep_pointers(const fmbym_params& p, int batch, void* state) {
     return k;
 }
 
+Keep keep_slice(const Keep& k, const fmbym_params& p, int b0) {
+    const size_t n = p.n, b = b0;
+    Keep r;
+    r.r1 = k.r1 + b * n * pitch_rows1(p.n);
+    r.mag = k.mag + b * n * pitch_mag(p.n);
+    r.gr = k.gr + b * n * n;
+    r.jac = k.jac + b * n * n;
+    r.r2 = k.r2 + b * n * pitch_rows2(p.n);
+    return r;
+}
+
 // Column-tile widths are the plan's tuning (fmbym_tuning: 4, 8 or 16 columns
 // per block); every width gives the same arithmetic per column.
 template <int N, int C>

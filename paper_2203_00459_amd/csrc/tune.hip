@@ -13,6 +13,7 @@ fmbym_tuning default_tuning(int n) {
     t.cols2 = n >= 512 ? 4 : (n >= 256 ? 8 : 16);
     t.cols_xy = n >= 512 ? 4 : (n >= 256 ? 8 : 16);
     t.cols_mag = n >= 512 ? 4 : 16;
+    t.split = n >= 512 ? 2 : 1;
     return t;
 }
 
@@ -64,7 +65,7 @@ TuneLayout tune_layout(const Plan& pl, int B, int with_bwd) {
     L.df = with_bwd ? take(B * n2 * 4) : 0;
     L.dg = with_bwd ? take(B * n2 * 4) : 0;
     L.state = with_bwd ? take(keep_bytes(pl.p, B)) : 0;
-    const size_t fw = fwd_layout(pl.p, B).total, bw = with_bwd ? bwd_workspace(pl.p, B) : 0;
+    const size_t fw = run_fwd_workspace(pl, B), bw = with_bwd ? run_bwd_workspace(pl, B) : 0;
     L.ws = take(fw > bw ? fw : bw);
     L.total = off;
     return L;
@@ -102,14 +103,14 @@ int fmbym_autotune(fmbym_plan plan, int32_t batch, int with_backward, void* work
     hipLaunchKernelGGL(k_tune_fill, dim3(1), dim3(256), 0, s, (float*)(w + L.dpose), (size_t)batch * 3, 0u, 1);
     const Keep keep = bwd ? keep_pointers(pl.p, batch, w + L.state) : Keep{};
     auto step = [&]() -> int {
-        int r = launch_forward(pl, batch, (float*)(w + L.f), (float*)(w + L.g), nullptr, nullptr,
-                               (float*)(w + L.pose), (float*)(w + L.cth), (float*)(w + L.cxy),
-                               (float*)(w + L.saved), w + L.ws, s, nullptr, bwd ? &keep : nullptr);
+        int r = run_forward(pl, batch, (float*)(w + L.f), (float*)(w + L.g), nullptr, nullptr,
+                            (float*)(w + L.pose), (float*)(w + L.cth), (float*)(w + L.cxy),
+                            (float*)(w + L.saved), w + L.ws, s, bwd ? &keep : nullptr);
         if (r || !bwd) return r;
-        return launch_backward(pl, batch, (float*)(w + L.f), (float*)(w + L.g), nullptr, nullptr,
-                               (float*)(w + L.pose), (float*)(w + L.cth), (float*)(w + L.cxy),
-                               (float*)(w + L.saved), (float*)(w + L.dpose), (float*)(w + L.df),
-                               (float*)(w + L.dg), nullptr, nullptr, w + L.ws, s, &keep);
+        return run_backward(pl, batch, (float*)(w + L.f), (float*)(w + L.g), nullptr, nullptr,
+                            (float*)(w + L.pose), (float*)(w + L.cth), (float*)(w + L.cxy),
+                            (float*)(w + L.saved), (float*)(w + L.dpose), (float*)(w + L.df),
+                            (float*)(w + L.dg), nullptr, nullptr, w + L.ws, s, &keep);
     };
     hipEvent_t e0, e1;
     hipError_t e = hipEventCreate(&e0);
@@ -137,14 +138,17 @@ int fmbym_autotune(fmbym_plan plan, int32_t batch, int with_backward, void* work
         return FMBYM_OK;
     };
     const fmbym_tuning start = pl.tune;
-    int32_t* knob[4] = {&pl.tune.cols1, &pl.tune.cols2, &pl.tune.cols_xy, &pl.tune.cols_mag};
-    const int nknobs = bwd ? 4 : 2;
-    const int widths[3] = {4, 8, 16};
+    int32_t* knob[5] = {&pl.tune.split, &pl.tune.cols1, &pl.tune.cols2, &pl.tune.cols_xy, &pl.tune.cols_mag};
+    const int nknobs = bwd ? 5 : 3;
+    const int widths[3] = {4, 8, 16}, splits[2] = {1, 2};
     float best_ms = 0.f;
     rc = timed(&best_ms);
     for (int k = 0; rc == FMBYM_OK && k < nknobs; ++k) {
         int keep_w = *knob[k];
-        for (int c : widths) {
+        const int* cand = k == 0 ? splits : widths;
+        const int ncand = k == 0 ? (batch >= 2 ? 2 : 1) : 3;
+        for (int ci = 0; ci < ncand; ++ci) {
+            const int c = cand[ci];
             if (c == keep_w) continue;
             *knob[k] = c;
             float ms = 0.f;

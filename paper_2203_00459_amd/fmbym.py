@@ -72,7 +72,7 @@ class fmbym_pair(ctypes.Structure):
 
 class fmbym_tuning(ctypes.Structure):
     _fields_ = [("cols1", ctypes.c_int32), ("cols2", ctypes.c_int32), ("cols_xy", ctypes.c_int32),
-                ("cols_mag", ctypes.c_int32)]
+                ("cols_mag", ctypes.c_int32), ("split", ctypes.c_int32)]
 
 
 class fmbym_mask_desc(ctypes.Structure):
@@ -222,7 +222,7 @@ def search_backward(plan, batch, f, g, m_f, m_g, pose, c_theta, c_xy, saved, d_p
         raise FmbymError(rc, "fmbym_search_backward")
 
 
-TUNING_FIELDS = ("cols1", "cols2", "cols_xy", "cols_mag")
+TUNING_FIELDS = ("cols1", "cols2", "cols_xy", "cols_mag", "split")
 
 
 def plan_get_tuning(plan) -> dict:

@@ -73,7 +73,7 @@ def test_calls_without_a_plan_are_rejected():
     assert L.fmbym_search_backward(None, 1, *([None] * 13), None, 0, None) == fmbym.FMBYM_EINVAL
     assert L.fmbym_search_state_size(None, 1) == 0
     assert L.fmbym_joint_workspace_size(None, 1, 64) == 0
-    t = fmbym.fmbym_tuning(8, 8, 8, 8)
+    t = fmbym.fmbym_tuning(8, 8, 8, 8, 1)
     assert L.fmbym_plan_get_tuning(None, ctypes.byref(t)) == fmbym.FMBYM_EINVAL
     assert L.fmbym_plan_set_tuning(None, ctypes.byref(t)) == fmbym.FMBYM_EINVAL
     assert L.fmbym_autotune_workspace_size(None, 1, 1) == 0

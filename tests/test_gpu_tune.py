@@ -13,13 +13,13 @@ from paper_2203_00459_amd import fmbym, synth, tune, workloads
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda:0"
-TUNINGS = [dict(cols1=c, cols2=c, cols_xy=c, cols_mag=c) for c in (4, 8, 16)] + [
-    dict(cols1=16, cols2=4, cols_xy=8, cols_mag=4)]
+TUNINGS = [dict(cols1=c, cols2=c, cols_xy=c, cols_mag=c, split=1) for c in (4, 8, 16)] + [
+    dict(cols1=16, cols2=4, cols_xy=8, cols_mag=4, split=2), dict(cols1=8, cols2=8, cols_xy=4, cols_mag=16, split=2)]
 
 
 @pytest.mark.parametrize("name", ["pair128", "batch256", "batch512"])
 def test_every_width_gives_the_same_bits(name):
-    B = 2
+    B = 3   # an odd batch: the split's halves are 2 and 1 pairs
     print(f"case {name}", flush=True)
     s = fmbym.Search(max_batch=B, **workloads.search_kwargs(name))
     f, g, _ = synth.make_batch(name, B, split="val")
@@ -47,7 +47,9 @@ def test_every_width_gives_the_same_bits(name):
 def test_set_tuning_rejects_unsupported_widths():
     s = fmbym.Search(max_batch=1, **workloads.search_kwargs("pair128"))
     with pytest.raises(fmbym.FmbymError):
-        fmbym.plan_set_tuning(s.plan, dict(cols1=4, cols2=6, cols_xy=4, cols_mag=4))
+        fmbym.plan_set_tuning(s.plan, dict(cols1=4, cols2=6, cols_xy=4, cols_mag=4, split=1))
+    with pytest.raises(fmbym.FmbymError):
+        fmbym.plan_set_tuning(s.plan, dict(cols1=4, cols2=4, cols_xy=4, cols_mag=4, split=3))
     s.close()
 
 
@@ -57,9 +59,10 @@ def test_autotune_sets_supported_widths_and_caches(tmp_path):
     r = tune.autotune(s, 8, with_backward=True, cache_path=path)
     print("autotune", r, flush=True)
     assert not r["from_cache"] and r["ms_per_step"] > 0
-    assert all(v in (4, 8, 16) for v in r["tuning"].values())
+    assert all(r["tuning"][k] in (4, 8, 16) for k in ("cols1", "cols2", "cols_xy", "cols_mag"))
+    assert r["tuning"]["split"] in (1, 2)
     assert fmbym.plan_get_tuning(s.plan) == r["tuning"]
-    fmbym.plan_set_tuning(s.plan, dict(cols1=4, cols2=4, cols_xy=4, cols_mag=4))
+    fmbym.plan_set_tuning(s.plan, dict(cols1=4, cols2=4, cols_xy=4, cols_mag=4, split=1))
     r2 = tune.autotune(s, 8, with_backward=True, cache_path=path)
     assert r2["from_cache"] and r2["tuning"] == r["tuning"]
     assert fmbym.plan_get_tuning(s.plan) == r["tuning"]
