@@ -78,7 +78,7 @@ def kernel_bytes(n: int, n_theta: int, n_r: int, batch: int, masked: bool, keep:
     runs once and also writes d g'/d theta; kb_rows_fwd2 transforms only the
     d c_xy lag rows; k_rows1 / k_cols1 run once)."""
     N2 = n * n
-    nrb = (n_r + 7) // 8
+    nrb = (n_r + max(2048 // n_theta, 4) - 1) // max(2048 // n_theta, 4)   # radius blocks of the polar pass
     hk = n_theta // 2 + 1
     m = 2 if masked else 1
     half = 2 * n * (n // 2) * 8            # both half spectra, complex64

@@ -71,9 +71,14 @@ int check_call(fmbym_plan plan, int32_t batch);
 // Record e as this thread's last HIP error (fmbym_last_hip_error); returns FMBYM_EHIP.
 int hip_fail(hipError_t e);
 
-// Geometry of the polar-gather blocks.
-constexpr int kRadiiPerBlock = 8;
-inline int radius_blocks(int n_r) { return (n_r + kRadiiPerBlock - 1) / kRadiiPerBlock; }
+// Geometry of the polar-gather blocks: radii per block of 256 threads, one
+// line per n_theta / 8 threads; at least 4 so that blocks of long lines still
+// sum several radii, and for n_theta >= 512 a single pass (the grid then fills
+// the GPU in whole rounds of blocks rather than leaving a nearly empty one).
+__host__ __device__ constexpr int radii_per_block(int n_theta) { return 2048 / n_theta > 4 ? 2048 / n_theta : 4; }
+inline int radius_blocks(int n_r, int n_theta) {
+    return (n_r + radii_per_block(n_theta) - 1) / radii_per_block(n_theta);
+}
 
 // Stage 2 correlates zero-padded scans of length pad2(n) = 3n/2 per axis: the
 // smallest length at which the circular correlation equals the linear one for

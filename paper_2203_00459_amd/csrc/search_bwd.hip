@@ -307,10 +307,10 @@ __global__ __launch_bounds__(256) void kb_polar(const float2* __restrict__ A,
                                                 const float2* __restrict__ tw,
                                                 const float2* __restrict__ dspec,
                                                 float2* __restrict__ dpol, int n_r, int batch) {
-    constexpr int L = NT, T = L / kEb, LPB = 256 / T, PASSES = (kRadiiPerBlock + LPB - 1) / LPB;
+    constexpr int L = NT, T = L / kEb, LPB = 256 / T, RPB = radii_per_block(NT), PASSES = (RPB + LPB - 1) / LPB;
     __shared__ float lre[LPB][LdsRows<L>::words(L)];
     __shared__ float lim[LPB][LdsRows<L>::words(L)];
-    const int nrb = (n_r + kRadiiPerBlock - 1) / kRadiiPerBlock;
+    const int nrb = (n_r + radii_per_block(NT) - 1) / radii_per_block(NT);
     const int total = batch * nrb;
     const int per_xcd = (total + 7) / 8;
     const int work = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
@@ -324,8 +324,8 @@ __global__ __launch_bounds__(256) void kb_polar(const float2* __restrict__ A,
     const float scale = 1.f / ((float)n_r * (float)NT);
     for (int pass = 0; pass < PASSES; ++pass) {
         const int slot = pass * LPB + line;
-        const int rad = rb * kRadiiPerBlock + slot;
-        const bool live = slot < kRadiiPerBlock && rad < n_r;
+        const int rad = rb * RPB + slot;
+        const bool live = slot < RPB && rad < n_r;
         float2 v[kEb];
 #pragma unroll
         for (int m = 0; m < kEb; ++m) {
@@ -697,7 +697,7 @@ size_t bwd_workspace(const fmbym_params& p, int batch) { return bwd_layout(p, ba
 template <int N, int NT>
 static void launch_bwd_polar(const Plan& pl, int B, const float2* A, const float2* dspec, float2* dpol,
                              hipStream_t s) {
-    const int nrb = radius_blocks(pl.p.n_r);
+    const int nrb = radius_blocks(pl.p.n_r, pl.p.n_theta);
     const int total = B * nrb;
     FMBYM_LAUNCH(kKBPolar, (kb_polar<NT, N>), dim3(((total + 7) / 8) * 8), dim3(256), s, A, pl.twiddle,
                  dspec, dpol, pl.p.n_r, B);

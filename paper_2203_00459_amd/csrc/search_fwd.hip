@@ -118,18 +118,18 @@ __global__ __launch_bounds__(C * N / kE) void k_cols1(const float4* __restrict__
     }
 }
 
-// One block per (pair, block of kRadiiPerBlock radii); grid is remapped so
+// One block per (pair, block of radii_per_block(NT) radii); grid is remapped so
 // that all blocks of one pair run on the same XCD (its L2 keeps the pair's
 // magnitude spectra).
 template <int NT, int N>
 __global__ __launch_bounds__(256) void k_polar(const float2* __restrict__ A,
                                                const float2* __restrict__ tw,
                                                float2* __restrict__ part, int n_r, int batch) {
-    constexpr int L = NT, T = L / kE, LPB = 256 / T, PASSES = (kRadiiPerBlock + LPB - 1) / LPB;
+    constexpr int L = NT, T = L / kE, LPB = 256 / T, RPB = radii_per_block(NT), PASSES = (RPB + LPB - 1) / LPB;
     constexpr int HK = NT / 2 + 1;
     __shared__ float lre[LPB][LdsRows<L>::words(L)];
     __shared__ float lim[LPB][LdsRows<L>::words(L)];
-    const int nrb = (n_r + kRadiiPerBlock - 1) / kRadiiPerBlock;
+    const int nrb = (n_r + radii_per_block(NT) - 1) / radii_per_block(NT);
     const int total = batch * nrb;
     // XCD-aware remap: hardware deals consecutive block ids round-robin over 8 XCDs
     const int per_xcd = (total + 7) / 8;
@@ -143,8 +143,8 @@ __global__ __launch_bounds__(256) void k_polar(const float2* __restrict__ A,
     for (int m = 0; m <= kE / 2; ++m) acc[m] = make_float2(0.f, 0.f);
     for (int pass = 0; pass < PASSES; ++pass) {
         const int slot = pass * LPB + line;
-        const int rad = rb * kRadiiPerBlock + slot;
-        const bool live = slot < kRadiiPerBlock && rad < n_r;
+        const int rad = rb * RPB + slot;
+        const bool live = slot < RPB && rad < n_r;
         float2 v[kE];
 #pragma unroll
         for (int m = 0; m < kE; ++m) {
@@ -252,7 +252,7 @@ __global__ __launch_bounds__(kAngleGroups * NT / kE) void k_angle_fin(
     __shared__ float red[T];
     __shared__ int redi[T];
     const int b = blockIdx.x;
-    const int nrb = (n_r + kRadiiPerBlock - 1) / kRadiiPerBlock;
+    const int nrb = (n_r + radii_per_block(NT) - 1) / radii_per_block(NT);
     const float2* src = part + (size_t)b * nrb * HK;
     {   // group q sums radius blocks q, q + G, ... ; the groups are then added in order
         const int q = threadIdx.x / T, tt = threadIdx.x % T;
@@ -628,7 +628,7 @@ FwdLayout fwd_layout(const fmbym_params& p, int batch) {
     const size_t r3 = B * n * (size_t)pitch_lag(p.n) * sizeof(float2);
     off = align256(off + (mag > r3 ? mag : r3));
     L.ptheta = off;
-    off = align256(off + B * (size_t)radius_blocks(p.n_r) * (p.n_theta / 2 + 1) * sizeof(float2));
+    off = align256(off + B * (size_t)radius_blocks(p.n_r, p.n_theta) * (p.n_theta / 2 + 1) * sizeof(float2));
     L.pxy = off;
     off = align256(off + B * (size_t)xy_partials_per_pair(p.n) * sizeof(float4));
     L.saved = off;
@@ -732,7 +732,7 @@ void launch_stage1_spectra(const Plan& pl, int B, const float* f, const float* g
 template <int N, int NT>
 static void launch_polar(const Plan& pl, int B, const float2* mag, float2* pth, float* c_theta,
                          float* pose, float* saved, hipStream_t s) {
-    const int nrb = radius_blocks(pl.p.n_r);
+    const int nrb = radius_blocks(pl.p.n_r, pl.p.n_theta);
     const int total = B * nrb;
     const int grid = ((total + 7) / 8) * 8;
     FMBYM_LAUNCH(kKPolar, (k_polar<NT, N>), dim3(grid), dim3(256), s, mag, pl.twiddle, pth, pl.p.n_r, B);
