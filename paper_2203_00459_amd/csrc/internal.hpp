@@ -58,7 +58,7 @@ bool valid_tile(int c);
 
 constexpr int kDmagTile = 16;     // bins per side of one tile of the CSR row order
 constexpr int kDmagRows = 256;    // at most this many CSR rows per adjoint block
-constexpr int kDmagChunk = 1024;  // and about this many entries (more only for a single row)
+constexpr int kDmagChunk = 512;   // and about this many entries (more only for a single row)
 
 // Build the plan's CSR transpose of the polar gather; returns a hipError_t.
 int build_polar_csr(Plan& pl);

@@ -374,16 +374,15 @@ __global__ __launch_bounds__(256) void kb_dmag(const int* __restrict__ ptr, cons
                                                const float2* __restrict__ dpol, float2* __restrict__ dA,
                                                int n, int n_r, int n_theta, int batch) {
     __shared__ float4 prod[kDmagChunk][kDmagPairs / 2];
-    __shared__ int lptr[kDmagRows + 1];
     const int tid = threadIdx.x;
+    // the block's entry range from two uniform reads: the entry loads need not
+    // wait for the rows' bounds, which each thread reads for itself
     const int r0 = part[blockIdx.x], nrow = part[blockIdx.x + 1] - r0;
-    for (int i = tid; i <= nrow; i += 256) lptr[i] = ptr[r0 + i];
-    __syncthreads();
-    const int e_begin = lptr[0], e_end = lptr[nrow];
+    const int e_begin = ptr[r0], e_end = ptr[r0 + nrow];
     const size_t pstride = (size_t)n_r * n_theta;
     const int p0 = blockIdx.y * kDmagPairs, np = min(kDmagPairs, batch - p0);
     const float2* src = dpol + (size_t)p0 * pstride;
-    const int my0 = tid < nrow ? lptr[tid] : 0, my1 = tid < nrow ? lptr[tid + 1] : 0;
+    const int my0 = tid < nrow ? ptr[r0 + tid] : 0, my1 = tid < nrow ? ptr[r0 + tid + 1] : 0;
     float2 acc[kDmagPairs];
 #pragma unroll
     for (int p = 0; p < kDmagPairs; ++p) acc[p] = make_float2(0.f, 0.f);
