@@ -117,7 +117,7 @@ FwdLayout fwd_layout(const fmbym_params& p, int batch);
 // its adjoint reads them instead of recomputing them.
 struct Keep {
     float4* r1;    // stage-1 row spectra [B][n][pitch_rows1] float4
-    float2* mag;   // stage-1 magnitudes [B][n][pitch_mag] float2
+    float2* pspec; // angular DFT of each radius of (P_f + i P_g) [B][n_r][n_theta] float2
     float* gr;     // g' = Rotate(g_w) [B][n][n]
     float* jac;    // d g' / d theta [B][n][n]
     float4* r2;    // stage-2 row spectra [B][n][pitch_rows2] float4

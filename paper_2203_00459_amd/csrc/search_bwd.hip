@@ -356,6 +356,53 @@ __global__ __launch_bounds__(256) void kb_polar(const float2* __restrict__ A,
     }
 }
 
+// kb_polar from the training forward's kept polar spectra: the angular DFT of
+// each radius (X = DFT(P_f + i P_g)) is read instead of gathered and
+// transformed again, the mirror X[-k] straight from the same row.
+template <int NT, int N>
+__global__ __launch_bounds__(256) void kb_polar_keep(const float2* __restrict__ pspec,
+                                                     const float2* __restrict__ tw,
+                                                     const float2* __restrict__ dspec,
+                                                     float2* __restrict__ dpol, int n_r, int batch) {
+    constexpr int L = NT, T = L / kEb, LPB = 256 / T, RPB = radii_per_block(NT), PASSES = (RPB + LPB - 1) / LPB;
+    __shared__ float lre[LPB][LdsRows<L>::words(L)];
+    __shared__ float lim[LPB][LdsRows<L>::words(L)];
+    const int nrb = (n_r + radii_per_block(NT) - 1) / radii_per_block(NT);
+    const int total = batch * nrb;
+    const int per_xcd = (total + 7) / 8;
+    const int work = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (work >= total) return;
+    const int b = work / nrb, rb = work % nrb;
+    const int line = threadIdx.x / T, t = threadIdx.x % T;
+    float2 D[kEb];
+#pragma unroll
+    for (int m = 0; m < kEb; ++m) D[m] = dspec[(size_t)b * NT + t + m * T];
+    const float scale = 1.f / ((float)n_r * (float)NT);
+    for (int pass = 0; pass < PASSES; ++pass) {
+        const int slot = pass * LPB + line;
+        const int rad = rb * RPB + slot;
+        const bool live = slot < RPB && rad < n_r;
+        const float2* X = pspec + ((size_t)b * n_r + (live ? rad : 0)) * NT;
+        float2 v[kEb];
+#pragma unroll
+        for (int m = 0; m < kEb; ++m) {
+            const int k = t + m * T;
+            const float2 x = live ? X[k] : make_float2(0.f, 0.f);
+            const float2 xm = live ? X[k == 0 ? 0 : NT - k] : make_float2(0.f, 0.f);
+            const float2 Pf = split_x(x, xm), Pg = split_y(x, xm);
+            const float2 a = cmulcj(D[m], Pg);     // conj(D) Pg
+            const float2 c = cmul(Pf, D[m]);
+            v[m] = make_float2(a.x - c.y, a.y + c.x);   // a + i c
+        }
+        ifft_line<L, kEb>(v, lre[line], lim[line], fresh_index(t), tw);
+        if (live) {
+            float2* o = dpol + ((size_t)b * n_r + rad) * NT;
+#pragma unroll
+            for (int m = 0; m < kEb; ++m) o[t + m * T] = cscale(v[m], scale);
+        }
+    }
+}
+
 // dA = Cart2Pol^T dP over the half-plane bins, from the plan's CSR transpose
 // of the polar gather (rows of bins outside the band are empty, so they come
 // out 0).  Block x owns the CSR rows [part[x], part[x+1]) (at most kDmagRows
@@ -694,12 +741,16 @@ static BwdLayout bwd_layout(const fmbym_params& p, int batch) {
 size_t bwd_workspace(const fmbym_params& p, int batch) { return bwd_layout(p, batch).total; }
 
 template <int N, int NT>
-static void launch_bwd_polar(const Plan& pl, int B, const float2* A, const float2* dspec, float2* dpol,
-                             hipStream_t s) {
+static void launch_bwd_polar(const Plan& pl, int B, const float2* A, const float2* pspec, const float2* dspec,
+                             float2* dpol, hipStream_t s) {
     const int nrb = radius_blocks(pl.p.n_r, pl.p.n_theta);
     const int total = B * nrb;
-    FMBYM_LAUNCH(kKBPolar, (kb_polar<NT, N>), dim3(((total + 7) / 8) * 8), dim3(256), s, A, pl.twiddle,
-                 dspec, dpol, pl.p.n_r, B);
+    if (pspec)
+        FMBYM_LAUNCH(kKBPolar, (kb_polar_keep<NT, N>), dim3(((total + 7) / 8) * 8), dim3(256), s, pspec,
+                     pl.twiddle, dspec, dpol, pl.p.n_r, B);
+    else
+        FMBYM_LAUNCH(kKBPolar, (kb_polar<NT, N>), dim3(((total + 7) / 8) * 8), dim3(256), s, A, pl.twiddle,
+                     dspec, dpol, pl.p.n_r, B);
 }
 
 template <int NT>
@@ -770,7 +821,7 @@ static int launch_bwd_n(const Plan& pl, int B, const float* f, const float* g, c
     float4* r1w = (float4*)(ws + fl.r1r2);
     const float4* r1 = keep ? keep->r1 : r1w;
     float2* magw = (float2*)(ws + fl.mag_r3);
-    const float2* mag = keep ? keep->mag : magw;
+    const float2* mag = magw;                 // recomputed |F| (unused with keep: kb_polar reads the spectra)
     const float4* rows2 = keep ? keep->r2 : rf;
     const int win = (pl.p.flags & FMBYM_HANN) ? 1 : 0;
     const int win2 = (win && !(pl.p.flags & FMBYM_XY_UNWINDOWED)) ? 1 : 0;
@@ -801,13 +852,13 @@ static int launch_bwd_n(const Plan& pl, int B, const float* f, const float* g, c
     // rotation-stage adjoint: recompute the stage-1 spectra, then transpose
     if (!keep) launch_stage1_spectra(pl, B, f, g, mf, mg, r1w, magw, s);
     switch (pl.p.n_theta) {
-        case 16: launch_bwd_polar<N, 16>(pl, B, mag, dspec, dpol, s); break;
-        case 32: launch_bwd_polar<N, 32>(pl, B, mag, dspec, dpol, s); break;
-        case 64: launch_bwd_polar<N, 64>(pl, B, mag, dspec, dpol, s); break;
-        case 128: launch_bwd_polar<N, 128>(pl, B, mag, dspec, dpol, s); break;
-        case 256: launch_bwd_polar<N, 256>(pl, B, mag, dspec, dpol, s); break;
-        case 512: launch_bwd_polar<N, 512>(pl, B, mag, dspec, dpol, s); break;
-        case 1024: launch_bwd_polar<N, 1024>(pl, B, mag, dspec, dpol, s); break;
+        case 16: launch_bwd_polar<N, 16>(pl, B, mag, keep ? keep->pspec : nullptr, dspec, dpol, s); break;
+        case 32: launch_bwd_polar<N, 32>(pl, B, mag, keep ? keep->pspec : nullptr, dspec, dpol, s); break;
+        case 64: launch_bwd_polar<N, 64>(pl, B, mag, keep ? keep->pspec : nullptr, dspec, dpol, s); break;
+        case 128: launch_bwd_polar<N, 128>(pl, B, mag, keep ? keep->pspec : nullptr, dspec, dpol, s); break;
+        case 256: launch_bwd_polar<N, 256>(pl, B, mag, keep ? keep->pspec : nullptr, dspec, dpol, s); break;
+        case 512: launch_bwd_polar<N, 512>(pl, B, mag, keep ? keep->pspec : nullptr, dspec, dpol, s); break;
+        case 1024: launch_bwd_polar<N, 1024>(pl, B, mag, keep ? keep->pspec : nullptr, dspec, dpol, s); break;
         default: return FMBYM_EUNSUPPORTED;
     }
     float2* dA = magw;                  // (recomputed magnitudes are dead after kb_polar)

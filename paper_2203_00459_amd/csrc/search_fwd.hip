@@ -124,7 +124,8 @@ __global__ __launch_bounds__(C * N / kE) void k_cols1(const float4* __restrict__
 template <int NT, int N>
 __global__ __launch_bounds__(256) void k_polar(const float2* __restrict__ A,
                                                const float2* __restrict__ tw,
-                                               float2* __restrict__ part, int n_r, int batch) {
+                                               float2* __restrict__ part, int n_r, int batch,
+                                               float2* __restrict__ spec_out) {
     constexpr int L = NT, T = L / kE, LPB = 256 / T, RPB = radii_per_block(NT), PASSES = (RPB + LPB - 1) / LPB;
     constexpr int HK = NT / 2 + 1;
     __shared__ float lre[LPB][LdsRows<L>::words(L)];
@@ -157,6 +158,11 @@ __global__ __launch_bounds__(256) void k_polar(const float2* __restrict__ A,
             }
         }
         fft_line<L, kE>(v, lre[line], lim[line], fresh_index(t), tw);
+        if (spec_out && live) {   // kept for the adjoint (training forward)
+            float2* o = spec_out + ((size_t)b * n_r + rad) * NT;
+#pragma unroll
+            for (int m = 0; m < kE; ++m) o[t + m * T] = v[m];
+        }
         float2 mir[kE];
         mirror_line<L, kE>(v, mir, lre[line], lim[line], fresh_index(t));
 #pragma unroll
@@ -642,7 +648,7 @@ FwdLayout fwd_layout(const fmbym_params& p, int batch) {
 size_t keep_bytes(const fmbym_params& p, int batch) {
     const size_t n = p.n, B = batch;
     return align256(B * n * (size_t)pitch_rows1(p.n) * sizeof(float4)) +
-           align256(B * n * (size_t)pitch_mag(p.n) * sizeof(float2)) + 2 * align256(B * n * n * sizeof(float)) +
+           align256(B * (size_t)p.n_r * p.n_theta * sizeof(float2)) + 2 * align256(B * n * n * sizeof(float)) +
            align256(B * n * (size_t)pitch_rows2(p.n) * sizeof(float4));
 }
 
@@ -652,8 +658,8 @@ Keep keep_pointers(const fmbym_params& p, int batch, void* state) {
     Keep k;
     k.r1 = (float4*)c;
     c += align256(B * n * (size_t)pitch_rows1(p.n) * sizeof(float4));
-    k.mag = (float2*)c;
-    c += align256(B * n * (size_t)pitch_mag(p.n) * sizeof(float2));
+    k.pspec = (float2*)c;
+    c += align256(B * (size_t)p.n_r * p.n_theta * sizeof(float2));
     k.gr = (float*)c;
     c += align256(B * n * n * sizeof(float));
     k.jac = (float*)c;
@@ -666,7 +672,7 @@ Keep keep_slice(const Keep& k, const fmbym_params& p, int b0) {
     const size_t n = p.n, b = b0;
     Keep r;
     r.r1 = k.r1 + b * n * pitch_rows1(p.n);
-    r.mag = k.mag + b * n * pitch_mag(p.n);
+    r.pspec = k.pspec + b * (size_t)p.n_r * p.n_theta;
     r.gr = k.gr + b * n * n;
     r.jac = k.jac + b * n * n;
     r.r2 = k.r2 + b * n * pitch_rows2(p.n);
@@ -731,11 +737,12 @@ void launch_stage1_spectra(const Plan& pl, int B, const float* f, const float* g
 
 template <int N, int NT>
 static void launch_polar(const Plan& pl, int B, const float2* mag, float2* pth, float* c_theta,
-                         float* pose, float* saved, hipStream_t s) {
+                         float* pose, float* saved, hipStream_t s, float2* spec_out) {
     const int nrb = radius_blocks(pl.p.n_r, pl.p.n_theta);
     const int total = B * nrb;
     const int grid = ((total + 7) / 8) * 8;
-    FMBYM_LAUNCH(kKPolar, (k_polar<NT, N>), dim3(grid), dim3(256), s, mag, pl.twiddle, pth, pl.p.n_r, B);
+    FMBYM_LAUNCH(kKPolar, (k_polar<NT, N>), dim3(grid), dim3(256), s, mag, pl.twiddle, pth, pl.p.n_r, B,
+                 spec_out);
     FMBYM_LAUNCH(kKAngleFin, k_angle_fin<NT>, dim3(B), dim3(kAngleGroups * NT / kE), s, pth, pl.p.n_r,
                  pl.twiddle, pl.p.temp_theta, c_theta, pose, saved);
 }
@@ -770,19 +777,19 @@ static int launch_n(const Plan& pl, int B, const float* f, const float* g, const
                     char* ws, hipStream_t s, const float* const* tab, const Keep* keep) {
     const FwdLayout lay = fwd_layout(pl.p, B);
     float4* r1 = keep ? keep->r1 : (float4*)(ws + lay.r1r2);
-    float2* mag = keep ? keep->mag : (float2*)(ws + lay.mag_r3);
+    float2* mag = (float2*)(ws + lay.mag_r3);   // dead after k_polar (the adjoint keeps the polar spectra)
     float2* pth = (float2*)(ws + lay.ptheta);
     float4* pxy = (float4*)(ws + lay.pxy);
     float* sv = saved ? saved : (float*)(ws + lay.saved);
     launch_stage1_rows_cols<N>(pl, B, f, g, mf, mg, r1, mag, s, tab);
     switch (pl.p.n_theta) {
-        case 16: launch_polar<N, 16>(pl, B, mag, pth, c_theta, pose, sv, s); break;
-        case 32: launch_polar<N, 32>(pl, B, mag, pth, c_theta, pose, sv, s); break;
-        case 64: launch_polar<N, 64>(pl, B, mag, pth, c_theta, pose, sv, s); break;
-        case 128: launch_polar<N, 128>(pl, B, mag, pth, c_theta, pose, sv, s); break;
-        case 256: launch_polar<N, 256>(pl, B, mag, pth, c_theta, pose, sv, s); break;
-        case 512: launch_polar<N, 512>(pl, B, mag, pth, c_theta, pose, sv, s); break;
-        case 1024: launch_polar<N, 1024>(pl, B, mag, pth, c_theta, pose, sv, s); break;
+        case 16: launch_polar<N, 16>(pl, B, mag, pth, c_theta, pose, sv, s, keep ? keep->pspec : nullptr); break;
+        case 32: launch_polar<N, 32>(pl, B, mag, pth, c_theta, pose, sv, s, keep ? keep->pspec : nullptr); break;
+        case 64: launch_polar<N, 64>(pl, B, mag, pth, c_theta, pose, sv, s, keep ? keep->pspec : nullptr); break;
+        case 128: launch_polar<N, 128>(pl, B, mag, pth, c_theta, pose, sv, s, keep ? keep->pspec : nullptr); break;
+        case 256: launch_polar<N, 256>(pl, B, mag, pth, c_theta, pose, sv, s, keep ? keep->pspec : nullptr); break;
+        case 512: launch_polar<N, 512>(pl, B, mag, pth, c_theta, pose, sv, s, keep ? keep->pspec : nullptr); break;
+        case 1024: launch_polar<N, 1024>(pl, B, mag, pth, c_theta, pose, sv, s, keep ? keep->pspec : nullptr); break;
         default: return FMBYM_EUNSUPPORTED;
     }
     stage2_n<N>(pl, B, f, g, mf, mg, sv, c_xy, ws, s, tab, keep);
