@@ -99,6 +99,8 @@ __host__ __device__ constexpr int pitch_lag(int n) { return 3 * n / 4 + kPitchPa
 // Lines per 256-thread block of a stage-2 row kernel, and the softmax
 // partials per pair of the inverse-row kernel (one per block of lag-row pairs).
 __host__ __device__ constexpr int rows2_lines(int n) { return 256 / (pad2(n) / kE2); }
+// Rows each line of k_rows2 transforms in sequence (the next one's loads overlap the current transform).
+constexpr int kRows2Seq = 2;
 inline int xy_partials_per_pair(int n) { return (n / 2) / rows2_lines(n); }
 
 // Workspace carve-up shared by forward and backward launchers.
@@ -188,14 +190,16 @@ __device__ __forceinline__ PairScans pair_scans(const float* const* __restrict__
     return PairScans{f + o, g + o, mf ? mf + o : nullptr, mg ? mg + o : nullptr};
 }
 
-// Windowed (and masked) scan value at an integer pixel.
+// Windowed (and masked) scan value at an integer pixel.  Branch-free: the
+// mask is read through x when there is none and the window values always
+// (hann has n entries), and both are applied by selects, so that the loads of
+// a whole row are issued before the first use instead of each behind a branch.
 __device__ __forceinline__ float scan_w(const float* __restrict__ x, const float* __restrict__ m,
                                         const float* __restrict__ hann, int n, int r, int c,
                                         bool win) {
-    float v = x[r * n + c];
-    if (m) v *= m[r * n + c];
-    if (win) v *= hann[r] * hann[c];
-    return v;
+    const float* mp = m ? m : x;
+    const float xv = x[r * n + c], mv = mp[r * n + c], wv = hann[r] * hann[c];
+    return xv * (m ? mv : 1.f) * (win ? wv : 1.f);
 }
 
 // Source position of output pixel (i, j) under Rotate: R(theta) y about the centre.

@@ -353,31 +353,46 @@ __global__ __launch_bounds__(256) void k_rows2(const float* __restrict__ f, cons
     __shared__ float lre[LPB][LdsRows<L>::words(L)];
     __shared__ float lim[LPB][LdsRows<L>::words(L)];
     const int line = threadIdx.x / T, t = threadIdx.x % T;
-    const int grow = blockIdx.x * LPB + line;
-    const int b = grow / N, i = grow % N;
-    const PairScans sc = pair_scans(tab, b, N, f, g, mf, mg);
-    const float* grow_g = gr + (size_t)grow * N;
-    float2 v[E];
+    // kRows2Seq rows per line, one after the other: the next row's loads are in
+    // flight during the current row's transform
+    auto load = [&](int grow, float2 (&v)[E]) {
+        const int b = grow / N, i = grow % N;
+        const PairScans sc = pair_scans(tab, b, N, f, g, mf, mg);
+        const float* grow_g = gr + (size_t)grow * N;
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-        const int x = t + m * T;
-        if (m < 2 * E / 3) {   // x < n: data; the padding up to 3n/2 is zero
-            const float a = scan_w(sc.f, sc.mf, hann, N, i, x, win);
-            v[m] = make_float2(a, grow_g[x]);
-        } else {
-            v[m] = make_float2(0.f, 0.f);
+        for (int m = 0; m < E; ++m) {
+            const int x = t + m * T;
+            if (m < 2 * E / 3) {   // x < n: data; the padding up to 3n/2 is zero
+                const float a = scan_w(sc.f, sc.mf, hann, N, i, x, win);
+                v[m] = make_float2(a, grow_g[x]);
+            } else {
+                v[m] = make_float2(0.f, 0.f);
+            }
         }
-    }
-    fft_line<L, E>(v, lre[line], lim[line], t, tw);
-    float2 mir[E];
-    mirror_line<L, E>(v, mir, lre[line], lim[line], t);
-    float4* o = out + (size_t)grow * P2;
+    };
+    const int grow0 = (blockIdx.x * kRows2Seq) * LPB + line;
+    float2 v[E];
+    load(grow0, v);
 #pragma unroll
-    for (int m = 0; m <= E / 2; ++m) {
-        const int k = t + m * T;
-        if (k <= H) {
-            const float2 X = split_x(v[m], mir[m]), Y = split_y(v[m], mir[m]);
-            o[k] = make_float4(X.x, X.y, Y.x, Y.y);
+    for (int it = 0; it < kRows2Seq; ++it) {
+        const int grow = grow0 + it * LPB;
+        float2 nx[E];
+        if (it + 1 < kRows2Seq) load(grow + LPB, nx);
+        fft_line<L, E>(v, lre[line], lim[line], fresh_index(t), tw);
+        float2 mir[E];
+        mirror_line<L, E>(v, mir, lre[line], lim[line], fresh_index(t));
+        float4* o = out + (size_t)grow * P2;
+#pragma unroll
+        for (int m = 0; m <= E / 2; ++m) {
+            const int k = t + m * T;
+            if (k <= H) {
+                const float2 X = split_x(v[m], mir[m]), Y = split_y(v[m], mir[m]);
+                o[k] = make_float4(X.x, X.y, Y.x, Y.y);
+            }
+        }
+        if (it + 1 < kRows2Seq) {
+#pragma unroll
+            for (int m = 0; m < E; ++m) v[m] = nx[m];
         }
     }
 }
@@ -764,7 +779,7 @@ static void stage2_n(const Plan& pl, int B, const float* f, const float* g, cons
     float* gr = keep ? keep->gr : (float*)(ws + lay.grot);
     FMBYM_LAUNCH(kKRotate, k_rotate<N>, dim3(B * (N / kRotTY) * (N / kRotTX)), dim3(256), s, g, mg, pl.hann,
                  sv, gr, keep ? keep->jac : nullptr, win2, tab);
-    FMBYM_LAUNCH(kKRows2, k_rows2<N>, dim3(B * N / LPB2), dim3(256), s, f, g, mf, mg, pl.hann,
+    FMBYM_LAUNCH(kKRows2, k_rows2<N>, dim3(B * N / (LPB2 * kRows2Seq)), dim3(256), s, f, g, mf, mg, pl.hann,
                  pl.twiddle3, gr, r2, win2, tab);
     launch_cols2<N>(pl, B, r2, r3, s);
     FMBYM_LAUNCH(kKRows3, k_rows3<N>, dim3(B * (N / 2) / LPB2), dim3(256), s, r3, pl.twiddle3, c_xy,
