@@ -195,11 +195,12 @@ __global__ __launch_bounds__(C * pad2(N) / kE2) void kb_cols_xy(const float4* rf
 }
 
 // Entry k of the full L-point Hermitian spectrum from stored columns 0 .. L/2.
+// Branch-free (one load at the stored index, then selects), as herm_get.
 __device__ __forceinline__ float2 herm_get2(float2 (*get)(const float4*, int), const float4* row,
                                             int L, int k) {
-    if (k == 0 || k == L / 2) return make_float2(get(row, k).x, 0.f);
-    if (k < L / 2) return get(row, k);
-    return cconj(get(row, L - k));
+    const float2 a = get(row, k <= L / 2 ? k : L - k);
+    const bool real = k == 0 || k == L / 2;
+    return make_float2(a.x, real ? 0.f : (k < L / 2 ? a.y : -a.y));
 }
 __device__ __forceinline__ float2 get_lo(const float4* row, int k) { return make_float2(row[k].x, row[k].y); }
 __device__ __forceinline__ float2 get_hi(const float4* row, int k) { return make_float2(row[k].z, row[k].w); }
@@ -227,9 +228,12 @@ __global__ __launch_bounds__(256) void kb_rows_xy(const float4* __restrict__ q12
         const float2 h1 = herm_get2(get_lo, row, L, k), h2 = herm_get2(get_hi, row, L, k);
         v[m] = make_float2(h1.x - h2.y, h1.y + h2.x);
     }
+    const size_t base = (size_t)b * N * N;
+    float jv[2 * E / 3];   // loaded before the transform, whose barriers the loads cannot cross
+#pragma unroll
+    for (int m = 0; m < 2 * E / 3; ++m) jv[m] = jac[base + (size_t)i * N + t + m * T];
     ifft_line<L, E>(v, lre[line], lim[line], t, tw);
     const float scale = 1.f / ((float)L * (float)L);
-    const size_t base = (size_t)b * N * N;
     float dth = 0.f;
 #pragma unroll
     for (int m = 0; m < 2 * E / 3; ++m) {
@@ -238,7 +242,7 @@ __global__ __launch_bounds__(256) void kb_rows_xy(const float4* __restrict__ q12
         const size_t o = base + (size_t)i * N + x;
         df2[o] = a;
         dgp[o] = d;
-        dth += d * jac[o];   // d g'(i, x) / d theta through the bilinear sample position
+        dth += d * jv[m];   // d g'(i, x) / d theta through the bilinear sample position
     }
     red[threadIdx.x] = dth;
     __syncthreads();
@@ -659,23 +663,24 @@ __global__ __launch_bounds__(256) void kb_rows_final(
     const float4* q = r1 + (size_t)grow * P1;
     float2 v[kEb];
 #pragma unroll
-    for (int m = 0; m < kEb; ++m) {
+    for (int m = 0; m < kEb; ++m) {   // one load at the stored index, then selects (no branches)
         const int k = t + m * T;
+        const float4 a = q[k <= H ? k : N - k];          // (Qf, Qg)
         float2 z;
-        if (k == 0 || k == H) {
-            const float4 a = q[k];
-            z = make_float2(a.x, a.z);
-        } else if (k < H) {
-            const float4 a = q[k];                       // (Qf, Qg)
-            z = make_float2(0.5f * (a.x - a.w), 0.5f * (a.y + a.z));
-        } else {
-            const float4 a = q[N - k];
-            z = make_float2(0.5f * (a.x + a.w), 0.5f * (a.z - a.y));
-        }
+        if (k == 0 || k == H) z = make_float2(a.x, a.z);
+        else if (k < H) z = make_float2(0.5f * (a.x - a.w), 0.5f * (a.y + a.z));
+        else z = make_float2(0.5f * (a.x + a.w), 0.5f * (a.z - a.y));
         v[m] = z;
     }
-    ifft_line<L, kEb>(v, lre[line], lim[line], t, tw);
     const size_t base = (size_t)b * N * N;
+    float s2fv[kEb], s2gv[kEb];   // loaded before the transform, whose barriers the loads cannot cross
+#pragma unroll
+    for (int m = 0; m < kEb; ++m) {
+        const size_t o = base + (size_t)i * N + t + m * T;
+        s2fv[m] = df2[o];
+        s2gv[m] = dgr[o];
+    }
+    ifft_line<L, kEb>(v, lre[line], lim[line], t, tw);
     const float hi = win ? hann[i] : 1.f;
 #pragma unroll
     for (int m = 0; m < kEb; ++m) {
@@ -683,8 +688,8 @@ __global__ __launch_bounds__(256) void kb_rows_final(
         const size_t o = base + (size_t)i * N + x;
         const float w = win ? hi * hann[x] : 1.f;
         const float w2 = win2 ? w : 1.f;
-        const float s2f = df2[o];
-        const float s2g = dgr[o];
+        const float s2f = s2fv[m];
+        const float s2g = s2gv[m];
         // stage 1 always sees the window; stage 2 sees it unless unwindowed
         const float dft = w * v[m].x + w2 * s2f;
         const float dgt = w * v[m].y + w2 * s2g;

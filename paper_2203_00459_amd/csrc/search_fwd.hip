@@ -520,10 +520,12 @@ __global__ __launch_bounds__(C * pad2(N) / kE2) void k_cols2(const float4* __res
 
 // Entry k of the full L-point Hermitian spectrum of a lag row whose columns
 // 0 .. L/2 are stored (the DC and Nyquist entries are real by symmetry).
+// Branch-free: one load at the stored index, then conjugate / drop the
+// imaginary part by selects, so a line's loads issue together.
 __device__ __forceinline__ float2 herm_get(const float2* __restrict__ row, int L, int k) {
-    if (k == 0 || k == L / 2) return make_float2(row[k].x, 0.f);
-    if (k < L / 2) return row[k];
-    return cconj(row[L - k]);
+    const float2 a = row[k <= L / 2 ? k : L - k];
+    const bool real = k == 0 || k == L / 2;
+    return make_float2(a.x, real ? 0.f : (k < L / 2 ? a.y : -a.y));
 }
 
 template <int N>
