@@ -168,7 +168,7 @@ __global__ __launch_bounds__(C * pad2(N) / kE2) void kb_cols_xy(const float4* rf
         else if (m >= 2 * E / 3) vd[m] = sd[(size_t)(n - N) * P3 + col];
         else vd[m] = make_float2(0.f, 0.f);
     }
-    fft_line<L, E, LdsCols<C>>(vd, lre[c], lim[c], fresh_index(t), tw);
+    // F and G' too before the first transform, whose barriers loads cannot cross
     float2 vf[E], vg[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
@@ -180,6 +180,7 @@ __global__ __launch_bounds__(C * pad2(N) / kE2) void kb_cols_xy(const float4* rf
             vf[m] = vg[m] = make_float2(0.f, 0.f);
         }
     }
+    fft_line<L, E, LdsCols<C>>(vd, lre[c], lim[c], fresh_index(t), tw);
     fft_line<L, E, LdsCols<C>>(vf, lre[c], lim[c], fresh_index(t), tw);
 #pragma unroll
     for (int m = 0; m < E; ++m) vf[m] = cmul(vf[m], vd[m]);          // X2 = F DC
@@ -528,20 +529,22 @@ __global__ __launch_bounds__(C * N / kEb) void kb_cols_mag(const float4* r1, flo
     const float4* src = r1 + (size_t)b * N * P1;   // may equal out: a block reads its columns first
     float4* dst = out + (size_t)b * N * P1;
     const float2* da = dA + (size_t)b * N * PA;
-    float2 vf[kEb], vg[kEb];
+    float2 vf[kEb], vg[kEb], d[kEb];
+    const int cl = col <= H ? col : H;   // padding lanes of the last tile read a valid column, then use 0
 #pragma unroll
     for (int m = 0; m < kEb; ++m) {
         const float4 q = src[(size_t)(t + m * T) * P1 + col];
         vf[m] = make_float2(q.x, q.y);
         vg[m] = make_float2(q.z, q.w);
+        d[m] = da[(t + m * T) * PA + cl];   // dA too before the transforms, whose barriers loads cannot cross
     }
     fft_line<L, kEb, LdsCols<C>>(vf, lre[c], lim[c], fresh_index(t), tw);
     fft_line<L, kEb, LdsCols<C>>(vg, lre[c], lim[c], fresh_index(t), tw);
 #pragma unroll
     for (int m = 0; m < kEb; ++m) {
-        const float2 d = col <= H ? da[(t + m * T) * PA + col] : make_float2(0.f, 0.f);
-        vf[m] = mag_adjoint(vf[m], d.x);
-        vg[m] = mag_adjoint(vg[m], d.y);
+        const float2 dm = col <= H ? d[m] : make_float2(0.f, 0.f);
+        vf[m] = mag_adjoint(vf[m], dm.x);
+        vg[m] = mag_adjoint(vg[m], dm.y);
     }
     ifft_line<L, kEb, LdsCols<C>>(vf, lre[c], lim[c], fresh_index(t), tw);
     ifft_line<L, kEb, LdsCols<C>>(vg, lre[c], lim[c], fresh_index(t), tw);
