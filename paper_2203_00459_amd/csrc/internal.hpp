@@ -101,6 +101,8 @@ __host__ __device__ constexpr int pitch_lag(int n) { return 3 * n / 4 + kPitchPa
 __host__ __device__ constexpr int rows2_lines(int n) { return 256 / (pad2(n) / kE2); }
 // Rows each line of k_rows2 transforms in sequence (the next one's loads overlap the current transform).
 constexpr int kRows2Seq = 2;
+// The same for k_rows1 (rows of n points).
+constexpr int kRows1Seq = 2;
 inline int xy_partials_per_pair(int n) { return (n / 2) / rows2_lines(n); }
 
 // Workspace carve-up shared by forward and backward launchers.

@@ -628,6 +628,8 @@ __global__ __launch_bounds__(256) void kb_rotate_adj(const float* __restrict__ d
         const int ic = (int)rintf(cy), jc = (int)rintf(cx);
         float py0, px0;
         rot_src(N, ic, jc, ct, st, py0, px0);
+        py0 -= (float)qr;   // offsets of the window centre's sample position from q
+        px0 -= (float)qc;
         const int r0 = ic - 1 - by0, c0w = jc - 1 - bx0;
         const bool inside = (unsigned)r0 <= (unsigned)(bh - 3) && (unsigned)c0w <= (unsigned)(bw - 3);
         const float* w = box + (inside ? r0 * kRotBox + c0w : 0);
@@ -636,9 +638,10 @@ __global__ __launch_bounds__(256) void kb_rotate_adj(const float* __restrict__ d
         for (int di = 0; di < 3; ++di)
 #pragma unroll
             for (int dj = 0; dj < 3; ++dj) {
-                const float ey = fabsf(py0 + ky[di][dj] - (float)qr), ex = fabsf(px0 + kx[di][dj] - (float)qc);
-                const float v = w[di * kRotBox + dj];
-                if (ey < 1.f && ex < 1.f) acc += (1.f - ey) * (1.f - ex) * v;
+                // bilinear weight max(0, 1 - |e_y|) max(0, 1 - |e_x|): zero outside the unit box
+                const float wy = fmaxf(0.f, 1.f - fabsf(py0 + ky[di][dj]));
+                const float wx = fmaxf(0.f, 1.f - fabsf(px0 + kx[di][dj]));
+                acc += wy * wx * w[di * kRotBox + dj];
             }
         if (!inside) acc = 0.f;   // unreachable by the box bounds; keeps every LDS read in the box
         dgr[(size_t)b * N * N + (size_t)qr * N + qc] = acc;

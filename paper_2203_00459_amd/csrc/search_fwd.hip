@@ -40,35 +40,50 @@ __global__ __launch_bounds__(256) void k_rows1(const float* __restrict__ f, cons
     __shared__ float lre[LPB][LdsRows<L>::words(L)];
     __shared__ float lim[LPB][LdsRows<L>::words(L)];
     const int line = threadIdx.x / T, t = threadIdx.x % T;
-    const int grow = blockIdx.x * LPB + line;     // row over the batch
-    const int i = grow % N;
-    const PairScans sc = pair_scans(tab, grow / N, N, f, g, mf, mg);
-    const size_t off = (size_t)i * N;
-    const float* fr = sc.f + off;
-    const float* gr = sc.g + off;
-    const float* mfr = sc.mf ? sc.mf + off : nullptr;
-    const float* mgr = sc.mg ? sc.mg + off : nullptr;
-    const float hi = win ? hann[i] : 1.f;
+    // windowed, masked row of f + i g; branch-free (masks through a fallback
+    // pointer, window always read, selects), so a row's loads issue together
+    auto load = [&](int grow, float2 (&v)[kE]) {
+        const int i = grow % N;
+        const PairScans sc = pair_scans(tab, grow / N, N, f, g, mf, mg);
+        const size_t off = (size_t)i * N;
+        const float* fr = sc.f + off;
+        const float* gr = sc.g + off;
+        const float* mfr = (sc.mf ? sc.mf : sc.f) + off;
+        const float* mgr = (sc.mg ? sc.mg : sc.g) + off;
+        const bool mfo = sc.mf != nullptr, mgo = sc.mg != nullptr;
+        const float hi = hann[i];
+#pragma unroll
+        for (int m = 0; m < kE; ++m) {
+            const int x = t + m * T;
+            const float hx = hann[x], a = fr[x], c = gr[x], ma = mfr[x], mc = mgr[x];
+            const float w = win ? hi * hx : 1.f;
+            v[m] = make_float2((mfo ? a * ma : a) * w, (mgo ? c * mc : c) * w);
+        }
+    };
+    // kRows1Seq rows per line in sequence: the next row's loads overlap the current transform
+    const int grow0 = (blockIdx.x * kRows1Seq) * LPB + line;
     float2 v[kE];
+    load(grow0, v);
 #pragma unroll
-    for (int m = 0; m < kE; ++m) {
-        const int x = t + m * T;
-        const float w = win ? hi * hann[x] : 1.f;
-        float a = fr[x], c = gr[x];
-        if (mfr) a *= mfr[x];
-        if (mgr) c *= mgr[x];
-        v[m] = make_float2(a * w, c * w);
-    }
-    fft_line<L, kE>(v, lre[line], lim[line], t, tw);
-    float2 mir[kE];
-    mirror_line<L, kE>(v, mir, lre[line], lim[line], t);
-    float4* o = out + (size_t)grow * P;
+    for (int it = 0; it < kRows1Seq; ++it) {
+        const int grow = grow0 + it * LPB;
+        float2 nx[kE];
+        if (it + 1 < kRows1Seq) load(grow + LPB, nx);
+        fft_line<L, kE>(v, lre[line], lim[line], fresh_index(t), tw);
+        float2 mir[kE];
+        mirror_line<L, kE>(v, mir, lre[line], lim[line], fresh_index(t));
+        float4* o = out + (size_t)grow * P;
 #pragma unroll
-    for (int m = 0; m <= kE / 2; ++m) {
-        const int k = t + m * T;
-        if (k <= H) {
-            const float2 X = split_x(v[m], mir[m]), Y = split_y(v[m], mir[m]);
-            o[k] = make_float4(X.x, X.y, Y.x, Y.y);
+        for (int m = 0; m <= kE / 2; ++m) {
+            const int k = t + m * T;
+            if (k <= H) {
+                const float2 X = split_x(v[m], mir[m]), Y = split_y(v[m], mir[m]);
+                o[k] = make_float4(X.x, X.y, Y.x, Y.y);
+            }
+        }
+        if (it + 1 < kRows1Seq) {
+#pragma unroll
+            for (int m = 0; m < kE; ++m) v[m] = nx[m];
         }
     }
 }
@@ -737,7 +752,7 @@ static void launch_stage1_rows_cols(const Plan& pl, int B, const float* f, const
                                     hipStream_t s, const float* const* tab) {
     const int win = (pl.p.flags & FMBYM_HANN) ? 1 : 0;
     constexpr int T1 = N / kE, LPB1 = 256 / T1;
-    FMBYM_LAUNCH(kKRows1, k_rows1<N>, dim3(B * N / LPB1), dim3(256), s, f, g, mf, mg, pl.hann,
+    FMBYM_LAUNCH(kKRows1, k_rows1<N>, dim3(B * N / (LPB1 * kRows1Seq)), dim3(256), s, f, g, mf, mg, pl.hann,
                  pl.twiddle, r1, win, tab);
     launch_cols1<N>(pl, B, r1, mag, s);
 }
