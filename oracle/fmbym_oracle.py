@@ -359,6 +359,40 @@ def search_grad(f, g, d_pose, p: Params, m_f=None, m_g=None) -> dict:
     return res
 
 
+# ------------------------------------------ full-circle heading (Conclusion)
+
+def search_full_circle(f, g, p: Params, m_f=None, m_g=None) -> dict:
+    """Heading over the whole circle, for the metric localisation with arbitrary
+    rotational offset that the Conclusion proposes.
+
+    Stage 1 sees only magnitude spectra, and those of real scans are point
+    symmetric (|F(-k)| = |F(k)|, the property behind Eq. 5-6), so it fixes the
+    heading modulo pi.  Headings theta and theta + pi give different rotated
+    scans, though, so stage 2 (Eq. 9) tells them apart: run it at both and
+    keep the one whose correlation surface has the larger peak (max over the
+    lags of c_xy; the stage-1 heading on ties).  The other heading is written
+    in [-pi, pi): theta + pi for theta < 0, else theta - pi.  Its pose is
+    that stage's own soft-argmax translation, t = R(theta + pi) t'.
+    """
+    out = search(f, g, p, m_f, m_g)
+    theta = out["theta"]
+    alt = theta + math.pi if float(theta) < 0 else theta - math.pi
+    if p.xy_unwindowed:
+        f2 = torch.as_tensor(f).to(F64)
+        g2 = torch.as_tensor(g).to(F64)
+        if m_f is not None:
+            f2 = f2 * torch.as_tensor(m_f).to(F64)
+        if m_g is not None:
+            g2 = g2 * torch.as_tensor(m_g).to(F64)
+    else:
+        f2, g2 = out["fw"], out["gw"]
+    tx2, ty2, c_xy2, _ = stage_translation(f2, g2, alt, p)
+    peaks = torch.stack([out["c_xy"].max(), c_xy2.max()])
+    turned = bool(peaks[1] > peaks[0])
+    pose = torch.stack([alt, tx2, ty2]) if turned else out["pose"]
+    return dict(pose=pose, peaks=peaks, turned=turned, plain=out["pose"], c_xy_turned=c_xy2)
+
+
 # ------------------------------------------------- plain joint search (Eq. 2)
 
 def joint_headings(n_angles: int) -> torch.Tensor:

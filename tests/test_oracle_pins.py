@@ -389,6 +389,63 @@ def test_rotated_joint_recovers_a_lattice_pose():
     assert (j["tx"], j["ty"]) == (tx * 0.5, ty * 0.5)
 
 
+# ------------------------------------------------------ full-circle heading
+
+def test_full_circle_recovers_a_half_turn():
+    """Compact scene turned by exactly pi about the centre pixel and shifted by
+    whole pixels (a lattice permutation, so Eq. 1 holds exactly): the magnitude
+    spectra coincide, stage 1 returns 0, and only the second stage-2 run, at
+    -pi, finds the shift (Cauchy-Schwarz: its peak is the autocorrelation's)."""
+    n = 32
+    f = _blob_scene(n, [(12, 14), (18, 11), (15, 20), (10, 9)], [1.0, 0.7, 0.5, 0.9]).numpy()
+    for ty, tx in [(2, -3), (-1, 4)]:
+        # f(x) = g(R(pi) x + t)  <=>  g[i, j] = f[n + ty - i, n + tx - j]
+        g = np.roll(np.flip(f, (0, 1)), (ty + 1, tx + 1), axis=(0, 1))
+        p = O.Params(n=n, n_theta=32, delta_xy=0.25, temp_theta=1e-6, temp_xy=1e-6, hann=False)
+        fc = O.search_full_circle(f, g, p)
+        assert abs(float(fc["plain"][0])) < 1e-12
+        assert fc["turned"] and float(fc["peaks"][1]) > float(fc["peaks"][0])
+        th, px, py = [float(v) for v in fc["pose"]]
+        assert abs(th + math.pi) < 1e-12
+        assert abs(px - 0.25 * tx) < 1e-9 and abs(py - 0.25 * ty) < 1e-9
+        # and the recovered pose maps g onto f on the lattice
+        i, j = np.mgrid[0:n, 0:n]
+        gi = np.rint(n / 2 + math.sin(th) * (j - n / 2) + math.cos(th) * (i - n / 2) + py / 0.25).astype(int)
+        gj = np.rint(n / 2 + math.cos(th) * (j - n / 2) - math.sin(th) * (i - n / 2) + px / 0.25).astype(int)
+        inside = (gi >= 0) & (gi < n) & (gj >= 0) & (gj < n)
+        assert np.array_equal(g[gi[inside], gj[inside]], f[inside])
+        assert np.abs(f[~inside]).max() < 1e-3 * f.max()     # the scene tails off before the edges
+
+
+def test_full_circle_keeps_the_plain_search_when_it_wins():
+    """Pure shift (heading 0): the first stage-2 run has the larger peak, and the
+    pose is the plain search's, unchanged."""
+    n = 32
+    f = _blob_scene(n, [(12, 14), (18, 11), (15, 20), (10, 9)], [1.0, 0.7, 0.5, 0.9])
+    g = torch.roll(f, shifts=(3, -2), dims=(0, 1))
+    p = O.Params(n=n, n_theta=32, delta_xy=0.25, temp_theta=1e-6, temp_xy=1e-6, hann=False)
+    fc = O.search_full_circle(f, g, p)
+    assert not fc["turned"] and float(fc["peaks"][0]) > float(fc["peaks"][1])
+    assert torch.equal(fc["pose"], O.search(f, g, p)["pose"])
+
+
+def test_full_circle_on_generated_pairs_beyond_a_quarter_turn():
+    """Generated pairs at headings past +-90 deg: the plain search returns the
+    heading modulo pi, the full-circle search the heading itself (within a bin)
+    and the translation (within pixels)."""
+    spec = synth.WORKLOADS["pair128"]
+    p = O.Params(n=128, n_theta=128, delta_xy=0.5, band_lo=0.02, band_hi=0.4, temp_xy=0.05)
+    for i, th in enumerate([math.radians(150.0), math.radians(-125.0)]):
+        f, g, pose = synth.make_pair(spec, 1, "val", i, theta=th)
+        fc = O.search_full_circle(f, g, p)
+        wrap = lambda a: (a + math.pi) % (2 * math.pi) - math.pi
+        assert abs(wrap(float(fc["plain"][0]) - th + math.pi)) <= math.pi / 128
+        assert fc["turned"]
+        assert abs(wrap(float(fc["pose"][0]) - th)) <= math.pi / 128
+        assert -math.pi <= float(fc["pose"][0]) < math.pi
+        assert math.hypot(float(fc["pose"][1]) - pose[1], float(fc["pose"][2]) - pose[2]) <= 1.5
+
+
 # -------------------------------------------------------------------- gradients
 
 def test_gradient_matches_finite_differences():
