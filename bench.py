@@ -14,6 +14,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -440,6 +441,41 @@ def search_bench(args) -> int:
             "decoupled_speedup": ms_j / ms,
             "median_theta_err_rad": {"decoupled": td, "joint": tj},
             "median_t_err_m": {"decoupled": xd, "joint": xj}}
+
+        # full-circle heading (stage 2 again at theta + pi) on the same scenes
+        # with headings drawn over the whole circle
+        fc_f, fc_g, fc_gt = synth.make_batch(args.workload, B, split="bench", theta_max_deg=180.0)
+        Ff, Fg = torch.from_numpy(fc_f).to(dev), torch.from_numpy(fc_g).to(dev)
+        for _ in range(args.warmup):
+            fc = s.full_circle(Ff, Fg)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            fc = s.full_circle(Ff, Fg)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_fc = e0.elapsed_time(e1) / args.steps
+        plain = s.forward(Ff, Fg, surfaces=False)["pose"].double().cpu().numpy()
+        fcp = fc["pose"].double().cpu().numpy()
+
+        def wrap(a):
+            return (a + math.pi) % (2 * math.pi) - math.pi
+        step_rad = math.pi / nt
+        e_plain = np.abs(wrap(plain[:, 0] - fc_gt[:, 0]))
+        e_fc = np.abs(wrap(fcp[:, 0] - fc_gt[:, 0]))
+        # pass model: the forward (92 n^2) plus stage 2 again (S6-S8: 60 n^2)
+        fc_bytes = (92 + 60) * n * n * B
+        extra["full_circle"] = {
+            "ms_per_step": ms_fc, "value": B / (ms_fc * 1e-3), "unit": "pairs/s",
+            "vs_decoupled_forward": ms_fc / ms,
+            "roofline_path": {"bound": "hbm", "bytes_per_step": fc_bytes,
+                              "achieved": fc_bytes / (ms_fc * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                              "unit": "GB/s", "frac": fc_bytes / (ms_fc * 1e-3) / 1e9 / HBM_PEAK_GBS},
+            "headings": "uniform over [-pi, pi)",
+            "theta_within_2_bins": {"decoupled": float((e_plain <= 2 * step_rad).mean()),
+                                    "full_circle": float((e_fc <= 2 * step_rad).mean())},
+            "median_t_err_m": float(np.median(np.hypot(fcp[:, 1] - fc_gt[:, 1], fcp[:, 2] - fc_gt[:, 2])))}
 
     # second timed pass: HIP events around every library launch, on its stream;
     # the batch unsplit, so that every launch is one kernel over the whole batch

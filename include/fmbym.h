@@ -203,6 +203,26 @@ FMBYM_API int fmbym_search_joint(fmbym_plan plan, int32_t batch, int32_t n_angle
                                  const float* g, const float* m_f, const float* m_g, float* pose,
                                  float* peak, void* workspace, size_t workspace_bytes, void* stream);
 
+/* ---------------------------------------------------------------- full-circle heading
+ *
+ * The search for an arbitrary rotational offset (metric localisation, which
+ * the paper's Conclusion proposes for the decoupled search).  Stage 1 sees
+ * magnitude spectra, point symmetric for real scans (Eq. 5-6), so it fixes the
+ * heading only modulo pi: fmbym_search returns theta in [-pi/2, pi/2).  This
+ * call runs fmbym_search's forward, then the translation stage (Eq. 9) again
+ * at theta + pi, and keeps per pair the heading whose c_xy has the larger
+ * maximum (the first, theta, on ties).  About twice fmbym_search's stage-2 work.
+ *   pose   [batch][3] output (required): theta in [-pi, pi] and the
+ *          translation soft-argmax of the kept heading (t = R(theta) t');
+ *          theta + pi is written as theta + pi for theta < 0, else theta - pi
+ *   peaks  [batch][2] output, max c_xy at theta and at theta + pi, or NULL
+ * Windowing, masks, batch split, memory, stream and error rules as in
+ * fmbym_search; forward only (no adjoint). */
+FMBYM_API size_t fmbym_full_circle_workspace_size(fmbym_plan plan, int32_t batch);
+FMBYM_API int fmbym_search_full_circle(fmbym_plan plan, int32_t batch, const float* f, const float* g,
+                                       const float* m_f, const float* m_g, float* pose, float* peaks,
+                                       void* workspace, size_t workspace_bytes, void* stream);
+
 /* ---------------------------------------------------------------- ragged work lists
  *
  * A serving batch whose pairs come at several scan sizes (the method is timed

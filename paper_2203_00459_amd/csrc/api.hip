@@ -217,6 +217,26 @@ int fmbym_search_joint(fmbym_plan plan, int32_t batch, int32_t n_angles, const f
     return e == hipSuccess ? FMBYM_OK : hip_fail(e);
 }
 
+size_t fmbym_full_circle_workspace_size(fmbym_plan plan, int32_t batch) {
+    if (check_call(plan, batch)) return 0;
+    return run_full_circle_workspace(*plan_cast(plan), batch);
+}
+
+int fmbym_search_full_circle(fmbym_plan plan, int32_t batch, const float* f, const float* g,
+                             const float* m_f, const float* m_g, float* pose, float* peaks, void* workspace,
+                             size_t workspace_bytes, void* stream) {
+    int rc = check_call(plan, batch);
+    if (rc) return rc;
+    if (!f || !g || !pose) return FMBYM_EINVAL;
+    if ((m_f == nullptr) != (m_g == nullptr)) return FMBYM_EINVAL;
+    const Plan* pl = plan_cast(plan);
+    if (!workspace || workspace_bytes < run_full_circle_workspace(*pl, batch)) return FMBYM_EWORKSPACE;
+    rc = run_full_circle(*pl, batch, f, g, m_f, m_g, pose, peaks, (char*)workspace, (hipStream_t)stream);
+    if (rc) return rc;
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? FMBYM_OK : hip_fail(e);
+}
+
 size_t fmbym_search_state_size(fmbym_plan plan, int32_t batch) {
     if (check_call(plan, batch)) return 0;
     return keep_bytes(plan_cast(plan)->p, batch);

@@ -143,6 +143,17 @@ void launch_stage2(const Plan& pl, int batch, const float* f, const float* g, co
                    const float* mg, const float* saved, float* c_xy, char* ws, hipStream_t s,
                    const float* const* tab);
 
+// The translation soft-argmax of stage 2 (k_xy_fin) over the partials that
+// launch_stage2 left in the forward layout of ws: t' and t = R t' with the
+// cos/sin in saved[b]; writes pose[b][1..2] and the softmax statistics.
+void launch_xy_fin(const Plan& pl, int batch, char* ws, float* pose, float* saved, hipStream_t s);
+
+// Full-circle heading: the forward, stage 2 again at theta + pi, the larger
+// correlation peak kept.  One call for `batch` pairs in ws (full_circle_workspace).
+size_t full_circle_workspace(const fmbym_params& p, int batch);
+int launch_full_circle(const Plan& pl, int batch, const float* f, const float* g, const float* mf,
+                       const float* mg, float* pose, float* peaks, char* ws, hipStream_t s);
+
 // Joint comparator: K headings -pi/2 + k pi / K, stage 2 at each, hard argmax.
 size_t joint_workspace(const fmbym_params& p, int batch, int n_angles);
 int launch_joint(const Plan& pl, int batch, int n_angles, const float* f, const float* g, const float* mf,
@@ -168,6 +179,9 @@ int run_backward(const Plan& pl, int batch, const float* f, const float* g, cons
                  const float* mg, const float* pose, const float* c_theta, const float* c_xy,
                  const float* saved, const float* d_pose, float* d_f, float* d_g, float* d_mf, float* d_mg,
                  char* ws, hipStream_t s, const Keep* keep_full);
+size_t run_full_circle_workspace(const Plan& pl, int batch);
+int run_full_circle(const Plan& pl, int batch, const float* f, const float* g, const float* mf,
+                    const float* mg, float* pose, float* peaks, char* ws, hipStream_t s);
 
 // keep: null (recompute the spectra and g'), or the state of a training forward.
 int launch_backward(const Plan& pl, int batch, const float* f, const float* g, const float* mf,

@@ -841,6 +841,12 @@ void launch_stage2(const Plan& pl, int batch, const float* f, const float* g, co
     }
 }
 
+void launch_xy_fin(const Plan& pl, int batch, char* ws, float* pose, float* saved, hipStream_t s) {
+    const FwdLayout lay = fwd_layout(pl.p, batch);
+    FMBYM_LAUNCH(kKXyFin, k_xy_fin, dim3(batch), dim3(64), s, (const float4*)(ws + lay.pxy),
+                 xy_partials_per_pair(pl.p.n), pl.p.temp_xy, pl.p.delta_xy, pose, saved);
+}
+
 void launch_rotate(const Plan& pl, int B, const float* g, const float* mg, const float* saved, float* gr,
                    float* jac, int win, hipStream_t s, const float* const* tab) {
     const int N = pl.p.n;

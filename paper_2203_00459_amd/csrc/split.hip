@@ -70,6 +70,9 @@ T* at_pair(T* x, int b0, size_t per_pair) { return x ? x + (size_t)b0 * per_pair
 }  // namespace
 
 size_t run_fwd_workspace(const Plan& pl, int batch) { return both(pl, batch, fwd_ws); }
+size_t run_full_circle_workspace(const Plan& pl, int batch) {
+    return both(pl, batch, full_circle_workspace);
+}
 size_t run_bwd_workspace(const Plan& pl, int batch) { return both(pl, batch, bwd_ws); }
 
 int run_forward(const Plan& pl, int batch, const float* f, const float* g, const float* mf, const float* mg,
@@ -83,6 +86,16 @@ int run_forward(const Plan& pl, int batch, const float* f, const float* g, const
                               at_pair(mg, b0, n2), at_pair(pose, b0, 3), at_pair(c_theta, b0, pl.p.n_theta),
                               at_pair(c_xy, b0, n2), at_pair(saved, b0, FMBYM_SAVED), ws + off, st, nullptr,
                               keep_full ? &k : nullptr);
+    });
+}
+
+int run_full_circle(const Plan& pl, int batch, const float* f, const float* g, const float* mf,
+                    const float* mg, float* pose, float* peaks, char* ws, hipStream_t s) {
+    const size_t n2 = (size_t)pl.p.n * pl.p.n;
+    return run_halves(pl, batch, s, full_circle_workspace, [&](int b0, int nb, hipStream_t st, size_t off) {
+        return launch_full_circle(pl, nb, at_pair(f, b0, n2), at_pair(g, b0, n2), at_pair(mf, b0, n2),
+                                  at_pair(mg, b0, n2), at_pair(pose, b0, 3), at_pair(peaks, b0, 2), ws + off,
+                                  st);
     });
 }
 

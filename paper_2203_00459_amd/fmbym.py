@@ -47,6 +47,7 @@ EXPORTS = (
     "fmbym_adam", "fmbym_pose_loss", "fmbym_search_state_size", "fmbym_search_train",
     "fmbym_search_backward_state", "fmbym_joint_workspace_size", "fmbym_search_joint",
     "fmbym_plan_get_tuning", "fmbym_plan_set_tuning", "fmbym_autotune_workspace_size", "fmbym_autotune",
+    "fmbym_full_circle_workspace_size", "fmbym_search_full_circle",
 )
 FMBYM_LOSS_L1 = 1
 FMBYM_LOSS_L2 = 2
@@ -126,6 +127,10 @@ def lib() -> ctypes.CDLL:
         L.fmbym_joint_workspace_size.restype = SZ
         L.fmbym_search_joint.argtypes = [VP, I32, I32] + [VP] * 6 + [VP, SZ, VP]
         L.fmbym_search_joint.restype = ctypes.c_int
+        L.fmbym_full_circle_workspace_size.argtypes = [VP, I32]
+        L.fmbym_full_circle_workspace_size.restype = SZ
+        L.fmbym_search_full_circle.argtypes = [VP, I32] + [VP] * 6 + [VP, SZ, VP]
+        L.fmbym_search_full_circle.restype = ctypes.c_int
         L.fmbym_search_state_size.argtypes = [VP, I32]
         L.fmbym_search_state_size.restype = SZ
         L.fmbym_search_train.argtypes = [VP, I32] + [VP] * 8 + [VP, SZ, VP, SZ, VP]
@@ -265,6 +270,18 @@ def search_joint(plan, batch, n_angles, f, g, m_f, m_g, pose, peak, workspace, w
                                   int(workspace_bytes), stream)
     if rc:
         raise FmbymError(rc, "fmbym_search_joint")
+
+
+def full_circle_workspace_size(plan, batch) -> int:
+    return int(lib().fmbym_full_circle_workspace_size(plan, int(batch)))
+
+
+def search_full_circle(plan, batch, f, g, m_f, m_g, pose, peaks, workspace, workspace_bytes, stream) -> None:
+    """fmbym_search_full_circle with raw device addresses (ints or None)."""
+    rc = lib().fmbym_search_full_circle(plan, int(batch), f, g, m_f, m_g, pose, peaks, workspace,
+                                        int(workspace_bytes), stream)
+    if rc:
+        raise FmbymError(rc, "fmbym_search_full_circle")
 
 
 def search_state_size(plan, batch) -> int:
@@ -431,6 +448,22 @@ class Search:
         search_joint(self.plan, B, n_angles, _ptr(f, (B, n, n), "f"), _ptr(g, (B, n, n), "g"),
                      _ptr(m_f, (B, n, n), "m_f"), _ptr(m_g, (B, n, n), "m_g"), _ptr(out["pose"]),
                      _ptr(out["peak"]), self._jws.data_ptr(), need, _stream())
+        return out
+
+    def full_circle(self, f, g, m_f=None, m_g=None) -> dict:
+        """Heading over the whole circle: pose [B, 3] and peaks [B, 2] (max c_xy at
+        theta and at theta + pi)."""
+        B, n = f.shape[0], self.n
+        dev = f.device
+        need = full_circle_workspace_size(self.plan, B)
+        if need == 0:
+            raise FmbymError(FMBYM_EINVAL, "fmbym_full_circle_workspace_size")
+        if self._jws is None or self._jws.numel() < need or self._jws.device != dev:
+            self._jws = torch.empty(need, dtype=torch.uint8, device=dev)
+        out = dict(pose=torch.empty(B, 3, device=dev), peaks=torch.empty(B, 2, device=dev))
+        search_full_circle(self.plan, B, _ptr(f, (B, n, n), "f"), _ptr(g, (B, n, n), "g"),
+                           _ptr(m_f, (B, n, n), "m_f"), _ptr(m_g, (B, n, n), "m_g"), _ptr(out["pose"]),
+                           _ptr(out["peaks"]), self._jws.data_ptr(), need, _stream())
         return out
 
     def _forward_keep(self, f, g, m_f, m_g) -> dict:

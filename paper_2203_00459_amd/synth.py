@@ -205,9 +205,15 @@ def make_pair(spec: SceneSpec, workload_id: int, split: str, index: int,
     return scans[0], scans[1], np.array([th, tt[0], tt[1]], dtype=np.float64)
 
 
-def make_batch(name: str, batch: int, split: str = "test", start: int = 0):
-    """Stack ``batch`` pairs of workload ``name``: f, g float32 [B, n, n]; pose float64 [B, 3]."""
+def make_batch(name: str, batch: int, split: str = "test", start: int = 0,
+               theta_max_deg: float | None = None):
+    """Stack ``batch`` pairs of workload ``name``: f, g float32 [B, n, n]; pose float64 [B, 3].
+
+    ``theta_max_deg`` widens the heading prior (180: headings over the whole
+    circle, the metric-localisation case); the seeds are those of ``name``."""
     spec = WORKLOADS[name]
+    if theta_max_deg is not None:
+        spec = dataclasses.replace(spec, theta_max_deg=float(theta_max_deg))
     wid = sorted(WORKLOADS).index(name) + 1
     fs, gs, ps = [], [], []
     for i in range(batch):

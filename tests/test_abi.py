@@ -79,6 +79,8 @@ def test_calls_without_a_plan_are_rejected():
     assert L.fmbym_autotune_workspace_size(None, 1, 1) == 0
     assert L.fmbym_autotune(None, 1, 1, None, 0, None, ctypes.byref(t), None) == fmbym.FMBYM_EINVAL
     assert L.fmbym_search_joint(None, 1, 64, *([None] * 6), None, 0, None) == fmbym.FMBYM_EINVAL
+    assert L.fmbym_full_circle_workspace_size(None, 1) == 0
+    assert L.fmbym_search_full_circle(None, 1, *([None] * 6), None, 0, None) == fmbym.FMBYM_EINVAL
     assert L.fmbym_search_train(None, 1, *([None] * 8), None, 0, None, 0, None) == fmbym.FMBYM_EINVAL
     assert L.fmbym_search_backward_state(None, 1, *([None] * 8), None, 0, *([None] * 5), None, 0,
                                          None) == fmbym.FMBYM_EINVAL
