@@ -134,6 +134,8 @@ def main() -> int:
         return ragged_bench(args)
     if args.workload in workloads.TRAIN:
         return train_bench(args)
+    if args.workload in workloads.DRIVE:
+        return drive_bench(args)
     return search_bench(args)
 
 
@@ -251,6 +253,75 @@ def train_bench(args) -> int:
                                "kind": "oracle",
                                "sample": "1 pair: FP64 oracle mask network + masked search + L2 loss, autograd"}
     print(json.dumps(res), flush=True)
+    return 0
+
+
+def drive_bench(args) -> int:
+    """One step = the forward search over every consecutive pair of a drive in
+    one launch (f = scans[:-1], g = scans[1:], overlapping views of one array);
+    the poses are chained into a trajectory and scored over 100 ... 800 m
+    segments against the drive's true poses."""
+    import numpy as np
+    import torch
+
+    from paper_2203_00459_amd import fmbym, odometry, synth, workloads
+
+    cfg = workloads.DRIVE[args.workload]
+    kw = workloads.search_kwargs(cfg["search"])
+    scans_np, gt, _ = synth.make_drive(cfg["drive"], split="bench")
+    dev = torch.device("cuda:0")
+    S = torch.from_numpy(scans_np).to(dev)
+    P = len(scans_np) - 1
+    n, nt = kw["n"], kw["n_theta"]
+    s = fmbym.Search(max_batch=P, **kw)
+    tuning, _ = fmbym.plan_autotune(s.plan, P, False, dev)
+    f, g = S[:-1], S[1:]
+    for _ in range(args.warmup):
+        out = s.forward(f, g, surfaces=False)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.steps):
+        out = s.forward(f, g, surfaces=False)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    rel = out["pose"].double().cpu().numpy()
+    drift = odometry.segment_errors(gt, odometry.chain(rel))
+    pass_bytes = 92 * n * n * P
+    res = {
+        "metric": f"scan-pairs/sec, {n}^2 radar odometry (forward search over a drive's consecutive pairs), 1 GPU",
+        "value": P / (ms * 1e-3),
+        "unit": "pairs/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "frames": len(scans_np), "pairs": P, "n": n, "n_theta": nt,
+                   "pass": "fwd", "launch": "all pairs in one call"},
+        "roofline_path": {"bound": "hbm", "bytes_per_step": pass_bytes,
+                          "achieved": pass_bytes / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": pass_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "drift": {"t_pct": drift["t_pct"], "r_deg_per_km": drift["r_deg_per_km"],
+                  "segments": drift["segments"],
+                  "per_length_m": {str(k): {"t_pct": v[0], "r_deg_per_km": v[1], "segments": v[2]}
+                                   for k, v in drift["per_length"].items()},
+                  "drive_m": float(np.hypot(*np.diff(gt[:, :2], axis=0).T).sum())},
+        "tuning": tuning,
+    }
+    if not args.no_cpu_baseline:
+        from oracle import fmbym_oracle as O
+        p = O.Params(**kw)
+        t0 = time.perf_counter()
+        done = 0
+        while done < P and (done < 2 or time.perf_counter() - t0 < 10.0):
+            O.search(scans_np[done], scans_np[done + 1], p)
+            done += 1
+        dt = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": done / dt, "unit": "pairs/s", "cores": torch.get_num_threads(),
+                               "kind": "oracle",
+                               "sample": f"the drive's first {done} pairs (about 10 s), FP64 oracle forward"}
+    print(json.dumps(res), flush=True)
+    s.close()
     return 0
 
 

@@ -239,3 +239,91 @@ def ragged_mix(n_pairs: int, mix, seed: int = 0) -> list[str]:
     names = [name for (name, _), c in zip(mix, counts) for _ in range(c)]
     rng = np.random.Generator(np.random.PCG64(seed))
     return [names[i] for i in rng.permutation(n_pairs)]
+
+
+# ------------------------------------------------------------------ drives
+
+@dataclasses.dataclass(frozen=True)
+class DriveSpec:
+    """A drive through a static world with one scan per frame: consecutive scans
+    are the pairs of radar odometry (Section IV: scans at 4 Hz, poses chained
+    into a trajectory and scored over segments, Table III(b))."""
+
+    scene: str                          # WORKLOADS key: scan size, resolution, scene density
+    frames: int
+    step_m: tuple = (2.0, 3.0)          # distance driven per frame (about 10 m/s at 4 Hz)
+    yaw_step_deg: float = 4.0           # bound of the per-frame heading change
+
+
+DRIVES = {
+    # 401 frames at 512 x 512, 0.2 m/px: about 1 km, long enough for segments of 100 ... 800 m
+    "drive512": DriveSpec(scene="batch512", frames=401),
+    # 121 frames at 256 x 256, 0.35 m/px: about 300 m
+    "drive256": DriveSpec(scene="batch256", frames=121),
+}
+
+
+def make_drive(name: str, split: str = "test", index: int = 0, scans: bool = True):
+    """Return (scans, poses, rel).
+
+    scans  float32 [K, n, n], scan k seen from the vehicle at frame k (None if
+           ``scans`` is False);
+    poses  float64 [K, 3], the vehicle pose (x, y, psi) in the world frame,
+           starting at (0, 0, 0): a point y of scan k's frame is the world
+           point R(psi) y + (x, y);
+    rel    float64 [K-1, 3], the pose (theta, t_x, t_y) of each consecutive
+           pair f = scan k, g = scan k + 1 in ``make_pair``'s convention (a
+           point at x in frame k appears at R(theta) x + t in frame k + 1):
+           theta = psi_k - psi_{k+1}, t = R(-psi_{k+1}) (p_k - p_{k+1}).
+
+    The world holds reflectors and segments at the single-pair scenes' density
+    (their count per disc of radius 0.45 n delta), drawn over the drive's
+    bounding box; every scan gets its own speckle.
+    """
+    ds = DRIVES[name]
+    spec = WORKLOADS[ds.scene]
+    rng = _rng(100 + sorted(DRIVES).index(name), split, index)
+    K = ds.frames
+    psi = np.zeros(K)
+    pos = np.zeros((K, 2))
+    rate = 0.0
+    for k in range(1, K):
+        # heading change per frame: a damped random walk, bounded
+        rate = float(np.clip(0.8 * rate + rng.normal(0.0, 1.5), -ds.yaw_step_deg, ds.yaw_step_deg))
+        psi[k] = psi[k - 1] + math.radians(rate)
+        pos[k] = pos[k - 1] + rng.uniform(*ds.step_m) * np.array([math.cos(psi[k]), math.sin(psi[k])])
+    rel = np.zeros((K - 1, 3))
+    for k in range(K - 1):
+        rel[k, 0] = psi[k] - psi[k + 1]
+        rel[k, 1:] = _rot(-psi[k + 1]) @ (pos[k] - pos[k + 1])
+    poses = np.concatenate([pos, psi[:, None]], axis=1)
+    if not scans:
+        return None, poses, rel
+    # static world over the drive's bounding box (a scan sees objects up to its
+    # half-diagonal away, plus half a segment)
+    reach = (spec.n / 2) * spec.delta * math.sqrt(2.0) + 8.0
+    lo, hi = pos.min(0) - reach, pos.max(0) + reach
+    per_area = 1.0 / (math.pi * (0.45 * spec.n * spec.delta) ** 2)
+    box = float(np.prod(hi - lo))
+    n_refl = int(rng.poisson(spec.n_reflectors * box * per_area))
+    n_seg = int(rng.poisson(spec.n_segments * box * per_area))
+    refl = lo + (hi - lo) * rng.uniform(0.0, 1.0, (n_refl, 2))
+    refl_amp = rng.uniform(0.5, 1.0, n_refl)
+    centre = lo + (hi - lo) * rng.uniform(0.0, 1.0, (n_seg, 2))
+    length = rng.uniform(2.0, 15.0, n_seg)
+    orient = rng.uniform(0, np.pi, n_seg)
+    half = 0.5 * length[:, None] * np.stack([np.cos(orient), np.sin(orient)], axis=1)
+    seg_amp = rng.uniform(0.3, 0.8, n_seg)
+    fall = _falloff(spec)
+    out = np.empty((K, spec.n, spec.n), dtype=np.float32)
+    for k in range(K):
+        near_r = np.linalg.norm(refl - pos[k], axis=1) <= reach
+        near_s = np.linalg.norm(centre - pos[k], axis=1) <= reach
+        world = _World(refl[near_r], refl_amp[near_r], (centre - half)[near_s], (centre + half)[near_s],
+                       seg_amp[near_s])
+        rot = _rot(-psi[k])            # world -> frame k: y = R(-psi) (x - p)
+        img = _render(spec, world, rot, -rot @ pos[k])
+        img *= fall
+        img += rng.rayleigh(spec.speckle_sigma, img.shape)
+        out[k] = img.astype(np.float32)
+    return out, poses, rel

@@ -39,6 +39,14 @@ TRAIN = {
 }
 
 
+# Radar odometry: the forward search over every consecutive pair of a drive
+# (synth.DRIVES), all pairs in one launch, chained and scored over segments.
+DRIVE = {
+    # 401 frames at 512 x 512 (about 1 km): 400 pairs with batch512's parameters
+    "drive512": dict(drive="drive512", search="batch512"),
+}
+
+
 def search_kwargs(name: str) -> dict:
     """Keyword arguments shared by the library's Search and the oracle's Params."""
     d = dict(SEARCH[name])
