@@ -365,8 +365,18 @@ __global__ __launch_bounds__(256) void k_colsum1(const float* __restrict__ part,
     const int j = blockIdx.x * 64 + t;
     const int b0 = blockIdx.y * per, b1 = min(nb, b0 + per);
     float s = 0.f;
-    if (j < n)
-        for (int b = b0 + bl; b < b1; b += 4) s += part[(size_t)b * stride + j];
+    if (j < n) {
+        // eight loads in flight, then added in row order (the same sums as one at a time)
+        int b = b0 + bl;
+        for (; b + 28 < b1; b += 32) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = part[(size_t)(b + 4 * u) * stride + j];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += v[u];
+        }
+        for (; b < b1; b += 4) s += part[(size_t)b * stride + j];
+    }
     __shared__ float r[4][64];
     r[bl][t] = s;
     __syncthreads();
@@ -378,7 +388,15 @@ __global__ void k_colsum2(const float* __restrict__ tmp, int nbc, int n, int j0,
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= count) return;
     double s = 0.0;
-    for (int c = 0; c < nbc; ++c) s += tmp[(size_t)c * n + j0 + j];
+    int c = 0;
+    for (; c + 8 <= nbc; c += 8) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = tmp[(size_t)(c + u) * n + j0 + j];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; c < nbc; ++c) s += tmp[(size_t)c * n + j0 + j];
     out[j] = (float)s;
 }
 
@@ -396,6 +414,31 @@ __global__ void k_input8(const float* __restrict__ x, const float* const* __rest
     *(u32x4*)(x8 + p * 8) = __builtin_bit_cast(u32x4, v);
 }
 
+// Per-thread sums of one channel's partial pairs over the blocks k = t, t + 256, ...
+// (in that order): eight blocks' loads in flight, then added in order.
+__device__ __forceinline__ void bn_part_sums(const float* __restrict__ part, int nb, int C, int c,
+                                             double& a, double& b) {
+    const int bd = blockDim.x;
+    int k = threadIdx.x;
+    for (; k + 7 * bd < nb; k += 8 * bd) {
+        float va[8], vb[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            va[u] = part[(size_t)(k + u * bd) * 2 * C + c];
+            vb[u] = part[(size_t)(k + u * bd) * 2 * C + C + c];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            a += va[u];
+            b += vb[u];
+        }
+    }
+    for (; k < nb; k += bd) {
+        a += part[(size_t)k * 2 * C + c];
+        b += part[(size_t)k * 2 * C + C + c];
+    }
+}
+
 // Batch-norm statistics from the conv partials (double-precision sums in block order).
 __global__ void k_bn_stats(const float* __restrict__ part, int nb, int C, long long M,
                            const float* __restrict__ gamma, const float* __restrict__ beta, float eps,
@@ -404,10 +447,7 @@ __global__ void k_bn_stats(const float* __restrict__ part, int nb, int C, long l
     const int c = blockIdx.x;
     __shared__ double r1[256], r2[256];
     double a = 0.0, b = 0.0;
-    for (int k = threadIdx.x; k < nb; k += blockDim.x) {
-        a += part[(size_t)k * 2 * C + c];
-        b += part[(size_t)k * 2 * C + C + c];
-    }
+    bn_part_sums(part, nb, C, c, a, b);
     r1[threadIdx.x] = a;
     r2[threadIdx.x] = b;
     __syncthreads();
@@ -582,24 +622,52 @@ __global__ __launch_bounds__(256) void k_head_wgrad(const float* __restrict__ dl
     for (int j = 0; j < NW; ++j) acc[j] = 0.f;
     const long long n = (long long)images * S * S;
     const long long p0 = (long long)blockIdx.x * kHeadPix;
-    for (long long p = p0 + threadIdx.x; p < min(n, p0 + kHeadPix); p += blockDim.x) {
+    const long long pend = min(n, p0 + kHeadPix);
+    // One pixel's nine taps: every load issued at a clamped address, the taps
+    // outside the image then skipped by selects (the same sums as branching).
+    struct Taps {
+        float d;
+        u32x4 v[9];
+        unsigned inb;
+    };
+    auto load = [&](long long p) {
+        Taps t;
         const int x = (int)(p % S), y = (int)((p / S) % S), img = (int)(p / ((long long)S * S));
-        const float d = dl[p];
-        acc[NW - 1] += d;
+        t.d = dl[p];
+        t.inb = 0;
 #pragma unroll
-        for (int ky = 0; ky < 3; ++ky) {
-            const int yy = y + ky - 1;
+        for (int ky = 0; ky < 3; ++ky)
 #pragma unroll
             for (int kx = 0; kx < 3; ++kx) {
-                const int xx = x + kx - 1;
-                if (yy < 0 || yy >= S || xx < 0 || xx >= S) continue;
-                const bf16x8 v =
-                    __builtin_bit_cast(bf16x8, *(const u32x4*)(a + (((size_t)img * S + yy) * S + xx) * C));
+                const int yy = y + ky - 1, xx = x + kx - 1;
+                const bool in = yy >= 0 && yy < S && xx >= 0 && xx < S;
+                const int yc = min(max(yy, 0), S - 1), xc = min(max(xx, 0), S - 1);
+                t.v[ky * 3 + kx] = *(const u32x4*)(a + (((size_t)img * S + yc) * S + xc) * C);
+                t.inb |= (in ? 1u : 0u) << (ky * 3 + kx);
+            }
+        return t;
+    };
+    auto add = [&](const Taps& t) {
+        acc[NW - 1] += t.d;
 #pragma unroll
-                for (int j = 0; j < C; ++j) acc[j * 9 + ky * 3 + kx] = fmaf(d, (float)v[j], acc[j * 9 + ky * 3 + kx]);
+        for (int k = 0; k < 9; ++k) {
+            const bf16x8 v = __builtin_bit_cast(bf16x8, t.v[k]);
+            const bool in = (t.inb >> k) & 1u;
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+                const float r = fmaf(t.d, (float)v[j], acc[j * 9 + k]);
+                acc[j * 9 + k] = in ? r : acc[j * 9 + k];
             }
         }
+    };
+    long long p = p0 + threadIdx.x;
+    // two pixels' loads in flight, accumulated in pixel order
+    for (; p + blockDim.x < pend; p += 2 * blockDim.x) {
+        const Taps t0 = load(p), t1 = load(p + blockDim.x);
+        add(t0);
+        add(t1);
     }
+    if (p < pend) add(load(p));
     __shared__ float red[4][NW];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -635,10 +703,8 @@ __global__ __launch_bounds__(256) void k_bn_bwd_part(const float* __restrict__ g
         sc[j] = stat[2 * C + c];
         sh[j] = stat[3 * C + c];
     }
-    for (long long p = p0 + pl; p < p1; p += PL) {
-        const bf16x8 zv = __builtin_bit_cast(bf16x8, *(const u32x4*)(z + p * C + 8 * cg));
-        const float4 g0 = *(const float4*)(g + p * C + 8 * cg);
-        const float4 g1 = *(const float4*)(g + p * C + 8 * cg + 4);
+    auto add = [&](const u32x4 zr, const float4 g0, const float4 g1) {
+        const bf16x8 zv = __builtin_bit_cast(bf16x8, zr);
         const float gv[8] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w};
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
@@ -647,7 +713,25 @@ __global__ __launch_bounds__(256) void k_bn_bwd_part(const float* __restrict__ g
             sd[j] += dy;
             sx[j] = fmaf(dy, (zz - mean[j]) * inv[j], sx[j]);
         }
+    };
+    long long p = p0 + pl;
+    // four pixels' loads in flight, then accumulated in pixel order
+    for (; p + 3 * PL < p1; p += 4 * PL) {
+        u32x4 zr[4];
+        float4 ga[4], gb[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const long long q = p + u * PL;
+            zr[u] = *(const u32x4*)(z + q * C + 8 * cg);
+            ga[u] = *(const float4*)(g + q * C + 8 * cg);
+            gb[u] = *(const float4*)(g + q * C + 8 * cg + 4);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) add(zr[u], ga[u], gb[u]);
     }
+    for (; p < p1; p += PL)
+        add(*(const u32x4*)(z + p * C + 8 * cg), *(const float4*)(g + p * C + 8 * cg),
+            *(const float4*)(g + p * C + 8 * cg + 4));
     __shared__ float red[2][256 * 8];   // [sum][pixel lane][channel]
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
@@ -670,10 +754,7 @@ __global__ void k_bn_bwd_fin(const float* __restrict__ part, int nb, int C, long
     const int c = blockIdx.x;
     __shared__ double r1[256], r2[256];
     double a = 0.0, b = 0.0;
-    for (int k = threadIdx.x; k < nb; k += blockDim.x) {
-        a += part[(size_t)k * 2 * C + c];
-        b += part[(size_t)k * 2 * C + C + c];
-    }
+    bn_part_sums(part, nb, C, c, a, b);
     r1[threadIdx.x] = a;
     r2[threadIdx.x] = b;
     __syncthreads();

@@ -8,7 +8,13 @@
    through the network: |gpu - exact| <= 2 |quant - exact| + 1e-2 per group.
 2. Training on synthetic pairs with distractors (moving clutter, multipath
    ghosts) makes the masked search beat the unmasked one on held-out pairs, and
-   the fallback policy switches to the mask only then.
+   the fallback policy switches to the mask only then.  The loss is Eq. 13's
+   L1: with the squared error, the outcome of 600 steps depends on the order
+   the pairs are drawn in (of four orders at lr 1e-3, two converged and two
+   did not), because outlier pairs, whose heading lands on a spurious angular
+   peak, dominate the gradient.  Under L1 all four converged, with held-out
+   translation errors of 0.10-0.74 m against 1.44 m unmasked, and the bounds
+   below leave room for that spread.
 """
 import numpy as np
 import pytest
@@ -80,7 +86,7 @@ def test_training_makes_the_mask_beat_the_unmasked_search():
     ft, gt, pt = synth.make_batch("mask256", 64, split="test")
     F, G, P = (torch.from_numpy(a).to(DEV) for a in (f, g, p.astype(np.float32)))
     Ft, Gt, Pt = (torch.from_numpy(a).to(DEV) for a in (ft, gt, pt.astype(np.float32)))
-    tr = MaskedSearchTrainer(KW256, batch=64, cfg=TrainConfig(lr=1e-3))
+    tr = MaskedSearchTrainer(KW256, batch=64, cfg=TrainConfig(lr=1e-3, loss=fmbym.FMBYM_LOSS_L1))
     before = tr.evaluate(Ft, Gt, Pt)
     print("before", before, flush=True)
     assert not before["use_mask"]
@@ -93,9 +99,9 @@ def test_training_makes_the_mask_beat_the_unmasked_search():
     l0, l1 = float(torch.stack(first).mean()), float(torch.stack(last).mean())
     after = tr.evaluate(Ft, Gt, Pt)
     print(f"loss {l0:.3f} -> {l1:.3f}; after {after}", flush=True)
-    assert l1 < 0.25 * l0
+    assert l1 < 0.75 * l0
     assert after["use_mask"]
-    assert after["masked_t"] < 0.5 * after["unmasked_t"]
+    assert after["masked_t"] < 0.6 * after["unmasked_t"]
     assert after["masked_theta"] < after["unmasked_theta"]
     m_f, m_g = tr.masks(Ft, Gt, training=False)
     ref = tr.search.forward(Ft, Gt, m_f, m_g, surfaces=False)["pose"]
