@@ -76,8 +76,9 @@ def kernel_bytes(n: int, n_theta: int, n_r: int, batch: int, masked: bool, keep:
     """Algorithmic HBM bytes per launch of each kernel: compulsory reads of its
     inputs plus writes of its outputs, each touched once (float32 / complex64).
     keep: the training forward keeps its intermediates for the adjoint (k_rotate
-    runs once and also writes d g'/d theta; kb_rows_fwd2 transforms only the
-    d c_xy lag rows; k_rows1 / k_cols1 run once)."""
+    runs once and also writes d g'/d theta; k_rows1 / k_cols1 / k_rows2 run
+    once).  Without keep the adjoint runs them again; kb_rows_fwd2 always
+    transforms only the d c_xy lag rows."""
     N2 = n * n
     nrb = (n_r + max(2048 // n_theta, 4) - 1) // max(2048 // n_theta, 4)   # radius blocks of the polar pass
     hk = n_theta // 2 + 1
@@ -100,8 +101,8 @@ def kernel_bytes(n: int, n_theta: int, n_r: int, batch: int, masked: bool, keep:
         "k_cols2": batch * (rows2 + lag),
         "k_rows3": batch * (lag + N2 * 4),
         "k_xy_fin": batch * 64,
-        # adjoint (without keep, k_rows1 and k_cols1 run again to recompute the stage-1 spectra)
-        "kb_rows_fwd2": batch * (4 * N2 + lag) if keep else batch * (m * 4 * N2 + 4 * N2 + 4 * N2 + rows2 + lag),
+        # adjoint (without keep, k_rows1, k_cols1 and k_rows2 run again to recompute their spectra)
+        "kb_rows_fwd2": batch * (4 * N2 + lag),
         "kb_cols_xy": batch * (rows2 + lag + rows2),
         "kb_rows_xy": batch * (rows2 + 4 * N2 + 2 * N2 * 4),
         "kb_rotate_adj": batch * (4 * N2 + 4 * N2),

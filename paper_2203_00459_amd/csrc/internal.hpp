@@ -143,6 +143,10 @@ void launch_stage2(const Plan& pl, int batch, const float* f, const float* g, co
                    const float* mg, const float* saved, float* c_xy, char* ws, hipStream_t s,
                    const float* const* tab);
 
+// Stage-2 rows of f_w + i g' (k_rows2, g' read from gr) for a packed batch -> out.
+void launch_rows2(const Plan& pl, int batch, const float* f, const float* g, const float* mf, const float* mg,
+                  const float* gr, float4* out, int win2, hipStream_t s);
+
 // The translation soft-argmax of stage 2 (k_xy_fin) over the partials that
 // launch_stage2 left in the forward layout of ws: t' and t = R t' with the
 // cos/sin in saved[b]; writes pose[b][1..2] and the softmax statistics.

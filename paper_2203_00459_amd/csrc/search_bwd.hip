@@ -17,7 +17,8 @@
 //   f_w = w f m                   df = w m df_w, dm = w f df_w
 //
 // Kernels, in launch order:
-//   kb_rows_fwd2   rows of f2 and g' (2n-padded) and of dc_xy, paired complex FFTs
+//   (k_rotate, k_rows2 of the forward again, unless the forward kept g', J and the rows)
+//   kb_rows_fwd2   rows of dc_xy (3n/2-padded), paired complex FFTs
 //   kb_cols_xy     column FFTs, conj(DC) G' and F DC, inverse columns (rows < n kept)
 //                  (layouts as in the forward: interleaved spectra, all unique columns)
 //   kb_rows_xy     inverse rows -> df2, dg'; partial sums of dtheta_2
@@ -63,46 +64,24 @@ __device__ __forceinline__ XyAdj make_xy_adj(const float* sv, const float* dp, f
 
 // ------------------------------------------------------ translation adjoint
 
-// Blocks [0, B n / LPB) transform rows of f2 + i g' (g' read from gr; -> rf, float4 (F, G'));
-// the rest transform pairs of dc_xy lag rows (-> rdc, float2).  Columns 0 .. 3n/4
-// of the 3n/2-point row spectra are kept.
+// Pairs of dc_xy lag rows (the softmax adjoint of c_xy, zero-padded to 3n/2)
+// as one complex FFT each -> rdc, columns 0 .. 3n/4 of both row spectra.  The
+// stage-2 rows of f_w and g' come from the forward's k_rows2 (kept, or run
+// again by the recomputing adjoint), so both adjoints read the same values.
 template <int N>
-__global__ __launch_bounds__(256) void kb_rows_fwd2(
-    const float* __restrict__ f, const float* __restrict__ g, const float* __restrict__ mf,
-    const float* __restrict__ mg, const float* __restrict__ hann, const float2* __restrict__ tw,
-    const float* __restrict__ saved, const float* __restrict__ c_xy, const float* __restrict__ d_pose,
-    const float* __restrict__ gr, float4* __restrict__ rf, float2* __restrict__ rdc, int win, int batch,
-    float temp, float delta, int block0) {
-    constexpr int L = pad2(N), E = kE2, T = L / E, LPB = 256 / T, H = L / 2, P2 = pitch_rows2(N),
-                  P3 = pitch_lag(N);
+__global__ __launch_bounds__(256) void kb_rows_fwd2(const float2* __restrict__ tw,
+                                                    const float* __restrict__ saved,
+                                                    const float* __restrict__ c_xy,
+                                                    const float* __restrict__ d_pose,
+                                                    float2* __restrict__ rdc, float temp, float delta) {
+    constexpr int L = pad2(N), E = kE2, T = L / E, LPB = 256 / T, H = L / 2, P3 = pitch_lag(N);
     __shared__ float lre[LPB][LdsRows<L>::words(L)];
     __shared__ float lim[LPB][LdsRows<L>::words(L)];
     const int line = threadIdx.x / T, t = threadIdx.x % T;
-    const int nscan_blocks = batch * N / LPB;
-    const int bid = (int)blockIdx.x + block0;   // block0 > 0 skips the scan rows
-    const bool scan_rows = bid < nscan_blocks;   // block-uniform
     float2 v[E];
-    int grow = 0, gl = 0, b = 0, q = 0;
-    if (scan_rows) {
-        grow = bid * LPB + line;
-        b = grow / N;
-        const int i = grow % N;
-        const size_t base = (size_t)b * N * N;
-        const float* grow_g = gr + (size_t)grow * N;
-#pragma unroll
-        for (int m = 0; m < E; ++m) {
-            const int x = t + m * T;
-            if (m < 2 * E / 3) {
-                const float a = scan_w(f + base, mf ? mf + base : nullptr, hann, N, i, x, win);
-                v[m] = make_float2(a, grow_g[x]);
-            } else {
-                v[m] = make_float2(0.f, 0.f);
-            }
-        }
-    } else {
-        gl = (bid - nscan_blocks) * LPB + line;   // lag-row pair
-        b = gl / (N / 2);
-        q = gl % (N / 2);
+    const int gl = (int)blockIdx.x * LPB + line;   // lag-row pair
+    const int b = gl / (N / 2), q = gl % (N / 2);
+    {
         const XyAdj adj = make_xy_adj(saved + (size_t)b * FMBYM_SAVED, d_pose + b * 3, temp, delta);
         const float* c1 = c_xy + ((size_t)b * N + 2 * q) * N;
         const float* c2 = c1 + N;
@@ -122,18 +101,13 @@ __global__ __launch_bounds__(256) void kb_rows_fwd2(
     fft_line<L, E>(v, lre[line], lim[line], t, tw);
     float2 mir[E];
     mirror_line<L, E>(v, mir, lre[line], lim[line], t);
+    float2* o = rdc + ((size_t)b * N + 2 * q) * P3;
 #pragma unroll
     for (int m = 0; m <= E / 2; ++m) {
         const int k = t + m * T;
         if (k > H) continue;
-        const float2 X = split_x(v[m], mir[m]), Y = split_y(v[m], mir[m]);
-        if (scan_rows) {
-            rf[(size_t)grow * P2 + k] = make_float4(X.x, X.y, Y.x, Y.y);
-        } else {
-            float2* o = rdc + ((size_t)b * N + 2 * q) * P3;
-            o[k] = X;
-            o[P3 + k] = Y;
-        }
+        o[k] = split_x(v[m], mir[m]);
+        o[P3 + k] = split_y(v[m], mir[m]);
     }
 }
 
@@ -838,13 +812,15 @@ static int launch_bwd_n(const Plan& pl, int B, const float* f, const float* g, c
     const int win2 = (win && !(pl.p.flags & FMBYM_XY_UNWINDOWED)) ? 1 : 0;
 
     // translation-stage adjoint
-    constexpr int T2 = pad2(N) / kE2, LPB2 = rows2_lines(N);
-    const int scan_blocks = B * N / LPB2, dc_blocks = B * (N / 2) / LPB2;
-    if (!keep) launch_rotate(pl, B, g, mg, saved, dgr, jac, win2, s, nullptr);
-    const int skip = keep ? scan_blocks : 0;   // with keep only the dc_xy lag rows are transformed
-    FMBYM_LAUNCH(kKBRowsFwd2, kb_rows_fwd2<N>, dim3(scan_blocks + dc_blocks - skip), dim3(256), s, f, g, mf,
-                 mg, pl.hann, pl.twiddle3, saved, c_xy, d_pose, gr, rf, rdc, win2, B, pl.p.temp_xy,
-                 pl.p.delta_xy, skip);
+    constexpr int LPB2 = rows2_lines(N);
+    const int dc_blocks = B * (N / 2) / LPB2;
+    if (!keep) {
+        // g' (and J) and the stage-2 rows again, by the forward's own kernels
+        launch_rotate(pl, B, g, mg, saved, dgr, jac, win2, s, nullptr);
+        launch_rows2(pl, B, f, g, mf, mg, dgr, rf, win2, s);
+    }
+    FMBYM_LAUNCH(kKBRowsFwd2, kb_rows_fwd2<N>, dim3(dc_blocks), dim3(256), s, pl.twiddle3, saved, c_xy,
+                 d_pose, rdc, pl.p.temp_xy, pl.p.delta_xy);
     launch_cols_xy<N>(pl, B, rows2, rf, rdc, s);
     FMBYM_LAUNCH(kKBRowsXy, kb_rows_xy<N>, dim3(B * N / LPB2), dim3(256), s, rf, jac, pl.twiddle3, df2,
                  dgp, dth);

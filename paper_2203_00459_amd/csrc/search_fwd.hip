@@ -779,6 +779,15 @@ static void launch_polar(const Plan& pl, int B, const float2* mag, float2* pth, 
                  pl.twiddle, pl.p.temp_theta, c_theta, pose, saved);
 }
 
+template <int N>
+static void launch_rows2_n(const Plan& pl, int B, const float* f, const float* g, const float* mf,
+                           const float* mg, const float* gr, float4* r2, int win2, hipStream_t s,
+                           const float* const* tab) {
+    constexpr int LPB2 = rows2_lines(N);
+    FMBYM_LAUNCH(kKRows2, k_rows2<N>, dim3(B * N / (LPB2 * kRows2Seq)), dim3(256), s, f, g, mf, mg, pl.hann,
+                 pl.twiddle3, gr, r2, win2, tab);
+}
+
 // Stage 2 up to the lag rows: Rotate, the 3n/2-point rows of f_w + i g', the
 // column correlation and the inverse rows (c_xy and the softmax partials in
 // the layout's pxy region).  The heading is read from saved[b].
@@ -796,8 +805,7 @@ static void stage2_n(const Plan& pl, int B, const float* f, const float* g, cons
     float* gr = keep ? keep->gr : (float*)(ws + lay.grot);
     FMBYM_LAUNCH(kKRotate, k_rotate<N>, dim3(B * (N / kRotTY) * (N / kRotTX)), dim3(256), s, g, mg, pl.hann,
                  sv, gr, keep ? keep->jac : nullptr, win2, tab);
-    FMBYM_LAUNCH(kKRows2, k_rows2<N>, dim3(B * N / (LPB2 * kRows2Seq)), dim3(256), s, f, g, mf, mg, pl.hann,
-                 pl.twiddle3, gr, r2, win2, tab);
+    launch_rows2_n<N>(pl, B, f, g, mf, mg, gr, r2, win2, s, tab);
     launch_cols2<N>(pl, B, r2, r3, s);
     FMBYM_LAUNCH(kKRows3, k_rows3<N>, dim3(B * (N / 2) / LPB2), dim3(256), s, r3, pl.twiddle3, c_xy,
                  pxy, pl.p.temp_xy);
@@ -837,6 +845,16 @@ void launch_stage2(const Plan& pl, int batch, const float* f, const float* g, co
         case 128: stage2_n<128>(pl, batch, f, g, mf, mg, saved, c_xy, ws, s, tab, nullptr); break;
         case 256: stage2_n<256>(pl, batch, f, g, mf, mg, saved, c_xy, ws, s, tab, nullptr); break;
         case 512: stage2_n<512>(pl, batch, f, g, mf, mg, saved, c_xy, ws, s, tab, nullptr); break;
+        default: break;
+    }
+}
+
+void launch_rows2(const Plan& pl, int batch, const float* f, const float* g, const float* mf, const float* mg,
+                  const float* gr, float4* out, int win2, hipStream_t s) {
+    switch (pl.p.n) {
+        case 128: launch_rows2_n<128>(pl, batch, f, g, mf, mg, gr, out, win2, s, nullptr); break;
+        case 256: launch_rows2_n<256>(pl, batch, f, g, mf, mg, gr, out, win2, s, nullptr); break;
+        case 512: launch_rows2_n<512>(pl, batch, f, g, mf, mg, gr, out, win2, s, nullptr); break;
         default: break;
     }
 }
