@@ -61,15 +61,21 @@ def measured_traffic(kernel: str):
             meta["fw"] = float(ln.split()[2])
     if meta.get("digest") != source_digest() or "ff" not in meta or "fw" not in meta:
         return None
+    # rows: kernel, dispatches, fetch KiB, write KiB, MB; of a kernel's template
+    # variants, the one with the most dispatches is the one the tuned plan ran
+    best = None
     for ln in lines:
         if ln.startswith("#") or not ln.strip():
             continue
         parts = ln.split()
         name = ln[:34].strip().split("<")[0]
-        if name == kernel and len(parts) >= 4:
-            fetch, write = float(parts[-4]), float(parts[-3])
-            return (fetch * meta["ff"] + write * meta["fw"]) * 1024.0
-    return None
+        if name == kernel and len(parts) >= 5:
+            count, fetch, write = int(parts[-4]), float(parts[-3]), float(parts[-2])
+            if best is None or count > best[0]:
+                best = (count, fetch, write)
+    if best is None:
+        return None
+    return (best[1] * meta["ff"] + best[2] * meta["fw"]) * 1024.0
 
 
 def kernel_bytes(n: int, n_theta: int, n_r: int, batch: int, masked: bool, keep: bool = False) -> dict:

@@ -1,0 +1,29 @@
+"""Host-side helpers of bench.py: the HBM-traffic lookup in the committed
+counter summary (CPU only)."""
+import bench
+
+
+def test_traffic_lookup_scales_the_counted_kib_of_the_most_run_variant(tmp_path, monkeypatch):
+    f = tmp_path / "traffic.txt"
+    f.write_text(
+        "# header\n"
+        f"# source-digest {bench.source_digest()}  (sha256)\n"
+        "# calibration-fetch 2.0\n"
+        "# calibration-write 1.0\n"
+        "\n"
+        f"{'kernel':<34} {'dispatches':>10} {'fetch_KiB':>12} {'write_KiB':>12} {'hbm_MB':>10}\n"
+        f"{'kb_cols_xy<512, 16>':<34} {26:>10d} {100.0:>12.1f} {50.0:>12.1f} {0.26:>10.2f}\n"
+        f"{'kb_cols_xy<512, 4>':<34} {192:>10d} {10.0:>12.1f} {5.0:>12.1f} {0.03:>10.2f}\n"
+        f"{'kb_dmag':<34} {244:>10d} {7.0:>12.1f} {3.0:>12.1f} {0.02:>10.2f}\n")
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    assert bench.measured_traffic("kb_cols_xy") == (10.0 * 2.0 + 5.0) * 1024.0
+    assert bench.measured_traffic("kb_dmag") == (7.0 * 2.0 + 3.0) * 1024.0
+    assert bench.measured_traffic("k_rows1") is None
+
+
+def test_traffic_lookup_refuses_a_summary_of_other_sources(tmp_path, monkeypatch):
+    f = tmp_path / "traffic.txt"
+    f.write_text("# source-digest 0000000000000000\n# calibration-fetch 2.0\n# calibration-write 1.0\n"
+                 f"{'kb_dmag':<34} {244:>10d} {7.0:>12.1f} {3.0:>12.1f} {0.02:>10.2f}\n")
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    assert bench.measured_traffic("kb_dmag") is None
