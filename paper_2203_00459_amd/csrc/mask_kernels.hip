@@ -23,10 +23,14 @@ namespace {
 // Input channels staged per pass: all of them up to 32, else 32 or 24 at a time.
 __host__ __device__ constexpr int chunk_ch(int cin) { return cin <= 32 ? cin : (cin % 32 == 0 ? 32 : 24); }
 
-// Pixels of a conv tile's input patch, (rows + 2) x (cols + 2), at side S.
-__host__ __device__ constexpr int patch_pixels(int S) {
-    return S >= kConvTile ? 3 * (kConvTile + 2) : (kConvTile / S + 2) * (S + 2);
-}
+// Convolution tiles are 16 x 16 pixels (sides S >= 16): the input patch with
+// its one-pixel halo is 18 x 18, 1.27 reads per output pixel where a
+// 256-pixel row strip reads 3.
+constexpr int kConvSide = 16;
+static_assert(kConvSide * kConvSide == kConvTile, "one conv tile per block");
+
+// Pixels of a conv tile's input patch, (rows + 2) x (cols + 2).
+__host__ __device__ constexpr int patch_pixels(int /*S*/) { return (kConvSide + 2) * (kConvSide + 2); }
 
 // Dynamic LDS bytes of the staged patch (G + 1 groups of 16 bytes per pixel).
 constexpr size_t patch_bytes(int cin, int S) { return (size_t)patch_pixels(S) * (chunk_ch(cin) / 8 + 1) * 16; }
@@ -43,6 +47,18 @@ __device__ __forceinline__ f32x4 mfma(u32x4 a, u32x4 b, f32x4 c) {
 struct TileGeo {
     int img, y0, x0, pr, pc;
 };
+
+// The convolution's tile: 16 x 16 pixels, tiles row-major within the image.
+__device__ __forceinline__ TileGeo conv_tile_geo(int blk, int S) {
+    TileGeo t;
+    const int per_row = S / kConvSide, per_img = per_row * per_row;
+    t.img = blk / per_img;
+    const int k = blk % per_img;
+    t.pr = t.pc = kConvSide;
+    t.y0 = (k / per_row) * kConvSide;
+    t.x0 = (k % per_row) * kConvSide;
+    return t;
+}
 
 __device__ __forceinline__ TileGeo tile_geo(int blk, int S) {
     TileGeo t;
@@ -84,7 +100,7 @@ __device__ __forceinline__ void stage_patch(const bf16* __restrict__ in, u32x4* 
 
 // ------------------------------------------------------------ convolution
 
-// out = conv3x3(in, w) over one 256-pixel tile per block, all output channels.
+// out = conv3x3(in, w) over one 16 x 16-pixel tile per block, all output channels.
 // K runs over (tap, input channel) in groups of 8; every 32-wide K step is one
 // matrix-core instruction per (16-pixel M-tile, 16-channel N-tile).  Each wave
 // owns 4 M-tiles; A comes from the LDS patch, B from the packed weights.
@@ -96,7 +112,7 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16* __restrict__ in, co
     constexpr int NT = pad16(COUT) / 16, K = 9 * CIN;
     static_assert(CIN % 8 == 0 && CIN % CC == 0, "input channels in groups of 8");
     extern __shared__ u32x4 patch[];   // patch_bytes(CIN, S)
-    const TileGeo t = tile_geo(blockIdx.x, S);
+    const TileGeo t = conv_tile_geo(blockIdx.x, S);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, r16 = lane & 15;
     const int W = t.pc + 2;
