@@ -60,26 +60,6 @@ __device__ __forceinline__ TileGeo conv_tile_geo(int blk, int S) {
     return t;
 }
 
-__device__ __forceinline__ TileGeo tile_geo(int blk, int S) {
-    TileGeo t;
-    const int per_img = S * S / kConvTile;
-    t.img = blk / per_img;
-    const int k = blk % per_img;
-    if (S >= kConvTile) {
-        const int per_row = S / kConvTile;
-        t.pr = 1;
-        t.pc = kConvTile;
-        t.y0 = k / per_row;
-        t.x0 = (k % per_row) * kConvTile;
-    } else {
-        t.pc = S;
-        t.pr = kConvTile / S;
-        t.y0 = k * t.pr;
-        t.x0 = 0;
-    }
-    return t;
-}
-
 // Stage channels [c0, c0 + 8G) of the tile's input patch (one pixel of halo on
 // every side, zeros outside the image) as G groups of 8 channels per pixel at a
 // pitch of G + 1 groups.
@@ -225,8 +205,10 @@ struct WgradGeo {
     static constexpr size_t red_bytes = WG == 1 ? (size_t)MT * GPW * 3 * 64 * 16 : 0;
 };
 
-__host__ __device__ constexpr int wg_pitch(int S) { return (S >= kConvTile ? kConvTile : S) + 8; }
-__host__ __device__ constexpr int wg_rows(int S) { return (S >= kConvTile ? 1 : kConvTile / S) + 2; }
+// The input patch of a 16 x 16 tile, transposed: 18 rows at a pitch of 24
+// (a B fragment reads 10 pixels from an 8-pixel-aligned column, 16-byte aligned).
+__host__ __device__ constexpr int wg_pitch(int /*S*/) { return kConvSide + 8; }
+__host__ __device__ constexpr int wg_rows(int /*S*/) { return kConvSide + 2; }
 
 // Weight gradient over `tpb` consecutive tiles per block:
 // part[block][co][tap CIN + ci] = sum over the tiles' pixels of dz[p][co] in[p + tap][ci].
@@ -260,7 +242,7 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16* __restrict__ dz, cons
         for (int k = 0; k < tpb; ++k) {
             const int tile = blockIdx.x * tpb + k;
             if (tile >= tiles) break;
-            const TileGeo t = tile_geo(tile, S);
+            const TileGeo t = conv_tile_geo(tile, S);
             const size_t img_base = (size_t)t.img * S * S;
             __syncthreads();
             // dz tile, transposed
