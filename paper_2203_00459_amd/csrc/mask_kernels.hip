@@ -807,7 +807,14 @@ __global__ void k_pool_bwd(const float* __restrict__ d_pool, const bf16* __restr
     const bf16x8 w2 = __builtin_bit_cast(bf16x8, *(const u32x4*)(b + (size_t)S * C));
     const bf16x8 w3 = __builtin_bit_cast(bf16x8, *(const u32x4*)(b + (size_t)S * C + C));
     const int mine = (y - 2 * Y) * 2 + (x - 2 * X);
-    const float* dp = d_pool + (((size_t)img * H + Y) * H + X) * C + 8 * cg;
+    // the pooled gradient and the skip gradient as vector loads, always issued
+    // (skip offsets and strides are multiples of 8 channels), then selects
+    const float4* dp = reinterpret_cast<const float4*>(d_pool + (((size_t)img * H + Y) * H + X) * C + 8 * cg);
+    const float4 d0 = dp[0], d1 = dp[1];
+    const float* sk = skip ? skip + p * skip_stride + skip_off + 8 * cg : d_pool;
+    const float4 s0 = reinterpret_cast<const float4*>(sk)[0], s1 = reinterpret_cast<const float4*>(sk)[1];
+    const float dv[8] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w};
+    const float sv[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
     float r[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
@@ -816,23 +823,25 @@ __global__ void k_pool_bwd(const float* __restrict__ d_pool, const bf16* __restr
 #pragma unroll
         for (int k = 1; k < 4; ++k)
             if (v[k] > v[arg]) arg = k;
-        r[j] = (skip ? skip[p * skip_stride + skip_off + 8 * cg + j] : 0.f) + (arg == mine ? dp[j] : 0.f);
+        r[j] = (skip ? sv[j] : 0.f) + (arg == mine ? dv[j] : 0.f);
     }
     float4* o = reinterpret_cast<float4*>(g + p * C + 8 * cg);
     o[0] = make_float4(r[0], r[1], r[2], r[3]);
     o[1] = make_float4(r[4], r[5], r[6], r[7]);
 }
 
-// Adjoint 1-D taps of up2: the outputs o that read input q, with their weights.
-__device__ __forceinline__ int up_adj(int q, int n, int* o, float* w) {
-    int k = 0;
-    if (q >= 1) { o[k] = 2 * q - 1; w[k++] = 0.25f; }
-    o[k] = 2 * q;
-    w[k++] = q == 0 ? 1.f : 0.75f;
-    o[k] = 2 * q + 1;
-    w[k++] = q == n - 1 ? 1.f : 0.75f;
-    if (q <= n - 2) { o[k] = 2 * q + 2; w[k++] = 0.25f; }
-    return k;
+// Adjoint 1-D taps of up2 (bilinear x2, half-pixel centres): the outputs that
+// read input q, in four fixed slots 2q - 1 .. 2q + 2, with their weights; a slot
+// outside the output gets weight 0 and a clamped index.
+__device__ __forceinline__ void up_taps(int q, int n, int* o, float* w) {
+    o[0] = q >= 1 ? 2 * q - 1 : 0;
+    w[0] = q >= 1 ? 0.25f : 0.f;
+    o[1] = 2 * q;
+    w[1] = q == 0 ? 1.f : 0.75f;
+    o[2] = 2 * q + 1;
+    w[2] = q == n - 1 ? 1.f : 0.75f;
+    o[3] = q <= n - 2 ? 2 * q + 2 : 2 * q + 1;
+    w[3] = q <= n - 2 ? 0.25f : 0.f;
 }
 
 __global__ void k_up_bwd(const float* __restrict__ d_cat, float* __restrict__ d_d, int images, int S,
@@ -843,20 +852,35 @@ __global__ void k_up_bwd(const float* __restrict__ d_cat, float* __restrict__ d_
     const int cg = (int)(it % G8);
     const long long q = it / G8;
     const int X = (int)(q % H), Y = (int)((q / H) % H), img = (int)(q / ((long long)H * H));
+    // the four output rows and columns that can read input (Y, X), in order;
+    // the ones outside get weight 0 and a clamped address, so all sixteen
+    // taps' loads issue together (adding 0 w leaves the same sums)
     int oy[4], ox[4];
     float wy[4], wx[4];
-    const int ny = up_adj(Y, H, oy, wy), nx = up_adj(X, H, ox, wx);
+    up_taps(Y, H, oy, wy);
+    up_taps(X, H, ox, wx);
+    float4 u[4][4][2];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const float4* src =
+                reinterpret_cast<const float4*>(d_cat + (((size_t)img * S + oy[a]) * S + ox[b]) * C + 8 * cg);
+            u[a][b][0] = src[0];
+            u[a][b][1] = src[1];
+        }
     float acc[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) acc[j] = 0.f;
-    for (int a = 0; a < ny; ++a) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
         float row[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) row[j] = 0.f;
-        for (int b = 0; b < nx; ++b) {
-            const float* src = d_cat + (((size_t)img * S + oy[a]) * S + ox[b]) * C + 8 * cg;
-            const float4 u = *(const float4*)src, v = *(const float4*)(src + 4);
-            const float vals[8] = {u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const float vals[8] = {u[a][b][0].x, u[a][b][0].y, u[a][b][0].z, u[a][b][0].w,
+                                   u[a][b][1].x, u[a][b][1].y, u[a][b][1].z, u[a][b][1].w};
 #pragma unroll
             for (int j = 0; j < 8; ++j) row[j] = fmaf(wx[b], vals[j], row[j]);
         }
