@@ -381,10 +381,19 @@ __global__ __launch_bounds__(256) void k_colsum1(const float* __restrict__ part,
     if (bl == 0 && j < n) tmp[(size_t)blockIdx.y * n + j] = ((r[0][t] + r[1][t]) + r[2][t]) + r[3][t];
 }
 
+// With cink > 0 the columns are a weight gradient in the packed K order
+// [co][tap][ci < cink] and land in the parameter layout [co][ci][tap] (ci < cin;
+// the padding channels are dropped); otherwise out[j] is column j0 + j.
 __global__ void k_colsum2(const float* __restrict__ tmp, int nbc, int n, int j0, int count,
-                          float* __restrict__ out) {
+                          float* __restrict__ out, int cin, int cink) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= count) return;
+    int dest = j;
+    if (cink > 0) {
+        const int co = j / (9 * cink), k = j % (9 * cink), tap = k / cink, ci = k % cink;
+        if (ci >= cin) return;
+        dest = (co * cin + ci) * 9 + tap;
+    }
     double s = 0.0;
     int c = 0;
     for (; c + 8 <= nbc; c += 8) {
@@ -395,7 +404,7 @@ __global__ void k_colsum2(const float* __restrict__ tmp, int nbc, int n, int j0,
         for (int u = 0; u < 8; ++u) s += v[u];
     }
     for (; c < nbc; ++c) s += tmp[(size_t)c * n + j0 + j];
-    out[j] = (float)s;
+    out[dest] = (float)s;
 }
 
 // ------------------------------------------------------------ element-wise
@@ -892,25 +901,22 @@ __global__ void k_up_bwd(const float* __restrict__ d_cat, float* __restrict__ d_
     o[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
 }
 
-__global__ void k_pack(const float* __restrict__ w, int cin, int cout, int cink, bf16* __restrict__ wf,
-                       bf16* __restrict__ wb) {
+__global__ void k_pack(const PackLayers t, const float* __restrict__ params, bf16* __restrict__ packed) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= cout * 9 * cink) return;
-    const int co = i / (9 * cink), k = i % (9 * cink), tap = k / cink, ci = k % cink;
-    wf[i] = ci < cin ? (bf16)w[((size_t)co * cin + ci) * 9 + tap] : (bf16)0.f;
-    if (wb && ci < cin) {
+    if (i >= t.start[t.n]) return;
+    int l = 0;
+    while (i >= t.start[l + 1]) ++l;
+    const int cin = t.cin[l], cout = t.cout[l], cink = t.cink[l];
+    const int e = i - t.start[l];
+    const int co = e / (9 * cink), k = e % (9 * cink), tap = k / cink, ci = k % cink;
+    const float* w = params + t.w[l];
+    packed[t.pf[l] + e] = ci < cin ? (bf16)w[((size_t)co * cin + ci) * 9 + tap] : (bf16)0.f;
+    if (t.pb[l] >= 0 && ci < cin) {
         // data gradient: [cin][9 cout], tap flipped
-        wb[(size_t)ci * 9 * cout + (8 - tap) * cout + co] = (bf16)w[((size_t)co * cin + ci) * 9 + tap];
+        packed[t.pb[l] + (size_t)ci * 9 * cout + (8 - tap) * cout + co] = (bf16)w[((size_t)co * cin + ci) * 9 + tap];
     }
 }
 
-__global__ void k_unpack_grad(const float* __restrict__ dw, int cin, int cout, int cink,
-                              float* __restrict__ out) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= cout * cin * 9) return;
-    const int co = i / (cin * 9), ci = (i / 9) % cin, tap = i % 9;
-    out[i] = dw[(size_t)co * 9 * cink + tap * cink + ci];
-}
 
 __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
                        float* __restrict__ v, long long n, float lr, float b1, float b2, float eps,
@@ -993,7 +999,7 @@ void wgrad_grid(int images, int S, int* blocks, int* tiles_per_block) {
 }
 
 bool launch_wgrad(int cin, int cout, const bf16* dz, const bf16* in, float* part, float* tmp, float* dw,
-                  int images, int S, hipStream_t s) {
+                  int real_cin, int images, int S, hipStream_t s) {
     int nb, tpb;
     wgrad_grid(images, S, &nb, &tpb);
     const int tiles = conv_blocks(images, S);
@@ -1006,7 +1012,8 @@ bool launch_wgrad(int cin, int cout, const bf16* dz, const bf16* in, float* part
         if (lds > kLdsLimit) return false;                                                        \
         FMBYM_LAUNCH_LDS(kMWgrad, (k_wgrad<CI, CO>), dim3(nb), dim3(256), lds, s, dz, in, part, S, tpb, tiles); \
         const int nbc = colsum1(kMWgrad, part, nb, (long long)n, n, tmp, s);                       \
-        FMBYM_LAUNCH(kMWgrad, k_colsum2, dim3(grid_for(n, 256)), dim3(256), s, tmp, nbc, n, 0, n, dw); \
+        FMBYM_LAUNCH(kMWgrad, k_colsum2, dim3(grid_for(n, 256)), dim3(256), s, tmp, nbc, n, 0, n, dw, \
+                     real_cin, cin);                                                              \
         return true;                                                                              \
     }
     FMBYM_CONV_PAIRS(FMBYM_WGRAD_CASE)
@@ -1061,8 +1068,8 @@ void launch_head_bwd(const float* d_mask, const float* mask, const bf16* a, cons
     const int nb = (int)((n + kHeadPix - 1) / kHeadPix), NW = 9 * C + 1;
     FMBYM_LAUNCH(kMHeadBwd, k_head_wgrad, dim3(nb), dim3(256), s, dl, a, part, images, S);
     const int nbc = colsum1(kMHeadBwd, part, nb, (long long)NW, NW, tmp, s);
-    FMBYM_LAUNCH(kMHeadBwd, k_colsum2, dim3(1), dim3(128), s, tmp, nbc, NW, 0, 9 * C, dw);
-    FMBYM_LAUNCH(kMHeadBwd, k_colsum2, dim3(1), dim3(64), s, tmp, nbc, NW, 9 * C, 1, db);
+    FMBYM_LAUNCH(kMHeadBwd, k_colsum2, dim3(1), dim3(128), s, tmp, nbc, NW, 0, 9 * C, dw, 0, 0);
+    FMBYM_LAUNCH(kMHeadBwd, k_colsum2, dim3(1), dim3(64), s, tmp, nbc, NW, 9 * C, 1, db, 0, 0);
 }
 
 void launch_bn_relu_bwd(const float* g, const bf16* z, const float* stat, const float* gamma, float* part,
@@ -1090,15 +1097,10 @@ void launch_up_bwd(const float* d_cat, float* d_d, int images, int S, int Cd, in
     FMBYM_LAUNCH(kMUpBwd, k_up_bwd, dim3(grid_for(n, 256)), dim3(256), s, d_cat, d_d, images, S, Cd, Ce);
 }
 
-void launch_pack(const float* w, int cin, int cout, int cink, bf16* wf, bf16* wb, hipStream_t s) {
-    const int n = cout * 9 * cink;
-    FMBYM_LAUNCH(kMPack, k_pack, dim3(grid_for(n, 256)), dim3(256), s, w, cin, cout, cink, wf, wb);
+void launch_pack(const PackLayers& t, const float* params, bf16* packed, hipStream_t s) {
+    FMBYM_LAUNCH(kMPack, k_pack, dim3(grid_for(t.start[t.n], 256)), dim3(256), s, t, params, packed);
 }
 
-void launch_unpack_grad(const float* dw, int cin, int cout, int cink, float* out, hipStream_t s) {
-    const int n = cout * cin * 9;
-    FMBYM_LAUNCH(kMWgrad, k_unpack_grad, dim3(grid_for(n, 256)), dim3(256), s, dw, cin, cout, cink, out);
-}
 
 void launch_adam(float* p, const float* g, float* m, float* v, long long n, float lr, float b1, float b2,
                  float eps, float c1, float c2, hipStream_t s) {

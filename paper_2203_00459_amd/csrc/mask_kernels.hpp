@@ -38,12 +38,13 @@ void launch_input8(const float* x, const float* const* x_tab, bf16* x8, int imag
 bool launch_conv3x3(int cin, int cout, bool stats, const bf16* in, const bf16* w, void* z,
                     float* part, int images, int S, hipStream_t s);
 
-// Weight gradient: dw[co][9 cin] (float, k as above) = sum over pixels of
-// dz[p][co] in[p + tap][ci], through per-block partials part (wgrad_grid) and
-// a fixed-order reduction (tmp: colsum_tmp_floats(cout 9 cin)).  Returns false
-// for an unsupported pair.
+// Weight gradient: sum over pixels of dz[p][co] in[p + tap][ci], through
+// per-block partials part (wgrad_grid) and a fixed-order reduction (tmp:
+// colsum_tmp_floats(cout 9 cin)); cin is the staged (padded) channel count and
+// the result lands in the parameter layout dw[co][ci][tap] for ci < real_cin.
+// Returns false for an unsupported pair.
 bool launch_wgrad(int cin, int cout, const bf16* dz, const bf16* in, float* part, float* tmp, float* dw,
-                  int images, int S, hipStream_t s);
+                  int real_cin, int images, int S, hipStream_t s);
 
 // Floats of the scratch `tmp` that the two-stage column sums of n columns need.
 size_t colsum_tmp_floats(int n);
@@ -92,12 +93,17 @@ void launch_pool_bwd(const float* d_pool, const bf16* e, const float* skip, int 
 void launch_up_bwd(const float* d_cat, float* d_d, int images, int S, int Cd, int Ce, hipStream_t s);
 
 // Pack conv weights (OIHW float) to the forward layout [cout][9 cink] (ci >=
-// cin zero) and, if wb is not null, the data-gradient layout [cin][9 cout] with
-// the taps flipped.
-void launch_pack(const float* w, int cin, int cout, int cink, bf16* wf, bf16* wb, hipStream_t s);
-
-// Scatter a [cout][9 cink] weight gradient into OIHW float (ci < cin).
-void launch_unpack_grad(const float* dw, int cin, int cout, int cink, float* out, hipStream_t s);
+// cin zero) and, where pb >= 0, the data-gradient layout [cin][9 cout] with
+// the taps flipped: every layer of a network in one launch.  Offsets count
+// floats of params (w) and bf16 elements of the packed buffer (pf, pb).
+constexpr int kMaxPackLayers = 16;
+struct PackLayers {
+    int n;
+    int cin[kMaxPackLayers], cout[kMaxPackLayers], cink[kMaxPackLayers];
+    int start[kMaxPackLayers + 1];   // first element of each layer's forward layout
+    long long w[kMaxPackLayers], pf[kMaxPackLayers], pb[kMaxPackLayers];
+};
+void launch_pack(const PackLayers& t, const float* params, bf16* packed, hipStream_t s);
 
 void launch_adam(float* p, const float* g, float* m, float* v, long long n, float lr, float b1,
                  float b2, float eps, float c1, float c2, hipStream_t s);

@@ -141,7 +141,7 @@ ActLayout act_layout(const Net& net, int I, int n) {
 }
 
 struct WsLayout {
-    size_t dz = 0, part = 0, coef = 0, wpart = 0, dw = 0, dl = 0, hpart = 0, tmp = 0, total = 0;
+    size_t dz = 0, part = 0, coef = 0, wpart = 0, dl = 0, hpart = 0, tmp = 0, total = 0;
     std::vector<size_t> g, dpool, dcat;
 };
 
@@ -150,7 +150,7 @@ WsLayout ws_layout(const Net& net, int I, int n) {
     Bump b;
     const size_t fl = 4;
     auto pix = [&](int l) { return (size_t)I * (size_t)(n >> l) * (size_t)(n >> l); };
-    size_t dz_max = 0, part_max = 0, wpart_max = 0, dw_max = 0;
+    size_t dz_max = 0, part_max = 0, wpart_max = 0;
     for (const ConvL& c : net.convs) {
         L.g.push_back(b.take(pix(c.level) * c.cout * fl));
         dz_max = std::max(dz_max, pix(c.level) * c.cout * 2);
@@ -158,7 +158,6 @@ WsLayout ws_layout(const Net& net, int I, int n) {
         int nb, tpb;
         wgrad_grid(I, n >> c.level, &nb, &tpb);
         wpart_max = std::max(wpart_max, (size_t)nb * c.cout * 9 * c.cink * fl);
-        dw_max = std::max(dw_max, (size_t)c.cout * 9 * c.cink * fl);
     }
     L.dpool.assign(net.levels, 0);
     for (int l = 1; l < net.levels; ++l) L.dpool[l] = b.take(pix(l) * net.ch(l - 1) * fl);
@@ -168,7 +167,6 @@ WsLayout ws_layout(const Net& net, int I, int n) {
     L.part = b.take(part_max);
     L.coef = b.take(3 * 96 * fl);
     L.wpart = b.take(wpart_max);
-    L.dw = b.take(dw_max);
     L.dl = b.take(pix(0) * fl);
     L.hpart = b.take(((pix(0) + 4095) / 4096) * (9 * net.base + 1) * fl);
     size_t cols = 2 * 96;
@@ -219,11 +217,20 @@ int fmbym_mask_pack(const fmbym_mask_desc* d, void* stream) {
     if (!build_net(d, net)) return FMBYM_EUNSUPPORTED;
     if (!d->params || !d->packed) return FMBYM_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    bf16* pk = (bf16*)d->packed;
-    for (size_t j = 0; j < net.convs.size(); ++j) {
+    PackLayers t{};
+    t.n = (int)net.convs.size();
+    if (t.n > kMaxPackLayers) return FMBYM_EUNSUPPORTED;
+    for (int j = 0; j < t.n; ++j) {
         const ConvL& c = net.convs[j];
-        launch_pack(d->params + c.w, c.cin, c.cout, c.cink, pk + c.pf, j ? pk + c.pb : nullptr, s);
+        t.cin[j] = c.cin;
+        t.cout[j] = c.cout;
+        t.cink[j] = c.cink;
+        t.start[j + 1] = t.start[j] + c.cout * 9 * c.cink;
+        t.w[j] = (long long)c.w;
+        t.pf[j] = (long long)c.pf;
+        t.pb[j] = j ? (long long)c.pb : -1;   // the first conv has no data gradient
     }
+    launch_pack(t, d->params, (bf16*)d->packed, s);
     return finish(s);
 }
 
@@ -282,9 +289,8 @@ int fmbym_mask_bwd(const fmbym_mask_desc* d, int32_t I, int32_t n, const float* 
         else
             in = at<bf16>(act, A.a[j - 1]);
         if (!launch_wgrad(c.cink, c.cout, dz, in, at<float>(wsp, W.wpart), at<float>(wsp, W.tmp),
-                          at<float>(wsp, W.dw), I, S, s))
+                          d_params + c.w, c.cin, I, S, s))
             return FMBYM_EUNSUPPORTED;
-        launch_unpack_grad(at<float>(wsp, W.dw), c.cin, c.cout, c.cink, d_params + c.w, s);
         if (j == 0) break;
         // data gradient into the buffer of this conv's input
         float* din;
