@@ -486,16 +486,25 @@ __global__ void k_bn_stats(const float* __restrict__ part, int nb, int C, long l
     stat[3 * C + c] = (float)((double)beta[c] - mean * sc);
 }
 
+// Eight consecutive floats from a 32-byte-aligned address as two vector loads.
+__device__ __forceinline__ void load8(const float* __restrict__ p, float (&v)[8]) {
+    const float4 a = reinterpret_cast<const float4*>(p)[0], b = reinterpret_cast<const float4*>(p)[1];
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+}
+
 __global__ void k_bn_relu(const bf16* __restrict__ z, const float* __restrict__ stat,
                           bf16* __restrict__ a, long long items, int C) {
     const long long it = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (it >= items) return;
     const int c0 = (int)(it % (C / 8)) * 8;
     const bf16x8 v = __builtin_bit_cast(bf16x8, *(const u32x4*)(z + it * 8));
+    float sc[8], sh[8];
+    load8(stat + 2 * C + c0, sc);
+    load8(stat + 3 * C + c0, sh);
     bf16x8 o;
 #pragma unroll
-    for (int j = 0; j < 8; ++j)
-        o[j] = (bf16)fmaxf(fmaf((float)v[j], stat[2 * C + c0 + j], stat[3 * C + c0 + j]), 0.f);
+    for (int j = 0; j < 8; ++j) o[j] = (bf16)fmaxf(fmaf((float)v[j], sc[j], sh[j]), 0.f);
     *(u32x4*)(a + it * 8) = __builtin_bit_cast(u32x4, o);
 }
 
@@ -787,15 +796,24 @@ __global__ void k_bn_bwd_apply(const float* __restrict__ g, const bf16* __restri
     if (it >= items) return;
     const int c0 = (int)(it % (C / 8)) * 8;
     const bf16x8 zv = __builtin_bit_cast(bf16x8, *(const u32x4*)(z + it * 8));
-    const float* gp = g + it * 8;
+    // eight channels of g and of each statistic as vector loads (C and c0 are
+    // multiples of 8), all issued before the arithmetic
+    float gv[8], mean[8], inv[8], sc[8], sh[8], k0[8], k1[8], k2[8];
+    load8(g + it * 8, gv);
+    load8(stat + c0, mean);
+    load8(stat + C + c0, inv);
+    load8(stat + 2 * C + c0, sc);
+    load8(stat + 3 * C + c0, sh);
+    load8(coef + c0, k0);
+    load8(coef + C + c0, k1);
+    load8(coef + 2 * C + c0, k2);
     bf16x8 o;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-        const int c = c0 + j;
         const float zz = (float)zv[j];
-        const float dy = fmaf(zz, stat[2 * C + c], stat[3 * C + c]) > 0.f ? gp[j] : 0.f;
-        const float xh = (zz - stat[c]) * stat[C + c];
-        o[j] = (bf16)(coef[c] * (dy - coef[C + c] - xh * coef[2 * C + c]));
+        const float dy = fmaf(zz, sc[j], sh[j]) > 0.f ? gv[j] : 0.f;
+        const float xh = (zz - mean[j]) * inv[j];
+        o[j] = (bf16)(k0[j] * (dy - k1[j] - xh * k2[j]));
     }
     *(u32x4*)(dz + it * 8) = __builtin_bit_cast(u32x4, o);
 }
