@@ -698,17 +698,20 @@ __global__ __launch_bounds__(256) void k_head_wgrad(const float* __restrict__ dl
 }
 
 // Per-block channel sums for the batch-norm adjoint: part[block][0][c] = sum dy,
-// part[block][1][c] = sum dy xhat over kBnPix pixels.  Thread (pixel lane,
-// 8-channel group) with blockDim = (C/8) (256 / (C/8)); the pixel lanes are
-// summed in order through LDS.
-constexpr int kBnPix = 1024;
+// part[block][1][c] = sum dy xhat over the block's bn_pixels(C) pixels (8192
+// channel values per block whatever C, so deep layers with few pixels still
+// spread over many blocks).  Thread (pixel lane, 8-channel group) with
+// blockDim = (C/8) (256 / (C/8)); the pixel lanes are summed in order
+// through LDS.
+constexpr int kBnValues = 8192;
+__host__ __device__ constexpr int bn_pixels(int C) { return kBnValues / C; }
 
 __global__ __launch_bounds__(256) void k_bn_bwd_part(const float* __restrict__ g, const bf16* __restrict__ z,
                                                      const float* __restrict__ stat, float* __restrict__ part,
                                                      long long M, int C) {
     const int G8 = C / 8, PL = blockDim.x / G8, cg = threadIdx.x % G8, pl = threadIdx.x / G8;
-    const long long p0 = (long long)blockIdx.x * kBnPix;
-    const long long p1 = min(M, p0 + kBnPix);
+    const long long p0 = (long long)blockIdx.x * bn_pixels(C);
+    const long long p1 = min(M, p0 + bn_pixels(C));
     float sd[8], sx[8], mean[8], inv[8], sc[8], sh[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
@@ -1039,7 +1042,7 @@ bool launch_wgrad(int cin, int cout, const bf16* dz, const bf16* in, float* part
     return false;
 }
 
-int bn_part_blocks(long long M, int /*C*/) { return (int)((M + kBnPix - 1) / kBnPix); }
+int bn_part_blocks(long long M, int C) { return (int)((M + bn_pixels(C) - 1) / bn_pixels(C)); }
 
 void launch_input8(const float* x, const float* const* x_tab, bf16* x8, int images, int S, hipStream_t s) {
     const long long n = (long long)images * S * S;
