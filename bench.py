@@ -99,7 +99,8 @@ def kernel_bytes(n: int, n_theta: int, n_r: int, batch: int, masked: bool, keep:
         # forward
         "k_rows1": batch * (m * 2 * 4 * N2 + half),
         "k_cols1": batch * (half + mag),
-        "k_polar": batch * (mag + nrb * hk * 8),
+        # with keep it also writes the per-radius angular spectra for the adjoint
+        "k_polar": batch * (mag + nrb * hk * 8 + (n_r * n_theta * 8 if keep else 0)),
         "k_angle_fin": batch * (nrb * hk * 8 + n_theta * 4),
         # without keep k_rotate runs twice per step: forward (g') and adjoint (g', d g'/d theta)
         "k_rotate": batch * (m * 4 * N2 + (8 * N2 if keep else 6 * N2)),
