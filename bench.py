@@ -78,6 +78,17 @@ def measured_traffic(kernel: str):
     return (best[1] * meta["ff"] + best[2] * meta["fw"]) * 1024.0
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (Linux), for the CPU-baseline record."""
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def kernel_bytes(n: int, n_theta: int, n_r: int, batch: int, masked: bool, keep: bool = False) -> dict:
     """Algorithmic HBM bytes per launch of each kernel: compulsory reads of its
     inputs plus writes of its outputs, each touched once (float32 / complex64).
@@ -257,7 +268,7 @@ def train_bench(args) -> int:
         pose = O.search(f[0], g[0], O.Params(**kw), m[0], m[1])["pose"]
         M.pose_loss(pose[None], torch.from_numpy(p[:1]).double(), "l2").backward()
         dt = time.perf_counter() - t0
-        res["cpu_baseline"] = {"value": 1.0 / dt, "unit": "pairs/s", "cores": torch.get_num_threads(),
+        res["cpu_baseline"] = {"value": 1.0 / dt, "unit": "pairs/s", "cores": torch.get_num_threads(), "cpu": cpu_model(),
                                "kind": "oracle",
                                "sample": "1 pair: FP64 oracle mask network + masked search + L2 loss, autograd"}
     print(json.dumps(res), flush=True)
@@ -325,7 +336,7 @@ def drive_bench(args) -> int:
             O.search(scans_np[done], scans_np[done + 1], p)
             done += 1
         dt = time.perf_counter() - t0
-        res["cpu_baseline"] = {"value": done / dt, "unit": "pairs/s", "cores": torch.get_num_threads(),
+        res["cpu_baseline"] = {"value": done / dt, "unit": "pairs/s", "cores": torch.get_num_threads(), "cpu": cpu_model(),
                                "kind": "oracle",
                                "sample": f"the drive's first {done} pairs (about 10 s), FP64 oracle forward"}
     print(json.dumps(res), flush=True)
@@ -410,7 +421,7 @@ def ragged_bench(args) -> int:
             O.search(f, g, p)
             t_pair[k] = time.perf_counter() - t0
         mean_t = sum(counts[k] * t_pair[k] for k in sizes) / cfg["n_pairs"]
-        res["cpu_baseline"] = {"value": 1.0 / mean_t, "unit": "pairs/s", "cores": torch.get_num_threads(),
+        res["cpu_baseline"] = {"value": 1.0 / mean_t, "unit": "pairs/s", "cores": torch.get_num_threads(), "cpu": cpu_model(),
                                "kind": "oracle",
                                "sample": "one pair of each size, FP64 oracle forward, weighted by the mix"}
     print(json.dumps(res), flush=True)
@@ -628,7 +639,7 @@ def search_bench(args) -> int:
             else:
                 O.search(f_np[b], g_np[b], p)
         dt = time.perf_counter() - t0
-        res["cpu_baseline"] = {"value": k / dt, "unit": "pairs/s", "cores": torch.get_num_threads(),
+        res["cpu_baseline"] = {"value": k / dt, "unit": "pairs/s", "cores": torch.get_num_threads(), "cpu": cpu_model(),
                                "kind": "oracle",
                                "sample": f"{k} of the {B} pairs, FP64 oracle "
                                          f"{'forward + autograd backward' if with_bwd else 'forward'}"}
