@@ -104,6 +104,43 @@ class MaskedSearchTrainer:
         return {"masked_theta": em[0], "masked_t": em[1], "unmasked_theta": eu[0], "unmasked_t": eu[1],
                 "use_mask": self.use_mask}
 
+    # ------------------------------------------------------ checkpoint / resume
+
+    def state_dict(self) -> dict:
+        """Everything a resumed run needs, as CPU tensors and plain values: the
+        FP32 master weights, Adam's moments and step count, the BatchNorm running
+        statistics, the fallback decision and the configuration."""
+        n = self.net
+        return {"params": n.params.detach().cpu().clone(), "adam_m": n.m.cpu().clone(),
+                "adam_v": n.v.cpu().clone(), "adam_step": int(n.step), "bn_running": n.bn_running.cpu().clone(),
+                "use_mask": bool(self.use_mask), "config": dataclasses.asdict(self.cfg)}
+
+    def load_state_dict(self, st: dict) -> None:
+        """Restore a state_dict (in place: the device buffers keep their
+        addresses) and re-pack the BF16 weights."""
+        check_state(st, self.net.params.numel(), self.net.bn_running.numel())
+        if st["config"]["levels"] != self.cfg.levels or st["config"]["base"] != self.cfg.base:
+            raise ValueError("checkpoint of a different network")
+        n = self.net
+        n.params.copy_(st["params"].to(n.params.device))
+        n.m.copy_(st["adam_m"].to(n.m.device))
+        n.v.copy_(st["adam_v"].to(n.v.device))
+        n.bn_running.copy_(st["bn_running"].to(n.bn_running.device))
+        n.step = int(st["adam_step"])
+        self.use_mask = bool(st["use_mask"])
+        n.pack()
+
+    def save(self, path: str, extra: dict | None = None) -> None:
+        """Write the state (plus the caller's own plain values, e.g. its data
+        order's RNG state, under "extra") with torch.save."""
+        save_checkpoint(path, self.state_dict(), extra)
+
+    def load(self, path: str) -> dict:
+        """Restore from save(); returns the caller's "extra" values."""
+        st = load_checkpoint(path)
+        self.load_state_dict(st)
+        return st.get("extra", {})
+
     @torch.no_grad()
     def predict(self, f, g):
         """Poses with the policy: the masked search once it has won, else the unmasked one."""
@@ -111,3 +148,27 @@ class MaskedSearchTrainer:
             m_f, m_g = self.masks(f, g, training=False)
             return self.search.forward(f, g, m_f, m_g, surfaces=False)["pose"]
         return self.search.forward(f, g, surfaces=False)["pose"]
+
+
+def check_state(st: dict, n_params: int, n_bn: int) -> None:
+    """Shapes and types of a trainer state; raises ValueError on a mismatch."""
+    for k in ("params", "adam_m", "adam_v"):
+        if not isinstance(st.get(k), torch.Tensor) or st[k].numel() != n_params or st[k].dtype != torch.float32:
+            raise ValueError(f"checkpoint field {k}: expected {n_params} float32 values")
+    if not isinstance(st.get("bn_running"), torch.Tensor) or st["bn_running"].numel() != n_bn:
+        raise ValueError(f"checkpoint field bn_running: expected {n_bn} values")
+    if int(st.get("adam_step", -1)) < 0:
+        raise ValueError("checkpoint field adam_step missing")
+
+
+def save_checkpoint(path: str, state: dict, extra: dict | None = None) -> None:
+    """torch.save of a trainer state (tensors and plain values only)."""
+    st = dict(state)
+    if extra is not None:
+        st["extra"] = dict(extra)
+    torch.save(st, path)
+
+
+def load_checkpoint(path: str) -> dict:
+    """torch.load with weights_only=True: tensors and plain values, no code."""
+    return torch.load(path, map_location="cpu", weights_only=True)

@@ -106,3 +106,43 @@ def test_training_makes_the_mask_beat_the_unmasked_search():
     m_f, m_g = tr.masks(Ft, Gt, training=False)
     ref = tr.search.forward(Ft, Gt, m_f, m_g, surfaces=False)["pose"]
     assert torch.equal(tr.predict(Ft, Gt), ref)
+
+
+def test_resume_from_a_checkpoint_continues_bit_for_bit(tmp_path):
+    """Train 2N steps straight; separately train N steps, save, build a fresh
+    trainer, load, train N more with the restored data order: the losses of the
+    last N steps and the final weights, moments and statistics are identical
+    (every kernel reduces in a fixed order)."""
+    ntrain, N, B = 64, 6, 8
+    f, g, p = synth.make_batch("mask256", ntrain, split="train")
+    F, G, P = (torch.from_numpy(a).to(DEV) for a in (f, g, p.astype(np.float32)))
+    cfg = TrainConfig(lr=1e-3, loss=fmbym.FMBYM_LOSS_L1)
+
+    def run(tr, rng, steps):
+        out = []
+        for _ in range(steps):
+            idx = torch.from_numpy(rng.choice(ntrain, B, replace=False)).to(DEV)
+            loss, _ = tr.step(F[idx].contiguous(), G[idx].contiguous(), P[idx].contiguous())
+            out.append(loss.clone())
+        return out
+
+    straight = MaskedSearchTrainer(KW256, batch=B, cfg=cfg)
+    ref = run(straight, np.random.Generator(np.random.PCG64(9)), 2 * N)
+    first = MaskedSearchTrainer(KW256, batch=B, cfg=cfg)
+    rng = np.random.Generator(np.random.PCG64(9))
+    run(first, rng, N)
+    path = str(tmp_path / "mask.pt")
+    first.save(path, extra={"rng": rng.bit_generator.state})
+    first.net.params.fill_(0.0)        # the resumed run must not read the old trainer
+    resumed = MaskedSearchTrainer(KW256, batch=B, cfg=cfg, params=np.zeros(straight.net.params.numel()))
+    extra = resumed.load(path)
+    rng2 = np.random.Generator(np.random.PCG64(0))
+    rng2.bit_generator.state = extra["rng"]
+    rest = run(resumed, rng2, N)
+    torch.cuda.synchronize()
+    for a, b in zip(ref[N:], rest):
+        assert torch.equal(a, b)
+    s1, s2 = straight.state_dict(), resumed.state_dict()
+    for k in ("params", "adam_m", "adam_v", "bn_running"):
+        assert torch.equal(s1[k], s2[k]), k
+    assert s1["adam_step"] == s2["adam_step"] == 2 * N
