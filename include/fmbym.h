@@ -57,6 +57,10 @@ extern "C" {
 /* flags */
 #define FMBYM_HANN 1u           /* periodic Hann window on both scans (Algorithm 1) */
 #define FMBYM_XY_UNWINDOWED 8u  /* translation stage on the unwindowed scans        */
+#define FMBYM_CHECK_FINITE 64u  /* forward calls count each pair's non-finite input
+                                   values (f, g and the masks) into
+                                   saved[b][FMBYM_SAVED_STATUS]; the search itself
+                                   is unchanged (non-finite values still propagate) */
 
 /* floats per pair in the `saved` statistics buffer, and its slots */
 #define FMBYM_SAVED 16
@@ -72,6 +76,7 @@ extern "C" {
 #define FMBYM_SAVED_THETA_MEAN 9  /* mean heading score over all lags                     */
 #define FMBYM_SAVED_THETA_ARG 10  /* lag l* of the largest heading score (lowest on ties) */
 #define FMBYM_SAVED_THETA_NU 11   /* sum_l p_l (l - l*): theta = (l* + nu) pi / n_theta   */
+#define FMBYM_SAVED_STATUS 12     /* with FMBYM_CHECK_FINITE: count of non-finite inputs */
 
 typedef struct fmbym_plan_s* fmbym_plan;
 
@@ -85,7 +90,7 @@ typedef struct {
     float temp_xy;      /* translation softmax temperature T_xy (> 0)                     */
     float band_lo;      /* band-pass: keep lo <= |k|/n <= hi (cycles per pixel) ...       */
     float band_hi;      /* ... disabled when band_hi <= 0                                  */
-    uint32_t flags;     /* FMBYM_HANN | FMBYM_XY_UNWINDOWED                                */
+    uint32_t flags;     /* FMBYM_HANN | FMBYM_XY_UNWINDOWED | FMBYM_CHECK_FINITE           */
 } fmbym_params;
 
 /* Launch choices of a plan: column-tile widths of the column passes (how many

@@ -39,7 +39,7 @@ int check_params(const fmbym_params* p) {
     if (!isfinite(p->band_lo) || !isfinite(p->band_hi)) return FMBYM_EINVAL;
     if (p->band_hi > 0.f && (p->band_lo < 0.f || p->band_lo > p->band_hi)) return FMBYM_EINVAL;
     if (p->n <= 0 || p->n_theta <= 0 || p->n_r <= 0) return FMBYM_EINVAL;
-    if (p->flags & ~(uint32_t)(FMBYM_HANN | FMBYM_XY_UNWINDOWED)) return FMBYM_EUNSUPPORTED;
+    if (p->flags & ~(uint32_t)(FMBYM_HANN | FMBYM_XY_UNWINDOWED | FMBYM_CHECK_FINITE)) return FMBYM_EUNSUPPORTED;
     if (p->n != 128 && p->n != 256 && p->n != 512) return FMBYM_EUNSUPPORTED;
     if (!pow2(p->n_theta) || p->n_theta < 16 || p->n_theta > 1024) return FMBYM_EUNSUPPORTED;
     if (p->n_r > 4096) return FMBYM_EUNSUPPORTED;

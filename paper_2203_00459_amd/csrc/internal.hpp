@@ -23,6 +23,7 @@ enum SavedSlot {
     kSavedThetaMean = FMBYM_SAVED_THETA_MEAN,  // mean heading score over the lags
     kSavedThetaArg = FMBYM_SAVED_THETA_ARG,    // lag of the largest heading score
     kSavedThetaNu = FMBYM_SAVED_THETA_NU,      // sum_l p_l (l - argmax lag)
+    kSavedStatus = FMBYM_SAVED_STATUS,         // non-finite input count (FMBYM_CHECK_FINITE)
 };
 
 struct Plan {
@@ -113,9 +114,11 @@ struct FwdLayout {
     size_t pxy;       // [B][xy_partials] float4
     size_t saved;     // [B][FMBYM_SAVED] float (used when the caller passes none)
     size_t grot;      // [B][n][n] float: g' = Rotate(g_w), the rotated stage-2 scan
+    size_t fin;       // [B][kFiniteSlices] int: non-finite input counts per slice
     size_t total;
 };
 FwdLayout fwd_layout(const fmbym_params& p, int batch);
+constexpr int kFiniteSlices = 64;   // blocks per pair of the non-finite count
 
 // Intermediates a training forward keeps in the caller's state buffer, so that
 // its adjoint reads them instead of recomputing them.

@@ -11,7 +11,7 @@ enum KernelId {
     kKBRowsFwd2, kKBColsXy, kKBRowsXy, kKBDtheta, kKBPolar, kKBDmag, kKBColsMag, kKBRowsFinal,
     kMInput, kMConvFwd, kMBnStats, kMBnRelu, kMPool, kMUpCat, kMHeadFwd, kMHeadBwd, kMBnBwd, kMWgrad,
     kMConvDgrad, kMPoolBwd, kMUpBwd, kMPack, kMAdam, kMLoss, kKRotate, kKBRotateAdj,
-    kKJointSetup, kKJointPeak, kKJointPick, kKTurnSetup, kKTurnPick,
+    kKJointSetup, kKJointPeak, kKJointPick, kKTurnSetup, kKTurnPick, kKFinite,
     kKernelCount
 };
 

@@ -673,6 +673,8 @@ FwdLayout fwd_layout(const fmbym_params& p, int batch) {
     off = align256(off + B * FMBYM_SAVED * sizeof(float));
     L.grot = off;
     off = align256(off + B * n * n * sizeof(float));
+    L.fin = off;
+    off = align256(off + B * kFiniteSlices * sizeof(int));
     L.total = off;
     return L;
 }
@@ -811,6 +813,44 @@ static void stage2_n(const Plan& pl, int B, const float* f, const float* g, cons
                  pxy, pl.p.temp_xy);
 }
 
+// Input check (FMBYM_CHECK_FINITE): slice q of pair b counts the values of f,
+// g (and the masks) in [q n^2 / S, (q + 1) n^2 / S) that are NaN or infinite;
+// then one thread per pair adds the slices in order into saved[b].
+__global__ __launch_bounds__(256) void k_finite_part(const float* __restrict__ f, const float* __restrict__ g,
+                                                     const float* __restrict__ mf, const float* __restrict__ mg,
+                                                     int n, int* __restrict__ counts,
+                                                     const float* const* __restrict__ tab) {
+    const int b = blockIdx.x / kFiniteSlices, q = blockIdx.x % kFiniteSlices;
+    const PairScans sc = pair_scans(tab, b, n, f, g, mf, mg);
+    const int n4 = n * n / 4, per = n4 / kFiniteSlices;   // n^2 / 4 float4 per scan, a multiple of 64
+    const float4* arr[4] = {(const float4*)sc.f, (const float4*)sc.g, (const float4*)sc.mf, (const float4*)sc.mg};
+    int bad = 0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        if (!arr[a]) continue;   // block-uniform
+        for (int i = q * per + (int)threadIdx.x; i < (q + 1) * per; i += 256) {
+            const float4 v = arr[a][i];
+            bad += !isfinite(v.x) + !isfinite(v.y) + !isfinite(v.z) + !isfinite(v.w);
+        }
+    }
+    __shared__ int red[256];
+    red[threadIdx.x] = bad;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) counts[blockIdx.x] = red[0];
+}
+
+__global__ void k_finite_fin(const int* __restrict__ counts, int batch, float* __restrict__ saved) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch) return;
+    long long c = 0;
+    for (int q = 0; q < kFiniteSlices; ++q) c += counts[b * kFiniteSlices + q];
+    saved[(size_t)b * FMBYM_SAVED + kSavedStatus] = (float)c;
+}
+
 template <int N>
 static int launch_n(const Plan& pl, int B, const float* f, const float* g, const float* mf,
                     const float* mg, float* pose, float* c_theta, float* c_xy, float* saved,
@@ -821,6 +861,12 @@ static int launch_n(const Plan& pl, int B, const float* f, const float* g, const
     float2* pth = (float2*)(ws + lay.ptheta);
     float4* pxy = (float4*)(ws + lay.pxy);
     float* sv = saved ? saved : (float*)(ws + lay.saved);
+    if (pl.p.flags & FMBYM_CHECK_FINITE) {
+        int* counts = (int*)(ws + lay.fin);
+        FMBYM_LAUNCH(kKFinite, k_finite_part, dim3(B * kFiniteSlices), dim3(256), s, f, g, mf, mg, N, counts,
+                     tab);
+        FMBYM_LAUNCH(kKFinite, k_finite_fin, dim3((B + 63) / 64), dim3(64), s, counts, B, sv);
+    }
     launch_stage1_rows_cols<N>(pl, B, f, g, mf, mg, r1, mag, s, tab);
     switch (pl.p.n_theta) {
         case 16: launch_polar<N, 16>(pl, B, mag, pth, c_theta, pose, sv, s, keep ? keep->pspec : nullptr); break;

@@ -23,6 +23,7 @@ FMBYM_EWORKSPACE = -3
 FMBYM_EHIP = -4
 FMBYM_HANN = 1
 FMBYM_XY_UNWINDOWED = 8
+FMBYM_CHECK_FINITE = 64
 FMBYM_SAVED = 16
 FMBYM_SAVED_THETA = 0
 FMBYM_SAVED_COS = 1
@@ -36,6 +37,7 @@ FMBYM_SAVED_TPY = 8
 FMBYM_SAVED_THETA_MEAN = 9
 FMBYM_SAVED_THETA_ARG = 10
 FMBYM_SAVED_THETA_NU = 11
+FMBYM_SAVED_STATUS = 12
 
 EXPORTS = (
     "fmbym_plan_create", "fmbym_plan_destroy", "fmbym_search_workspace_size", "fmbym_search",
@@ -389,8 +391,9 @@ class Search:
     def __init__(self, n: int, n_theta: int, n_r: int | None = None, delta_xy: float = 1.0,
                  temp_theta: float = 1.0, temp_xy: float = 1.0, band_lo: float = 0.0,
                  band_hi: float = 0.0, hann: bool = True, xy_unwindowed: bool = False,
-                 max_batch: int = 64):
-        flags = (FMBYM_HANN if hann else 0) | (FMBYM_XY_UNWINDOWED if xy_unwindowed else 0)
+                 check_finite: bool = False, max_batch: int = 64):
+        flags = ((FMBYM_HANN if hann else 0) | (FMBYM_XY_UNWINDOWED if xy_unwindowed else 0)
+                 | (FMBYM_CHECK_FINITE if check_finite else 0))
         self.params = fmbym_params(n, n_theta, n if n_r is None else n_r, delta_xy, temp_theta,
                                    temp_xy, band_lo, band_hi, flags)
         self.n, self.n_theta, self.max_batch = n, n_theta, max_batch

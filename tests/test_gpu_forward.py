@@ -122,3 +122,31 @@ def test_bitwise_deterministic():
     b = _run(kw, f, g)
     for k in ("pose", "c_theta", "c_xy", "saved"):
         assert torch.equal(a[k], b[k]), k
+
+
+def test_check_finite_counts_non_finite_inputs():
+    """FMBYM_CHECK_FINITE: each pair's count of NaN / infinite values in f, g and
+    the masks lands in saved[b][FMBYM_SAVED_STATUS] (counted here with numpy);
+    a clean pair's outputs are bitwise those of a plan without the flag."""
+    kw = workloads.search_kwargs("pair128")
+    B = 3
+    f, g, _ = synth.make_batch("pair128", B, split="val", start=11)
+    rng = np.random.default_rng(8)
+    mf = rng.uniform(0.2, 1.0, f.shape).astype(np.float32)
+    mg = rng.uniform(0.2, 1.0, f.shape).astype(np.float32)
+    f[1, 3, 5] = np.nan
+    f[1, 100, 7] = np.inf
+    g[1, 64, 64] = -np.inf
+    mg[2, 0, 0] = np.nan
+    mg[2, 127, 127] = np.nan
+    mf[2, 50, 60] = np.inf
+    want = [int((~np.isfinite(a[b])).sum() + (~np.isfinite(c[b])).sum() + (~np.isfinite(m1[b])).sum()
+                + (~np.isfinite(m2[b])).sum()) for b in range(B) for a, c, m1, m2 in [(f, g, mf, mg)]]
+    assert want == [0, 3, 3]
+    checked = _run(dict(kw, check_finite=True), f, g, mf, mg)
+    plain = _run(kw, f, g, mf, mg)
+    got = [int(v) for v in checked["saved"][:, fmbym.FMBYM_SAVED_STATUS].cpu()]
+    print("non-finite counts", got, flush=True)
+    assert got == want
+    for k in ("pose", "c_theta", "c_xy"):
+        assert torch.equal(checked[k][0], plain[k][0]), k
