@@ -142,12 +142,29 @@ class MaskedSearchTrainer:
         return st.get("extra", {})
 
     @torch.no_grad()
-    def predict(self, f, g):
-        """Poses with the policy: the masked search once it has won, else the unmasked one."""
-        if self.use_mask:
-            m_f, m_g = self.masks(f, g, training=False)
-            return self.search.forward(f, g, m_f, m_g, surfaces=False)["pose"]
-        return self.search.forward(f, g, surfaces=False)["pose"]
+    def predict(self, f, g, min_mask_mean: float = 1e-3):
+        """Poses with the policy: the masked search once it has won, else the
+        unmasked one; and per pair, the unmasked pose wherever the network has
+        all but blanked a scan (mask mean below min_mask_mean)."""
+        if not self.use_mask:
+            return self.search.forward(f, g, surfaces=False)["pose"]
+        m_f, m_g = self.masks(f, g, training=False)
+        masked = self.search.forward(f, g, m_f, m_g, surfaces=False)["pose"]
+        blank = blank_masks(m_f.mean(dim=(1, 2)), m_g.mean(dim=(1, 2)), min_mask_mean)
+        if not bool(blank.any()):
+            return masked
+        plain = self.search.forward(f, g, surfaces=False)["pose"]
+        return fallback_poses(masked, plain, blank)
+
+
+def blank_masks(mean_f, mean_g, min_mean: float):
+    """Pairs whose mask of either scan has a mean below min_mean [B] bool."""
+    return (mean_f < min_mean) | (mean_g < min_mean)
+
+
+def fallback_poses(masked, plain, blank):
+    """The masked poses, with the unmasked pose in the rows flagged blank."""
+    return torch.where(blank[:, None], plain, masked)
 
 
 def check_state(st: dict, n_params: int, n_bn: int) -> None:

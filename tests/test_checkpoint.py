@@ -46,3 +46,18 @@ def test_malformed_states_are_refused():
     del bad["adam_step"]
     with pytest.raises(ValueError):
         train.check_state(bad, 1000, 64)
+
+
+def test_blank_mask_fallback_policy():
+    """A pair whose network output has all but blanked a scan falls back to
+    the unmasked pose; the other pairs keep the masked one."""
+    masked = torch.tensor([[0.1, 1.0, 2.0], [0.2, 3.0, 4.0], [0.3, 5.0, 6.0]])
+    plain = torch.tensor([[9.1, 9.0, 9.0], [9.2, 9.0, 9.0], [9.3, 9.0, 9.0]])
+    m_f = torch.rand(3, 8, 8) * 0.5 + 0.25
+    m_g = m_f.clone()
+    m_g[1].zero_()                      # forced zero mask on pair 1's second scan
+    blank = train.blank_masks(m_f.mean(dim=(1, 2)), m_g.mean(dim=(1, 2)), 1e-3)
+    assert blank.tolist() == [False, True, False]
+    out = train.fallback_poses(masked, plain, blank)
+    assert torch.equal(out[0], masked[0]) and torch.equal(out[2], masked[2])
+    assert torch.equal(out[1], plain[1])
