@@ -5,6 +5,7 @@
 #include <new>
 
 #include "internal.hpp"
+#include "profile.hpp"
 
 using namespace fmbym;
 
@@ -147,6 +148,7 @@ size_t fmbym_search_workspace_size(fmbym_plan plan, int32_t batch, int with_back
 int fmbym_search(fmbym_plan plan, int32_t batch, const float* f, const float* g, const float* m_f,
                  const float* m_g, float* pose, float* c_theta, float* c_xy, float* saved,
                  void* workspace, size_t workspace_bytes, void* stream) {
+    const TraceRange trace_range("fmbym_search");
     int rc = check_call(plan, batch);
     if (rc) return rc;
     if (!f || !g || !pose) return FMBYM_EINVAL;
@@ -165,6 +167,7 @@ int fmbym_search_backward(fmbym_plan plan, int32_t batch, const float* f, const 
                           const float* c_theta, const float* c_xy, const float* saved,
                           const float* d_pose, float* d_f, float* d_g, float* d_m_f, float* d_m_g,
                           void* workspace, size_t workspace_bytes, void* stream) {
+    const TraceRange trace_range("fmbym_search_backward");
     int rc = check_call(plan, batch);
     if (rc) return rc;
     if (!f || !g || !pose || !c_theta || !c_xy || !saved || !d_pose || !d_f || !d_g)
@@ -204,6 +207,7 @@ size_t fmbym_joint_workspace_size(fmbym_plan plan, int32_t batch, int32_t n_angl
 int fmbym_search_joint(fmbym_plan plan, int32_t batch, int32_t n_angles, const float* f, const float* g,
                        const float* m_f, const float* m_g, float* pose, float* peak, void* workspace,
                        size_t workspace_bytes, void* stream) {
+    const TraceRange trace_range("fmbym_search_joint");
     int rc = check_call(plan, batch);
     if (rc) return rc;
     if (n_angles < 1 || n_angles > 4096 || !f || !g || !pose) return FMBYM_EINVAL;
@@ -225,6 +229,7 @@ size_t fmbym_full_circle_workspace_size(fmbym_plan plan, int32_t batch) {
 int fmbym_search_full_circle(fmbym_plan plan, int32_t batch, const float* f, const float* g,
                              const float* m_f, const float* m_g, float* pose, float* peaks, void* workspace,
                              size_t workspace_bytes, void* stream) {
+    const TraceRange trace_range("fmbym_search_full_circle");
     int rc = check_call(plan, batch);
     if (rc) return rc;
     if (!f || !g || !pose) return FMBYM_EINVAL;
@@ -246,6 +251,7 @@ int fmbym_search_train(fmbym_plan plan, int32_t batch, const float* f, const flo
                        const float* m_g, float* pose, float* c_theta, float* c_xy, float* saved,
                        void* state, size_t state_bytes, void* workspace, size_t workspace_bytes,
                        void* stream) {
+    const TraceRange trace_range("fmbym_search_train");
     int rc = check_call(plan, batch);
     if (rc) return rc;
     if (!f || !g || !pose || !c_theta || !c_xy || !saved) return FMBYM_EINVAL;
@@ -267,6 +273,7 @@ int fmbym_search_backward_state(fmbym_plan plan, int32_t batch, const float* f, 
                                 const void* state, size_t state_bytes, const float* d_pose, float* d_f,
                                 float* d_g, float* d_m_f, float* d_m_g, void* workspace,
                                 size_t workspace_bytes, void* stream) {
+    const TraceRange trace_range("fmbym_search_backward_state");
     int rc = check_call(plan, batch);
     if (rc) return rc;
     if (!f || !g || !pose || !c_theta || !c_xy || !saved || !d_pose || !d_f || !d_g)

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "internal.hpp"
+#include "profile.hpp"
 #include "mask_kernels.hpp"
 #include "mask_net.hpp"
 
@@ -213,6 +214,7 @@ size_t fmbym_mask_bn_channels(const fmbym_mask_desc* d) {
 }
 
 int fmbym_mask_pack(const fmbym_mask_desc* d, void* stream) {
+    const TraceRange trace_range("fmbym_mask_pack");
     Net net;
     if (!build_net(d, net)) return FMBYM_EUNSUPPORTED;
     if (!d->params || !d->packed) return FMBYM_EINVAL;
@@ -248,11 +250,13 @@ size_t fmbym_mask_workspace_bytes(const fmbym_mask_desc* d, int32_t images, int3
 
 int fmbym_mask_fwd(const fmbym_mask_desc* d, int32_t I, int32_t n, const float* x, float* mask, void* act,
                    size_t act_bytes, int training, void* stream) {
+    const TraceRange trace_range("fmbym_mask_fwd");
     return mask_forward(d, I, n, x, nullptr, mask, act, act_bytes, training, (hipStream_t)stream);
 }
 
 int fmbym_mask_bwd(const fmbym_mask_desc* d, int32_t I, int32_t n, const float* d_mask, const void* act,
                    size_t act_bytes, float* d_params, void* ws, size_t ws_bytes, void* stream) {
+    const TraceRange trace_range("fmbym_mask_bwd");
     Net net;
     if (!d) return FMBYM_EINVAL;
     if (!build_net(d, net)) return FMBYM_EUNSUPPORTED;
@@ -319,6 +323,7 @@ int fmbym_mask_bwd(const fmbym_mask_desc* d, int32_t I, int32_t n, const float* 
 
 int fmbym_adam(float* params, const float* grad, float* m, float* v, int64_t count, int32_t step, float lr,
                float beta1, float beta2, float eps, void* stream) {
+    const TraceRange trace_range("fmbym_adam");
     if (!params || !grad || !m || !v || count < 1 || step < 1) return FMBYM_EINVAL;
     if (!(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
         return FMBYM_EINVAL;
@@ -331,6 +336,7 @@ int fmbym_adam(float* params, const float* grad, float* m, float* v, int64_t cou
 
 int fmbym_pose_loss(int32_t batch, const float* pose, const float* target, int32_t kind, float* loss,
                     float* d_pose, void* stream) {
+    const TraceRange trace_range("fmbym_pose_loss");
     if (batch < 1 || !pose || !target || !loss || !d_pose) return FMBYM_EINVAL;
     if (kind != FMBYM_LOSS_L1 && kind != FMBYM_LOSS_L2) return FMBYM_EINVAL;
     hipStream_t s = (hipStream_t)stream;

@@ -3,6 +3,7 @@
 // by fmbym_profile_enable, so the search calls still allocate nothing.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 namespace fmbym {
 
@@ -19,6 +20,17 @@ extern const char* const kKernelNames[kKernelCount];
 
 void prof_before(hipStream_t s, int id);
 void prof_after(hipStream_t s, int id);
+
+// A named range on the host timeline (roctx) for the lifetime of the object:
+// every entry point opens one, so a marker trace (rocprofv3 --marker-trace)
+// shows which call enqueued which kernels.  Costs nothing measurable when no
+// tool is attached.
+struct TraceRange {
+    explicit TraceRange(const char* name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange&) = delete;
+    TraceRange& operator=(const TraceRange&) = delete;
+};
 
 // While alive, launches on this thread are not timed (used around graph capture).
 struct ProfilePause {

@@ -278,6 +278,7 @@ int fmbym_ragged_create(const fmbym_plan* plans, int32_t n_plans, const fmbym_pa
 }
 
 int fmbym_ragged_launch(fmbym_ragged rg, void* stream) {
+    const TraceRange trace_range("fmbym_ragged_launch");
     if (!rg) return FMBYM_EINVAL;
     Ragged* r = reinterpret_cast<Ragged*>(rg);
     hipError_t e = hipGraphLaunch(r->exec, (hipStream_t)stream);
