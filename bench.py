@@ -28,6 +28,8 @@ BF16_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 matrix cores, vendor figure
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_batch512.txt")
+CPU_SECONDS = 10.0          # the CPU baseline keeps adding pairs until this much time has gone
+PROFILE_STEPS = 50          # steps of the event-timed per-kernel pass (its event pool grows with them)
 
 
 def source_digest() -> str:
@@ -135,8 +137,8 @@ def kernel_bytes(n: int, n_theta: int, n_r: int, batch: int, masked: bool, keep:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="batch512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pairs", type=int, default=4)
@@ -225,13 +227,14 @@ def train_bench(args) -> int:
     ev1.record()
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / args.steps
-    fmbym.profile_enable(args.steps * 600)
-    for i in range(args.steps):
+    psteps = min(args.steps, PROFILE_STEPS)
+    fmbym.profile_enable(psteps * 600)
+    for i in range(psteps):
         step(i)
     torch.cuda.synchronize()
     prof = fmbym.profile_read()
     fmbym.profile_enable(0)
-    per_step = {k: t / args.steps for k, (t, c) in prof.items()}
+    per_step = {k: t / psteps for k, (t, c) in prof.items()}
     dom = max(per_step, key=per_step.get)
     mk = mask_kernel_model(2 * B, n, levels)
     sb = kernel_bytes(n, kw["n_theta"], n, B, masked=True, keep=True)
@@ -262,15 +265,19 @@ def train_bench(args) -> int:
         from oracle import mask_oracle as M
         from paper_2203_00459_amd.train import he_init
         th = torch.from_numpy(he_init(levels, 8, 0)).double().requires_grad_(True)
+        done = 0
         t0 = time.perf_counter()
-        X = torch.from_numpy(np.stack([f[0], g[0]])).double()
-        m = M.forward(X, th, levels, 8)
-        pose = O.search(f[0], g[0], O.Params(**kw), m[0], m[1])["pose"]
-        M.pose_loss(pose[None], torch.from_numpy(p[:1]).double(), "l2").backward()
+        while done < B and (done < 1 or time.perf_counter() - t0 < CPU_SECONDS):
+            X = torch.from_numpy(np.stack([f[done], g[done]])).double()
+            m = M.forward(X, th, levels, 8)
+            pose = O.search(f[done], g[done], O.Params(**kw), m[0], m[1])["pose"]
+            M.pose_loss(pose[None], torch.from_numpy(p[done:done + 1]).double(), "l2").backward()
+            done += 1
         dt = time.perf_counter() - t0
-        res["cpu_baseline"] = {"value": 1.0 / dt, "unit": "pairs/s", "cores": torch.get_num_threads(), "cpu": cpu_model(),
+        res["cpu_baseline"] = {"value": done / dt, "unit": "pairs/s", "cores": torch.get_num_threads(), "cpu": cpu_model(),
                                "kind": "oracle",
-                               "sample": "1 pair: FP64 oracle mask network + masked search + L2 loss, autograd"}
+                               "sample": f"{done} pairs (about {CPU_SECONDS:.0f} s): FP64 oracle mask network + "
+                                         "masked search + L2 loss, autograd"}
     print(json.dumps(res), flush=True)
     return 0
 
@@ -332,7 +339,7 @@ def drive_bench(args) -> int:
         p = O.Params(**kw)
         t0 = time.perf_counter()
         done = 0
-        while done < P and (done < 2 or time.perf_counter() - t0 < 10.0):
+        while done < P and (done < 2 or time.perf_counter() - t0 < CPU_SECONDS):
             O.search(scans_np[done], scans_np[done + 1], p)
             done += 1
         dt = time.perf_counter() - t0
@@ -413,17 +420,24 @@ def ragged_bench(args) -> int:
     }
     if not args.no_cpu_baseline:
         from oracle import fmbym_oracle as O
-        t_pair = {}
-        for k in sizes:
-            p = O.Params(**workloads.search_kwargs(k))
-            f, g = scans[k][0][0].cpu().numpy(), scans[k][1][0].cpu().numpy()
-            t0 = time.perf_counter()
-            O.search(f, g, p)
-            t_pair[k] = time.perf_counter() - t0
-        mean_t = sum(counts[k] * t_pair[k] for k in sizes) / cfg["n_pairs"]
+        # rounds of one pair of each size until about CPU_SECONDS of work; per-size
+        # mean times weighted by the mix
+        spent = {k: 0.0 for k in sizes}
+        rounds = 0
+        t_all = time.perf_counter()
+        while rounds < min(counts.values()) and (rounds < 1 or time.perf_counter() - t_all < CPU_SECONDS):
+            for k in sizes:
+                p = O.Params(**workloads.search_kwargs(k))
+                f, g = scans[k][0][rounds].cpu().numpy(), scans[k][1][rounds].cpu().numpy()
+                t0 = time.perf_counter()
+                O.search(f, g, p)
+                spent[k] += time.perf_counter() - t0
+            rounds += 1
+        mean_t = sum(counts[k] * spent[k] / rounds for k in sizes) / cfg["n_pairs"]
         res["cpu_baseline"] = {"value": 1.0 / mean_t, "unit": "pairs/s", "cores": torch.get_num_threads(), "cpu": cpu_model(),
                                "kind": "oracle",
-                               "sample": "one pair of each size, FP64 oracle forward, weighted by the mix"}
+                               "sample": f"{rounds} pair(s) of each size (about {CPU_SECONDS:.0f} s), FP64 oracle "
+                                         "forward, weighted by the mix"}
     print(json.dumps(res), flush=True)
     r.close()
     return 0
@@ -485,9 +499,19 @@ def search_bench(args) -> int:
         return ev0.elapsed_time(ev1) / args.steps
 
     ms = timed(with_bwd)
+    # per-step times from events between the steps, in a pass of its own (the
+    # mean above has no events inside its timed region)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    evs[0].record()
+    for i in range(args.steps):
+        step(with_bwd)
+        evs[i + 1].record()
+    torch.cuda.synchronize()
+    per_step = sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps))
+    ms_median = per_step[len(per_step) // 2]
     # the adjoint that recomputes the spectra (fmbym_search + fmbym_search_backward), same step
     ms_recompute = timed(False) if with_bwd else None
-    extra = {}
+    extra = {"ms_per_step_median": ms_median, "ms_per_step_p90": per_step[(9 * len(per_step)) // 10]}
     if mode == "fwd" and B == 1:
         # one pair: a captured launch (one HIP graph replay per pair)
         r = fmbym.Ragged([s], [(f[0], g[0])], stamps=False)
@@ -573,8 +597,8 @@ def search_bench(args) -> int:
     fmbym.plan_set_tuning(s.plan, dict(tuning, split=1))
     for _ in range(2):
         step()
-    fmbym.profile_enable(args.steps * 96)
-    for _ in range(args.steps):
+    fmbym.profile_enable(min(args.steps, PROFILE_STEPS) * 96)
+    for _ in range(min(args.steps, PROFILE_STEPS)):
         step()
     torch.cuda.synchronize()
     prof = fmbym.profile_read()
@@ -631,17 +655,21 @@ def search_bench(args) -> int:
     if not args.no_cpu_baseline:
         from oracle import fmbym_oracle as O
         p = O.Params(**kw)
-        k = min(args.cpu_pairs, B)
+        # at least --cpu-pairs runs, then more until about CPU_SECONDS of work,
+        # cycling over the batch's pairs (at most four passes)
+        k = 0
         t0 = time.perf_counter()
-        for b in range(k):
+        while k < 4 * B and (k < args.cpu_pairs or time.perf_counter() - t0 < CPU_SECONDS):
+            b = k % B
             if with_bwd:
                 O.search_grad(f_np[b], g_np[b], [1.0, 1.0, 1.0], p)
             else:
                 O.search(f_np[b], g_np[b], p)
+            k += 1
         dt = time.perf_counter() - t0
         res["cpu_baseline"] = {"value": k / dt, "unit": "pairs/s", "cores": torch.get_num_threads(), "cpu": cpu_model(),
                                "kind": "oracle",
-                               "sample": f"{k} of the {B} pairs, FP64 oracle "
+                               "sample": f"{k} oracle runs over {min(k, B)} of the {B} pairs, FP64 oracle "
                                          f"{'forward + autograd backward' if with_bwd else 'forward'}"}
     print(json.dumps(res), flush=True)
     return 0
