@@ -71,6 +71,10 @@ def _case(case):
         kw.update(n_theta=64, temp_theta=20.0, temp_xy=2.0)
     if case == "unwindowed_xy":
         kw.update(xy_unwindowed=True)
+    if case == "theta16":
+        kw.update(n_theta=16, temp_theta=20.0)
+    if case == "theta1024":
+        kw.update(n_theta=1024, temp_theta=2.0)
     B = 2
     f, g, _ = synth.make_batch(name, B, split="val", start=3)
     mf = mg = None
@@ -81,7 +85,7 @@ def _case(case):
     return kw, f, g, mf, mg
 
 
-CASES = ["plain", "masked", "unwindowed_xy", "n256_theta64"]
+CASES = ["plain", "masked", "unwindowed_xy", "n256_theta64", "theta16", "theta1024"]
 
 
 @pytest.mark.parametrize("case", CASES)

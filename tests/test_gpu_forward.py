@@ -53,7 +53,8 @@ def _run(kw, f, g, mf=None, mg=None, max_batch=None):
     return out
 
 
-@pytest.mark.parametrize("case", ["pair128", "ragged", "masked", "n256_theta64_nohann", "unwindowed_xy"])
+@pytest.mark.parametrize("case", ["pair128", "ragged", "masked", "n256_theta64_nohann", "unwindowed_xy",
+                                  "theta16", "theta1024_r512"])
 def test_forward_small_cases(case):
     print(f"case {case}", flush=True)
     kw = workloads.search_kwargs("pair128")
@@ -71,6 +72,12 @@ def test_forward_small_cases(case):
         B = 2
     elif case == "unwindowed_xy":
         kw.update(xy_unwindowed=True, temp_theta=3.0)
+        B = 2
+    elif case == "theta16":               # the smallest angle grid: one radius block holds 128 radii
+        kw.update(n_theta=16, temp_theta=3.0)
+        B = 2
+    elif case == "theta1024_r512":        # the largest angle grid, radii denser than the scan's
+        kw.update(n_theta=1024, n_r=512)
         B = 2
     f, g, _ = synth.make_batch(name, B, split="val", start=7)
     if case == "masked":
