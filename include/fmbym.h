@@ -76,7 +76,8 @@ extern "C" {
 #define FMBYM_SAVED_THETA_MEAN 9  /* mean heading score over all lags                     */
 #define FMBYM_SAVED_THETA_ARG 10  /* lag l* of the largest heading score (lowest on ties) */
 #define FMBYM_SAVED_THETA_NU 11   /* sum_l p_l (l - l*): theta = (l* + nu) pi / n_theta   */
-#define FMBYM_SAVED_STATUS 12     /* with FMBYM_CHECK_FINITE: count of non-finite inputs */
+#define FMBYM_SAVED_STATUS 12     /* with FMBYM_CHECK_FINITE: count of non-finite inputs,
+                                     else 0; slots 13 .. 15 are reserved and written as 0 */
 
 typedef struct fmbym_plan_s* fmbym_plan;
 

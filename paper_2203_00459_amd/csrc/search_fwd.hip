@@ -351,6 +351,9 @@ __global__ __launch_bounds__(kAngleGroups * NT / kE) void k_angle_fin(
         sv[kSavedThetaMean] = dc * scale;
         sv[kSavedThetaArg] = (float)lag_star;
         sv[kSavedThetaNu] = nu;
+        // the status slot (set afterwards when the inputs are checked) and the
+        // reserved slots are defined too
+        for (int i = kSavedStatus; i < FMBYM_SAVED; ++i) sv[i] = 0.f;
     }
 }
 
@@ -861,12 +864,6 @@ static int launch_n(const Plan& pl, int B, const float* f, const float* g, const
     float2* pth = (float2*)(ws + lay.ptheta);
     float4* pxy = (float4*)(ws + lay.pxy);
     float* sv = saved ? saved : (float*)(ws + lay.saved);
-    if (pl.p.flags & FMBYM_CHECK_FINITE) {
-        int* counts = (int*)(ws + lay.fin);
-        FMBYM_LAUNCH(kKFinite, k_finite_part, dim3(B * kFiniteSlices), dim3(256), s, f, g, mf, mg, N, counts,
-                     tab);
-        FMBYM_LAUNCH(kKFinite, k_finite_fin, dim3((B + 63) / 64), dim3(64), s, counts, B, sv);
-    }
     launch_stage1_rows_cols<N>(pl, B, f, g, mf, mg, r1, mag, s, tab);
     switch (pl.p.n_theta) {
         case 16: launch_polar<N, 16>(pl, B, mag, pth, c_theta, pose, sv, s, keep ? keep->pspec : nullptr); break;
@@ -881,6 +878,12 @@ static int launch_n(const Plan& pl, int B, const float* f, const float* g, const
     stage2_n<N>(pl, B, f, g, mf, mg, sv, c_xy, ws, s, tab, keep);
     FMBYM_LAUNCH(kKXyFin, k_xy_fin, dim3(B), dim3(64), s, pxy, xy_partials_per_pair(N), pl.p.temp_xy,
                  pl.p.delta_xy, pose, sv);
+    if (pl.p.flags & FMBYM_CHECK_FINITE) {   // after k_angle_fin, which clears the status slot
+        int* counts = (int*)(ws + lay.fin);
+        FMBYM_LAUNCH(kKFinite, k_finite_part, dim3(B * kFiniteSlices), dim3(256), s, f, g, mf, mg, N, counts,
+                     tab);
+        FMBYM_LAUNCH(kKFinite, k_finite_fin, dim3((B + 63) / 64), dim3(64), s, counts, B, sv);
+    }
     return FMBYM_OK;
 }
 

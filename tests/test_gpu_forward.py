@@ -157,3 +157,30 @@ def test_check_finite_counts_non_finite_inputs():
     assert got == want
     for k in ("pose", "c_theta", "c_xy"):
         assert torch.equal(checked[k][0], plain[k][0]), k
+
+
+@pytest.mark.parametrize("check", [False, True])
+def test_every_saved_slot_is_written(check):
+    """The forward defines all FMBYM_SAVED slots of every pair: the statistics,
+    the status slot (0 without FMBYM_CHECK_FINITE, the count with it) and the
+    reserved slots (0), whatever the buffer held before (NaN here)."""
+    kw = dict(workloads.search_kwargs("pair128"), check_finite=check)
+    B, n = 3, kw["n"]
+    f, g, _ = synth.make_batch("pair128", B, split="val", start=5)
+    dev = torch.device("cuda:0")
+    s = fmbym.Search(max_batch=B, **kw)
+    F, G = torch.from_numpy(f).to(dev), torch.from_numpy(g).to(dev)
+    pose = torch.empty(B, 3, device=dev)
+    saved = torch.full((B, fmbym.FMBYM_SAVED), float("nan"), device=dev)
+    ws = s.workspace(B, False, dev)
+    fmbym.search(s.plan, B, F.data_ptr(), G.data_ptr(), None, None, pose.data_ptr(), None, None,
+                 saved.data_ptr(), ws.data_ptr(), ws.numel(), torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    sv = saved.cpu()
+    print(f"check_finite={check} saved[0] = {sv[0].tolist()}", flush=True)
+    assert bool(torch.isfinite(sv).all())
+    assert bool((sv[:, fmbym.FMBYM_SAVED_STATUS:] == 0).all())
+    ref = s.forward(F, G, surfaces=False)
+    torch.cuda.synchronize()
+    assert torch.equal(ref["pose"], pose)
+    s.close()
