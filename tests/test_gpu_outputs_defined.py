@@ -1,11 +1,13 @@
-"""Every element of every output of the search entry points is written.
+"""Every element of every output of the search and mask-network entry points
+is written.
 
 Each output buffer is filled with NaN before its call through the C ABI; with
 finite inputs every element must come back finite.  This catches an output
 slot or a tail of rows or columns that a kernel leaves untouched, which a
 comparison of two calls can miss when both buffers happen to hold the same
-stale memory.  Sizes: three 128 x 128 pairs without masks, two 256 x 256
-pairs with masks."""
+stale memory.  Search sizes: three 128 x 128 pairs without masks, two
+256 x 256 pairs with masks; the mask network at 128 and 256.  The ragged
+launch's poses are checked the same way in its own test."""
 import numpy as np
 import pytest
 import torch
@@ -101,3 +103,36 @@ def test_every_output_element_is_written(name, B, masked):
     for k in fwd:
         assert torch.equal(fwd[k], trn[k]), k
     s.close()
+
+
+@pytest.mark.parametrize("n,images", [(128, 3), (256, 2)])
+def test_mask_network_outputs_are_written(n, images):
+    """fmbym_mask_fwd (masks), fmbym_mask_bwd (parameter gradients) and
+    fmbym_pose_loss (loss and its gradient), each into NaN-filled buffers."""
+    from paper_2203_00459_amd.train import he_init
+    print(f"mask network n={n} images={images}", flush=True)
+    stream = torch.cuda.current_stream().cuda_stream
+    net = fmbym.MaskNet(he_init(4, 8, 0), levels=4)
+    x = torch.from_numpy(np.random.default_rng(2).uniform(0, 1, (images, n, n)).astype(np.float32)).to(DEV)
+    act_bytes = fmbym.mask_activation_bytes(net.desc, images, n)
+    act = _bytes(act_bytes)
+    mask = _nan(images, n, n)
+    fmbym.mask_fwd(net.desc, images, n, x.data_ptr(), mask.data_ptr(), act.data_ptr(), act_bytes, True, stream)
+    d_mask = torch.from_numpy(np.random.default_rng(3).normal(size=(images, n, n)).astype(np.float32)).to(DEV)
+    ws_bytes = fmbym.mask_workspace_bytes(net.desc, images, n)
+    ws = _bytes(ws_bytes)
+    d_params = torch.full_like(net.params, float("nan"))
+    fmbym.mask_bwd(net.desc, images, n, d_mask.data_ptr(), act.data_ptr(), act_bytes, d_params.data_ptr(),
+                   ws.data_ptr(), ws_bytes, stream)
+    pose = torch.from_numpy(np.random.default_rng(4).normal(size=(images, 3)).astype(np.float32)).to(DEV)
+    target = torch.zeros(images, 3, device=DEV)
+    loss, d_pose = _nan(1), _nan(images, 3)
+    fmbym.pose_loss(images, pose.data_ptr(), target.data_ptr(), fmbym.FMBYM_LOSS_L1, loss.data_ptr(),
+                    d_pose.data_ptr(), stream)
+    torch.cuda.synchronize()
+    for k, v in dict(mask=mask, d_params=d_params, loss=loss, d_pose=d_pose).items():
+        bad = int((~torch.isfinite(v)).sum())
+        print(f"  {k}: {tuple(v.shape)} non-finite {bad}", flush=True)
+        assert bad == 0, k
+    # the same masks as the binding's own call
+    assert torch.equal(net.forward(x, training=True), mask)
