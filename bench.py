@@ -480,8 +480,13 @@ def search_bench(args) -> int:
         torch.cuda.synchronize()
         del src, dst
 
-    def step(keep=with_bwd):
-        # the training pair: the forward keeps its intermediates, the adjoint reads them
+    def step(keep=with_bwd, fused=True):
+        # the training forward keeps its intermediates and the adjoint reads them;
+        # fused: both in one fmbym_search_vjp call (each half of the batch runs
+        # both passes on its stream, one fork and join), else the two calls
+        if with_bwd and keep and fused:
+            s.vjp(f, g, None, None, d_pose)
+            return
         o = s.forward(f, g, keep=keep)
         if with_bwd:
             s.backward(f, g, None, None, o, d_pose)
@@ -512,6 +517,21 @@ def search_bench(args) -> int:
     # the adjoint that recomputes the spectra (fmbym_search + fmbym_search_backward), same step
     ms_recompute = timed(False) if with_bwd else None
     extra = {"ms_per_step_median": ms_median, "ms_per_step_p90": per_step[(9 * len(per_step)) // 10]}
+    if with_bwd:
+        # the same step as the two calls fmbym_search_train + fmbym_search_backward_state
+        # (two forks and joins per step)
+        for _ in range(args.warmup):
+            step(True, fused=False)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            step(True, fused=False)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_pair = e0.elapsed_time(e1) / args.steps
+        extra["training_pair_path"] = {"ms_per_step": ms_pair, "value": B / (ms_pair * 1e-3), "unit": "pairs/s",
+                                       "calls": "fmbym_search_train, fmbym_search_backward_state"}
     if mode == "fwd" and B == 1:
         # one pair: a captured launch (one HIP graph replay per pair)
         r = fmbym.Ragged([s], [(f[0], g[0])], stamps=False)
@@ -632,7 +652,8 @@ def search_bench(args) -> int:
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "batch": B, "n": n, "n_theta": nt,
-                   "pass": "fwd+bwd (forward keeps its intermediates for the adjoint)" if with_bwd else mode},
+                   "pass": "fwd+bwd, one fmbym_search_vjp call per step (the forward keeps its "
+                           "intermediates for the adjoint)" if with_bwd else mode},
         "roofline": {"bound": "hbm", "kernel": dom, "launch": "whole batch, unsplit (per-kernel pass)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": None if achieved is None else achieved / HBM_PEAK_GBS,

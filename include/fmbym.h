@@ -192,6 +192,21 @@ FMBYM_API int fmbym_search_backward_state(fmbym_plan plan, int32_t batch, const 
                                           float* d_m_g, void* workspace, size_t workspace_bytes,
                                           void* stream);
 
+/* Training forward and its adjoint in one call, for an upstream gradient d_pose
+ * the caller already holds (a vector-Jacobian product of the search): the
+ * results of fmbym_search_train followed by fmbym_search_backward_state on the
+ * same buffers, bit for bit.  With the plan's split = 2 each half of the batch
+ * runs both passes on its own stream, forked and joined once for the pair
+ * (the two calls fork and join twice).  Arguments as for those two calls; the
+ * workspace is that of fmbym_search_workspace_size(plan, batch, 1).  d_pose
+ * must not depend on this call's pose (for a loss of the pose, use the two
+ * calls with the loss in between). */
+FMBYM_API int fmbym_search_vjp(fmbym_plan plan, int32_t batch, const float* f, const float* g,
+                               const float* m_f, const float* m_g, float* pose, float* c_theta,
+                               float* c_xy, float* saved, void* state, size_t state_bytes,
+                               const float* d_pose, float* d_f, float* d_g, float* d_m_f, float* d_m_g,
+                               void* workspace, size_t workspace_bytes, void* stream);
+
 /* ---------------------------------------------------------------- joint comparator
  *
  * The exhaustive search that the decoupling replaces (Eq. 2-3 with the heading

@@ -292,6 +292,28 @@ int fmbym_search_backward_state(fmbym_plan plan, int32_t batch, const float* f, 
     return e == hipSuccess ? FMBYM_OK : hip_fail(e);
 }
 
+int fmbym_search_vjp(fmbym_plan plan, int32_t batch, const float* f, const float* g, const float* m_f,
+                     const float* m_g, float* pose, float* c_theta, float* c_xy, float* saved, void* state,
+                     size_t state_bytes, const float* d_pose, float* d_f, float* d_g, float* d_m_f,
+                     float* d_m_g, void* workspace, size_t workspace_bytes, void* stream) {
+    const TraceRange trace_range("fmbym_search_vjp");
+    int rc = check_call(plan, batch);
+    if (rc) return rc;
+    if (!f || !g || !pose || !c_theta || !c_xy || !saved || !d_pose || !d_f || !d_g) return FMBYM_EINVAL;
+    if ((m_f == nullptr) != (m_g == nullptr)) return FMBYM_EINVAL;
+    if ((m_f == nullptr) != (d_m_f == nullptr) || (m_g == nullptr) != (d_m_g == nullptr))
+        return FMBYM_EINVAL;
+    const Plan* pl = plan_cast(plan);
+    if (!state || state_bytes < keep_bytes(pl->p, batch)) return FMBYM_EWORKSPACE;
+    if (!workspace || workspace_bytes < run_bwd_workspace(*pl, batch)) return FMBYM_EWORKSPACE;
+    const Keep keep = keep_pointers(pl->p, batch, state);
+    rc = run_vjp(*pl, batch, f, g, m_f, m_g, pose, c_theta, c_xy, saved, d_pose, d_f, d_g, d_m_f, d_m_g,
+                 (char*)workspace, (hipStream_t)stream, keep);
+    if (rc) return rc;
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? FMBYM_OK : hip_fail(e);
+}
+
 const char* fmbym_strerror(int code) {
     switch (code) {
         case FMBYM_OK: return "success";

@@ -186,6 +186,10 @@ int run_backward(const Plan& pl, int batch, const float* f, const float* g, cons
                  const float* mg, const float* pose, const float* c_theta, const float* c_xy,
                  const float* saved, const float* d_pose, float* d_f, float* d_g, float* d_mf, float* d_mg,
                  char* ws, hipStream_t s, const Keep* keep_full);
+// Training forward then adjoint per half of the batch, one fork and join.
+int run_vjp(const Plan& pl, int batch, const float* f, const float* g, const float* mf, const float* mg,
+            float* pose, float* c_theta, float* c_xy, float* saved, const float* d_pose, float* d_f,
+            float* d_g, float* d_mf, float* d_mg, char* ws, hipStream_t s, const Keep& keep_full);
 size_t run_full_circle_workspace(const Plan& pl, int batch);
 int run_full_circle(const Plan& pl, int batch, const float* f, const float* g, const float* mf,
                     const float* mg, float* pose, float* peaks, char* ws, hipStream_t s);

@@ -115,4 +115,25 @@ int run_backward(const Plan& pl, int batch, const float* f, const float* g, cons
     });
 }
 
+int run_vjp(const Plan& pl, int batch, const float* f, const float* g, const float* mf, const float* mg,
+            float* pose, float* c_theta, float* c_xy, float* saved, const float* d_pose, float* d_f,
+            float* d_g, float* d_mf, float* d_mg, char* ws, hipStream_t s, const Keep& keep_full) {
+    const size_t n2 = (size_t)pl.p.n * pl.p.n;
+    // a half's adjoint follows its own forward on its stream: the region sized
+    // for the adjoint holds the forward's workspace too
+    return run_halves(pl, batch, s, bwd_ws, [&](int b0, int nb, hipStream_t st, size_t off) {
+        const Keep k = keep_slice(keep_full, pl.p, b0);
+        int rc = launch_forward(pl, nb, at_pair(f, b0, n2), at_pair(g, b0, n2), at_pair(mf, b0, n2),
+                                at_pair(mg, b0, n2), at_pair(pose, b0, 3), at_pair(c_theta, b0, pl.p.n_theta),
+                                at_pair(c_xy, b0, n2), at_pair(saved, b0, FMBYM_SAVED), ws + off, st, nullptr,
+                                &k);
+        if (rc) return rc;
+        return launch_backward(pl, nb, at_pair(f, b0, n2), at_pair(g, b0, n2), at_pair(mf, b0, n2),
+                               at_pair(mg, b0, n2), at_pair(pose, b0, 3), at_pair(c_theta, b0, pl.p.n_theta),
+                               at_pair(c_xy, b0, n2), at_pair(saved, b0, FMBYM_SAVED), at_pair(d_pose, b0, 3),
+                               at_pair(d_f, b0, n2), at_pair(d_g, b0, n2), at_pair(d_mf, b0, n2),
+                               at_pair(d_mg, b0, n2), ws + off, st, &k);
+    });
+}
+
 }  // namespace fmbym

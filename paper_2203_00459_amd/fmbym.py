@@ -47,7 +47,7 @@ EXPORTS = (
     "fmbym_mask_param_count", "fmbym_mask_packed_bytes", "fmbym_mask_bn_channels", "fmbym_mask_pack",
     "fmbym_mask_activation_bytes", "fmbym_mask_fwd", "fmbym_mask_workspace_bytes", "fmbym_mask_bwd",
     "fmbym_adam", "fmbym_pose_loss", "fmbym_search_state_size", "fmbym_search_train",
-    "fmbym_search_backward_state", "fmbym_joint_workspace_size", "fmbym_search_joint",
+    "fmbym_search_backward_state", "fmbym_search_vjp", "fmbym_joint_workspace_size", "fmbym_search_joint",
     "fmbym_plan_get_tuning", "fmbym_plan_set_tuning", "fmbym_autotune_workspace_size", "fmbym_autotune",
     "fmbym_full_circle_workspace_size", "fmbym_search_full_circle",
 )
@@ -139,6 +139,8 @@ def lib() -> ctypes.CDLL:
         L.fmbym_search_train.restype = ctypes.c_int
         L.fmbym_search_backward_state.argtypes = [VP, I32] + [VP] * 8 + [VP, SZ] + [VP] * 5 + [VP, SZ, VP]
         L.fmbym_search_backward_state.restype = ctypes.c_int
+        L.fmbym_search_vjp.argtypes = [VP, I32] + [VP] * 8 + [VP, SZ] + [VP] * 5 + [VP, SZ, VP]
+        L.fmbym_search_vjp.restype = ctypes.c_int
         L.fmbym_strerror.argtypes = [ctypes.c_int]
         L.fmbym_strerror.restype = ctypes.c_char_p
         L.fmbym_last_hip_error.argtypes = []
@@ -306,6 +308,16 @@ def search_backward_state(plan, batch, f, g, m_f, m_g, pose, c_theta, c_xy, save
                                            workspace, int(workspace_bytes), stream)
     if rc:
         raise FmbymError(rc, "fmbym_search_backward_state")
+
+
+def search_vjp(plan, batch, f, g, m_f, m_g, pose, c_theta, c_xy, saved, state, state_bytes, d_pose, d_f, d_g,
+               d_m_f, d_m_g, workspace, workspace_bytes, stream) -> None:
+    """fmbym_search_vjp with raw device addresses (ints or None)."""
+    rc = lib().fmbym_search_vjp(plan, int(batch), f, g, m_f, m_g, pose, c_theta, c_xy, saved, state,
+                                int(state_bytes), d_pose, d_f, d_g, d_m_f, d_m_g, workspace,
+                                int(workspace_bytes), stream)
+    if rc:
+        raise FmbymError(rc, "fmbym_search_vjp")
 
 
 def profile_enable(capacity: int) -> None:
@@ -481,6 +493,26 @@ class Search:
                      _ptr(m_f, (B, n, n), "m_f"), _ptr(m_g, (B, n, n), "m_g"), _ptr(out["pose"]),
                      _ptr(out["c_theta"]), _ptr(out["c_xy"]), _ptr(out["saved"]), out["state"].data_ptr(),
                      need, ws.data_ptr(), ws.numel(), _stream())
+        return out
+
+    def vjp(self, f, g, m_f, m_g, d_pose) -> dict:
+        """Training forward and adjoint in one call for a given d_pose: the
+        outputs of forward(keep=True) and of backward on them, in one dict."""
+        B, n = f.shape[0], self.n
+        dev = f.device
+        need = search_state_size(self.plan, B)
+        out = dict(pose=torch.empty(B, 3, device=dev), c_theta=torch.empty(B, self.n_theta, device=dev),
+                   c_xy=torch.empty(B, n, n, device=dev), saved=torch.empty(B, FMBYM_SAVED, device=dev),
+                   state=torch.empty(need, dtype=torch.uint8, device=dev),
+                   d_f=torch.empty(B, n, n, device=dev), d_g=torch.empty(B, n, n, device=dev),
+                   d_m_f=None if m_f is None else torch.empty(B, n, n, device=dev),
+                   d_m_g=None if m_g is None else torch.empty(B, n, n, device=dev))
+        ws = self.workspace(B, True, dev)
+        search_vjp(self.plan, B, _ptr(f, (B, n, n), "f"), _ptr(g, (B, n, n), "g"),
+                   _ptr(m_f, (B, n, n), "m_f"), _ptr(m_g, (B, n, n), "m_g"), _ptr(out["pose"]),
+                   _ptr(out["c_theta"]), _ptr(out["c_xy"]), _ptr(out["saved"]), out["state"].data_ptr(), need,
+                   _ptr(d_pose.contiguous(), (B, 3), "d_pose"), _ptr(out["d_f"]), _ptr(out["d_g"]),
+                   _ptr(out["d_m_f"]), _ptr(out["d_m_g"]), ws.data_ptr(), ws.numel(), _stream())
         return out
 
     def backward(self, f, g, m_f, m_g, fwd: dict, d_pose) -> dict:

@@ -84,6 +84,8 @@ def test_calls_without_a_plan_are_rejected():
     assert L.fmbym_search_train(None, 1, *([None] * 8), None, 0, None, 0, None) == fmbym.FMBYM_EINVAL
     assert L.fmbym_search_backward_state(None, 1, *([None] * 8), None, 0, *([None] * 5), None, 0,
                                          None) == fmbym.FMBYM_EINVAL
+    assert L.fmbym_search_vjp(None, 1, *([None] * 8), None, 0, *([None] * 5), None, 0,
+                              None) == fmbym.FMBYM_EINVAL
     assert L.fmbym_plan_destroy(None) == fmbym.FMBYM_EINVAL
     p = fmbym.fmbym_params(*[GOOD[k] for k, _ in fmbym.fmbym_params._fields_])
     assert L.fmbym_plan_create(ctypes.byref(p), 1, None) == fmbym.FMBYM_EINVAL

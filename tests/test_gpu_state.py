@@ -68,3 +68,27 @@ def test_state_buffer_is_checked():
                            o["c_theta"].data_ptr(), o["c_xy"].data_ptr(), o["saved"].data_ptr(), st.data_ptr(),
                            need - 1, ws.data_ptr(), ws.numel(), fmbym._stream())
     s.close()
+
+
+@pytest.mark.parametrize("name,B,masked", [("pair128", 3, True), ("batch256", 3, False), ("batch512", 4, False)])
+@pytest.mark.parametrize("split", [1, 2])
+def test_vjp_equals_the_training_pair(name, B, masked, split):
+    """fmbym_search_vjp (forward and adjoint per half, one fork and join) gives
+    bit for bit what fmbym_search_train then fmbym_search_backward_state give."""
+    print(f"case {name} B={B} masked={masked} split={split}", flush=True)
+    s = fmbym.Search(max_batch=B, **workloads.search_kwargs(name))
+    fmbym.plan_set_tuning(s.plan, dict(fmbym.plan_get_tuning(s.plan), split=split))
+    f, g, mf, mg = _inputs(name, B, masked)
+    d_pose = torch.from_numpy(np.random.Generator(np.random.PCG64(7)).normal(size=(B, 3))
+                              .astype(np.float32)).to(DEV)
+    fwd = s.forward(f, g, mf, mg, keep=True)
+    grd = s.backward(f, g, mf, mg, fwd, d_pose)
+    ref = {**{k: v.clone() for k, v in fwd.items()}, **{k: None if v is None else v.clone() for k, v in grd.items()}}
+    out = s.vjp(f, g, mf, mg, d_pose)
+    torch.cuda.synchronize()
+    for k in ("pose", "c_theta", "c_xy", "saved", "d_f", "d_g", "d_m_f", "d_m_g"):   # state has padding
+        if ref[k] is None:
+            assert out[k] is None, k
+            continue
+        assert torch.equal(out[k], ref[k]), k
+    s.close()
