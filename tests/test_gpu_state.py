@@ -92,3 +92,35 @@ def test_vjp_equals_the_training_pair(name, B, masked, split):
             continue
         assert torch.equal(out[k], ref[k]), k
     s.close()
+
+
+def test_vjp_buffers_are_checked():
+    """fmbym_search_vjp rejects a state one byte short and a workspace one byte
+    short of the adjoint's (which it needs), before enqueueing anything."""
+    B = 2
+    s = fmbym.Search(max_batch=B, **workloads.search_kwargs("batch256"))
+    f, g, _, _ = _inputs("batch256", B, False)
+    n, nt = s.n, s.n_theta
+    o = {k: torch.empty(B, *sh, device=DEV) for k, sh in (("pose", (3,)), ("c_theta", (nt,)), ("c_xy", (n, n)),
+                                                          ("saved", (fmbym.FMBYM_SAVED,)), ("d_pose", (3,)),
+                                                          ("d_f", (n, n)), ("d_g", (n, n)))}
+    need = fmbym.search_state_size(s.plan, B)
+    st = torch.empty(need, dtype=torch.uint8, device=DEV)
+    ws_full = fmbym.search_workspace_size(s.plan, B, True)
+    ws = torch.empty(ws_full, dtype=torch.uint8, device=DEV)
+
+    def call(state_bytes, ws_bytes):
+        fmbym.search_vjp(s.plan, B, f.data_ptr(), g.data_ptr(), None, None, o["pose"].data_ptr(),
+                         o["c_theta"].data_ptr(), o["c_xy"].data_ptr(), o["saved"].data_ptr(), st.data_ptr(),
+                         state_bytes, o["d_pose"].data_ptr(), o["d_f"].data_ptr(), o["d_g"].data_ptr(), None,
+                         None, ws.data_ptr(), ws_bytes, fmbym._stream())
+
+    for state_bytes, ws_bytes in ((need - 1, ws_full), (need, ws_full - 1)):
+        with pytest.raises(fmbym.FmbymError) as e:
+            call(state_bytes, ws_bytes)
+        assert e.value.code == fmbym.FMBYM_EWORKSPACE
+    o["d_pose"].zero_()
+    call(need, ws_full)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(o["d_f"]).all())
+    s.close()
