@@ -1,5 +1,5 @@
-"""Host-side helpers of bench.py: the HBM-traffic lookup in the committed
-counter summary (CPU only)."""
+"""Host-side parts of bench.py: the HBM-traffic lookup in the committed
+counter summary and the refusal of more than one GPU (CPU only)."""
 import bench
 
 
@@ -27,3 +27,17 @@ def test_traffic_lookup_refuses_a_summary_of_other_sources(tmp_path, monkeypatch
                  f"{'kb_dmag':<34} {244:>10d} {7.0:>12.1f} {3.0:>12.1f} {0.02:>10.2f}\n")
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
     assert bench.measured_traffic("kb_dmag") is None
+
+
+def test_more_than_one_gpu_is_refused_before_any_device_work():
+    """--gpus N > 1 exits with status 2 and says why, before importing the
+    library or touching a device (runs on the CPU)."""
+    import os
+    import subprocess
+    import sys
+    here = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(here, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=here)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
+    assert r.stdout == ""
