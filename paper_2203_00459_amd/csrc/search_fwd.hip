@@ -9,7 +9,10 @@
 //   k_angle_fin  sum over radius blocks, inverse angular DFT -> c_theta,
 //                temperature softmax and soft-argmax -> theta (stays on device).
 // Stage 2 (translation, Eq. 9)
-//   k_rows2      f_w and g' = Rotate(g_w, theta) zero-padded to 2n, row DFTs.
+//   k_rotate     g' = Rotate(g_w, theta) through an LDS-staged source box.
+//   k_rows2      f_w and g' zero-padded to 3n/2 (the shortest length whose
+//                circular correlation equals the linear one on the searched
+//                lag window), row DFTs; 3n/4 + 1 unique columns kept.
 //   k_cols2      column DFTs of both, conj(F) G', inverse column DFT, keeping
 //                the n central lag rows.
 //   k_rows3      inverse row DFTs of two lag rows at a time -> c_xy, and
@@ -18,7 +21,7 @@
 //
 // Data between passes: row kernels write the two spectra they produce
 // interleaved (float4 per column), so a column tile of 8 reads 128-byte
-// segments; every row keeps all its unique columns (0 .. n/2 or 0 .. n), so
+// segments; every row keeps all its unique columns (0 .. n/2 or 0 .. 3n/4), so
 // column kernels treat every column alike.  All reductions are in a fixed
 // order; results are bitwise reproducible.
 #include "internal.hpp"

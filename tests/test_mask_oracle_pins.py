@@ -159,3 +159,166 @@ def test_pose_losses_and_adam_closed_forms():
 def test_init_is_deterministic(levels, base):
     a, b = M.init_params(levels, base, seed=3), M.init_params(levels, base, seed=3)
     assert a.dtype == np.float32 and a.size == M.param_count(levels, base) and np.array_equal(a, b)
+
+
+# ------------------------------------------------------------------ bf16 storage
+
+def _bf16_rne_bits(x32: np.ndarray) -> np.ndarray:
+    """Round float32 values to the nearest bfloat16 (8 significant bits), ties to
+    the even significand, by integer arithmetic on the IEEE-754 bit patterns:
+    add 0x7FFF plus the lowest kept bit, then clear the 16 dropped bits."""
+    u = x32.astype(np.float32).view(np.uint32).astype(np.uint64)
+    r = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return r.astype(np.uint32).view(np.float32)
+
+
+def test_bf16_rounds_to_nearest_even_on_chosen_values():
+    # (input, bfloat16 value): the significand keeps 8 bits (7 stored); ties go to
+    # the even significand; the stored value is that of the input rounded to FP32
+    # first (the GPU rounds its FP32 results), so 1 + 2^-8 + 2^-40 is a tie.
+    cases = [
+        (1.0 + 2.0 ** -9, 1.0),                          # below the half-way point
+        (1.0 + 2.0 ** -8, 1.0),                          # tie, 1.0 is even
+        (1.0 + 3 * 2.0 ** -8, 1.0 + 2.0 ** -6),          # tie, rounds up to the even neighbour
+        (1.0 + 2.0 ** -8 + 2.0 ** -20, 1.0 + 2.0 ** -7),  # just above the tie
+        (1.0 + 2.0 ** -8 + 2.0 ** -40, 1.0),             # FP32 rounding makes it a tie
+        (-(1.0 + 2.0 ** -8), -1.0),
+        (255.5, 256.0),                                  # 255 + 1/2 has 9 significant bits: tie to 256
+        (257.0, 256.0),                                  # tie between 256 and 258, 256 is even
+        (70000.0, 70144.0),                              # beyond the FP16 range, exact bf16 step 512
+        (2.0 ** -130, 2.0 ** -130),                      # subnormal, representable
+        (1.5 * 2.0 ** -133, 2.0 ** -132),                # subnormal tie goes to the even count 2
+        (2.0 ** -134, 0.0),                              # half the smallest subnormal: tie to zero
+        (3.0e38, 3.00405527047391e38),
+    ]
+    x = torch.tensor([c[0] for c in cases], dtype=DT)
+    got = M.bf16(x).tolist()
+    for (inp, want), g in zip(cases, got):
+        assert g == want, (inp, g, want)
+    assert torch.equal(M.bf16(x, on=False), x)
+
+
+def test_bf16_matches_bit_arithmetic_over_exponents():
+    r = _rng(11)
+    mant = r.random(200_000) + 1.0
+    expo = r.integers(-140, 120, size=mant.size).astype(np.float64)
+    sign = np.where(r.random(mant.size) < 0.5, -1.0, 1.0)
+    x32 = (sign * mant * np.exp2(expo)).astype(np.float32)
+    want = _bf16_rne_bits(x32).astype(np.float64)
+    got = M.bf16(torch.tensor(x32.astype(np.float64), dtype=DT)).numpy()
+    assert np.array_equal(got, want)
+
+
+def test_bf16_has_identity_derivative():
+    x = torch.tensor([1.0 + 2.0 ** -8, 3.3, -7.1], dtype=DT, requires_grad=True)
+    (M.bf16(x) * torch.tensor([1.0, 2.0, 3.0], dtype=DT)).sum().backward()
+    assert torch.equal(x.grad, torch.tensor([1.0, 2.0, 3.0], dtype=DT))
+
+
+# ------------------------------------------ running statistics and inference mode
+
+def _delta_net(levels, base, scale_a, scale_b, gam, bet, head_w, head_b):
+    """Flat parameters of a one-level, one-channel net whose convolutions are
+    centre taps: enc0a multiplies by scale_a, enc0b by scale_b, the head by head_w."""
+    assert (levels, base) == (1, 1)
+    def tap(s):
+        w = np.zeros(9)
+        w[4] = s
+        return w
+    th = np.concatenate([tap(scale_a), [gam[0]], [bet[0]], tap(scale_b), [gam[1]], [bet[1]],
+                         tap(head_w), [head_b]])
+    assert th.size == M.param_count(1, 1)
+    return torch.tensor(th, dtype=DT)
+
+
+def test_running_stats_momentum_and_unbiased_variance_by_hand():
+    r = _rng(12)
+    x = r.normal(0.5, 1.2, size=(2, 3, 3))
+    th = _delta_net(1, 1, 1.0, 2.0, (1.5, 0.7), (-0.2, 0.1), 1.0, 0.0)
+    rm0 = torch.tensor([0.3, -0.1], dtype=DT)
+    rv0 = torch.tensor([2.0, 0.5], dtype=DT)
+    rm, rv = M.running_stats(torch.tensor(x, dtype=DT), th, 1, 1, rm0, rv0, momentum=0.1)
+    # by hand: z1 = x; a1 = relu(BN(z1)) with the biased batch variance; z2 = 2 a1
+    v = x.reshape(-1)
+    N = v.size
+    mu1 = sum(v) / N
+    var1_b = sum((t - mu1) ** 2 for t in v) / N
+    var1_u = sum((t - mu1) ** 2 for t in v) / (N - 1)
+    a1 = [max(0.0, (t - mu1) / math.sqrt(var1_b + 1e-5) * 1.5 - 0.2) for t in v]
+    z2 = [2.0 * t for t in a1]
+    mu2 = sum(z2) / N
+    var2_u = sum((t - mu2) ** 2 for t in z2) / (N - 1)
+    want_m = [0.9 * 0.3 + 0.1 * mu1, 0.9 * -0.1 + 0.1 * mu2]
+    want_v = [0.9 * 2.0 + 0.1 * var1_u, 0.9 * 0.5 + 0.1 * var2_u]
+    assert np.allclose(rm.numpy(), want_m, rtol=0, atol=1e-13)
+    assert np.allclose(rv.numpy(), want_v, rtol=0, atol=1e-13)
+
+
+def test_forward_eval_is_inference_batchnorm_and_relu_by_hand():
+    r = _rng(13)
+    x = r.normal(0.0, 1.0, size=(2, 4, 4))
+    gam, bet = (1.3, 0.8), (-0.4, 0.25)
+    th = _delta_net(1, 1, 0.5, -1.5, gam, bet, 2.0, -0.3)
+    rm = torch.tensor([0.2, 0.6], dtype=DT)
+    rv = torch.tensor([0.9, 1.7], dtype=DT)
+    m = M.forward_eval(torch.tensor(x, dtype=DT), th, 1, 1, rm, rv).numpy()
+    eps = 1e-5
+    want = np.empty_like(x)
+    clipped = 0
+    for idx in np.ndindex(*x.shape):
+        z1 = 0.5 * x[idx]
+        a1 = (z1 - 0.2) / math.sqrt(0.9 + eps) * gam[0] + bet[0]
+        clipped += a1 < 0
+        a1 = max(0.0, a1)
+        z2 = -1.5 * a1
+        a2 = (z2 - 0.6) / math.sqrt(1.7 + eps) * gam[1] + bet[1]
+        clipped += a2 < 0
+        a2 = max(0.0, a2)
+        want[idx] = 1.0 / (1.0 + math.exp(-(2.0 * a2 - 0.3)))
+    assert clipped > 0          # the case exercises the ReLU
+    assert np.allclose(m, want, rtol=0, atol=1e-14)
+
+
+def test_forward_eval_on_the_batch_statistics_is_the_training_forward():
+    # BatchNorm on running statistics equal to the batch's (biased variance, as
+    # the training normalisation uses) is the training-mode layer, at every depth
+    r = _rng(14)
+    L, base = 3, 4
+    x = torch.tensor(r.random((3, 16, 16)), dtype=DT)
+    th = torch.tensor(M.init_params(L, base, seed=4), dtype=DT)
+    m, acts = M.forward(x, th, L, base, keep=True)
+    means, vars_ = [], []
+    for c in M.conv_list(L, base):
+        mu, var = M.batch_stats(acts[f"{c.name}.z"])
+        means.append(mu)
+        vars_.append(var)
+    got = M.forward_eval(x, th, L, base, torch.cat(means), torch.cat(vars_))
+    assert torch.allclose(got, m, rtol=0, atol=1e-12)
+    # and running statistics that differ from the batch's change the mask
+    other = M.forward_eval(x, th, L, base, torch.cat(means) + 0.1, torch.cat(vars_))
+    assert float((other - m).abs().max()) > 1e-3
+
+
+def test_quant_forward_rounds_at_the_documented_points_by_hand():
+    # one level, centre taps: the stored values are bf16(x), bf16(w), bf16(z) and
+    # bf16(relu(BN(z))) with BN on the stored z; the head stays unrounded
+    r = _rng(15)
+    x = r.random((2, 3, 3)) * 3.0
+    gam, bet = (1.1, 0.9), (0.05, -0.02)
+    wa, wb = 1.0 + 2.0 ** -6 + 2.0 ** -9, 0.7
+    th = _delta_net(1, 1, wa, wb, gam, bet, 1.7, 0.1)
+    q = lambda v: float(_bf16_rne_bits(np.array([v], dtype=np.float32))[0])
+    N = x.size
+    z1 = [q(q(t) * q(wa)) for t in x.reshape(-1)]
+    mu = sum(z1) / N
+    var = sum((t - mu) ** 2 for t in z1) / N
+    a1 = [q(max(0.0, (t - mu) / math.sqrt(var + 1e-5) * gam[0] + bet[0])) for t in z1]
+    z2 = [q(t * q(wb)) for t in a1]
+    mu = sum(z2) / N
+    var = sum((t - mu) ** 2 for t in z2) / N
+    a2 = [q(max(0.0, (t - mu) / math.sqrt(var + 1e-5) * gam[1] + bet[1])) for t in z2]
+    want = np.array([1.0 / (1.0 + math.exp(-(1.7 * t + 0.1))) for t in a2]).reshape(x.shape)
+    got = M.forward(torch.tensor(x, dtype=DT), th, 1, 1, quant=True).numpy()
+    assert np.allclose(got, want, rtol=0, atol=1e-12)
+    exact = M.forward(torch.tensor(x, dtype=DT), th, 1, 1).numpy()
+    assert np.abs(exact - want).max() > 1e-4     # the rounding is visible

@@ -475,3 +475,100 @@ def test_gradient_matches_finite_differences():
         fd = (loss(*args_p) - loss(*args_m)) / (2 * h)
         ad = float(res[name][idx])
         assert abs(fd - ad) <= 1e-6 * max(1.0, abs(fd)), (name, fd, ad)
+
+
+# ------------------------------------------------ alternative readings (options)
+
+def _linear_corr_loops(fw, gp):
+    """c[s] = sum_x fw[x] gp[x + s] over the lag window [-n/2, n/2)^2, zero outside (pure Python)."""
+    n = fw.shape[0]
+    out = np.zeros((n, n))
+    for iy, sy in enumerate(range(-n // 2, n // 2)):
+        for ix, sx in enumerate(range(-n // 2, n // 2)):
+            acc = 0.0
+            for y in range(n):
+                for x in range(n):
+                    if 0 <= y + sy < n and 0 <= x + sx < n:
+                        acc += fw[y, x] * gp[y + sy, x + sx]
+            out[iy, ix] = acc
+    return out
+
+
+def test_unwindowed_translation_stage():
+    """With xy_unwindowed, stage 2 correlates the masked scans without the window
+    (stage 1 keeps it): c_xy is the linear correlation of f m_f with g m_g rotated
+    by the stage-1 heading, and the windowed reading gives a different surface."""
+    n = 12
+    r = np.random.default_rng(40)
+    f, g = torch.tensor(r.random((n, n))), torch.tensor(r.random((n, n)))
+    mf, mg = torch.tensor(r.random((n, n))), torch.tensor(r.random((n, n)))
+    base = dict(n=n, n_theta=16, delta_xy=0.5, temp_theta=0.05, temp_xy=0.5, hann=True)
+    un = O.search(f, g, O.Params(**base, xy_unwindowed=True), mf, mg)
+    win = O.search(f, g, O.Params(**base), mf, mg)
+    np.testing.assert_allclose(un["c_theta"].numpy(), win["c_theta"].numpy(), rtol=0, atol=1e-12)
+    gp = O.rotate(g * mg, un["theta"]).numpy()
+    want = _linear_corr_loops((f * mf).numpy(), gp)
+    np.testing.assert_allclose(un["c_xy"].numpy(), want, rtol=0, atol=1e-10)
+    assert float((un["c_xy"] - win["c_xy"]).abs().max()) > 1e-2 * float(un["c_xy"].abs().max())
+    # the full-circle search's second run reads the same unwindowed scans
+    fc = O.search_full_circle(f, g, O.Params(**base, xy_unwindowed=True), mf, mg)
+    th = float(un["theta"])
+    alt = th + math.pi if th < 0 else th - math.pi
+    want2 = _linear_corr_loops((f * mf).numpy(), O.rotate(g * mg, torch.tensor(alt, dtype=F64)).numpy())
+    np.testing.assert_allclose(fc["c_xy_turned"].numpy(), want2, rtol=0, atol=1e-10)
+
+
+def test_marginal_angle_score_is_the_radius_mean_of_the_2d_correlation():
+    """Algorithm 1's 'Mean over r' of the 2-D (radius, angle) circular correlation,
+    computed here with numpy's FFT, is the marginal reading; with one radius the
+    two readings coincide."""
+    n_r, n_t = 5, 12
+    pf, pg = rnd(n_r, n_t, seed=41), rnd(n_r, n_t, seed=42)
+    c2 = np.fft.ifft2(np.conj(np.fft.fft2(pf.numpy())) * np.fft.fft2(pg.numpy())).real
+    want = c2.mean(axis=0)[np.arange(-n_t // 2, n_t // 2) % n_t]
+    np.testing.assert_allclose(O.angle_correlation_marginal(pf, pg).numpy(), want, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(O.angle_correlation_marginal(pf[:1], pg[:1]).numpy(),
+                               O.angle_correlation(pf[:1], pg[:1]).numpy(), rtol=0, atol=1e-12)
+    assert np.abs(O.angle_correlation(pf, pg).numpy() - want).max() > 1e-2
+
+
+def test_marginal_reading_in_the_search():
+    """The search's marginal option scores the polar spectra it resampled."""
+    n = 16
+    f, g = rnd(n, n, seed=43).abs(), rnd(n, n, seed=44).abs()
+    out = O.search(f, g, O.Params(n=n, n_theta=16, angle_marginal=True))
+    pf, pg = out["pf"].numpy(), out["pg"].numpy()
+    n_t = pf.shape[1]
+    c2 = np.fft.ifft2(np.conj(np.fft.fft2(pf)) * np.fft.fft2(pg)).real
+    want = c2.mean(axis=0)[np.arange(-n_t // 2, n_t // 2) % n_t]
+    np.testing.assert_allclose(out["c_theta"].numpy(), want, rtol=0, atol=1e-9)
+
+
+@pytest.mark.parametrize("n_lags,temp", [(4, 1.0), (16, 0.5), (7, 2.0)])
+def test_zscore_softmax_closed_form(n_lags, temp):
+    """A one-hot score vector of n lags standardised by its mean and population
+    standard deviation sqrt(n - 1) / n: the peak's logit exceeds every other by
+    n / sqrt(n - 1), so p_peak = 1 / (1 + (n - 1) exp(-n / (sqrt(n - 1) T)))."""
+    c = torch.zeros(n_lags, dtype=F64)
+    c[2] = 3.7          # any positive height: standardisation removes it
+    c = c - 11.0        # and any offset
+    p = O.softmax_weights(c, temp, zscore=True)
+    want = 1.0 / (1.0 + (n_lags - 1) * math.exp(-n_lags / (math.sqrt(n_lags - 1) * temp)))
+    assert abs(float(p[2]) - want) < 1e-14
+    np.testing.assert_allclose(p.sum().item(), 1.0, atol=1e-15)
+    # without standardisation the raw height decides
+    q = O.softmax_weights(c, temp, zscore=False)
+    assert abs(float(q[2]) - 1.0 / (1.0 + (n_lags - 1) * math.exp(-3.7 / temp))) < 1e-14
+
+
+def test_zscore_search_ignores_the_scale_of_the_scans():
+    """Both score surfaces are linear in each scan, so standardised logits make the
+    pose independent of a positive rescaling of f; raw logits do not."""
+    n = 16
+    f, g = rnd(n, n, seed=45).abs(), rnd(n, n, seed=46).abs()
+    pz = O.Params(n=n, n_theta=16, delta_xy=0.5, temp_theta=0.5, temp_xy=0.5, zscore=True)
+    pr = O.Params(n=n, n_theta=16, delta_xy=0.5, temp_theta=0.5, temp_xy=0.5)
+    a, b = O.search(f, g, pz)["pose"], O.search(7.0 * f, g, pz)["pose"]
+    np.testing.assert_allclose(a.numpy(), b.numpy(), rtol=0, atol=1e-12)
+    a, b = O.search(f, g, pr)["pose"], O.search(7.0 * f, g, pr)["pose"]
+    assert float((a - b).abs().max()) > 1e-3
