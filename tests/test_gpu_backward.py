@@ -134,7 +134,7 @@ def test_adjoint_translation_stage(case):
         _check_pair(res, b, ref, names, "translation")
 
 
-def _dtheta2_flip_bound(f, g, d_pose, p):
+def _dtheta2_flip_bound(f, g, d_pose, p, mf=None, mg=None):
     """Largest change of the Rotate-path heading gradient that re-deciding the
     bilinear cell of sample positions can cause, for every output pixel whose
     position lies within eps of a lattice line; eps covers a heading offset of
@@ -142,12 +142,13 @@ def _dtheta2_flip_bound(f, g, d_pose, p):
     position rounding.  Computed from the oracle alone."""
     ft = torch.as_tensor(f, dtype=torch.float64).clone().requires_grad_(True)
     gt = torch.as_tensor(g, dtype=torch.float64)
-    o = O.search(ft, gt, p)
+    o = O.search(ft, gt, p, mf, mg)
     loss = (o["pose"] * torch.as_tensor(d_pose, dtype=torch.float64)).sum()
     dgp = torch.autograd.grad(loss, o["gp"])[0].numpy()
     th = float(o["theta"])
     n = p.n
-    g2 = g.astype(np.float64) if p.xy_unwindowed else (O.hann2d(n).numpy() * g)
+    g1 = g.astype(np.float64) * (1.0 if mg is None else mg.astype(np.float64))
+    g2 = g1 if p.xy_unwindowed else (O.hann2d(n).numpy() * g1)
     pad = n                                              # rotated positions stay within n of the grid
     gp = np.pad(g2, pad)                                 # zero outside
     c, s = math.cos(th), math.sin(th)
@@ -175,18 +176,18 @@ def _dtheta2_flip_bound(f, g, d_pose, p):
     return float((np.abs(dgp) * dev).sum()), th
 
 
-def _full_chain_check(out, res, b, f, g, d_pose, p, label):
-    ref = O.search_grad(f, g, d_pose, p)
-    unit = O.search_grad(f, g, np.array([1.0, 0.0, 0.0]), p)      # gradient of a unit dtheta_total
-    bound, th_o = _dtheta2_flip_bound(f, g, d_pose, p)
+def _full_chain_check(out, res, b, f, g, d_pose, p, label, mf=None, mg=None):
+    ref = O.search_grad(f, g, d_pose, p, mf, mg)
+    unit = O.search_grad(f, g, np.array([1.0, 0.0, 0.0]), p, mf, mg)   # gradient of a unit dtheta_total
+    bound, th_o = _dtheta2_flip_bound(f, g, d_pose, p, mf, mg)
     d_th = abs(float(out["pose"][b, 0]) - th_o)
     assert d_th <= THETA_WINDOW, f"heading differs by {d_th:.2e} rad, beyond the window"
-    r = torch.cat([(res["d_f"][b].double().cpu() - ref["d_f"]).reshape(-1),
-                   (res["d_g"][b].double().cpu() - ref["d_g"]).reshape(-1)])
-    G = torch.cat([unit["d_f"].reshape(-1), unit["d_g"].reshape(-1)])
+    names = ["d_f", "d_g"] + (["d_m_f", "d_m_g"] if mf is not None else [])
+    r = torch.cat([(res[k][b].double().cpu() - ref[k]).reshape(-1) for k in names])
+    G = torch.cat([unit[k].reshape(-1) for k in names])
     coef = float((r @ G) / (G @ G))
     resid = r - coef * G
-    scale = float(torch.cat([ref["d_f"].reshape(-1), ref["d_g"].reshape(-1)]).abs().max())
+    scale = float(torch.cat([ref[k].reshape(-1) for k in names]).abs().max())
     e = float(resid.abs().max()) / scale
     # the shift along G is visible only in proportion to |G|: allow the flip bound
     # plus whatever shift stays below the bar (G ~ 0 when the heading softmax is saturated)
@@ -276,3 +277,119 @@ def test_autograd_function():
     d = np.tile(np.array([1.0, 2.0, -1.0], np.float32), (2, 1))
     _, res = _gpu_grad(kw, f, g, None, None, d)
     assert torch.equal(F.grad, res["d_f"]) and torch.equal(G.grad, res["d_g"])
+
+
+# ------------------------------------------------------------ 512 x 512 (the benchmark's size)
+
+C3_PAIRS = (0, 31)        # first and last pair of the benchmark's 32-pair batch
+C3_TEMP_THETA = 20.0      # heading softmax unsaturated on both (largest weight 0.42 and 0.69)
+
+
+def _c3_inputs():
+    name = "batch512"
+    kw = workloads.search_kwargs(name)
+    kw.update(temp_theta=C3_TEMP_THETA)
+    f, g, _ = synth.make_batch(name, workloads.SEARCH[name]["batch"], split="test")
+    idx = list(C3_PAIRS)
+    return kw, np.ascontiguousarray(f[idx]), np.ascontiguousarray(g[idx])
+
+
+def _assert_unsaturated(f, g, p, mf=None, mg=None):
+    """The heading softmax must spread its weight, or d theta / d input vanishes
+    and the comparison could not see an error in the rotation-stage adjoint."""
+    for b in range(f.shape[0]):
+        o = O.search(f[b], g[b], p, None if mf is None else mf[b], None if mg is None else mg[b])
+        pmax = float(O.softmax_weights(o["c_theta"], p.temp_theta, p.zscore).max())
+        print(f"pair {b}: largest heading weight {pmax:.3f}", flush=True)
+        assert 0.05 < pmax < 0.95, pmax
+
+
+def _gpu_grad_state(kw, f, g, mf, mg, d_pose):
+    """The training pair: forward keeping its intermediates, adjoint reading them."""
+    s = fmbym.Search(max_batch=f.shape[0], **kw)
+    F, G, MF, MG = _dev(f), _dev(g), _dev(mf), _dev(mg)
+    out = s.forward(F, G, MF, MG, keep=True)
+    res = s.backward(F, G, MF, MG, out, _dev(d_pose))
+    torch.cuda.synchronize()
+    return out, res
+
+
+@pytest.mark.parametrize("path", ["recompute", "state"])
+def test_adjoint_rotation_stage_512(path):
+    """d_pose = e_theta at 512 x 512 with 512 bins and an unsaturated heading
+    softmax: the polar, angular and |F| adjoints at the benchmark's size, on the
+    recomputing adjoint and on the training pair's stored intermediates."""
+    kw, f, g = _c3_inputs()
+    p = O.Params(**kw)
+    _assert_unsaturated(f, g, p)
+    B = f.shape[0]
+    d_pose = np.tile(np.array([1.0, 0.0, 0.0], np.float32), (B, 1))
+    _, res = (_gpu_grad if path == "recompute" else _gpu_grad_state)(kw, f, g, None, None, d_pose)
+    for b in range(B):
+        ref = O.search_grad(f[b], g[b], d_pose[b].astype(np.float64), p)
+        _check_pair(res, b, ref, ["d_f", "d_g"], f"rotation 512 {path}")
+
+
+@pytest.mark.parametrize("path", ["recompute", "state"])
+def test_adjoint_full_chain_512_unsaturated(path):
+    """The whole chain at 512 x 512 with the heading softmax unsaturated, so the
+    heading's gradient (both its paths) carries real weight."""
+    kw, f, g = _c3_inputs()
+    p = O.Params(**kw)
+    B = f.shape[0]
+    d_pose = np.random.default_rng(7).standard_normal((B, 3)).astype(np.float32)
+    out, res = (_gpu_grad if path == "recompute" else _gpu_grad_state)(kw, f, g, None, None, d_pose)
+    for b in range(B):
+        _full_chain_check(out, res, b, f[b], g[b], d_pose[b].astype(np.float64), p, f"c3 {path}")
+
+
+@pytest.mark.parametrize("which,d_pose,temp_theta", [
+    ("f", (1.0, 0.0, 0.0), C3_TEMP_THETA), ("g", (1.0, 0.0, 0.0), C3_TEMP_THETA),
+    ("f", (0.0, 1.0, -1.0), 1e-4), ("g", (0.0, -0.5, 1.0), 1e-4),
+])
+def test_adjoint_finite_differences_512(which, d_pose, temp_theta):
+    """<grad, v> against central differences (h = 1e-3) of the FP64 forward on
+    8 x 8 patches at 512 x 512: the heading (unsaturated softmax) and the
+    translation (saturated heading, so theta is fixed).  The bar is normwise on
+    the patch, 1e-3 |g_patch| |v| with g the oracle's gradient: a relative
+    error e of the gradient moves <g, v> by at most e |g_patch| |v|, and a
+    patch whose directional derivative happens to be small (one here is 5x
+    below the others) must not tighten the bar on the gradient."""
+    kw, f, g = _c3_inputs()
+    kw.update(temp_theta=temp_theta)
+    f, g = f[:1], g[:1]
+    dp = np.array([d_pose], np.float32)
+    _, res = _gpu_grad(kw, f, g, None, None, dp)
+    p = O.Params(**kw)
+    ref = O.search_grad(f[0], g[0], dp[0].astype(np.float64), p)["d_f" if which == "f" else "d_g"].numpy()
+    rng = np.random.default_rng(12)
+    h = 1e-3
+    base_f, base_g = f[0].astype(np.float64), g[0].astype(np.float64)
+    grad = res["d_f" if which == "f" else "d_g"][0].double().cpu().numpy()
+    for (r0, c0) in [(252, 252), (180, 300), (310, 140)]:
+        v = np.zeros_like(base_f)
+        v[r0:r0 + 8, c0:c0 + 8] = rng.standard_normal((8, 8))
+
+        def loss(sign):
+            ff = base_f + sign * h * v if which == "f" else base_f
+            gg = base_g + sign * h * v if which == "g" else base_g
+            return float((O.search(ff, gg, p)["pose"].numpy() * dp[0]).sum())
+
+        fd = (loss(1) - loss(-1)) / (2 * h)
+        ad = float((grad * v).sum())
+        scale = float(np.linalg.norm(ref[r0:r0 + 8, c0:c0 + 8]) * np.linalg.norm(v))
+        print(f"512 patch {which}{(r0, c0)} d_pose {d_pose}: fd {fd:.6e} adjoint {ad:.6e} "
+              f"|g_patch||v| {scale:.3e}", flush=True)
+        assert abs(fd - ad) <= 1e-3 * scale, (fd, ad, scale)
+
+
+def test_adjoint_full_chain_masked():
+    """The whole chain with masks (Eq. 11): d_f, d_g, d_m_f and d_m_g at once."""
+    kw, f, g, mf, mg = _case("masked")
+    B = f.shape[0]
+    d_pose = np.random.default_rng(5).standard_normal((B, 3)).astype(np.float32)
+    out, res = _gpu_grad(kw, f, g, mf, mg, d_pose)
+    p = O.Params(**kw)
+    for b in range(B):
+        _full_chain_check(out, res, b, f[b], g[b], d_pose[b].astype(np.float64), p, "masked",
+                          mf[b], mg[b])
