@@ -80,17 +80,6 @@ def measured_traffic(kernel: str):
     return (best[1] * meta["ff"] + best[2] * meta["fw"]) * 1024.0
 
 
-def cpu_model() -> str:
-    """The host CPU's model name (Linux), for the CPU-baseline record."""
-    try:
-        for ln in open("/proc/cpuinfo"):
-            if ln.startswith("model name"):
-                return ln.split(":", 1)[1].strip()
-    except OSError:
-        pass
-    return "unknown"
-
-
 def kernel_bytes(n: int, n_theta: int, n_r: int, batch: int, masked: bool, keep: bool = False) -> dict:
     """Algorithmic HBM bytes per launch of each kernel: compulsory reads of its
     inputs plus writes of its outputs, each touched once (float32 / complex64).
@@ -132,6 +121,70 @@ def kernel_bytes(n: int, n_theta: int, n_r: int, batch: int, masked: bool, keep:
         "kb_cols_mag": batch * (half + mag + half),
         "kb_rows_final": batch * (half + 2 * N2 * 4 + m * 2 * 4 * N2 + 2 * N2 * 4 + (m - 1) * 2 * N2 * 4),
     }
+
+
+def pass_model_bytes(n: int) -> dict:
+    """HBM bytes per pair of each kernel on the pass model of the survey's
+    byte derivation (fp32 data, complex64 intermediates, ZeroPad to 2n, every
+    pass reading its inputs and writing its outputs once).  These are the
+    figures the roofline's `achieved` uses; the library's own per-launch model
+    (``kernel_bytes``: 3n/2 padding, the passes as this library fuses them) is
+    reported beside it.  Kernels that share one pass of the model get the
+    pass's bytes once, on the kernel that moves them."""
+    N2 = n * n
+    return {
+        "k_rows1": 16 * N2,        # S2 rows R2C
+        "k_cols1": 12 * N2,        # S3 columns + |F|
+        "k_polar": 4 * N2,         # S4 polar gather + angular FFT + sum over r
+        "k_rows2": 24 * N2,        # S6 rotate + 2n rows (k_rotate is part of this pass)
+        "k_cols2": 24 * N2,        # S7 columns fwd . conj . inv
+        "k_rows3": 12 * N2,        # S8 inverse rows + softmax
+        "kb_rows_fwd2": 40 * N2,   # translation adjoint: padded rows of f_w, g' and dc
+        "kb_cols_xy": 40 * N2,     # column adjoint
+        "kb_rows_xy": 28 * N2,     # inverse rows + dtheta_2
+        "kb_rotate_adj": 8 * N2,   # Rotate transpose
+        "kb_polar": 12 * N2,       # angular adjoint
+        "kb_dmag": 12 * N2,        # CSR transpose gather
+        "kb_cols_mag": 20 * N2,    # column adjoint with recomputed F
+        "kb_rows_final": 24 * N2,  # final rows + Hann + mask
+    }
+
+
+def cpu_description() -> str:
+    """Model name, family/model/stepping and logical CPU count of the host (Linux)."""
+    info = {}
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ":" in ln:
+                k, v = ln.split(":", 1)
+                info.setdefault(k.strip(), v.strip())
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count() or 0
+    return (f"{info.get('model name', 'unknown')} (family {info.get('cpu family', '?')}, model "
+            f"{info.get('model', '?')}, stepping {info.get('stepping', '?')}), {usable} usable of "
+            f"{os.cpu_count()} logical CPUs")
+
+
+def oracle_leg(run, n_items: int, threads: int, min_runs: int, seconds: float):
+    """Time `run(i)` on the host with torch at `threads` threads: at least
+    min_runs calls, then more until `seconds` have gone (at most four passes
+    over the n_items inputs).  Returns (runs, seconds)."""
+    import torch
+    prev = torch.get_num_threads()
+    torch.set_num_threads(threads)
+    try:
+        k = 0
+        t0 = time.perf_counter()
+        while k < 4 * n_items and (k < min_runs or time.perf_counter() - t0 < seconds):
+            run(k % n_items)
+            k += 1
+        return k, time.perf_counter() - t0
+    finally:
+        torch.set_num_threads(prev)
 
 
 def main() -> int:
@@ -274,7 +327,7 @@ def train_bench(args) -> int:
             M.pose_loss(pose[None], torch.from_numpy(p[done:done + 1]).double(), "l2").backward()
             done += 1
         dt = time.perf_counter() - t0
-        res["cpu_baseline"] = {"value": done / dt, "unit": "pairs/s", "cores": torch.get_num_threads(), "cpu": cpu_model(),
+        res["cpu_baseline"] = {"value": done / dt, "unit": "pairs/s", "cores": torch.get_num_threads(), "cpu": cpu_description(),
                                "kind": "oracle",
                                "sample": f"{done} pairs (about {CPU_SECONDS:.0f} s): FP64 oracle mask network + "
                                          "masked search + L2 loss, autograd"}
@@ -343,7 +396,7 @@ def drive_bench(args) -> int:
             O.search(scans_np[done], scans_np[done + 1], p)
             done += 1
         dt = time.perf_counter() - t0
-        res["cpu_baseline"] = {"value": done / dt, "unit": "pairs/s", "cores": torch.get_num_threads(), "cpu": cpu_model(),
+        res["cpu_baseline"] = {"value": done / dt, "unit": "pairs/s", "cores": torch.get_num_threads(), "cpu": cpu_description(),
                                "kind": "oracle",
                                "sample": f"the drive's first {done} pairs (about 10 s), FP64 oracle forward"}
     print(json.dumps(res), flush=True)
@@ -434,7 +487,7 @@ def ragged_bench(args) -> int:
                 spent[k] += time.perf_counter() - t0
             rounds += 1
         mean_t = sum(counts[k] * spent[k] / rounds for k in sizes) / cfg["n_pairs"]
-        res["cpu_baseline"] = {"value": 1.0 / mean_t, "unit": "pairs/s", "cores": torch.get_num_threads(), "cpu": cpu_model(),
+        res["cpu_baseline"] = {"value": 1.0 / mean_t, "unit": "pairs/s", "cores": torch.get_num_threads(), "cpu": cpu_description(),
                                "kind": "oracle",
                                "sample": f"{rounds} pair(s) of each size (about {CPU_SECONDS:.0f} s), FP64 oracle "
                                          "forward, weighted by the mix"}
@@ -627,7 +680,10 @@ def search_bench(args) -> int:
     per_kernel = {k: (t / c) for k, (t, c) in prof.items()}
     dom = max(prof, key=lambda k: prof[k][0])
     kb = kernel_bytes(n, nt, n, B, masked=False, keep=with_bwd)
-    achieved = kb[dom] / (per_kernel[dom] * 1e-3) / 1e9 if dom in kb else None
+    pm = pass_model_bytes(n)
+    launch_s = per_kernel[dom] * 1e-3
+    achieved = pm[dom] * B / launch_s / 1e9 if dom in pm else None
+    achieved_lib = kb[dom] / launch_s / 1e9 if dom in kb else None
 
     if with_bwd:
         metric = "scan-pairs/sec, 512^2 decoupled search fwd+bwd, 1 GPU"
@@ -655,10 +711,15 @@ def search_bench(args) -> int:
                    "pass": "fwd+bwd, one fmbym_search_vjp call per step (the forward keeps its "
                            "intermediates for the adjoint)" if with_bwd else mode},
         "roofline": {"bound": "hbm", "kernel": dom, "launch": "whole batch, unsplit (per-kernel pass)",
+                     "launch_ms": per_kernel[dom],
                      "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": None if achieved is None else achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(dom) if args.workload == "batch512" else None,
-                     "algorithmic_bytes": kb.get(dom)},
+                     "algorithmic_bytes": None if dom not in pm else pm[dom] * B,
+                     "byte_model": f"pass model, {pm[dom] // (n * n) if dom in pm else '?'} n^2 per pair",
+                     "library_model": {"algorithmic_bytes": kb.get(dom), "achieved": achieved_lib,
+                                       "frac": None if achieved_lib is None else achieved_lib / HBM_PEAK_GBS,
+                                       "note": "the library's own passes: 3n/2 padding, fused stages"}},
         "kernels_ms": {k: round(v, 5) for k, v in sorted(per_kernel.items())},
     }
     # whole path against the pass model's bytes per pair (304 n^2 fwd+bwd, 92 n^2 fwd)
@@ -669,29 +730,45 @@ def search_bench(args) -> int:
     res.update(extra)
     res["tuning"] = tuning
     if ms_recompute is not None:
+        frac_rc = pass_bytes / (ms_recompute * 1e-3) / 1e9 / HBM_PEAK_GBS
         res["recompute_path"] = {"ms_per_step": ms_recompute, "value": B / (ms_recompute * 1e-3),
-                                 "unit": "pairs/s",
-                                 "frac": pass_bytes / (ms_recompute * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                                 "unit": "pairs/s", "frac": frac_rc, "target_frac": 0.5,
+                                 "meets_target": frac_rc >= 0.5,
+                                 "calls": "fmbym_search, fmbym_search_backward (spectra recomputed)"}
+
+    from oracle import fmbym_oracle as O
+    p = O.Params(**kw)
+    # pose error against the FP64 oracle on sampled pairs of the timed batch
+    # (the GPU poses of one more step on the same inputs)
+    gpu_pose = (s.vjp(f, g, None, None, d_pose) if with_bwd else s.forward(f, g, surfaces=False))["pose"]
+    gpu_pose = gpu_pose.double().cpu().numpy()
+    sample = sorted({0, B // 3, (2 * B) // 3, B - 1})
+    dth, dt_px = [], []
+    for b in sample:
+        ref = O.search(f_np[b], g_np[b], p)["pose"].numpy()
+        dth.append(abs(gpu_pose[b, 0] - ref[0]))
+        dt_px.append(float(np.hypot(gpu_pose[b, 1] - ref[1], gpu_pose[b, 2] - ref[2])) / kw["delta_xy"])
+    res["pose_err_vs_oracle"] = {"pairs": sample, "max_theta_rad": float(max(dth)),
+                                 "max_t_px": float(max(dt_px)), "max_t_m": float(max(dt_px)) * kw["delta_xy"],
+                                 "bar": {"theta_rad": 1e-3, "t_px": 1e-3},
+                                 "within_bar": bool(max(dth) <= 1e-3 and max(dt_px) <= 1e-3)}
 
     if not args.no_cpu_baseline:
-        from oracle import fmbym_oracle as O
-        p = O.Params(**kw)
-        # at least --cpu-pairs runs, then more until about CPU_SECONDS of work,
-        # cycling over the batch's pairs (at most four passes)
-        k = 0
-        t0 = time.perf_counter()
-        while k < 4 * B and (k < args.cpu_pairs or time.perf_counter() - t0 < CPU_SECONDS):
-            b = k % B
+        def run(b):
             if with_bwd:
                 O.search_grad(f_np[b], g_np[b], [1.0, 1.0, 1.0], p)
             else:
                 O.search(f_np[b], g_np[b], p)
-            k += 1
-        dt = time.perf_counter() - t0
-        res["cpu_baseline"] = {"value": k / dt, "unit": "pairs/s", "cores": torch.get_num_threads(), "cpu": cpu_model(),
+
+        what = "forward + autograd backward" if with_bwd else "forward"
+        threads = torch.get_num_threads()
+        k, dt = oracle_leg(run, B, threads, args.cpu_pairs, CPU_SECONDS)
+        k1, dt1 = oracle_leg(run, B, 1, 2, CPU_SECONDS)
+        res["cpu_baseline"] = {"value": k / dt, "unit": "pairs/s", "cores": threads, "cpu": cpu_description(),
                                "kind": "oracle",
-                               "sample": f"{k} oracle runs over {min(k, B)} of the {B} pairs, FP64 oracle "
-                                         f"{'forward + autograd backward' if with_bwd else 'forward'}"}
+                               "sample": f"{k} oracle runs over {min(k, B)} of the {B} pairs, FP64 oracle {what}",
+                               "one_thread": {"value": k1 / dt1, "unit": "pairs/s", "cores": 1,
+                                              "sample": f"{k1} oracle runs over {min(k1, B)} of the {B} pairs"}}
     print(json.dumps(res), flush=True)
     return 0
 
