@@ -297,6 +297,22 @@ FMBYM_API int fmbym_ragged_create(const fmbym_plan* plans, int32_t n_plans, cons
 /* Enqueue one replay of the whole work list on `stream`. */
 FMBYM_API int fmbym_ragged_launch(fmbym_ragged r, void* stream);
 FMBYM_API int fmbym_ragged_destroy(fmbym_ragged r);
+
+/* The same work list in one call, without a launch object: validates and
+ * groups `pairs` (a HOST array) as fmbym_ragged_create does, copies the
+ * per-pair pointer table into the caller's workspace in stream order, and
+ * enqueues every group's batched forward search (network-masked groups after
+ * their mask network) one after another on `stream`.  Poses and stamps as for
+ * fmbym_ragged_create; each pair's pose is bit for bit what fmbym_search gives
+ * it alone with the plan of its size.  Allocates no device memory and creates
+ * no stream, event or graph; the workspace (fmbym_search_ragged_workspace_size
+ * bytes) must not be used by another call in flight. */
+FMBYM_API size_t fmbym_search_ragged_workspace_size(const fmbym_plan* plans, int32_t n_plans,
+                                                    const fmbym_pair* pairs, int32_t n_pairs,
+                                                    const struct fmbym_mask_desc_s* net);
+FMBYM_API int fmbym_search_ragged(const fmbym_plan* plans, int32_t n_plans, const fmbym_pair* pairs,
+                                  int32_t n_pairs, const struct fmbym_mask_desc_s* net, float* pose,
+                                  uint64_t* stamps, void* workspace, size_t workspace_bytes, void* stream);
 /* Rate of the device wall clock behind the stamps, in kHz, for the current device. */
 FMBYM_API int fmbym_wall_clock_khz(int32_t* khz);
 

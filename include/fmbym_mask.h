@@ -83,10 +83,14 @@ FMBYM_API int fmbym_mask_fwd(const fmbym_mask_desc* net, int32_t images, int32_t
 FMBYM_API size_t fmbym_mask_workspace_bytes(const fmbym_mask_desc* net, int32_t images, int32_t n);
 
 /* Backward pass of a training forward: given d_mask = dL/dmask [images][n][n]
- * and the forward's act, writes dL/dparams (FP32, flat layout, overwritten). */
+ * and the forward's act, writes dL/dparams (FP32, flat layout, overwritten)
+ * and, unless d_x is NULL, dL/dx [images][n][n] (FP32, overwritten): the
+ * gradient of the loss with respect to the network's input scans (the
+ * straight-through derivative of their BF16 rounding), for a caller that
+ * trains what produces the scans or checks the network's sensitivity. */
 FMBYM_API int fmbym_mask_bwd(const fmbym_mask_desc* net, int32_t images, int32_t n,
                              const float* d_mask, const void* act, size_t act_bytes, float* d_params,
-                             void* workspace, size_t workspace_bytes, void* stream);
+                             float* d_x, void* workspace, size_t workspace_bytes, void* stream);
 
 /* Adam (bias-corrected, step >= 1) over `count` FP32 parameters in place. */
 FMBYM_API int fmbym_adam(float* params, const float* grad, float* m, float* v, int64_t count,

@@ -215,3 +215,12 @@ def grad(x, d_mask, theta, levels: int, base: int, eps: float = 1e-5, quant: boo
     m = forward(x, th, levels, base, eps, quant=quant)
     (m * d_mask).sum().backward()
     return th.grad.detach()
+
+
+def grad_input(x, d_mask, theta, levels: int, base: int, eps: float = 1e-5, quant: bool = False):
+    """d<mask, d_mask>/d x, the gradient with respect to the input scans, by FP64 autograd
+    (through the training forward's batch statistics, like ``grad``)."""
+    xx = torch.as_tensor(x).to(torch.float64).detach().clone().requires_grad_(True)
+    m = forward(xx, theta.detach(), levels, base, eps, quant=quant)
+    (m * d_mask).sum().backward()
+    return xx.grad.detach()

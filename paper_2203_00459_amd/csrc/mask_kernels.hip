@@ -421,6 +421,29 @@ __global__ void k_input8(const float* __restrict__ x, const float* const* __rest
     *(u32x4*)(x8 + p * 8) = __builtin_bit_cast(u32x4, v);
 }
 
+// d x of the one-channel input: the first convolution's adjoint in FP32, one
+// pixel per thread, taps and channels summed in a fixed order (ky, kx, c).
+__global__ void k_input_grad(const bf16* __restrict__ dz, const float* __restrict__ w, float* __restrict__ dx,
+                             long long npix, int S, int C) {
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npix) return;
+    const int S2 = S * S;
+    const long long img = p / S2;
+    const int i = (int)(p % S2) / S, j = (int)(p % S2) % S;
+    float acc = 0.f;
+    for (int ky = 0; ky < 3; ++ky) {
+        const int y = i + 1 - ky;           // forward: z[y][x] reads in[y + ky - 1][x + kx - 1]
+        if (y < 0 || y >= S) continue;
+        for (int kx = 0; kx < 3; ++kx) {
+            const int x = j + 1 - kx;
+            if (x < 0 || x >= S) continue;
+            const bf16* d = dz + ((img * S2) + (long long)y * S + x) * C;
+            for (int c = 0; c < C; ++c) acc += w[c * 9 + ky * 3 + kx] * (float)d[c];
+        }
+    }
+    dx[p] = acc;
+}
+
 // Per-thread sums of one channel's partial pairs over the blocks k = t, t + 256, ...
 // (in that order): eight blocks' loads in flight, then added in order.
 __device__ __forceinline__ void bn_part_sums(const float* __restrict__ part, int nb, int C, int c,
@@ -1047,6 +1070,11 @@ int bn_part_blocks(long long M, int C) { return (int)((M + bn_pixels(C) - 1) / b
 void launch_input8(const float* x, const float* const* x_tab, bf16* x8, int images, int S, hipStream_t s) {
     const long long n = (long long)images * S * S;
     FMBYM_LAUNCH(kMInput, k_input8, dim3(grid_for(n, 256)), dim3(256), s, x, x_tab, x8, n, S * S);
+}
+
+void launch_input_grad(const bf16* dz, const float* w, float* dx, int images, int S, int C, hipStream_t s) {
+    const long long n = (long long)images * S * S;
+    FMBYM_LAUNCH(kMInputGrad, k_input_grad, dim3(grid_for(n, 256)), dim3(256), s, dz, w, dx, n, S, C);
 }
 
 void launch_bn_stats(const float* part, int nb, int C, long long M, const float* gamma,

@@ -30,6 +30,10 @@ void wgrad_grid(int images, int S, int* blocks, int* tiles_per_block);
 // x [I][S][S] float (or image i at x_tab[i] when x_tab is not null) -> [I][S][S][8]
 // bf16 with the scan in channel 0, zeros elsewhere.
 void launch_input8(const float* x, const float* const* x_tab, bf16* x8, int images, int S, hipStream_t s);
+// Gradient of the network input x (one channel) from the first convolution's
+// output gradient dz [images][S][S][C] (BF16, NHWC) and its FP32 weights
+// w [C][1][3][3]: dx[p] = sum_{c, tap} w[c][tap] dz[p - tap + 1][c].
+void launch_input_grad(const bf16* dz, const float* w, float* dx, int images, int S, int C, hipStream_t s);
 
 // z = conv3x3(in, w) for (cin, cout) in the supported set; w packed [cout][9 cin]
 // bf16 (k = tap cin + ci, tap = 3 ky + kx).  With stats, z is bf16 and

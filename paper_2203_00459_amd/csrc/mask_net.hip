@@ -255,7 +255,7 @@ int fmbym_mask_fwd(const fmbym_mask_desc* d, int32_t I, int32_t n, const float* 
 }
 
 int fmbym_mask_bwd(const fmbym_mask_desc* d, int32_t I, int32_t n, const float* d_mask, const void* act,
-                   size_t act_bytes, float* d_params, void* ws, size_t ws_bytes, void* stream) {
+                   size_t act_bytes, float* d_params, float* d_x, void* ws, size_t ws_bytes, void* stream) {
     const TraceRange trace_range("fmbym_mask_bwd");
     Net net;
     if (!d) return FMBYM_EINVAL;
@@ -295,7 +295,10 @@ int fmbym_mask_bwd(const fmbym_mask_desc* d, int32_t I, int32_t n, const float* 
         if (!launch_wgrad(c.cink, c.cout, dz, in, at<float>(wsp, W.wpart), at<float>(wsp, W.tmp),
                           d_params + c.w, c.cin, I, S, s))
             return FMBYM_EUNSUPPORTED;
-        if (j == 0) break;
+        if (j == 0) {
+            if (d_x) launch_input_grad(dz, P + c.w, d_x, I, S, c.cout, s);
+            break;
+        }
         // data gradient into the buffer of this conv's input
         float* din;
         if (c.enc && c.first_of_level)

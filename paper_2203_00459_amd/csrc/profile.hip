@@ -17,7 +17,7 @@ const char* const kKernelNames[kKernelCount] = {
     "m_input8", "m_conv_fwd", "m_bn_stats", "m_bn_relu", "m_maxpool", "m_up_concat", "m_head_fwd",
     "m_head_bwd", "m_bn_bwd", "m_wgrad", "m_conv_dgrad", "m_pool_bwd", "m_up_bwd", "m_pack", "m_adam",
     "m_pose_loss", "k_rotate", "kb_rotate_adj", "k_joint_setup", "k_joint_peak", "k_joint_pick",
-    "k_turn_setup", "k_turn_pick", "k_finite",
+    "k_turn_setup", "k_turn_pick", "k_finite", "m_input_grad",
 };
 
 namespace {

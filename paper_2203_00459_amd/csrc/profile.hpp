@@ -12,7 +12,7 @@ enum KernelId {
     kKBRowsFwd2, kKBColsXy, kKBRowsXy, kKBDtheta, kKBPolar, kKBDmag, kKBColsMag, kKBRowsFinal,
     kMInput, kMConvFwd, kMBnStats, kMBnRelu, kMPool, kMUpCat, kMHeadFwd, kMHeadBwd, kMBnBwd, kMWgrad,
     kMConvDgrad, kMPoolBwd, kMUpBwd, kMPack, kMAdam, kMLoss, kKRotate, kKBRotateAdj,
-    kKJointSetup, kKJointPeak, kKJointPick, kKTurnSetup, kKTurnPick, kKFinite,
+    kKJointSetup, kKJointPeak, kKJointPick, kKTurnSetup, kKTurnPick, kKFinite, kMInputGrad,
     kKernelCount
 };
 

@@ -102,6 +102,36 @@ int plan_groups(const fmbym_plan* plans, int n_plans, const fmbym_pair* pairs, i
     return FMBYM_OK;
 }
 
+// Host copy of the device pointer table: rows (f, g, m_f, m_g) of every pair in
+// slot order, then the scan rows of the network groups; network masks of a
+// group live at its mask_off in `workspace`.
+std::vector<const float*> pointer_table(const std::vector<Group>& groups, const std::vector<int>& slots,
+                                        const fmbym_pair* pairs, int n_pairs, const void* workspace) {
+    size_t xrows = 0;
+    for (const Group& gr : groups)
+        if (gr.kind == kNet) xrows += 2 * (size_t)gr.count;
+    std::vector<const float*> tab(4 * (size_t)n_pairs + xrows);
+    for (const Group& gr : groups) {
+        const int n = gr.plan->p.n;
+        for (int b = 0; b < gr.count; ++b) {
+            const int s = gr.first + b;
+            const fmbym_pair& q = pairs[slots[s]];
+            tab[4 * s] = q.f;
+            tab[4 * s + 1] = q.g;
+            tab[4 * s + 2] = q.m_f;
+            tab[4 * s + 3] = q.m_g;
+            if (gr.kind == kNet) {
+                const float* masks = (const float*)((const char*)workspace + gr.mask_off);
+                tab[4 * s + 2] = masks + (size_t)b * n * n;                 // network mask of f
+                tab[4 * s + 3] = masks + (size_t)(gr.count + b) * n * n;    // and of g
+                tab[4 * (size_t)n_pairs + gr.xtab_first + b] = q.f;
+                tab[4 * (size_t)n_pairs + gr.xtab_first + gr.count + b] = q.g;
+            }
+        }
+    }
+    return tab;
+}
+
 __global__ void k_ragged_start(unsigned long long* __restrict__ stamps, int n_pairs) {
     if (threadIdx.x == 0) stamps[n_pairs] = (unsigned long long)wall_clock64();
 }
@@ -182,6 +212,33 @@ static int record_launch(Ragged& r, const std::vector<Group>& groups, float* pos
 
 }  // namespace fmbym
 
+namespace fmbym {
+namespace {
+
+// The one-call form's workspace: the groups' regions, then the pointer table
+// and the slot list that fmbym_ragged_create would allocate.
+struct OneCall {
+    size_t tab_off, slot_off, total;
+};
+
+OneCall one_call_layout(size_t groups_bytes, size_t tab_rows, int n_pairs) {
+    OneCall o{};
+    o.tab_off = align256(groups_bytes);
+    o.slot_off = align256(o.tab_off + tab_rows * sizeof(const float*));
+    o.total = align256(o.slot_off + (size_t)n_pairs * sizeof(int));
+    return o;
+}
+
+size_t net_rows(const std::vector<Group>& groups) {
+    size_t x = 0;
+    for (const Group& gr : groups)
+        if (gr.kind == kNet) x += 2 * (size_t)gr.count;
+    return x;
+}
+
+}  // namespace
+}  // namespace fmbym
+
 using namespace fmbym;
 
 extern "C" {
@@ -212,28 +269,7 @@ int fmbym_ragged_create(const fmbym_plan* plans, int32_t n_plans, const fmbym_pa
     if (!r) return FMBYM_EINVAL;
     r->n_pairs = n_pairs;
     if (net) r->net = *net;
-    size_t xrows = 0;
-    for (const Group& gr : groups)
-        if (gr.kind == kNet) xrows += 2 * (size_t)gr.count;
-    std::vector<const float*> tab(4 * (size_t)n_pairs + xrows);
-    for (const Group& gr : groups) {
-        const int n = gr.plan->p.n;
-        for (int b = 0; b < gr.count; ++b) {
-            const int s = gr.first + b;
-            const fmbym_pair& q = pairs[slots[s]];
-            tab[4 * s] = q.f;
-            tab[4 * s + 1] = q.g;
-            tab[4 * s + 2] = q.m_f;
-            tab[4 * s + 3] = q.m_g;
-            if (gr.kind == kNet) {
-                const float* masks = (const float*)((const char*)workspace + gr.mask_off);
-                tab[4 * s + 2] = masks + (size_t)b * n * n;                 // network mask of f
-                tab[4 * s + 3] = masks + (size_t)(gr.count + b) * n * n;    // and of g
-                tab[4 * (size_t)n_pairs + gr.xtab_first + b] = q.f;
-                tab[4 * (size_t)n_pairs + gr.xtab_first + gr.count + b] = q.g;
-            }
-        }
-    }
+    const std::vector<const float*> tab = pointer_table(groups, slots, pairs, n_pairs, workspace);
     hipError_t e = hipGetDevice(&r->device);
     if (e == hipSuccess) e = hipMalloc((void**)&r->tab, sizeof(const float*) * tab.size());
     if (e == hipSuccess) e = hipMalloc((void**)&r->slot_pair, sizeof(int) * n_pairs);
@@ -275,6 +311,61 @@ int fmbym_ragged_create(const fmbym_plan* plans, int32_t n_plans, const fmbym_pa
     }
     *out = (fmbym_ragged)r;
     return FMBYM_OK;
+}
+
+size_t fmbym_search_ragged_workspace_size(const fmbym_plan* plans, int32_t n_plans, const fmbym_pair* pairs,
+                                          int32_t n_pairs, const fmbym_mask_desc* net) {
+    std::vector<Group> groups;
+    std::vector<int> slots;
+    size_t bytes = 0;
+    if (plan_groups(plans, n_plans, pairs, n_pairs, net, groups, slots, &bytes)) return 0;
+    return one_call_layout(bytes, 4 * (size_t)n_pairs + net_rows(groups), n_pairs).total;
+}
+
+int fmbym_search_ragged(const fmbym_plan* plans, int32_t n_plans, const fmbym_pair* pairs, int32_t n_pairs,
+                        const fmbym_mask_desc* net, float* pose, uint64_t* stamps, void* workspace,
+                        size_t workspace_bytes, void* stream) {
+    const TraceRange trace_range("fmbym_search_ragged");
+    std::vector<Group> groups;
+    std::vector<int> slots;
+    size_t bytes = 0;
+    int rc = plan_groups(plans, n_plans, pairs, n_pairs, net, groups, slots, &bytes);
+    if (rc) return rc;
+    if (!pose) return FMBYM_EINVAL;
+    const std::vector<const float*> tab_h = pointer_table(groups, slots, pairs, n_pairs, workspace);
+    const OneCall L = one_call_layout(bytes, tab_h.size(), n_pairs);
+    if (!workspace || workspace_bytes < L.total) return FMBYM_EWORKSPACE;
+    char* ws = (char*)workspace;
+    const float** tab = (const float**)(ws + L.tab_off);
+    int* slot_pair = (int*)(ws + L.slot_off);
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long* st = (unsigned long long*)stamps;
+    // the tables go into the workspace in stream order (the host vectors may be
+    // released once the copies return: pageable sources are staged by then)
+    hipError_t e = hipMemcpyAsync(tab, tab_h.data(), sizeof(const float*) * tab_h.size(),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(slot_pair, slots.data(), sizeof(int) * (size_t)n_pairs, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e);
+    if (st) hipLaunchKernelGGL(k_ragged_start, dim3(1), dim3(64), 0, s, st, n_pairs);
+    fmbym_mask_desc net_copy{};
+    if (net) net_copy = *net;
+    for (const Group& gr : groups) {
+        float* pose_g = (float*)(ws + gr.pose_off);
+        if (gr.kind == kNet) {
+            rc = mask_forward(&net_copy, 2 * gr.count, gr.plan->p.n, nullptr,
+                              tab + 4 * (size_t)n_pairs + gr.xtab_first, (float*)(ws + gr.mask_off),
+                              ws + gr.act_off, gr.act_bytes, 0, s);
+            if (rc) return rc;
+        }
+        rc = launch_forward(*gr.plan, gr.count, nullptr, nullptr, nullptr, nullptr, pose_g, nullptr, nullptr,
+                            nullptr, ws + gr.ws_off, s, tab + 4 * (size_t)gr.first);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_ragged_poses, dim3((gr.count + 63) / 64), dim3(64), 0, s, pose_g,
+                           slot_pair + gr.first, gr.count, pose, st);
+    }
+    e = hipGetLastError();
+    return e == hipSuccess ? FMBYM_OK : hip_fail(e);
 }
 
 int fmbym_ragged_launch(fmbym_ragged rg, void* stream) {

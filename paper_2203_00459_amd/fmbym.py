@@ -50,6 +50,7 @@ EXPORTS = (
     "fmbym_search_backward_state", "fmbym_search_vjp", "fmbym_joint_workspace_size", "fmbym_search_joint",
     "fmbym_plan_get_tuning", "fmbym_plan_set_tuning", "fmbym_autotune_workspace_size", "fmbym_autotune",
     "fmbym_full_circle_workspace_size", "fmbym_search_full_circle",
+    "fmbym_search_ragged_workspace_size", "fmbym_search_ragged",
 )
 FMBYM_LOSS_L1 = 1
 FMBYM_LOSS_L2 = 2
@@ -156,6 +157,10 @@ def lib() -> ctypes.CDLL:
         L.fmbym_ragged_create.argtypes = [ctypes.POINTER(VP), I32, PP, I32, VP, VP, VP, VP, SZ,
                                           ctypes.POINTER(VP)]
         L.fmbym_ragged_create.restype = ctypes.c_int
+        L.fmbym_search_ragged_workspace_size.argtypes = [ctypes.POINTER(VP), I32, PP, I32, VP]
+        L.fmbym_search_ragged_workspace_size.restype = SZ
+        L.fmbym_search_ragged.argtypes = [ctypes.POINTER(VP), I32, PP, I32, VP, VP, VP, VP, SZ, VP]
+        L.fmbym_search_ragged.restype = ctypes.c_int
         L.fmbym_ragged_launch.argtypes = [VP, VP]
         L.fmbym_ragged_launch.restype = ctypes.c_int
         L.fmbym_ragged_destroy.argtypes = [VP]
@@ -174,7 +179,7 @@ def lib() -> ctypes.CDLL:
         L.fmbym_mask_workspace_bytes.restype = SZ
         L.fmbym_mask_fwd.argtypes = [MD, I32, I32, VP, VP, VP, SZ, ctypes.c_int, VP]
         L.fmbym_mask_fwd.restype = ctypes.c_int
-        L.fmbym_mask_bwd.argtypes = [MD, I32, I32, VP, VP, SZ, VP, VP, SZ, VP]
+        L.fmbym_mask_bwd.argtypes = [MD, I32, I32, VP, VP, SZ, VP, VP, VP, SZ, VP]
         L.fmbym_mask_bwd.restype = ctypes.c_int
         L.fmbym_adam.argtypes = [VP, VP, VP, VP, ctypes.c_int64, I32, ctypes.c_float, ctypes.c_float,
                                  ctypes.c_float, ctypes.c_float, VP]
@@ -359,6 +364,20 @@ def ragged_create(plans, pairs, pose, stamps, workspace, workspace_bytes, net=No
     if rc:
         raise FmbymError(rc, "fmbym_ragged_create")
     return h
+
+
+def search_ragged_workspace_size(plans, pairs, net=None) -> int:
+    return int(lib().fmbym_search_ragged_workspace_size(_plan_array(plans), len(plans), pairs, len(pairs),
+                                                        None if net is None else ctypes.addressof(net)))
+
+
+def search_ragged(plans, pairs, pose, stamps, workspace, workspace_bytes, stream, net=None) -> None:
+    """fmbym_search_ragged: the work list searched in one call (no launch object)."""
+    rc = lib().fmbym_search_ragged(_plan_array(plans), len(plans), pairs, len(pairs),
+                                   None if net is None else ctypes.addressof(net), pose, stamps, workspace,
+                                   int(workspace_bytes), stream)
+    if rc:
+        raise FmbymError(rc, "fmbym_search_ragged")
 
 
 def ragged_launch(ragged, stream) -> None:
@@ -560,6 +579,44 @@ class SearchFunction(torch.autograd.Function):
         return None, r["d_f"], r["d_g"], r["d_m_f"], r["d_m_g"]
 
 
+def pair_array(pairs, net=None):
+    """A ctypes fmbym_pair array of (f, g), (f, g, m_f, m_g) or (f, g, "net")
+    device tensors, and their device."""
+    arr = (fmbym_pair * len(pairs))()
+    dev = None
+    for i, q in enumerate(pairs):
+        f, g = q[0], q[1]
+        n = f.shape[-1]
+        if len(q) == 3 and isinstance(q[2], str):
+            if q[2] != "net" or net is None:
+                raise ValueError("a (f, g, 'net') pair needs the net argument")
+            arr[i] = fmbym_pair(n, FMBYM_PAIR_NET_MASK, _ptr(f, (n, n), "f"), _ptr(g, (n, n), "g"), None, None)
+        else:
+            m_f, m_g = (q[2], q[3]) if len(q) > 2 else (None, None)
+            arr[i] = fmbym_pair(n, 0, _ptr(f, (n, n), "f"), _ptr(g, (n, n), "g"),
+                                _ptr(m_f, (n, n), "m_f"), _ptr(m_g, (n, n), "m_g"))
+        dev = f.device
+    return arr, dev
+
+
+def ragged_search(searches, pairs, net: "MaskNet | None" = None, stamps: bool = False):
+    """The one-call ragged search (fmbym_search_ragged): poses [P, 3] of a mixed
+    list of pairs, as ``Ragged`` would give them, without a launch object.
+    With stamps, returns (poses, stamps [P + 1])."""
+    arr, dev = pair_array(pairs, net)
+    plans = [s.plan for s in searches]
+    desc = None if net is None else net.desc
+    need = search_ragged_workspace_size(plans, arr, desc)
+    if need == 0:
+        raise FmbymError(FMBYM_EINVAL, "fmbym_search_ragged_workspace_size")
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    pose = torch.empty(len(pairs), 3, device=dev)
+    st = torch.zeros(len(pairs) + 1, dtype=torch.int64, device=dev) if stamps else None
+    search_ragged(plans, arr, pose.data_ptr(), None if st is None else st.data_ptr(), ws.data_ptr(), need,
+                  _stream(), desc)
+    return (pose, st) if stamps else pose
+
+
 class Ragged:
     """A ragged work list (pairs of mixed sizes) as one replayable launch.
 
@@ -575,23 +632,8 @@ class Ragged:
     def __init__(self, searches, pairs, stamps: bool = True, net: "MaskNet | None" = None):
         self.searches = list(searches)
         self.net = net
-        self._keep = []
-        arr = (fmbym_pair * len(pairs))()
-        dev = None
-        for i, q in enumerate(pairs):
-            f, g = q[0], q[1]
-            n = f.shape[-1]
-            if len(q) == 3 and isinstance(q[2], str):
-                if q[2] != "net" or net is None:
-                    raise ValueError("a (f, g, 'net') pair needs the net argument")
-                arr[i] = fmbym_pair(n, FMBYM_PAIR_NET_MASK, _ptr(f, (n, n), "f"), _ptr(g, (n, n), "g"),
-                                    None, None)
-            else:
-                m_f, m_g = (q[2], q[3]) if len(q) > 2 else (None, None)
-                arr[i] = fmbym_pair(n, 0, _ptr(f, (n, n), "f"), _ptr(g, (n, n), "g"),
-                                    _ptr(m_f, (n, n), "m_f"), _ptr(m_g, (n, n), "m_g"))
-            self._keep.append(q)
-            dev = f.device
+        self._keep = list(pairs)
+        arr, dev = pair_array(pairs, net)
         plans = [s.plan for s in self.searches]
         desc = None if net is None else net.desc
         need = ragged_workspace_size(plans, arr, desc)
@@ -661,9 +703,9 @@ def mask_fwd(desc, images, n, x, mask, act, act_bytes, training, stream) -> None
                                 int(bool(training)), stream), "fmbym_mask_fwd")
 
 
-def mask_bwd(desc, images, n, d_mask, act, act_bytes, d_params, ws, ws_bytes, stream) -> None:
+def mask_bwd(desc, images, n, d_mask, act, act_bytes, d_params, ws, ws_bytes, stream, d_x=None) -> None:
     _check(lib().fmbym_mask_bwd(ctypes.byref(desc), int(images), int(n), d_mask, act, int(act_bytes),
-                                d_params, ws, int(ws_bytes), stream), "fmbym_mask_bwd")
+                                d_params, d_x, ws, int(ws_bytes), stream), "fmbym_mask_bwd")
 
 
 def adam(params, grad, m, v, count, step, lr, beta1, beta2, eps, stream) -> None:
@@ -728,15 +770,18 @@ class MaskNet:
         self._shape = (I, n)
         return mask
 
-    def backward(self, d_mask):
-        """dL/dparams (flat FP32) of the last training forward, given dL/dmask."""
+    def backward(self, d_mask, input_grad: bool = False):
+        """dL/dparams (flat FP32) of the last training forward, given dL/dmask;
+        with input_grad, the pair (dL/dparams, dL/dx)."""
         I, n = self._shape
         need = mask_workspace_bytes(self.desc, I, n)
         ws = self._buf("_ws", need, d_mask.device)
         d_params = torch.empty_like(self.params)
+        d_x = torch.empty(I, n, n, device=d_mask.device) if input_grad else None
         mask_bwd(self.desc, I, n, _ptr(d_mask.contiguous(), (I, n, n), "d_mask"), self._act.data_ptr(),
-                 self._act.numel(), d_params.data_ptr(), ws.data_ptr(), ws.numel(), _stream())
-        return d_params
+                 self._act.numel(), d_params.data_ptr(), ws.data_ptr(), ws.numel(), _stream(),
+                 d_x=None if d_x is None else d_x.data_ptr())
+        return (d_params, d_x) if input_grad else d_params
 
     def adam_step(self, grad, lr: float, beta1: float = 0.9, beta2: float = 0.999,
                   eps: float = 1e-8) -> None:

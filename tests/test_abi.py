@@ -122,7 +122,7 @@ def test_mask_calls_reject_bad_arguments():
     assert fmbym.mask_param_count(bad) == 0
     assert L.fmbym_mask_fwd(ctypes.byref(bad), 1, 128, None, None, None, 0, 1, None) == fmbym.FMBYM_EUNSUPPORTED
     assert L.fmbym_mask_fwd(ctypes.byref(d), 1, 128, None, None, None, 0, 1, None) == fmbym.FMBYM_EINVAL
-    assert L.fmbym_mask_bwd(None, 1, 128, None, None, 0, None, None, 0, None) == fmbym.FMBYM_EINVAL
+    assert L.fmbym_mask_bwd(None, 1, 128, None, None, 0, None, None, None, 0, None) == fmbym.FMBYM_EINVAL
     assert L.fmbym_mask_pack(ctypes.byref(d), None) == fmbym.FMBYM_EINVAL
     assert L.fmbym_adam(None, None, None, None, 1, 1, 1e-3, 0.9, 0.999, 1e-8, None) == fmbym.FMBYM_EINVAL
     assert L.fmbym_pose_loss(1, None, None, 2, None, None, None) == fmbym.FMBYM_EINVAL

@@ -97,6 +97,29 @@ def test_backward_matches_oracle(levels, scene, images):
     print(f"  worst |gpu-exact| / (|quant-exact| + 1e-3) over groups: {worst:.3f}", flush=True)
 
 
+@pytest.mark.parametrize("levels,scene,images", [(1, "pair128", 4), (4, "mask256", 4)])
+def test_input_gradient_matches_oracle(levels, scene, images):
+    """d_x of fmbym_mask_bwd: the first convolution's adjoint on top of the rest,
+    against FP64 autograd with respect to the scans, on the same bar."""
+    x = _scans(scene, images)
+    n = x.shape[-1]
+    p, net = _gpu_net(levels, seed=2)
+    dm = np.random.Generator(np.random.PCG64(9)).normal(size=(images, n, n)).astype(np.float32)
+    print(f"mask input grad levels={levels} scene={scene} images={images}", flush=True)
+    net.forward(torch.from_numpy(x).to(DEV))
+    g_p, g_x = net.backward(torch.from_numpy(dm).to(DEV), input_grad=True)
+    g_x = g_x.double().cpu()
+    assert torch.equal(g_p, net.backward(torch.from_numpy(dm).to(DEV)))   # d_x changes nothing else
+    X, D, P = torch.from_numpy(x).to(DT), torch.from_numpy(dm).to(DT), torch.from_numpy(p).to(DT)
+    ref = M.grad_input(X, D, P, levels, 8)
+    ref_q = M.grad_input(X, D, P, levels, 8, quant=True)
+    nr = float(ref.norm())
+    eg = float((g_x - ref).norm()) / nr
+    eq = float((ref_q - ref).norm()) / nr
+    print(f"  |gpu-exact| {eg:.3e} |quant-exact| {eq:.3e} (normwise relative)", flush=True)
+    assert eg <= 2 * eq + 1e-3
+
+
 def test_running_statistics_and_eval_mode():
     levels, images = 2, 4
     x = _scans("pair128", images)

@@ -107,7 +107,7 @@ def test_every_output_element_is_written(name, B, masked):
 
 @pytest.mark.parametrize("n,images", [(128, 3), (256, 2)])
 def test_mask_network_outputs_are_written(n, images):
-    """fmbym_mask_fwd (masks), fmbym_mask_bwd (parameter gradients) and
+    """fmbym_mask_fwd (masks), fmbym_mask_bwd (parameter and input gradients) and
     fmbym_pose_loss (loss and its gradient), each into NaN-filled buffers."""
     from paper_2203_00459_amd.train import he_init
     print(f"mask network n={n} images={images}", flush=True)
@@ -122,15 +122,16 @@ def test_mask_network_outputs_are_written(n, images):
     ws_bytes = fmbym.mask_workspace_bytes(net.desc, images, n)
     ws = _bytes(ws_bytes)
     d_params = torch.full_like(net.params, float("nan"))
+    d_x = _nan(images, n, n)
     fmbym.mask_bwd(net.desc, images, n, d_mask.data_ptr(), act.data_ptr(), act_bytes, d_params.data_ptr(),
-                   ws.data_ptr(), ws_bytes, stream)
+                   ws.data_ptr(), ws_bytes, stream, d_x=d_x.data_ptr())
     pose = torch.from_numpy(np.random.default_rng(4).normal(size=(images, 3)).astype(np.float32)).to(DEV)
     target = torch.zeros(images, 3, device=DEV)
     loss, d_pose = _nan(1), _nan(images, 3)
     fmbym.pose_loss(images, pose.data_ptr(), target.data_ptr(), fmbym.FMBYM_LOSS_L1, loss.data_ptr(),
                     d_pose.data_ptr(), stream)
     torch.cuda.synchronize()
-    for k, v in dict(mask=mask, d_params=d_params, loss=loss, d_pose=d_pose).items():
+    for k, v in dict(mask=mask, d_params=d_params, d_x=d_x, loss=loss, d_pose=d_pose).items():
         bad = int((~torch.isfinite(v)).sum())
         print(f"  {k}: {tuple(v.shape)} non-finite {bad}", flush=True)
         assert bad == 0, k

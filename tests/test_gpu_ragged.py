@@ -155,3 +155,25 @@ def test_ragged_rejects_a_size_without_a_plan():
     pairs = _work_list(["pair128", "batch256"])
     with pytest.raises(fmbym.FmbymError):
         fmbym.Ragged([searches["pair128"]], pairs)
+
+
+def test_one_call_ragged_search_equals_the_launch_object():
+    """fmbym_search_ragged (no launch object, no graph): the same poses as the
+    captured launch, bit for bit, for a list with unmasked, caller-masked and
+    network-masked pairs of the three sizes; twice, the second on a shorter list."""
+    from paper_2203_00459_amd.train import he_init
+    searches = _searches()
+    net = fmbym.MaskNet(he_init(4, 8, seed=6), levels=4)
+    base = _work_list(NAMES, masked_every=3)
+    pairs = [(q[0], q[1], "net") if i % 4 == 1 else tuple(q) for i, q in enumerate(base)]
+    for rep, sub in enumerate((pairs, pairs[2:7])):
+        r = fmbym.Ragged([searches[k] for k in SIZES], sub, net=net)
+        ref = r.launch().clone()
+        pose, st = fmbym.ragged_search([searches[k] for k in SIZES], sub, net=net, stamps=True)
+        torch.cuda.synchronize()
+        print(f"one-call ragged {rep} ({len(sub)} pairs): max |diff| {(pose - ref).abs().max().item()}",
+              flush=True)
+        assert torch.equal(pose, ref)
+        lat = (st[:-1] - st[-1]).double()
+        assert bool((lat > 0).all())
+        r.close()

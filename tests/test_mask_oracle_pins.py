@@ -141,6 +141,25 @@ def test_gradient_matches_central_differences():
     assert abs(float(fd) - float(g @ v)) <= 1e-6 * max(1.0, abs(float(fd)))
 
 
+def test_input_gradient_matches_central_differences():
+    """The input gradient (what fmbym_mask_bwd returns as d_x) against central
+    differences of the FP64 forward, one scan pixel at a time (a perturbation of
+    every pixel at once can carry a ReLU or max-pool switch inside +-h)."""
+    r = _rng(16)
+    L, base = 2, 2
+    x = torch.tensor(r.random((2, 8, 8)), dtype=DT)
+    th = torch.tensor(M.init_params(L, base, seed=3), dtype=DT)
+    dm = torch.tensor(r.normal(size=(2, 8, 8)), dtype=DT)
+    g = M.grad_input(x, dm, th, L, base)
+    assert g.shape == x.shape
+    h = 1e-5
+    for idx in [(0, 3, 3), (1, 0, 0), (0, 7, 2), (1, 5, 6), (0, 0, 7), (1, 7, 7)]:
+        e = torch.zeros_like(x)
+        e[idx] = 1.0
+        fd = ((M.forward(x + h * e, th, L, base) - M.forward(x - h * e, th, L, base)) * dm).sum() / (2 * h)
+        assert abs(float(fd) - float(g[idx])) <= 1e-6 * max(1.0, abs(float(fd))), idx
+
+
 def test_pose_losses_and_adam_closed_forms():
     p = torch.tensor([[0.1, 1.0, -2.0], [0.0, 0.5, 0.5]], dtype=DT)
     t = torch.tensor([[0.0, 0.0, 0.0], [0.2, 0.5, 1.5]], dtype=DT)
