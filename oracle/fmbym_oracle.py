@@ -13,10 +13,12 @@ Everything is plain, slow and written to be read against the paper:
     itself pinned by the tests);
   * gradients come from torch autograd over this same FP64 code.
 
-Conventions.  Scans are [n, n] arrays; row i is y = (i - n/2) delta and column
-j is x = (j - n/2) delta; the sensor is pixel (n/2, n/2).  R(theta) rotates x
-toward y.  The pose satisfies Eq. 1, f(x) ~= g(R x + t).  Forward DFTs are
-unnormalised, inverse DFTs carry 1/n per axis.
+Conventions.  Scans are [n, n] arrays; row i is y = (i - c) delta and column
+j is x = (j - c) delta with the origin pixel c = floor(n/2) (n/2 for the even
+sizes, (n - 1)/2 for the odd sizes the paper measures); the sensor is pixel
+(c, c).  R(theta) rotates x toward y.  The pose satisfies Eq. 1,
+f(x) ~= g(R x + t).  Forward DFTs are unnormalised, inverse DFTs carry 1/n
+per axis.
 
 Readings of passages that the paper leaves open (all shared with the HIP
 library, which implements the same definitions):
@@ -27,16 +29,19 @@ library, which implements the same definitions):
     correlation along angle per radius, averaged over radius (Algorithm 1's
     "Mean over r").  The marginal reading is available as ``angle_marginal``.
   * Candidate grids are the lag grids theta_l = l pi / n_theta and
-    t' = s delta with l, s in [-n/2, n/2) (Algorithm 1's Linspace lists).
+    t' = s delta with l, s in [-floor(n/2), n - 1 - floor(n/2)] (Algorithm 1's
+    Linspace lists): [-n/2, n/2) for even n, symmetric for odd n.
   * The Hann window is the periodic one, applied as an outer product; stage 2
-    uses the windowed scans (Algorithm 1 reassigns f and g).
+    uses the windowed scans (Algorithm 1 reassigns f and g).  Written about the
+    origin pixel, h[k] = (1 + cos(2 pi (k - c) / n)) / 2, which is the periodic
+    Hann for even n and its symmetric counterpart about c for odd n.
   * The band-pass is a hard annulus band_lo <= |k|/n <= band_hi in cycles per
     pixel (disabled when band_hi <= 0).
   * Polar grid: n_theta angles over [0, pi) and n_r radii over [0, n/2) bins;
     bilinear on the lattice with indices taken modulo n.
-  * Rotate samples g at R(theta) y about the centre pixel with zeros outside.
+  * Rotate samples g at R(theta) y about the origin pixel with zeros outside.
   * ZeroPad pads to 2n, so c_xy is the exact linear correlation for every lag
-    in the [-n/2, n/2)^2 window.
+    of the window (the lag grid above, on both axes).
   * The frame change is t = R(theta) t' (Eq. 1 together with the conventions
     above; Algorithm 1's BuildSO2(-theta) matches the reversed correlation
     order).
@@ -118,13 +123,20 @@ def hann_periodic(n: int) -> torch.Tensor:
     return 0.5 * (1.0 - torch.cos(2.0 * math.pi * k / n))
 
 
+def hann_centred(n: int) -> torch.Tensor:
+    """h[k] = (1 + cos(2 pi (k - c) / n)) / 2 about the origin pixel c = floor(n/2):
+    the periodic Hann for even n, peaked at and symmetric about c for odd n."""
+    k = torch.arange(n, dtype=F64) - (n // 2)
+    return 0.5 * (1.0 + torch.cos(2.0 * math.pi * k / n))
+
+
 def hann2d(n: int) -> torch.Tensor:
-    h = hann_periodic(n)
+    h = hann_centred(n)
     return h[:, None] * h[None, :]
 
 
 def signed_freq(n: int) -> torch.Tensor:
-    """Frequency index of DFT bin k, mapped to [-n/2, n/2)."""
+    """Frequency index of DFT bin k, mapped to [-n/2, n/2) (odd n: [-(n-1)/2, (n-1)/2])."""
     k = torch.arange(n, dtype=torch.int64)
     return torch.where(k < (n + 1) // 2, k, k - n) if n % 2 else torch.where(k < n // 2, k, k - n)
 
@@ -196,26 +208,28 @@ def cart2pol(a: torch.Tensor, n_r: int, n_theta: int) -> torch.Tensor:
 
 
 def rotate(g: torch.Tensor, theta: torch.Tensor) -> torch.Tensor:
-    """g'(y) = g(R(theta) y) about the centre pixel, bilinear, zeros outside (Algorithm 1, Rotate)."""
+    """g'(y) = g(R(theta) y) about the origin pixel floor(n/2), bilinear, zeros outside
+    (Algorithm 1, Rotate)."""
     n = g.shape[-1]
-    c = torch.arange(n, dtype=F64) - n / 2.0
+    o = n // 2
+    c = torch.arange(n, dtype=F64) - o
     yx = c[None, :].expand(n, n)            # x offset of output pixel [i, j]
     yy = c[:, None].expand(n, n)            # y offset
     ct, st = torch.cos(theta), torch.sin(theta)
     px = ct * yx - st * yy
     py = st * yx + ct * yy
-    return bilinear_zero(g, py + n / 2.0, px + n / 2.0)
+    return bilinear_zero(g, py + o, px + o)
 
 
 # -------------------------------------------------------------- correlations
 
 def lag_indices(n: int) -> torch.Tensor:
-    """Lags -n/2 .. n/2-1 in storage order."""
+    """Lags -floor(n/2) .. n - 1 - floor(n/2) in storage order ([-n/2, n/2) for even n)."""
     return torch.arange(n, dtype=torch.int64) - n // 2
 
 
 def angle_correlation(pf: torch.Tensor, pg: torch.Tensor) -> torch.Tensor:
-    """c[l] = (1/n_r) sum_b sum_a pf[b, a] pg[b, (a + l) mod n_theta] for l in [-n/2, n/2) (Eq. 8).
+    """c[l] = (1/n_r) sum_b sum_a pf[b, a] pg[b, (a + l) mod n_theta] for l on the lag grid (Eq. 8).
 
     The defining sum, evaluated one lag at a time (wrap padding along angle).
     """
@@ -233,9 +247,9 @@ def angle_correlation_marginal(pf: torch.Tensor, pg: torch.Tensor) -> torch.Tens
 
 
 def xy_correlation_direct(fw: torch.Tensor, gp: torch.Tensor) -> torch.Tensor:
-    """c[s] = sum_x fw[x] gp[x + s], linear (zero outside), s in [-n/2, n/2)^2 (Eq. 3 on the lattice).
-
-    Storage [i, j] holds lag (s_y, s_x) = (i - n/2, j - n/2).  O(n^4): tiny n only.
+    """c[s] = sum_x fw[x] gp[x + s], linear (zero outside), s on the lag grid squared (Eq. 3 on
+    the lattice).  Storage [i, j] holds lag (s_y, s_x) = (i - floor(n/2), j - floor(n/2)).
+    O(n^4): tiny n only.
     """
     n = fw.shape[-1]
     lags = lag_indices(n).tolist()
@@ -439,7 +453,8 @@ def joint_scores(fw: torch.Tensor, gw: torch.Tensor, thetas, n_lag: int) -> torc
     [-n_lag/2, n_lag/2)^2 in pixels.  Direct sums: tiny n only.
     """
     n = fw.shape[-1]
-    c = torch.arange(n, dtype=F64) - n / 2.0
+    o = n // 2
+    c = torch.arange(n, dtype=F64) - o
     xx = c[None, :].expand(n, n)
     yy = c[:, None].expand(n, n)
     lags = lag_indices(n_lag).tolist()
@@ -450,7 +465,7 @@ def joint_scores(fw: torch.Tensor, gw: torch.Tensor, thetas, n_lag: int) -> torc
         py = st * xx + ct * yy
         for iy, sy in enumerate(lags):
             for ix, sx in enumerate(lags):
-                v = bilinear_zero(gw, py + sy + n / 2.0, px + sx + n / 2.0)
+                v = bilinear_zero(gw, py + sy + o, px + sx + o)
                 out[k, iy, ix] = (fw * v).sum()
     return out
 

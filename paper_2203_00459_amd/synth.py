@@ -7,8 +7,8 @@ the HIP path may consume its output.
 Data model (Section III-A, Eq. 1): a world point at ``x`` in the frame of scan
 ``f`` appears at ``x' = R(theta*) x + t*`` in the frame of scan ``g``, so that
 ``f(x) ~= g(R x + t)``.  Pixel ``[i, j]`` of an ``n x n`` scan sits at
-``x = (j - n/2) * delta`` and ``y = (i - n/2) * delta`` metres; the sensor is at
-pixel ``(n/2, n/2)``.
+``x = (j - c) * delta`` and ``y = (i - c) * delta`` metres with ``c = n // 2``
+(``n/2`` for even n, ``(n - 1)/2`` for odd n); the sensor is at pixel ``(c, c)``.
 
 The real scans the method was evaluated on (a public FMCW radar dataset) are
 not available, so these scenes stand in for them: non-negative power images
@@ -51,6 +51,10 @@ WORKLOADS = {
     "batch256": SceneSpec(n=256, delta=0.35, n_reflectors=60, n_segments=20, speckle_sigma=0.15),
     # batches at 512 x 512, 0.2 m/px (102.4 m field of view), same scene density
     "batch512": SceneSpec(n=512, delta=0.2, n_reflectors=60, n_segments=20, speckle_sigma=0.15),
+    # the paper's three measured sizes (odd sides, about 102 m across each), c3's scene density
+    "paper127": SceneSpec(n=127, delta=0.8, n_reflectors=60, n_segments=20, speckle_sigma=0.15),
+    "paper255": SceneSpec(n=255, delta=0.4, n_reflectors=60, n_segments=20, speckle_sigma=0.15),
+    "paper511": SceneSpec(n=511, delta=0.2, n_reflectors=60, n_segments=20, speckle_sigma=0.15),
     # mask-training pairs at 256 x 256 with moving clutter and multipath ghosts
     "mask256": SceneSpec(n=256, delta=0.35, n_reflectors=60, n_segments=20, speckle_sigma=0.15,
                          distractors=True),
@@ -71,7 +75,7 @@ def _rot(theta: float) -> np.ndarray:
 
 def _to_px(p: np.ndarray, n: int, delta: float) -> np.ndarray:
     """World metres (x, y) -> fractional pixel (col, row)."""
-    return p / delta + n / 2.0
+    return p / delta + (n // 2)
 
 
 def _splat_gaussian(img: np.ndarray, col: float, row: float, amp: float, sigma: float) -> None:
@@ -151,7 +155,7 @@ def _render(spec: SceneSpec, world: _World, rot: np.ndarray, t: np.ndarray) -> n
 
 def _falloff(spec: SceneSpec) -> np.ndarray:
     n, delta = spec.n, spec.delta
-    c = (np.arange(n) - n / 2.0) * delta
+    c = (np.arange(n) - n // 2) * delta
     r = np.sqrt(c[None, :] ** 2 + c[:, None] ** 2)
     with np.errstate(divide="ignore"):
         return np.minimum(1.0, np.where(r > 0, spec.falloff_m / np.maximum(r, 1e-12), 1.0))

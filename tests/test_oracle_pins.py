@@ -572,3 +572,134 @@ def test_zscore_search_ignores_the_scale_of_the_scans():
     np.testing.assert_allclose(a.numpy(), b.numpy(), rtol=0, atol=1e-12)
     a, b = O.search(f, g, pr)["pose"], O.search(7.0 * f, g, pr)["pose"]
     assert float((a - b).abs().max()) > 1e-3
+
+
+# ------------------------------------------- odd sizes (127 / 255 / 511 px, 733 angle bins)
+
+def test_centred_hann_is_the_periodic_hann_for_even_n_and_symmetric_for_odd_n():
+    """The window written about the origin pixel c = floor(n/2) is the periodic Hann for
+    even n; for odd n it peaks at c and is mirror symmetric about it."""
+    for n in (16, 32, 128):
+        np.testing.assert_allclose(O.hann_centred(n).numpy(), O.hann_periodic(n).numpy(), atol=1e-15)
+    for n in (15, 127):
+        h = O.hann_centred(n).numpy()
+        c = n // 2
+        assert h[c] == 1.0
+        np.testing.assert_allclose(h[c + 1:], h[:c][::-1], atol=1e-15)
+        # half a period from the peak the cosine is -cos(pi / n): the window is small but not zero
+        assert abs(h[0] - 0.5 * (1.0 - math.cos(math.pi / n))) < 1e-15
+
+
+def test_odd_size_spectra():
+    """Parseval and shift invariance (Eq. 5-7) at odd sizes, against numpy's FFT."""
+    for n in (15, 21):
+        f = rnd(n, n, seed=40 + n)
+        F = O.dft2(f)
+        np.testing.assert_allclose(F.numpy(), np.fft.fft2(f.numpy()), atol=1e-10)
+        assert abs(float((f ** 2).sum()) - float((F.abs() ** 2).sum()) / n ** 2) < 1e-10
+        g = torch.roll(f, shifts=(4, -7), dims=(0, 1))
+        np.testing.assert_allclose(O.dft2(g).abs().numpy(), F.abs().numpy(), atol=1e-10)
+
+
+def test_odd_size_rotate_quarter_turn_about_the_origin_pixel():
+    """For odd n the origin pixel c = (n - 1)/2 is the lattice centre, so a quarter turn maps
+    every pixel onto a pixel: g'(y) = g(R y) reads column c - (i - c), row c + (j - c)."""
+    n = 15
+    c = n // 2
+    g = rnd(n, n, seed=50)
+    gq = O.rotate(g, torch.tensor(math.pi / 2, dtype=F64))
+    for i in range(n):
+        for j in range(n):
+            # y = (j - c, i - c) -> R y = (-(i - c), j - c) -> column c - (i - c), row c + (j - c)
+            assert abs(float(gq[i, j]) - float(g[c + (j - c), c - (i - c)])) < 1e-12
+
+
+def test_odd_lag_grid_is_symmetric():
+    """Odd n: lags -(n-1)/2 .. (n-1)/2, so a flat score surface averages to exactly zero
+    (the even-n grid mean is -delta/2 instead)."""
+    assert O.lag_indices(7).tolist() == [-3, -2, -1, 0, 1, 2, 3]
+    n, n_t = 15, 9
+    f = torch.zeros(n, n, dtype=F64)
+    f[n // 2, n // 2] = 1.0                      # |F| = 1 everywhere: c_theta flat
+    p = O.Params(n=n, n_theta=n_t, delta_xy=0.5)
+    out = O.search(f, f.clone(), p)
+    ct = out["c_theta"].numpy()
+    np.testing.assert_allclose(ct, ct[0], atol=1e-12)
+    assert abs(float(out["theta"])) < 1e-15
+    z = O.search(torch.zeros(n, n, dtype=F64), torch.zeros(n, n, dtype=F64), p)
+    assert abs(float(z["theta"])) < 1e-15 and abs(float(z["tx"])) < 1e-15 and abs(float(z["ty"])) < 1e-15
+
+
+def test_odd_size_angle_correlation_defining_sum():
+    """Eq. 8 at an odd number of bins (7): pure-Python circular sums over the symmetric lags."""
+    n_r, n_t = 3, 7
+    pf, pg = rnd(n_r, n_t, seed=51), rnd(n_r, n_t, seed=52)
+    a, b = pf.numpy(), pg.numpy()
+    want = [sum(a[r, i] * b[r, (i + l) % n_t] for r in range(n_r) for i in range(n_t)) / n_r
+            for l in range(-3, 4)]
+    np.testing.assert_allclose(O.angle_correlation(pf, pg).numpy(), want, atol=1e-12)
+
+
+def test_odd_size_integer_shift_is_recovered_exactly():
+    """Compact scene, no window, integer translation at n = 31: theta = 0 and t = s delta."""
+    n = 31
+    f = _blob_scene(n, [(12, 14), (18, 11), (15, 20), (10, 9)], [1.0, 0.7, 0.5, 0.9])
+    for s in [(3, -2), (-4, 5)]:
+        g = torch.roll(f, shifts=s, dims=(0, 1))
+        p = O.Params(n=n, n_theta=33, delta_xy=0.25, temp_theta=1e-6, temp_xy=1e-6, hann=False)
+        out = O.search(f, g, p)
+        assert int(torch.argmax(out["c_theta"])) == 16          # lag 0 of 33
+        assert abs(float(out["theta"])) < 1e-12
+        iy, ix = np.unravel_index(int(torch.argmax(out["c_xy"])), (n, n))
+        assert (iy - n // 2, ix - n // 2) == s
+        assert abs(float(out["tx"]) - 0.25 * s[1]) < 1e-9 and abs(float(out["ty"]) - 0.25 * s[0]) < 1e-9
+
+
+def test_odd_size_decoupled_search_agrees_with_joint_brute_force():
+    """Eq. 2-3 brute force vs the decoupled search at n = 31: within a bin and a pixel; both
+    land on the generator's pose (the origin pixel is shared by scenes, Rotate and lags)."""
+    n, n_t = 31, 63
+    spec = synth.SceneSpec(n=n, delta=1.0, n_reflectors=12, n_segments=3, speckle_sigma=0.02,
+                           theta_max_deg=12.0, t_max_m=3.0)
+    for i in range(2):
+        f, g, pose = synth.make_pair(spec, 98, "test", i)
+        p = O.Params(n=n, n_theta=n_t, delta_xy=1.0, temp_theta=1e-3, temp_xy=1e-3)
+        dec = O.search(f, g, p)
+        thetas = [k * math.pi / n_t for k in range(-8, 9)]
+        joint = O.joint_search(f, g, O.Params(n=n, n_theta=n_t, delta_xy=1.0, hann=False), thetas,
+                               n_lag=11)
+        assert abs(joint["theta"] - pose[0]) <= math.pi / n_t
+        assert abs(joint["tx"] - pose[1]) <= 1.0 and abs(joint["ty"] - pose[2]) <= 1.0
+        assert abs(float(dec["theta"]) - joint["theta"]) <= math.pi / n_t + 1e-12
+        assert abs(float(dec["tx"]) - joint["tx"]) <= 1.0 + 1e-9
+        assert abs(float(dec["ty"]) - joint["ty"]) <= 1.0 + 1e-9
+
+
+def test_generator_origin_is_the_origin_pixel():
+    """The scene generator puts world (0, 0) at pixel (floor(n/2), floor(n/2)) for even and
+    odd sides, the oracle's origin, and a point at (x, y) metres x / delta pixels to the right
+    and y / delta rows down from it."""
+    for n, d in ((127, 0.8), (128, 0.5), (511, 0.2)):
+        np.testing.assert_allclose(synth._to_px(np.zeros(2), n, d), [n // 2, n // 2], atol=0)
+        np.testing.assert_allclose(synth._to_px(np.array([2 * d, -3 * d]), n, d),
+                                   [n // 2 + 2, n // 2 - 3], atol=1e-12)
+
+
+def test_known_pose_pairs_at_the_papers_127_px():
+    """Eq. 1 end to end at the paper's smallest size (127 px, 0.8 m/px, 733 bins, T_theta = 2):
+    generated pairs come back within 1.5 degrees (median 0.5) and within a pixel.  At 127 px
+    the magnitude spectra are coarse: the oracle's own heading error reaches about 1.2 degrees
+    on these scenes at any temperature or bin count, while a sign or frame error would show
+    up as about twice the heading (up to 20 degrees)."""
+    spec = synth.WORKLOADS["paper127"]
+    n_t = 733
+    th_err, t_err = [], []
+    for i in range(6):
+        f, g, pose = synth.make_pair(spec, 5, "val", i)
+        p = O.Params(n=127, n_theta=n_t, delta_xy=0.8, temp_theta=2.0, band_lo=0.02, band_hi=0.4,
+                     temp_xy=0.05)
+        est = O.search(f, g, p)["pose"].numpy()
+        th_err.append(abs(est[0] - pose[0]))
+        t_err.append(np.hypot(est[1] - pose[1], est[2] - pose[2]))
+    assert max(th_err) <= math.radians(1.5) and np.median(th_err) <= math.radians(0.5)
+    assert max(t_err) <= 0.8
