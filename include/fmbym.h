@@ -207,6 +207,29 @@ FMBYM_API int fmbym_search_vjp(fmbym_plan plan, int32_t batch, const float* f, c
                                const float* d_pose, float* d_f, float* d_g, float* d_m_f, float* d_m_g,
                                void* workspace, size_t workspace_bytes, void* stream);
 
+/* ---------------------------------------------------------------- without allocation
+ *
+ * For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): fmbym_search with its
+ * workspace in a static device array of the library, FMBYM_NOALLOC_SCRATCH_BYTES
+ * on every GPU the library runs on, held from module load until the process
+ * ends.  Arguments are those of fmbym_search without the workspace; the
+ * results are fmbym_search's on the same inputs, bit for bit (same kernels).
+ * Returns FMBYM_EWORKSPACE, having enqueued nothing, when the batch's forward
+ * workspace (fmbym_search_workspace_size(plan, batch, 0)) exceeds the array:
+ * at 512 x 512 with 512 angle bins that admits up to 10 pairs, at 256 x 256
+ * with 256 bins 42, at 128 x 128 with 128 bins 160.  FMBYM_EINVAL when the
+ * current device is not the one the plan was created on.  The first call on a
+ * device looks up the array's device address (no allocation); no call
+ * allocates, frees or calls an allocating library routine.  Every call on one
+ * GPU uses the same array and leaves its contents behind: calls that may
+ * overlap on a GPU (several streams or host threads) race, and the caller must
+ * serialise them. */
+#define FMBYM_NOALLOC_SCRATCH_BYTES (64u << 20)
+FMBYM_API int fmbym_search_noalloc(fmbym_plan plan, int32_t batch, const float* f, const float* g,
+                                   const float* m_f, const float* m_g, float* pose, float* c_theta,
+                                   float* c_xy, float* saved, void* stream);
+
 /* ---------------------------------------------------------------- joint comparator
  *
  * The exhaustive search that the decoupling replaces (Eq. 2-3 with the heading

@@ -49,9 +49,10 @@ EXPORTS = (
     "fmbym_adam", "fmbym_pose_loss", "fmbym_search_state_size", "fmbym_search_train",
     "fmbym_search_backward_state", "fmbym_search_vjp", "fmbym_joint_workspace_size", "fmbym_search_joint",
     "fmbym_plan_get_tuning", "fmbym_plan_set_tuning", "fmbym_autotune_workspace_size", "fmbym_autotune",
-    "fmbym_full_circle_workspace_size", "fmbym_search_full_circle",
+    "fmbym_full_circle_workspace_size", "fmbym_search_full_circle", "fmbym_search_noalloc",
     "fmbym_search_ragged_workspace_size", "fmbym_search_ragged",
 )
+FMBYM_NOALLOC_SCRATCH_BYTES = 64 << 20
 FMBYM_LOSS_L1 = 1
 FMBYM_LOSS_L2 = 2
 
@@ -142,6 +143,8 @@ def lib() -> ctypes.CDLL:
         L.fmbym_search_backward_state.restype = ctypes.c_int
         L.fmbym_search_vjp.argtypes = [VP, I32] + [VP] * 8 + [VP, SZ] + [VP] * 5 + [VP, SZ, VP]
         L.fmbym_search_vjp.restype = ctypes.c_int
+        L.fmbym_search_noalloc.argtypes = [VP, I32] + [VP] * 8 + [VP]
+        L.fmbym_search_noalloc.restype = ctypes.c_int
         L.fmbym_strerror.argtypes = [ctypes.c_int]
         L.fmbym_strerror.restype = ctypes.c_char_p
         L.fmbym_last_hip_error.argtypes = []
@@ -225,6 +228,13 @@ def search(plan, batch, f, g, m_f, m_g, pose, c_theta, c_xy, saved, workspace, w
                             int(workspace_bytes), stream)
     if rc:
         raise FmbymError(rc, "fmbym_search")
+
+
+def search_noalloc(plan, batch, f, g, m_f, m_g, pose, c_theta, c_xy, saved, stream) -> None:
+    """fmbym_search_noalloc (the forward on the library's static scratch array)."""
+    rc = lib().fmbym_search_noalloc(plan, int(batch), f, g, m_f, m_g, pose, c_theta, c_xy, saved, stream)
+    if rc:
+        raise FmbymError(rc, "fmbym_search_noalloc")
 
 
 def search_backward(plan, batch, f, g, m_f, m_g, pose, c_theta, c_xy, saved, d_pose, d_f, d_g,
