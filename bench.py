@@ -28,6 +28,9 @@ BF16_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 matrix cores, vendor figure
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_batch512.txt")
+# Table III(a), f-raw (the decoupled search without a mask), Hz at batch 1:
+# (ThinkPad i7 CPU, Jetson Nano) per scan side
+PAPER_F_RAW_HZ = {127: (83.2, 28.3), 255: (58.2, 22.3), 511: (21.0, 9.4)}
 CPU_SECONDS = 10.0          # the CPU baseline keeps adding pairs until this much time has gone
 PROFILE_STEPS = 50          # steps of the event-timed per-kernel pass (its event pool grows with them)
 
@@ -97,6 +100,7 @@ def kernel_bytes(n: int, n_theta: int, n_r: int, batch: int, masked: bool, keep:
     h2 = 3 * n // 4 + 1                     # unique columns of the 3n/2-point stage-2 rows
     rows2 = n * h2 * 16                     # stage-2 row spectra (F, G'), complex64 pairs
     lag = n * h2 * 8                        # stage-2 lag rows, complex64
+    m2 = {127: 192, 255: 384, 511: 768}.get(n, 3 * n // 2)   # odd sides: stage-2 line length
     return {
         # forward
         "k_rows1": batch * (m * 2 * 4 * N2 + half),
@@ -120,6 +124,15 @@ def kernel_bytes(n: int, n_theta: int, n_r: int, batch: int, masked: bool, keep:
         "kb_dmag": batch * (polar + mag),
         "kb_cols_mag": batch * (half + mag + half),
         "kb_rows_final": batch * (half + 2 * N2 * 4 + m * 2 * 4 * N2 + 2 * N2 * 4 + (m - 1) * 2 * N2 * 4),
+        # odd sides (the paper's 127 / 255 / 511 px): stage-1 half spectra of (n + 1)/2
+        # columns, stage 2 padded to m2 = 3 2^b with m2/2 + 1 columns
+        "ko_rows1": batch * (m * 2 * 4 * N2 + n * ((n + 1) // 2) * 16),
+        "ko_cols1": batch * (n * ((n + 1) // 2) * (16 + 8)),
+        "ko_polar": batch * (n * ((n + 1) // 2) * 8),
+        "ko_rotate": batch * (m * 4 * N2 + 4 * N2),
+        "ko_rows2": batch * (m * 4 * N2 + 4 * N2 + n * (m2 // 2 + 1) * 16),
+        "ko_cols2": batch * (n * (m2 // 2 + 1) * (16 + 8)),
+        "ko_rows3": batch * (n * (m2 // 2 + 1) * 8 + 4 * N2),
     }
 
 
@@ -147,6 +160,9 @@ def pass_model_bytes(n: int) -> dict:
         "kb_dmag": 12 * N2,        # CSR transpose gather
         "kb_cols_mag": 20 * N2,    # column adjoint with recomputed F
         "kb_rows_final": 24 * N2,  # final rows + Hann + mask
+        # odd sides: the same passes
+        "ko_rows1": 16 * N2, "ko_cols1": 12 * N2, "ko_polar": 4 * N2, "ko_rows2": 24 * N2,
+        "ko_cols2": 24 * N2, "ko_rows3": 12 * N2,
     }
 
 
@@ -522,7 +538,10 @@ def search_bench(args) -> int:
             with_bwd = False
     d_pose = torch.ones(B, 3, device=dev)
     # column-tile widths measured on this GPU for this workload (untimed; results do not depend on them)
-    tuning, _ = fmbym.plan_autotune(s.plan, B, with_bwd, dev)
+    if n % 2:   # odd sides: no tunable column tiles (their column passes have fixed widths)
+        tuning = fmbym.plan_get_tuning(s.plan)
+    else:
+        tuning, _ = fmbym.plan_autotune(s.plan, B, with_bwd, dev)
     torch.cuda.synchronize()
 
     if args.copy_probe_mb:
@@ -585,6 +604,29 @@ def search_bench(args) -> int:
         ms_pair = e0.elapsed_time(e1) / args.steps
         extra["training_pair_path"] = {"ms_per_step": ms_pair, "value": B / (ms_pair * 1e-3), "unit": "pairs/s",
                                        "calls": "fmbym_search_train, fmbym_search_backward_state"}
+    if n % 2:
+        # the paper's own timing is one pair per call (Table III(a)): the eager
+        # forward at batch 1 on its own plan, beside its ThinkPad / Jetson figures
+        s1 = fmbym.Search(max_batch=1, **kw)
+        f1, g1 = f[:1].contiguous(), g[:1].contiguous()
+        for _ in range(args.warmup):
+            s1.forward(f1, g1, surfaces=False)
+        torch.cuda.synchronize()
+        iters = max(args.steps, 200)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(iters):
+            s1.forward(f1, g1, surfaces=False)
+        e1.record()
+        torch.cuda.synchronize()
+        lat = e0.elapsed_time(e1) / iters
+        s1.close()
+        paper = PAPER_F_RAW_HZ.get(n)
+        extra["batch1"] = {"ms_per_pair": lat, "hz": 1e3 / lat, "calls": "eager fmbym_search, one pair"}
+        if paper:
+            extra["paper_context"] = {"f_raw_hz": {"thinkpad_i7_cpu": paper[0], "jetson_nano": paper[1]},
+                                      "note": "Table III(a): batch 1 on the paper's hardware; context, "
+                                              "not a target"}
     if mode == "fwd" and B == 1:
         # one pair: a captured launch (one HIP graph replay per pair)
         r = fmbym.Ragged([s], [(f[0], g[0])], stamps=False)

@@ -9,18 +9,22 @@
  * on masked scans f o m_f, g o m_g (Eq. 11).
  *
  * Conventions (shared by every entry point)
- *   - Scans are float32, row-major [n][n]; row i is y = (i - n/2) delta_xy and
- *     column j is x = (j - n/2) delta_xy metres; the sensor is pixel (n/2, n/2).
+ *   - Scans are float32, row-major [n][n]; row i is y = (i - c) delta_xy and
+ *     column j is x = (j - c) delta_xy metres with the origin pixel
+ *     c = floor(n/2) (n/2 for even n, (n - 1)/2 for the odd sides the paper
+ *     measures, Section IV-C); the sensor is pixel (c, c).
  *   - pose[b] = {theta (rad), t_x (m), t_y (m)} satisfies Eq. 1.
- *   - c_theta[b][k] is the heading score of lag l = k - n_theta/2, i.e. of the
+ *   - c_theta[b][k] is the heading score of lag l = k - floor(n_theta/2), i.e. of the
  *     candidate theta_l = l pi / n_theta, CENTRED: the mean score over all
  *     lags is subtracted and returned in saved[b][FMBYM_SAVED_THETA_MEAN].  The
  *     scores are sums of products of non-negative magnitudes, so the mean is
  *     orders of magnitude larger than the lag-dependent part that the softmax
  *     sees; computing the centred part without it keeps that part exact to
  *     FP32 rounding of its own size.  c = c_theta + mean recovers the sums.
- *   - c_xy[b][i][j] is the translation score of lag (s_y, s_x) = (i - n/2, j - n/2)
+ *   - c_xy[b][i][j] is the translation score of lag (s_y, s_x) = (i - c, j - c)
  *     pixels, the linear correlation sum_x f_w[x] g'[x + s].
+ *   - The Hann window is (1 + cos(2 pi (k - c) / n)) / 2 per axis: the periodic
+ *     Hann for even n, symmetric about the origin pixel for odd n.
  *   - Forward DFTs are unnormalised; correlation values equal their defining sums.
  *
  * Memory and errors
@@ -83,8 +87,12 @@ typedef struct fmbym_plan_s* fmbym_plan;
 
 /* ScanMatch's parameter list (Algorithm 1) plus the band-pass of its stage 1. */
 typedef struct {
-    int32_t n;          /* scan side: 128, 256 or 512                                     */
-    int32_t n_theta;    /* angle bins over [0, pi): power of two, 16..1024; delta_theta = pi/n_theta */
+    int32_t n;          /* scan side: 128, 256 or 512; or the paper's 127, 255 or 511 (forward
+                           only: the calls below that need the adjoint, the training pair, the
+                           joint and full-circle searches, the autotuner and ragged lists return
+                           FMBYM_EUNSUPPORTED or a zero size for them; no FMBYM_CHECK_FINITE)  */
+    int32_t n_theta;    /* angle bins over [0, pi), delta_theta = pi/n_theta: a power of two in
+                           16..1024, or at the odd sides any count in 16..1024 (the paper's 733) */
     int32_t n_r;        /* polar radii over [0, n/2) frequency bins: 1..4096 (the method uses n) */
     float delta_xy;     /* metres per pixel (> 0)                                         */
     float temp_theta;   /* heading softmax temperature T_theta (> 0)                      */

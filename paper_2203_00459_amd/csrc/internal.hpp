@@ -47,6 +47,12 @@ struct Plan {
     int* csr_dst;
     int* dmag_part;    // [dmag_nparts + 1] first CSR row of each adjoint block
     int dmag_nparts;
+    // Odd sides (forward only): the Bluestein chirp c_j = exp(i pi j^2 / n)
+    // [n], its filter spectrum DFT_M(c wrapped) / M [odd_m1(n)], and the polar
+    // angles (cos, sin)(pi a / n_theta) [n_theta].
+    float2* chirp;
+    float2* bspec;
+    float2* polar_cs;
     fmbym_tuning tune; // column-tile widths of the column passes, batch split
     hipStream_t aux;   // second stream of a split batch (default priority)
     hipEvent_t fork, join;
@@ -68,6 +74,8 @@ inline Plan* plan_cast(fmbym_plan p) { return reinterpret_cast<Plan*>(p); }
 
 // FMBYM_EINVAL unless plan is set and 1 <= batch <= its max_batch.
 int check_call(fmbym_plan plan, int32_t batch);
+// check_call, and FMBYM_EUNSUPPORTED for plans whose path is forward only (odd sides).
+int check_full_path(fmbym_plan plan, int32_t batch);
 
 // Record e as this thread's last HIP error (fmbym_last_hip_error); returns FMBYM_EHIP.
 int hip_fail(hipError_t e);
@@ -105,6 +113,29 @@ constexpr int kRows2Seq = 2;
 // The same for k_rows1 (rows of n points).
 constexpr int kRows1Seq = 2;
 inline int xy_partials_per_pair(int n) { return (n / 2) / rows2_lines(n); }
+
+// ------------------------------------------------------------ odd sides
+//
+// Scan sides 2^a - 1 (the paper's 127, 255 and 511 px) run a forward path of
+// their own (search_odd.hip): stage-1 DFTs of n points by Bluestein's chirp
+// transform over a power-of-two line of odd_m1(n) >= 2n - 1 points, stage 2
+// zero-padded to odd_m2(n) = 3 2^b >= n + (n - 1)/2 points, and the heading
+// correlation over any n_theta as a linear correlation over odd_lt(n_theta)
+// points folded back onto the circle.
+inline bool odd_side(int n) { return n == 127 || n == 255 || n == 511; }
+inline int odd_m1(int n) { return n == 127 ? 256 : n == 255 ? 512 : 1024; }
+inline int odd_m2(int n) { return n == 127 ? 192 : n == 255 ? 384 : 768; }
+inline int odd_lt(int n_theta) {
+    const int need = 2 * n_theta - 1;
+    return need <= 512 ? 512 : need <= 768 ? 768 : need <= 1024 ? 1024 : need <= 1536 ? 1536 : 2048;
+}
+size_t odd_fwd_workspace(const fmbym_params& p, int batch);
+int launch_forward_odd(const Plan& pl, int batch, const float* f, const float* g, const float* mf,
+                       const float* mg, float* pose, float* c_theta, float* c_xy, float* saved, char* ws,
+                       hipStream_t s);
+// The translation soft-argmax's final merge over `ppp` online-softmax partials per pair.
+void launch_xy_fin_parts(const float4* part, int ppp, float temp_xy, float delta_xy, int batch, float* pose,
+                         float* saved, hipStream_t s);
 
 // Workspace carve-up shared by forward and backward launchers.
 struct FwdLayout {
@@ -362,6 +393,66 @@ __device__ __forceinline__ float2 mag_sample(const float2* __restrict__ A, int n
         }
     }
     return acc;
+}
+
+// ------------------------------------------------------------ block reductions
+
+// Deterministic reductions over the first `cnt` threads (a power of two) of
+// the block; every thread of the block must call them (they hold barriers).
+__device__ __forceinline__ float block_max(float v, float* red, int cnt) {
+    if ((int)threadIdx.x < cnt) red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = cnt / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    const float r = red[0];
+    __syncthreads();
+    return r;
+}
+__device__ __forceinline__ float block_sum(float v, float* red, int cnt) {
+    if ((int)threadIdx.x < cnt) red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = cnt / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    const float r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// Largest value and its lowest index, over the block (deterministic tree).
+__device__ __forceinline__ void block_argmax(float v, int idx, float* rv, int* ri, int cnt,
+                                             float& out_v, int& out_i) {
+    if ((int)threadIdx.x < cnt) {
+        rv[threadIdx.x] = v;
+        ri[threadIdx.x] = idx;
+    }
+    __syncthreads();
+    for (int s = cnt / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            const float a = rv[threadIdx.x], b = rv[threadIdx.x + s];
+            const int ia = ri[threadIdx.x], ib = ri[threadIdx.x + s];
+            if (b > a || (b == a && ib < ia)) {
+                rv[threadIdx.x] = b;
+                ri[threadIdx.x] = ib;
+            }
+        }
+        __syncthreads();
+    }
+    out_v = rv[0];
+    out_i = ri[0];
+    __syncthreads();
+}
+
+// Online-softmax merge of two partials (max, sum of exp, and two weighted sums).
+__device__ __forceinline__ float4 softmax_merge(float4 a, float4 c, float inv_t) {
+    if (c.x == -INFINITY) return a;   // empty partials (threads past the end)
+    if (a.x == -INFINITY) return c;
+    const float M = fmaxf(a.x, c.x);
+    const float ea = expf((a.x - M) * inv_t), ec = expf((c.x - M) * inv_t);
+    return make_float4(M, a.y * ea + c.y * ec, a.z * ea + c.z * ec, a.w * ea + c.w * ec);
 }
 
 }  // namespace fmbym

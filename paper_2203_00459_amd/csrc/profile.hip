@@ -18,6 +18,7 @@ const char* const kKernelNames[kKernelCount] = {
     "m_head_bwd", "m_bn_bwd", "m_wgrad", "m_conv_dgrad", "m_pool_bwd", "m_up_bwd", "m_pack", "m_adam",
     "m_pose_loss", "k_rotate", "kb_rotate_adj", "k_joint_setup", "k_joint_peak", "k_joint_pick",
     "k_turn_setup", "k_turn_pick", "k_finite", "m_input_grad",
+    "ko_rows1", "ko_cols1", "ko_polar", "ko_angle_fin", "ko_rotate", "ko_rows2", "ko_cols2", "ko_rows3",
 };
 
 namespace {

@@ -13,6 +13,7 @@ enum KernelId {
     kMInput, kMConvFwd, kMBnStats, kMBnRelu, kMPool, kMUpCat, kMHeadFwd, kMHeadBwd, kMBnBwd, kMWgrad,
     kMConvDgrad, kMPoolBwd, kMUpBwd, kMPack, kMAdam, kMLoss, kKRotate, kKBRotateAdj,
     kKJointSetup, kKJointPeak, kKJointPick, kKTurnSetup, kKTurnPick, kKFinite, kMInputGrad,
+    kORows1, kOCols1, kOPolar, kOAngleFin, kORotate, kORows2, kOCols2, kORows3,
     kKernelCount
 };
 

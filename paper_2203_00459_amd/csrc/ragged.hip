@@ -44,6 +44,7 @@ int plan_groups(const fmbym_plan* plans, int n_plans, const fmbym_pair* pairs, i
         return FMBYM_EINVAL;
     for (int k = 0; k < n_plans; ++k) {
         if (!plans[k]) return FMBYM_EINVAL;
+        if (odd_side(plan_cast(plans[k])->p.n)) return FMBYM_EUNSUPPORTED;   // odd sides: packed batches only
         for (int j = 0; j < k; ++j)
             if (plan_cast(plans[j])->p.n == plan_cast(plans[k])->p.n) return FMBYM_EINVAL;
     }

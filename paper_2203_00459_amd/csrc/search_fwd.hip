@@ -210,55 +210,6 @@ __global__ __launch_bounds__(256) void k_polar(const float2* __restrict__ A,
     }
 }
 
-// Deterministic reductions over the first `cnt` threads (a power of two) of
-// the block; every thread of the block must call them (they hold barriers).
-__device__ __forceinline__ float block_max(float v, float* red, int cnt) {
-    if ((int)threadIdx.x < cnt) red[threadIdx.x] = v;
-    __syncthreads();
-    for (int s = cnt / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
-        __syncthreads();
-    }
-    const float r = red[0];
-    __syncthreads();
-    return r;
-}
-__device__ __forceinline__ float block_sum(float v, float* red, int cnt) {
-    if ((int)threadIdx.x < cnt) red[threadIdx.x] = v;
-    __syncthreads();
-    for (int s = cnt / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
-    }
-    const float r = red[0];
-    __syncthreads();
-    return r;
-}
-
-// Largest value and its lowest index, over the block (deterministic tree).
-__device__ __forceinline__ void block_argmax(float v, int idx, float* rv, int* ri, int cnt,
-                                             float& out_v, int& out_i) {
-    if ((int)threadIdx.x < cnt) {
-        rv[threadIdx.x] = v;
-        ri[threadIdx.x] = idx;
-    }
-    __syncthreads();
-    for (int s = cnt / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) {
-            const float a = rv[threadIdx.x], b = rv[threadIdx.x + s];
-            const int ia = ri[threadIdx.x], ib = ri[threadIdx.x + s];
-            if (b > a || (b == a && ib < ia)) {
-                rv[threadIdx.x] = b;
-                ri[threadIdx.x] = ib;
-            }
-        }
-        __syncthreads();
-    }
-    out_v = rv[0];
-    out_i = ri[0];
-    __syncthreads();
-}
-
 // Sum over radius blocks, inverse angular DFT without its k = 0 term (the
 // mean over lags, kept apart so that the lag-dependent part is exact to its
 // own rounding), softmax and soft-argmax.  theta is formed as (l* + nu) dtheta
@@ -618,14 +569,6 @@ __global__ __launch_bounds__(256) void k_rows3(const float2* __restrict__ in,
 
 // Merge of the online-softmax partials of one pair: 64 threads, each folds a
 // strided subset, then a fixed-order tree.
-__device__ __forceinline__ float4 softmax_merge(float4 a, float4 c, float inv_t) {
-    if (c.x == -INFINITY) return a;   // empty partials (threads past the end)
-    if (a.x == -INFINITY) return c;
-    const float M = fmaxf(a.x, c.x);
-    const float ea = expf((a.x - M) * inv_t), ec = expf((c.x - M) * inv_t);
-    return make_float4(M, a.y * ea + c.y * ec, a.z * ea + c.z * ec, a.w * ea + c.w * ec);
-}
-
 __global__ __launch_bounds__(64) void k_xy_fin(const float4* __restrict__ part, int ppp, float temp,
                                                float delta, float* __restrict__ pose,
                                                float* __restrict__ saved) {
@@ -662,6 +605,10 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 FwdLayout fwd_layout(const fmbym_params& p, int batch) {
     const size_t n = p.n, B = batch;
     FwdLayout L{};
+    if (odd_side(p.n)) {   // the odd path carves its own regions; only the size is shared
+        L.total = odd_fwd_workspace(p, batch);
+        return L;
+    }
     size_t off = 0;
     L.r1r2 = off;
     const size_t r1 = B * n * (size_t)pitch_rows1(p.n) * sizeof(float4);
@@ -911,6 +858,11 @@ void launch_rows2(const Plan& pl, int batch, const float* f, const float* g, con
     }
 }
 
+void launch_xy_fin_parts(const float4* part, int ppp, float temp_xy, float delta_xy, int batch, float* pose,
+                         float* saved, hipStream_t s) {
+    FMBYM_LAUNCH(kKXyFin, k_xy_fin, dim3(batch), dim3(64), s, part, ppp, temp_xy, delta_xy, pose, saved);
+}
+
 void launch_xy_fin(const Plan& pl, int batch, char* ws, float* pose, float* saved, hipStream_t s) {
     const FwdLayout lay = fwd_layout(pl.p, batch);
     FMBYM_LAUNCH(kKXyFin, k_xy_fin, dim3(batch), dim3(64), s, (const float4*)(ws + lay.pxy),
@@ -943,6 +895,10 @@ void launch_rotate(const Plan& pl, int B, const float* g, const float* mg, const
 int launch_forward(const Plan& pl, int batch, const float* f, const float* g, const float* mf,
                    const float* mg, float* pose, float* c_theta, float* c_xy, float* saved,
                    char* ws, hipStream_t s, const float* const* tab, const Keep* keep) {
+    if (odd_side(pl.p.n)) {   // forward only, packed batches
+        if (tab || keep) return FMBYM_EUNSUPPORTED;
+        return launch_forward_odd(pl, batch, f, g, mf, mg, pose, c_theta, c_xy, saved, ws, s);
+    }
     switch (pl.p.n) {
         case 128: return launch_n<128>(pl, batch, f, g, mf, mg, pose, c_theta, c_xy, saved, ws, s, tab, keep);
         case 256: return launch_n<256>(pl, batch, f, g, mf, mg, pose, c_theta, c_xy, saved, ws, s, tab, keep);

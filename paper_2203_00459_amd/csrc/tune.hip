@@ -79,13 +79,13 @@ using namespace fmbym;
 extern "C" {
 
 size_t fmbym_autotune_workspace_size(fmbym_plan plan, int32_t batch, int with_backward) {
-    if (check_call(plan, batch)) return 0;
+    if (check_full_path(plan, batch)) return 0;   // odd sides have no tunable column tiles
     return tune_layout(*plan_cast(plan), batch, with_backward ? 1 : 0).total;
 }
 
 int fmbym_autotune(fmbym_plan plan, int32_t batch, int with_backward, void* workspace, size_t workspace_bytes,
                    void* stream, fmbym_tuning* best, float* ms_per_step) {
-    int rc = check_call(plan, batch);
+    int rc = check_full_path(plan, batch);
     if (rc) return rc;
     if (!best) return FMBYM_EINVAL;
     Plan& pl = *plan_cast(plan);

@@ -15,12 +15,21 @@ SEARCH = {
     # 32 pairs, 512 x 512, 512 angle bins, forward and adjoint (the headline workload)
     "batch512": dict(batch=32, n=512, n_theta=512, delta_xy=0.2, temp_theta=1.0, temp_xy=1.0,
                      band_lo=0.02, band_hi=0.40),
+    # the paper's measured sizes and ScanMatch defaults: 733 heading bins, T_theta = 2, T_xy = 1;
+    # 32 pairs per batch, forward
+    "paper127": dict(batch=32, n=127, n_theta=733, delta_xy=0.8, temp_theta=2.0, temp_xy=1.0,
+                     band_lo=0.02, band_hi=0.40),
+    "paper255": dict(batch=32, n=255, n_theta=733, delta_xy=0.4, temp_theta=2.0, temp_xy=1.0,
+                     band_lo=0.02, band_hi=0.40),
+    "paper511": dict(batch=32, n=511, n_theta=733, delta_xy=0.2, temp_theta=2.0, temp_xy=1.0,
+                     band_lo=0.02, band_hi=0.40),
 }
 
 # What one bench step of each search workload runs: the forward alone (one pair,
 # timed as a captured launch), the forward beside the joint comparator over
 # 64 headings, or the forward and the adjoint.
-PASS = {"pair128": "fwd", "batch256": "fwd+joint64", "batch512": "fwd+bwd"}
+PASS = {"pair128": "fwd", "batch256": "fwd+joint64", "batch512": "fwd+bwd",
+        "paper127": "fwd", "paper255": "fwd", "paper511": "fwd"}
 JOINT_ANGLES = 64
 
 # Ragged serving batches: pairs of the three sizes above in one launch.
