@@ -11,8 +11,11 @@ level two 3x3 convolutions (padding 1, no bias), each followed by BatchNorm
 (batch statistics, eps 1e-5) and ReLU; 2x2 max-pooling between encoder
 levels; bilinear x2 upsampling (half-pixel centres, edge clamped) and
 concatenation [upsampled, skip] in the decoder; a 3x3 head convolution with
-bias and a sigmoid.  Channels double per level from ``base``.  The scans of a
-pair go through the same network (shared weights).
+bias and a sigmoid.  Channels double per level from ``base``.  ``ch`` is the
+number of input and output channels: 1 for the network whose two scans of a
+pair go through the same weights one at a time, 2 for Table II's dual-input
+network, which sees both scans of a pair stacked as channels (f, g) and
+returns both masks (m_f, m_g).
 
 Every layer is a plain torch-CPU FP64 library call (conv2d, batch_norm,
 max_pool2d, interpolate, sigmoid); gradients come from FP64 autograd.  The
@@ -22,7 +25,7 @@ loops and closed forms.
 Flat parameter vector (the library's documented layout, restated here):
 for each convolution in order enc0a, enc0b, enc1a, enc1b, ..., dec(L-2)a,
 dec(L-2)b, ..., dec0a, dec0b: weight [c_out][c_in][3][3], then gamma [c_out],
-then beta [c_out]; finally the head weight [1][base][3][3] and its bias.
+then beta [c_out]; finally the head weight [ch][base][3][3] and its bias [ch].
 """
 from __future__ import annotations
 
@@ -57,14 +60,14 @@ def conv_list(levels: int, base: int, in_ch: int = 1) -> list[Conv]:
     return out
 
 
-def param_count(levels: int, base: int) -> int:
-    return sum(c.c_out * c.c_in * 9 + 2 * c.c_out for c in conv_list(levels, base)) + base * 9 + 1
+def param_count(levels: int, base: int, ch: int = 1) -> int:
+    return sum(c.c_out * c.c_in * 9 + 2 * c.c_out for c in conv_list(levels, base, ch)) + ch * (base * 9 + 1)
 
 
-def unpack(theta: torch.Tensor, levels: int, base: int) -> dict:
+def unpack(theta: torch.Tensor, levels: int, base: int, ch: int = 1) -> dict:
     """Views of the flat parameter vector: {name: (w, gamma, beta)}, 'head': (w, b)."""
     out, o = {}, 0
-    for c in conv_list(levels, base):
+    for c in conv_list(levels, base, ch):
         nw = c.c_out * c.c_in * 9
         w = theta[o:o + nw].reshape(c.c_out, c.c_in, 3, 3)
         o += nw
@@ -73,19 +76,20 @@ def unpack(theta: torch.Tensor, levels: int, base: int) -> dict:
         bet = theta[o:o + c.c_out]
         o += c.c_out
         out[c.name] = (w, gam, bet)
-    out["head"] = (theta[o:o + base * 9].reshape(1, base, 3, 3), theta[o + base * 9:o + base * 9 + 1])
-    assert o + base * 9 + 1 == theta.numel()
+    nh = ch * base * 9
+    out["head"] = (theta[o:o + nh].reshape(ch, base, 3, 3), theta[o + nh:o + nh + ch])
+    assert o + nh + ch == theta.numel()
     return out
 
 
-def init_params(levels: int, base: int, seed: int = 0) -> np.ndarray:
+def init_params(levels: int, base: int, seed: int = 0, ch: int = 1) -> np.ndarray:
     """He-normal convolution weights, gamma 1, beta 0, head bias 0 (float32)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     parts = []
-    for c in conv_list(levels, base):
+    for c in conv_list(levels, base, ch):
         std = math.sqrt(2.0 / (9 * c.c_in))
         parts += [rng.normal(0.0, std, c.c_out * c.c_in * 9), np.ones(c.c_out), np.zeros(c.c_out)]
-    parts += [rng.normal(0.0, math.sqrt(1.0 / (9 * base)), base * 9), np.zeros(1)]
+    parts += [rng.normal(0.0, math.sqrt(1.0 / (9 * base)), ch * base * 9), np.zeros(ch)]
     return np.concatenate(parts).astype(np.float32)
 
 
@@ -112,15 +116,24 @@ def up2(x):
     return F.interpolate(x, scale_factor=2, mode="bilinear", align_corners=False)
 
 
+def _as_channels(x, ch: int):
+    """[I, n, n] scans for one channel, [I, ch, n, n] otherwise -> [I, ch, n, n]."""
+    return x[:, None] if ch == 1 else x
+
+
+def _from_channels(m, ch: int):
+    return m[:, 0] if ch == 1 else m
+
+
 def forward(x, theta, levels: int, base: int, eps: float = 1e-5, keep: bool = False,
-            quant: bool = False):
-    """Masks for images x [I, n, n] (FP64 tensors); theta is the flat FP64 vector.
-    Returns m [I, n, n] and, with keep=True, every intermediate by name.
-    quant=True stores the scan, the conv weights, every conv output, activation
-    and upsampled tensor in bfloat16 (the arithmetic stays FP64); the head's
-    weights and everything after the last activation stay unrounded."""
-    P = unpack(theta, levels, base)
-    h = bf16(x[:, None], quant)
+            quant: bool = False, ch: int = 1):
+    """Masks for images x [I, n, n] (ch = 1) or [I, ch, n, n] (FP64 tensors); theta is
+    the flat FP64 vector.  Returns m of the same shape as x and, with keep=True, every
+    intermediate by name.  quant=True stores the scan, the conv weights, every conv
+    output, activation and upsampled tensor in bfloat16 (the arithmetic stays FP64);
+    the head's weights and everything after the last activation stay unrounded."""
+    P = unpack(theta, levels, base, ch)
+    h = bf16(_as_channels(x, ch), quant)
     acts, skips = {}, []
     for l in range(levels):
         if l > 0:
@@ -138,8 +151,8 @@ def forward(x, theta, levels: int, base: int, eps: float = 1e-5, keep: bool = Fa
             acts[f"dec{l}{part}.z"], acts[f"dec{l}{part}"] = z, h
     wh, bh = P["head"]
     logit = F.conv2d(h, wh, bh, padding=1)
-    m = torch.sigmoid(logit)[:, 0]
-    acts["logit"] = logit[:, 0]
+    m = _from_channels(torch.sigmoid(logit), ch)
+    acts["logit"] = _from_channels(logit, ch)
     return (m, acts) if keep else m
 
 
@@ -170,12 +183,12 @@ def adam_step(theta, grad, m, v, step: int, lr: float, b1: float = 0.9, b2: floa
 
 
 def running_stats(x, theta, levels: int, base: int, run_mean, run_var, momentum: float = 0.1,
-                  eps: float = 1e-5, quant: bool = False):
+                  eps: float = 1e-5, quant: bool = False, ch: int = 1):
     """Running statistics after one training pass: each BN channel moves by
     `momentum` towards its batch mean and unbiased batch variance."""
-    _, acts = forward(x, theta, levels, base, eps, keep=True, quant=quant)
+    _, acts = forward(x, theta, levels, base, eps, keep=True, quant=quant, ch=ch)
     means, vars_ = [], []
-    for c in conv_list(levels, base):
+    for c in conv_list(levels, base, ch):
         z = acts[f"{c.name}.z"]
         means.append(z.mean(dim=(0, 2, 3)))
         vars_.append(z.var(dim=(0, 2, 3), unbiased=True))
@@ -183,11 +196,11 @@ def running_stats(x, theta, levels: int, base: int, run_mean, run_var, momentum:
     return (1 - momentum) * run_mean + momentum * mu, (1 - momentum) * run_var + momentum * var
 
 
-def forward_eval(x, theta, levels: int, base: int, run_mean, run_var, eps: float = 1e-5):
+def forward_eval(x, theta, levels: int, base: int, run_mean, run_var, eps: float = 1e-5, ch: int = 1):
     """Masks with BatchNorm on the given running statistics (inference)."""
-    P = unpack(theta, levels, base)
+    P = unpack(theta, levels, base, ch)
     stats, o = {}, 0
-    for c in conv_list(levels, base):
+    for c in conv_list(levels, base, ch):
         stats[c.name] = (run_mean[o:o + c.c_out], run_var[o:o + c.c_out])
         o += c.c_out
 
@@ -196,7 +209,7 @@ def forward_eval(x, theta, levels: int, base: int, run_mean, run_var, eps: float
         z = F.conv2d(h, w, padding=1)
         return F.relu(F.batch_norm(z, *stats[name], g, b, training=False, eps=eps))
 
-    h, skips = x[:, None], []
+    h, skips = _as_channels(x, ch), []
     for l in range(levels):
         if l > 0:
             h = F.max_pool2d(h, 2)
@@ -206,21 +219,22 @@ def forward_eval(x, theta, levels: int, base: int, run_mean, run_var, eps: float
         h = torch.cat([up2(h), skips[l]], dim=1)
         h = cbr(cbr(h, f"dec{l}a"), f"dec{l}b")
     wh, bh = P["head"]
-    return torch.sigmoid(F.conv2d(h, wh, bh, padding=1))[:, 0]
+    return _from_channels(torch.sigmoid(F.conv2d(h, wh, bh, padding=1)), ch)
 
 
-def grad(x, d_mask, theta, levels: int, base: int, eps: float = 1e-5, quant: bool = False):
+def grad(x, d_mask, theta, levels: int, base: int, eps: float = 1e-5, quant: bool = False, ch: int = 1):
     """d<mask, d_mask>/d theta by FP64 autograd (the mask network's adjoint)."""
     th = theta.detach().clone().requires_grad_(True)
-    m = forward(x, th, levels, base, eps, quant=quant)
+    m = forward(x, th, levels, base, eps, quant=quant, ch=ch)
     (m * d_mask).sum().backward()
     return th.grad.detach()
 
 
-def grad_input(x, d_mask, theta, levels: int, base: int, eps: float = 1e-5, quant: bool = False):
+def grad_input(x, d_mask, theta, levels: int, base: int, eps: float = 1e-5, quant: bool = False,
+               ch: int = 1):
     """d<mask, d_mask>/d x, the gradient with respect to the input scans, by FP64 autograd
     (through the training forward's batch statistics, like ``grad``)."""
     xx = torch.as_tensor(x).to(torch.float64).detach().clone().requires_grad_(True)
-    m = forward(xx, theta.detach(), levels, base, eps, quant=quant)
+    m = forward(xx, theta.detach(), levels, base, eps, quant=quant, ch=ch)
     (m * d_mask).sum().backward()
     return xx.grad.detach()

@@ -341,3 +341,59 @@ def test_quant_forward_rounds_at_the_documented_points_by_hand():
     assert np.allclose(got, want, rtol=0, atol=1e-12)
     exact = M.forward(torch.tensor(x, dtype=DT), th, 1, 1).numpy()
     assert np.abs(exact - want).max() > 1e-4     # the rounding is visible
+
+
+# ------------------------------------------------ Table II's dual-input network
+
+TABLE_II = [  # (c_in, c_out) of every convolution, encoder then decoder, then the head
+    (2, 8), (8, 8), (8, 16), (16, 16), (16, 32), (32, 32), (32, 64), (64, 64), (64, 128), (128, 128),
+    (128, 256), (256, 256),
+    (384, 128), (128, 128), (192, 64), (64, 64), (96, 32), (32, 32), (48, 16), (16, 16), (24, 8), (8, 8),
+]
+
+
+def test_dual_network_is_table_ii():
+    """6 levels, 8 -> 256 channels, two scans in and two masks out: the channel list
+    written out by hand from the table, about 1.97 M convolution weights."""
+    convs = M.conv_list(6, 8, 2)
+    assert [(c.c_in, c.c_out) for c in convs] == TABLE_II
+    n_conv = sum(ci * co * 9 for ci, co in TABLE_II) + 8 * 2 * 9
+    assert n_conv == 1_965_024
+    bn = sum(2 * co for _, co in TABLE_II)
+    assert M.param_count(6, 8, 2) == n_conv + bn + 2
+    th = torch.tensor(M.init_params(6, 8, seed=0, ch=2), dtype=DT)
+    assert th.numel() == M.param_count(6, 8, 2)
+    P = M.unpack(th, 6, 8, 2)
+    assert P["head"][0].shape == (2, 8, 3, 3) and P["head"][1].shape == (2,)
+
+
+def test_dual_network_channel_order_against_the_single_channel_network():
+    """A dual net whose first convolution ignores input channel 1 and whose two head
+    rows are equal returns two identical masks, each the one-channel network's mask of
+    channel 0 with the same weights: input channel 0 is the first scan, head row k is
+    mask k, and nothing else mixes the channels."""
+    r = _rng(21)
+    L, base = 3, 4
+    th1 = M.init_params(L, base, seed=5)
+    P1 = M.unpack(torch.tensor(th1, dtype=DT), L, base)
+    parts = []
+    for c in M.conv_list(L, base, 2):
+        w, g, b = P1[c.name]
+        if c.name == "enc0a":
+            w2 = torch.zeros(c.c_out, 2, 3, 3, dtype=DT)
+            w2[:, 0] = w[:, 0]
+            w = w2
+        parts += [w.reshape(-1), g, b]
+    wh, bh = P1["head"]
+    parts += [torch.cat([wh, wh]).reshape(-1), torch.cat([bh, bh])]
+    th2 = torch.cat(parts)
+    x = torch.tensor(r.random((3, 16, 16)), dtype=DT)
+    y = torch.tensor(r.random((3, 16, 16)), dtype=DT)
+    m1 = M.forward(x, torch.tensor(th1, dtype=DT), L, base)
+    m2 = M.forward(torch.stack([x, y], dim=1), th2, L, base, ch=2)
+    assert m2.shape == (3, 2, 16, 16)
+    np.testing.assert_allclose(m2[:, 0].numpy(), m1.numpy(), atol=1e-12)
+    np.testing.assert_allclose(m2[:, 1].numpy(), m1.numpy(), atol=1e-12)
+    # and a different second scan changes nothing
+    m3 = M.forward(torch.stack([x, 2 * y + 1], dim=1), th2, L, base, ch=2)
+    np.testing.assert_allclose(m3.numpy(), m2.numpy(), atol=1e-12)
