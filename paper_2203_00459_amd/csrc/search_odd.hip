@@ -15,8 +15,9 @@
 //                centred by its angular mean; the linear correlation along
 //                angle through one LT-point DFT of the zero-padded pair
 //                (LT >= 2 n_theta - 1), summed over a block of radii.
-//   ko_angle_fin sum over radius blocks, inverse DFT, the circular
-//                correlation folded back from the linear one
+//   ko_angle_sum sum over radius blocks, one spectrum bin per thread.
+//   ko_angle_fin inverse DFT, the circular correlation folded back from the
+//                linear one
 //                (c[l] = lin[l mod n_theta] + lin[(l mod n_theta) - n_theta]),
 //                softmax and soft-argmax -> theta.
 // Stage 2 (Eq. 9)
@@ -35,10 +36,15 @@ namespace fmbym {
 
 namespace {
 
-constexpr int kOddRadii = 16;   // radii per block of the heading correlation
+constexpr int kOddPasses = 4;   // radii per line of a heading-correlation block (in sequence)
 constexpr int kOddE1 = 8;       // elements per thread of the Bluestein lines
 
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Elements per thread and radii per block of the heading correlation over LT points.
+__host__ __device__ constexpr int odd_lt_e(int lt) { return (lt & (lt - 1)) == 0 ? 8 : 12; }
+__host__ __device__ constexpr int odd_radii(int lt) { return (256 / (lt / odd_lt_e(lt))) * kOddPasses; }
+__host__ __device__ constexpr int odd_radius_blocks(int n_r, int lt) { return (n_r + odd_radii(lt) - 1) / odd_radii(lt); }
 
 // Pitches (elements) of the odd path's row arrays.
 constexpr int odd_u(int n) { return (n + 1) / 2; }          // stage-1 unique columns (a power of two)
@@ -50,7 +56,7 @@ struct OddLayout {
 
 OddLayout odd_layout(const fmbym_params& p, int batch) {
     const size_t n = p.n, B = batch, U = odd_u(p.n), P2 = odd_p2(odd_m2(p.n));
-    const int lt = odd_lt(p.n_theta), nrb = (p.n_r + kOddRadii - 1) / kOddRadii;
+    const int lt = odd_lt(p.n_theta), nrb = odd_radius_blocks(p.n_r, lt);
     OddLayout L{};
     size_t off = 0;
     L.r12 = off;   // stage-1 row spectra, then the stage-2 row spectra
@@ -204,7 +210,9 @@ __global__ __launch_bounds__(C * M / kOddE1) void ko_cols1(const float4* __restr
 }
 
 // Bilinear read of both magnitude spectra at frequency (uy, ux) in bins, with
-// indices modulo n and |F(-k)| = |F(k)| for columns past (n - 1)/2.
+// indices modulo n and |F(-k)| = |F(k)| for columns past (n - 1)/2.  The polar
+// grid has 0 <= uy < n/2 and |ux| < n/2, so every corner index lies in
+// [-(n+1)/2, (n+1)/2] and one conditional add reduces it modulo n.
 __device__ __forceinline__ float2 odd_mag_sample(const float2* __restrict__ A, int n, float uy, float ux) {
     const int U = (n + 1) / 2;
     const float fy = floorf(uy), fx = floorf(ux);
@@ -215,7 +223,9 @@ __device__ __forceinline__ float2 odd_mag_sample(const float2* __restrict__ A, i
     for (int dy = 0; dy < 2; ++dy) {
 #pragma unroll
         for (int dx = 0; dx < 2; ++dx) {
-            int ky = ((y0 + dy) % n + n) % n, kx = ((x0 + dx) % n + n) % n;
+            int ky = y0 + dy, kx = x0 + dx;
+            ky = ky < 0 ? ky + n : ky;
+            kx = kx < 0 ? kx + n : kx;
             if (kx >= U) {
                 kx = n - kx;
                 ky = ky == 0 ? 0 : n - ky;
@@ -229,7 +239,8 @@ __device__ __forceinline__ float2 odd_mag_sample(const float2* __restrict__ A, i
     return acc;
 }
 
-// Heading correlation over kOddRadii radii per block.  Radius b samples
+// Heading correlation over odd_radii(LT) radii per block (kOddPasses per
+// line, one after the other).  Radius b samples
 // rho = (n/2) b / n_r bins at the plan's angles; each radius's profiles are
 // centred by their angular means (sum_a (P_f - mu_f)(P_g - mu_g)(. + l) is the
 // circular correlation minus S_f S_g / n_theta, its mean over the lags), then
@@ -240,12 +251,12 @@ __global__ __launch_bounds__(256) void ko_polar(const float2* __restrict__ A, in
                                                 const float2* __restrict__ cs, int n_theta, int n_r,
                                                 const float2* __restrict__ tw, float2* __restrict__ part,
                                                 float* __restrict__ partm, int batch) {
-    constexpr int T = LT / E, LPB = 256 / T, PASSES = kOddRadii / LPB, HK = LT / 2 + 1;
-    static_assert(kOddRadii % LPB == 0, "whole passes");
+    constexpr int T = LT / E, LPB = 256 / T, PASSES = kOddPasses, HK = LT / 2 + 1, RPB = LPB * PASSES;
+    static_assert(T % 64 == 0, "a line is whole wavefronts");
     __shared__ float lre[LPB][LdsRows<LT>::words(LT)];
     __shared__ float lim[LPB][LdsRows<LT>::words(LT)];
-    __shared__ float red[2][256];
-    const int nrb = (n_r + kOddRadii - 1) / kOddRadii;
+    __shared__ float2 red[4];   // per-wavefront angular sums (S_f, S_g)
+    const int nrb = (n_r + RPB - 1) / RPB;
     const int total = batch * nrb;
     const int per_xcd = (total + 7) / 8;
     const int work = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;   // a pair's blocks on one XCD
@@ -258,7 +269,7 @@ __global__ __launch_bounds__(256) void ko_polar(const float2* __restrict__ A, in
     for (int m = 0; m <= E / 2; ++m) acc[m] = make_float2(0.f, 0.f);
     float accm = 0.f;
     for (int pass = 0; pass < PASSES; ++pass) {
-        const int rad = rb * kOddRadii + pass * LPB + line;
+        const int rad = rb * RPB + pass * LPB + line;
         const bool live = rad < n_r;
         const float rho = 0.5f * (float)n * (float)rad / (float)n_r;
         float2 v[E];
@@ -275,19 +286,25 @@ __global__ __launch_bounds__(256) void ko_polar(const float2* __restrict__ A, in
             sf += v[m].x;
             sg += v[m].y;
         }
-        // angular sums of this radius: fixed-order tree over the line's threads
-        red[0][threadIdx.x] = sf;
-        red[1][threadIdx.x] = sg;
-        __syncthreads();
-        for (int s = T / 2; s > 0; s >>= 1) {
-            if (t < s) {
-                red[0][threadIdx.x] += red[0][threadIdx.x + s];
-                red[1][threadIdx.x] += red[1][threadIdx.x + s];
-            }
-            __syncthreads();
+        // angular sums of this radius: a butterfly within each wavefront whose
+        // lane-0 value every lane takes (one rounding order for all), then the
+        // line's wavefronts added in order
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            sf += __shfl_xor(sf, off);
+            sg += __shfl_xor(sg, off);
         }
-        const float Sf = red[0][line * T], Sg = red[1][line * T];
-        __syncthreads();   // red is rewritten by the next pass
+        sf = __shfl(sf, 0);
+        sg = __shfl(sg, 0);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = make_float2(sf, sg);
+        __syncthreads();
+        float Sf = 0.f, Sg = 0.f;
+#pragma unroll
+        for (int w = 0; w < T / 64; ++w) {
+            const float2 r = red[line * (T / 64) + w];
+            Sf += r.x;
+            Sg += r.y;
+        }
         const float muf = Sf / (float)n_theta, mug = Sg / (float)n_theta;
 #pragma unroll
         for (int m = 0; m < E; ++m) {
@@ -312,7 +329,8 @@ __global__ __launch_bounds__(256) void ko_polar(const float2* __restrict__ A, in
             sim[line * HK + k] = acc[m].y;
         }
     }
-    if (t == 0) red[0][line] = accm;
+    __shared__ float redm[LPB];
+    if (t == 0) redm[line] = accm;
     __syncthreads();
     float2* dst = part + ((size_t)b * nrb + rb) * HK;
     for (int k = threadIdx.x; k < HK; k += 256) {
@@ -322,7 +340,7 @@ __global__ __launch_bounds__(256) void ko_polar(const float2* __restrict__ A, in
     }
     if (threadIdx.x == 0) {
         float s = 0.f;
-        for (int l = 0; l < LPB; ++l) s += red[0][l];
+        for (int l = 0; l < LPB; ++l) s += redm[l];
         partm[(size_t)b * nrb + rb] = s;
     }
 }
@@ -331,6 +349,35 @@ __global__ __launch_bounds__(256) void ko_polar(const float2* __restrict__ A, in
 // centred profiles (d mod LT), the circular correlation folded back from it,
 // then the softmax and the soft-argmax as for even sides:
 // theta = (l* + nu) pi / n_theta with nu = sum_l p_l (l - l*).
+// Sum over the radius blocks of a pair, in block order, for one spectrum bin
+// per thread (and, by one thread, of the S_f S_g partials): the totals replace
+// radius block 0 of the partials (a thread reads and writes only its bin).
+template <int LT>
+__global__ __launch_bounds__(256) void ko_angle_sum(float2* __restrict__ part, float* __restrict__ partm, int n_r) {
+    constexpr int HK = LT / 2 + 1;
+    const int b = blockIdx.y, k = blockIdx.x * 256 + threadIdx.x;
+    const int nrb = odd_radius_blocks(n_r, LT);
+    float2* src = part + (size_t)b * nrb * HK;
+    if (k < HK) {
+        float2 s = make_float2(0.f, 0.f);
+        int r = 0;
+        for (; r + 8 <= nrb; r += 8) {   // eight loads in flight, then added in order
+            float2 v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = src[(size_t)(r + u) * HK + k];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s = cadd(s, v[u]);
+        }
+        for (; r < nrb; ++r) s = cadd(s, src[(size_t)r * HK + k]);
+        src[k] = s;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        float m = 0.f;
+        for (int r = 0; r < nrb; ++r) m += partm[(size_t)b * nrb + r];
+        partm[(size_t)b * nrb] = m;
+    }
+}
+
 template <int LT, int E>
 __global__ __launch_bounds__(LT / E) void ko_angle_fin(const float2* __restrict__ part,
                                                        const float* __restrict__ partm, int n_r, int n_theta,
@@ -340,19 +387,12 @@ __global__ __launch_bounds__(LT / E) void ko_angle_fin(const float2* __restrict_
     constexpr int T = LT / E, HK = LT / 2 + 1, J = E / 2 + 1;   // n_theta <= (LT + 1) / 2 lags
     __shared__ float lre[LdsRows<LT>::words(LT)];
     __shared__ float lim[LdsRows<LT>::words(LT)];
-    __shared__ float2 psum[HK];
     __shared__ float lin[LT];
     __shared__ float red[T];
     __shared__ int redi[T];
     const int b = blockIdx.x, t = threadIdx.x;
-    const int nrb = (n_r + kOddRadii - 1) / kOddRadii;
-    const float2* src = part + (size_t)b * nrb * HK;
-    for (int k = t; k < HK; k += T) {
-        float2 s = make_float2(0.f, 0.f);
-        for (int r = 0; r < nrb; ++r) s = cadd(s, src[(size_t)r * HK + k]);
-        psum[k] = s;
-    }
-    __syncthreads();
+    const int nrb = odd_radius_blocks(n_r, LT);
+    const float2* psum = part + (size_t)b * nrb * HK;   // block 0 holds the totals (ko_angle_sum)
     float2 v[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
@@ -403,8 +443,7 @@ __global__ __launch_bounds__(LT / E) void ko_angle_fin(const float2* __restrict_
     const float Z = block_sum(se, red, T);
     const float SN = block_sum(sn, red, T);
     if (t == 0) {
-        float mean = 0.f;
-        for (int r = 0; r < nrb; ++r) mean += partm[(size_t)b * nrb + r];
+        const float mean = partm[(size_t)b * nrb];   // the total (ko_angle_sum)
         const float nu = SN / Z;
         const float theta = ((float)lag_star + nu) * (3.14159265358979323846f / (float)n_theta);
         pose[b * 3 + 0] = theta;
@@ -597,10 +636,12 @@ void launch_angle(const Plan& pl, int B, const float2* A, float2* pth, float* pt
                   float* sv, hipStream_t s) {
     constexpr int E = (LT & (LT - 1)) == 0 ? 8 : 12;
     const float2* tw = (LT & (LT - 1)) == 0 ? pl.twiddle : pl.twiddle3;
-    const int nrb = (pl.p.n_r + kOddRadii - 1) / kOddRadii;
+    const int nrb = odd_radius_blocks(pl.p.n_r, LT);
     const int total = B * nrb;
     FMBYM_LAUNCH(kOPolar, (ko_polar<LT, E>), dim3(((total + 7) / 8) * 8), dim3(256), s, A, pl.p.n, pl.polar_cs,
                  pl.p.n_theta, pl.p.n_r, tw, pth, pthm, B);
+    FMBYM_LAUNCH(kOAngleFin, ko_angle_sum<LT>, dim3((LT / 2 + 1 + 255) / 256, B), dim3(256), s, pth, pthm,
+                 pl.p.n_r);
     FMBYM_LAUNCH(kOAngleFin, (ko_angle_fin<LT, E>), dim3(B), dim3(LT / E), s, pth, pthm, pl.p.n_r, pl.p.n_theta,
                  tw, pl.p.temp_theta, c_theta, pose, sv);
 }
