@@ -229,18 +229,18 @@ def main() -> int:
     return search_bench(args)
 
 
-def mask_layers(levels: int, base: int):
+def mask_layers(levels: int, base: int, channels: int = 1):
     """(c_in, c_out, level) of the mask network's convolutions in order."""
     ch = [base << l for l in range(levels)]
     out = []
     for l in range(levels):
-        out += [(1 if l == 0 else ch[l - 1], ch[l], l), (ch[l], ch[l], l)]
+        out += [(channels if l == 0 else ch[l - 1], ch[l], l), (ch[l], ch[l], l)]
     for l in range(levels - 2, -1, -1):
         out += [(ch[l + 1] + ch[l], ch[l], l), (ch[l], ch[l], l)]
     return out
 
 
-def mask_kernel_model(images: int, n: int, levels: int = 4, base: int = 8) -> dict:
+def mask_kernel_model(images: int, n: int, levels: int = 4, base: int = 8, channels: int = 1) -> dict:
     """Algorithmic HBM bytes and flops per training step of the mask network's
     kernel groups: every tensor read and written once (BF16 activations, FP32
     gradients), convolution flops 2 * pixels * 9 * c_in * c_out."""
@@ -250,7 +250,7 @@ def mask_kernel_model(images: int, n: int, levels: int = 4, base: int = 8) -> di
         bb, ff = m.get(k, (0.0, 0.0))
         m[k] = (bb + b, ff + f)
 
-    for j, (ci, co, l) in enumerate(mask_layers(levels, base)):
+    for j, (ci, co, l) in enumerate(mask_layers(levels, base, channels)):
         px = images * (n >> l) ** 2
         cik = max(ci, 8)
         add("m_conv_fwd", px * (cik + co) * 2, 2.0 * px * 9 * ci * co)
@@ -274,12 +274,14 @@ def train_bench(args) -> int:
 
     cfg = workloads.TRAIN[args.workload]
     B, n, levels = cfg["batch"], cfg["n"], cfg["levels"]
+    C = cfg.get("channels", 1)
+    loss = fmbym.FMBYM_LOSS_L1 if cfg.get("loss") == "l1" else fmbym.FMBYM_LOSS_L2
     kw = workloads.search_kwargs(cfg["search"])
     dev = torch.device("cuda:0")
     pool = 4 * B
     f, g, p = synth.make_batch(cfg["scenes"], pool, split="bench")
     F, G, P = (torch.from_numpy(a).to(dev) for a in (f, g, p.astype(np.float32)))
-    tr = MaskedSearchTrainer(kw, batch=B, cfg=TrainConfig(levels=levels, lr=1e-4))
+    tr = MaskedSearchTrainer(kw, batch=B, cfg=TrainConfig(levels=levels, lr=1e-4, channels=C, loss=loss))
     batches = [(F[k * B:(k + 1) * B].contiguous(), G[k * B:(k + 1) * B].contiguous(),
                 P[k * B:(k + 1) * B].contiguous()) for k in range(pool // B)]
 
@@ -305,7 +307,7 @@ def train_bench(args) -> int:
     fmbym.profile_enable(0)
     per_step = {k: t / psteps for k, (t, c) in prof.items()}
     dom = max(per_step, key=per_step.get)
-    mk = mask_kernel_model(2 * B, n, levels)
+    mk = mask_kernel_model(2 * B // C, n, levels, 8, C)   # samples per network call
     sb = kernel_bytes(n, kw["n_theta"], n, B, masked=True, keep=True)
     if dom in mk:
         byts, flops = mk[dom]
@@ -321,7 +323,9 @@ def train_bench(args) -> int:
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "bf16 conv (fp32 accumulate), f32 search", "data": "synthetic",
-        "config": {"workload": args.workload, "batch": B, "n": n, "levels": levels, "images_per_step": 2 * B},
+        "config": {"workload": args.workload, "batch": B, "n": n, "levels": levels, "channels": C,
+                   "mask_params": int(tr.net.params.numel()), "loss": "l1" if loss == fmbym.FMBYM_LOSS_L1 else "l2",
+                   "images_per_step": 2 * B},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None},
         "conv_fwd_mfma": None if not conv_t else {
@@ -333,20 +337,22 @@ def train_bench(args) -> int:
         from oracle import fmbym_oracle as O
         from oracle import mask_oracle as M
         from paper_2203_00459_amd.train import he_init
-        th = torch.from_numpy(he_init(levels, 8, 0)).double().requires_grad_(True)
+        th = torch.from_numpy(he_init(levels, 8, 0, C)).double().requires_grad_(True)
         done = 0
         t0 = time.perf_counter()
         while done < B and (done < 1 or time.perf_counter() - t0 < CPU_SECONDS):
             X = torch.from_numpy(np.stack([f[done], g[done]])).double()
-            m = M.forward(X, th, levels, 8)
+            m = M.forward(X, th, levels, 8) if C == 1 else M.forward(X[None], th, levels, 8, ch=2)[0]
             pose = O.search(f[done], g[done], O.Params(**kw), m[0], m[1])["pose"]
-            M.pose_loss(pose[None], torch.from_numpy(p[done:done + 1]).double(), "l2").backward()
+            M.pose_loss(pose[None], torch.from_numpy(p[done:done + 1]).double(),
+                        "l1" if loss == fmbym.FMBYM_LOSS_L1 else "l2").backward()
             done += 1
         dt = time.perf_counter() - t0
         res["cpu_baseline"] = {"value": done / dt, "unit": "pairs/s", "cores": torch.get_num_threads(), "cpu": cpu_description(),
                                "kind": "oracle",
                                "sample": f"{done} pairs (about {CPU_SECONDS:.0f} s): FP64 oracle mask network + "
-                                         "masked search + L2 loss, autograd"}
+                                         f"masked search + {'L1' if loss == fmbym.FMBYM_LOSS_L1 else 'L2'} loss, "
+                                         "autograd"}
     print(json.dumps(res), flush=True)
     return 0
 

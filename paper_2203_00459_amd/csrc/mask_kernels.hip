@@ -80,16 +80,22 @@ __device__ __forceinline__ void stage_patch(const bf16* __restrict__ in, u32x4* 
 
 // ------------------------------------------------------------ convolution
 
-// out = conv3x3(in, w) over one 16 x 16-pixel tile per block, all output channels.
-// K runs over (tap, input channel) in groups of 8; every 32-wide K step is one
-// matrix-core instruction per (16-pixel M-tile, 16-channel N-tile).  Each wave
-// owns 4 M-tiles; A comes from the LDS patch, B from the packed weights.
+// out = conv3x3(in, w) over one 16 x 16-pixel tile per block (blockIdx.x) and
+// one chunk of output channels (blockIdx.y): all of them up to 96, else 64 at
+// a time, so that the accumulators stay within 96 registers.  K runs over (tap, input
+// channel) in groups of 8; every 32-wide K step is one matrix-core instruction
+// per (16-pixel M-tile, 16-channel N-tile).  Each wave owns 4 M-tiles; A comes
+// from the LDS patch, B from the packed weights.
+__host__ __device__ constexpr int co_chunk(int cout) { return cout > 96 ? 64 : cout; }
+
 template <int CIN, int COUT, bool STATS, class OutT>
 __global__ __launch_bounds__(256) void k_conv3x3(const bf16* __restrict__ in, const bf16* __restrict__ w,
                                                  OutT* __restrict__ out, float* __restrict__ part,
                                                  int S) {
     constexpr int CC = chunk_ch(CIN), NCH = CIN / CC, G = CC / 8, NQ = 9 * G, NS = (NQ + 3) / 4;
-    constexpr int NT = pad16(COUT) / 16, K = 9 * CIN;
+    constexpr int CO = co_chunk(COUT), NT = pad16(CO) / 16, K = 9 * CIN;
+    static_assert(COUT % CO == 0, "whole output-channel chunks");
+    const int co0 = blockIdx.y * CO;
     static_assert(CIN % 8 == 0 && CIN % CC == 0, "input channels in groups of 8");
     extern __shared__ u32x4 patch[];   // patch_bytes(CIN, S)
     const TileGeo t = conv_tile_geo(blockIdx.x, S);
@@ -127,8 +133,8 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16* __restrict__ in, co
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
                 const int co = nt * 16 + r16;
-                b[nt] = (valid && co < COUT)
-                            ? *(const u32x4*)(w + (size_t)co * K + tap * CIN + c0 + 8 * cg)
+                b[nt] = (valid && co < CO)
+                            ? *(const u32x4*)(w + (size_t)(co0 + co) * K + tap * CIN + c0 + 8 * cg)
                             : zero;
             }
 #pragma unroll
@@ -150,16 +156,16 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16* __restrict__ in, co
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
                 const int co = nt * 16 + r16;
-                if (co >= COUT) continue;
+                if (co >= CO) continue;
                 const float v = acc[mi][nt][r];
                 if constexpr (STATS) {
                     const bf16 h = (bf16)v;
-                    out[pix * COUT + co] = h;
+                    out[pix * COUT + co0 + co] = h;
                     const float hv = (float)h;
                     s1[nt] += hv;
                     s2[nt] += hv * hv;
                 } else {
-                    out[pix * COUT + co] = v;
+                    out[pix * COUT + co0 + co] = v;
                 }
             }
         }
@@ -177,15 +183,15 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16* __restrict__ in, co
             }
         }
         __syncthreads();
-        for (int c = threadIdx.x; c < COUT; c += blockDim.x) {
+        for (int c = threadIdx.x; c < CO; c += blockDim.x) {
             float a = 0.f, b = 0.f;
 #pragma unroll
             for (int wv = 0; wv < 4; ++wv) {
                 a += red[wv][0][c];
                 b += red[wv][1][c];
             }
-            part[(size_t)blockIdx.x * 2 * COUT + c] = a;
-            part[(size_t)blockIdx.x * 2 * COUT + COUT + c] = b;
+            part[(size_t)blockIdx.x * 2 * COUT + co0 + c] = a;
+            part[(size_t)blockIdx.x * 2 * COUT + COUT + co0 + c] = b;
         }
     }
 }
@@ -198,7 +204,8 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16* __restrict__ in, co
 template <int CIN, int COUT>
 struct WgradGeo {
     static constexpr int CC = chunk_ch(CIN), NCH = CIN / CC;
-    static constexpr int MT = pad16(COUT) / 16, NB = 3 * CC, NG = (NB + 15) / 16;
+    static constexpr int CO = co_chunk(COUT);   // output channels per block (blockIdx.y chunks)
+    static constexpr int MT = pad16(CO) / 16, NB = 3 * CC, NG = (NB + 15) / 16;
     static constexpr int WG = NG >= 4 ? 4 : 1;            // waves across groups
     static constexpr int GPW = (NG + WG - 1) / WG;        // groups per wave
     static constexpr int KPW = (kConvTile / 32) * WG / 4; // pixel steps per wave
@@ -210,21 +217,24 @@ struct WgradGeo {
 __host__ __device__ constexpr int wg_pitch(int /*S*/) { return kConvSide + 8; }
 __host__ __device__ constexpr int wg_rows(int /*S*/) { return kConvSide + 2; }
 
-// Weight gradient over `tpb` consecutive tiles per block:
+// Weight gradient over `tpb` consecutive tiles per block (blockIdx.x) for the
+// output channels of chunk blockIdx.y:
 // part[block][co][tap CIN + ci] = sum over the tiles' pixels of dz[p][co] in[p + tap][ci].
 // M = output channels, K = pixels (8 per lane: one tile row), N = (tap, ci).
-// LDS: dz tile transposed [COUT][256], the input patch transposed per channel
-// [CC][rows][pitch] (pixels contiguous), and the wave-reduction area.
+// LDS: the chunk's dz tile transposed [CO][256], the input patch transposed
+// per channel [CC][rows][pitch] (pixels contiguous), and the wave-reduction area.
 template <int CIN, int COUT>
 __global__ __launch_bounds__(256) void k_wgrad(const bf16* __restrict__ dz, const bf16* __restrict__ in,
                                                float* __restrict__ part, int S, int tpb, int tiles) {
     using Geo = WgradGeo<CIN, COUT>;
-    constexpr int CC = Geo::CC, MT = Geo::MT, NB = Geo::NB, NG = Geo::NG, WG = Geo::WG, GPW = Geo::GPW,
-                  KPW = Geo::KPW;
+    constexpr int CC = Geo::CC, CO = Geo::CO, MT = Geo::MT, NB = Geo::NB, NG = Geo::NG, WG = Geo::WG,
+                  GPW = Geo::GPW, KPW = Geo::KPW;
     constexpr int K = 9 * CIN;
+    static_assert(COUT % CO == 0 && CO % 8 == 0, "whole output-channel chunks of 8-channel groups");
+    const int co0 = blockIdx.y * CO;
     extern __shared__ u32x4 smem[];
-    bf16* dzt = reinterpret_cast<bf16*>(smem);                       // [COUT][256]
-    bf16* pt = dzt + COUT * kConvTile;                               // [CC][rows][pitch]
+    bf16* dzt = reinterpret_cast<bf16*>(smem);                       // [CO][256]
+    bf16* pt = dzt + CO * kConvTile;                                 // [CC][rows][pitch]
     const int PW = wg_pitch(S), PRW = wg_rows(S);
     f32x4* red = reinterpret_cast<f32x4*>(pt + (size_t)CC * PRW * PW);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -245,11 +255,11 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16* __restrict__ dz, cons
             const TileGeo t = conv_tile_geo(tile, S);
             const size_t img_base = (size_t)t.img * S * S;
             __syncthreads();
-            // dz tile, transposed
-            for (int it = threadIdx.x; it < kConvTile * COUT / 8; it += blockDim.x) {
-                const int p = it / (COUT / 8), cg = it % (COUT / 8);
+            // the chunk's dz tile, transposed
+            for (int it = threadIdx.x; it < kConvTile * CO / 8; it += blockDim.x) {
+                const int p = it / (CO / 8), cg = it % (CO / 8);
                 const size_t pix = img_base + (size_t)(t.y0 + p / t.pc) * S + t.x0 + p % t.pc;
-                const bf16x8 v = __builtin_bit_cast(bf16x8, *(const u32x4*)(dz + pix * COUT + 8 * cg));
+                const bf16x8 v = __builtin_bit_cast(bf16x8, *(const u32x4*)(dz + pix * COUT + co0 + 8 * cg));
 #pragma unroll
                 for (int j = 0; j < 8; ++j) dzt[(8 * cg + j) * kConvTile + p] = v[j];
             }
@@ -279,7 +289,7 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16* __restrict__ dz, cons
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt) {
                     const int co = mt * 16 + r16;
-                    a[mt] = co < COUT ? *(const u32x4*)(dzt + co * kConvTile + p0) : zero;
+                    a[mt] = co < CO ? *(const u32x4*)(dzt + co * kConvTile + p0) : zero;
                 }
 #pragma unroll
                 for (int gi = 0; gi < GPW; ++gi) {
@@ -344,7 +354,7 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16* __restrict__ dz, cons
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int co = mt * 16 + 4 * g + r;
-                        if (co < COUT) pb[(size_t)co * K + kg] = acc[mt][gi][kx][r];
+                        if (co < CO) pb[(size_t)(co0 + co) * K + kg] = acc[mt][gi][kx][r];
                     }
                 }
             }
@@ -410,23 +420,32 @@ __global__ void k_colsum2(const float* __restrict__ tmp, int nbc, int n, int j0,
 // ------------------------------------------------------------ element-wise
 
 // Scan -> 8-channel BF16 input; image i is x + i S^2, or x_tab[i] for a table of scans.
+// Channel c of pixel p is plane c of x (x + c npix + p) for the dual-input network.
 __global__ void k_input8(const float* __restrict__ x, const float* const* __restrict__ x_tab,
-                         bf16* __restrict__ x8, long long npix, int S2) {
+                         bf16* __restrict__ x8, long long npix, int S2, int ch) {
     const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npix) return;
     bf16x8 v;
 #pragma unroll
     for (int j = 0; j < 8; ++j) v[j] = (bf16)0.f;
-    v[0] = (bf16)(x_tab ? x_tab[p / S2][p % S2] : x[p]);
+    if (x_tab) {
+        v[0] = (bf16)x_tab[p / S2][p % S2];
+    } else {
+        v[0] = (bf16)x[p];
+        if (ch > 1) v[1] = (bf16)x[npix + p];
+    }
     *(u32x4*)(x8 + p * 8) = __builtin_bit_cast(u32x4, v);
 }
 
-// d x of the one-channel input: the first convolution's adjoint in FP32, one
-// pixel per thread, taps and channels summed in a fixed order (ky, kx, c).
+// d x of the network input (plane ci of ch): the first convolution's adjoint
+// in FP32, one pixel per thread, taps and channels summed in a fixed order
+// (ky, kx, c); w is the FP32 weight [C][ch][3][3].
 __global__ void k_input_grad(const bf16* __restrict__ dz, const float* __restrict__ w, float* __restrict__ dx,
-                             long long npix, int S, int C) {
-    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= npix) return;
+                             long long npix, int S, int C, int ch) {
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= npix * ch) return;
+    const int ci = (int)(q / npix);
+    const long long p = q % npix;
     const int S2 = S * S;
     const long long img = p / S2;
     const int i = (int)(p % S2) / S, j = (int)(p % S2) % S;
@@ -438,10 +457,10 @@ __global__ void k_input_grad(const bf16* __restrict__ dz, const float* __restric
             const int x = j + 1 - kx;
             if (x < 0 || x >= S) continue;
             const bf16* d = dz + ((img * S2) + (long long)y * S + x) * C;
-            for (int c = 0; c < C; ++c) acc += w[c * 9 + ky * 3 + kx] * (float)d[c];
+            for (int c = 0; c < C; ++c) acc += w[(c * ch + ci) * 9 + ky * 3 + kx] * (float)d[c];
         }
     }
-    dx[p] = acc;
+    dx[q] = acc;
 }
 
 // Per-thread sums of one channel's partial pairs over the blocks k = t, t + 256, ...
@@ -592,13 +611,18 @@ __global__ void k_up_concat(const bf16* __restrict__ d, const bf16* __restrict__
     *(u32x4*)(cat + p * C + 8 * cg) = outv;
 }
 
+// Output channel o of the head is plane o of mask (mask + o images S^2); w is [ch][C][3][3].
 __global__ void k_head_fwd(const bf16* __restrict__ a, const float* __restrict__ w,
                            const float* __restrict__ b, float* __restrict__ mask, int images, int S,
-                           int C) {
-    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= (long long)images * S * S) return;
+                           int C, int ch) {
+    const long long npix = (long long)images * S * S;
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= npix * ch) return;
+    const int o = (int)(q / npix);
+    const long long p = q % npix;
+    w += (size_t)o * C * 9;
     const int x = (int)(p % S), y = (int)((p / S) % S), img = (int)(p / ((long long)S * S));
-    float acc = b[0];
+    float acc = b[o];
     for (int ky = 0; ky < 3; ++ky) {
         const int yy = y + ky - 1;
         if (yy < 0 || yy >= S) continue;
@@ -613,7 +637,7 @@ __global__ void k_head_fwd(const bf16* __restrict__ a, const float* __restrict__
             }
         }
     }
-    mask[p] = 1.f / (1.f + expf(-acc));
+    mask[q] = 1.f / (1.f + expf(-acc));
 }
 
 __global__ void k_head_dl(const float* __restrict__ dm, const float* __restrict__ m, float* __restrict__ dl,
@@ -624,25 +648,31 @@ __global__ void k_head_dl(const float* __restrict__ dm, const float* __restrict_
     dl[p] = dm[p] * v * (1.f - v);
 }
 
-// g[p][ci] = sum_taps w[ci][tap] dl[p - (ky - 1, kx - 1)], one pixel (8 channels) per thread.
+// g[p][ci] = sum_o sum_taps w[o][ci][tap] dl[o][p - (ky - 1, kx - 1)], one pixel
+// (8 channels) per thread, output channels o in order.
 __global__ void k_head_g(const float* __restrict__ dl, const float* __restrict__ w, float* __restrict__ g,
-                         int images, int S) {
+                         int images, int S, int ch) {
+    const long long npix = (long long)images * S * S;
     const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= (long long)images * S * S) return;
+    if (p >= npix) return;
     const int x = (int)(p % S), y = (int)((p / S) % S), img = (int)(p / ((long long)S * S));
     float acc[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) acc[j] = 0.f;
+    for (int o = 0; o < ch; ++o) {
+        const float* wo = w + (size_t)o * 8 * 9;
+        const float* dlo = dl + o * npix;
 #pragma unroll
-    for (int ky = 0; ky < 3; ++ky) {
-        const int yy = y - (ky - 1);
+        for (int ky = 0; ky < 3; ++ky) {
+            const int yy = y - (ky - 1);
 #pragma unroll
-        for (int kx = 0; kx < 3; ++kx) {
-            const int xx = x - (kx - 1);
-            if (yy < 0 || yy >= S || xx < 0 || xx >= S) continue;
-            const float d = dl[((size_t)img * S + yy) * S + xx];
+            for (int kx = 0; kx < 3; ++kx) {
+                const int xx = x - (kx - 1);
+                if (yy < 0 || yy >= S || xx < 0 || xx >= S) continue;
+                const float d = dlo[((size_t)img * S + yy) * S + xx];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) acc[j] = fmaf(w[j * 9 + ky * 3 + kx], d, acc[j]);
+                for (int j = 0; j < 8; ++j) acc[j] = fmaf(wo[j * 9 + ky * 3 + kx], d, acc[j]);
+            }
         }
     }
     float4* o = reinterpret_cast<float4*>(g + p * 8);
@@ -1010,13 +1040,17 @@ size_t colsum_tmp_floats(int n) { return (size_t)kColChunks * n; }
 
 // ------------------------------------------------------------------ launchers
 
+// (c_in, c_out) of the supported convolutions: the forward pairs of the 4- and
+// 6-level networks (base 8) and their data gradients (c_out -> c_in).
 #define FMBYM_CONV_PAIRS(X)                                                                      \
     X(8, 8) X(8, 16) X(16, 16) X(16, 32) X(32, 32) X(32, 64) X(64, 64) X(96, 32) X(48, 16) X(24, 8) \
-    X(16, 8) X(32, 16) X(64, 32) X(32, 96) X(16, 48) X(8, 24)
+    X(16, 8) X(32, 16) X(64, 32) X(32, 96) X(16, 48) X(8, 24)                                       \
+    X(64, 128) X(128, 128) X(128, 256) X(256, 256) X(384, 128) X(192, 64)                           \
+    X(128, 64) X(256, 128) X(128, 384) X(64, 192)
 
 bool launch_conv3x3(int cin, int cout, bool stats, const bf16* in, const bf16* w, void* z, float* part,
                     int images, int S, hipStream_t s) {
-    const dim3 grid(conv_blocks(images, S)), block(256);
+    const dim3 grid(conv_blocks(images, S), cout / co_chunk(cout)), block(256);
     const size_t lds = patch_bytes(cin, S);
     if (lds + 4 * 2 * 96 * sizeof(float) > kLdsLimit) return false;
 #define FMBYM_CONV_CASE(CI, CO)                                                                   \
@@ -1048,13 +1082,14 @@ bool launch_wgrad(int cin, int cout, const bf16* dz, const bf16* in, float* part
     wgrad_grid(images, S, &nb, &tpb);
     const int tiles = conv_blocks(images, S);
     const int n = cout * 9 * cin;
-#define FMBYM_WGRAD_CASE(CI, CO)                                                                  \
-    if (cin == CI && cout == CO) {                                                                \
-        using Geo = WgradGeo<CI, CO>;                                                             \
-        const size_t lds = (size_t)CO * kConvTile * 2 + (size_t)Geo::CC * wg_rows(S) * wg_pitch(S) * 2 + \
+#define FMBYM_WGRAD_CASE(CI, COUT_)                                                                  \
+    if (cin == CI && cout == COUT_) {                                                                \
+        using Geo = WgradGeo<CI, COUT_>;                                                             \
+        const size_t lds = (size_t)Geo::CO * kConvTile * 2 + (size_t)Geo::CC * wg_rows(S) * wg_pitch(S) * 2 + \
                            Geo::red_bytes;                                                        \
         if (lds > kLdsLimit) return false;                                                        \
-        FMBYM_LAUNCH_LDS(kMWgrad, (k_wgrad<CI, CO>), dim3(nb), dim3(256), lds, s, dz, in, part, S, tpb, tiles); \
+        FMBYM_LAUNCH_LDS(kMWgrad, (k_wgrad<CI, COUT_>), dim3(nb, COUT_ / Geo::CO), dim3(256), lds, s, dz, in, part, S, \
+                         tpb, tiles);                                                             \
         const int nbc = colsum1(kMWgrad, part, nb, (long long)n, n, tmp, s);                       \
         FMBYM_LAUNCH(kMWgrad, k_colsum2, dim3(grid_for(n, 256)), dim3(256), s, tmp, nbc, n, 0, n, dw, \
                      real_cin, cin);                                                              \
@@ -1067,14 +1102,16 @@ bool launch_wgrad(int cin, int cout, const bf16* dz, const bf16* in, float* part
 
 int bn_part_blocks(long long M, int C) { return (int)((M + bn_pixels(C) - 1) / bn_pixels(C)); }
 
-void launch_input8(const float* x, const float* const* x_tab, bf16* x8, int images, int S, hipStream_t s) {
+void launch_input8(const float* x, const float* const* x_tab, bf16* x8, int images, int S, int ch,
+                   hipStream_t s) {
     const long long n = (long long)images * S * S;
-    FMBYM_LAUNCH(kMInput, k_input8, dim3(grid_for(n, 256)), dim3(256), s, x, x_tab, x8, n, S * S);
+    FMBYM_LAUNCH(kMInput, k_input8, dim3(grid_for(n, 256)), dim3(256), s, x, x_tab, x8, n, S * S, ch);
 }
 
-void launch_input_grad(const bf16* dz, const float* w, float* dx, int images, int S, int C, hipStream_t s) {
+void launch_input_grad(const bf16* dz, const float* w, float* dx, int images, int S, int C, int ch,
+                       hipStream_t s) {
     const long long n = (long long)images * S * S;
-    FMBYM_LAUNCH(kMInputGrad, k_input_grad, dim3(grid_for(n, 256)), dim3(256), s, dz, w, dx, n, S, C);
+    FMBYM_LAUNCH(kMInputGrad, k_input_grad, dim3(grid_for(n * ch, 256)), dim3(256), s, dz, w, dx, n, S, C, ch);
 }
 
 void launch_bn_stats(const float* part, int nb, int C, long long M, const float* gamma,
@@ -1103,22 +1140,25 @@ void launch_up_concat(const bf16* d, const bf16* e, bf16* cat, int images, int S
 }
 
 void launch_head_fwd(const bf16* a, const float* w, const float* b, float* mask, int images, int S,
-                     int C, hipStream_t s) {
+                     int C, int ch, hipStream_t s) {
     const long long n = (long long)images * S * S;
-    FMBYM_LAUNCH(kMHeadFwd, k_head_fwd, dim3(grid_for(n, 256)), dim3(256), s, a, w, b, mask, images, S, C);
+    FMBYM_LAUNCH(kMHeadFwd, k_head_fwd, dim3(grid_for(n * ch, 256)), dim3(256), s, a, w, b, mask, images, S, C,
+                 ch);
 }
 
 void launch_head_bwd(const float* d_mask, const float* mask, const bf16* a, const float* w, float* dl,
-                     float* g, float* part, float* tmp, float* dw, float* db, int images, int S, int C,
+                     float* g, float* part, float* tmp, float* dw, float* db, int images, int S, int C, int ch,
                      hipStream_t s) {
     const long long n = (long long)images * S * S;
-    FMBYM_LAUNCH(kMHeadBwd, k_head_dl, dim3(grid_for(n, 256)), dim3(256), s, d_mask, mask, dl, n);
-    FMBYM_LAUNCH(kMHeadBwd, k_head_g, dim3(grid_for(n, 256)), dim3(256), s, dl, w, g, images, S);
+    FMBYM_LAUNCH(kMHeadBwd, k_head_dl, dim3(grid_for(n * ch, 256)), dim3(256), s, d_mask, mask, dl, n * ch);
+    FMBYM_LAUNCH(kMHeadBwd, k_head_g, dim3(grid_for(n, 256)), dim3(256), s, dl, w, g, images, S, ch);
     const int nb = (int)((n + kHeadPix - 1) / kHeadPix), NW = 9 * C + 1;
-    FMBYM_LAUNCH(kMHeadBwd, k_head_wgrad, dim3(nb), dim3(256), s, dl, a, part, images, S);
-    const int nbc = colsum1(kMHeadBwd, part, nb, (long long)NW, NW, tmp, s);
-    FMBYM_LAUNCH(kMHeadBwd, k_colsum2, dim3(1), dim3(128), s, tmp, nbc, NW, 0, 9 * C, dw, 0, 0);
-    FMBYM_LAUNCH(kMHeadBwd, k_colsum2, dim3(1), dim3(64), s, tmp, nbc, NW, 9 * C, 1, db, 0, 0);
+    for (int o = 0; o < ch; ++o) {   // one output channel's weights and bias at a time
+        FMBYM_LAUNCH(kMHeadBwd, k_head_wgrad, dim3(nb), dim3(256), s, dl + o * n, a, part, images, S);
+        const int nbc = colsum1(kMHeadBwd, part, nb, (long long)NW, NW, tmp, s);
+        FMBYM_LAUNCH(kMHeadBwd, k_colsum2, dim3(1), dim3(128), s, tmp, nbc, NW, 0, 9 * C, dw + o * 9 * C, 0, 0);
+        FMBYM_LAUNCH(kMHeadBwd, k_colsum2, dim3(1), dim3(64), s, tmp, nbc, NW, 9 * C, 1, db + o, 0, 0);
+    }
 }
 
 void launch_bn_relu_bwd(const float* g, const bf16* z, const float* stat, const float* gamma, float* part,

@@ -27,13 +27,16 @@ void wgrad_grid(int images, int S, int* blocks, int* tiles_per_block);
 
 // --- launchers (all asynchronous on s; shapes checked by the caller) -------
 
-// x [I][S][S] float (or image i at x_tab[i] when x_tab is not null) -> [I][S][S][8]
-// bf16 with the scan in channel 0, zeros elsewhere.
-void launch_input8(const float* x, const float* const* x_tab, bf16* x8, int images, int S, hipStream_t s);
-// Gradient of the network input x (one channel) from the first convolution's
+// x [ch][I][S][S] float (ch = 1 or 2 planes; for ch = 1 image i may instead
+// come from x_tab[i]) -> [I][S][S][8] bf16 with plane c in channel c, zeros
+// elsewhere.
+void launch_input8(const float* x, const float* const* x_tab, bf16* x8, int images, int S, int ch,
+                   hipStream_t s);
+// Gradient of the network input x [ch][I][S][S] from the first convolution's
 // output gradient dz [images][S][S][C] (BF16, NHWC) and its FP32 weights
-// w [C][1][3][3]: dx[p] = sum_{c, tap} w[c][tap] dz[p - tap + 1][c].
-void launch_input_grad(const bf16* dz, const float* w, float* dx, int images, int S, int C, hipStream_t s);
+// w [C][ch][3][3]: dx[ci][p] = sum_{c, tap} w[c][ci][tap] dz[p - tap + 1][c].
+void launch_input_grad(const bf16* dz, const float* w, float* dx, int images, int S, int C, int ch,
+                       hipStream_t s);
 
 // z = conv3x3(in, w) for (cin, cout) in the supported set; w packed [cout][9 cin]
 // bf16 (k = tap cin + ci, tap = 3 ky + kx).  With stats, z is bf16 and
@@ -70,14 +73,16 @@ void launch_maxpool(const bf16* in, bf16* out, int images, int S, int C, hipStre
 void launch_up_concat(const bf16* d, const bf16* e, bf16* cat, int images, int S, int Cd, int Ce,
                       hipStream_t s);
 
-// Head: mask = sigmoid(conv3x3(a, w) + b), a [I][S][S][C] bf16, w [C][3][3] float.
+// Head: mask = sigmoid(conv3x3(a, w) + b), a [I][S][S][C] bf16, w [ch][C][3][3]
+// float, b [ch]; mask [ch][I][S][S] (plane o is output channel o).
 void launch_head_fwd(const bf16* a, const float* w, const float* b, float* mask, int images, int S,
-                     int C, hipStream_t s);
-// Head adjoint: dl = d_mask m (1 - m); g [I][S][S][C] float = conv3x3^T(dl, w);
-// dw [C][3][3] and db (float, written) through per-block partials in part.
+                     int C, int ch, hipStream_t s);
+// Head adjoint: dl = d_mask m (1 - m) ([ch][I][S][S]); g [I][S][S][C] float =
+// conv3x3^T(dl, w); dw [ch][C][3][3] and db [ch] (float, written) through
+// per-block partials in part.
 void launch_head_bwd(const float* d_mask, const float* mask, const bf16* a, const float* w,
                      float* dl, float* g, float* part, float* tmp, float* dw, float* db, int images, int S,
-                     int C, hipStream_t s);
+                     int C, int ch, hipStream_t s);
 
 // Batch-norm + ReLU adjoint given g = dL/da (float): dy = g [a > 0];
 // dgamma = sum dy xhat, dbeta = sum dy (written to dgamma/dbeta);
@@ -100,7 +105,7 @@ void launch_up_bwd(const float* d_cat, float* d_d, int images, int S, int Cd, in
 // cin zero) and, where pb >= 0, the data-gradient layout [cin][9 cout] with
 // the taps flipped: every layer of a network in one launch.  Offsets count
 // floats of params (w) and bf16 elements of the packed buffer (pf, pb).
-constexpr int kMaxPackLayers = 16;
+constexpr int kMaxPackLayers = 24;
 struct PackLayers {
     int n;
     int cin[kMaxPackLayers], cout[kMaxPackLayers], cink[kMaxPackLayers];

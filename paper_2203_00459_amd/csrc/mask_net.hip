@@ -3,7 +3,8 @@
 //
 // Layer plan (parameter order): enc0a, enc0b, ..., enc(L-1)a, enc(L-1)b,
 // dec(L-2)a, dec(L-2)b, ..., dec0a, dec0b, then the head.  Inputs: enc0a reads
-// the scan (as 8 channels, the scan in channel 0), enc{l}a reads the max-pool
+// the scans (as 8 channels: one scan in channel 0, or for the dual-input
+// network f in channel 0 and g in channel 1), enc{l}a reads the max-pool
 // of enc{l-1}b's activation, every b conv reads its a conv's activation,
 // dec{l}a reads concat[up2(deeper), enc{l}b] where deeper is dec{l+1}b (or
 // enc{L-1}b at the bottom).  The head reads the last conv's activation.
@@ -29,7 +30,7 @@ struct ConvL {
 };
 
 struct Net {
-    int levels = 0, base = 0;
+    int levels = 0, base = 0, chans = 1;   // chans: input scans and output masks per sample
     float eps = 0.f, momentum = 0.f;
     std::vector<ConvL> convs;
     size_t n_params = 0, n_packed = 0, head_w = 0, head_b = 0;
@@ -48,10 +49,12 @@ struct Net {
 size_t al64(size_t x) { return (x + 63) & ~(size_t)63; }
 
 bool build_net(const fmbym_mask_desc* d, Net& net) {
-    if (!d || d->levels < 1 || d->levels > 4 || d->base_channels != 8) return false;
+    if (!d || d->levels < 1 || d->levels > 6 || d->base_channels != 8) return false;
+    if (d->channels != 0 && d->channels != 1 && d->channels != 2) return false;
     net = Net();
     net.levels = d->levels;
     net.base = d->base_channels;
+    net.chans = d->channels == 2 ? 2 : 1;
     net.eps = d->bn_eps;
     net.momentum = d->bn_momentum;
     size_t po = 0, pk = 0;
@@ -79,7 +82,7 @@ bool build_net(const fmbym_mask_desc* d, Net& net) {
         net.convs.push_back(c);
     };
     for (int l = 0; l < net.levels; ++l) {
-        add(l == 0 ? 1 : net.ch(l - 1), net.ch(l), l, true, true);
+        add(l == 0 ? net.chans : net.ch(l - 1), net.ch(l), l, true, true);
         add(net.ch(l), net.ch(l), l, true, false);
     }
     for (int l = net.levels - 2; l >= 0; --l) {
@@ -87,9 +90,9 @@ bool build_net(const fmbym_mask_desc* d, Net& net) {
         add(net.ch(l), net.ch(l), l, false, false);
     }
     net.head_w = po;
-    po += (size_t)net.base * 9;
+    po += (size_t)net.chans * net.base * 9;
     net.head_b = po;
-    po += 1;
+    po += net.chans;
     net.n_params = po;
     net.n_packed = pk;
     net.bn_channels = bn;
@@ -134,9 +137,9 @@ ActLayout act_layout(const Net& net, int I, int n) {
     for (int l = 1; l < net.levels; ++l) L.pool[l] = b.take(pix(l) * net.ch(l - 1) * bf);
     L.cat.assign(net.levels, 0);
     for (int l = 0; l + 1 < net.levels; ++l) L.cat[l] = b.take(pix(l) * (net.ch(l + 1) + net.ch(l)) * bf);
-    L.mask = b.take(pix(0) * fl);
+    L.mask = b.take(pix(0) * net.chans * fl);
     L.part = b.take(part_max);
-    L.tmp = b.take(colsum_tmp_floats(2 * 96) * fl);
+    L.tmp = b.take(colsum_tmp_floats(2 * 256) * fl);
     L.total = b.off;
     return L;
 }
@@ -166,11 +169,11 @@ WsLayout ws_layout(const Net& net, int I, int n) {
     for (int l = 0; l + 1 < net.levels; ++l) L.dcat[l] = b.take(pix(l) * (net.ch(l + 1) + net.ch(l)) * fl);
     L.dz = b.take(dz_max);
     L.part = b.take(part_max);
-    L.coef = b.take(3 * 96 * fl);
+    L.coef = b.take(3 * 256 * fl);   // per-channel coefficients of the widest BN layer
     L.wpart = b.take(wpart_max);
-    L.dl = b.take(pix(0) * fl);
+    L.dl = b.take(pix(0) * net.chans * fl);
     L.hpart = b.take(((pix(0) + 4095) / 4096) * (9 * net.base + 1) * fl);
-    size_t cols = 2 * 96;
+    size_t cols = 2 * 256;
     for (const ConvL& c : net.convs) cols = std::max(cols, (size_t)c.cout * 9 * c.cink);
     L.tmp = b.take(colsum_tmp_floats((int)cols) * fl);
     L.total = b.off;
@@ -273,7 +276,8 @@ int fmbym_mask_bwd(const fmbym_mask_desc* d, int32_t I, int32_t n, const float* 
     const int last = net.last();
     launch_head_bwd(d_mask, at<float>(act, A.mask), at<bf16>(act, A.a[last]), P + net.head_w,
                     at<float>(wsp, W.dl), at<float>(wsp, W.g[last]), at<float>(wsp, W.hpart),
-                    at<float>(wsp, W.tmp), d_params + net.head_w, d_params + net.head_b, I, n, net.base, s);
+                    at<float>(wsp, W.tmp), d_params + net.head_w, d_params + net.head_b, I, n, net.base,
+                    net.chans, s);
     for (int j = last; j >= 0; --j) {
         const ConvL& c = net.convs[j];
         const int S = n >> c.level;
@@ -296,7 +300,7 @@ int fmbym_mask_bwd(const fmbym_mask_desc* d, int32_t I, int32_t n, const float* 
                           d_params + c.w, c.cin, I, S, s))
             return FMBYM_EUNSUPPORTED;
         if (j == 0) {
-            if (d_x) launch_input_grad(dz, P + c.w, d_x, I, S, c.cout, s);
+            if (d_x) launch_input_grad(dz, P + c.w, d_x, I, S, c.cout, net.chans, s);
             break;
         }
         // data gradient into the buffer of this conv's input
@@ -358,13 +362,14 @@ int mask_forward(const fmbym_mask_desc* d, int I, int n, const float* x, const f
     if (!build_net(d, net)) return FMBYM_EUNSUPPORTED;
     if (!size_ok(net, I, n)) return FMBYM_EUNSUPPORTED;
     if ((!x && !x_tab) || !mask || !d->params || !d->packed || !d->bn_running) return FMBYM_EINVAL;
+    if (x_tab && net.chans != 1) return FMBYM_EUNSUPPORTED;   // scan tables hold one scan per image
     if (!(d->bn_eps > 0.f) || !(d->bn_momentum >= 0.f && d->bn_momentum <= 1.f)) return FMBYM_EINVAL;
     const ActLayout A = act_layout(net, I, n);
     if (!act || act_bytes < A.total) return FMBYM_EWORKSPACE;
     const bf16* pk = (const bf16*)d->packed;
     float* run_mean = d->bn_running;
     float* run_var = d->bn_running + net.bn_channels;
-    launch_input8(x, x_tab, at<bf16>(act, A.x8), I, n, s);
+    launch_input8(x, x_tab, at<bf16>(act, A.x8), I, n, net.chans, s);
     for (int j = 0; j <= net.last(); ++j) {
         const ConvL& c = net.convs[j];
         const int S = n >> c.level;
@@ -392,8 +397,8 @@ int mask_forward(const fmbym_mask_desc* d, int I, int n, const float* x, const f
         launch_bn_relu(at<bf16>(act, A.z[j]), at<float>(act, A.stat[j]), at<bf16>(act, A.a[j]), M, c.cout, s);
     }
     launch_head_fwd(at<bf16>(act, A.a[net.last()]), d->params + net.head_w, d->params + net.head_b, mask, I,
-                    n, net.base, s);
-    (void)hipMemcpyAsync(at<float>(act, A.mask), mask, (size_t)I * n * n * sizeof(float),
+                    n, net.base, net.chans, s);
+    (void)hipMemcpyAsync(at<float>(act, A.mask), mask, (size_t)net.chans * I * n * n * sizeof(float),
                          hipMemcpyDeviceToDevice, s);
     return finish(s);
 }

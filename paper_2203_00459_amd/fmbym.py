@@ -84,7 +84,7 @@ class fmbym_mask_desc(ctypes.Structure):
     _fields_ = [
         ("levels", ctypes.c_int32), ("base_channels", ctypes.c_int32), ("bn_eps", ctypes.c_float),
         ("bn_momentum", ctypes.c_float), ("params", ctypes.c_void_p), ("packed", ctypes.c_void_p),
-        ("bn_running", ctypes.c_void_p),
+        ("bn_running", ctypes.c_void_p), ("channels", ctypes.c_int32),
     ]
 
 
@@ -731,12 +731,14 @@ def pose_loss(batch, pose, target, kind, loss, d_pose, stream) -> None:
 class MaskNet:
     """Device buffers of the mask network (FP32 parameters, BF16 packed
     weights, running statistics, Adam moments) and its calls on torch tensors.
-    ``params`` uses the library's flat layout (include/fmbym_mask.h)."""
+    ``params`` uses the library's flat layout (include/fmbym_mask.h).
+    channels = 2 is the dual-input network: scans and masks are passed as the
+    stacked planes [f batch; g batch] ([2 B, n, n])."""
 
     def __init__(self, params, levels: int = 4, base: int = 8, bn_eps: float = 1e-5,
-                 bn_momentum: float = 0.1, device="cuda:0"):
-        self.levels, self.base = levels, base
-        self.desc = fmbym_mask_desc(levels, base, bn_eps, bn_momentum, None, None, None)
+                 bn_momentum: float = 0.1, device="cuda:0", channels: int = 1):
+        self.levels, self.base, self.channels = levels, base, channels
+        self.desc = fmbym_mask_desc(levels, base, bn_eps, bn_momentum, None, None, None, channels)
         n_p = mask_param_count(self.desc)
         if n_p == 0:
             raise FmbymError(FMBYM_EUNSUPPORTED, "fmbym_mask_param_count")
@@ -768,14 +770,18 @@ class MaskNet:
         return cur
 
     def forward(self, x, training: bool = True):
-        """x [I, n, n] float32 scans -> masks [I, n, n]; keeps the activations for backward."""
-        I, n = x.shape[0], x.shape[-1]
+        """x [C I, n, n] float32 scans (C planes of I) -> masks [C I, n, n]; keeps the
+        activations for backward."""
+        C = self.channels
+        I, n = x.shape[0] // C, x.shape[-1]
+        if I * C != x.shape[0]:
+            raise ValueError(f"x: {x.shape[0]} scans is not a multiple of {C} planes")
         need = mask_activation_bytes(self.desc, I, n)
         if need == 0:
             raise FmbymError(FMBYM_EUNSUPPORTED, "fmbym_mask_activation_bytes")
         act = self._buf("_act", need, x.device)
-        mask = torch.empty(I, n, n, device=x.device)
-        mask_fwd(self.desc, I, n, _ptr(x, (I, n, n), "x"), mask.data_ptr(), act.data_ptr(), act.numel(),
+        mask = torch.empty(C * I, n, n, device=x.device)
+        mask_fwd(self.desc, I, n, _ptr(x, (C * I, n, n), "x"), mask.data_ptr(), act.data_ptr(), act.numel(),
                  training, _stream())
         self._shape = (I, n)
         return mask
@@ -784,11 +790,12 @@ class MaskNet:
         """dL/dparams (flat FP32) of the last training forward, given dL/dmask;
         with input_grad, the pair (dL/dparams, dL/dx)."""
         I, n = self._shape
+        C = self.channels
         need = mask_workspace_bytes(self.desc, I, n)
         ws = self._buf("_ws", need, d_mask.device)
         d_params = torch.empty_like(self.params)
-        d_x = torch.empty(I, n, n, device=d_mask.device) if input_grad else None
-        mask_bwd(self.desc, I, n, _ptr(d_mask.contiguous(), (I, n, n), "d_mask"), self._act.data_ptr(),
+        d_x = torch.empty(C * I, n, n, device=d_mask.device) if input_grad else None
+        mask_bwd(self.desc, I, n, _ptr(d_mask.contiguous(), (C * I, n, n), "d_mask"), self._act.data_ptr(),
                  self._act.numel(), d_params.data_ptr(), ws.data_ptr(), ws.numel(), _stream(),
                  d_x=None if d_x is None else d_x.data_ptr())
         return (d_params, d_x) if input_grad else d_params

@@ -58,7 +58,14 @@ WORKLOADS = {
     # mask-training pairs at 256 x 256 with moving clutter and multipath ghosts
     "mask256": SceneSpec(n=256, delta=0.35, n_reflectors=60, n_segments=20, speckle_sigma=0.15,
                          distractors=True),
+    # the same at 512 x 512, 0.2 m/px (the dual-input network's training pairs)
+    "mask512": SceneSpec(n=512, delta=0.2, n_reflectors=60, n_segments=20, speckle_sigma=0.15,
+                         distractors=True),
 }
+
+# Seed stream of each family (fixed: adding a family never reseeds another).
+WORKLOAD_ID = {"batch256": 1, "batch512": 2, "mask256": 3, "pair128": 4, "paper127": 5, "paper255": 6,
+               "paper511": 7, "mask512": 8}
 
 SPLIT_OFFSET = {"train": 0, "val": 1_000_000, "test": 2_000_000, "bench": 3_000_000}
 
@@ -218,7 +225,7 @@ def make_batch(name: str, batch: int, split: str = "test", start: int = 0,
     spec = WORKLOADS[name]
     if theta_max_deg is not None:
         spec = dataclasses.replace(spec, theta_max_deg=float(theta_max_deg))
-    wid = sorted(WORKLOADS).index(name) + 1
+    wid = WORKLOAD_ID[name]
     fs, gs, ps = [], [], []
     for i in range(batch):
         f, g, p = make_pair(spec, wid, split, start + i)

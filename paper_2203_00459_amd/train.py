@@ -22,22 +22,22 @@ import torch
 from . import fmbym
 
 
-def he_init(levels: int, base: int, seed: int) -> np.ndarray:
+def he_init(levels: int, base: int, seed: int, channels: int = 1) -> np.ndarray:
     """Flat parameters in the library's layout: He-normal conv weights
     (std sqrt(2 / (9 c_in))), BatchNorm gamma 1 and beta 0, head weights with
-    std sqrt(1 / (9 base)) and a zero bias."""
+    std sqrt(1 / (9 base)) and zero biases; `channels` scans in and masks out."""
     rng = np.random.Generator(np.random.PCG64(seed))
     ch = [base << l for l in range(levels)]
     convs = []
     for l in range(levels):
-        convs += [(1 if l == 0 else ch[l - 1], ch[l]), (ch[l], ch[l])]
+        convs += [(channels if l == 0 else ch[l - 1], ch[l]), (ch[l], ch[l])]
     for l in range(levels - 2, -1, -1):
         convs += [(ch[l + 1] + ch[l], ch[l]), (ch[l], ch[l])]
     parts = []
     for cin, cout in convs:
         parts += [rng.normal(0.0, math.sqrt(2.0 / (9 * cin)), cout * cin * 9), np.ones(cout),
                   np.zeros(cout)]
-    parts += [rng.normal(0.0, math.sqrt(1.0 / (9 * base)), base * 9), np.zeros(1)]
+    parts += [rng.normal(0.0, math.sqrt(1.0 / (9 * base)), channels * base * 9), np.zeros(channels)]
     return np.concatenate(parts).astype(np.float32)
 
 
@@ -45,6 +45,7 @@ def he_init(levels: int, base: int, seed: int) -> np.ndarray:
 class TrainConfig:
     levels: int = 4
     base: int = 8
+    channels: int = 1          # 2: the dual-input network (both scans in, both masks out)
     lr: float = 1e-3
     loss: int = fmbym.FMBYM_LOSS_L2
     seed: int = 0
@@ -58,11 +59,14 @@ class MaskedSearchTrainer:
         self.cfg = cfg
         self.batch = batch
         self.search = fmbym.Search(max_batch=batch, **search_kwargs)
-        p = he_init(cfg.levels, cfg.base, cfg.seed) if params is None else params
-        self.net = fmbym.MaskNet(p, levels=cfg.levels, base=cfg.base)
+        p = he_init(cfg.levels, cfg.base, cfg.seed, cfg.channels) if params is None else params
+        self.net = fmbym.MaskNet(p, levels=cfg.levels, base=cfg.base, channels=cfg.channels)
         self.use_mask = False
 
     def masks(self, f, g, training: bool):
+        """Masks of both scans of every pair: the scans stacked [f; g] go through
+        the network as 2B images (shared weights) or, for the dual-input network,
+        as B samples of two channels; either way the masks come back [m_f; m_g]."""
         B = f.shape[0]
         m = self.net.forward(torch.cat([f, g]), training=training)
         return m[:B].contiguous(), m[B:].contiguous()

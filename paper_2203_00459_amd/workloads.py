@@ -45,6 +45,10 @@ RAGGED = {
 TRAIN = {
     # 16 pairs of 256 x 256 scans with moving clutter and multipath ghosts; search as batch256
     "mask256": dict(batch=16, n=256, levels=4, scenes="mask256", search="batch256"),
+    # Table II's dual-input network (6 levels, 8 -> 256 channels, both scans in, both
+    # masks out) at 512 x 512 with distractors, 4 pairs per step, L1 loss (Eq. 13),
+    # Adam at 1e-4; search as batch512
+    "dual512": dict(batch=4, n=512, levels=6, channels=2, scenes="mask512", search="batch512", loss="l1"),
 }
 
 

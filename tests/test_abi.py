@@ -118,8 +118,12 @@ def test_mask_calls_reject_bad_arguments():
     assert fmbym.mask_activation_bytes(d, 4, 64) == 0          # 64 >> 3 < 16 and n unsupported
     assert fmbym.mask_activation_bytes(d, 4, 128) > 0
     assert fmbym.mask_workspace_bytes(d, 0, 256) == 0
-    bad = fmbym.fmbym_mask_desc(5, 8, 1e-5, 0.1, None, None, None)
+    bad = fmbym.fmbym_mask_desc(7, 8, 1e-5, 0.1, None, None, None)
     assert fmbym.mask_param_count(bad) == 0
+    assert fmbym.mask_param_count(fmbym.fmbym_mask_desc(4, 8, 1e-5, 0.1, None, None, None, 3)) == 0
+    six = fmbym.fmbym_mask_desc(6, 8, 1e-5, 0.1, None, None, None, 2)
+    assert fmbym.mask_activation_bytes(six, 1, 256) == 0         # 256 >> 5 < 16
+    assert fmbym.mask_activation_bytes(six, 1, 512) > 0
     assert L.fmbym_mask_fwd(ctypes.byref(bad), 1, 128, None, None, None, 0, 1, None) == fmbym.FMBYM_EUNSUPPORTED
     assert L.fmbym_mask_fwd(ctypes.byref(d), 1, 128, None, None, None, 0, 1, None) == fmbym.FMBYM_EINVAL
     assert L.fmbym_mask_bwd(None, 1, 128, None, None, 0, None, None, None, 0, None) == fmbym.FMBYM_EINVAL
@@ -130,9 +134,15 @@ def test_mask_calls_reject_bad_arguments():
 
 def test_mask_param_count_matches_the_oracle_layout():
     from oracle import mask_oracle as M
-    for levels in (1, 2, 3, 4):
-        d = fmbym.fmbym_mask_desc(levels, 8, 1e-5, 0.1, None, None, None)
-        assert fmbym.mask_param_count(d) == M.param_count(levels, 8)
+    for levels in (1, 2, 3, 4, 5, 6):
+        for ch in (1, 2):
+            d = fmbym.fmbym_mask_desc(levels, 8, 1e-5, 0.1, None, None, None, ch)
+            assert fmbym.mask_param_count(d) == M.param_count(levels, 8, ch)
+    # Table II's dual-input network: 1,965,024 convolution weights (about 1.97 M),
+    # 1504 BatchNorm channels, two head biases
+    d = fmbym.fmbym_mask_desc(6, 8, 1e-5, 0.1, None, None, None, 2)
+    assert fmbym.mask_bn_channels(d) == 1504
+    assert fmbym.mask_param_count(d) == 1_965_024 + 2 * 1504 + 2
 
 
 def test_ragged_mix_counts_and_order():

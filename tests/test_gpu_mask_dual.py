@@ -1,0 +1,143 @@
+"""Table II's dual-input mask network on the GPU against the FP64 oracle.
+
+The network sees both scans of a pair as two input channels and returns both
+masks; its six levels run 8 -> 256 channels (about 1.97 M weights), so its
+deep convolutions split their output channels into chunks of 64 on the matrix
+cores.  The scans and masks travel as the stacked planes [f batch; g batch],
+the oracle's [pair, channel] layout transposed.  Bar as for the one-channel
+network: |gpu - exact| <= 2 |quant - exact| + tau (tau 1e-4 for the masks,
+1e-3 relative for gradients, normwise per parameter group), where quant is the
+oracle with BF16 storage at the GPU's rounding points."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mask_oracle as M
+from paper_2203_00459_amd import fmbym, synth
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+DT = torch.float64
+
+
+def _pairs(name, B, split="val"):
+    f, g, _ = synth.make_batch(name, B, split=split)
+    planes = np.concatenate([f, g])                      # [2B, n, n]: plane 0 then plane 1
+    oracle_x = torch.from_numpy(np.stack([f, g], axis=1)).to(DT)   # [B, 2, n, n]
+    return planes, oracle_x
+
+
+def _to_oracle(t, B):
+    """[2B, n, n] planes -> [B, 2, n, n]."""
+    n = t.shape[-1]
+    return t.reshape(2, B, n, n).permute(1, 0, 2, 3)
+
+
+def _groups(levels):
+    out, o = [], 0
+    for c in M.conv_list(levels, 8, 2):
+        nw = c.c_out * c.c_in * 9
+        out += [(c.name + ".w", slice(o, o + nw)), (c.name + ".gamma", slice(o + nw, o + nw + c.c_out)),
+                (c.name + ".beta", slice(o + nw + c.c_out, o + nw + 2 * c.c_out))]
+        o += nw + 2 * c.c_out
+    out += [("head.w", slice(o, o + 2 * 72)), ("head.b", slice(o + 2 * 72, o + 2 * 72 + 2))]
+    return out
+
+
+CASES = [(6, "batch512", 2), (2, "pair128", 3)]
+
+
+@pytest.mark.parametrize("levels,scene,B", CASES)
+def test_dual_forward_matches_oracle(levels, scene, B):
+    print(f"dual fwd levels={levels} scene={scene} B={B}", flush=True)
+    x, X = _pairs(scene, B)
+    p = M.init_params(levels, 8, seed=3, ch=2)
+    net = fmbym.MaskNet(p, levels=levels, channels=2)
+    assert net.params.numel() == M.param_count(levels, 8, 2)
+    m = _to_oracle(net.forward(torch.from_numpy(x).to(DEV)).double().cpu(), B)
+    P = torch.from_numpy(p).to(DT)
+    ref = M.forward(X, P, levels, 8, ch=2)
+    ref_q = M.forward(X, P, levels, 8, quant=True, ch=2)
+    eg, eq = (m - ref).abs(), (ref_q - ref).abs()
+    print(f"  |gpu-exact| max {eg.max():.3e} mean {eg.mean():.3e}; |quant-exact| max {eq.max():.3e} "
+          f"mean {eq.mean():.3e}", flush=True)
+    assert float(eg.max()) <= 2 * float(eq.max()) + 1e-4
+    assert float(eg.mean()) <= 2 * float(eq.mean()) + 1e-4
+
+
+@pytest.mark.parametrize("levels,scene,B", CASES)
+def test_dual_backward_matches_oracle(levels, scene, B):
+    """Parameter gradient per group and the input gradient of both scan channels."""
+    print(f"dual bwd levels={levels} scene={scene} B={B}", flush=True)
+    x, X = _pairs(scene, B)
+    n = x.shape[-1]
+    p = M.init_params(levels, 8, seed=4, ch=2)
+    net = fmbym.MaskNet(p, levels=levels, channels=2)
+    dm = np.random.Generator(np.random.PCG64(17)).normal(size=(2 * B, n, n)).astype(np.float32)
+    net.forward(torch.from_numpy(x).to(DEV))
+    g_p, g_x = net.backward(torch.from_numpy(dm).to(DEV), input_grad=True)
+    g_p = g_p.double().cpu()
+    g_x = _to_oracle(g_x.double().cpu(), B)
+    D = _to_oracle(torch.from_numpy(dm).to(DT), B)
+    P = torch.from_numpy(p).to(DT)
+    ref = M.grad(X, D, P, levels, 8, ch=2)
+    ref_q = M.grad(X, D, P, levels, 8, quant=True, ch=2)
+    worst = 0.0
+    for name, sl in _groups(levels):
+        nr = max(float(ref[sl].norm()), 1e-30)
+        eg = float((g_p[sl] - ref[sl]).norm()) / nr
+        eq = float((ref_q[sl] - ref[sl]).norm()) / nr
+        worst = max(worst, eg / (eq + 1e-3))
+        assert eg <= 2 * eq + 1e-3, (name, eg, eq)
+    print(f"  worst parameter group ratio {worst:.3f}", flush=True)
+    rx = M.grad_input(X, D, P, levels, 8, ch=2)
+    rxq = M.grad_input(X, D, P, levels, 8, quant=True, ch=2)
+    nr = float(rx.norm())
+    eg = float((g_x - rx).norm()) / nr
+    eq = float((rxq - rx).norm()) / nr
+    print(f"  d_x: |gpu-exact| {eg:.3e} |quant-exact| {eq:.3e}", flush=True)
+    assert eg <= 2 * eq + 1e-3
+
+
+def test_dual_inference_mode_and_running_statistics():
+    """Running statistics after a training pass, then the inference forward on them."""
+    levels, B = 6, 2
+    x, X = _pairs("mask512", B, split="test")
+    p = M.init_params(levels, 8, seed=5, ch=2)
+    net = fmbym.MaskNet(p, levels=levels, channels=2)
+    nbn = net.bn_running.numel() // 2
+    rm0, rv0 = torch.zeros(nbn, dtype=DT), torch.ones(nbn, dtype=DT)
+    xt = torch.from_numpy(x).to(DEV)
+    net.forward(xt, training=True)
+    torch.cuda.synchronize()
+    P = torch.from_numpy(p).to(DT)
+    rm, rv = M.running_stats(X, P, levels, 8, rm0, rv0, quant=True, ch=2)
+    got = net.bn_running.double().cpu()
+    e_m = float((got[:nbn] - rm).abs().max() / rm.abs().max())
+    e_v = float((got[nbn:] - rv).abs().max() / rv.abs().max())
+    print(f"running mean {e_m:.2e} var {e_v:.2e}", flush=True)
+    assert e_m <= 1e-2 and e_v <= 1e-2
+    m = _to_oracle(net.forward(xt, training=False).double().cpu(), B)
+    ref = M.forward_eval(X, P, levels, 8, got[:nbn], got[nbn:], ch=2)
+    e = float((m - ref).abs().max())
+    print(f"inference masks max |gpu - exact| {e:.3e}", flush=True)
+    assert e <= 5e-2
+
+
+def test_dual_training_step_runs_through_the_search():
+    """One training step of the dual network through the masked search (L1, Eq. 13):
+    finite loss and gradients, and parameters that move."""
+    from paper_2203_00459_amd import workloads
+    from paper_2203_00459_amd.train import MaskedSearchTrainer, TrainConfig
+    kw = workloads.search_kwargs("batch512")
+    f, g, pose = synth.make_batch("mask512", 2, split="train")
+    F, G, T = (torch.from_numpy(a.astype(np.float32)).to(DEV) for a in (f, g, pose))
+    tr = MaskedSearchTrainer(kw, batch=2, cfg=TrainConfig(levels=6, channels=2, lr=1e-4,
+                                                         loss=fmbym.FMBYM_LOSS_L1))
+    before = tr.net.params.clone()
+    loss, out = tr.step(F, G, T)
+    torch.cuda.synchronize()
+    assert torch.isfinite(loss).all() and torch.isfinite(out).all()
+    assert not torch.equal(before, tr.net.params)
+    assert torch.isfinite(tr.net.params).all()
