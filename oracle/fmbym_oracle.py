@@ -46,7 +46,9 @@ library, which implements the same definitions):
     above; Algorithm 1's BuildSO2(-theta) matches the reversed correlation
     order).
   * Soft-argmax uses softmax((c - max c) / T); with ``zscore`` the scores are
-    first standardised (c - mean) / std.
+    first standardised (c - mean) / std.  With ``hard_argmax`` both stages take
+    the lag of the first maximum instead (the search of Eq. 2-3 without the
+    soft relaxation).
 """
 from __future__ import annotations
 
@@ -75,6 +77,7 @@ class Params:
     angle_marginal: bool = False
     zscore: bool = False
     xy_unwindowed: bool = False
+    hard_argmax: bool = False
 
     @property
     def radii(self) -> int:
@@ -280,6 +283,18 @@ def xy_correlation(fw: torch.Tensor, gp: torch.Tensor) -> torch.Tensor:
 
 # --------------------------------------------------------------- soft-argmax
 
+def argmax_weights(c: torch.Tensor) -> torch.Tensor:
+    """One-hot weights at the first maximum of c in storage (row-major) order."""
+    w = torch.zeros(c.numel(), dtype=c.dtype)
+    w[int(torch.argmax(c.reshape(-1)))] = 1.0
+    return w.reshape(c.shape)
+
+
+def score_weights(c: torch.Tensor, p: "Params", temp: float) -> torch.Tensor:
+    """The weights of a stage's candidates: hard argmax or temperature softmax."""
+    return argmax_weights(c) if p.hard_argmax else softmax_weights(c, temp, p.zscore)
+
+
 def softmax_weights(c: torch.Tensor, temp: float, zscore: bool) -> torch.Tensor:
     """p = softmax((c - max c) / T) over all entries (Section III-D, SoftArgMax)."""
     z = c.reshape(-1)
@@ -301,7 +316,7 @@ def stage_rotation(fw: torch.Tensor, gw: torch.Tensor, p: Params):
     pg = cart2pol(ag, p.radii, p.n_theta)
     c_theta = angle_correlation_marginal(pf, pg) if p.angle_marginal else angle_correlation(pf, pg)
     grid = lag_indices(p.n_theta).to(F64) * (math.pi / p.n_theta)
-    w = softmax_weights(c_theta, p.temp_theta, p.zscore)
+    w = score_weights(c_theta, p, p.temp_theta)
     theta = (w * grid).sum()
     return theta, c_theta, dict(af=af, ag=ag, pf=pf, pg=pg)
 
@@ -312,7 +327,7 @@ def stage_translation(fw: torch.Tensor, gw: torch.Tensor, theta: torch.Tensor, p
     gp = rotate(gw, theta)
     c_xy = xy_correlation_direct(fw, gp) if direct else xy_correlation(fw, gp)
     lag = lag_indices(p.n).to(F64) * p.delta_xy
-    w = softmax_weights(c_xy, p.temp_xy, p.zscore)
+    w = score_weights(c_xy, p, p.temp_xy)
     tpx = (w * lag[None, :]).sum()
     tpy = (w * lag[:, None]).sum()
     ct, st = torch.cos(theta), torch.sin(theta)

@@ -703,3 +703,19 @@ def test_known_pose_pairs_at_the_papers_127_px():
         t_err.append(np.hypot(est[1] - pose[1], est[2] - pose[2]))
     assert max(th_err) <= math.radians(1.5) and np.median(th_err) <= math.radians(0.5)
     assert max(t_err) <= 0.8
+
+
+def test_hard_argmax_reading_on_integer_shifts_and_ties():
+    """The hard-argmax reading (Eq. 2-3 without the soft relaxation): integer shifts of a
+    compact scene come back exactly (Cauchy-Schwarz: the correlation peaks at the shift),
+    and among equal maxima the first in storage order wins."""
+    n = 32
+    f = _blob_scene(n, [(12, 14), (18, 11), (15, 20), (10, 9)], [1.0, 0.7, 0.5, 0.9])
+    for s in [(3, -2), (-4, 5), (0, 1)]:
+        g = torch.roll(f, shifts=s, dims=(0, 1))
+        p = O.Params(n=n, n_theta=32, delta_xy=0.25, hann=False, hard_argmax=True)
+        out = O.search(f, g, p)
+        assert float(out["theta"]) == 0.0
+        assert float(out["tx"]) == 0.25 * s[1] and float(out["ty"]) == 0.25 * s[0]
+    w = O.argmax_weights(torch.tensor([[1.0, 3.0, 3.0], [0.0, 3.0, 2.0]], dtype=F64))
+    assert w.tolist() == [[0.0, 1.0, 0.0], [0.0, 0.0, 0.0]]
