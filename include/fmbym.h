@@ -60,7 +60,24 @@ extern "C" {
 
 /* flags */
 #define FMBYM_HANN 1u           /* periodic Hann window on both scans (Algorithm 1) */
+#define FMBYM_ANGLE_MARGINAL 2u /* heading scores from the radius-summed polar profiles,
+                                   c[l] = (1/n_r) sum_a S_f[a] S_g[a + l] with S = sum over
+                                   radii: the marginal reading of Algorithm 1's "Mean over
+                                   r" (default: Eq. 8's per-radius correlation, averaged)  */
+#define FMBYM_LOGIT_ZSCORE 4u   /* both softmaxes on standardised scores, (c - mean)/std
+                                   over the lags (population std): softmax((c - max c) /
+                                   (T std)); a reading of the temperature's scale          */
 #define FMBYM_XY_UNWINDOWED 8u  /* translation stage on the unwindowed scans        */
+#define FMBYM_HARD_ARGMAX 16u   /* hard argmax instead of both soft-argmaxes: theta and t'
+                                   are the lags of the first maximum (lowest heading index;
+                                   row-major (s_y, s_x) for c_xy), the search of Eq. 2-3
+                                   without the soft relaxation                              */
+/* The three readings are forward only: the adjoint, the training pair and the
+ * one-call vjp return FMBYM_EUNSUPPORTED for a plan with any of them, and so do
+ * the full-circle search with FMBYM_LOGIT_ZSCORE or FMBYM_HARD_ARGMAX, odd sides
+ * (plan creation) and fmbym_autotune with the adjoint.  Saved slots hold the
+ * statistics of the chosen reading (THETA_SUM, XY_SUM with T std as the
+ * temperature; THETA_NU 0 under FMBYM_HARD_ARGMAX). */
 #define FMBYM_CHECK_FINITE 64u  /* forward calls count each pair's non-finite input
                                    values (f, g and the masks) into
                                    saved[b][FMBYM_SAVED_STATUS]; the search itself
@@ -99,15 +116,22 @@ typedef struct {
     float temp_xy;      /* translation softmax temperature T_xy (> 0)                     */
     float band_lo;      /* band-pass: keep lo <= |k|/n <= hi (cycles per pixel) ...       */
     float band_hi;      /* ... disabled when band_hi <= 0                                  */
-    uint32_t flags;     /* FMBYM_HANN | FMBYM_XY_UNWINDOWED | FMBYM_CHECK_FINITE           */
+    uint32_t flags;     /* FMBYM_HANN | FMBYM_XY_UNWINDOWED | FMBYM_CHECK_FINITE |
+                           FMBYM_ANGLE_MARGINAL | FMBYM_LOGIT_ZSCORE | FMBYM_HARD_ARGMAX      */
 } fmbym_params;
 
 /* Launch choices of a plan: column-tile widths of the column passes (how many
- * float4 columns one block transforms: 4, 8 or 16) and the batch split.  They
- * change speed, never results: every choice runs the same arithmetic on every
- * pair and column.  A new plan starts from defaults for its n; fmbym_autotune
- * measures and sets the fastest.  Because of the split's stream and events,
- * calls on one plan must not be issued concurrently from several host threads. */
+ * float4 columns one block transforms: 4, 8 or 16), the batch split, the rows
+ * each line of the two row passes transforms in sequence, and the radix plan
+ * of the n-point column lines of stage 1 and of the |F| adjoint.  Widths, split
+ * and rows change speed, never results: every choice runs the same arithmetic
+ * on every pair, row and column.  The radix plans (radix-8 stages with 8
+ * elements per thread, or radix-4 with 4) round differently, so results move
+ * by FP32 rounding, within the parity tolerances.  A block may not exceed 1024
+ * threads: width * n / radix <= 1024.  A new plan starts from defaults for its
+ * n; fmbym_autotune measures and sets the fastest.  Because of the split's
+ * stream and events, calls on one plan must not be issued concurrently from
+ * several host threads. */
 typedef struct {
     int32_t cols1;      /* stage-1 column FFTs and |F|                      */
     int32_t cols2;      /* stage-2 column correlation                       */
@@ -117,6 +141,10 @@ typedef struct {
                            batch concurrently, the second on a stream the plan
                            owns (joined back to the caller's stream by events;
                            still capturable into a graph)                   */
+    int32_t rows1;      /* 1 or 2 rows per line in sequence, stage-1 rows    */
+    int32_t rows2;      /* 1 or 2 rows per line in sequence, stage-2 rows    */
+    int32_t radix1;     /* 8 or 4: radix plan of the stage-1 column lines    */
+    int32_t radix_mag;  /* 8 or 4: radix plan of the |F| adjoint's columns   */
 } fmbym_tuning;
 
 /* Validate `p` and build a plan (uploads constant tables to the current device;
@@ -154,15 +182,16 @@ FMBYM_API int fmbym_search_backward(fmbym_plan plan, int32_t batch, const float*
 /* ---------------------------------------------------------------- tuning
  *
  * fmbym_plan_get_tuning / fmbym_plan_set_tuning read and replace the plan's
- * launch choices (set: FMBYM_EINVAL unless every width is 4, 8 or 16 and
- * split is 1 or 2).
+ * launch choices (set: FMBYM_EINVAL unless every width is 4, 8 or 16, split
+ * and the rows are 1 or 2, the radix plans 8 or 4, and the blocks fit).
  * Not to be called while searches on the plan are in flight.
  *
  * fmbym_autotune times whole search steps on synthetic inputs it writes into
  * its workspace (fmbym_autotune_workspace_size bytes) and picks the choices one
  * at a time (split over 1, 2, then the widths over 4, 8, 16 in the order cols1,
- * cols2, cols_xy, cols_mag; with_backward = 0 times the forward alone and
- * leaves the adjoint's widths as they are).  It synchronises `stream`, creates and
+ * cols2, cols_xy, cols_mag, then rows1, rows2 over 1, 2 and radix1, radix_mag
+ * over 8, 4, each with the width it got; with_backward = 0 times the forward
+ * alone and leaves the adjoint's choices as they are).  It synchronises `stream`, creates and
  * destroys two HIP events, sets the result on the plan and writes it to *best;
  * ms_per_step (or NULL) receives the best step time.  Results of the searches
  * do not depend on the choice. */

@@ -32,6 +32,12 @@ int check_full_path(fmbym_plan plan, int32_t batch) {
     return odd_side(plan_cast(plan)->p.n) ? FMBYM_EUNSUPPORTED : FMBYM_OK;
 }
 
+int check_adjoint(fmbym_plan plan, int32_t batch) {
+    const int rc = check_full_path(plan, batch);
+    if (rc) return rc;
+    return (plan_cast(plan)->p.flags & kReadingFlags) ? FMBYM_EUNSUPPORTED : FMBYM_OK;
+}
+
 }  // namespace fmbym
 
 namespace {
@@ -46,11 +52,12 @@ int check_params(const fmbym_params* p) {
     if (!isfinite(p->band_lo) || !isfinite(p->band_hi)) return FMBYM_EINVAL;
     if (p->band_hi > 0.f && (p->band_lo < 0.f || p->band_lo > p->band_hi)) return FMBYM_EINVAL;
     if (p->n <= 0 || p->n_theta <= 0 || p->n_r <= 0) return FMBYM_EINVAL;
-    if (p->flags & ~(uint32_t)(FMBYM_HANN | FMBYM_XY_UNWINDOWED | FMBYM_CHECK_FINITE)) return FMBYM_EUNSUPPORTED;
+    if (p->flags & ~(uint32_t)(FMBYM_HANN | FMBYM_XY_UNWINDOWED | FMBYM_CHECK_FINITE | kReadingFlags))
+        return FMBYM_EUNSUPPORTED;
     if (p->n_r > 4096) return FMBYM_EUNSUPPORTED;
     if (odd_side(p->n)) {   // forward only; any number of heading bins
         if (p->n_theta < 16 || p->n_theta > 1024) return FMBYM_EUNSUPPORTED;
-        if (p->flags & FMBYM_CHECK_FINITE) return FMBYM_EUNSUPPORTED;
+        if (p->flags & (FMBYM_CHECK_FINITE | kReadingFlags)) return FMBYM_EUNSUPPORTED;
         return FMBYM_OK;
     }
     if (p->n != 128 && p->n != 256 && p->n != 512) return FMBYM_EUNSUPPORTED;
@@ -218,7 +225,7 @@ int fmbym_plan_destroy(fmbym_plan plan) {
 
 size_t fmbym_search_workspace_size(fmbym_plan plan, int32_t batch, int with_backward) {
     if (check_call(plan, batch)) return 0;
-    if (with_backward && check_full_path(plan, batch)) return 0;   // odd sides: forward only
+    if (with_backward && check_adjoint(plan, batch)) return 0;   // odd sides and the readings: forward only
     const Plan* pl = plan_cast(plan);
     const size_t fwd = run_fwd_workspace(*pl, batch);
     if (!with_backward) return fwd;
@@ -249,7 +256,7 @@ int fmbym_search_backward(fmbym_plan plan, int32_t batch, const float* f, const 
                           const float* d_pose, float* d_f, float* d_g, float* d_m_f, float* d_m_g,
                           void* workspace, size_t workspace_bytes, void* stream) {
     const TraceRange trace_range("fmbym_search_backward");
-    int rc = check_full_path(plan, batch);
+    int rc = check_adjoint(plan, batch);
     if (rc) return rc;
     if (!f || !g || !pose || !c_theta || !c_xy || !saved || !d_pose || !d_f || !d_g)
         return FMBYM_EINVAL;
@@ -273,9 +280,7 @@ int fmbym_plan_get_tuning(fmbym_plan plan, fmbym_tuning* out) {
 
 int fmbym_plan_set_tuning(fmbym_plan plan, const fmbym_tuning* t) {
     if (!plan || !t) return FMBYM_EINVAL;
-    if (!valid_tile(t->cols1) || !valid_tile(t->cols2) || !valid_tile(t->cols_xy) || !valid_tile(t->cols_mag))
-        return FMBYM_EINVAL;
-    if (t->split != 1 && t->split != 2) return FMBYM_EINVAL;
+    if (!tuning_ok(*t, plan_cast(plan)->p.n)) return FMBYM_EINVAL;
     plan_cast(plan)->tune = *t;
     return FMBYM_OK;
 }
@@ -313,6 +318,7 @@ int fmbym_search_full_circle(fmbym_plan plan, int32_t batch, const float* f, con
     const TraceRange trace_range("fmbym_search_full_circle");
     int rc = check_full_path(plan, batch);
     if (rc) return rc;
+    if (plan_cast(plan)->p.flags & (FMBYM_LOGIT_ZSCORE | FMBYM_HARD_ARGMAX)) return FMBYM_EUNSUPPORTED;
     if (!f || !g || !pose) return FMBYM_EINVAL;
     if ((m_f == nullptr) != (m_g == nullptr)) return FMBYM_EINVAL;
     const Plan* pl = plan_cast(plan);
@@ -324,7 +330,7 @@ int fmbym_search_full_circle(fmbym_plan plan, int32_t batch, const float* f, con
 }
 
 size_t fmbym_search_state_size(fmbym_plan plan, int32_t batch) {
-    if (check_full_path(plan, batch)) return 0;
+    if (check_adjoint(plan, batch)) return 0;
     return keep_bytes(plan_cast(plan)->p, batch);
 }
 
@@ -333,7 +339,7 @@ int fmbym_search_train(fmbym_plan plan, int32_t batch, const float* f, const flo
                        void* state, size_t state_bytes, void* workspace, size_t workspace_bytes,
                        void* stream) {
     const TraceRange trace_range("fmbym_search_train");
-    int rc = check_full_path(plan, batch);
+    int rc = check_adjoint(plan, batch);
     if (rc) return rc;
     if (!f || !g || !pose || !c_theta || !c_xy || !saved) return FMBYM_EINVAL;
     if ((m_f == nullptr) != (m_g == nullptr)) return FMBYM_EINVAL;
@@ -355,7 +361,7 @@ int fmbym_search_backward_state(fmbym_plan plan, int32_t batch, const float* f, 
                                 float* d_g, float* d_m_f, float* d_m_g, void* workspace,
                                 size_t workspace_bytes, void* stream) {
     const TraceRange trace_range("fmbym_search_backward_state");
-    int rc = check_full_path(plan, batch);
+    int rc = check_adjoint(plan, batch);
     if (rc) return rc;
     if (!f || !g || !pose || !c_theta || !c_xy || !saved || !d_pose || !d_f || !d_g)
         return FMBYM_EINVAL;
@@ -378,7 +384,7 @@ int fmbym_search_vjp(fmbym_plan plan, int32_t batch, const float* f, const float
                      size_t state_bytes, const float* d_pose, float* d_f, float* d_g, float* d_m_f,
                      float* d_m_g, void* workspace, size_t workspace_bytes, void* stream) {
     const TraceRange trace_range("fmbym_search_vjp");
-    int rc = check_full_path(plan, batch);
+    int rc = check_adjoint(plan, batch);
     if (rc) return rc;
     if (!f || !g || !pose || !c_theta || !c_xy || !saved || !d_pose || !d_f || !d_g) return FMBYM_EINVAL;
     if ((m_f == nullptr) != (m_g == nullptr)) return FMBYM_EINVAL;

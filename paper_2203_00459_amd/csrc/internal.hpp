@@ -62,6 +62,8 @@ struct Plan {
 // 128-byte lines in stage 1; the 3n/2-point columns run 4 wide at 512).
 fmbym_tuning default_tuning(int n);
 bool valid_tile(int c);
+// Every field in its range and every block within 1024 threads at side n.
+bool tuning_ok(const fmbym_tuning& t, int n);
 
 constexpr int kDmagTile = 16;     // bins per side of one tile of the CSR row order
 constexpr int kDmagRows = 256;    // at most this many CSR rows per adjoint block
@@ -76,6 +78,10 @@ inline Plan* plan_cast(fmbym_plan p) { return reinterpret_cast<Plan*>(p); }
 int check_call(fmbym_plan plan, int32_t batch);
 // check_call, and FMBYM_EUNSUPPORTED for plans whose path is forward only (odd sides).
 int check_full_path(fmbym_plan plan, int32_t batch);
+// The alternative readings of the scores (forward only).
+constexpr uint32_t kReadingFlags = FMBYM_ANGLE_MARGINAL | FMBYM_LOGIT_ZSCORE | FMBYM_HARD_ARGMAX;
+// check_full_path, and FMBYM_EUNSUPPORTED for plans with a reading flag (no adjoint).
+int check_adjoint(fmbym_plan plan, int32_t batch);
 
 // Record e as this thread's last HIP error (fmbym_last_hip_error); returns FMBYM_EHIP.
 int hip_fail(hipError_t e);
@@ -108,10 +114,6 @@ __host__ __device__ constexpr int pitch_lag(int n) { return 3 * n / 4 + kPitchPa
 // Lines per 256-thread block of a stage-2 row kernel, and the softmax
 // partials per pair of the inverse-row kernel (one per block of lag-row pairs).
 __host__ __device__ constexpr int rows2_lines(int n) { return 256 / (pad2(n) / kE2); }
-// Rows each line of k_rows2 transforms in sequence (the next one's loads overlap the current transform).
-constexpr int kRows2Seq = 2;
-// The same for k_rows1 (rows of n points).
-constexpr int kRows1Seq = 2;
 inline int xy_partials_per_pair(int n) { return (n / 2) / rows2_lines(n); }
 
 // ------------------------------------------------------------ odd sides

@@ -487,11 +487,11 @@ __device__ __forceinline__ float2 mag_adjoint(float2 F, float dA) {
 // stage-1 row spectra: column DFTs again, dF = dA F / |F| (dA already
 // carries the band gain), unnormalised inverse column DFT.  For columns 0 and
 // n/2 the row pass uses only the real part of the result.
-template <int N, int C>
-__global__ __launch_bounds__(C * N / kEb) void kb_cols_mag(const float4* r1, float4* out,
+template <int N, int C, int E>
+__global__ __launch_bounds__(C * N / E) void kb_cols_mag(const float4* r1, float4* out,
                                                            const float2* __restrict__ dA,
                                                            const float2* __restrict__ tw, int batch) {
-    constexpr int L = N, T = L / kEb, H = N / 2, TILES = H / C + 1, P1 = pitch_rows1(N), PA = pitch_mag(N);
+    constexpr int L = N, T = L / E, H = N / 2, TILES = H / C + 1, P1 = pitch_rows1(N), PA = pitch_mag(N);
     __shared__ float lre[C][LdsCols<C>::words(L)];
     __shared__ float lim[C][LdsCols<C>::words(L)];
     const int c = threadIdx.x % C, t = threadIdx.x / C;
@@ -503,28 +503,28 @@ __global__ __launch_bounds__(C * N / kEb) void kb_cols_mag(const float4* r1, flo
     const float4* src = r1 + (size_t)b * N * P1;   // may equal out: a block reads its columns first
     float4* dst = out + (size_t)b * N * P1;
     const float2* da = dA + (size_t)b * N * PA;
-    float2 vf[kEb], vg[kEb], d[kEb];
+    float2 vf[E], vg[E], d[E];
     const int cl = col <= H ? col : H;   // padding lanes of the last tile read a valid column, then use 0
 #pragma unroll
-    for (int m = 0; m < kEb; ++m) {
+    for (int m = 0; m < E; ++m) {
         const float4 q = src[(size_t)(t + m * T) * P1 + col];
         vf[m] = make_float2(q.x, q.y);
         vg[m] = make_float2(q.z, q.w);
         d[m] = da[(t + m * T) * PA + cl];   // dA too before the transforms, whose barriers loads cannot cross
     }
-    fft_line<L, kEb, LdsCols<C>>(vf, lre[c], lim[c], fresh_index(t), tw);
-    fft_line<L, kEb, LdsCols<C>>(vg, lre[c], lim[c], fresh_index(t), tw);
+    fft_line<L, E, LdsCols<C>>(vf, lre[c], lim[c], fresh_index(t), tw);
+    fft_line<L, E, LdsCols<C>>(vg, lre[c], lim[c], fresh_index(t), tw);
 #pragma unroll
-    for (int m = 0; m < kEb; ++m) {
+    for (int m = 0; m < E; ++m) {
         const float2 dm = col <= H ? d[m] : make_float2(0.f, 0.f);
         vf[m] = mag_adjoint(vf[m], dm.x);
         vg[m] = mag_adjoint(vg[m], dm.y);
     }
-    ifft_line<L, kEb, LdsCols<C>>(vf, lre[c], lim[c], fresh_index(t), tw);
-    ifft_line<L, kEb, LdsCols<C>>(vg, lre[c], lim[c], fresh_index(t), tw);
+    ifft_line<L, E, LdsCols<C>>(vf, lre[c], lim[c], fresh_index(t), tw);
+    ifft_line<L, E, LdsCols<C>>(vg, lre[c], lim[c], fresh_index(t), tw);
     if (col > H) return;
 #pragma unroll
-    for (int m = 0; m < kEb; ++m)
+    for (int m = 0; m < E; ++m)
         dst[(size_t)(t + m * T) * P1 + col] = make_float4(vf[m].x, vf[m].y, vg[m].x, vg[m].y);
 }
 
@@ -765,12 +765,21 @@ static void launch_cols_xy(const Plan& pl, int B, const float4* rows2, float4* r
     }
 }
 
+template <int N, int C, int E>
+static void launch_cols_mag_ce(const Plan& pl, int B, const float4* r1, float4* out, const float2* dA,
+                               hipStream_t s) {
+    const int tiles_mag = B * ((N / 2) / C + 1);
+    if constexpr (C * N / E <= 1024)
+        FMBYM_LAUNCH(kKBColsMag, (kb_cols_mag<N, C, E>), dim3(((tiles_mag + 7) / 8) * 8), dim3(C * N / E), s, r1,
+                     out, dA, pl.twiddle, B);
+}
+
+// The radix plan of these column lines (elements per thread, 8 or 4) is the plan's tuning.
 template <int N, int C>
 static void launch_cols_mag_c(const Plan& pl, int B, const float4* r1, float4* out, const float2* dA,
                               hipStream_t s) {
-    const int tiles_mag = B * ((N / 2) / C + 1);
-    FMBYM_LAUNCH(kKBColsMag, (kb_cols_mag<N, C>), dim3(((tiles_mag + 7) / 8) * 8), dim3(C * N / kEb), s, r1,
-                 out, dA, pl.twiddle, B);
+    if (pl.tune.radix_mag == 4) launch_cols_mag_ce<N, C, 4>(pl, B, r1, out, dA, s);
+    else launch_cols_mag_ce<N, C, 8>(pl, B, r1, out, dA, s);
 }
 
 template <int N>

@@ -33,7 +33,7 @@ constexpr int kE = 8;   // elements per thread in every FFT line
 
 // ------------------------------------------------------------------ stage 1
 
-template <int N>
+template <int N, int SEQ>
 __global__ __launch_bounds__(256) void k_rows1(const float* __restrict__ f, const float* __restrict__ g,
                                                const float* __restrict__ mf, const float* __restrict__ mg,
                                                const float* __restrict__ hann,
@@ -63,15 +63,15 @@ __global__ __launch_bounds__(256) void k_rows1(const float* __restrict__ f, cons
             v[m] = make_float2((mfo ? a * ma : a) * w, (mgo ? c * mc : c) * w);
         }
     };
-    // kRows1Seq rows per line in sequence: the next row's loads overlap the current transform
-    const int grow0 = (blockIdx.x * kRows1Seq) * LPB + line;
+    // SEQ rows per line in sequence: the next row's loads overlap the current transform
+    const int grow0 = (blockIdx.x * SEQ) * LPB + line;
     float2 v[kE];
     load(grow0, v);
 #pragma unroll
-    for (int it = 0; it < kRows1Seq; ++it) {
+    for (int it = 0; it < SEQ; ++it) {
         const int grow = grow0 + it * LPB;
         float2 nx[kE];
-        if (it + 1 < kRows1Seq) load(grow + LPB, nx);
+        if (it + 1 < SEQ) load(grow + LPB, nx);
         fft_line<L, kE>(v, lre[line], lim[line], fresh_index(t), tw);
         float2 mir[kE];
         mirror_line<L, kE>(v, mir, lre[line], lim[line], fresh_index(t));
@@ -84,7 +84,7 @@ __global__ __launch_bounds__(256) void k_rows1(const float* __restrict__ f, cons
                 o[k] = make_float4(X.x, X.y, Y.x, Y.y);
             }
         }
-        if (it + 1 < kRows1Seq) {
+        if (it + 1 < SEQ) {
 #pragma unroll
             for (int m = 0; m < kE; ++m) v[m] = nx[m];
         }
@@ -99,13 +99,14 @@ __device__ __forceinline__ float band_gain(int ky_signed, int kx, int on, int lo
 
 // Column DFTs of both stage-1 spectra and their band-passed magnitudes,
 // written interleaved.  Tiles of C columns cover 0 .. n/2; the last tile has
-// one live column.
-template <int N, int C>
-__global__ __launch_bounds__(C * N / kE) void k_cols1(const float4* __restrict__ in,
+// one live column.  E elements per thread set the radix plan (radix-8 stages
+// for E = 8, radix-4 for E = 4; a tuning choice).
+template <int N, int C, int E>
+__global__ __launch_bounds__(C * N / E) void k_cols1(const float4* __restrict__ in,
                                                       float2* __restrict__ A,
                                                       const float2* __restrict__ tw, int band_on,
                                                       int lo2, int hi2, int batch) {
-    constexpr int L = N, T = L / kE, H = N / 2, P1 = pitch_rows1(N), PA = pitch_mag(N);
+    constexpr int L = N, T = L / E, H = N / 2, P1 = pitch_rows1(N), PA = pitch_mag(N);
     constexpr int TILES = H / C + 1;
     __shared__ float lre[C][LdsCols<C>::words(L)];
     __shared__ float lim[C][LdsCols<C>::words(L)];
@@ -116,19 +117,19 @@ __global__ __launch_bounds__(C * N / kE) void k_cols1(const float4* __restrict__
     const int tile = work % TILES, b = work / TILES;
     const int col = tile * C + c;
     const float4* src = in + (size_t)b * N * P1;
-    float2 vf[kE], vg[kE];
+    float2 vf[E], vg[E];
 #pragma unroll
-    for (int m = 0; m < kE; ++m) {
+    for (int m = 0; m < E; ++m) {
         const float4 q = src[(size_t)(t + m * T) * P1 + col];
         vf[m] = make_float2(q.x, q.y);
         vg[m] = make_float2(q.z, q.w);
     }
-    fft_line<L, kE, LdsCols<C>>(vf, lre[c], lim[c], fresh_index(t), tw);
-    fft_line<L, kE, LdsCols<C>>(vg, lre[c], lim[c], fresh_index(t), tw);
+    fft_line<L, E, LdsCols<C>>(vf, lre[c], lim[c], fresh_index(t), tw);
+    fft_line<L, E, LdsCols<C>>(vg, lre[c], lim[c], fresh_index(t), tw);
     if (col > H) return;   // padding lane of the last tile (no barriers follow)
     float2* dst = A + (size_t)b * N * PA;
 #pragma unroll
-    for (int m = 0; m < kE; ++m) {
+    for (int m = 0; m < E; ++m) {
         const int ky = t + m * T;
         const float gain = band_gain(ky < H ? ky : ky - N, col, band_on, lo2, hi2);
         dst[ky * PA + col] = make_float2(sqrtf(vf[m].x * vf[m].x + vf[m].y * vf[m].y) * gain,
@@ -139,7 +140,10 @@ __global__ __launch_bounds__(C * N / kE) void k_cols1(const float4* __restrict__
 // One block per (pair, block of radii_per_block(NT) radii); grid is remapped so
 // that all blocks of one pair run on the same XCD (its L2 keeps the pair's
 // magnitude spectra).
-template <int NT, int N>
+// MARG (the marginal reading of Alg. 1's "Mean over r"): the block writes the
+// sums over its radii of the angular spectra of both profiles (P_f, then P_g,
+// HK bins each) instead of the sum of their products.
+template <int NT, int N, bool MARG>
 __global__ __launch_bounds__(256) void k_polar(const float2* __restrict__ A,
                                                const float2* __restrict__ tw,
                                                float2* __restrict__ part, int n_r, int batch,
@@ -157,9 +161,9 @@ __global__ __launch_bounds__(256) void k_polar(const float2* __restrict__ A,
     const int b = work / nrb, rb = work % nrb;
     const int line = threadIdx.x / T, t = threadIdx.x % T;
     const float2* Ab = A + (size_t)b * N * pitch_mag(N);
-    float2 acc[kE / 2 + 1];
+    float2 acc[kE / 2 + 1], accg[kE / 2 + 1];
 #pragma unroll
-    for (int m = 0; m <= kE / 2; ++m) acc[m] = make_float2(0.f, 0.f);
+    for (int m = 0; m <= kE / 2; ++m) acc[m] = accg[m] = make_float2(0.f, 0.f);
     for (int pass = 0; pass < PASSES; ++pass) {
         const int slot = pass * LPB + line;
         const int rad = rb * RPB + slot;
@@ -187,25 +191,35 @@ __global__ __launch_bounds__(256) void k_polar(const float2* __restrict__ A,
         for (int m = 0; m <= kE / 2; ++m) {
             const float2 Xf = split_x(v[m], mir[m]);
             const float2 Xg = split_y(v[m], mir[m]);
-            acc[m] = cadd(acc[m], cmulcj(Xf, Xg));
+            if constexpr (MARG) {
+                acc[m] = cadd(acc[m], Xf);
+                accg[m] = cadd(accg[m], Xg);
+            } else {
+                acc[m] = cadd(acc[m], cmulcj(Xf, Xg));
+            }
         }
     }
-    // fixed-order sum over the lines of the block, through LDS
+    // fixed-order sum over the lines of the block, through LDS (2 HK <= the words of a line)
+    constexpr int NS = MARG ? 2 : 1, W = NS * HK;
     __syncthreads();
     float* sre = &lre[0][0];
     float* sim = &lim[0][0];
     for (int m = 0; m <= kE / 2; ++m) {
         const int k = t + m * T;
         if (k < HK) {
-            sre[line * HK + k] = acc[m].x;
-            sim[line * HK + k] = acc[m].y;
+            sre[line * W + k] = acc[m].x;
+            sim[line * W + k] = acc[m].y;
+            if constexpr (MARG) {
+                sre[line * W + HK + k] = accg[m].x;
+                sim[line * W + HK + k] = accg[m].y;
+            }
         }
     }
     __syncthreads();
-    float2* dst = part + ((size_t)b * nrb + rb) * HK;
-    for (int k = threadIdx.x; k < HK; k += blockDim.x) {
+    float2* dst = part + ((size_t)b * nrb + rb) * W;
+    for (int k = threadIdx.x; k < W; k += blockDim.x) {
         float2 s = make_float2(0.f, 0.f);
-        for (int l = 0; l < LPB; ++l) s = cadd(s, make_float2(sre[l * HK + k], sim[l * HK + k]));
+        for (int l = 0; l < LPB; ++l) s = cadd(s, make_float2(sre[l * W + k], sim[l * W + k]));
         dst[k] = s;
     }
 }
@@ -216,10 +230,17 @@ __global__ __launch_bounds__(256) void k_polar(const float2* __restrict__ A,
 // with nu = sum p_l (l - l*), which stays accurate when the softmax is sharp.
 constexpr int kAngleGroups = 4;   // thread groups that share the radius-block sum
 
-template <int NT>
+// MARG: the partials hold the radius sums of both angular spectra; groups 0, 1
+// add those of P_f over alternate radius blocks, groups 2, 3 those of P_g, and
+// the score spectrum is conj(S_f) S_g.  mode bit kScoreZ standardises the
+// scores (softmax of (c - max c) / (T sigma), sigma their standard deviation
+// over the lags), bit kScoreHard takes theta = l* dtheta (the first maximum).
+constexpr int kScoreZ = 1, kScoreHard = 2;
+
+template <int NT, bool MARG>
 __global__ __launch_bounds__(kAngleGroups * NT / kE) void k_angle_fin(
     const float2* __restrict__ part, int n_r, const float2* __restrict__ tw, float temp,
-    float* __restrict__ c_theta, float* __restrict__ pose, float* __restrict__ saved) {
+    float* __restrict__ c_theta, float* __restrict__ pose, float* __restrict__ saved, int mode) {
     constexpr int L = NT, T = L / kE, HK = NT / 2 + 1;
     __shared__ float lre[kAngleGroups][LdsRows<L>::words(L)];   // one line per group: the groups
     __shared__ float lim[kAngleGroups][LdsRows<L>::words(L)];   // repeat the transform, race-free
@@ -228,13 +249,16 @@ __global__ __launch_bounds__(kAngleGroups * NT / kE) void k_angle_fin(
     __shared__ int redi[T];
     const int b = blockIdx.x;
     const int nrb = (n_r + radii_per_block(NT) - 1) / radii_per_block(NT);
-    const float2* src = part + (size_t)b * nrb * HK;
+    constexpr int W = MARG ? 2 * HK : HK;   // floats2 per radius block of the partials
+    const float2* src = part + (size_t)b * nrb * W;
     {   // group q sums radius blocks q, q + G, ... ; the groups are then added in order
+        // (MARG: groups 0, 1 over alternate blocks of S_f, groups 2, 3 of S_g)
         const int q = threadIdx.x / T, tt = threadIdx.x % T;
+        const int r0 = MARG ? (q & 1) : q, rs = MARG ? 2 : kAngleGroups, off = MARG ? (q >> 1) * HK : 0;
         for (int k = tt; k < HK; k += T) {
             float2 s = make_float2(0.f, 0.f);
 #pragma unroll 8
-            for (int r = q; r < nrb; r += kAngleGroups) s = cadd(s, src[(size_t)r * HK + k]);   // loads overlap
+            for (int r = r0; r < nrb; r += rs) s = cadd(s, src[(size_t)r * W + off + k]);   // loads overlap
             psum[q][k] = s;
         }
     }
@@ -249,9 +273,14 @@ __global__ __launch_bounds__(kAngleGroups * NT / kE) void k_angle_fin(
     for (int m = 0; m < kE; ++m) {
         const int k = t + m * T;
         const int kk = k < HK ? k : NT - k;
-        float2 s = psum[0][kk];
+        float2 s;
+        if constexpr (MARG) {
+            s = cmulcj(cadd(psum[0][kk], psum[1][kk]), cadd(psum[2][kk], psum[3][kk]));
+        } else {
+            s = psum[0][kk];
 #pragma unroll
-        for (int q = 1; q < kAngleGroups; ++q) s = cadd(s, psum[q][kk]);
+            for (int q = 1; q < kAngleGroups; ++q) s = cadd(s, psum[q][kk]);
+        }
         if (k == 0) {
             dc = s.x;
             s = make_float2(0.f, 0.f);
@@ -277,7 +306,18 @@ __global__ __launch_bounds__(kAngleGroups * NT / kE) void k_angle_fin(
     int kmax;
     block_argmax(lmax, larg, red, redi, T, cmax, kmax);
     const int lag_star = kmax - NT / 2;
-    const float inv_t = 1.f / temp;
+    float sigma = 1.f;
+    if (mode & kScoreZ) {   // standard deviation of the scores over the lags (two fixed-order passes)
+        float s1 = 0.f;
+#pragma unroll
+        for (int m = 0; m < kE; ++m) s1 += c[m];
+        const float mean = block_sum(s1, red, T) / (float)NT;
+        float s2 = 0.f;
+#pragma unroll
+        for (int m = 0; m < kE; ++m) s2 += (c[m] - mean) * (c[m] - mean);
+        sigma = sqrtf(block_sum(s2, red, T) / (float)NT);
+    }
+    const float inv_t = 1.f / (temp * sigma);
     float se = 0.f, sn = 0.f;
 #pragma unroll
     for (int m = 0; m < kE; ++m) {
@@ -291,7 +331,7 @@ __global__ __launch_bounds__(kAngleGroups * NT / kE) void k_angle_fin(
     const float Z = block_sum(se, red, T);
     const float SN = block_sum(sn, red, T);
     if (threadIdx.x == 0) {
-        const float nu = SN / Z;
+        const float nu = (mode & kScoreHard) ? 0.f : SN / Z;
         const float theta = ((float)lag_star + nu) * (3.14159265358979323846f / (float)NT);
         pose[b * 3 + 0] = theta;
         float* sv = saved + (size_t)b * FMBYM_SAVED;
@@ -313,7 +353,7 @@ __global__ __launch_bounds__(kAngleGroups * NT / kE) void k_angle_fin(
 
 // ------------------------------------------------------------------ stage 2
 
-template <int N>
+template <int N, int SEQ>
 __global__ __launch_bounds__(256) void k_rows2(const float* __restrict__ f, const float* __restrict__ g,
                                                const float* __restrict__ mf, const float* __restrict__ mg,
                                                const float* __restrict__ hann,
@@ -325,7 +365,7 @@ __global__ __launch_bounds__(256) void k_rows2(const float* __restrict__ f, cons
     __shared__ float lre[LPB][LdsRows<L>::words(L)];
     __shared__ float lim[LPB][LdsRows<L>::words(L)];
     const int line = threadIdx.x / T, t = threadIdx.x % T;
-    // kRows2Seq rows per line, one after the other: the next row's loads are in
+    // SEQ rows per line, one after the other: the next row's loads are in
     // flight during the current row's transform
     auto load = [&](int grow, float2 (&v)[E]) {
         const int b = grow / N, i = grow % N;
@@ -342,14 +382,14 @@ __global__ __launch_bounds__(256) void k_rows2(const float* __restrict__ f, cons
             }
         }
     };
-    const int grow0 = (blockIdx.x * kRows2Seq) * LPB + line;
+    const int grow0 = (blockIdx.x * SEQ) * LPB + line;
     float2 v[E];
     load(grow0, v);
 #pragma unroll
-    for (int it = 0; it < kRows2Seq; ++it) {
+    for (int it = 0; it < SEQ; ++it) {
         const int grow = grow0 + it * LPB;
         float2 nx[E];
-        if (it + 1 < kRows2Seq) load(grow + LPB, nx);
+        if (it + 1 < SEQ) load(grow + LPB, nx);
         fft_line<L, E>(v, lre[line], lim[line], fresh_index(t), tw);
         float2 mir[E];
         mirror_line<L, E>(v, mir, lre[line], lim[line], fresh_index(t));
@@ -362,7 +402,7 @@ __global__ __launch_bounds__(256) void k_rows2(const float* __restrict__ f, cons
                 o[k] = make_float4(X.x, X.y, Y.x, Y.y);
             }
         }
-        if (it + 1 < kRows2Seq) {
+        if (it + 1 < SEQ) {
 #pragma unroll
             for (int m = 0; m < E; ++m) v[m] = nx[m];
         }
@@ -598,6 +638,65 @@ __global__ __launch_bounds__(64) void k_xy_fin(const float4* __restrict__ part, 
     }
 }
 
+// The translation soft-argmax of a pair from its whole surface c_xy, for the
+// readings that need the surface's own statistics first: standardised scores
+// (kScoreZ: softmax of (c - max c) / (T sigma), sigma the standard deviation
+// over the n^2 lags) and the hard argmax (kScoreHard: t' = the lag of the first
+// maximum in row-major order).  One block of 1024 threads per pair; every sum
+// runs in a fixed order (strided per thread, then a tree).
+__global__ __launch_bounds__(1024) void k_xy_stats(const float* __restrict__ c_xy, int n, float temp, float delta,
+                                                   int mode, float* __restrict__ pose, float* __restrict__ saved) {
+    __shared__ float red[1024];
+    __shared__ int redi[1024];
+    const int b = blockIdx.x, t = threadIdx.x;
+    const int nn = n * n, half = n / 2;
+    const float* c = c_xy + (size_t)b * nn;
+    float s1 = 0.f, lmax = -INFINITY;
+    int larg = 0;
+    for (int i = t; i < nn; i += 1024) {
+        const float v = c[i];
+        s1 += v;
+        if (v > lmax) {   // i increases: the first maximum of the thread keeps the lowest index
+            lmax = v;
+            larg = i;
+        }
+    }
+    float cmax;
+    int imax;
+    block_argmax(lmax, larg, red, redi, 1024, cmax, imax);
+    float sigma = 1.f;
+    if (mode & kScoreZ) {
+        const float mean = block_sum(s1, red, 1024) / (float)nn;
+        float s2 = 0.f;
+        for (int i = t; i < nn; i += 1024) s2 += (c[i] - mean) * (c[i] - mean);
+        sigma = sqrtf(block_sum(s2, red, 1024) / (float)nn);
+    }
+    const float inv_t = 1.f / (temp * sigma);
+    float z = 0.f, sx = 0.f, sy = 0.f;
+    for (int i = t; i < nn; i += 1024) {
+        const float e = expf((c[i] - cmax) * inv_t);
+        z += e;
+        sx += e * (float)(i % n - half);
+        sy += e * (float)(i / n - half);
+    }
+    const float Z = block_sum(z, red, 1024);
+    const float SX = block_sum(sx, red, 1024);
+    const float SY = block_sum(sy, red, 1024);
+    if (t == 0) {
+        float* sv = saved + (size_t)b * FMBYM_SAVED;
+        const bool hard = (mode & kScoreHard) != 0;
+        const float tpx = delta * (hard ? (float)(imax % n - half) : SX / Z);
+        const float tpy = delta * (hard ? (float)(imax / n - half) : SY / Z);
+        const float ct = sv[kSavedCos], st = sv[kSavedSin];
+        pose[b * 3 + 1] = ct * tpx - st * tpy;
+        pose[b * 3 + 2] = st * tpx + ct * tpy;
+        sv[kSavedXyMax] = cmax;
+        sv[kSavedXySum] = Z;
+        sv[kSavedTpx] = tpx;
+        sv[kSavedTpy] = tpy;
+    }
+}
+
 // ---------------------------------------------------------------- launcher
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -619,7 +718,8 @@ FwdLayout fwd_layout(const fmbym_params& p, int batch) {
     const size_t r3 = B * n * (size_t)pitch_lag(p.n) * sizeof(float2);
     off = align256(off + (mag > r3 ? mag : r3));
     L.ptheta = off;
-    off = align256(off + B * (size_t)radius_blocks(p.n_r, p.n_theta) * (p.n_theta / 2 + 1) * sizeof(float2));
+    const size_t spectra = (p.flags & FMBYM_ANGLE_MARGINAL) ? 2 : 1;   // marginal: both profiles' spectra
+    off = align256(off + B * (size_t)radius_blocks(p.n_r, p.n_theta) * (p.n_theta / 2 + 1) * spectra * sizeof(float2));
     L.pxy = off;
     off = align256(off + B * (size_t)xy_partials_per_pair(p.n) * sizeof(float4));
     L.saved = off;
@@ -667,12 +767,21 @@ Keep keep_slice(const Keep& k, const fmbym_params& p, int b0) {
 }
 
 // Column-tile widths are the plan's tuning (fmbym_tuning: 4, 8 or 16 columns
-// per block); every width gives the same arithmetic per column.
+// per block); every width gives the same arithmetic per column.  The radix
+// plan of the stage-1 columns (elements per thread, 8 or 4) is tuned too; the
+// two plans round differently.  Blocks stay within 1024 threads (tuning_ok).
+template <int N, int C, int E>
+static void launch_cols1_ce(const Plan& pl, int B, const float4* r1, float2* mag, hipStream_t s) {
+    const int tiles1 = B * ((N / 2) / C + 1);
+    if constexpr (C * N / E <= 1024)
+        FMBYM_LAUNCH(kKCols1, (k_cols1<N, C, E>), dim3(((tiles1 + 7) / 8) * 8), dim3(C * N / E), s, r1, mag,
+                     pl.twiddle, pl.band_on, pl.band_lo2, pl.band_hi2, B);
+}
+
 template <int N, int C>
 static void launch_cols1_c(const Plan& pl, int B, const float4* r1, float2* mag, hipStream_t s) {
-    const int tiles1 = B * ((N / 2) / C + 1);
-    FMBYM_LAUNCH(kKCols1, (k_cols1<N, C>), dim3(((tiles1 + 7) / 8) * 8), dim3(C * N / kE), s, r1, mag,
-                 pl.twiddle, pl.band_on, pl.band_lo2, pl.band_hi2, B);
+    if (pl.tune.radix1 == 4) launch_cols1_ce<N, C, 4>(pl, B, r1, mag, s);
+    else launch_cols1_ce<N, C, 8>(pl, B, r1, mag, s);
 }
 
 template <int N>
@@ -707,8 +816,13 @@ static void launch_stage1_rows_cols(const Plan& pl, int B, const float* f, const
                                     hipStream_t s, const float* const* tab) {
     const int win = (pl.p.flags & FMBYM_HANN) ? 1 : 0;
     constexpr int T1 = N / kE, LPB1 = 256 / T1;
-    FMBYM_LAUNCH(kKRows1, k_rows1<N>, dim3(B * N / (LPB1 * kRows1Seq)), dim3(256), s, f, g, mf, mg, pl.hann,
-                 pl.twiddle, r1, win, tab);
+    // rows per line in sequence (1 or 2): the plan's tuning, the same arithmetic per row
+    if (pl.tune.rows1 == 1)
+        FMBYM_LAUNCH(kKRows1, (k_rows1<N, 1>), dim3(B * N / LPB1), dim3(256), s, f, g, mf, mg, pl.hann,
+                     pl.twiddle, r1, win, tab);
+    else
+        FMBYM_LAUNCH(kKRows1, (k_rows1<N, 2>), dim3(B * N / (LPB1 * 2)), dim3(256), s, f, g, mf, mg, pl.hann,
+                     pl.twiddle, r1, win, tab);
     launch_cols1<N>(pl, B, r1, mag, s);
 }
 
@@ -722,16 +836,29 @@ void launch_stage1_spectra(const Plan& pl, int B, const float* f, const float* g
     }
 }
 
+// Score readings of the plan's flags for k_angle_fin / k_xy_stats.
+static int score_mode(const Plan& pl) {
+    return ((pl.p.flags & FMBYM_LOGIT_ZSCORE) ? kScoreZ : 0) | ((pl.p.flags & FMBYM_HARD_ARGMAX) ? kScoreHard : 0);
+}
+
 template <int N, int NT>
 static void launch_polar(const Plan& pl, int B, const float2* mag, float2* pth, float* c_theta,
                          float* pose, float* saved, hipStream_t s, float2* spec_out) {
     const int nrb = radius_blocks(pl.p.n_r, pl.p.n_theta);
     const int total = B * nrb;
     const int grid = ((total + 7) / 8) * 8;
-    FMBYM_LAUNCH(kKPolar, (k_polar<NT, N>), dim3(grid), dim3(256), s, mag, pl.twiddle, pth, pl.p.n_r, B,
-                 spec_out);
-    FMBYM_LAUNCH(kKAngleFin, k_angle_fin<NT>, dim3(B), dim3(kAngleGroups * NT / kE), s, pth, pl.p.n_r,
-                 pl.twiddle, pl.p.temp_theta, c_theta, pose, saved);
+    const int mode = score_mode(pl);
+    if (pl.p.flags & FMBYM_ANGLE_MARGINAL) {
+        FMBYM_LAUNCH(kKPolar, (k_polar<NT, N, true>), dim3(grid), dim3(256), s, mag, pl.twiddle, pth, pl.p.n_r, B,
+                     spec_out);
+        FMBYM_LAUNCH(kKAngleFin, (k_angle_fin<NT, true>), dim3(B), dim3(kAngleGroups * NT / kE), s, pth,
+                     pl.p.n_r, pl.twiddle, pl.p.temp_theta, c_theta, pose, saved, mode);
+    } else {
+        FMBYM_LAUNCH(kKPolar, (k_polar<NT, N, false>), dim3(grid), dim3(256), s, mag, pl.twiddle, pth, pl.p.n_r,
+                     B, spec_out);
+        FMBYM_LAUNCH(kKAngleFin, (k_angle_fin<NT, false>), dim3(B), dim3(kAngleGroups * NT / kE), s, pth,
+                     pl.p.n_r, pl.twiddle, pl.p.temp_theta, c_theta, pose, saved, mode);
+    }
 }
 
 template <int N>
@@ -739,8 +866,12 @@ static void launch_rows2_n(const Plan& pl, int B, const float* f, const float* g
                            const float* mg, const float* gr, float4* r2, int win2, hipStream_t s,
                            const float* const* tab) {
     constexpr int LPB2 = rows2_lines(N);
-    FMBYM_LAUNCH(kKRows2, k_rows2<N>, dim3(B * N / (LPB2 * kRows2Seq)), dim3(256), s, f, g, mf, mg, pl.hann,
-                 pl.twiddle3, gr, r2, win2, tab);
+    if (pl.tune.rows2 == 1)
+        FMBYM_LAUNCH(kKRows2, (k_rows2<N, 1>), dim3(B * N / LPB2), dim3(256), s, f, g, mf, mg, pl.hann,
+                     pl.twiddle3, gr, r2, win2, tab);
+    else
+        FMBYM_LAUNCH(kKRows2, (k_rows2<N, 2>), dim3(B * N / (LPB2 * 2)), dim3(256), s, f, g, mf, mg, pl.hann,
+                     pl.twiddle3, gr, r2, win2, tab);
 }
 
 // Stage 2 up to the lag rows: Rotate, the 3n/2-point rows of f_w + i g', the
@@ -825,9 +956,17 @@ static int launch_n(const Plan& pl, int B, const float* f, const float* g, const
         case 1024: launch_polar<N, 1024>(pl, B, mag, pth, c_theta, pose, sv, s, keep ? keep->pspec : nullptr); break;
         default: return FMBYM_EUNSUPPORTED;
     }
-    stage2_n<N>(pl, B, f, g, mf, mg, sv, c_xy, ws, s, tab, keep);
-    FMBYM_LAUNCH(kKXyFin, k_xy_fin, dim3(B), dim3(64), s, pxy, xy_partials_per_pair(N), pl.p.temp_xy,
-                 pl.p.delta_xy, pose, sv);
+    const int mode = score_mode(pl);
+    // the readings that need the whole surface first keep c_xy in the workspace
+    // when the caller does not want it (g' is dead by then)
+    float* cxy = (mode && !c_xy) ? (float*)(ws + lay.grot) : c_xy;
+    stage2_n<N>(pl, B, f, g, mf, mg, sv, cxy, ws, s, tab, keep);
+    if (mode)
+        FMBYM_LAUNCH(kKXyFin, k_xy_stats, dim3(B), dim3(1024), s, cxy, N, pl.p.temp_xy, pl.p.delta_xy, mode, pose,
+                     sv);
+    else
+        FMBYM_LAUNCH(kKXyFin, k_xy_fin, dim3(B), dim3(64), s, pxy, xy_partials_per_pair(N), pl.p.temp_xy,
+                     pl.p.delta_xy, pose, sv);
     if (pl.p.flags & FMBYM_CHECK_FINITE) {   // after k_angle_fin, which clears the status slot
         int* counts = (int*)(ws + lay.fin);
         FMBYM_LAUNCH(kKFinite, k_finite_part, dim3(B * kFiniteSlices), dim3(256), s, f, g, mf, mg, N, counts,

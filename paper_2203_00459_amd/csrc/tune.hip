@@ -14,10 +14,21 @@ fmbym_tuning default_tuning(int n) {
     t.cols_xy = n >= 512 ? 4 : (n >= 256 ? 8 : 16);
     t.cols_mag = n >= 512 ? 4 : 16;
     t.split = n >= 512 ? 2 : 1;
+    t.rows1 = t.rows2 = 2;
+    t.radix1 = t.radix_mag = 8;
     return t;
 }
 
 bool valid_tile(int c) { return c == 4 || c == 8 || c == 16; }
+
+bool tuning_ok(const fmbym_tuning& t, int n) {
+    if (!valid_tile(t.cols1) || !valid_tile(t.cols2) || !valid_tile(t.cols_xy) || !valid_tile(t.cols_mag))
+        return false;
+    if (t.split != 1 && t.split != 2) return false;
+    if ((t.rows1 != 1 && t.rows1 != 2) || (t.rows2 != 1 && t.rows2 != 2)) return false;
+    if ((t.radix1 != 8 && t.radix1 != 4) || (t.radix_mag != 8 && t.radix_mag != 4)) return false;
+    return t.cols1 * n / t.radix1 <= 1024 && t.cols_mag * n / t.radix_mag <= 1024;
+}
 
 namespace {
 
@@ -79,13 +90,14 @@ using namespace fmbym;
 extern "C" {
 
 size_t fmbym_autotune_workspace_size(fmbym_plan plan, int32_t batch, int with_backward) {
-    if (check_full_path(plan, batch)) return 0;   // odd sides have no tunable column tiles
+    // odd sides have no tunable column tiles; the readings have no adjoint
+    if (with_backward ? check_adjoint(plan, batch) : check_full_path(plan, batch)) return 0;
     return tune_layout(*plan_cast(plan), batch, with_backward ? 1 : 0).total;
 }
 
 int fmbym_autotune(fmbym_plan plan, int32_t batch, int with_backward, void* workspace, size_t workspace_bytes,
                    void* stream, fmbym_tuning* best, float* ms_per_step) {
-    int rc = check_full_path(plan, batch);
+    int rc = with_backward ? check_adjoint(plan, batch) : check_full_path(plan, batch);
     if (rc) return rc;
     if (!best) return FMBYM_EINVAL;
     Plan& pl = *plan_cast(plan);
@@ -138,19 +150,32 @@ int fmbym_autotune(fmbym_plan plan, int32_t batch, int with_backward, void* work
         return FMBYM_OK;
     };
     const fmbym_tuning start = pl.tune;
-    int32_t* knob[5] = {&pl.tune.split, &pl.tune.cols1, &pl.tune.cols2, &pl.tune.cols_xy, &pl.tune.cols_mag};
-    const int nknobs = bwd ? 5 : 3;
-    const int widths[3] = {4, 8, 16}, splits[2] = {1, 2};
+    // knobs in order; the adjoint's (cols_xy, cols_mag, radix_mag) only when it is timed
+    struct Knob {
+        int32_t* v;
+        const int* cand;
+        int ncand;
+        bool bwd_only;
+    };
+    const int widths[3] = {4, 8, 16}, pair12[2] = {1, 2}, radices[2] = {8, 4};
+    const Knob knobs[] = {
+        {&pl.tune.split, pair12, batch >= 2 ? 2 : 1, false}, {&pl.tune.cols1, widths, 3, false},
+        {&pl.tune.cols2, widths, 3, false},                  {&pl.tune.cols_xy, widths, 3, true},
+        {&pl.tune.cols_mag, widths, 3, true},                {&pl.tune.rows1, pair12, 2, false},
+        {&pl.tune.rows2, pair12, 2, false},                  {&pl.tune.radix1, radices, 2, false},
+        {&pl.tune.radix_mag, radices, 2, true},
+    };
     float best_ms = 0.f;
     rc = timed(&best_ms);
-    for (int k = 0; rc == FMBYM_OK && k < nknobs; ++k) {
-        int keep_w = *knob[k];
-        const int* cand = k == 0 ? splits : widths;
-        const int ncand = k == 0 ? (batch >= 2 ? 2 : 1) : 3;
-        for (int ci = 0; ci < ncand; ++ci) {
-            const int c = cand[ci];
+    for (const Knob& k : knobs) {
+        if (rc != FMBYM_OK) break;
+        if (k.bwd_only && !bwd) continue;
+        int keep_w = *k.v;
+        for (int ci = 0; ci < k.ncand; ++ci) {
+            const int c = k.cand[ci];
             if (c == keep_w) continue;
-            *knob[k] = c;
+            *k.v = c;
+            if (!tuning_ok(pl.tune, pl.p.n)) continue;   // a block beyond 1024 threads
             float ms = 0.f;
             rc = timed(&ms);
             if (rc) break;
@@ -159,7 +184,7 @@ int fmbym_autotune(fmbym_plan plan, int32_t batch, int with_backward, void* work
                 keep_w = c;
             }
         }
-        *knob[k] = keep_w;
+        *k.v = keep_w;
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);

@@ -22,7 +22,10 @@ FMBYM_EUNSUPPORTED = -2
 FMBYM_EWORKSPACE = -3
 FMBYM_EHIP = -4
 FMBYM_HANN = 1
+FMBYM_ANGLE_MARGINAL = 2
+FMBYM_LOGIT_ZSCORE = 4
 FMBYM_XY_UNWINDOWED = 8
+FMBYM_HARD_ARGMAX = 16
 FMBYM_CHECK_FINITE = 64
 FMBYM_SAVED = 16
 FMBYM_SAVED_THETA = 0
@@ -77,7 +80,8 @@ class fmbym_pair(ctypes.Structure):
 
 class fmbym_tuning(ctypes.Structure):
     _fields_ = [("cols1", ctypes.c_int32), ("cols2", ctypes.c_int32), ("cols_xy", ctypes.c_int32),
-                ("cols_mag", ctypes.c_int32), ("split", ctypes.c_int32)]
+                ("cols_mag", ctypes.c_int32), ("split", ctypes.c_int32), ("rows1", ctypes.c_int32),
+                ("rows2", ctypes.c_int32), ("radix1", ctypes.c_int32), ("radix_mag", ctypes.c_int32)]
 
 
 class fmbym_mask_desc(ctypes.Structure):
@@ -246,7 +250,7 @@ def search_backward(plan, batch, f, g, m_f, m_g, pose, c_theta, c_xy, saved, d_p
         raise FmbymError(rc, "fmbym_search_backward")
 
 
-TUNING_FIELDS = ("cols1", "cols2", "cols_xy", "cols_mag", "split")
+TUNING_FIELDS = ("cols1", "cols2", "cols_xy", "cols_mag", "split", "rows1", "rows2", "radix1", "radix_mag")
 
 
 def plan_get_tuning(plan) -> dict:
@@ -258,7 +262,9 @@ def plan_get_tuning(plan) -> dict:
 
 
 def plan_set_tuning(plan, tuning: dict) -> None:
-    t = fmbym_tuning(*[int(tuning[k]) for k in TUNING_FIELDS])
+    """Replace the plan's launch choices; fields missing from `tuning` keep their value."""
+    cur = plan_get_tuning(plan)
+    t = fmbym_tuning(*[int(tuning.get(k, cur[k])) for k in TUNING_FIELDS])
     rc = lib().fmbym_plan_set_tuning(plan, ctypes.byref(t))
     if rc:
         raise FmbymError(rc, "fmbym_plan_set_tuning")
@@ -432,9 +438,11 @@ class Search:
     def __init__(self, n: int, n_theta: int, n_r: int | None = None, delta_xy: float = 1.0,
                  temp_theta: float = 1.0, temp_xy: float = 1.0, band_lo: float = 0.0,
                  band_hi: float = 0.0, hann: bool = True, xy_unwindowed: bool = False,
-                 check_finite: bool = False, max_batch: int = 64):
+                 check_finite: bool = False, max_batch: int = 64, angle_marginal: bool = False,
+                 zscore: bool = False, hard_argmax: bool = False):
         flags = ((FMBYM_HANN if hann else 0) | (FMBYM_XY_UNWINDOWED if xy_unwindowed else 0)
-                 | (FMBYM_CHECK_FINITE if check_finite else 0))
+                 | (FMBYM_CHECK_FINITE if check_finite else 0) | (FMBYM_ANGLE_MARGINAL if angle_marginal else 0)
+                 | (FMBYM_LOGIT_ZSCORE if zscore else 0) | (FMBYM_HARD_ARGMAX if hard_argmax else 0))
         self.params = fmbym_params(n, n_theta, n if n_r is None else n_r, delta_xy, temp_theta,
                                    temp_xy, band_lo, band_hi, flags)
         self.n, self.n_theta, self.max_batch = n, n_theta, max_batch

@@ -1,10 +1,12 @@
-"""Autotuning of the search's column-tile widths, with a JSON cache.
+"""Autotuning of the search's launch choices, with a JSON cache.
 
 The library's fmbym_autotune times whole search steps for each column pass at
-4, 8 and 16 columns per block and keeps the fastest (the widths never change
-a result).  This module keys the outcome by (GPU architecture, n, n_theta,
-n_r, batch, pass) and stores it in a JSON file, so a later process sets the
-widths without measuring again.
+4, 8 and 16 columns per block, the batch split, the rows per line of the row
+passes and the radix plan of the n-point column lines, and keeps the fastest
+(only the radix plans change results, by FP32 rounding).  This module keys
+the outcome by (GPU architecture, n, n_theta, n_r, batch, pass) and stores it
+in a JSON file, so a later process sets the choices without measuring again;
+an entry without every current field is measured again.
 """
 from __future__ import annotations
 
@@ -42,7 +44,7 @@ def autotune(search: "fmbym.Search", batch: int, with_backward: bool = True, cac
     path = cache_path or default_cache_path()
     key = cache_key(search, batch, with_backward)
     cache = _load(path)
-    if not refresh and key in cache:
+    if not refresh and key in cache and set(fmbym.TUNING_FIELDS) <= set(cache[key].get("tuning", {})):
         fmbym.plan_set_tuning(search.plan, cache[key]["tuning"])
         return dict(cache[key], from_cache=True)
     tuning, ms = fmbym.plan_autotune(search.plan, batch, with_backward, torch.device("cuda"))
