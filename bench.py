@@ -224,6 +224,8 @@ def main() -> int:
         return ragged_bench(args)
     if args.workload in workloads.TRAIN:
         return train_bench(args)
+    if args.workload in workloads.TRAIN_RUN:
+        return train_run_bench(args)
     if args.workload in workloads.DRIVE:
         return drive_bench(args)
     return search_bench(args)
@@ -298,24 +300,7 @@ def train_bench(args) -> int:
     ev1.record()
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / args.steps
-    psteps = min(args.steps, PROFILE_STEPS)
-    fmbym.profile_enable(psteps * 600)
-    for i in range(psteps):
-        step(i)
-    torch.cuda.synchronize()
-    prof = fmbym.profile_read()
-    fmbym.profile_enable(0)
-    per_step = {k: t / psteps for k, (t, c) in prof.items()}
-    dom = max(per_step, key=per_step.get)
-    mk = mask_kernel_model(2 * B // C, n, levels, 8, C)   # samples per network call
-    sb = kernel_bytes(n, kw["n_theta"], n, B, masked=True, keep=True)
-    if dom in mk:
-        byts, flops = mk[dom]
-    else:
-        byts, flops = sb.get(dom, 0), 0.0
-    t_dom = per_step[dom] * 1e-3
-    achieved = byts / t_dom / 1e9
-    conv_t = per_step.get("m_conv_fwd", 0.0) * 1e-3
+    rf = train_roofline(step, min(args.steps, PROFILE_STEPS), B, n, kw, levels, C)
     res = {
         "metric": f"scan-pairs/sec, {n}^2 masked-search training step (mask net fwd+bwd, search fwd+bwd, Adam), 1 GPU",
         "value": B / (ms * 1e-3),
@@ -326,12 +311,7 @@ def train_bench(args) -> int:
         "config": {"workload": args.workload, "batch": B, "n": n, "levels": levels, "channels": C,
                    "mask_params": int(tr.net.params.numel()), "loss": "l1" if loss == fmbym.FMBYM_LOSS_L1 else "l2",
                    "images_per_step": 2 * B},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
-        "conv_fwd_mfma": None if not conv_t else {
-            "achieved": mk["m_conv_fwd"][1] / conv_t / 1e12, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": mk["m_conv_fwd"][1] / conv_t / 1e12 / BF16_PEAK_TFLOPS},
-        "kernels_ms_per_step": {k: round(v, 5) for k, v in sorted(per_step.items())},
+        **rf,
     }
     if not args.no_cpu_baseline:
         from oracle import fmbym_oracle as O
@@ -353,6 +333,146 @@ def train_bench(args) -> int:
                                "sample": f"{done} pairs (about {CPU_SECONDS:.0f} s): FP64 oracle mask network + "
                                          f"masked search + {'L1' if loss == fmbym.FMBYM_LOSS_L1 else 'L2'} loss, "
                                          "autograd"}
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+def train_roofline(step, psteps: int, B: int, n: int, kw: dict, levels: int, C: int) -> dict:
+    """Per-kernel event times over `psteps` training steps (step(i) runs step i):
+    the dominant kernel against HBM on the network's byte model (or the search's),
+    the forward convolutions against the BF16 matrix-core peak, and every kernel's
+    time per step."""
+    import torch
+
+    from paper_2203_00459_amd import fmbym
+
+    fmbym.profile_enable(psteps * 600)
+    for i in range(psteps):
+        step(i)
+    torch.cuda.synchronize()
+    prof = fmbym.profile_read()
+    fmbym.profile_enable(0)
+    per_step = {k: t / psteps for k, (t, c) in prof.items()}
+    dom = max(per_step, key=per_step.get)
+    mk = mask_kernel_model(2 * B // C, n, levels, 8, C)   # samples per network call
+    sb = kernel_bytes(n, kw["n_theta"], n, B, masked=True, keep=True)
+    byts = mk[dom][0] if dom in mk else sb.get(dom, 0)
+    achieved = byts / (per_step[dom] * 1e-3) / 1e9
+    conv_t = per_step.get("m_conv_fwd", 0.0) * 1e-3
+    return {
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "conv_fwd_mfma": None if not conv_t else {
+            "achieved": mk["m_conv_fwd"][1] / conv_t / 1e12, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": mk["m_conv_fwd"][1] / conv_t / 1e12 / BF16_PEAK_TFLOPS},
+        "kernels_ms_per_step": {k: round(v, 5) for k, v in sorted(per_step.items())},
+    }
+
+
+def held_out_errors(tr, F, G, P) -> dict:
+    """Errors of the masked search (network in inference mode) and of the
+    unmasked search on held-out pairs: mean heading error (deg), mean and median
+    translation error (m), and the fraction of pairs off by more than 20 degrees
+    or 2 m."""
+    import torch
+
+    with torch.no_grad():
+        m_f, m_g = tr.masks(F, G, training=False)
+        pm = tr.search.forward(F, G, m_f, m_g, surfaces=False)["pose"]
+        pu = tr.search.forward(F, G, surfaces=False)["pose"]
+
+    def err(pose):
+        d = (pose - P).double()
+        th = d[:, 0].abs() * (180.0 / math.pi)
+        t = d[:, 1:].norm(dim=1)
+        return {"theta_deg": float(th.mean()), "t_m": float(t.mean()), "t_m_median": float(t.median()),
+                "off_20deg_or_2m": float(((th > 20.0) | (t > 2.0)).double().mean())}
+
+    return {"masked": err(pm), "unmasked": err(pu)}
+
+
+def train_run_bench(args) -> int:
+    """The configured mask-learning run: a generated training set trained for
+    whole epochs (batch B, Adam), once per loss from the same initialisation and
+    data order, each judged on held-out pairs against the unmasked search.  The
+    headline rate is the first loss's training steps after `warmup` untimed
+    ones (held-out evaluations between epochs are outside the timed segments)."""
+    import numpy as np
+    import torch
+
+    from paper_2203_00459_amd import synth, workloads
+
+    cfg = workloads.TRAIN_RUN[args.workload]
+    B, n_pairs, n_test = cfg["batch"], cfg["pairs"], cfg["held_out"]
+    t0 = time.perf_counter()
+    f, g, p = synth.make_batch_parallel(cfg["scenes"], n_pairs, split="train")
+    ft, gt, pt = synth.make_batch(cfg["scenes"], n_test, split="test")
+    print(f"generated {n_pairs} training and {n_test} held-out pairs in {time.perf_counter() - t0:.0f} s",
+          file=sys.stderr, flush=True)
+
+    from paper_2203_00459_amd import fmbym
+    from paper_2203_00459_amd.train import MaskedSearchTrainer, TrainConfig
+
+    dev = torch.device("cuda:0")
+    F, G, P = (torch.from_numpy(a).to(dev) for a in (f, g, p.astype(np.float32)))
+    Ft, Gt, Pt = (torch.from_numpy(a).to(dev) for a in (ft, gt, pt.astype(np.float32)))
+    del f, g
+    kw = workloads.search_kwargs(cfg["search"])
+    per_epoch = n_pairs // B
+    losses_out, headline = {}, None
+    for li, loss_name in enumerate(cfg["losses"]):
+        loss = fmbym.FMBYM_LOSS_L1 if loss_name == "l1" else fmbym.FMBYM_LOSS_L2
+        tr = MaskedSearchTrainer(kw, batch=n_test, cfg=TrainConfig(levels=cfg["levels"], lr=cfg["lr"], loss=loss))
+        rng = np.random.Generator(np.random.PCG64(0))
+        rec = {"before": held_out_errors(tr, Ft, Gt, Pt)}
+        step_losses, timed_ms, timed_steps = [], 0.0, 0
+        warm = min(args.warmup, per_epoch) if li == 0 else 0
+        for epoch in range(cfg["epochs"]):
+            perm = torch.from_numpy(rng.permutation(n_pairs)).to(dev)
+            first = warm if epoch == 0 else 0
+            for i in range(first):
+                idx = perm[i * B:(i + 1) * B]
+                step_losses.append(tr.step(F[idx].contiguous(), G[idx].contiguous(), P[idx].contiguous())[0])
+            torch.cuda.synchronize()
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record()
+            for i in range(first, per_epoch):
+                idx = perm[i * B:(i + 1) * B]
+                step_losses.append(tr.step(F[idx].contiguous(), G[idx].contiguous(), P[idx].contiguous())[0])
+            ev1.record()
+            torch.cuda.synchronize()
+            timed_ms += ev0.elapsed_time(ev1)
+            timed_steps += per_epoch - first
+            rec[f"epoch{epoch + 1}"] = held_out_errors(tr, Ft, Gt, Pt)
+            print(f"{loss_name} epoch {epoch + 1}: {rec[f'epoch{epoch + 1}']}", file=sys.stderr, flush=True)
+        sl = torch.stack(step_losses).double().cpu().numpy().reshape(-1)
+        rec["loss_first50"], rec["loss_last50"] = float(sl[:50].mean()), float(sl[-50:].mean())
+        rec["ms_per_step"] = timed_ms / timed_steps
+        rec["use_mask"] = bool(tr.evaluate(Ft, Gt, Pt)["use_mask"])
+        losses_out[loss_name] = rec
+        if li == 0:
+            headline = (timed_ms, timed_steps, tr)
+
+    timed_ms, timed_steps, tr = headline
+    ms = timed_ms / timed_steps
+    bi = [(F[k * B:(k + 1) * B].contiguous(), G[k * B:(k + 1) * B].contiguous(),
+           P[k * B:(k + 1) * B].contiguous()) for k in range(4)]
+    rf = train_roofline(lambda i: tr.step(*bi[i % 4]), PROFILE_STEPS, B, kw["n"], kw, cfg["levels"], 1)
+    res = {
+        "metric": f"scan-pairs/sec, {kw['n']}^2 masked-search training ({n_pairs} pairs, batch {B}, "
+                  f"{cfg['losses'][0].upper()} pose loss), 1 GPU",
+        "value": B / (ms * 1e-3),
+        "unit": "pairs/s",
+        "n_gpus": 1, "steps": timed_steps, "warmup": min(args.warmup, per_epoch), "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 conv (fp32 accumulate), f32 search", "data": "synthetic",
+        "config": {"workload": args.workload, "pairs": n_pairs, "held_out": n_test, "batch": B,
+                   "epochs": cfg["epochs"], "lr": cfg["lr"], "levels": cfg["levels"], "losses": list(cfg["losses"]),
+                   "order": "PCG64(0) permutation per epoch, the same for every loss"},
+        "gain": losses_out,
+        **rf,
+        "cpu_baseline": None,
+    }
     print(json.dumps(res), flush=True)
     return 0
 

@@ -185,8 +185,12 @@ def _distractors(spec: SceneSpec, world: _World, rng: np.random.Generator, img: 
 
 
 def make_pair(spec: SceneSpec, workload_id: int, split: str, index: int,
-              theta: float | None = None, t: tuple[float, float] | None = None):
-    """Return (f, g, pose) with f, g float32 [n, n] and pose float64 (theta rad, tx m, ty m)."""
+              theta: float | None = None, t: tuple[float, float] | None = None,
+              blob_scale: float = 1.0):
+    """Return (f, g, pose) with f, g float32 [n, n] and pose float64 (theta rad, tx m, ty m).
+
+    ``blob_scale`` scales the clutter blobs' amplitude (0 removes them) without
+    changing any random draw, so the rest of the pair is the same scene."""
     rng = _rng(workload_id, split, index)
     world = _draw_world(spec, rng)
     th = rng.uniform(-1, 1) * math.radians(spec.theta_max_deg)
@@ -202,7 +206,7 @@ def make_pair(spec: SceneSpec, workload_id: int, split: str, index: int,
             r = radius * math.sqrt(rng.uniform())
             a = rng.uniform(0, 2 * math.pi)
             blobs.append((np.array([r * math.cos(a), r * math.sin(a)]), rng.uniform(1.0, 3.0),
-                          rng.uniform(0.5, 1.0), None))
+                          blob_scale * rng.uniform(0.5, 1.0), None))
     fall = _falloff(spec)
     scans = []
     for rot, tr in ((np.eye(2), np.zeros(2)), (_rot(th), tt)):
@@ -233,6 +237,31 @@ def make_batch(name: str, batch: int, split: str = "test", start: int = 0,
         gs.append(g)
         ps.append(p)
     return np.stack(fs), np.stack(gs), np.stack(ps)
+
+
+def _batch_chunk(args):
+    name, split, start, count = args
+    return start, make_batch(name, count, split=split, start=start)
+
+
+def make_batch_parallel(name: str, batch: int, split: str = "train", workers: int | None = None,
+                        chunk: int = 250):
+    """``make_batch`` spread over worker processes: the same pairs in the same
+    order (every pair has its own seed).  The workers are spawned, so this may
+    be called from a process that already uses the GPU."""
+    import multiprocessing as mp
+    import os
+    if workers is None:
+        workers = min(16, os.cpu_count() or 1)
+    spec = WORKLOADS[name]
+    f = np.empty((batch, spec.n, spec.n), np.float32)
+    g = np.empty_like(f)
+    p = np.empty((batch, 3), np.float64)
+    jobs = [(name, split, s, min(chunk, batch - s)) for s in range(0, batch, chunk)]
+    with mp.get_context("spawn").Pool(workers) as pool:
+        for start, (a, b, c) in pool.imap_unordered(_batch_chunk, jobs):
+            f[start:start + len(a)], g[start:start + len(a)], p[start:start + len(a)] = a, b, c
+    return f, g, p
 
 
 def noise_batch(n: int, batch: int, seed: int = 0):

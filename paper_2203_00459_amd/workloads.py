@@ -52,6 +52,17 @@ TRAIN = {
 }
 
 
+# The configured mask-learning run: a fixed training set, trained for whole
+# epochs under each loss from the same initialisation and data order, judged on
+# held-out pairs against the unmasked search.
+TRAIN_RUN = {
+    # 20,000 pairs of 256 x 256 scans with distractors, batch 16, two epochs at
+    # Adam 1e-3; the squared pose loss, with Eq. 13's L1 beside it
+    "mask256_20k": dict(pairs=20000, held_out=256, batch=16, epochs=2, lr=1e-3, levels=4,
+                        scenes="mask256", search="batch256", losses=("l2", "l1")),
+}
+
+
 # Radar odometry: the forward search over every consecutive pair of a drive
 # (synth.DRIVES), all pairs in one launch, chained and scored over segments.
 DRIVE = {

@@ -8,13 +8,22 @@
    through the network: |gpu - exact| <= 2 |quant - exact| + 1e-2 per group.
 2. Training on synthetic pairs with distractors (moving clutter, multipath
    ghosts) makes the masked search beat the unmasked one on held-out pairs, and
-   the fallback policy switches to the mask only then.  The loss is Eq. 13's
-   L1: with the squared error, the outcome of 600 steps depends on the order
-   the pairs are drawn in (of four orders at lr 1e-3, two converged and two
-   did not), because outlier pairs, whose heading lands on a spurious angular
-   peak, dominate the gradient.  Under L1 all four converged, with held-out
+   the fallback policy switches to the mask only then.  The short run (1,024
+   pairs, 600 steps) uses Eq. 13's L1: with the squared error, the outcome of
+   so short a run depends on the order the pairs are drawn in (of four orders
+   at lr 1e-3, two converged and two did not).  The clutter blobs send a sixth
+   of the unmasked poses tens of degrees or metres off, and those pairs hold
+   most of a batch's squared loss (shown on the CPU with the oracle in
+   test_clutter_outliers.py).  Under L1 all four converged, with held-out
    translation errors of 0.10-0.74 m against 1.44 m unmasked, and the bounds
    below leave room for that spread.
+3. The configured run: 20,000 pairs, batch 16, the squared loss, two epochs at
+   lr 1e-3, for four data orders, with the bars the short run had before it
+   moved to L1 (last 50 steps' loss below a quarter of the first 50's, held-out
+   translation error below half the unmasked one).  Every order converges
+   (held-out 0.10-0.44 m against 1.36 m unmasked, losses down 9-280x); the
+   slow ones first get worse than the unmasked search while the outliers'
+   steps dominate, then recover.
 """
 import numpy as np
 import pytest
@@ -106,6 +115,35 @@ def test_training_makes_the_mask_beat_the_unmasked_search():
     m_f, m_g = tr.masks(Ft, Gt, training=False)
     ref = tr.search.forward(Ft, Gt, m_f, m_g, surfaces=False)["pose"]
     assert torch.equal(tr.predict(Ft, Gt), ref)
+
+
+def test_squared_loss_on_20k_pairs_beats_the_unmasked_search_for_every_order():
+    ntrain, B, epochs = 20000, 16, 2
+    f, g, p = synth.make_batch_parallel("mask256", ntrain, split="train")
+    ft, gt, pt = synth.make_batch("mask256", 256, split="test")
+    F, G, P = (torch.from_numpy(a).to(DEV) for a in (f, g, p.astype(np.float32)))
+    Ft, Gt, Pt = (torch.from_numpy(a).to(DEV) for a in (ft, gt, pt.astype(np.float32)))
+    del f, g
+    print("generated", flush=True)
+    per_epoch = ntrain // B
+    for order in range(4):
+        tr = MaskedSearchTrainer(KW256, batch=256, cfg=TrainConfig(lr=1e-3, loss=fmbym.FMBYM_LOSS_L2))
+        rng = np.random.Generator(np.random.PCG64(order))
+        losses = []
+        for _ in range(epochs):
+            perm = torch.from_numpy(rng.permutation(ntrain)).to(DEV)
+            for i in range(per_epoch):
+                idx = perm[i * B:(i + 1) * B]
+                losses.append(tr.step(F[idx].contiguous(), G[idx].contiguous(), P[idx].contiguous())[0])
+        sl = torch.stack(losses).reshape(-1).double().cpu()
+        l0, l1 = float(sl[:50].mean()), float(sl[-50:].mean())
+        after = tr.evaluate(Ft, Gt, Pt)
+        print(f"order {order}: loss {l0:.3f} -> {l1:.3f}; after {after}", flush=True)
+        assert l1 < 0.25 * l0
+        assert after["use_mask"]
+        assert after["masked_t"] < 0.5 * after["unmasked_t"]
+        assert after["masked_theta"] < after["unmasked_theta"]
+        tr.search.close()
 
 
 def test_resume_from_a_checkpoint_continues_bit_for_bit(tmp_path):
