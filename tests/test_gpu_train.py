@@ -25,6 +25,8 @@
    slow ones first get worse than the unmasked search while the outliers'
    steps dominate, then recover.
 """
+import sys
+
 import numpy as np
 import pytest
 import torch
@@ -117,14 +119,18 @@ def test_training_makes_the_mask_beat_the_unmasked_search():
     assert torch.equal(tr.predict(Ft, Gt), ref)
 
 
+@pytest.mark.early
 def test_squared_loss_on_20k_pairs_beats_the_unmasked_search_for_every_order():
     ntrain, B, epochs = 20000, 16, 2
+    # generated by worker processes, before this process first uses the GPU (the
+    # test runs first in its session)
+    assert not torch.cuda.is_initialized()
     f, g, p = synth.make_batch_parallel("mask256", ntrain, split="train")
     ft, gt, pt = synth.make_batch("mask256", 256, split="test")
     F, G, P = (torch.from_numpy(a).to(DEV) for a in (f, g, p.astype(np.float32)))
     Ft, Gt, Pt = (torch.from_numpy(a).to(DEV) for a in (ft, gt, pt.astype(np.float32)))
     del f, g
-    print("generated", flush=True)
+    print("generated", file=sys.__stderr__, flush=True)
     per_epoch = ntrain // B
     for order in range(4):
         tr = MaskedSearchTrainer(KW256, batch=256, cfg=TrainConfig(lr=1e-3, loss=fmbym.FMBYM_LOSS_L2))
@@ -138,7 +144,7 @@ def test_squared_loss_on_20k_pairs_beats_the_unmasked_search_for_every_order():
         sl = torch.stack(losses).reshape(-1).double().cpu()
         l0, l1 = float(sl[:50].mean()), float(sl[-50:].mean())
         after = tr.evaluate(Ft, Gt, Pt)
-        print(f"order {order}: loss {l0:.3f} -> {l1:.3f}; after {after}", flush=True)
+        print(f"order {order}: loss {l0:.3f} -> {l1:.3f}; after {after}", file=sys.__stderr__, flush=True)
         assert l1 < 0.25 * l0
         assert after["use_mask"]
         assert after["masked_t"] < 0.5 * after["unmasked_t"]
