@@ -9,6 +9,9 @@
 // D[4 (l / 16) + r][l % 16], r < 4.
 #include <math.h>
 
+#include <algorithm>
+#include <type_traits>
+
 #include "mask_kernels.hpp"
 #include "profile.hpp"
 
@@ -36,6 +39,18 @@ __host__ __device__ constexpr int patch_pixels(int /*S*/) { return (kConvSide + 
 constexpr size_t patch_bytes(int cin, int S) { return (size_t)patch_pixels(S) * (chunk_ch(cin) / 8 + 1) * 16; }
 
 constexpr size_t kLdsLimit = 64 * 1024;
+
+// The convolution's output tile (256 pixels x the chunk's channels) is staged
+// in LDS when it fits in kOutStageLimit bytes, so that each thread writes whole
+// 16-byte groups of a pixel's channels to HBM instead of single elements: pixel
+// p of the tile at element p * out_pitch.  The pitch keeps rows 16-byte aligned
+// and shifts the four pixel groups of a store instruction across banks.
+constexpr size_t kOutStageLimit = 40 * 1024;
+__host__ __device__ constexpr int out_pitch(int co, int elem) { return co + 16 / elem; }
+__host__ __device__ constexpr size_t out_tile_bytes(int co, int elem) {
+    return (size_t)kConvTile * out_pitch(co, elem) * elem;
+}
+__host__ __device__ constexpr bool out_staged(int co, int elem) { return out_tile_bytes(co, elem) <= kOutStageLimit; }
 
 __device__ __forceinline__ bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
 
@@ -86,12 +101,19 @@ __device__ __forceinline__ void stage_patch(const bf16* __restrict__ in, u32x4* 
 // channel) in groups of 8; every 32-wide K step is one matrix-core instruction
 // per (16-pixel M-tile, 16-channel N-tile).  Each wave owns 4 M-tiles; A comes
 // from the LDS patch, B from the packed weights.
+// MODE kConvDgrad: out is FP32 (the data gradient).  kConvTrain: out = z in
+// BF16 and the block's sums of the stored z and z^2 go to part.  kConvInfer:
+// out = relu(z scale + shift) in BF16 with the running statistics' scale and
+// shift (inference; no z, no partials).
 __host__ __device__ constexpr int co_chunk(int cout) { return cout > 96 ? 64 : cout; }
 
-template <int CIN, int COUT, bool STATS, class OutT>
+template <int CIN, int COUT, int MODE>
 __global__ __launch_bounds__(256) void k_conv3x3(const bf16* __restrict__ in, const bf16* __restrict__ w,
-                                                 OutT* __restrict__ out, float* __restrict__ part,
-                                                 int S) {
+                                                 void* __restrict__ outv, float* __restrict__ part,
+                                                 int S, BnInfer bn) {
+    using OutT = typename std::conditional<MODE == kConvDgrad, float, bf16>::type;
+    OutT* __restrict__ out = static_cast<OutT*>(outv);
+    constexpr bool STATS = MODE == kConvTrain;
     constexpr int CC = chunk_ch(CIN), NCH = CIN / CC, G = CC / 8, NQ = 9 * G, NS = (NQ + 3) / 4;
     constexpr int CO = co_chunk(COUT), NT = pad16(CO) / 16, K = 9 * CIN;
     static_assert(COUT % CO == 0, "whole output-channel chunks");
@@ -143,10 +165,31 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16* __restrict__ in, co
                 for (int nt = 0; nt < NT; ++nt) acc[mi][nt] = mfma(a[mi], b[nt], acc[mi][nt]);
         }
     }
+    // inference: batch norm on the running statistics and ReLU on the BF16-rounded
+    // output, the arithmetic of the training pass's statistics and BN + ReLU passes
+    float csc[NT], csh[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        csc[nt] = csh[nt] = 0.f;
+        if constexpr (MODE == kConvInfer) {
+            const int c = co0 + nt * 16 + r16;
+            if (nt * 16 + r16 < CO) {
+                const double mean = bn.run_mean[c], var = bn.run_var[c];
+                const double inv = 1.0 / sqrt(var + (double)bn.eps);
+                const double sc = (double)bn.gamma[c] * inv;
+                csc[nt] = (float)sc;
+                csh[nt] = (float)((double)bn.beta[c] - mean * sc);
+            }
+        }
+    }
     float s1[NT], s2[NT];
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) s1[nt] = s2[nt] = 0.f;
     const size_t img_base = (size_t)t.img * S * S;
+    constexpr int ELEM = (int)sizeof(OutT), TP = out_pitch(CO, ELEM);
+    constexpr bool STAGED = out_staged(CO, ELEM);
+    OutT* stage = reinterpret_cast<OutT*>(patch);
+    if constexpr (STAGED) __syncthreads();   // every wave is done with the patch
 #pragma unroll
     for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
@@ -158,17 +201,32 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16* __restrict__ in, co
                 const int co = nt * 16 + r16;
                 if (co >= CO) continue;
                 const float v = acc[mi][nt][r];
+                OutT o;
                 if constexpr (STATS) {
                     const bf16 h = (bf16)v;
-                    out[pix * COUT + co0 + co] = h;
+                    o = h;
                     const float hv = (float)h;
                     s1[nt] += hv;
                     s2[nt] += hv * hv;
+                } else if constexpr (MODE == kConvInfer) {
+                    o = (bf16)fmaxf(fmaf((float)(bf16)v, csc[nt], csh[nt]), 0.f);
                 } else {
-                    out[pix * COUT + co0 + co] = v;
+                    o = v;
                 }
+                if constexpr (STAGED) stage[p * TP + co] = o;
+                else out[pix * COUT + co0 + co] = o;
             }
         }
+    if constexpr (STAGED) {
+        __syncthreads();
+        constexpr int VEC = 16 / ELEM, VPP = CO / VEC;   // 16-byte groups per pixel
+        static_assert(CO % VEC == 0, "whole 16-byte groups per pixel");
+        for (int it = threadIdx.x; it < kConvTile * VPP; it += blockDim.x) {
+            const int p = it / VPP, q = it % VPP;
+            const size_t pix = img_base + (size_t)(t.y0 + p / t.pc) * S + t.x0 + p % t.pc;
+            *(u32x4*)(out + pix * COUT + co0 + q * VEC) = *(const u32x4*)(stage + p * TP + q * VEC);
+        }
+    }
     if constexpr (STATS) {
         __shared__ float red[4][2][NT * 16];
 #pragma unroll
@@ -1048,19 +1106,24 @@ size_t colsum_tmp_floats(int n) { return (size_t)kColChunks * n; }
     X(64, 128) X(128, 128) X(128, 256) X(256, 256) X(384, 128) X(192, 64)                           \
     X(128, 64) X(256, 128) X(128, 384) X(64, 192)
 
-bool launch_conv3x3(int cin, int cout, bool stats, const bf16* in, const bf16* w, void* z, float* part,
-                    int images, int S, hipStream_t s) {
+bool launch_conv3x3(int cin, int cout, int mode, const bf16* in, const bf16* w, void* out, float* part,
+                    const BnInfer& bn, int images, int S, hipStream_t s) {
     const dim3 grid(conv_blocks(images, S), cout / co_chunk(cout)), block(256);
-    const size_t lds = patch_bytes(cin, S);
+    const int elem = mode == kConvDgrad ? 4 : 2;
+    size_t lds = patch_bytes(cin, S);
+    if (out_staged(co_chunk(cout), elem)) lds = std::max(lds, out_tile_bytes(co_chunk(cout), elem));
     if (lds + 4 * 2 * 96 * sizeof(float) > kLdsLimit) return false;
 #define FMBYM_CONV_CASE(CI, CO)                                                                   \
     if (cin == CI && cout == CO) {                                                                \
-        if (stats)                                                                                \
-            FMBYM_LAUNCH_LDS(kMConvFwd, (k_conv3x3<CI, CO, true, bf16>), grid, block, lds, s, in, w, \
-                               (bf16*)z, part, S);                                                \
+        if (mode == kConvTrain)                                                                   \
+            FMBYM_LAUNCH_LDS(kMConvFwd, (k_conv3x3<CI, CO, kConvTrain>), grid, block, lds, s, in, w, out, part, \
+                             S, bn);                                                              \
+        else if (mode == kConvInfer)                                                              \
+            FMBYM_LAUNCH_LDS(kMConvFwd, (k_conv3x3<CI, CO, kConvInfer>), grid, block, lds, s, in, w, out, part, \
+                             S, bn);                                                              \
         else                                                                                      \
-            FMBYM_LAUNCH_LDS(kMConvDgrad, (k_conv3x3<CI, CO, false, float>), grid, block, lds, s, in, w, \
-                               (float*)z, part, S);                                               \
+            FMBYM_LAUNCH_LDS(kMConvDgrad, (k_conv3x3<CI, CO, kConvDgrad>), grid, block, lds, s, in, w, out, \
+                             part, S, bn);                                                        \
         return true;                                                                              \
     }
     FMBYM_CONV_PAIRS(FMBYM_CONV_CASE)

@@ -38,12 +38,27 @@ void launch_input8(const float* x, const float* const* x_tab, bf16* x8, int imag
 void launch_input_grad(const bf16* dz, const float* w, float* dx, int images, int S, int C, int ch,
                        hipStream_t s);
 
-// z = conv3x3(in, w) for (cin, cout) in the supported set; w packed [cout][9 cin]
-// bf16 (k = tap cin + ci, tap = 3 ky + kx).  With stats, z is bf16 and
-// part[block][2][cout] receives the block's sums of z and z^2 (of the stored
-// bf16 values); otherwise z is float.  Returns false for an unsupported pair.
-bool launch_conv3x3(int cin, int cout, bool stats, const bf16* in, const bf16* w, void* z,
-                    float* part, int images, int S, hipStream_t s);
+// Batch norm on the running statistics, for the inference-mode convolution.
+struct BnInfer {
+    const float* gamma;
+    const float* beta;
+    const float* run_mean;
+    const float* run_var;
+    float eps;
+};
+enum ConvMode { kConvDgrad = 0, kConvTrain = 1, kConvInfer = 2 };
+
+// 3x3 convolution for (cin, cout) in the supported set; w packed [cout][9 cin]
+// bf16 (k = tap cin + ci, tap = 3 ky + kx).
+//   kConvDgrad: out = conv (float);
+//   kConvTrain: out = z = bf16(conv), and part[block][2][cout] receives the
+//               block's sums of z and z^2 (of the stored bf16 values);
+//   kConvInfer: out = bf16(relu(bf16(conv) scale + shift)) with bn's scale
+//               gamma / sqrt(run_var + eps) and shift beta - run_mean scale
+//               (computed in double as the statistics pass does); no partials.
+// Returns false for an unsupported pair.
+bool launch_conv3x3(int cin, int cout, int mode, const bf16* in, const bf16* w, void* out, float* part,
+                    const BnInfer& bn, int images, int S, hipStream_t s);
 
 // Weight gradient: sum over pixels of dz[p][co] in[p + tap][ci], through
 // per-block partials part (wgrad_grid) and a fixed-order reduction (tmp:

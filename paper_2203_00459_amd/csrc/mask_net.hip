@@ -311,7 +311,7 @@ int fmbym_mask_bwd(const fmbym_mask_desc* d, int32_t I, int32_t n, const float* 
             din = at<float>(wsp, W.dcat[c.level]);
         else
             din = at<float>(wsp, W.g[j - 1]);
-        if (!launch_conv3x3(c.cout, c.cin, false, dz, pk + c.pb, din, nullptr, I, S, s))
+        if (!launch_conv3x3(c.cout, c.cin, kConvDgrad, dz, pk + c.pb, din, nullptr, BnInfer{}, I, S, s))
             return FMBYM_EUNSUPPORTED;
         // the gradient of the next conv down (parameter order j - 1) when it is a b conv
         if (!c.enc && c.first_of_level) {
@@ -387,12 +387,19 @@ int mask_forward(const fmbym_mask_desc* d, int I, int n, const float* x, const f
         } else {
             in = at<bf16>(act, A.a[j - 1]);
         }
-        if (!launch_conv3x3(c.cink, c.cout, true, in, pk + c.pf, at<bf16>(act, A.z[j]), at<float>(act, A.part),
-                            I, S, s))
+        if (!training) {   // BN on the running statistics and ReLU inside the convolution
+            const BnInfer bn{d->params + c.gamma, d->params + c.beta, run_mean + c.bn, run_var + c.bn, net.eps};
+            if (!launch_conv3x3(c.cink, c.cout, kConvInfer, in, pk + c.pf, at<bf16>(act, A.a[j]), nullptr, bn, I,
+                                S, s))
+                return FMBYM_EUNSUPPORTED;
+            continue;
+        }
+        if (!launch_conv3x3(c.cink, c.cout, kConvTrain, in, pk + c.pf, at<bf16>(act, A.z[j]), at<float>(act, A.part),
+                            BnInfer{}, I, S, s))
             return FMBYM_EUNSUPPORTED;
         const long long M = (long long)I * S * S;
         launch_bn_stats(at<float>(act, A.part), conv_blocks(I, S), c.cout, M, d->params + c.gamma,
-                        d->params + c.beta, net.eps, net.momentum, training ? 1 : 0, run_mean + c.bn,
+                        d->params + c.beta, net.eps, net.momentum, 1, run_mean + c.bn,
                         run_var + c.bn, at<float>(act, A.stat[j]), at<float>(act, A.tmp), s);
         launch_bn_relu(at<bf16>(act, A.z[j]), at<float>(act, A.stat[j]), at<bf16>(act, A.a[j]), M, c.cout, s);
     }
