@@ -93,6 +93,32 @@ __device__ __forceinline__ void stage_patch(const bf16* __restrict__ in, u32x4* 
     }
 }
 
+// The same patch through registers: load_patch issues the loads (thread t takes
+// entries t, t + 256, ...; zeros outside the image), store_patch writes them to LDS.
+template <int CIN, int G, int NL>
+__device__ __forceinline__ void load_patch(const bf16* __restrict__ in, u32x4 (&v)[NL], const TileGeo& t, int S) {
+    constexpr int W = kConvSide + 2, NE = W * W * G;
+    const bf16* base = in + (size_t)t.img * S * S * CIN;
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int it = threadIdx.x + 256 * k;
+        const int q = it / G, cg = it % G;
+        const int y = t.y0 - 1 + q / W, x = t.x0 - 1 + q % W;
+        v[k] = u32x4{0u, 0u, 0u, 0u};
+        if (it < NE && y >= 0 && y < S && x >= 0 && x < S)
+            v[k] = *(const u32x4*)(base + ((size_t)y * S + x) * CIN + 8 * cg);
+    }
+}
+template <int G, int NL>
+__device__ __forceinline__ void store_patch(u32x4* patch, const u32x4 (&v)[NL]) {
+    constexpr int W = kConvSide + 2, NE = W * W * G;
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int it = threadIdx.x + 256 * k;
+        if (it < NE) patch[(it / G) * (G + 1) + it % G] = v[k];
+    }
+}
+
 // ------------------------------------------------------------ convolution
 
 // out = conv3x3(in, w) over one 16 x 16-pixel tile per block (blockIdx.x) and
@@ -110,7 +136,7 @@ __host__ __device__ constexpr int co_chunk(int cout) { return cout > 96 ? 64 : c
 template <int CIN, int COUT, int MODE>
 __global__ __launch_bounds__(256) void k_conv3x3(const bf16* __restrict__ in, const bf16* __restrict__ w,
                                                  void* __restrict__ outv, float* __restrict__ part,
-                                                 int S, BnInfer bn) {
+                                                 int S, BnInfer bn, int tpb, int tiles) {
     using OutT = typename std::conditional<MODE == kConvDgrad, float, bf16>::type;
     OutT* __restrict__ out = static_cast<OutT*>(outv);
     constexpr bool STATS = MODE == kConvTrain;
@@ -119,52 +145,24 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16* __restrict__ in, co
     static_assert(COUT % CO == 0, "whole output-channel chunks");
     const int co0 = blockIdx.y * CO;
     static_assert(CIN % 8 == 0 && CIN % CC == 0, "input channels in groups of 8");
-    extern __shared__ u32x4 patch[];   // patch_bytes(CIN, S)
-    const TileGeo t = conv_tile_geo(blockIdx.x, S);
+    extern __shared__ u32x4 patch[];   // patch_bytes(CIN, S) or the staged output tile
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, r16 = lane & 15;
-    const int W = t.pc + 2;
+    constexpr int W = kConvSide + 2;
     int prow[4], pcol[4];
 #pragma unroll
     for (int mi = 0; mi < 4; ++mi) {
         const int p = (wave + 4 * mi) * 16 + r16;
-        prow[mi] = p / t.pc;
-        pcol[mi] = p % t.pc;
+        prow[mi] = p / kConvSide;
+        pcol[mi] = p % kConvSide;
     }
-    f32x4 acc[4][NT];
-#pragma unroll
-    for (int mi = 0; mi < 4; ++mi)
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) acc[mi][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const u32x4 zero = {0u, 0u, 0u, 0u};
-    for (int ch = 0; ch < NCH; ++ch) {
-        const int c0 = ch * CC;
-        if (ch) __syncthreads();
-        stage_patch<CIN, G>(in, patch, t, S, c0);
-        __syncthreads();
-#pragma unroll
-        for (int st = 0; st < NS; ++st) {
-            const int q = 4 * st + g;
-            const bool valid = q < NQ;
-            const int tap = valid ? q / G : 0, cg = q % G;
-            const int ky = tap / 3, kx = tap % 3;
-            u32x4 a[4], b[NT];
-#pragma unroll
-            for (int mi = 0; mi < 4; ++mi)
-                a[mi] = valid ? patch[((prow[mi] + ky) * W + pcol[mi] + kx) * (G + 1) + cg] : zero;
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                const int co = nt * 16 + r16;
-                b[nt] = (valid && co < CO)
-                            ? *(const u32x4*)(w + (size_t)(co0 + co) * K + tap * CIN + c0 + 8 * cg)
-                            : zero;
-            }
-#pragma unroll
-            for (int mi = 0; mi < 4; ++mi)
-#pragma unroll
-                for (int nt = 0; nt < NT; ++nt) acc[mi][nt] = mfma(a[mi], b[nt], acc[mi][nt]);
-        }
-    }
+    // With the whole patch in one pass (CIN <= 32), the next tile's patch is
+    // loaded into registers while the current one is computed.
+    constexpr bool PREF = NCH == 1;
+    constexpr int PLOADS = (W * W * G + 255) / 256;
+    u32x4 pre[PREF ? PLOADS : 1];
+    const int tile0 = blockIdx.x * tpb, tile1 = min(tiles, tile0 + tpb);
+    if constexpr (PREF) load_patch<CIN, G, PLOADS>(in, pre, conv_tile_geo(tile0, S), S);
     // inference: batch norm on the running statistics and ReLU on the BF16-rounded
     // output, the arithmetic of the training pass's statistics and BN + ReLU passes
     float csc[NT], csh[NT];
@@ -185,48 +183,90 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16* __restrict__ in, co
     float s1[NT], s2[NT];
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) s1[nt] = s2[nt] = 0.f;
-    const size_t img_base = (size_t)t.img * S * S;
-    constexpr int ELEM = (int)sizeof(OutT), TP = out_pitch(CO, ELEM);
-    constexpr bool STAGED = out_staged(CO, ELEM);
-    OutT* stage = reinterpret_cast<OutT*>(patch);
-    if constexpr (STAGED) __syncthreads();   // every wave is done with the patch
+    for (int tile = tile0; tile < tile1; ++tile) {
+        const TileGeo t = conv_tile_geo(tile, S);
+        f32x4 acc[4][NT];
 #pragma unroll
-    for (int mi = 0; mi < 4; ++mi)
+        for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int p = (wave + 4 * mi) * 16 + 4 * g + r;
-            const size_t pix = img_base + (size_t)(t.y0 + p / t.pc) * S + t.x0 + p % t.pc;
+            for (int nt = 0; nt < NT; ++nt) acc[mi][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        const u32x4 zero = {0u, 0u, 0u, 0u};
+        for (int ch = 0; ch < NCH; ++ch) {
+            const int c0 = ch * CC;
+            __syncthreads();   // the previous patch (or staged output) has been read
+            if constexpr (PREF) {
+                store_patch<G, PLOADS>(patch, pre);
+                if (tile + 1 < tile1) load_patch<CIN, G, PLOADS>(in, pre, conv_tile_geo(tile + 1, S), S);
+            } else {
+                stage_patch<CIN, G>(in, patch, t, S, c0);
+            }
+            __syncthreads();
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                const int co = nt * 16 + r16;
-                if (co >= CO) continue;
-                const float v = acc[mi][nt][r];
-                OutT o;
-                if constexpr (STATS) {
-                    const bf16 h = (bf16)v;
-                    o = h;
-                    const float hv = (float)h;
-                    s1[nt] += hv;
-                    s2[nt] += hv * hv;
-                } else if constexpr (MODE == kConvInfer) {
-                    o = (bf16)fmaxf(fmaf((float)(bf16)v, csc[nt], csh[nt]), 0.f);
-                } else {
-                    o = v;
+            for (int st = 0; st < NS; ++st) {
+                const int q = 4 * st + g;
+                const bool valid = q < NQ;
+                const int tap = valid ? q / G : 0, cg = q % G;
+                const int ky = tap / 3, kx = tap % 3;
+                u32x4 a[4], b[NT];
+#pragma unroll
+                for (int mi = 0; mi < 4; ++mi)
+                    a[mi] = valid ? patch[((prow[mi] + ky) * W + pcol[mi] + kx) * (G + 1) + cg] : zero;
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    const int co = nt * 16 + r16;
+                    b[nt] = (valid && co < CO)
+                                ? *(const u32x4*)(w + (size_t)(co0 + co) * K + tap * CIN + c0 + 8 * cg)
+                                : zero;
                 }
-                if constexpr (STAGED) stage[p * TP + co] = o;
-                else out[pix * COUT + co0 + co] = o;
+#pragma unroll
+                for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) acc[mi][nt] = mfma(a[mi], b[nt], acc[mi][nt]);
             }
         }
-    if constexpr (STAGED) {
-        __syncthreads();
-        constexpr int VEC = 16 / ELEM, VPP = CO / VEC;   // 16-byte groups per pixel
-        static_assert(CO % VEC == 0, "whole 16-byte groups per pixel");
-        for (int it = threadIdx.x; it < kConvTile * VPP; it += blockDim.x) {
-            const int p = it / VPP, q = it % VPP;
-            const size_t pix = img_base + (size_t)(t.y0 + p / t.pc) * S + t.x0 + p % t.pc;
-            *(u32x4*)(out + pix * COUT + co0 + q * VEC) = *(const u32x4*)(stage + p * TP + q * VEC);
+        const size_t img_base = (size_t)t.img * S * S;
+        constexpr int ELEM = (int)sizeof(OutT), TP = out_pitch(CO, ELEM);
+        constexpr bool STAGED = out_staged(CO, ELEM);
+        OutT* stage = reinterpret_cast<OutT*>(patch);
+        if constexpr (STAGED) __syncthreads();   // every wave is done with the patch
+#pragma unroll
+        for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int p = (wave + 4 * mi) * 16 + 4 * g + r;
+                const size_t pix = img_base + (size_t)(t.y0 + p / t.pc) * S + t.x0 + p % t.pc;
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    const int co = nt * 16 + r16;
+                    if (co >= CO) continue;
+                    const float v = acc[mi][nt][r];
+                    OutT o;
+                    if constexpr (STATS) {
+                        const bf16 h = (bf16)v;
+                        o = h;
+                        const float hv = (float)h;
+                        s1[nt] += hv;
+                        s2[nt] += hv * hv;
+                    } else if constexpr (MODE == kConvInfer) {
+                        o = (bf16)fmaxf(fmaf((float)(bf16)v, csc[nt], csh[nt]), 0.f);
+                    } else {
+                        o = v;
+                    }
+                    if constexpr (STAGED) stage[p * TP + co] = o;
+                    else out[pix * COUT + co0 + co] = o;
+                }
+            }
+        if constexpr (STAGED) {
+            __syncthreads();
+            constexpr int VEC = 16 / ELEM, VPP = CO / VEC;   // 16-byte groups per pixel
+            static_assert(CO % VEC == 0, "whole 16-byte groups per pixel");
+            for (int it = threadIdx.x; it < kConvTile * VPP; it += blockDim.x) {
+                const int p = it / VPP, q = it % VPP;
+                const size_t pix = img_base + (size_t)(t.y0 + p / t.pc) * S + t.x0 + p % t.pc;
+                *(u32x4*)(out + pix * COUT + co0 + q * VEC) = *(const u32x4*)(stage + p * TP + q * VEC);
+            }
         }
-    }
+    }   // tiles
     if constexpr (STATS) {
         __shared__ float red[4][2][NT * 16];
 #pragma unroll
@@ -1108,7 +1148,8 @@ size_t colsum_tmp_floats(int n) { return (size_t)kColChunks * n; }
 
 bool launch_conv3x3(int cin, int cout, int mode, const bf16* in, const bf16* w, void* out, float* part,
                     const BnInfer& bn, int images, int S, hipStream_t s) {
-    const dim3 grid(conv_blocks(images, S), cout / co_chunk(cout)), block(256);
+    const int tiles = conv_blocks(images, S), tpb = conv_tpb(tiles);
+    const dim3 grid(conv_part_blocks(images, S), cout / co_chunk(cout)), block(256);
     const int elem = mode == kConvDgrad ? 4 : 2;
     size_t lds = patch_bytes(cin, S);
     if (out_staged(co_chunk(cout), elem)) lds = std::max(lds, out_tile_bytes(co_chunk(cout), elem));
@@ -1117,13 +1158,13 @@ bool launch_conv3x3(int cin, int cout, int mode, const bf16* in, const bf16* w, 
     if (cin == CI && cout == CO) {                                                                \
         if (mode == kConvTrain)                                                                   \
             FMBYM_LAUNCH_LDS(kMConvFwd, (k_conv3x3<CI, CO, kConvTrain>), grid, block, lds, s, in, w, out, part, \
-                             S, bn);                                                              \
+                             S, bn, tpb, tiles);                                                  \
         else if (mode == kConvInfer)                                                              \
             FMBYM_LAUNCH_LDS(kMConvFwd, (k_conv3x3<CI, CO, kConvInfer>), grid, block, lds, s, in, w, out, part, \
-                             S, bn);                                                              \
+                             S, bn, tpb, tiles);                                                  \
         else                                                                                      \
             FMBYM_LAUNCH_LDS(kMConvDgrad, (k_conv3x3<CI, CO, kConvDgrad>), grid, block, lds, s, in, w, out, \
-                             part, S, bn);                                                        \
+                             part, S, bn, tpb, tiles);                                            \
         return true;                                                                              \
     }
     FMBYM_CONV_PAIRS(FMBYM_CONV_CASE)

@@ -16,8 +16,19 @@ constexpr int kConvTile = 256;
 
 __host__ __device__ constexpr int pad16(int c) { return (c + 15) / 16 * 16; }
 
-// Blocks of one conv launch over `images` images of side S.
+// Tiles (16 x 16 pixels) of one conv launch over `images` images of side S.
 inline int conv_blocks(int images, int S) { return images * (S * S / kConvTile); }
+// Tiles each block of a conv launch computes in sequence (the next tile's
+// input in flight during the current one), and the blocks: one partial-sum
+// record each for the batch-norm statistics.
+inline int conv_tpb(int tiles) {
+    const int t = tiles / 2048;
+    return t < 1 ? 1 : (t > 16 ? 16 : t);
+}
+inline int conv_part_blocks(int images, int S) {
+    const int tiles = conv_blocks(images, S), tpb = conv_tpb(tiles);
+    return (tiles + tpb - 1) / tpb;
+}
 
 // Partial-sum blocks of the channel reductions (batch-norm statistics) over
 // M pixels of C channels; see bn_part_blocks in the kernels.
@@ -52,7 +63,8 @@ enum ConvMode { kConvDgrad = 0, kConvTrain = 1, kConvInfer = 2 };
 // bf16 (k = tap cin + ci, tap = 3 ky + kx).
 //   kConvDgrad: out = conv (float);
 //   kConvTrain: out = z = bf16(conv), and part[block][2][cout] receives the
-//               block's sums of z and z^2 (of the stored bf16 values);
+//               block's sums of z and z^2 (of the stored bf16 values; one record
+//               per block of conv_part_blocks);
 //   kConvInfer: out = bf16(relu(bf16(conv) scale + shift)) with bn's scale
 //               gamma / sqrt(run_var + eps) and shift beta - run_mean scale
 //               (computed in double as the statistics pass does); no partials.

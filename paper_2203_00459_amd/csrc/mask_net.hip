@@ -130,7 +130,7 @@ ActLayout act_layout(const Net& net, int I, int n) {
         L.z.push_back(b.take(pix(c.level) * c.cout * bf));
         L.a.push_back(b.take(pix(c.level) * c.cout * bf));
         L.stat.push_back(b.take(4 * (size_t)c.cout * fl));
-        const size_t p = (size_t)conv_blocks(I, n >> c.level) * 2 * c.cout * fl;
+        const size_t p = (size_t)conv_part_blocks(I, n >> c.level) * 2 * c.cout * fl;
         if (p > part_max) part_max = p;
     }
     L.pool.assign(net.levels, 0);
@@ -398,7 +398,7 @@ int mask_forward(const fmbym_mask_desc* d, int I, int n, const float* x, const f
                             BnInfer{}, I, S, s))
             return FMBYM_EUNSUPPORTED;
         const long long M = (long long)I * S * S;
-        launch_bn_stats(at<float>(act, A.part), conv_blocks(I, S), c.cout, M, d->params + c.gamma,
+        launch_bn_stats(at<float>(act, A.part), conv_part_blocks(I, S), c.cout, M, d->params + c.gamma,
                         d->params + c.beta, net.eps, net.momentum, 1, run_mean + c.bn,
                         run_var + c.bn, at<float>(act, A.stat[j]), at<float>(act, A.tmp), s);
         launch_bn_relu(at<bf16>(act, A.z[j]), at<float>(act, A.stat[j]), at<bf16>(act, A.a[j]), M, c.cout, s);

@@ -8,22 +8,21 @@
    through the network: |gpu - exact| <= 2 |quant - exact| + 1e-2 per group.
 2. Training on synthetic pairs with distractors (moving clutter, multipath
    ghosts) makes the masked search beat the unmasked one on held-out pairs, and
-   the fallback policy switches to the mask only then.  The short run (1,024
-   pairs, 600 steps) uses Eq. 13's L1: with the squared error, the outcome of
-   so short a run depends on the order the pairs are drawn in (of four orders
-   at lr 1e-3, two converged and two did not).  The clutter blobs send a sixth
-   of the unmasked poses tens of degrees or metres off, and those pairs hold
-   most of a batch's squared loss (shown on the CPU with the oracle in
-   test_clutter_outliers.py).  Under L1 all four converged, with held-out
-   translation errors of 0.10-0.74 m against 1.44 m unmasked, and the bounds
-   below leave room for that spread.
-3. The configured run: 20,000 pairs, batch 16, the squared loss, two epochs at
-   lr 1e-3, for four data orders, with the bars the short run had before it
-   moved to L1 (last 50 steps' loss below a quarter of the first 50's, held-out
-   translation error below half the unmasked one).  Every order converges
-   (held-out 0.10-0.44 m against 1.36 m unmasked, losses down 9-280x); the
-   slow ones first get worse than the unmasked search while the outliers'
-   steps dominate, then recover.
+   the fallback policy switches to the mask only then.  The run is the
+   configured one: 20,000 pairs, batch 16, two epochs at lr 1e-3, under the
+   squared loss for four data orders and under Eq. 13's L1 for one, with the
+   bars: the last 50 steps' loss below a quarter of the first 50's, held-out
+   translation error below half the unmasked one, heading error below it.
+   Every run converges (held-out 0.10-0.25 m under L2 and 0.06 m under L1,
+   against 1.36 m unmasked); the
+   slow orders first get worse than the unmasked search while the outlier
+   pairs' steps dominate (the clutter blobs send about a sixth of the unmasked
+   poses tens of degrees or metres off, and those pairs hold most of a batch's
+   squared loss: test_clutter_outliers.py shows it on the CPU), then recover.
+   A short run (1,024 pairs, 600 steps) is not a stable test: its outcome
+   depended on the data order under L2, and under L1 a rounding-level change
+   (the order of the batch-norm statistics' sums) turned a converging run into
+   one that did not.
 """
 import sys
 
@@ -91,36 +90,23 @@ def test_chain_gradient_matches_oracle():
     print(f"chain gradient: worst |gpu-exact| / bound {worst:.3f}", flush=True)
 
 
-def test_training_makes_the_mask_beat_the_unmasked_search():
-    ntrain, steps, B = 1024, 600, 16
-    f, g, p = synth.make_batch("mask256", ntrain, split="train")
-    ft, gt, pt = synth.make_batch("mask256", 64, split="test")
-    F, G, P = (torch.from_numpy(a).to(DEV) for a in (f, g, p.astype(np.float32)))
-    Ft, Gt, Pt = (torch.from_numpy(a).to(DEV) for a in (ft, gt, pt.astype(np.float32)))
-    tr = MaskedSearchTrainer(KW256, batch=64, cfg=TrainConfig(lr=1e-3, loss=fmbym.FMBYM_LOSS_L1))
-    before = tr.evaluate(Ft, Gt, Pt)
-    print("before", before, flush=True)
-    assert not before["use_mask"]
-    rng = np.random.Generator(np.random.PCG64(0))
-    first, last = [], []
-    for s in range(steps):
-        idx = torch.from_numpy(rng.choice(ntrain, B, replace=False)).to(DEV)
-        loss, _ = tr.step(F[idx].contiguous(), G[idx].contiguous(), P[idx].contiguous())
-        (first if s < 50 else last if s >= steps - 50 else []).append(loss)
-    l0, l1 = float(torch.stack(first).mean()), float(torch.stack(last).mean())
-    after = tr.evaluate(Ft, Gt, Pt)
-    print(f"loss {l0:.3f} -> {l1:.3f}; after {after}", flush=True)
-    assert l1 < 0.75 * l0
-    assert after["use_mask"]
-    assert after["masked_t"] < 0.6 * after["unmasked_t"]
-    assert after["masked_theta"] < after["unmasked_theta"]
-    m_f, m_g = tr.masks(Ft, Gt, training=False)
-    ref = tr.search.forward(Ft, Gt, m_f, m_g, surfaces=False)["pose"]
-    assert torch.equal(tr.predict(Ft, Gt), ref)
+def _train(tr, F, G, P, order, epochs, B):
+    """Whole epochs over the training set in a PCG64(order) permutation per
+    epoch; returns the mean loss of the first and of the last 50 steps."""
+    ntrain = F.shape[0]
+    rng = np.random.Generator(np.random.PCG64(order))
+    losses = []
+    for _ in range(epochs):
+        perm = torch.from_numpy(rng.permutation(ntrain)).to(DEV)
+        for i in range(ntrain // B):
+            idx = perm[i * B:(i + 1) * B]
+            losses.append(tr.step(F[idx].contiguous(), G[idx].contiguous(), P[idx].contiguous())[0])
+    sl = torch.stack(losses).reshape(-1).double().cpu()
+    return float(sl[:50].mean()), float(sl[-50:].mean())
 
 
 @pytest.mark.early
-def test_squared_loss_on_20k_pairs_beats_the_unmasked_search_for_every_order():
+def test_training_on_20k_pairs_beats_the_unmasked_search_for_every_order():
     ntrain, B, epochs = 20000, 16, 2
     # generated by worker processes, before this process first uses the GPU (the
     # test runs first in its session)
@@ -131,24 +117,23 @@ def test_squared_loss_on_20k_pairs_beats_the_unmasked_search_for_every_order():
     Ft, Gt, Pt = (torch.from_numpy(a).to(DEV) for a in (ft, gt, pt.astype(np.float32)))
     del f, g
     print("generated", file=sys.__stderr__, flush=True)
-    per_epoch = ntrain // B
-    for order in range(4):
-        tr = MaskedSearchTrainer(KW256, batch=256, cfg=TrainConfig(lr=1e-3, loss=fmbym.FMBYM_LOSS_L2))
-        rng = np.random.Generator(np.random.PCG64(order))
-        losses = []
-        for _ in range(epochs):
-            perm = torch.from_numpy(rng.permutation(ntrain)).to(DEV)
-            for i in range(per_epoch):
-                idx = perm[i * B:(i + 1) * B]
-                losses.append(tr.step(F[idx].contiguous(), G[idx].contiguous(), P[idx].contiguous())[0])
-        sl = torch.stack(losses).reshape(-1).double().cpu()
-        l0, l1 = float(sl[:50].mean()), float(sl[-50:].mean())
+    runs = [(fmbym.FMBYM_LOSS_L2, order) for order in range(4)] + [(fmbym.FMBYM_LOSS_L1, 0)]
+    for loss, order in runs:
+        tr = MaskedSearchTrainer(KW256, batch=256, cfg=TrainConfig(lr=1e-3, loss=loss))
+        before = tr.evaluate(Ft, Gt, Pt)
+        assert not before["use_mask"]     # the untrained network loses to the plain search
+        l0, l1 = _train(tr, F, G, P, order, epochs, B)
         after = tr.evaluate(Ft, Gt, Pt)
-        print(f"order {order}: loss {l0:.3f} -> {l1:.3f}; after {after}", file=sys.__stderr__, flush=True)
+        name = "L1" if loss == fmbym.FMBYM_LOSS_L1 else "L2"
+        print(f"{name} order {order}: loss {l0:.3f} -> {l1:.3f}; after {after}", file=sys.__stderr__, flush=True)
         assert l1 < 0.25 * l0
         assert after["use_mask"]
         assert after["masked_t"] < 0.5 * after["unmasked_t"]
         assert after["masked_theta"] < after["unmasked_theta"]
+        # the fallback policy now answers with the masked search
+        m_f, m_g = tr.masks(Ft, Gt, training=False)
+        ref = tr.search.forward(Ft, Gt, m_f, m_g, surfaces=False)["pose"]
+        assert torch.equal(tr.predict(Ft, Gt), ref)
         tr.search.close()
 
 
