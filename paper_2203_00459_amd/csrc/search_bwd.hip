@@ -398,15 +398,22 @@ __global__ __launch_bounds__(256) void kb_dmag(const int* __restrict__ ptr, cons
                                                const float* __restrict__ val, const int* __restrict__ dst,
                                                const int* __restrict__ part,
                                                const float2* __restrict__ dpol, float2* __restrict__ dA,
-                                               int n, int n_r, int n_theta, int batch) {
+                                               int n, int n_r, int n_theta, int batch, int nparts) {
     __shared__ float4 prod[kDmagChunk][kDmagPairs / 2];
     const int tid = threadIdx.x;
+    // work item (run, pair group), runs fastest, in contiguous eighths per XCD:
+    // neighbouring bins, whose polar samples overlap, share one XCD's L2
+    const int groups = (batch + kDmagPairs - 1) / kDmagPairs, total = nparts * groups;
+    const int per_xcd = (total + 7) / 8;
+    const int work = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (work >= total) return;
+    const int run = work % nparts, grp = work / nparts;
     // the block's entry range from two uniform reads: the entry loads need not
     // wait for the rows' bounds, which each thread reads for itself
-    const int r0 = part[blockIdx.x], nrow = part[blockIdx.x + 1] - r0;
+    const int r0 = part[run], nrow = part[run + 1] - r0;
     const int e_begin = ptr[r0], e_end = ptr[r0 + nrow];
     const size_t pstride = (size_t)n_r * n_theta;
-    const int p0 = blockIdx.y * kDmagPairs, np = min(kDmagPairs, batch - p0);
+    const int p0 = grp * kDmagPairs, np = min(kDmagPairs, batch - p0);
     const float2* src = dpol + (size_t)p0 * pstride;
     const int my0 = tid < nrow ? ptr[r0 + tid] : 0, my1 = tid < nrow ? ptr[r0 + tid + 1] : 0;
     float2 acc[kDmagPairs];
@@ -858,9 +865,9 @@ static int launch_bwd_n(const Plan& pl, int B, const float* f, const float* g, c
         default: return FMBYM_EUNSUPPORTED;
     }
     float2* dA = magw;                  // (recomputed magnitudes are dead after kb_polar)
-    FMBYM_LAUNCH(kKBDmag, kb_dmag, dim3(pl.dmag_nparts, (B + kDmagPairs - 1) / kDmagPairs), dim3(256), s,
-                 pl.csr_ptr, pl.csr_col, pl.csr_val, pl.csr_dst, pl.dmag_part, dpol, dA, N, pl.p.n_r,
-                 pl.p.n_theta, B);
+    const int dmag_work = pl.dmag_nparts * ((B + kDmagPairs - 1) / kDmagPairs);
+    FMBYM_LAUNCH(kKBDmag, kb_dmag, dim3(((dmag_work + 7) / 8) * 8), dim3(256), s, pl.csr_ptr, pl.csr_col,
+                 pl.csr_val, pl.csr_dst, pl.dmag_part, dpol, dA, N, pl.p.n_r, pl.p.n_theta, B, pl.dmag_nparts);
     launch_cols_mag<N>(pl, B, r1, r1w, dA, s);
     FMBYM_LAUNCH(kKBRotateAdj, kb_rotate_adj<N>, dim3(B * (N / kRotTY) * (N / kRotTX)), dim3(256), s, dgp,
                  saved, dgr);
