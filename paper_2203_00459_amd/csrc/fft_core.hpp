@@ -1,4 +1,4 @@
-// Device-side building blocks of the search kernels: complex helpers, radix-2/3/4/8
+// Device-side building blocks of the search kernels: complex helpers, radix-2/3/4/6/8/12
 // butterflies and a Stockham autosort FFT over one "line" of L = 2^a or 3 2^a
 // points held cooperatively by T threads, each owning E = L/T elements in
 // registers.  Lines exchange data between stages through a padded LDS buffer
@@ -82,6 +82,51 @@ __device__ __forceinline__ void dft3(float2& a, float2& b, float2& c) {
     c = csub(m, r);
 }
 
+// 12 = 4 x 3: DFT4 over n1 of v[3 n1 + n2] for each n2, twiddles W12^(n2 k1),
+// then DFT3 over n2 for each k1 gives X[k1 + 4 k2].
+__device__ __forceinline__ void dft12(float2 (&v)[12]) {
+    const float h = 0.86602540378443864676f;   // sqrt(3) / 2
+#pragma unroll
+    for (int n2 = 0; n2 < 3; ++n2) dft4(v[n2], v[3 + n2], v[6 + n2], v[9 + n2]);
+    // row n2 = 1: W12^1, W12^2, W12^3 = -i; row n2 = 2: W12^2, W12^4, W12^6 = -1
+    const float2 w1 = make_float2(h, -0.5f), w2 = make_float2(0.5f, -h), w4 = make_float2(-0.5f, -h);
+    v[4] = cmul(v[4], w1);
+    v[7] = cmul(v[7], w2);
+    v[10] = mul_negi(v[10]);
+    v[5] = cmul(v[5], w2);
+    v[8] = cmul(v[8], w4);
+    v[11] = make_float2(-v[11].x, -v[11].y);
+    float2 x[12];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        float2 a = v[3 * k1], b = v[3 * k1 + 1], c = v[3 * k1 + 2];
+        dft3(a, b, c);
+        x[k1] = a;
+        x[k1 + 4] = b;
+        x[k1 + 8] = c;
+    }
+#pragma unroll
+    for (int k = 0; k < 12; ++k) v[k] = x[k];
+}
+
+// 6 = 3 x 2: DFT3 over n1 of v[2 n1 + n2] for each n2, twiddles W6^(n2 k1), then
+// DFT2 over n2 for each k1 gives X[k1 + 3 k2].
+__device__ __forceinline__ void dft6(float2 (&v)[6]) {
+    const float h = 0.86602540378443864676f;
+    dft3(v[0], v[2], v[4]);
+    dft3(v[1], v[3], v[5]);
+    v[3] = cmul(v[3], make_float2(0.5f, -h));
+    v[5] = cmul(v[5], make_float2(-0.5f, -h));
+    float2 x[6];
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1) {
+        x[k1] = cadd(v[2 * k1], v[2 * k1 + 1]);
+        x[k1 + 3] = csub(v[2 * k1], v[2 * k1 + 1]);
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v[k] = x[k];
+}
+
 template <int R>
 __device__ __forceinline__ void dft_r(float2 (&v)[R]);
 template <>
@@ -92,6 +137,10 @@ template <>
 __device__ __forceinline__ void dft_r<4>(float2 (&v)[4]) { dft4(v[0], v[1], v[2], v[3]); }
 template <>
 __device__ __forceinline__ void dft_r<8>(float2 (&v)[8]) { dft8(v); }
+template <>
+__device__ __forceinline__ void dft_r<6>(float2 (&v)[6]) { dft6(v); }
+template <>
+__device__ __forceinline__ void dft_r<12>(float2 (&v)[12]) { dft12(v); }
 
 // LDS layouts of a line (separate re/im planes, 32 banks of 4 bytes).  The
 // Stockham stages read unit-stride and write stride-Ns patterns, the mirror
@@ -133,21 +182,27 @@ constexpr int pow2_part(int x) { return (x & (x - 1)) == 0 ? x : pow2_part(x / 3
 constexpr int max_pow2_radix(int E) { return E % 8 == 0 ? 8 : (E % 4 == 0 ? 4 : 2); }
 
 // Radix plan of a length-L line with E elements per thread: power-of-two
-// stages of radix min(max_pow2_radix(E), what is left of 2^a), then one radix-3
-// stage for lengths 3 2^a.  Every radix divides E.
+// stages of radix min(max_pow2_radix(E), what is left of 2^a); for lengths
+// 3 2^a the last stage takes the factor 3 together with what is left of 2^a
+// when that is 6 or 12 and E allows it (one LDS exchange fewer than a separate
+// radix-3 stage), else a radix-3 stage of its own.  Every radix divides E.
+constexpr int stage_radix(int left, int E) {
+    return (left == 6 || left == 12) && E % left == 0
+               ? left
+               : (pow2_part(left) > 1 ? (pow2_part(left) < max_pow2_radix(E) ? pow2_part(left) : max_pow2_radix(E))
+                                      : left);
+}
 template <int L, int E, int S>
 struct StageRadix {
     static constexpr int done = StageRadix<L, E, S - 1>::done * StageRadix<L, E, S - 1>::R;
     static constexpr int left = L / done;
-    static constexpr int p2 = pow2_part(left);
-    static constexpr int R = p2 > 1 ? (p2 < max_pow2_radix(E) ? p2 : max_pow2_radix(E)) : left;
+    static constexpr int R = stage_radix(left, E);
 };
 template <int L, int E>
 struct StageRadix<L, E, 0> {
     static constexpr int done = 1;
     static constexpr int left = L;
-    static constexpr int p2 = pow2_part(L);
-    static constexpr int R = p2 > 1 ? (p2 < max_pow2_radix(E) ? p2 : max_pow2_radix(E)) : L;
+    static constexpr int R = stage_radix(L, E);
 };
 template <int L, int E, int S = 0, bool END = (StageRadix<L, E, S>::done == L)>
 struct NumStagesFrom {
