@@ -2,7 +2,9 @@
 scratch array) against fmbym_search on the same inputs, through the C ABI: the
 same kernels on the same values, so every output must agree bit for bit.  Two
 calls in a row, the second with a smaller input, so the second reads an array
-that still holds the first call's contents."""
+that still holds the first call's contents; then smaller and other plans on
+the same array (256 px masked, 128 px, the 255 px odd side masked, standardised
+logits)."""
 import numpy as np
 import pytest
 import torch
@@ -65,6 +67,14 @@ def test_noalloc_equals_search_twice_smaller_second(split):
     s3 = fmbym.Search(max_batch=1, **workloads.search_kwargs("pair128"))
     _compare(s3, *_inputs("pair128", 1, False), "128 B=1")
     s3.close()
+    # the paper's odd side (its own kernels and workspace layout), masked, and a
+    # plan with a reading flag whose scores pass through the workspace
+    s4 = fmbym.Search(max_batch=2, **workloads.search_kwargs("paper255"))
+    _compare(s4, *_inputs("paper255", 2, True), "255 B=2 masked")
+    s4.close()
+    s5 = fmbym.Search(max_batch=2, **dict(workloads.search_kwargs("batch256"), zscore=True))
+    _compare(s5, *_inputs("batch256", 2, False, start=3), "256 B=2 zscore")
+    s5.close()
 
 
 def test_noalloc_rejects_a_batch_beyond_the_array():
