@@ -132,8 +132,18 @@ __device__ __forceinline__ void store_patch(u32x4* patch, const u32x4 (&v)[NL]) 
 // out = relu(z scale + shift) in BF16 with the running statistics' scale and
 // shift (inference; no z, no partials).
 __host__ __device__ constexpr int co_chunk(int cout) { return cout > 96 ? 64 : cout; }
+// A launch with few tiles (the deep levels) takes its output channels in
+// smaller chunks, half or a quarter of co_chunk down to 16, until it has at
+// least kConvMinBlocks blocks: more blocks to fill the GPU, each staging the
+// same input patch.
+constexpr int kConvMinBlocks = 512;
+inline int conv_chunk(int cout, int blocks) {
+    int co = co_chunk(cout);
+    for (int k = 0; k < 2 && co % 32 == 0 && blocks * (cout / co) < kConvMinBlocks; ++k) co /= 2;
+    return co;
+}
 
-template <int CIN, int COUT, int MODE>
+template <int CIN, int COUT, int MODE, int CO_ = co_chunk(COUT)>
 __global__ __launch_bounds__(256) void k_conv3x3(const bf16* __restrict__ in, const bf16* __restrict__ w,
                                                  void* __restrict__ outv, float* __restrict__ part,
                                                  int S, BnInfer bn, int tpb, int tiles) {
@@ -141,7 +151,7 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16* __restrict__ in, co
     OutT* __restrict__ out = static_cast<OutT*>(outv);
     constexpr bool STATS = MODE == kConvTrain;
     constexpr int CC = chunk_ch(CIN), NCH = CIN / CC, G = CC / 8, NQ = 9 * G, NS = (NQ + 3) / 4;
-    constexpr int CO = co_chunk(COUT), NT = pad16(CO) / 16, K = 9 * CIN;
+    constexpr int CO = CO_, NT = pad16(CO) / 16, K = 9 * CIN;
     static_assert(COUT % CO == 0, "whole output-channel chunks");
     const int co0 = blockIdx.y * CO;
     static_assert(CIN % 8 == 0 && CIN % CC == 0, "input channels in groups of 8");
@@ -299,10 +309,10 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16* __restrict__ in, co
 // fragments come from the same two aligned LDS reads (the kx shift is a
 // 16-bit funnel shift).  With fewer than 4 groups the 4 waves split the
 // pixel steps instead and their accumulators are summed in wave order.
-template <int CIN, int COUT>
+template <int CIN, int COUT, int CO_ = co_chunk(COUT)>
 struct WgradGeo {
     static constexpr int CC = chunk_ch(CIN), NCH = CIN / CC;
-    static constexpr int CO = co_chunk(COUT);   // output channels per block (blockIdx.y chunks)
+    static constexpr int CO = CO_;   // output channels per block (blockIdx.y chunks)
     static constexpr int MT = pad16(CO) / 16, NB = 3 * CC, NG = (NB + 15) / 16;
     static constexpr int WG = NG >= 4 ? 4 : 1;            // waves across groups
     static constexpr int GPW = (NG + WG - 1) / WG;        // groups per wave
@@ -321,10 +331,10 @@ __host__ __device__ constexpr int wg_rows(int /*S*/) { return kConvSide + 2; }
 // M = output channels, K = pixels (8 per lane: one tile row), N = (tap, ci).
 // LDS: the chunk's dz tile transposed [CO][256], the input patch transposed
 // per channel [CC][rows][pitch] (pixels contiguous), and the wave-reduction area.
-template <int CIN, int COUT>
+template <int CIN, int COUT, int CO_ = co_chunk(COUT)>
 __global__ __launch_bounds__(256) void k_wgrad(const bf16* __restrict__ dz, const bf16* __restrict__ in,
                                                float* __restrict__ part, int S, int tpb, int tiles) {
-    using Geo = WgradGeo<CIN, COUT>;
+    using Geo = WgradGeo<CIN, COUT, CO_>;
     constexpr int CC = Geo::CC, CO = Geo::CO, MT = Geo::MT, NB = Geo::NB, NG = Geo::NG, WG = Geo::WG,
                   GPW = Geo::GPW, KPW = Geo::KPW;
     constexpr int K = 9 * CIN;
@@ -1146,25 +1156,48 @@ size_t colsum_tmp_floats(int n) { return (size_t)kColChunks * n; }
     X(64, 128) X(128, 128) X(128, 256) X(256, 256) X(384, 128) X(192, 64)                           \
     X(128, 64) X(256, 128) X(128, 384) X(64, 192)
 
+template <int CI, int COUT, int CO>
+void launch_conv_co(int mode, dim3 grid, size_t lds, hipStream_t s, const bf16* in, const bf16* w, void* out,
+                    float* part, int S, const BnInfer& bn, int tpb, int tiles) {
+    if (mode == kConvTrain)
+        FMBYM_LAUNCH_LDS(kMConvFwd, (k_conv3x3<CI, COUT, kConvTrain, CO>), grid, dim3(256), lds, s, in, w, out, part,
+                         S, bn, tpb, tiles);
+    else if (mode == kConvInfer)
+        FMBYM_LAUNCH_LDS(kMConvFwd, (k_conv3x3<CI, COUT, kConvInfer, CO>), grid, dim3(256), lds, s, in, w, out, part,
+                         S, bn, tpb, tiles);
+    else
+        FMBYM_LAUNCH_LDS(kMConvDgrad, (k_conv3x3<CI, COUT, kConvDgrad, CO>), grid, dim3(256), lds, s, in, w, out,
+                         part, S, bn, tpb, tiles);
+}
+
 bool launch_conv3x3(int cin, int cout, int mode, const bf16* in, const bf16* w, void* out, float* part,
                     const BnInfer& bn, int images, int S, hipStream_t s) {
-    const int tiles = conv_blocks(images, S), tpb = conv_tpb(tiles);
-    const dim3 grid(conv_part_blocks(images, S), cout / co_chunk(cout)), block(256);
+    const int tiles = conv_blocks(images, S), tpb = conv_tpb(tiles), nb = conv_part_blocks(images, S);
+    const int co = conv_chunk(cout, nb);
+    const dim3 grid(nb, cout / co);
     const int elem = mode == kConvDgrad ? 4 : 2;
     size_t lds = patch_bytes(cin, S);
-    if (out_staged(co_chunk(cout), elem)) lds = std::max(lds, out_tile_bytes(co_chunk(cout), elem));
+    if (out_staged(co, elem)) lds = std::max(lds, out_tile_bytes(co, elem));
     if (lds + 4 * 2 * 96 * sizeof(float) > kLdsLimit) return false;
 #define FMBYM_CONV_CASE(CI, CO)                                                                   \
     if (cin == CI && cout == CO) {                                                                \
-        if (mode == kConvTrain)                                                                   \
-            FMBYM_LAUNCH_LDS(kMConvFwd, (k_conv3x3<CI, CO, kConvTrain>), grid, block, lds, s, in, w, out, part, \
-                             S, bn, tpb, tiles);                                                  \
-        else if (mode == kConvInfer)                                                              \
-            FMBYM_LAUNCH_LDS(kMConvFwd, (k_conv3x3<CI, CO, kConvInfer>), grid, block, lds, s, in, w, out, part, \
-                             S, bn, tpb, tiles);                                                  \
-        else                                                                                      \
-            FMBYM_LAUNCH_LDS(kMConvDgrad, (k_conv3x3<CI, CO, kConvDgrad>), grid, block, lds, s, in, w, out, \
-                             part, S, bn, tpb, tiles);                                            \
+        constexpr int C0 = co_chunk(CO);                                                          \
+        if (co == C0)                                                                             \
+            launch_conv_co<CI, CO, C0>(mode, grid, lds, s, in, w, out, part, S, bn, tpb, tiles);  \
+        else if constexpr (C0 % 32 == 0) {                                                        \
+            if (co == C0 / 2)                                                                     \
+                launch_conv_co<CI, CO, C0 / 2>(mode, grid, lds, s, in, w, out, part, S, bn, tpb, tiles); \
+            else if constexpr (C0 % 64 == 0) {                                                    \
+                if (co == C0 / 4)                                                                 \
+                    launch_conv_co<CI, CO, C0 / 4>(mode, grid, lds, s, in, w, out, part, S, bn, tpb, tiles); \
+                else                                                                              \
+                    return false;                                                                 \
+            } else {                                                                              \
+                return false;                                                                     \
+            }                                                                                     \
+        } else {                                                                                  \
+            return false;                                                                         \
+        }                                                                                         \
         return true;                                                                              \
     }
     FMBYM_CONV_PAIRS(FMBYM_CONV_CASE)
@@ -1180,24 +1213,41 @@ void wgrad_grid(int images, int S, int* blocks, int* tiles_per_block) {
     *blocks = (tiles + tpb - 1) / tpb;
 }
 
+template <int CI, int COUT, int CO>
+bool launch_wgrad_co(const bf16* dz, const bf16* in, float* part, int S, int nb, int tpb, int tiles, hipStream_t s) {
+    using Geo = WgradGeo<CI, COUT, CO>;
+    const size_t lds = (size_t)Geo::CO * kConvTile * 2 + (size_t)Geo::CC * wg_rows(S) * wg_pitch(S) * 2 + Geo::red_bytes;
+    if (lds > kLdsLimit) return false;
+    FMBYM_LAUNCH_LDS(kMWgrad, (k_wgrad<CI, COUT, CO>), dim3(nb, COUT / CO), dim3(256), lds, s, dz, in, part, S, tpb,
+                     tiles);
+    return true;
+}
+
 bool launch_wgrad(int cin, int cout, const bf16* dz, const bf16* in, float* part, float* tmp, float* dw,
                   int real_cin, int images, int S, hipStream_t s) {
     int nb, tpb;
     wgrad_grid(images, S, &nb, &tpb);
     const int tiles = conv_blocks(images, S);
     const int n = cout * 9 * cin;
+    const int co = conv_chunk(cout, nb);
 #define FMBYM_WGRAD_CASE(CI, COUT_)                                                                  \
     if (cin == CI && cout == COUT_) {                                                                \
-        using Geo = WgradGeo<CI, COUT_>;                                                             \
-        const size_t lds = (size_t)Geo::CO * kConvTile * 2 + (size_t)Geo::CC * wg_rows(S) * wg_pitch(S) * 2 + \
-                           Geo::red_bytes;                                                        \
-        if (lds > kLdsLimit) return false;                                                        \
-        FMBYM_LAUNCH_LDS(kMWgrad, (k_wgrad<CI, COUT_>), dim3(nb, COUT_ / Geo::CO), dim3(256), lds, s, dz, in, part, S, \
-                         tpb, tiles);                                                             \
-        const int nbc = colsum1(kMWgrad, part, nb, (long long)n, n, tmp, s);                       \
-        FMBYM_LAUNCH(kMWgrad, k_colsum2, dim3(grid_for(n, 256)), dim3(256), s, tmp, nbc, n, 0, n, dw, \
-                     real_cin, cin);                                                              \
-        return true;                                                                              \
+        constexpr int C0 = co_chunk(COUT_);                                                          \
+        bool ok = false;                                                                             \
+        if (co == C0)                                                                                \
+            ok = launch_wgrad_co<CI, COUT_, C0>(dz, in, part, S, nb, tpb, tiles, s);                 \
+        else if constexpr (C0 % 32 == 0) {                                                           \
+            if (co == C0 / 2)                                                                        \
+                ok = launch_wgrad_co<CI, COUT_, C0 / 2>(dz, in, part, S, nb, tpb, tiles, s);         \
+            else if constexpr (C0 % 64 == 0) {                                                       \
+                if (co == C0 / 4) ok = launch_wgrad_co<CI, COUT_, C0 / 4>(dz, in, part, S, nb, tpb, tiles, s); \
+            }                                                                                        \
+        }                                                                                            \
+        if (!ok) return false;                                                                       \
+        const int nbc = colsum1(kMWgrad, part, nb, (long long)n, n, tmp, s);                         \
+        FMBYM_LAUNCH(kMWgrad, k_colsum2, dim3(grid_for(n, 256)), dim3(256), s, tmp, nbc, n, 0, n, dw,   \
+                     real_cin, cin);                                                                 \
+        return true;                                                                                 \
     }
     FMBYM_CONV_PAIRS(FMBYM_WGRAD_CASE)
 #undef FMBYM_WGRAD_CASE
