@@ -35,8 +35,15 @@ static_assert(kConvSide * kConvSide == kConvTile, "one conv tile per block");
 // Pixels of a conv tile's input patch, (rows + 2) x (cols + 2).
 __host__ __device__ constexpr int patch_pixels(int /*S*/) { return (kConvSide + 2) * (kConvSide + 2); }
 
-// Dynamic LDS bytes of the staged patch (G + 1 groups of 16 bytes per pixel).
-constexpr size_t patch_bytes(int cin, int S) { return (size_t)patch_pixels(S) * (chunk_ch(cin) / 8 + 1) * 16; }
+// Dynamic LDS bytes of the staged patch (patch_pitch(G) groups of 16 bytes per pixel).
+// Pixel pitch of the staged patch in 16-byte groups: the smallest odd count that
+// holds the pixel's G groups, so that eight lanes reading eight consecutive
+// pixels at a stride of an odd number of 16-byte slots touch eight different
+// slots of every 128 bytes of banks.
+__host__ __device__ constexpr int patch_pitch(int G) { return G | 1; }
+constexpr size_t patch_bytes(int cin, int S) {
+    return (size_t)patch_pixels(S) * patch_pitch(chunk_ch(cin) / 8) * 16;
+}
 
 constexpr size_t kLdsLimit = 64 * 1024;
 
@@ -77,7 +84,7 @@ __device__ __forceinline__ TileGeo conv_tile_geo(int blk, int S) {
 
 // Stage channels [c0, c0 + 8G) of the tile's input patch (one pixel of halo on
 // every side, zeros outside the image) as G groups of 8 channels per pixel at a
-// pitch of G + 1 groups.
+// pitch of patch_pitch(G) groups.
 template <int CIN, int G>
 __device__ __forceinline__ void stage_patch(const bf16* __restrict__ in, u32x4* patch, const TileGeo& t,
                                             int S, int c0) {
@@ -89,7 +96,7 @@ __device__ __forceinline__ void stage_patch(const bf16* __restrict__ in, u32x4* 
         u32x4 v = {0u, 0u, 0u, 0u};
         if (y >= 0 && y < S && x >= 0 && x < S)
             v = *(const u32x4*)(base + ((size_t)y * S + x) * CIN + c0 + 8 * cg);
-        patch[q * (G + 1) + cg] = v;
+        patch[q * patch_pitch(G) + cg] = v;
     }
 }
 
@@ -115,7 +122,7 @@ __device__ __forceinline__ void store_patch(u32x4* patch, const u32x4 (&v)[NL]) 
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
         const int it = threadIdx.x + 256 * k;
-        if (it < NE) patch[(it / G) * (G + 1) + it % G] = v[k];
+        if (it < NE) patch[(it / G) * patch_pitch(G) + it % G] = v[k];
     }
 }
 
@@ -220,7 +227,7 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16* __restrict__ in, co
                 u32x4 a[4], b[NT];
 #pragma unroll
                 for (int mi = 0; mi < 4; ++mi)
-                    a[mi] = valid ? patch[((prow[mi] + ky) * W + pcol[mi] + kx) * (G + 1) + cg] : zero;
+                    a[mi] = valid ? patch[((prow[mi] + ky) * W + pcol[mi] + kx) * patch_pitch(G) + cg] : zero;
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) {
                     const int co = nt * 16 + r16;
@@ -324,12 +331,18 @@ struct WgradGeo {
 // (a B fragment reads 10 pixels from an 8-pixel-aligned column, 16-byte aligned).
 __host__ __device__ constexpr int wg_pitch(int /*S*/) { return kConvSide + 8; }
 __host__ __device__ constexpr int wg_rows(int /*S*/) { return kConvSide + 2; }
+// LDS strides of the weight gradient's staged operands, in bf16 elements: the
+// dz tile's channel rows and the patch's channel planes are padded to an odd
+// number of 16-byte slots, so that the lanes of a fragment read (consecutive
+// channels) fall on different slots of every 128 bytes of banks.
+constexpr int kDztPitch = kConvTile + 8;
+__host__ __device__ constexpr int wg_plane(int S) { return wg_rows(S) * wg_pitch(S) + 8; }
 
 // Weight gradient over `tpb` consecutive tiles per block (blockIdx.x) for the
 // output channels of chunk blockIdx.y:
 // part[block][co][tap CIN + ci] = sum over the tiles' pixels of dz[p][co] in[p + tap][ci].
 // M = output channels, K = pixels (8 per lane: one tile row), N = (tap, ci).
-// LDS: the chunk's dz tile transposed [CO][256], the input patch transposed
+// LDS: the chunk's dz tile transposed [CO][kDztPitch], the input patch transposed
 // per channel [CC][rows][pitch] (pixels contiguous), and the wave-reduction area.
 template <int CIN, int COUT, int CO_ = co_chunk(COUT)>
 __global__ __launch_bounds__(256) void k_wgrad(const bf16* __restrict__ dz, const bf16* __restrict__ in,
@@ -341,10 +354,10 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16* __restrict__ dz, cons
     static_assert(COUT % CO == 0 && CO % 8 == 0, "whole output-channel chunks of 8-channel groups");
     const int co0 = blockIdx.y * CO;
     extern __shared__ u32x4 smem[];
-    bf16* dzt = reinterpret_cast<bf16*>(smem);                       // [CO][256]
-    bf16* pt = dzt + CO * kConvTile;                                 // [CC][rows][pitch]
-    const int PW = wg_pitch(S), PRW = wg_rows(S);
-    f32x4* red = reinterpret_cast<f32x4*>(pt + (size_t)CC * PRW * PW);
+    bf16* dzt = reinterpret_cast<bf16*>(smem);                       // [CO][kDztPitch]
+    bf16* pt = dzt + CO * kDztPitch;                                 // [CC][plane: rows x pitch]
+    const int PW = wg_pitch(S), PRW = wg_rows(S), PL = wg_plane(S);
+    f32x4* red = reinterpret_cast<f32x4*>(pt + (size_t)CC * PL);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, r16 = lane & 15;
     const u32x4 zero = {0u, 0u, 0u, 0u};
@@ -369,7 +382,7 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16* __restrict__ dz, cons
                 const size_t pix = img_base + (size_t)(t.y0 + p / t.pc) * S + t.x0 + p % t.pc;
                 const bf16x8 v = __builtin_bit_cast(bf16x8, *(const u32x4*)(dz + pix * COUT + co0 + 8 * cg));
 #pragma unroll
-                for (int j = 0; j < 8; ++j) dzt[(8 * cg + j) * kConvTile + p] = v[j];
+                for (int j = 0; j < 8; ++j) dzt[(8 * cg + j) * kDztPitch + p] = v[j];
             }
             // input patch of the chunk, transposed per channel
             {
@@ -384,7 +397,7 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16* __restrict__ dz, cons
                         u = *(const u32x4*)(base + ((size_t)y * S + x) * CIN + c0 + 8 * cg);
                     const bf16x8 v = __builtin_bit_cast(bf16x8, u);
 #pragma unroll
-                    for (int j = 0; j < 8; ++j) pt[((size_t)(8 * cg + j) * PRW + r) * PW + c] = v[j];
+                    for (int j = 0; j < 8; ++j) pt[(size_t)(8 * cg + j) * PL + r * PW + c] = v[j];
                 }
             }
             __syncthreads();
@@ -397,7 +410,7 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16* __restrict__ dz, cons
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt) {
                     const int co = mt * 16 + r16;
-                    a[mt] = co < CO ? *(const u32x4*)(dzt + co * kConvTile + p0) : zero;
+                    a[mt] = co < CO ? *(const u32x4*)(dzt + co * kDztPitch + p0) : zero;
                 }
 #pragma unroll
                 for (int gi = 0; gi < GPW; ++gi) {
@@ -407,7 +420,7 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16* __restrict__ dz, cons
                     u32x4 b0 = zero, b1 = zero, b2 = zero;
                     if (bc < NB) {
                         const int ky = bc / CC, ci = bc % CC;
-                        const bf16* src = pt + ((size_t)ci * PRW + row + ky) * PW + col;
+                        const bf16* src = pt + (size_t)ci * PL + (row + ky) * PW + col;
                         const u32x4 w = *(const u32x4*)src;
                         const unsigned w4 = *(const unsigned*)(src + 8);
                         b0 = w;
@@ -1216,7 +1229,7 @@ void wgrad_grid(int images, int S, int* blocks, int* tiles_per_block) {
 template <int CI, int COUT, int CO>
 bool launch_wgrad_co(const bf16* dz, const bf16* in, float* part, int S, int nb, int tpb, int tiles, hipStream_t s) {
     using Geo = WgradGeo<CI, COUT, CO>;
-    const size_t lds = (size_t)Geo::CO * kConvTile * 2 + (size_t)Geo::CC * wg_rows(S) * wg_pitch(S) * 2 + Geo::red_bytes;
+    const size_t lds = (size_t)Geo::CO * kDztPitch * 2 + (size_t)Geo::CC * wg_plane(S) * 2 + Geo::red_bytes;
     if (lds > kLdsLimit) return false;
     FMBYM_LAUNCH_LDS(kMWgrad, (k_wgrad<CI, COUT, CO>), dim3(nb, COUT / CO), dim3(256), lds, s, dz, in, part, S, tpb,
                      tiles);
