@@ -81,9 +81,10 @@ FMBYM_API int fmbym_mask_pack(const fmbym_mask_desc* net, void* stream);
 FMBYM_API size_t fmbym_mask_activation_bytes(const fmbym_mask_desc* net, int32_t images, int32_t n);
 
 /* Forward pass: x [channels][images][n][n] scans -> mask [channels][images][n][n] in (0, 1).
- * act receives every saved activation; training != 0 uses batch statistics
- * and updates bn_running (required before fmbym_mask_bwd), training == 0 uses
- * bn_running. */
+ * training != 0 uses batch statistics, updates bn_running and saves in act
+ * every activation fmbym_mask_bwd reads (it is required before the backward);
+ * training == 0 uses bn_running and uses act as scratch only (the layer
+ * outputs, not the saved state of a training forward). */
 FMBYM_API int fmbym_mask_fwd(const fmbym_mask_desc* net, int32_t images, int32_t n, const float* x,
                              float* mask, void* act, size_t act_bytes, int training, void* stream);
 

@@ -35,15 +35,11 @@ static_assert(kConvSide * kConvSide == kConvTile, "one conv tile per block");
 // Pixels of a conv tile's input patch, (rows + 2) x (cols + 2).
 __host__ __device__ constexpr int patch_pixels(int /*S*/) { return (kConvSide + 2) * (kConvSide + 2); }
 
-// Dynamic LDS bytes of the staged patch (patch_pitch(G) groups of 16 bytes per pixel).
 // Pixel pitch of the staged patch in 16-byte groups: the smallest odd count that
 // holds the pixel's G groups, so that eight lanes reading eight consecutive
 // pixels at a stride of an odd number of 16-byte slots touch eight different
 // slots of every 128 bytes of banks.
 __host__ __device__ constexpr int patch_pitch(int G) { return G | 1; }
-constexpr size_t patch_bytes(int cin, int S) {
-    return (size_t)patch_pixels(S) * patch_pitch(chunk_ch(cin) / 8) * 16;
-}
 
 constexpr size_t kLdsLimit = 64 * 1024;
 
@@ -82,47 +78,151 @@ __device__ __forceinline__ TileGeo conv_tile_geo(int blk, int S) {
     return t;
 }
 
-// Stage channels [c0, c0 + 8G) of the tile's input patch (one pixel of halo on
-// every side, zeros outside the image) as G groups of 8 channels per pixel at a
-// pitch of patch_pitch(G) groups.
-template <int CIN, int G>
-__device__ __forceinline__ void stage_patch(const bf16* __restrict__ in, u32x4* patch, const TileGeo& t,
-                                            int S, int c0) {
-    const int W = t.pc + 2, npix = (t.pr + 2) * W;
-    const bf16* base = in + (size_t)t.img * S * S * CIN;
-    for (int it = threadIdx.x; it < npix * G; it += blockDim.x) {
-        const int q = it / G, cg = it % G;
-        const int y = t.y0 - 1 + q / W, x = t.x0 - 1 + q % W;
-        u32x4 v = {0u, 0u, 0u, 0u};
-        if (y >= 0 && y < S && x >= 0 && x < S)
-            v = *(const u32x4*)(base + ((size_t)y * S + x) * CIN + c0 + 8 * cg);
-        patch[q * patch_pitch(G) + cg] = v;
+// 1-D taps of the half-pixel bilinear x2 upsampling at output o of a length-n input.
+__device__ __forceinline__ void up_taps(int o, int n, int& i0, int& i1, float& w1) {
+    const float s = fmaxf(0.f, 0.5f * (float)o - 0.25f);
+    i0 = (int)s;
+    w1 = s - (float)i0;
+    i1 = min(i0 + 1, n - 1);
+}
+
+// Side of the low-resolution region an up-concat tile interpolates from: the
+// patch rows y0 - 1 .. y0 + 16 fall between low-resolution rows y0/2 - 1 and
+// y0/2 + 8 (the same for columns).
+constexpr int kUpSide = kConvSide / 2 + 2;
+
+// Dynamic LDS bytes of a convolution's staged input: the patch at a pitch of
+// patch_pitch(G) 16-byte groups per pixel, and for the up-concat input the
+// low-resolution entries after it.
+constexpr size_t conv_in_bytes(int cin, int src) {
+    return (size_t)patch_pixels(0) * patch_pitch(chunk_ch(cin) / 8) * 16 +
+           (src == kSrcUpCat ? (size_t)kUpSide * kUpSide * (chunk_ch(cin) / 8) * 16 : 0);
+}
+
+// Channel groups of the chunk starting at channel c0 that come from the
+// upsampled deeper activation (the first 2 CIN / 3 channels of an up-concat
+// input); the chunk's remaining groups come from the skip activation.
+template <int CIN, int SRC>
+__device__ __forceinline__ int up_groups(int c0, int G) {
+    if constexpr (SRC != kSrcUpCat) {
+        return 0;
+    } else {
+        const int d = 2 * CIN / 3 / 8 - c0 / 8;
+        return d < 0 ? 0 : (d > G ? G : d);
     }
 }
 
-// The same patch through registers: load_patch issues the loads (thread t takes
-// entries t, t + 256, ...; zeros outside the image), store_patch writes them to LDS.
-template <int CIN, int G, int NL>
-__device__ __forceinline__ void load_patch(const bf16* __restrict__ in, u32x4 (&v)[NL], const TileGeo& t, int S) {
-    constexpr int W = kConvSide + 2, NE = W * W * G;
-    const bf16* base = in + (size_t)t.img * S * S * CIN;
-#pragma unroll
-    for (int k = 0; k < NL; ++k) {
-        const int it = threadIdx.x + 256 * k;
+// Entries of a tile's staged input for a chunk of G groups of 8 channels, dg
+// of them upsampled: plain and up-concat skip entries are (patch pixel, group)
+// pairs, scan entries one patch pixel each, and the up-concat input adds the
+// deeper activation's dg groups at the kUpSide^2 low-resolution pixels.
+template <int SRC>
+__host__ __device__ constexpr int stage_entries(int G, int dg) {
+    return SRC == kSrcScan ? (kConvSide + 2) * (kConvSide + 2)
+                           : (kConvSide + 2) * (kConvSide + 2) * (G - dg) + kUpSide * kUpSide * dg;
+}
+
+// Entry `it` of the staged input of the chunk at channel c0 (zeros outside
+// the image):
+//   plain: pixel it / G of the patch, group it % G of the input;
+//   scans: pixel it of the patch, the scan planes' values as FP32 bits in the
+//          first lanes (rounded to BF16 when stored, as channels 0 and 1);
+//   up-concat: first pixel q, group dg + k of the chunk from the skip
+//          activation for it = q (G - dg) + k, then the deeper activation's
+//          groups k < dg at low-resolution pixel q of the kUpSide^2 region.
+template <int CIN, int SRC>
+__device__ __forceinline__ u32x4 fetch_entry(const ConvSrc& src, const TileGeo& t, int S, int c0, int G, int dg,
+                                             int it) {
+    constexpr int W = kConvSide + 2;
+    u32x4 v = {0u, 0u, 0u, 0u};
+    if constexpr (SRC == kSrcPlain) {
         const int q = it / G, cg = it % G;
         const int y = t.y0 - 1 + q / W, x = t.x0 - 1 + q % W;
-        v[k] = u32x4{0u, 0u, 0u, 0u};
-        if (it < NE && y >= 0 && y < S && x >= 0 && x < S)
-            v[k] = *(const u32x4*)(base + ((size_t)y * S + x) * CIN + 8 * cg);
+        if (y >= 0 && y < S && x >= 0 && x < S)
+            v = *(const u32x4*)(src.in + (((size_t)t.img * S + y) * S + x) * CIN + c0 + 8 * cg);
+    } else if constexpr (SRC == kSrcScan) {
+        const int y = t.y0 - 1 + it / W, x = t.x0 - 1 + it % W;
+        if (y >= 0 && y < S && x >= 0 && x < S) {
+            const size_t p = (size_t)y * S + x;
+            if (src.x_tab) {
+                v[0] = __float_as_uint(src.x_tab[t.img][p]);
+            } else {
+                const size_t pi = (size_t)t.img * S * S + p;
+                v[0] = __float_as_uint(src.x[pi]);
+                if (src.ch > 1) v[1] = __float_as_uint(src.x[src.plane + pi]);
+            }
+        }
+    } else {
+        constexpr int CD = 2 * CIN / 3, CE = CIN - CD;
+        const int sg = G - dg, nskip = W * W * sg;
+        if (it < nskip) {
+            const int q = it / sg, k = it % sg;
+            const int y = t.y0 - 1 + q / W, x = t.x0 - 1 + q % W;
+            if (y >= 0 && y < S && x >= 0 && x < S)
+                v = *(const u32x4*)(src.skip + (((size_t)t.img * S + y) * S + x) * CE + c0 + 8 * (dg + k) - CD);
+        } else {
+            const int j = it - nskip, q = j / dg, k = j % dg, H = S / 2;
+            const int ly = t.y0 / 2 - 1 + q / kUpSide, lx = t.x0 / 2 - 1 + q % kUpSide;
+            if (ly >= 0 && ly < H && lx >= 0 && lx < H)
+                v = *(const u32x4*)(src.in + (((size_t)t.img * H + ly) * H + lx) * CD + c0 + 8 * k);
+        }
+    }
+    return v;
+}
+
+// Write entry `it` to LDS: patch pixel q at patch[q * pitch + group]; the
+// up-concat input's low-resolution entries after the patch.
+template <int SRC>
+__device__ __forceinline__ void put_entry(u32x4* patch, int pitch, int G, int dg, int it, u32x4 v) {
+    constexpr int W = kConvSide + 2;
+    if constexpr (SRC == kSrcPlain) {
+        patch[(it / G) * pitch + it % G] = v;
+    } else if constexpr (SRC == kSrcScan) {
+        bf16x8 o;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) o[j] = (bf16)0.f;
+        o[0] = (bf16)__uint_as_float(v[0]);
+        o[1] = (bf16)__uint_as_float(v[1]);
+        patch[it * pitch] = __builtin_bit_cast(u32x4, o);
+    } else {
+        const int sg = G - dg, nskip = W * W * sg;
+        if (it < nskip)
+            patch[(it / sg) * pitch + dg + it % sg] = v;
+        else
+            patch[W * W * pitch + (it - nskip)] = v;
     }
 }
-template <int G, int NL>
-__device__ __forceinline__ void store_patch(u32x4* patch, const u32x4 (&v)[NL]) {
-    constexpr int W = kConvSide + 2, NE = W * W * G;
+
+// The up-concat input's first dg groups of every patch pixel: the bilinear x2
+// upsampling of the low-resolution entries staged after the patch (the
+// arithmetic of the upsampling layer, rounded to BF16).
+__device__ __forceinline__ void up_interp(u32x4* patch, int pitch, int dg, const TileGeo& t, int S) {
+    constexpr int W = kConvSide + 2;
+    const u32x4* lr = patch + W * W * pitch;
+    const int H = S / 2, ly0 = t.y0 / 2 - 1, lx0 = t.x0 / 2 - 1;
+    for (int it = threadIdx.x; it < W * W * dg; it += blockDim.x) {
+        const int q = it / dg, k = it % dg;
+        const int y = t.y0 - 1 + q / W, x = t.x0 - 1 + q % W;
+        u32x4 v = {0u, 0u, 0u, 0u};
+        if (y >= 0 && y < S && x >= 0 && x < S) {
+            int y0, y1, x0, x1;
+            float wy, wx;
+            up_taps(y, H, y0, y1, wy);
+            up_taps(x, H, x0, x1, wx);
+            const bf16x8 a = as_bf16x8(lr[((y0 - ly0) * kUpSide + x0 - lx0) * dg + k]);
+            const bf16x8 b = as_bf16x8(lr[((y0 - ly0) * kUpSide + x1 - lx0) * dg + k]);
+            const bf16x8 c = as_bf16x8(lr[((y1 - ly0) * kUpSide + x0 - lx0) * dg + k]);
+            const bf16x8 d = as_bf16x8(lr[((y1 - ly0) * kUpSide + x1 - lx0) * dg + k]);
+            bf16x8 o;
 #pragma unroll
-    for (int k = 0; k < NL; ++k) {
-        const int it = threadIdx.x + 256 * k;
-        if (it < NE) patch[(it / G) * patch_pitch(G) + it % G] = v[k];
+            for (int j = 0; j < 8; ++j) {
+                const float top = (1.f - wx) * (float)a[j] + wx * (float)b[j];
+                const float bot = (1.f - wx) * (float)c[j] + wx * (float)d[j];
+                o[j] = (bf16)((1.f - wy) * top + wy * bot);
+            }
+            v = __builtin_bit_cast(u32x4, o);
+        }
+        patch[q * pitch + k] = v;
     }
 }
 
@@ -150,10 +250,10 @@ inline int conv_chunk(int cout, int blocks) {
     return co;
 }
 
-template <int CIN, int COUT, int MODE, int CO_ = co_chunk(COUT)>
-__global__ __launch_bounds__(256) void k_conv3x3(const bf16* __restrict__ in, const bf16* __restrict__ w,
+template <int CIN, int COUT, int MODE, int CO_ = co_chunk(COUT), int SRC = kSrcPlain, bool POOL = false>
+__global__ __launch_bounds__(256) void k_conv3x3(ConvSrc src, const bf16* __restrict__ w,
                                                  void* __restrict__ outv, float* __restrict__ part,
-                                                 int S, BnInfer bn, int tpb, int tiles) {
+                                                 bf16* __restrict__ pool, int S, BnInfer bn, int tpb, int tiles) {
     using OutT = typename std::conditional<MODE == kConvDgrad, float, bf16>::type;
     OutT* __restrict__ out = static_cast<OutT*>(outv);
     constexpr bool STATS = MODE == kConvTrain;
@@ -162,7 +262,12 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16* __restrict__ in, co
     static_assert(COUT % CO == 0, "whole output-channel chunks");
     const int co0 = blockIdx.y * CO;
     static_assert(CIN % 8 == 0 && CIN % CC == 0, "input channels in groups of 8");
-    extern __shared__ u32x4 patch[];   // patch_bytes(CIN, S) or the staged output tile
+    static_assert(SRC == kSrcPlain || MODE == kConvInfer, "fused inputs in inference only");
+    static_assert(SRC != kSrcScan || CIN == 8, "scans feed the 8-channel first convolution");
+    static_assert(SRC != kSrcUpCat || CIN % 24 == 0, "up-concat input: 2 CIN / 3 upsampled, CIN / 3 skip channels");
+    static_assert(!POOL || (MODE == kConvInfer && out_staged(CO_, 2)), "pooling from the staged output tile");
+    constexpr int PITCH = patch_pitch(G);
+    extern __shared__ u32x4 patch[];   // conv_lds(CIN, SRC) or the staged output tile
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, r16 = lane & 15;
     constexpr int W = kConvSide + 2;
@@ -176,10 +281,20 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16* __restrict__ in, co
     // With the whole patch in one pass (CIN <= 32), the next tile's patch is
     // loaded into registers while the current one is computed.
     constexpr bool PREF = NCH == 1;
-    constexpr int PLOADS = (W * W * G + 255) / 256;
+    constexpr int DG0 = SRC == kSrcUpCat ? (2 * CIN / 3 / 8 < G ? 2 * CIN / 3 / 8 : G) : 0;
+    constexpr int NE = stage_entries<SRC>(G, DG0);   // entries of the one chunk (c0 = 0)
+    constexpr int PLOADS = (NE + 255) / 256;
     u32x4 pre[PREF ? PLOADS : 1];
     const int tile0 = blockIdx.x * tpb, tile1 = min(tiles, tile0 + tpb);
-    if constexpr (PREF) load_patch<CIN, G, PLOADS>(in, pre, conv_tile_geo(tile0, S), S);
+    auto prefetch = [&](int tile) {
+        const TileGeo tn = conv_tile_geo(tile, S);
+#pragma unroll
+        for (int k = 0; k < PLOADS; ++k) {
+            const int it = threadIdx.x + 256 * k;
+            pre[k] = it < NE ? fetch_entry<CIN, SRC>(src, tn, S, 0, G, DG0, it) : u32x4{0u, 0u, 0u, 0u};
+        }
+    };
+    if constexpr (PREF) prefetch(tile0);
     // inference: batch norm on the running statistics and ReLU on the BF16-rounded
     // output, the arithmetic of the training pass's statistics and BN + ReLU passes
     float csc[NT], csh[NT];
@@ -211,11 +326,22 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16* __restrict__ in, co
         for (int ch = 0; ch < NCH; ++ch) {
             const int c0 = ch * CC;
             __syncthreads();   // the previous patch (or staged output) has been read
+            const int dg = up_groups<CIN, SRC>(c0, G);
             if constexpr (PREF) {
-                store_patch<G, PLOADS>(patch, pre);
-                if (tile + 1 < tile1) load_patch<CIN, G, PLOADS>(in, pre, conv_tile_geo(tile + 1, S), S);
+#pragma unroll
+                for (int k = 0; k < PLOADS; ++k) {
+                    const int it = threadIdx.x + 256 * k;
+                    if (it < NE) put_entry<SRC>(patch, PITCH, G, DG0, it, pre[k]);
+                }
+                if (tile + 1 < tile1) prefetch(tile + 1);
             } else {
-                stage_patch<CIN, G>(in, patch, t, S, c0);
+                const int ne = stage_entries<SRC>(G, dg);
+                for (int it = threadIdx.x; it < ne; it += blockDim.x)
+                    put_entry<SRC>(patch, PITCH, G, dg, it, fetch_entry<CIN, SRC>(src, t, S, c0, G, dg, it));
+            }
+            if constexpr (SRC == kSrcUpCat) {
+                __syncthreads();
+                up_interp(patch, PITCH, dg, t, S);
             }
             __syncthreads();
 #pragma unroll
@@ -227,7 +353,7 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16* __restrict__ in, co
                 u32x4 a[4], b[NT];
 #pragma unroll
                 for (int mi = 0; mi < 4; ++mi)
-                    a[mi] = valid ? patch[((prow[mi] + ky) * W + pcol[mi] + kx) * patch_pitch(G) + cg] : zero;
+                    a[mi] = valid ? patch[((prow[mi] + ky) * W + pcol[mi] + kx) * PITCH + cg] : zero;
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) {
                     const int co = nt * 16 + r16;
@@ -281,6 +407,25 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16* __restrict__ in, co
                 const int p = it / VPP, q = it % VPP;
                 const size_t pix = img_base + (size_t)(t.y0 + p / t.pc) * S + t.x0 + p % t.pc;
                 *(u32x4*)(out + pix * COUT + co0 + q * VEC) = *(const u32x4*)(stage + p * TP + q * VEC);
+            }
+            if constexpr (POOL) {
+                // 2 x 2 max pooling of the tile into the next level's input [I][S/2][S/2][COUT]
+                const int H = S / 2;
+                for (int it = threadIdx.x; it < kConvTile / 4 * VPP; it += blockDim.x) {
+                    const int pp = it / VPP, q = it % VPP;
+                    const int py = pp / (kConvSide / 2), px = pp % (kConvSide / 2);
+                    const int p00 = 2 * py * kConvSide + 2 * px;
+                    const bf16x8 v00 = as_bf16x8(*(const u32x4*)(stage + p00 * TP + q * VEC));
+                    const bf16x8 v01 = as_bf16x8(*(const u32x4*)(stage + (p00 + 1) * TP + q * VEC));
+                    const bf16x8 v10 = as_bf16x8(*(const u32x4*)(stage + (p00 + kConvSide) * TP + q * VEC));
+                    const bf16x8 v11 = as_bf16x8(*(const u32x4*)(stage + (p00 + kConvSide + 1) * TP + q * VEC));
+                    bf16x8 o;
+#pragma unroll
+                    for (int j = 0; j < 8; ++j)
+                        o[j] = (bf16)fmaxf(fmaxf((float)v00[j], (float)v01[j]), fmaxf((float)v10[j], (float)v11[j]));
+                    const size_t pq = ((size_t)t.img * H + t.y0 / 2 + py) * H + t.x0 / 2 + px;
+                    *(u32x4*)(pool + pq * COUT + co0 + q * VEC) = __builtin_bit_cast(u32x4, o);
+                }
             }
         }
     }   // tiles
@@ -691,14 +836,6 @@ __global__ void k_maxpool(const bf16* __restrict__ in, bf16* __restrict__ out, i
     *(u32x4*)(out + q * C + 8 * cg) = __builtin_bit_cast(u32x4, o);
 }
 
-// 1-D taps of the half-pixel bilinear x2 upsampling at output o of a length-n input.
-__device__ __forceinline__ void up_taps(int o, int n, int& i0, int& i1, float& w1) {
-    const float s = fmaxf(0.f, 0.5f * (float)o - 0.25f);
-    i0 = (int)s;
-    w1 = s - (float)i0;
-    i1 = min(i0 + 1, n - 1);
-}
-
 __global__ void k_up_concat(const bf16* __restrict__ d, const bf16* __restrict__ e, bf16* __restrict__ cat,
                             int images, int S, int Cd, int Ce) {
     const int C = Cd + Ce, G8 = C / 8, H = S / 2;
@@ -733,24 +870,29 @@ __global__ void k_up_concat(const bf16* __restrict__ d, const bf16* __restrict__
 }
 
 // Output channel o of the head is plane o of mask (mask + o images S^2); w is [ch][C][3][3].
-__global__ void k_head_fwd(const bf16* __restrict__ a, const float* __restrict__ w,
-                           const float* __restrict__ b, float* __restrict__ mask, int images, int S,
-                           int C, int ch) {
+// One pixel per thread; the 256 pixels of a block share o (images S^2 is a
+// multiple of 256), so the weights are block-uniform loads.
+template <int C>
+__global__ __launch_bounds__(256) void k_head_fwd(const bf16* __restrict__ a, const float* __restrict__ w,
+                                                  const float* __restrict__ b, float* __restrict__ mask,
+                                                  int images, int S, int ch) {
     const long long npix = (long long)images * S * S;
-    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= npix * ch) return;
-    const int o = (int)(q / npix);
-    const long long p = q % npix;
+    const long long q0 = (long long)blockIdx.x * blockDim.x;
+    if (q0 >= npix * ch) return;
+    const int o = (int)(q0 / npix);
+    const long long p = q0 - o * npix + threadIdx.x;
     w += (size_t)o * C * 9;
     const int x = (int)(p % S), y = (int)((p / S) % S), img = (int)(p / ((long long)S * S));
     float acc = b[o];
+#pragma unroll
     for (int ky = 0; ky < 3; ++ky) {
         const int yy = y + ky - 1;
-        if (yy < 0 || yy >= S) continue;
+#pragma unroll
         for (int kx = 0; kx < 3; ++kx) {
             const int xx = x + kx - 1;
-            if (xx < 0 || xx >= S) continue;
+            if (yy < 0 || yy >= S || xx < 0 || xx >= S) continue;
             const bf16* ap = a + (((size_t)img * S + yy) * S + xx) * C;
+#pragma unroll
             for (int cg = 0; cg < C / 8; ++cg) {
                 const bf16x8 v = __builtin_bit_cast(bf16x8, *(const u32x4*)(ap + 8 * cg));
 #pragma unroll
@@ -758,7 +900,7 @@ __global__ void k_head_fwd(const bf16* __restrict__ a, const float* __restrict__
             }
         }
     }
-    mask[q] = 1.f / (1.f + expf(-acc));
+    mask[o * npix + p] = 1.f / (1.f + expf(-acc));
 }
 
 __global__ void k_head_dl(const float* __restrict__ dm, const float* __restrict__ m, float* __restrict__ dl,
@@ -1172,15 +1314,16 @@ size_t colsum_tmp_floats(int n) { return (size_t)kColChunks * n; }
 template <int CI, int COUT, int CO>
 void launch_conv_co(int mode, dim3 grid, size_t lds, hipStream_t s, const bf16* in, const bf16* w, void* out,
                     float* part, int S, const BnInfer& bn, int tpb, int tiles) {
+    const ConvSrc src{in, nullptr, nullptr, nullptr, 0, 0};
     if (mode == kConvTrain)
-        FMBYM_LAUNCH_LDS(kMConvFwd, (k_conv3x3<CI, COUT, kConvTrain, CO>), grid, dim3(256), lds, s, in, w, out, part,
-                         S, bn, tpb, tiles);
+        FMBYM_LAUNCH_LDS(kMConvFwd, (k_conv3x3<CI, COUT, kConvTrain, CO>), grid, dim3(256), lds, s, src, w, out,
+                         part, nullptr, S, bn, tpb, tiles);
     else if (mode == kConvInfer)
-        FMBYM_LAUNCH_LDS(kMConvFwd, (k_conv3x3<CI, COUT, kConvInfer, CO>), grid, dim3(256), lds, s, in, w, out, part,
-                         S, bn, tpb, tiles);
+        FMBYM_LAUNCH_LDS(kMConvFwd, (k_conv3x3<CI, COUT, kConvInfer, CO>), grid, dim3(256), lds, s, src, w, out,
+                         part, nullptr, S, bn, tpb, tiles);
     else
-        FMBYM_LAUNCH_LDS(kMConvDgrad, (k_conv3x3<CI, COUT, kConvDgrad, CO>), grid, dim3(256), lds, s, in, w, out,
-                         part, S, bn, tpb, tiles);
+        FMBYM_LAUNCH_LDS(kMConvDgrad, (k_conv3x3<CI, COUT, kConvDgrad, CO>), grid, dim3(256), lds, s, src, w, out,
+                         part, nullptr, S, bn, tpb, tiles);
 }
 
 bool launch_conv3x3(int cin, int cout, int mode, const bf16* in, const bf16* w, void* out, float* part,
@@ -1189,7 +1332,7 @@ bool launch_conv3x3(int cin, int cout, int mode, const bf16* in, const bf16* w, 
     const int co = conv_chunk(cout, nb);
     const dim3 grid(nb, cout / co);
     const int elem = mode == kConvDgrad ? 4 : 2;
-    size_t lds = patch_bytes(cin, S);
+    size_t lds = conv_in_bytes(cin, kSrcPlain);
     if (out_staged(co, elem)) lds = std::max(lds, out_tile_bytes(co, elem));
     if (lds + 4 * 2 * 96 * sizeof(float) > kLdsLimit) return false;
 #define FMBYM_CONV_CASE(CI, CO)                                                                   \
@@ -1215,6 +1358,64 @@ bool launch_conv3x3(int cin, int cout, int mode, const bf16* in, const bf16* w, 
     }
     FMBYM_CONV_PAIRS(FMBYM_CONV_CASE)
 #undef FMBYM_CONV_CASE
+    return false;
+}
+
+template <int CI, int COUT, int SRC, bool POOL, int CO>
+void launch_infer_co(dim3 grid, size_t lds, hipStream_t s, const ConvSrc& src, const bf16* w, bf16* out, bf16* pool,
+                     int S, const BnInfer& bn, int tpb, int tiles) {
+    FMBYM_LAUNCH_LDS(kMConvFwd, (k_conv3x3<CI, COUT, kConvInfer, CO, SRC, POOL>), grid, dim3(256), lds, s, src, w,
+                     (void*)out, (float*)nullptr, pool, S, bn, tpb, tiles);
+}
+
+// The output-channel chunk co of conv_chunk: co_chunk(COUT), or a half or a quarter of it.
+template <int CI, int COUT, int SRC, bool POOL>
+bool launch_infer_ci(int co, dim3 grid, size_t lds, hipStream_t s, const ConvSrc& src, const bf16* w, bf16* out,
+                     bf16* pool, int S, const BnInfer& bn, int tpb, int tiles) {
+    constexpr int C0 = co_chunk(COUT);
+    if (co == C0) {
+        launch_infer_co<CI, COUT, SRC, POOL, C0>(grid, lds, s, src, w, out, pool, S, bn, tpb, tiles);
+        return true;
+    }
+    if constexpr (C0 % 32 == 0) {
+        if (co == C0 / 2) {
+            launch_infer_co<CI, COUT, SRC, POOL, C0 / 2>(grid, lds, s, src, w, out, pool, S, bn, tpb, tiles);
+            return true;
+        }
+        if constexpr (C0 % 64 == 0) {
+            if (co == C0 / 4) {
+                launch_infer_co<CI, COUT, SRC, POOL, C0 / 4>(grid, lds, s, src, w, out, pool, S, bn, tpb, tiles);
+                return true;
+            }
+        }
+    }
+    return false;
+}
+
+bool launch_conv_infer(int cin, int cout, int kind, const ConvSrc& src, const bf16* w, bf16* out, bf16* pool,
+                       const BnInfer& bn, int images, int S, hipStream_t s) {
+    if (kind == kSrcPlain && !pool) return launch_conv3x3(cin, cout, kConvInfer, src.in, w, out, nullptr, bn, images, S, s);
+    const int tiles = conv_blocks(images, S), tpb = conv_tpb(tiles), nb = conv_part_blocks(images, S);
+    const int co = conv_chunk(cout, nb);
+    const dim3 grid(nb, cout / co);
+    size_t lds = conv_in_bytes(cin, kind);
+    if (out_staged(co, 2)) lds = std::max(lds, out_tile_bytes(co, 2));
+    if (lds > kLdsLimit) return false;
+#define FMBYM_INFER_CASE(KIND, POOL, CI, CO)                                                                \
+    if (kind == KIND && (pool != nullptr) == POOL && cin == CI && cout == CO)                               \
+        return launch_infer_ci<CI, CO, KIND, POOL>(co, grid, lds, s, src, w, out, pool, S, bn, tpb, tiles);
+    FMBYM_INFER_CASE(kSrcScan, false, 8, 8)
+    FMBYM_INFER_CASE(kSrcUpCat, false, 24, 8)
+    FMBYM_INFER_CASE(kSrcUpCat, false, 48, 16)
+    FMBYM_INFER_CASE(kSrcUpCat, false, 96, 32)
+    FMBYM_INFER_CASE(kSrcUpCat, false, 192, 64)
+    FMBYM_INFER_CASE(kSrcUpCat, false, 384, 128)
+    FMBYM_INFER_CASE(kSrcPlain, true, 8, 8)
+    FMBYM_INFER_CASE(kSrcPlain, true, 16, 16)
+    FMBYM_INFER_CASE(kSrcPlain, true, 32, 32)
+    FMBYM_INFER_CASE(kSrcPlain, true, 64, 64)
+    FMBYM_INFER_CASE(kSrcPlain, true, 128, 128)
+#undef FMBYM_INFER_CASE
     return false;
 }
 
@@ -1306,11 +1507,12 @@ void launch_up_concat(const bf16* d, const bf16* e, bf16* cat, int images, int S
                        Cd, Ce);
 }
 
-void launch_head_fwd(const bf16* a, const float* w, const float* b, float* mask, int images, int S,
+bool launch_head_fwd(const bf16* a, const float* w, const float* b, float* mask, int images, int S,
                      int C, int ch, hipStream_t s) {
     const long long n = (long long)images * S * S;
-    FMBYM_LAUNCH(kMHeadFwd, k_head_fwd, dim3(grid_for(n * ch, 256)), dim3(256), s, a, w, b, mask, images, S, C,
-                 ch);
+    if (C != 8 || n % 256 != 0) return false;
+    FMBYM_LAUNCH(kMHeadFwd, k_head_fwd<8>, dim3(grid_for(n * ch, 256)), dim3(256), s, a, w, b, mask, images, S, ch);
+    return true;
 }
 
 void launch_head_bwd(const float* d_mask, const float* mask, const bf16* a, const float* w, float* dl,

@@ -59,6 +59,24 @@ struct BnInfer {
 };
 enum ConvMode { kConvDgrad = 0, kConvTrain = 1, kConvInfer = 2 };
 
+// Input of a convolution.  Plain: in [I][S][S][cin] BF16.  The inference pass
+// also reads two fused inputs:
+//   kSrcUpCat: concat[up2(in), skip] formed while staging (the upsampling
+//              layer's arithmetic), in [I][S/2][S/2][2 cin / 3] the deeper
+//              activation and skip [I][S][S][cin / 3];
+//   kSrcScan:  the FP32 scans as the 8-channel first input (plane c in channel
+//              c, zeros elsewhere): x [ch][I][S][S] with plane stride `plane`
+//              (I S^2), or for ch = 1 image i at x_tab[i].
+enum ConvSrcKind { kSrcPlain = 0, kSrcUpCat = 1, kSrcScan = 2 };
+struct ConvSrc {
+    const bf16* in;
+    const bf16* skip;
+    const float* x;
+    const float* const* x_tab;
+    long long plane;
+    int ch;
+};
+
 // 3x3 convolution for (cin, cout) in the supported set; w packed [cout][9 cin]
 // bf16 (k = tap cin + ci, tap = 3 ky + kx).
 //   kConvDgrad: out = conv (float);
@@ -71,6 +89,12 @@ enum ConvMode { kConvDgrad = 0, kConvTrain = 1, kConvInfer = 2 };
 // Returns false for an unsupported pair.
 bool launch_conv3x3(int cin, int cout, int mode, const bf16* in, const bf16* w, void* out, float* part,
                     const BnInfer& bn, int images, int S, hipStream_t s);
+// Inference convolution (kConvInfer arithmetic) from the input `kind` of src;
+// with pool non-null it also writes the 2 x 2 max pooling of its output,
+// pool [I][S/2][S/2][cout] (the next level's input).  Returns false for an
+// unsupported (cin, cout, kind, pool) combination.
+bool launch_conv_infer(int cin, int cout, int kind, const ConvSrc& src, const bf16* w, bf16* out, bf16* pool,
+                       const BnInfer& bn, int images, int S, hipStream_t s);
 
 // Weight gradient: sum over pixels of dz[p][co] in[p + tap][ci], through
 // per-block partials part (wgrad_grid) and a fixed-order reduction (tmp:
@@ -101,8 +125,9 @@ void launch_up_concat(const bf16* d, const bf16* e, bf16* cat, int images, int S
                       hipStream_t s);
 
 // Head: mask = sigmoid(conv3x3(a, w) + b), a [I][S][S][C] bf16, w [ch][C][3][3]
-// float, b [ch]; mask [ch][I][S][S] (plane o is output channel o).
-void launch_head_fwd(const bf16* a, const float* w, const float* b, float* mask, int images, int S,
+// float, b [ch]; mask [ch][I][S][S] (plane o is output channel o).  Returns
+// false unless C = 8 (the base width).
+bool launch_head_fwd(const bf16* a, const float* w, const float* b, float* mask, int images, int S,
                      int C, int ch, hipStream_t s);
 // Head adjoint: dl = d_mask m (1 - m) ([ch][I][S][S]); g [I][S][S][C] float =
 // conv3x3^T(dl, w); dw [ch][C][3][3] and db [ch] (float, written) through

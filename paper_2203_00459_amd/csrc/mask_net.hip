@@ -369,6 +369,42 @@ int mask_forward(const fmbym_mask_desc* d, int I, int n, const float* x, const f
     const bf16* pk = (const bf16*)d->packed;
     float* run_mean = d->bn_running;
     float* run_var = d->bn_running + net.bn_channels;
+    if (!training) {
+        // Inference: BN on the running statistics and ReLU inside each convolution;
+        // the first reads the scans, every encoder b convolution above the bottom
+        // also writes the max pooling its level's successor reads, and every
+        // decoder a convolution forms concat[up2(deeper), skip] while staging.
+        for (int j = 0; j <= net.last(); ++j) {
+            const ConvL& c = net.convs[j];
+            const int S = n >> c.level;
+            ConvSrc src{nullptr, nullptr, nullptr, nullptr, 0, 0};
+            int kind = kSrcPlain;
+            if (j == 0) {
+                kind = kSrcScan;
+                src.x = x;
+                src.x_tab = x_tab;
+                src.plane = (long long)I * n * n;
+                src.ch = net.chans;
+            } else if (c.enc && c.first_of_level) {
+                src.in = at<bf16>(act, A.pool[c.level]);
+            } else if (!c.enc && c.first_of_level) {
+                kind = kSrcUpCat;
+                src.in = at<bf16>(act, A.a[net.deeper(c.level)]);
+                src.skip = at<bf16>(act, A.a[net.enc_b(c.level)]);
+            } else {
+                src.in = at<bf16>(act, A.a[j - 1]);
+            }
+            bf16* pool = c.enc && !c.first_of_level && c.level + 1 < net.levels ? at<bf16>(act, A.pool[c.level + 1])
+                                                                                : nullptr;
+            const BnInfer bn{d->params + c.gamma, d->params + c.beta, run_mean + c.bn, run_var + c.bn, net.eps};
+            if (!launch_conv_infer(c.cink, c.cout, kind, src, pk + c.pf, at<bf16>(act, A.a[j]), pool, bn, I, S, s))
+                return FMBYM_EUNSUPPORTED;
+        }
+        if (!launch_head_fwd(at<bf16>(act, A.a[net.last()]), d->params + net.head_w, d->params + net.head_b, mask, I,
+                             n, net.base, net.chans, s))
+            return FMBYM_EUNSUPPORTED;
+        return finish(s);
+    }
     launch_input8(x, x_tab, at<bf16>(act, A.x8), I, n, net.chans, s);
     for (int j = 0; j <= net.last(); ++j) {
         const ConvL& c = net.convs[j];
@@ -387,13 +423,6 @@ int mask_forward(const fmbym_mask_desc* d, int I, int n, const float* x, const f
         } else {
             in = at<bf16>(act, A.a[j - 1]);
         }
-        if (!training) {   // BN on the running statistics and ReLU inside the convolution
-            const BnInfer bn{d->params + c.gamma, d->params + c.beta, run_mean + c.bn, run_var + c.bn, net.eps};
-            if (!launch_conv3x3(c.cink, c.cout, kConvInfer, in, pk + c.pf, at<bf16>(act, A.a[j]), nullptr, bn, I,
-                                S, s))
-                return FMBYM_EUNSUPPORTED;
-            continue;
-        }
         if (!launch_conv3x3(c.cink, c.cout, kConvTrain, in, pk + c.pf, at<bf16>(act, A.z[j]), at<float>(act, A.part),
                             BnInfer{}, I, S, s))
             return FMBYM_EUNSUPPORTED;
@@ -403,8 +432,9 @@ int mask_forward(const fmbym_mask_desc* d, int I, int n, const float* x, const f
                         run_var + c.bn, at<float>(act, A.stat[j]), at<float>(act, A.tmp), s);
         launch_bn_relu(at<bf16>(act, A.z[j]), at<float>(act, A.stat[j]), at<bf16>(act, A.a[j]), M, c.cout, s);
     }
-    launch_head_fwd(at<bf16>(act, A.a[net.last()]), d->params + net.head_w, d->params + net.head_b, mask, I,
-                    n, net.base, net.chans, s);
+    if (!launch_head_fwd(at<bf16>(act, A.a[net.last()]), d->params + net.head_w, d->params + net.head_b, mask, I,
+                         n, net.base, net.chans, s))
+        return FMBYM_EUNSUPPORTED;
     (void)hipMemcpyAsync(at<float>(act, A.mask), mask, (size_t)net.chans * I * n * n * sizeof(float),
                          hipMemcpyDeviceToDevice, s);
     return finish(s);
