@@ -96,7 +96,11 @@ FMBYM_API size_t fmbym_mask_workspace_bytes(const fmbym_mask_desc* net, int32_t 
  * and, unless d_x is NULL, dL/dx [channels][images][n][n] (FP32, overwritten): the
  * gradient of the loss with respect to the network's input scans (the
  * straight-through derivative of their BF16 rounding), for a caller that
- * trains what produces the scans or checks the network's sensitivity. */
+ * trains what produces the scans or checks the network's sensitivity.
+ * The weight gradients run on a second stream the library keeps per device,
+ * forked from and joined back into `stream` with events, so the call's work
+ * is complete when `stream`'s is (a graph capture of `stream` takes both);
+ * calls from several host threads enqueue one at a time. */
 FMBYM_API int fmbym_mask_bwd(const fmbym_mask_desc* net, int32_t images, int32_t n,
                              const float* d_mask, const void* act, size_t act_bytes, float* d_params,
                              float* d_x, void* workspace, size_t workspace_bytes, void* stream);

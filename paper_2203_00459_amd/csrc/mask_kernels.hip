@@ -55,6 +55,18 @@ __host__ __device__ constexpr size_t out_tile_bytes(int co, int elem) {
 }
 __host__ __device__ constexpr bool out_staged(int co, int elem) { return out_tile_bytes(co, elem) <= kOutStageLimit; }
 
+// The weights of a block's output channels are staged in LDS, once per block,
+// when the input is staged in one pass (cin <= 32) and they take at most
+// kWStageLimit bytes: the B fragments then come from LDS, and no global load
+// in the tile loop waits behind the next tile's patch loads (the vector-memory
+// counter is in order).  Rows of cin 9 weights at a pitch of an odd number of
+// 16-byte slots.
+constexpr size_t kWStageLimit = 28 * 1024;
+__host__ __device__ constexpr int w_pitch(int cin) { return (9 * cin * 2 / 16) % 2 == 0 ? 9 * cin + 8 : 9 * cin; }
+__host__ __device__ constexpr size_t w_stage_bytes(int cin, int co) {
+    return cin <= 32 && (size_t)co * w_pitch(cin) * 2 <= kWStageLimit ? (size_t)co * w_pitch(cin) * 2 : 0;
+}
+
 __device__ __forceinline__ bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
 
 __device__ __forceinline__ f32x4 mfma(u32x4 a, u32x4 b, f32x4 c) {
@@ -94,9 +106,18 @@ constexpr int kUpSide = kConvSide / 2 + 2;
 // Dynamic LDS bytes of a convolution's staged input: the patch at a pitch of
 // patch_pitch(G) 16-byte groups per pixel, and for the up-concat input the
 // low-resolution entries after it.
-constexpr size_t conv_in_bytes(int cin, int src) {
+__host__ __device__ constexpr size_t conv_in_bytes(int cin, int src) {
     return (size_t)patch_pixels(0) * patch_pitch(chunk_ch(cin) / 8) * 16 +
            (src == kSrcUpCat ? (size_t)kUpSide * kUpSide * (chunk_ch(cin) / 8) * 16 : 0);
+}
+
+// Bytes of the region before a convolution's staged weights: the staged input
+// or, when it is staged, the output tile (elem bytes per value), in 16-byte units.
+__host__ __device__ constexpr size_t conv_lds_region(int cin, int src, int co, int elem) {
+    return ((conv_in_bytes(cin, src) > (out_staged(co, elem) ? out_tile_bytes(co, elem) : 0)
+                 ? conv_in_bytes(cin, src)
+                 : (out_staged(co, elem) ? out_tile_bytes(co, elem) : 0)) +
+            15) / 16 * 16;
 }
 
 // Channel groups of the chunk starting at channel c0 that come from the
@@ -267,7 +288,19 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvSrc src, const bf16* __rest
     static_assert(SRC != kSrcUpCat || CIN % 24 == 0, "up-concat input: 2 CIN / 3 upsampled, CIN / 3 skip channels");
     static_assert(!POOL || (MODE == kConvInfer && out_staged(CO_, 2)), "pooling from the staged output tile");
     constexpr int PITCH = patch_pitch(G);
-    extern __shared__ u32x4 patch[];   // conv_lds(CIN, SRC) or the staged output tile
+    // LDS: the staged input (conv_in_bytes) or output tile, then the weights
+    constexpr size_t R0 = conv_lds_region(CIN, SRC, CO_, (int)sizeof(OutT));
+    constexpr int KP = w_pitch(CIN);
+    constexpr bool WLDS = w_stage_bytes(CIN, CO_) > 0;
+    extern __shared__ u32x4 patch[];
+    bf16* wl = reinterpret_cast<bf16*>(reinterpret_cast<char*>(patch) + R0);
+    if constexpr (WLDS) {
+        // read by the compute only after the first tile's barriers
+        for (int it = threadIdx.x; it < CO_ * (K / 8); it += blockDim.x) {
+            const int co = it / (K / 8), kg = it % (K / 8);
+            *(u32x4*)(wl + co * KP + 8 * kg) = *(const u32x4*)(w + (size_t)(co0 + co) * K + 8 * kg);
+        }
+    }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, r16 = lane & 15;
     constexpr int W = kConvSide + 2;
@@ -278,15 +311,19 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvSrc src, const bf16* __rest
         prow[mi] = p / kConvSide;
         pcol[mi] = p % kConvSide;
     }
-    // With the whole patch in one pass (CIN <= 32), the next tile's patch is
-    // loaded into registers while the current one is computed.
+    // With the whole patch in one pass (CIN <= 32), the patches of the next PD
+    // tiles are loaded into registers while the current one is computed: two
+    // tiles ahead when a patch takes at most three loads per thread (the small
+    // layers, whose compute is too short to cover one load's latency), else one.
     constexpr bool PREF = NCH == 1;
     constexpr int DG0 = SRC == kSrcUpCat ? (2 * CIN / 3 / 8 < G ? 2 * CIN / 3 / 8 : G) : 0;
     constexpr int NE = stage_entries<SRC>(G, DG0);   // entries of the one chunk (c0 = 0)
     constexpr int PLOADS = (NE + 255) / 256;
-    u32x4 pre[PREF ? PLOADS : 1];
+    constexpr int PD = 1;
+    constexpr int NPRE = PREF ? PLOADS : 1;
+    u32x4 preA[NPRE], preB[NPRE];
     const int tile0 = blockIdx.x * tpb, tile1 = min(tiles, tile0 + tpb);
-    auto prefetch = [&](int tile) {
+    auto prefetch = [&](u32x4 (&pre)[NPRE], int tile) {
         const TileGeo tn = conv_tile_geo(tile, S);
 #pragma unroll
         for (int k = 0; k < PLOADS; ++k) {
@@ -294,7 +331,11 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvSrc src, const bf16* __rest
             pre[k] = it < NE ? fetch_entry<CIN, SRC>(src, tn, S, 0, G, DG0, it) : u32x4{0u, 0u, 0u, 0u};
         }
     };
-    if constexpr (PREF) prefetch(tile0);
+    if constexpr (PREF) {
+        prefetch(preA, tile0);
+        if constexpr (PD == 2)
+            if (tile0 + 1 < tile1) prefetch(preB, tile0 + 1);
+    }
     // inference: batch norm on the running statistics and ReLU on the BF16-rounded
     // output, the arithmetic of the training pass's statistics and BN + ReLU passes
     float csc[NT], csh[NT];
@@ -315,7 +356,7 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvSrc src, const bf16* __rest
     float s1[NT], s2[NT];
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) s1[nt] = s2[nt] = 0.f;
-    for (int tile = tile0; tile < tile1; ++tile) {
+    auto body = [&](int tile, u32x4 (&pre)[NPRE]) {
         const TileGeo t = conv_tile_geo(tile, S);
         f32x4 acc[4][NT];
 #pragma unroll
@@ -333,7 +374,7 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvSrc src, const bf16* __rest
                     const int it = threadIdx.x + 256 * k;
                     if (it < NE) put_entry<SRC>(patch, PITCH, G, DG0, it, pre[k]);
                 }
-                if (tile + 1 < tile1) prefetch(tile + 1);
+                if (tile + PD < tile1) prefetch(pre, tile + PD);
             } else {
                 const int ne = stage_entries<SRC>(G, dg);
                 for (int it = threadIdx.x; it < ne; it += blockDim.x)
@@ -357,9 +398,12 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvSrc src, const bf16* __rest
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) {
                     const int co = nt * 16 + r16;
-                    b[nt] = (valid && co < CO)
-                                ? *(const u32x4*)(w + (size_t)(co0 + co) * K + tap * CIN + c0 + 8 * cg)
-                                : zero;
+                    if constexpr (WLDS)
+                        b[nt] = (valid && co < CO) ? *(const u32x4*)(wl + co * KP + tap * CIN + c0 + 8 * cg) : zero;
+                    else
+                        b[nt] = (valid && co < CO)
+                                    ? *(const u32x4*)(w + (size_t)(co0 + co) * K + tap * CIN + c0 + 8 * cg)
+                                    : zero;
                 }
 #pragma unroll
                 for (int mi = 0; mi < 4; ++mi)
@@ -428,7 +472,15 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvSrc src, const bf16* __rest
                 }
             }
         }
-    }   // tiles
+    };
+    if constexpr (PD == 2) {
+        for (int tile = tile0; tile < tile1; tile += 2) {
+            body(tile, preA);
+            if (tile + 1 < tile1) body(tile + 1, preB);
+        }
+    } else {
+        for (int tile = tile0; tile < tile1; ++tile) body(tile, preA);
+    }
     if constexpr (STATS) {
         __shared__ float red[4][2][NT * 16];
 #pragma unroll
@@ -883,21 +935,28 @@ __global__ __launch_bounds__(256) void k_head_fwd(const bf16* __restrict__ a, co
     const long long p = q0 - o * npix + threadIdx.x;
     w += (size_t)o * C * 9;
     const int x = (int)(p % S), y = (int)((p / S) % S), img = (int)(p / ((long long)S * S));
+    // every tap's load issued first at a clamped address; taps outside the
+    // image are then skipped (the sum over the taps inside, in tap order)
+    u32x4 v[9][C / 8];
+    unsigned inb = 0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const int yy = y + k / 3 - 1, xx = x + k % 3 - 1;
+        inb |= (yy >= 0 && yy < S && xx >= 0 && xx < S ? 1u : 0u) << k;
+        const int yc = min(max(yy, 0), S - 1), xc = min(max(xx, 0), S - 1);
+        const bf16* ap = a + (((size_t)img * S + yc) * S + xc) * C;
+#pragma unroll
+        for (int cg = 0; cg < C / 8; ++cg) v[k][cg] = *(const u32x4*)(ap + 8 * cg);
+    }
     float acc = b[o];
 #pragma unroll
-    for (int ky = 0; ky < 3; ++ky) {
-        const int yy = y + ky - 1;
+    for (int k = 0; k < 9; ++k) {
+        if (!((inb >> k) & 1u)) continue;
 #pragma unroll
-        for (int kx = 0; kx < 3; ++kx) {
-            const int xx = x + kx - 1;
-            if (yy < 0 || yy >= S || xx < 0 || xx >= S) continue;
-            const bf16* ap = a + (((size_t)img * S + yy) * S + xx) * C;
+        for (int cg = 0; cg < C / 8; ++cg) {
+            const bf16x8 vv = __builtin_bit_cast(bf16x8, v[k][cg]);
 #pragma unroll
-            for (int cg = 0; cg < C / 8; ++cg) {
-                const bf16x8 v = __builtin_bit_cast(bf16x8, *(const u32x4*)(ap + 8 * cg));
-#pragma unroll
-                for (int j = 0; j < 8; ++j) acc = fmaf((float)v[j], w[(8 * cg + j) * 9 + ky * 3 + kx], acc);
-            }
+            for (int j = 0; j < 8; ++j) acc = fmaf((float)vv[j], w[(8 * cg + j) * 9 + k], acc);
         }
     }
     mask[o * npix + p] = 1.f / (1.f + expf(-acc));
@@ -925,17 +984,21 @@ __global__ void k_head_g(const float* __restrict__ dl, const float* __restrict__
     for (int o = 0; o < ch; ++o) {
         const float* wo = w + (size_t)o * 8 * 9;
         const float* dlo = dl + o * npix;
+        // the nine loads first (clamped addresses), then the taps inside the image in order
+        float d[9];
+        unsigned inb = 0;
 #pragma unroll
-        for (int ky = 0; ky < 3; ++ky) {
-            const int yy = y - (ky - 1);
+        for (int k = 0; k < 9; ++k) {
+            const int yy = y - (k / 3 - 1), xx = x - (k % 3 - 1);
+            inb |= (yy >= 0 && yy < S && xx >= 0 && xx < S ? 1u : 0u) << k;
+            const int yc = min(max(yy, 0), S - 1), xc = min(max(xx, 0), S - 1);
+            d[k] = dlo[((size_t)img * S + yc) * S + xc];
+        }
 #pragma unroll
-            for (int kx = 0; kx < 3; ++kx) {
-                const int xx = x - (kx - 1);
-                if (yy < 0 || yy >= S || xx < 0 || xx >= S) continue;
-                const float d = dlo[((size_t)img * S + yy) * S + xx];
+        for (int k = 0; k < 9; ++k) {
+            if (!((inb >> k) & 1u)) continue;
 #pragma unroll
-                for (int j = 0; j < 8; ++j) acc[j] = fmaf(wo[j * 9 + ky * 3 + kx], d, acc[j]);
-            }
+            for (int j = 0; j < 8; ++j) acc[j] = fmaf(wo[j * 9 + k], d[k], acc[j]);
         }
     }
     float4* o = reinterpret_cast<float4*>(g + p * 8);
@@ -1332,8 +1395,7 @@ bool launch_conv3x3(int cin, int cout, int mode, const bf16* in, const bf16* w, 
     const int co = conv_chunk(cout, nb);
     const dim3 grid(nb, cout / co);
     const int elem = mode == kConvDgrad ? 4 : 2;
-    size_t lds = conv_in_bytes(cin, kSrcPlain);
-    if (out_staged(co, elem)) lds = std::max(lds, out_tile_bytes(co, elem));
+    const size_t lds = conv_lds_region(cin, kSrcPlain, co, elem) + w_stage_bytes(cin, co);
     if (lds + 4 * 2 * 96 * sizeof(float) > kLdsLimit) return false;
 #define FMBYM_CONV_CASE(CI, CO)                                                                   \
     if (cin == CI && cout == CO) {                                                                \
@@ -1398,8 +1460,7 @@ bool launch_conv_infer(int cin, int cout, int kind, const ConvSrc& src, const bf
     const int tiles = conv_blocks(images, S), tpb = conv_tpb(tiles), nb = conv_part_blocks(images, S);
     const int co = conv_chunk(cout, nb);
     const dim3 grid(nb, cout / co);
-    size_t lds = conv_in_bytes(cin, kind);
-    if (out_staged(co, 2)) lds = std::max(lds, out_tile_bytes(co, 2));
+    const size_t lds = conv_lds_region(cin, kind, co, 2) + w_stage_bytes(cin, co);
     if (lds > kLdsLimit) return false;
 #define FMBYM_INFER_CASE(KIND, POOL, CI, CO)                                                                \
     if (kind == KIND && (pool != nullptr) == POOL && cin == CI && cout == CO)                               \

@@ -11,6 +11,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "internal.hpp"
@@ -145,7 +146,7 @@ ActLayout act_layout(const Net& net, int I, int n) {
 }
 
 struct WsLayout {
-    size_t dz = 0, part = 0, coef = 0, wpart = 0, dl = 0, hpart = 0, tmp = 0, total = 0;
+    size_t dz[2] = {0, 0}, part = 0, coef = 0, wpart = 0, dl = 0, hpart = 0, tmp = 0, total = 0;
     std::vector<size_t> g, dpool, dcat;
 };
 
@@ -167,7 +168,8 @@ WsLayout ws_layout(const Net& net, int I, int n) {
     for (int l = 1; l < net.levels; ++l) L.dpool[l] = b.take(pix(l) * net.ch(l - 1) * fl);
     L.dcat.assign(net.levels, 0);
     for (int l = 0; l + 1 < net.levels; ++l) L.dcat[l] = b.take(pix(l) * (net.ch(l + 1) + net.ch(l)) * fl);
-    L.dz = b.take(dz_max);
+    L.dz[0] = b.take(dz_max);   // layers alternate: a weight gradient may still read the other
+    L.dz[1] = b.take(dz_max);
     L.part = b.take(part_max);
     L.coef = b.take(3 * 256 * fl);   // per-channel coefficients of the widest BN layer
     L.wpart = b.take(wpart_max);
@@ -192,6 +194,46 @@ const T* at(const void* base, size_t off) {
 int finish(hipStream_t) {
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? FMBYM_OK : hip_fail(e);
+}
+
+// The backward's weight gradients run on a second stream per device, beside
+// the chain of data gradients on the caller's stream: the weight gradient of
+// layer j waits for that layer's dz (event dz), and the chain waits for it
+// (event w[j % 2]) before it overwrites that dz buffer two layers later and
+// at the end.  Enqueueing holds g_lane_mu, so calls from several host threads
+// take the events in turn (a wait uses the event's state when it is enqueued).
+constexpr int kMaxLanes = 64;
+struct WgradLane {
+    hipStream_t s = nullptr;
+    hipEvent_t dz = nullptr;
+    hipEvent_t w[2] = {nullptr, nullptr};
+};
+std::mutex g_lane_mu;
+WgradLane g_lanes[kMaxLanes];
+
+// The lane of the current device, created on first use (call with g_lane_mu held).
+hipError_t wgrad_lane(WgradLane** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxLanes) return hipErrorInvalidDevice;
+    WgradLane& L = g_lanes[dev];
+    if (!L.s) {
+        WgradLane n;
+        e = hipStreamCreateWithFlags(&n.s, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&n.dz, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&n.w[0], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&n.w[1], hipEventDisableTiming);
+        if (e != hipSuccess) {
+            for (hipEvent_t ev : {n.dz, n.w[0], n.w[1]})
+                if (ev) (void)hipEventDestroy(ev);
+            if (n.s) (void)hipStreamDestroy(n.s);
+            return e;
+        }
+        L = n;
+    }
+    *out = &L;
+    return hipSuccess;
 }
 
 }  // namespace
@@ -274,6 +316,18 @@ int fmbym_mask_bwd(const fmbym_mask_desc* d, int32_t I, int32_t n, const float* 
     const float* P = d->params;
     void* wsp = ws;
     const int last = net.last();
+    std::lock_guard<std::mutex> lane_lock(g_lane_mu);
+    WgradLane* lane = nullptr;
+    if (const hipError_t e = wgrad_lane(&lane); e != hipSuccess) return hip_fail(e);
+    bool side_used = false;
+    // the caller's stream waits for every weight gradient before any return
+    auto join = [&](int rc) {
+        if (side_used) {
+            const hipError_t e = hipStreamWaitEvent(s, lane->w[0], 0);
+            if (e != hipSuccess && rc == FMBYM_OK) rc = hip_fail(e);
+        }
+        return rc;
+    };
     launch_head_bwd(d_mask, at<float>(act, A.mask), at<bf16>(act, A.a[last]), P + net.head_w,
                     at<float>(wsp, W.dl), at<float>(wsp, W.g[last]), at<float>(wsp, W.hpart),
                     at<float>(wsp, W.tmp), d_params + net.head_w, d_params + net.head_b, I, n, net.base,
@@ -282,7 +336,9 @@ int fmbym_mask_bwd(const fmbym_mask_desc* d, int32_t I, int32_t n, const float* 
         const ConvL& c = net.convs[j];
         const int S = n >> c.level;
         const long long M = (long long)I * S * S;
-        bf16* dz = at<bf16>(wsp, W.dz);
+        bf16* dz = at<bf16>(wsp, W.dz[j & 1]);
+        // dz[j % 2] was last read by the weight gradient of layer j + 2
+        if (j + 2 <= last && hipStreamWaitEvent(s, lane->w[j & 1], 0) != hipSuccess) return join(finish(s));
         launch_bn_relu_bwd(at<float>(wsp, W.g[j]), at<bf16>(act, A.z[j]), at<float>(act, A.stat[j]),
                            P + c.gamma, at<float>(wsp, W.part), at<float>(wsp, W.tmp), at<float>(wsp, W.coef),
                            d_params + c.gamma,
@@ -296,9 +352,16 @@ int fmbym_mask_bwd(const fmbym_mask_desc* d, int32_t I, int32_t n, const float* 
             in = at<bf16>(act, A.cat[c.level]);
         else
             in = at<bf16>(act, A.a[j - 1]);
-        if (!launch_wgrad(c.cink, c.cout, dz, in, at<float>(wsp, W.wpart), at<float>(wsp, W.tmp),
-                          d_params + c.w, c.cin, I, S, s))
-            return FMBYM_EUNSUPPORTED;
+        if (hipEventRecord(lane->dz, s) != hipSuccess || hipStreamWaitEvent(lane->s, lane->dz, 0) != hipSuccess)
+            return join(finish(s));
+        side_used = true;
+        const bool ok = launch_wgrad(c.cink, c.cout, dz, in, at<float>(wsp, W.wpart), at<float>(wsp, W.tmp),
+                                     d_params + c.w, c.cin, I, S, lane->s);
+        if (hipEventRecord(lane->w[j & 1], lane->s) != hipSuccess) return join(finish(s));
+        if (!ok) {   // w[0] then marks the lane's last work, which the join waits for
+            (void)hipEventRecord(lane->w[0], lane->s);
+            return join(FMBYM_EUNSUPPORTED);
+        }
         if (j == 0) {
             if (d_x) launch_input_grad(dz, P + c.w, d_x, I, S, c.cout, net.chans, s);
             break;
@@ -311,8 +374,10 @@ int fmbym_mask_bwd(const fmbym_mask_desc* d, int32_t I, int32_t n, const float* 
             din = at<float>(wsp, W.dcat[c.level]);
         else
             din = at<float>(wsp, W.g[j - 1]);
-        if (!launch_conv3x3(c.cout, c.cin, kConvDgrad, dz, pk + c.pb, din, nullptr, BnInfer{}, I, S, s))
-            return FMBYM_EUNSUPPORTED;
+        if (!launch_conv3x3(c.cout, c.cin, kConvDgrad, dz, pk + c.pb, din, nullptr, BnInfer{}, I, S, s)) {
+            (void)hipEventRecord(lane->w[0], lane->s);
+            return join(FMBYM_EUNSUPPORTED);
+        }
         // the gradient of the next conv down (parameter order j - 1) when it is a b conv
         if (!c.enc && c.first_of_level) {
             // deeper activation of dec{l}a: dec{l+1}b or enc{L-1}b
@@ -325,7 +390,7 @@ int fmbym_mask_bwd(const fmbym_mask_desc* d, int32_t I, int32_t n, const float* 
                             n >> (l - 1), net.ch(l - 1), s);
         }
     }
-    return finish(s);
+    return join(finish(s));   // layer 0's weight gradient recorded w[0] last
 }
 
 int fmbym_adam(float* params, const float* grad, float* m, float* v, int64_t count, int32_t step, float lr,
