@@ -26,6 +26,11 @@ namespace {
 // Input channels staged per pass: all of them up to 32, else 32 or 24 at a time.
 __host__ __device__ constexpr int chunk_ch(int cin) { return cin <= 32 ? cin : (cin % 32 == 0 ? 32 : 24); }
 
+// Threads of a convolution, weight-gradient or head weight-gradient block (its
+// launch bounds; a compile-time stride keeps the block-size load, and the wait
+// for every load in flight it brings, out of the staging loops).
+constexpr int kConvThreads = 256;
+
 // Convolution tiles are 16 x 16 pixels (sides S >= 16): the input patch with
 // its one-pixel halo is 18 x 18, 1.27 reads per output pixel where a
 // 256-pixel row strip reads 3.
@@ -221,7 +226,7 @@ __device__ __forceinline__ void up_interp(u32x4* patch, int pitch, int dg, const
     constexpr int W = kConvSide + 2;
     const u32x4* lr = patch + W * W * pitch;
     const int H = S / 2, ly0 = t.y0 / 2 - 1, lx0 = t.x0 / 2 - 1;
-    for (int it = threadIdx.x; it < W * W * dg; it += blockDim.x) {
+    for (int it = threadIdx.x; it < W * W * dg; it += kConvThreads) {
         const int q = it / dg, k = it % dg;
         const int y = t.y0 - 1 + q / W, x = t.x0 - 1 + q % W;
         u32x4 v = {0u, 0u, 0u, 0u};
@@ -296,7 +301,7 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvSrc src, const bf16* __rest
     bf16* wl = reinterpret_cast<bf16*>(reinterpret_cast<char*>(patch) + R0);
     if constexpr (WLDS) {
         // read by the compute only after the first tile's barriers
-        for (int it = threadIdx.x; it < CO_ * (K / 8); it += blockDim.x) {
+        for (int it = threadIdx.x; it < CO_ * (K / 8); it += kConvThreads) {
             const int co = it / (K / 8), kg = it % (K / 8);
             *(u32x4*)(wl + co * KP + 8 * kg) = *(const u32x4*)(w + (size_t)(co0 + co) * K + 8 * kg);
         }
@@ -377,7 +382,7 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvSrc src, const bf16* __rest
                 if (tile + PD < tile1) prefetch(pre, tile + PD);
             } else {
                 const int ne = stage_entries<SRC>(G, dg);
-                for (int it = threadIdx.x; it < ne; it += blockDim.x)
+                for (int it = threadIdx.x; it < ne; it += kConvThreads)
                     put_entry<SRC>(patch, PITCH, G, dg, it, fetch_entry<CIN, SRC>(src, t, S, c0, G, dg, it));
             }
             if constexpr (SRC == kSrcUpCat) {
@@ -447,7 +452,7 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvSrc src, const bf16* __rest
             __syncthreads();
             constexpr int VEC = 16 / ELEM, VPP = CO / VEC;   // 16-byte groups per pixel
             static_assert(CO % VEC == 0, "whole 16-byte groups per pixel");
-            for (int it = threadIdx.x; it < kConvTile * VPP; it += blockDim.x) {
+            for (int it = threadIdx.x; it < kConvTile * VPP; it += kConvThreads) {
                 const int p = it / VPP, q = it % VPP;
                 const size_t pix = img_base + (size_t)(t.y0 + p / t.pc) * S + t.x0 + p % t.pc;
                 *(u32x4*)(out + pix * COUT + co0 + q * VEC) = *(const u32x4*)(stage + p * TP + q * VEC);
@@ -455,7 +460,7 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvSrc src, const bf16* __rest
             if constexpr (POOL) {
                 // 2 x 2 max pooling of the tile into the next level's input [I][S/2][S/2][COUT]
                 const int H = S / 2;
-                for (int it = threadIdx.x; it < kConvTile / 4 * VPP; it += blockDim.x) {
+                for (int it = threadIdx.x; it < kConvTile / 4 * VPP; it += kConvThreads) {
                     const int pp = it / VPP, q = it % VPP;
                     const int py = pp / (kConvSide / 2), px = pp % (kConvSide / 2);
                     const int p00 = 2 * py * kConvSide + 2 * px;
@@ -495,7 +500,7 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvSrc src, const bf16* __rest
             }
         }
         __syncthreads();
-        for (int c = threadIdx.x; c < CO; c += blockDim.x) {
+        for (int c = threadIdx.x; c < CO; c += kConvThreads) {
             float a = 0.f, b = 0.f;
 #pragma unroll
             for (int wv = 0; wv < 4; ++wv) {
@@ -574,7 +579,7 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16* __restrict__ dz, cons
             const size_t img_base = (size_t)t.img * S * S;
             __syncthreads();
             // the chunk's dz tile, transposed
-            for (int it = threadIdx.x; it < kConvTile * CO / 8; it += blockDim.x) {
+            for (int it = threadIdx.x; it < kConvTile * CO / 8; it += kConvThreads) {
                 const int p = it / (CO / 8), cg = it % (CO / 8);
                 const size_t pix = img_base + (size_t)(t.y0 + p / t.pc) * S + t.x0 + p % t.pc;
                 const bf16x8 v = __builtin_bit_cast(bf16x8, *(const u32x4*)(dz + pix * COUT + co0 + 8 * cg));
@@ -585,7 +590,7 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16* __restrict__ dz, cons
             {
                 const int W = t.pc + 2, npix = (t.pr + 2) * W;
                 const bf16* base = in + (size_t)t.img * S * S * CIN;
-                for (int it = threadIdx.x; it < npix * (CC / 8); it += blockDim.x) {
+                for (int it = threadIdx.x; it < npix * (CC / 8); it += kConvThreads) {
                     const int q = it / (CC / 8), cg = it % (CC / 8);
                     const int r = q / W, c = q % W;
                     const int y = t.y0 - 1 + r, x = t.x0 - 1 + c;
@@ -1057,8 +1062,8 @@ __global__ __launch_bounds__(256) void k_head_wgrad(const float* __restrict__ dl
     };
     long long p = p0 + threadIdx.x;
     // two pixels' loads in flight, accumulated in pixel order
-    for (; p + blockDim.x < pend; p += 2 * blockDim.x) {
-        const Taps t0 = load(p), t1 = load(p + blockDim.x);
+    for (; p + kConvThreads < pend; p += 2 * kConvThreads) {
+        const Taps t0 = load(p), t1 = load(p + kConvThreads);
         add(t0);
         add(t1);
     }
@@ -1072,7 +1077,7 @@ __global__ __launch_bounds__(256) void k_head_wgrad(const float* __restrict__ dl
         if (lane == 0) red[wave][j] = v;
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < NW; j += blockDim.x)
+    for (int j = threadIdx.x; j < NW; j += kConvThreads)
         part[(size_t)blockIdx.x * NW + j] = red[0][j] + red[1][j] + red[2][j] + red[3][j];
 }
 
