@@ -276,8 +276,18 @@ inline int conv_chunk(int cout, int blocks) {
     return co;
 }
 
+// Waves per SIMD the compiler must leave room for, where measured faster than
+// its own register choice (1: no constraint): the 24-channel up-concat
+// inference convolution at 4 (361 against 403 us at 64 x 512^2, no spills) and
+// the 8-channel pooling one at 6 (154 against 165 us).  Others lost time or
+// spilled at a higher count.
+constexpr int conv_waves(int cin, int mode, int src, bool pool) {
+    return mode != kConvInfer ? 1 : (src == kSrcUpCat && cin == 24 ? 4 : (pool && cin == 8 ? 6 : 1));
+}
+
 template <int CIN, int COUT, int MODE, int CO_ = co_chunk(COUT), int SRC = kSrcPlain, bool POOL = false>
-__global__ __launch_bounds__(256) void k_conv3x3(ConvSrc src, const bf16* __restrict__ w,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(conv_waves(CIN, MODE, SRC, POOL)))) void
+k_conv3x3(ConvSrc src, const bf16* __restrict__ w,
                                                  void* __restrict__ outv, float* __restrict__ part,
                                                  bf16* __restrict__ pool, int S, BnInfer bn, int tpb, int tiles) {
     using OutT = typename std::conditional<MODE == kConvDgrad, float, bf16>::type;
