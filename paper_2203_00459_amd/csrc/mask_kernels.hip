@@ -937,44 +937,70 @@ __global__ void k_up_concat(const bf16* __restrict__ d, const bf16* __restrict__
 }
 
 // Output channel o of the head is plane o of mask (mask + o images S^2); w is [ch][C][3][3].
-// One pixel per thread; the 256 pixels of a block share o (images S^2 is a
-// multiple of 256), so the weights are block-uniform loads.
+// A block computes a 16 x 64-pixel tile of every output channel from its
+// 18 x 66-pixel input patch staged in LDS with zeros outside the image (all
+// loads issued before the stores); a thread owns four pixels of one column.
+// Each pixel sums its nine taps in tap order; a tap outside the image adds
+// products of zero, which leave every nonzero sum unchanged and change at
+// most the sign of a zero one (the sigmoid maps both zeros to 1/2), so the
+// masks are those of a sum over the taps inside the image.  The weights sit
+// in LDS as [o][tap][channel], read as 16-byte broadcasts.
+constexpr int kHeadRows = 16, kHeadCols = 64;
 template <int C>
 __global__ __launch_bounds__(256) void k_head_fwd(const bf16* __restrict__ a, const float* __restrict__ w,
                                                   const float* __restrict__ b, float* __restrict__ mask,
                                                   int images, int S, int ch) {
+    constexpr int PR = kHeadRows + 2, PC = kHeadCols + 2, G = C / 8, NE = PR * PC * G;
+    constexpr int NL = (NE + 255) / 256;
+    __shared__ u32x4 tile[NE];
+    __shared__ f32x4 wl[2 * 9 * C / 4];   // up to two output channels
+    const int tx = S / kHeadCols, ty = S / kHeadRows;
+    const int img = blockIdx.x / (tx * ty), k = blockIdx.x % (tx * ty);
+    const int y0 = (k / tx) * kHeadRows, x0 = (k % tx) * kHeadCols;
+    u32x4 v[NL];
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+        const int it = threadIdx.x + 256 * l;
+        const int q = it / G, cg = it % G;
+        const int y = y0 - 1 + q / PC, x = x0 - 1 + q % PC;
+        v[l] = u32x4{0u, 0u, 0u, 0u};
+        if (it < NE && y >= 0 && y < S && x >= 0 && x < S)
+            v[l] = *(const u32x4*)(a + (((size_t)img * S + y) * S + x) * C + 8 * cg);
+    }
+    for (int i = threadIdx.x; i < ch * 9 * C; i += 256) {
+        const int o = i / (9 * C), t = (i / C) % 9, ci = i % C;
+        reinterpret_cast<float*>(wl)[i] = w[((size_t)o * C + ci) * 9 + t];
+    }
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+        const int it = threadIdx.x + 256 * l;
+        if (it < NE) tile[it] = v[l];
+    }
+    __syncthreads();
     const long long npix = (long long)images * S * S;
-    const long long q0 = (long long)blockIdx.x * blockDim.x;
-    if (q0 >= npix * ch) return;
-    const int o = (int)(q0 / npix);
-    const long long p = q0 - o * npix + threadIdx.x;
-    w += (size_t)o * C * 9;
-    const int x = (int)(p % S), y = (int)((p / S) % S), img = (int)(p / ((long long)S * S));
-    // every tap's load issued first at a clamped address; taps outside the
-    // image are then skipped (the sum over the taps inside, in tap order)
-    u32x4 v[9][C / 8];
-    unsigned inb = 0;
+    const int c = threadIdx.x % kHeadCols, r0 = (threadIdx.x / kHeadCols) * 4;
+    for (int o = 0; o < ch; ++o) {
+        const float bo = b[o];
+        float acc[4] = {bo, bo, bo, bo};
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        const int yy = y + k / 3 - 1, xx = x + k % 3 - 1;
-        inb |= (yy >= 0 && yy < S && xx >= 0 && xx < S ? 1u : 0u) << k;
-        const int yc = min(max(yy, 0), S - 1), xc = min(max(xx, 0), S - 1);
-        const bf16* ap = a + (((size_t)img * S + yc) * S + xc) * C;
+        for (int t = 0; t < 9; ++t) {
 #pragma unroll
-        for (int cg = 0; cg < C / 8; ++cg) v[k][cg] = *(const u32x4*)(ap + 8 * cg);
-    }
-    float acc = b[o];
+            for (int cg = 0; cg < G; ++cg) {
+                const f32x4 w0 = wl[((o * 9 + t) * C + 8 * cg) / 4], w1 = wl[((o * 9 + t) * C + 8 * cg) / 4 + 1];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        if (!((inb >> k) & 1u)) continue;
+                for (int rr = 0; rr < 4; ++rr) {
+                    const bf16x8 e = __builtin_bit_cast(bf16x8, tile[((r0 + rr + t / 3) * PC + c + t % 3) * G + cg]);
 #pragma unroll
-        for (int cg = 0; cg < C / 8; ++cg) {
-            const bf16x8 vv = __builtin_bit_cast(bf16x8, v[k][cg]);
+                    for (int j = 0; j < 4; ++j) acc[rr] = fmaf((float)e[j], w0[j], acc[rr]);
 #pragma unroll
-            for (int j = 0; j < 8; ++j) acc = fmaf((float)vv[j], w[(8 * cg + j) * 9 + k], acc);
+                    for (int j = 0; j < 4; ++j) acc[rr] = fmaf((float)e[j + 4], w1[j], acc[rr]);
+                }
+            }
         }
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr)
+            mask[o * npix + ((size_t)img * S + y0 + r0 + rr) * S + x0 + c] = 1.f / (1.f + expf(-acc[rr]));
     }
-    mask[o * npix + p] = 1.f / (1.f + expf(-acc));
 }
 
 __global__ void k_head_dl(const float* __restrict__ dm, const float* __restrict__ m, float* __restrict__ dl,
@@ -1586,8 +1612,9 @@ void launch_up_concat(const bf16* d, const bf16* e, bf16* cat, int images, int S
 bool launch_head_fwd(const bf16* a, const float* w, const float* b, float* mask, int images, int S,
                      int C, int ch, hipStream_t s) {
     const long long n = (long long)images * S * S;
-    if (C != 8 || n % 256 != 0) return false;
-    FMBYM_LAUNCH(kMHeadFwd, k_head_fwd<8>, dim3(grid_for(n * ch, 256)), dim3(256), s, a, w, b, mask, images, S, ch);
+    if (C != 8 || ch < 1 || ch > 2 || S % kHeadCols != 0 || S % kHeadRows != 0) return false;
+    FMBYM_LAUNCH(kMHeadFwd, k_head_fwd<8>, dim3(n / (kHeadRows * kHeadCols)), dim3(256), s, a, w, b, mask, images, S,
+                 ch);
     return true;
 }
 
