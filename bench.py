@@ -226,6 +226,8 @@ def main() -> int:
         return train_bench(args)
     if args.workload in workloads.TRAIN_RUN:
         return train_run_bench(args)
+    if args.workload in workloads.INFER:
+        return infer_bench(args)
     if args.workload in workloads.DRIVE:
         return drive_bench(args)
     return search_bench(args)
@@ -262,6 +264,107 @@ def mask_kernel_model(images: int, n: int, levels: int = 4, base: int = 8, chann
         if j:
             add("m_conv_dgrad", px * (co * 2 + ci * 4), 2.0 * px * 9 * ci * co)
     return m
+
+
+def mask_infer_model(images: int, n: int, levels: int = 4, base: int = 8, channels: int = 1) -> dict:
+    """Algorithmic HBM bytes and flops of the fused inference pass: every
+    tensor it reads or writes once.  The first convolution reads the FP32
+    scans, a decoder's first reads the skip activation and the deeper one at a
+    quarter of its pixels, an encoder's second also writes the pooled output;
+    the head reads the last activation and writes FP32 masks."""
+    conv_b, flops = 0.0, 0.0
+    layers = mask_layers(levels, base, channels)
+    for j, (ci, co, l) in enumerate(layers):
+        px = images * (n >> l) ** 2
+        if j == 0:
+            rd = px * channels * 4
+        elif j >= 2 * levels and (j - 2 * levels) % 2 == 0:
+            rd = px * (ci // 3) * 2 + px * (2 * ci // 3) * 2 / 4
+        else:
+            rd = px * ci * 2
+        wr = px * co * 2 + (px * co * 2 / 4 if j < 2 * levels and j % 2 == 1 and l + 1 < levels else 0)
+        conv_b += rd + wr
+        flops += 2.0 * px * 9 * ci * co
+    px0 = images * n * n
+    return {"m_conv_fwd": (conv_b, flops), "m_head_fwd": (px0 * base * 2 + px0 * channels * 4, 0.0)}
+
+
+def infer_bench(args) -> int:
+    """One step = one inference pass of the mask network (running statistics)
+    over both scans of every pair of the batch, as inside the masked ragged
+    launch."""
+    import numpy as np
+    import torch
+
+    from paper_2203_00459_amd import fmbym, synth, workloads
+    from paper_2203_00459_amd.train import he_init
+
+    cfg = workloads.INFER[args.workload]
+    B, n, levels = cfg["pairs"], cfg["n"], cfg["levels"]
+    f, g, _ = synth.make_batch(cfg["scenes"], B, split="bench")
+    X = torch.from_numpy(np.concatenate([f, g])).to("cuda:0")
+    params = he_init(levels, 8, 0)
+    net = fmbym.MaskNet(params, levels=levels, base=8)
+    # running statistics as a trained network has them (not the initial 0 / 1)
+    nb = net.bn_running.numel() // 2
+    rs = np.random.Generator(np.random.PCG64(7))
+    net.bn_running.copy_(torch.from_numpy(np.concatenate([0.1 * rs.standard_normal(nb), 0.5 + rs.random(nb)])
+                                          .astype(np.float32)).to("cuda:0"))
+    for _ in range(args.warmup):
+        net.forward(X, training=False)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.steps):
+        net.forward(X, training=False)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    psteps = min(args.steps, PROFILE_STEPS)
+    fmbym.profile_enable(psteps * 64)
+    for _ in range(psteps):
+        net.forward(X, training=False)
+    torch.cuda.synchronize()
+    prof = fmbym.profile_read()
+    fmbym.profile_enable(0)
+    per_step = {k: t / psteps for k, (t, c) in prof.items()}
+    mk = mask_infer_model(2 * B, n, levels)
+    conv_ms = per_step.get("m_conv_fwd", 0.0)
+    achieved = mk["m_conv_fwd"][0] / (conv_ms * 1e-3) / 1e9
+    path_b = sum(b for b, _ in mk.values())
+    res = {
+        "metric": f"images/sec, {n}^2 mask-network inference ({levels} levels, running statistics), 1 GPU",
+        "value": 2 * B / (ms * 1e-3),
+        "unit": "images/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 conv (fp32 accumulate)", "data": "synthetic",
+        "config": {"workload": args.workload, "images": 2 * B, "n": n, "levels": levels,
+                   "mask_params": int(net.params.numel())},
+        "roofline": {"bound": "hbm", "kernel": "m_conv_fwd (every convolution of the pass)", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "conv_fwd_mfma": {"achieved": mk["m_conv_fwd"][1] / (conv_ms * 1e-3) / 1e12, "peak": BF16_PEAK_TFLOPS,
+                          "unit": "TFLOP/s", "frac": mk["m_conv_fwd"][1] / (conv_ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS},
+        "roofline_path": {"bytes": path_b, "achieved": path_b / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                          "frac": path_b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "kernels_ms_per_step": {k: round(v, 5) for k, v in sorted(per_step.items())},
+    }
+    if not args.no_cpu_baseline:
+        from oracle import mask_oracle as M
+        th = torch.from_numpy(params).double()
+        run_mean = net.bn_running[:nb].double().cpu()
+        run_var = net.bn_running[nb:].double().cpu()
+        done, t0 = 0, time.perf_counter()
+        while done < 2 * B and (done < 1 or time.perf_counter() - t0 < CPU_SECONDS):
+            x = X[done:done + 1].double().cpu()
+            M.forward_eval(x, th, levels, 8, run_mean, run_var)
+            done += 1
+        dt = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": done / dt, "unit": "images/s", "cores": torch.get_num_threads(),
+                               "cpu": cpu_description(), "kind": "oracle",
+                               "sample": f"{done} images (about {CPU_SECONDS:.0f} s): FP64 oracle inference forward"}
+    print(json.dumps(res), flush=True)
+    return 0
 
 
 def train_bench(args) -> int:

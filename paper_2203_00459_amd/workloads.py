@@ -52,6 +52,14 @@ TRAIN = {
 }
 
 
+# Mask-network inference on the running statistics, the pass the masked ragged
+# launch runs: both scans of each pair through the 4-level network.
+INFER = {
+    # 32 pairs of 512 x 512 scans with distractors: 64 images
+    "mask512_infer": dict(pairs=32, n=512, levels=4, scenes="mask512"),
+}
+
+
 # The configured mask-learning run: a fixed training set, trained for whole
 # epochs under each loss from the same initialisation and data order, judged on
 # held-out pairs against the unmasked search.
