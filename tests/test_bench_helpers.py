@@ -41,3 +41,20 @@ def test_more_than_one_gpu_is_refused_before_any_device_work():
     assert r.returncode == 2
     assert "one GPU only" in r.stderr
     assert r.stdout == ""
+
+
+def test_inference_byte_model_counts_each_fused_tensor_once():
+    """Two levels, one 32 x 32 image, counted by hand: the first convolution
+    reads the FP32 scan, the encoder's second also writes the pooled level-1
+    input, the decoder's first reads the skip activation and the deeper one
+    at its own (quarter) size; the head reads the last activation and writes
+    the FP32 mask."""
+    import bench
+
+    m = bench.mask_infer_model(1, 32, levels=2, base=8)
+    p0, p1 = 32 * 32, 16 * 16
+    conv = ((p0 * 4 + p0 * 16) + (p0 * 16 + p0 * 16 + p1 * 16) + (p1 * 16 + p1 * 32) + (p1 * 32 + p1 * 32)
+            + (p0 * 16 + p1 * 32 + p0 * 16) + (p0 * 16 + p0 * 16))
+    flops = 2 * 9 * (p0 * 1 * 8 + p0 * 8 * 8 + p1 * 8 * 16 + p1 * 16 * 16 + p0 * 24 * 8 + p0 * 8 * 8)
+    assert m["m_conv_fwd"] == (conv, flops)
+    assert m["m_head_fwd"] == (p0 * 16 + p0 * 4, 0.0)
