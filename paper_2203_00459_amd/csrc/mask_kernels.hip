@@ -1560,8 +1560,15 @@ bool launch_wgrad(int cin, int cout, const bf16* dz, const bf16* in, float* part
             }                                                                                        \
         }                                                                                            \
         if (!ok) return false;                                                                       \
-        const int nbc = colsum1(kMWgrad, part, nb, (long long)n, n, tmp, s);                         \
-        FMBYM_LAUNCH(kMWgrad, k_colsum2, dim3(grid_for(n, 256)), dim3(256), s, tmp, nbc, n, 0, n, dw,   \
+        /* up to kColChunks partial rows: the second stage reads them directly (the first would copy \
+           them: one row per chunk), with the same sums */                                           \
+        const float* rows = part;                                                                    \
+        int nbc = nb;                                                                                \
+        if (nb > kColChunks) {                                                                       \
+            nbc = colsum1(kMWgrad, part, nb, (long long)n, n, tmp, s);                               \
+            rows = tmp;                                                                              \
+        }                                                                                            \
+        FMBYM_LAUNCH(kMWgrad, k_colsum2, dim3(grid_for(n, 256)), dim3(256), s, rows, nbc, n, 0, n, dw,  \
                      real_cin, cin);                                                                 \
         return true;                                                                                 \
     }
