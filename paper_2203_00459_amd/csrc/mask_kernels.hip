@@ -750,6 +750,31 @@ __global__ void k_colsum2(const float* __restrict__ tmp, int nbc, int n, int j0,
     out[dest] = (float)s;
 }
 
+// The head's second stage: column j = o (9 C + 1) + r of tmp is dw[o][r] for
+// r < 9 C (the [ch][C][3][3] layout) and db[o] for r = 9 C; each a sum of the
+// chunks in order in double precision, as k_colsum2 adds them.
+__global__ void k_head_colsum2(const float* __restrict__ tmp, int nbc, int n, float* __restrict__ dw,
+                               float* __restrict__ db) {
+    constexpr int NW = 9 * 8 + 1;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double s = 0.0;
+    int c = 0;
+    for (; c + 8 <= nbc; c += 8) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = tmp[(size_t)(c + u) * n + j];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; c < nbc; ++c) s += tmp[(size_t)c * n + j];
+    const int o = j / NW, r = j % NW;
+    if (r < NW - 1)
+        dw[o * (NW - 1) + r] = (float)s;
+    else
+        db[o] = (float)s;
+}
+
 // ------------------------------------------------------------ element-wise
 
 // Scan -> 8-channel BF16 input; image i is x + i S^2, or x_tab[i] for a table of scans.
@@ -1053,6 +1078,11 @@ constexpr int kHeadPix = 4096;   // pixels per head weight-gradient block
 __global__ __launch_bounds__(256) void k_head_wgrad(const float* __restrict__ dl, const bf16* __restrict__ a,
                                                     float* __restrict__ part, int images, int S) {
     constexpr int C = 8, NW = 9 * C + 1;
+    // output channel o = blockIdx.y: its dl plane, and its NW columns of a
+    // partial row that holds every output channel's (row = blockIdx.x)
+    const int o = blockIdx.y;
+    dl += (size_t)o * images * S * S;
+    part += (size_t)blockIdx.x * gridDim.y * NW + (size_t)o * NW;
     float acc[NW];
 #pragma unroll
     for (int j = 0; j < NW; ++j) acc[j] = 0.f;
@@ -1114,7 +1144,7 @@ __global__ __launch_bounds__(256) void k_head_wgrad(const float* __restrict__ dl
     }
     __syncthreads();
     for (int j = threadIdx.x; j < NW; j += kConvThreads)
-        part[(size_t)blockIdx.x * NW + j] = red[0][j] + red[1][j] + red[2][j] + red[3][j];
+        part[j] = red[0][j] + red[1][j] + red[2][j] + red[3][j];
 }
 
 // Per-block channel sums for the batch-norm adjoint: part[block][0][c] = sum dy,
@@ -1631,13 +1661,12 @@ void launch_head_bwd(const float* d_mask, const float* mask, const bf16* a, cons
     const long long n = (long long)images * S * S;
     FMBYM_LAUNCH(kMHeadBwd, k_head_dl, dim3(grid_for(n * ch, 256)), dim3(256), s, d_mask, mask, dl, n * ch);
     FMBYM_LAUNCH(kMHeadBwd, k_head_g, dim3(grid_for(n, 256)), dim3(256), s, dl, w, g, images, S, ch);
+    // every output channel in one launch (blockIdx.y), its partials in its own
+    // columns of each block's row; the column sums as one array of ch NW columns
     const int nb = (int)((n + kHeadPix - 1) / kHeadPix), NW = 9 * C + 1;
-    for (int o = 0; o < ch; ++o) {   // one output channel's weights and bias at a time
-        FMBYM_LAUNCH(kMHeadBwd, k_head_wgrad, dim3(nb), dim3(256), s, dl + o * n, a, part, images, S);
-        const int nbc = colsum1(kMHeadBwd, part, nb, (long long)NW, NW, tmp, s);
-        FMBYM_LAUNCH(kMHeadBwd, k_colsum2, dim3(1), dim3(128), s, tmp, nbc, NW, 0, 9 * C, dw + o * 9 * C, 0, 0);
-        FMBYM_LAUNCH(kMHeadBwd, k_colsum2, dim3(1), dim3(64), s, tmp, nbc, NW, 9 * C, 1, db + o, 0, 0);
-    }
+    FMBYM_LAUNCH(kMHeadBwd, k_head_wgrad, dim3(nb, ch), dim3(256), s, dl, a, part, images, S);
+    const int nbc = colsum1(kMHeadBwd, part, nb, (long long)ch * NW, ch * NW, tmp, s);
+    FMBYM_LAUNCH(kMHeadBwd, k_head_colsum2, dim3(1), dim3(256), s, tmp, nbc, ch * NW, dw, db);
 }
 
 void launch_bn_relu_bwd(const float* g, const bf16* z, const float* stat, const float* gamma, float* part,

@@ -174,7 +174,7 @@ WsLayout ws_layout(const Net& net, int I, int n) {
     L.coef = b.take(3 * 256 * fl);   // per-channel coefficients of the widest BN layer
     L.wpart = b.take(wpart_max);
     L.dl = b.take(pix(0) * net.chans * fl);
-    L.hpart = b.take(((pix(0) + 4095) / 4096) * (9 * net.base + 1) * fl);
+    L.hpart = b.take(((pix(0) + 4095) / 4096) * net.chans * (9 * net.base + 1) * fl);   // rows of every output channel
     size_t cols = 2 * 256;
     for (const ConvL& c : net.convs) cols = std::max(cols, (size_t)c.cout * 9 * c.cink);
     L.tmp = b.take(colsum_tmp_floats((int)cols) * fl);
