@@ -908,24 +908,38 @@ __global__ void k_bn_relu(const bf16* __restrict__ z, const float* __restrict__ 
     *(u32x4*)(a + it * 8) = __builtin_bit_cast(u32x4, o);
 }
 
-__global__ void k_maxpool(const bf16* __restrict__ in, bf16* __restrict__ out, int images, int S,
-                          int C) {
+// BN + ReLU of an encoder's second convolution and the 2 x 2 max pooling of
+// its result in one pass: one thread per (pooled pixel, 8-channel group)
+// writes the four activations and their maximum (the max of the window's
+// BF16 values taken in FP32, exact), with k_bn_relu's arithmetic.
+__global__ void k_bn_relu_pool(const bf16* __restrict__ z, const float* __restrict__ stat, bf16* __restrict__ a,
+                               bf16* __restrict__ pool, int images, int S, int C) {
     const int H = S / 2, G8 = C / 8;
     const long long it = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (it >= (long long)images * H * H * G8) return;
     const int cg = (int)(it % G8);
     const long long q = it / G8;
     const int X = (int)(q % H), Y = (int)((q / H) % H), img = (int)(q / ((long long)H * H));
-    const bf16* b = in + (((size_t)img * S + 2 * Y) * S + 2 * X) * C + 8 * cg;
-    const bf16x8 v00 = __builtin_bit_cast(bf16x8, *(const u32x4*)b);
-    const bf16x8 v01 = __builtin_bit_cast(bf16x8, *(const u32x4*)(b + C));
-    const bf16x8 v10 = __builtin_bit_cast(bf16x8, *(const u32x4*)(b + (size_t)S * C));
-    const bf16x8 v11 = __builtin_bit_cast(bf16x8, *(const u32x4*)(b + (size_t)S * C + C));
+    const size_t p00 = (((size_t)img * S + 2 * Y) * S + 2 * X) * C + 8 * cg;
+    const size_t off[4] = {0, (size_t)C, (size_t)S * C, (size_t)S * C + C};
+    float sc[8], sh[8];
+    load8(stat + 2 * C + 8 * cg, sc);
+    load8(stat + 3 * C + 8 * cg, sh);
+    bf16x8 v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = __builtin_bit_cast(bf16x8, *(const u32x4*)(z + p00 + off[k]));
+    bf16x8 h[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) h[k][j] = (bf16)fmaxf(fmaf((float)v[k][j], sc[j], sh[j]), 0.f);
+        *(u32x4*)(a + p00 + off[k]) = __builtin_bit_cast(u32x4, h[k]);
+    }
     bf16x8 o;
 #pragma unroll
     for (int j = 0; j < 8; ++j)
-        o[j] = (bf16)fmaxf(fmaxf((float)v00[j], (float)v01[j]), fmaxf((float)v10[j], (float)v11[j]));
-    *(u32x4*)(out + q * C + 8 * cg) = __builtin_bit_cast(u32x4, o);
+        o[j] = (bf16)fmaxf(fmaxf((float)h[0][j], (float)h[1][j]), fmaxf((float)h[2][j], (float)h[3][j]));
+    *(u32x4*)(pool + q * C + 8 * cg) = __builtin_bit_cast(u32x4, o);
 }
 
 __global__ void k_up_concat(const bf16* __restrict__ d, const bf16* __restrict__ e, bf16* __restrict__ cat,
@@ -1634,9 +1648,10 @@ void launch_bn_relu(const bf16* z, const float* stat, bf16* a, long long M, int 
     FMBYM_LAUNCH(kMBnRelu, k_bn_relu, dim3(grid_for(items, 256)), dim3(256), s, z, stat, a, items, C);
 }
 
-void launch_maxpool(const bf16* in, bf16* out, int images, int S, int C, hipStream_t s) {
+void launch_bn_relu_pool(const bf16* z, const float* stat, bf16* a, bf16* pool, int images, int S, int C,
+                         hipStream_t s) {
     const long long items = (long long)images * (S / 2) * (S / 2) * (C / 8);
-    FMBYM_LAUNCH(kMPool, k_maxpool, dim3(grid_for(items, 256)), dim3(256), s, in, out, images, S, C);
+    FMBYM_LAUNCH(kMBnRelu, k_bn_relu_pool, dim3(grid_for(items, 256)), dim3(256), s, z, stat, a, pool, images, S, C);
 }
 
 void launch_up_concat(const bf16* d, const bf16* e, bf16* cat, int images, int S, int Cd, int Ce,

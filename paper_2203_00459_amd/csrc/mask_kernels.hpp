@@ -117,8 +117,10 @@ void launch_bn_stats(const float* part, int nb, int C, long long M, const float*
 // a = relu(z scale + shift) per channel, bf16 -> bf16.
 void launch_bn_relu(const bf16* z, const float* stat, bf16* a, long long M, int C, hipStream_t s);
 
-// 2x2 max-pool, [I][S][S][C] -> [I][S/2][S/2][C].
-void launch_maxpool(const bf16* in, bf16* out, int images, int S, int C, hipStream_t s);
+// a = BN + ReLU of z (as launch_bn_relu) and pool = its 2 x 2 max pooling in
+// one pass; z, a [I][S][S][C], pool [I][S/2][S/2][C].
+void launch_bn_relu_pool(const bf16* z, const float* stat, bf16* a, bf16* pool, int images, int S, int C,
+                         hipStream_t s);
 
 // cat = [up2(d), e] with d [I][S/2][S/2][Cd], e [I][S][S][Ce] -> [I][S][S][Cd + Ce].
 void launch_up_concat(const bf16* d, const bf16* e, bf16* cat, int images, int S, int Cd, int Ce,

@@ -478,9 +478,7 @@ int mask_forward(const fmbym_mask_desc* d, int I, int n, const float* x, const f
         if (j == 0) {
             in = at<bf16>(act, A.x8);
         } else if (c.enc && c.first_of_level) {
-            launch_maxpool(at<bf16>(act, A.a[net.enc_b(c.level - 1)]), at<bf16>(act, A.pool[c.level]), I,
-                           n >> (c.level - 1), net.ch(c.level - 1), s);
-            in = at<bf16>(act, A.pool[c.level]);
+            in = at<bf16>(act, A.pool[c.level]);   // written by the previous level's BN + ReLU pass
         } else if (!c.enc && c.first_of_level) {
             launch_up_concat(at<bf16>(act, A.a[net.deeper(c.level)]), at<bf16>(act, A.a[net.enc_b(c.level)]),
                              at<bf16>(act, A.cat[c.level]), I, S, net.ch(c.level + 1), net.ch(c.level), s);
@@ -495,7 +493,11 @@ int mask_forward(const fmbym_mask_desc* d, int I, int n, const float* x, const f
         launch_bn_stats(at<float>(act, A.part), conv_part_blocks(I, S), c.cout, M, d->params + c.gamma,
                         d->params + c.beta, net.eps, net.momentum, 1, run_mean + c.bn,
                         run_var + c.bn, at<float>(act, A.stat[j]), at<float>(act, A.tmp), s);
-        launch_bn_relu(at<bf16>(act, A.z[j]), at<float>(act, A.stat[j]), at<bf16>(act, A.a[j]), M, c.cout, s);
+        if (c.enc && !c.first_of_level && c.level + 1 < net.levels)   // with the next level's input
+            launch_bn_relu_pool(at<bf16>(act, A.z[j]), at<float>(act, A.stat[j]), at<bf16>(act, A.a[j]),
+                                at<bf16>(act, A.pool[c.level + 1]), I, S, c.cout, s);
+        else
+            launch_bn_relu(at<bf16>(act, A.z[j]), at<float>(act, A.stat[j]), at<bf16>(act, A.a[j]), M, c.cout, s);
     }
     if (!launch_head_fwd(at<bf16>(act, A.a[net.last()]), d->params + net.head_w, d->params + net.head_b, mask, I,
                          n, net.base, net.chans, s))
