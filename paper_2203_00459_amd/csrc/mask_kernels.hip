@@ -1042,18 +1042,17 @@ __global__ __launch_bounds__(256) void k_head_fwd(const bf16* __restrict__ a, co
     }
 }
 
-__global__ void k_head_dl(const float* __restrict__ dm, const float* __restrict__ m, float* __restrict__ dl,
-                          long long n) {
-    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const float v = m[p];
-    dl[p] = dm[p] * v * (1.f - v);
+// The head's logit gradient dl = d_mask m (1 - m) (the sigmoid's derivative),
+// formed where it is read from the mask gradient and the saved mask.
+__device__ __forceinline__ float head_dl(float dm, float m) {
+#pragma clang fp contract(off)
+    return dm * m * (1.f - m);
 }
 
 // g[p][ci] = sum_o sum_taps w[o][ci][tap] dl[o][p - (ky - 1, kx - 1)], one pixel
 // (8 channels) per thread, output channels o in order.
-__global__ void k_head_g(const float* __restrict__ dl, const float* __restrict__ w, float* __restrict__ g,
-                         int images, int S, int ch) {
+__global__ void k_head_g(const float* __restrict__ dm, const float* __restrict__ m, const float* __restrict__ w,
+                         float* __restrict__ g, int images, int S, int ch) {
     const long long npix = (long long)images * S * S;
     const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npix) return;
@@ -1063,17 +1062,21 @@ __global__ void k_head_g(const float* __restrict__ dl, const float* __restrict__
     for (int j = 0; j < 8; ++j) acc[j] = 0.f;
     for (int o = 0; o < ch; ++o) {
         const float* wo = w + (size_t)o * 8 * 9;
-        const float* dlo = dl + o * npix;
-        // the nine loads first (clamped addresses), then the taps inside the image in order
-        float d[9];
+        const float* dmo = dm + o * npix;
+        const float* mo = m + o * npix;
+        // the loads first (clamped addresses), then the taps inside the image in order
+        float dv[9], mv[9], d[9];
         unsigned inb = 0;
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
             const int yy = y - (k / 3 - 1), xx = x - (k % 3 - 1);
             inb |= (yy >= 0 && yy < S && xx >= 0 && xx < S ? 1u : 0u) << k;
             const int yc = min(max(yy, 0), S - 1), xc = min(max(xx, 0), S - 1);
-            d[k] = dlo[((size_t)img * S + yc) * S + xc];
+            dv[k] = dmo[((size_t)img * S + yc) * S + xc];
+            mv[k] = mo[((size_t)img * S + yc) * S + xc];
         }
+#pragma unroll
+        for (int k = 0; k < 9; ++k) d[k] = head_dl(dv[k], mv[k]);
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
             if (!((inb >> k) & 1u)) continue;
@@ -1089,13 +1092,15 @@ __global__ void k_head_g(const float* __restrict__ dl, const float* __restrict__
 constexpr int kHeadPix = 4096;   // pixels per head weight-gradient block
 
 // part[block][ci 9 + tap] = sum dl[p] a[p + tap][ci]; part[block][9 C] = sum dl.
-__global__ __launch_bounds__(256) void k_head_wgrad(const float* __restrict__ dl, const bf16* __restrict__ a,
-                                                    float* __restrict__ part, int images, int S) {
+__global__ __launch_bounds__(256) void k_head_wgrad(const float* __restrict__ dm, const float* __restrict__ m,
+                                                    const bf16* __restrict__ a, float* __restrict__ part,
+                                                    int images, int S) {
     constexpr int C = 8, NW = 9 * C + 1;
-    // output channel o = blockIdx.y: its dl plane, and its NW columns of a
-    // partial row that holds every output channel's (row = blockIdx.x)
+    // output channel o = blockIdx.y: its mask and mask-gradient planes, and its
+    // NW columns of a partial row that holds every output channel's (row = blockIdx.x)
     const int o = blockIdx.y;
-    dl += (size_t)o * images * S * S;
+    dm += (size_t)o * images * S * S;
+    m += (size_t)o * images * S * S;
     part += (size_t)blockIdx.x * gridDim.y * NW + (size_t)o * NW;
     float acc[NW];
 #pragma unroll
@@ -1106,14 +1111,15 @@ __global__ __launch_bounds__(256) void k_head_wgrad(const float* __restrict__ dl
     // One pixel's nine taps: every load issued at a clamped address, the taps
     // outside the image then skipped by selects (the same sums as branching).
     struct Taps {
-        float d;
+        float dm, m;
         u32x4 v[9];
         unsigned inb;
     };
     auto load = [&](long long p) {
         Taps t;
         const int x = (int)(p % S), y = (int)((p / S) % S), img = (int)(p / ((long long)S * S));
-        t.d = dl[p];
+        t.dm = dm[p];
+        t.m = m[p];
         t.inb = 0;
 #pragma unroll
         for (int ky = 0; ky < 3; ++ky)
@@ -1128,14 +1134,18 @@ __global__ __launch_bounds__(256) void k_head_wgrad(const float* __restrict__ dl
         return t;
     };
     auto add = [&](const Taps& t) {
-        acc[NW - 1] += t.d;
+        const float d = head_dl(t.dm, t.m);
+        {
+#pragma clang fp contract(off)
+            acc[NW - 1] += d;   // d rounded, then added: not fused into its product
+        }
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
             const bf16x8 v = __builtin_bit_cast(bf16x8, t.v[k]);
             const bool in = (t.inb >> k) & 1u;
 #pragma unroll
             for (int j = 0; j < C; ++j) {
-                const float r = fmaf(t.d, (float)v[j], acc[j * 9 + k]);
+                const float r = fmaf(d, (float)v[j], acc[j * 9 + k]);
                 acc[j * 9 + k] = in ? r : acc[j * 9 + k];
             }
         }
@@ -1670,16 +1680,15 @@ bool launch_head_fwd(const bf16* a, const float* w, const float* b, float* mask,
     return true;
 }
 
-void launch_head_bwd(const float* d_mask, const float* mask, const bf16* a, const float* w, float* dl,
-                     float* g, float* part, float* tmp, float* dw, float* db, int images, int S, int C, int ch,
+void launch_head_bwd(const float* d_mask, const float* mask, const bf16* a, const float* w, float* g,
+                     float* part, float* tmp, float* dw, float* db, int images, int S, int C, int ch,
                      hipStream_t s) {
     const long long n = (long long)images * S * S;
-    FMBYM_LAUNCH(kMHeadBwd, k_head_dl, dim3(grid_for(n * ch, 256)), dim3(256), s, d_mask, mask, dl, n * ch);
-    FMBYM_LAUNCH(kMHeadBwd, k_head_g, dim3(grid_for(n, 256)), dim3(256), s, dl, w, g, images, S, ch);
+    FMBYM_LAUNCH(kMHeadBwd, k_head_g, dim3(grid_for(n, 256)), dim3(256), s, d_mask, mask, w, g, images, S, ch);
     // every output channel in one launch (blockIdx.y), its partials in its own
     // columns of each block's row; the column sums as one array of ch NW columns
     const int nb = (int)((n + kHeadPix - 1) / kHeadPix), NW = 9 * C + 1;
-    FMBYM_LAUNCH(kMHeadBwd, k_head_wgrad, dim3(nb, ch), dim3(256), s, dl, a, part, images, S);
+    FMBYM_LAUNCH(kMHeadBwd, k_head_wgrad, dim3(nb, ch), dim3(256), s, d_mask, mask, a, part, images, S);
     const int nbc = colsum1(kMHeadBwd, part, nb, (long long)ch * NW, ch * NW, tmp, s);
     FMBYM_LAUNCH(kMHeadBwd, k_head_colsum2, dim3(1), dim3(256), s, tmp, nbc, ch * NW, dw, db);
 }

@@ -131,12 +131,12 @@ void launch_up_concat(const bf16* d, const bf16* e, bf16* cat, int images, int S
 // false unless C = 8 (the base width).
 bool launch_head_fwd(const bf16* a, const float* w, const float* b, float* mask, int images, int S,
                      int C, int ch, hipStream_t s);
-// Head adjoint: dl = d_mask m (1 - m) ([ch][I][S][S]); g [I][S][S][C] float =
-// conv3x3^T(dl, w); dw [ch][C][3][3] and db [ch] (float, written) through
-// per-block partials in part.
-void launch_head_bwd(const float* d_mask, const float* mask, const bf16* a, const float* w,
-                     float* dl, float* g, float* part, float* tmp, float* dw, float* db, int images, int S,
-                     int C, int ch, hipStream_t s);
+// Head adjoint: with dl = d_mask m (1 - m) ([ch][I][S][S], formed where read),
+// g [I][S][S][C] float = conv3x3^T(dl, w); dw [ch][C][3][3] and db [ch] (float,
+// written) through per-block partials in part.
+void launch_head_bwd(const float* d_mask, const float* mask, const bf16* a, const float* w, float* g,
+                     float* part, float* tmp, float* dw, float* db, int images, int S, int C, int ch,
+                     hipStream_t s);
 
 // Batch-norm + ReLU adjoint given g = dL/da (float): dy = g [a > 0];
 // dgamma = sum dy xhat, dbeta = sum dy (written to dgamma/dbeta);

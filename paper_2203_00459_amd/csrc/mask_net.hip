@@ -146,7 +146,7 @@ ActLayout act_layout(const Net& net, int I, int n) {
 }
 
 struct WsLayout {
-    size_t dz[2] = {0, 0}, part = 0, coef = 0, wpart = 0, dl = 0, hpart = 0, tmp = 0, total = 0;
+    size_t dz[2] = {0, 0}, part = 0, coef = 0, wpart = 0, hpart = 0, tmp = 0, total = 0;
     std::vector<size_t> g, dpool, dcat;
 };
 
@@ -173,7 +173,6 @@ WsLayout ws_layout(const Net& net, int I, int n) {
     L.part = b.take(part_max);
     L.coef = b.take(3 * 256 * fl);   // per-channel coefficients of the widest BN layer
     L.wpart = b.take(wpart_max);
-    L.dl = b.take(pix(0) * net.chans * fl);
     L.hpart = b.take(((pix(0) + 4095) / 4096) * net.chans * (9 * net.base + 1) * fl);   // rows of every output channel
     size_t cols = 2 * 256;
     for (const ConvL& c : net.convs) cols = std::max(cols, (size_t)c.cout * 9 * c.cink);
@@ -329,7 +328,7 @@ int fmbym_mask_bwd(const fmbym_mask_desc* d, int32_t I, int32_t n, const float* 
         return rc;
     };
     launch_head_bwd(d_mask, at<float>(act, A.mask), at<bf16>(act, A.a[last]), P + net.head_w,
-                    at<float>(wsp, W.dl), at<float>(wsp, W.g[last]), at<float>(wsp, W.hpart),
+                    at<float>(wsp, W.g[last]), at<float>(wsp, W.hpart),
                     at<float>(wsp, W.tmp), d_params + net.head_w, d_params + net.head_b, I, n, net.base,
                     net.chans, s);
     for (int j = last; j >= 0; --j) {
