@@ -1021,8 +1021,8 @@ __global__ __launch_bounds__(256) void k_head_fwd(const bf16* __restrict__ a, co
     for (int o = 0; o < ch; ++o) {
         const float bo = b[o];
         float acc[4] = {bo, bo, bo, bo};
-#pragma unroll
-        for (int t = 0; t < 9; ++t) {
+#pragma unroll 1
+        for (int t = 0; t < 9; ++t) {   // one tap at a time (fewer operands live at once)
 #pragma unroll
             for (int cg = 0; cg < G; ++cg) {
                 const f32x4 w0 = wl[((o * 9 + t) * C + 8 * cg) / 4], w1 = wl[((o * 9 + t) * C + 8 * cg) / 4 + 1];
