@@ -137,8 +137,8 @@ def kernel_bytes(n: int, n_theta: int, n_r: int, batch: int, masked: bool, keep:
 
 
 def pass_model_bytes(n: int) -> dict:
-    """HBM bytes per pair of each kernel on the pass model of the survey's
-    byte derivation (fp32 data, complex64 intermediates, ZeroPad to 2n, every
+    """HBM bytes per pair of each kernel on the pass model of the method's
+    steps (fp32 data, complex64 intermediates, ZeroPad to 2n, every
     pass reading its inputs and writing its outputs once).  These are the
     figures the roofline's `achieved` uses; the library's own per-launch model
     (``kernel_bytes``: 3n/2 padding, the passes as this library fuses them) is

@@ -7,7 +7,7 @@ the pose loss against the known poses, the search's adjoint down to the masks,
 the network's adjoint down to its parameters, and an Adam update.  Every
 stage runs in the library's kernels; this module only sequences the calls.
 
-The unmasked search is the fallback and the judge: ``evaluate`` reports the
+The unmasked search is the fallback and the yardstick: ``evaluate`` reports the
 pose error of both searches on held-out pairs, and ``use_mask`` is only set
 once the masked search has beaten the unmasked one there.
 """
@@ -103,7 +103,7 @@ class MaskedSearchTrainer:
             return float(d[:, 0].abs().mean()), float(d[:, 1:].norm(dim=1).mean())
 
         em, eu = err(pm), err(pu)
-        # the judge: translation error first (the paper's drift metric), heading as a tie-break
+        # the comparison: translation error first (the paper's drift metric), heading as a tie-break
         self.use_mask = (em[1], em[0]) < (eu[1], eu[0])
         return {"masked_theta": em[0], "masked_t": em[1], "unmasked_theta": eu[0], "unmasked_t": eu[1],
                 "use_mask": self.use_mask}
