@@ -277,12 +277,12 @@ inline int conv_chunk(int cout, int blocks) {
 }
 
 // Waves per SIMD the compiler must leave room for, where measured faster than
-// its own register choice (1: no constraint): the 24-channel up-concat
-// inference convolution at 4 (361 against 403 us at 64 x 512^2, no spills) and
-// the 8-channel pooling one at 6 (154 against 165 us).  Others lost time or
-// spilled at a higher count.
+// its own register choice (1: no constraint): the 24- and 48-channel up-concat
+// inference convolutions at 4 (361 against 403 us and 212 against 238 us at
+// 64 x 512^2; the 48-channel one spills 8 bytes) and the 8-channel pooling one
+// at 6 (154 against 165 us).  Others lost time or spilled more at a higher count.
 constexpr int conv_waves(int cin, int mode, int src, bool pool) {
-    return mode != kConvInfer ? 1 : (src == kSrcUpCat && cin == 24 ? 4 : (pool && cin == 8 ? 6 : 1));
+    return mode != kConvInfer ? 1 : (src == kSrcUpCat && (cin == 24 || cin == 48) ? 4 : (pool && cin == 8 ? 6 : 1));
 }
 
 template <int CIN, int COUT, int MODE, int CO_ = co_chunk(COUT), int SRC = kSrcPlain, bool POOL = false>
