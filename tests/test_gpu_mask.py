@@ -122,7 +122,8 @@ def test_input_gradient_matches_oracle(levels, scene, images):
     assert eg <= 2 * eq + 1e-3
 
 
-@pytest.mark.parametrize("levels,scene,images", [(2, "pair128", 4), (4, "mask256", 16)])
+@pytest.mark.parametrize("levels,scene,images", [(1, "pair128", 4), (2, "pair128", 4), (3, "pair128", 4), (4, "pair128", 4),
+                                                (4, "mask256", 16)])
 def test_running_statistics_and_eval_mode(levels, scene, images):
     x = _scans(scene, images)
     p, net = _gpu_net(levels, seed=2)
