@@ -196,8 +196,12 @@ def running_stats(x, theta, levels: int, base: int, run_mean, run_var, momentum:
     return (1 - momentum) * run_mean + momentum * mu, (1 - momentum) * run_var + momentum * var
 
 
-def forward_eval(x, theta, levels: int, base: int, run_mean, run_var, eps: float = 1e-5, ch: int = 1):
-    """Masks with BatchNorm on the given running statistics (inference)."""
+def forward_eval(x, theta, levels: int, base: int, run_mean, run_var, eps: float = 1e-5, ch: int = 1,
+                 quant: bool = False):
+    """Masks with BatchNorm on the given running statistics (inference).
+    quant=True stores in bfloat16 what the training forward's quant mode
+    stores (the scan, the conv weights, every conv output, activation and
+    upsampled tensor); the arithmetic stays FP64."""
     P = unpack(theta, levels, base, ch)
     stats, o = {}, 0
     for c in conv_list(levels, base, ch):
@@ -206,17 +210,17 @@ def forward_eval(x, theta, levels: int, base: int, run_mean, run_var, eps: float
 
     def cbr(h, name):
         w, g, b = P[name]
-        z = F.conv2d(h, w, padding=1)
-        return F.relu(F.batch_norm(z, *stats[name], g, b, training=False, eps=eps))
+        z = bf16(F.conv2d(h, bf16(w, quant), padding=1), quant)
+        return bf16(F.relu(F.batch_norm(z, *stats[name], g, b, training=False, eps=eps)), quant)
 
-    h, skips = _as_channels(x, ch), []
+    h, skips = bf16(_as_channels(x, ch), quant), []
     for l in range(levels):
         if l > 0:
             h = F.max_pool2d(h, 2)
         h = cbr(cbr(h, f"enc{l}a"), f"enc{l}b")
         skips.append(h)
     for l in range(levels - 2, -1, -1):
-        h = torch.cat([up2(h), skips[l]], dim=1)
+        h = torch.cat([bf16(up2(h), quant), skips[l]], dim=1)
         h = cbr(cbr(h, f"dec{l}a"), f"dec{l}b")
     wh, bh = P["head"]
     return _from_channels(torch.sigmoid(F.conv2d(h, wh, bh, padding=1)), ch)

@@ -137,8 +137,15 @@ def test_running_statistics_and_eval_mode(levels, scene, images):
     # eval mode normalises with the given running statistics
     me = net.forward(torch.from_numpy(x).to(DEV), training=False).double().cpu()
     ref_e = M.forward_eval(X, P, levels, 8, torch.tensor(rm0), torch.tensor(rv0))
-    print(f"eval mode: max {(me - ref_e).abs().max():.3e} mean {(me - ref_e).abs().mean():.3e}", flush=True)
-    assert float((me - ref_e).abs().max()) <= 5e-2 and float((me - ref_e).abs().mean()) <= 5e-3
+    # the bar of the training forward: as close to the exact masks as the same
+    # pass with the library's BF16 storage is, plus a term for FP32 arithmetic
+    ref_q = M.forward_eval(X, P, levels, 8, torch.tensor(rm0), torch.tensor(rv0), quant=True)
+    nr = float(ref_e.norm())
+    eg, eq = float((me - ref_e).norm()) / nr, float((ref_q - ref_e).norm()) / nr
+    mg, mq = float((me - ref_e).abs().max()), float((ref_q - ref_e).abs().max())
+    print(f"eval mode: |gpu-exact| {eg:.3e} |quant-exact| {eq:.3e} (normwise); max {mg:.3e} / {mq:.3e}", flush=True)
+    assert eg <= 2 * eq + 1e-3
+    assert mg <= 2 * mq + 1e-3
     # a training pass moves them by the momentum towards the batch statistics
     net.forward(torch.from_numpy(x).to(DEV), training=True)
     got = net.bn_running.double().cpu()

@@ -318,6 +318,26 @@ def test_forward_eval_on_the_batch_statistics_is_the_training_forward():
     assert float((other - m).abs().max()) > 1e-3
 
 
+def test_quant_forward_eval_on_the_batch_statistics_is_the_quant_training_forward():
+    # the same identity with BF16 storage: on the statistics of the stored z,
+    # inference rounds at the training forward's points and gives its masks;
+    # and the rounding is there (the quant masks differ from the exact ones)
+    r = _rng(16)
+    L, base = 3, 4
+    x = torch.tensor(r.random((3, 16, 16)) * 3.0, dtype=DT)
+    th = torch.tensor(M.init_params(L, base, seed=5), dtype=DT)
+    m, acts = M.forward(x, th, L, base, keep=True, quant=True)
+    means, vars_ = [], []
+    for c in M.conv_list(L, base):
+        mu, var = M.batch_stats(acts[f"{c.name}.z"])
+        means.append(mu)
+        vars_.append(var)
+    got = M.forward_eval(x, th, L, base, torch.cat(means), torch.cat(vars_), quant=True)
+    assert torch.allclose(got, m, rtol=0, atol=1e-12)
+    exact = M.forward_eval(x, th, L, base, torch.cat(means), torch.cat(vars_))
+    assert float((exact - m).abs().max()) > 1e-5
+
+
 def test_quant_forward_rounds_at_the_documented_points_by_hand():
     # one level, centre taps: the stored values are bf16(x), bf16(w), bf16(z) and
     # bf16(relu(BN(z))) with BN on the stored z; the head stays unrounded
