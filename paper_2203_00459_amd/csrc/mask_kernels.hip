@@ -1348,31 +1348,50 @@ __device__ __forceinline__ void up_taps(int q, int n, int* o, float* w) {
     w[3] = q <= n - 2 ? 0.25f : 0.f;
 }
 
-__global__ void k_up_bwd(const float* __restrict__ d_cat, float* __restrict__ d_d, int images, int S,
-                         int Cd, int Ce) {
-    const int H = S / 2, C = Cd + Ce, G8 = Cd / 8;
-    const long long it = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (it >= (long long)images * H * H * G8) return;
-    const int cg = (int)(it % G8);
-    const long long q = it / G8;
-    const int X = (int)(q % H), Y = (int)((q / H) % H), img = (int)(q / ((long long)H * H));
+// A block takes a TH x TW tile of low-resolution pixels (TW = min(32, H),
+// TH = 256 / TW) and gpb of its 8-channel groups (from blockIdx.y gpb) one
+// after another, all of them when the tiles alone fill the GPU: for each, the
+// full-resolution rows 2 Y0 - 1 .. 2 (Y0 + TH) and columns likewise, clamped
+// to the image, are staged in LDS first (each value read once from memory
+// instead of by up to four taps), then each thread sums its pixel's sixteen
+// taps as below.
+__global__ __launch_bounds__(256) void k_up_bwd(const float* __restrict__ d_cat, float* __restrict__ d_d,
+                                                int images, int S, int Cd, int Ce, int gpb) {
+    const int H = S / 2, C = Cd + Ce;
+    const int TW = H < 32 ? H : 32, TH = 256 / TW, RW = 2 * TW + 2, RH = 2 * TH + 2;
+    const int tiles_x = H / TW, tiles_y = H / TH;
+    const int img = blockIdx.x / (tiles_x * tiles_y), k = blockIdx.x % (tiles_x * tiles_y);
+    const int Y0 = (k / tiles_x) * TH, X0 = (k % tiles_x) * TW;
+    const int ry0 = 2 * Y0 - 1, rx0 = 2 * X0 - 1;
+    extern __shared__ float4 stg[];   // [RH][RW][2]
+    const int Y = Y0 + threadIdx.x / TW, X = X0 + threadIdx.x % TW;
     // the four output rows and columns that can read input (Y, X), in order;
-    // the ones outside get weight 0 and a clamped address, so all sixteen
-    // taps' loads issue together (adding 0 w leaves the same sums)
+    // the ones outside get weight 0 and a clamped index (adding 0 w leaves the same sums)
     int oy[4], ox[4];
     float wy[4], wx[4];
     up_taps(Y, H, oy, wy);
     up_taps(X, H, ox, wx);
-    float4 u[4][4][2];
+    for (int cg = blockIdx.y * gpb; cg < (blockIdx.y + 1) * gpb; ++cg) {
+    if (cg != blockIdx.y * gpb) __syncthreads();   // the previous group's taps have been read
+    // every staged value's loads first, then the LDS stores
+    constexpr int NL = 10;   // ceil(2 * 34 * 34 / 256) and ceil(2 * 18 * 66 / 256)
+    float4 v[NL];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const float4* src =
-                reinterpret_cast<const float4*>(d_cat + (((size_t)img * S + oy[a]) * S + ox[b]) * C + 8 * cg);
-            u[a][b][0] = src[0];
-            u[a][b][1] = src[1];
+    for (int l = 0; l < NL; ++l) {
+        const int it = threadIdx.x + 256 * l;
+        v[l] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (it < RH * RW * 2) {
+            const int e = it >> 1, h = it & 1;
+            const int y = min(max(ry0 + e / RW, 0), S - 1), x = min(max(rx0 + e % RW, 0), S - 1);
+            v[l] = reinterpret_cast<const float4*>(d_cat + (((size_t)img * S + y) * S + x) * C + 8 * cg)[h];
         }
+    }
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+        const int it = threadIdx.x + 256 * l;
+        if (it < RH * RW * 2) stg[it] = v[l];
+    }
+    __syncthreads();
     float acc[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) acc[j] = 0.f;
@@ -1383,17 +1402,19 @@ __global__ void k_up_bwd(const float* __restrict__ d_cat, float* __restrict__ d_
         for (int j = 0; j < 8; ++j) row[j] = 0.f;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            const float vals[8] = {u[a][b][0].x, u[a][b][0].y, u[a][b][0].z, u[a][b][0].w,
-                                   u[a][b][1].x, u[a][b][1].y, u[a][b][1].z, u[a][b][1].w};
+            const int e = (oy[a] - ry0) * RW + ox[b] - rx0;
+            const float4 u0 = stg[2 * e], u1 = stg[2 * e + 1];
+            const float vals[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
 #pragma unroll
             for (int j = 0; j < 8; ++j) row[j] = fmaf(wx[b], vals[j], row[j]);
         }
 #pragma unroll
         for (int j = 0; j < 8; ++j) acc[j] = fmaf(wy[a], row[j], acc[j]);
     }
-    float4* o = reinterpret_cast<float4*>(d_d + q * Cd + 8 * cg);
+    float4* o = reinterpret_cast<float4*>(d_d + (((size_t)img * H + Y) * H + X) * Cd + 8 * cg);
     o[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
     o[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
+    }   // channel groups
 }
 
 __global__ void k_pack(const PackLayers t, const float* __restrict__ params, bf16* __restrict__ packed) {
@@ -1714,8 +1735,11 @@ void launch_pool_bwd(const float* d_pool, const bf16* e, const float* skip, int 
 }
 
 void launch_up_bwd(const float* d_cat, float* d_d, int images, int S, int Cd, int Ce, hipStream_t s) {
-    const long long n = (long long)images * (S / 2) * (S / 2) * (Cd / 8);
-    FMBYM_LAUNCH(kMUpBwd, k_up_bwd, dim3(grid_for(n, 256)), dim3(256), s, d_cat, d_d, images, S, Cd, Ce);
+    const int H = S / 2, TW = H < 32 ? H : 32, TH = 256 / TW;
+    const int tiles = images * (H / TW) * (H / TH), gpb = tiles >= 1024 ? Cd / 8 : 1;
+    const dim3 grid(tiles, Cd / 8 / gpb);
+    const size_t lds = (size_t)(2 * TH + 2) * (2 * TW + 2) * 32;
+    FMBYM_LAUNCH_LDS(kMUpBwd, k_up_bwd, grid, dim3(256), lds, s, d_cat, d_d, images, S, Cd, Ce, gpb);
 }
 
 void launch_pack(const PackLayers& t, const float* params, bf16* packed, hipStream_t s) {
