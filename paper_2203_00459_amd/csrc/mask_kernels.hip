@@ -554,6 +554,8 @@ __host__ __device__ constexpr int wg_plane(int S) { return wg_rows(S) * wg_pitch
 // output channels of chunk blockIdx.y:
 // part[block][co][tap CIN + ci] = sum over the tiles' pixels of dz[p][co] in[p + tap][ci].
 // M = output channels, K = pixels (8 per lane: one tile row), N = (tap, ci).
+// Input-channel chunks (blockIdx.z of gridDim.z) write disjoint columns, so
+// launches with few tiles spread them over blocks with the same sums.
 // LDS: the chunk's dz tile transposed [CO][kDztPitch], the input patch transposed
 // per channel [CC][rows][pitch] (pixels contiguous), and the wave-reduction area.
 template <int CIN, int COUT, int CO_ = co_chunk(COUT)>
@@ -573,7 +575,8 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16* __restrict__ dz, cons
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, r16 = lane & 15;
     const u32x4 zero = {0u, 0u, 0u, 0u};
-    for (int ch = 0; ch < Geo::NCH; ++ch) {
+    const int nch = Geo::NCH / gridDim.z;   // the launcher makes it divide
+    for (int ch = blockIdx.z * nch; ch < (blockIdx.z + 1) * nch; ++ch) {
         const int c0 = ch * CC;
         f32x4 acc[MT][GPW][3];
 #pragma unroll
@@ -1609,8 +1612,11 @@ bool launch_wgrad_co(const bf16* dz, const bf16* in, float* part, int S, int nb,
     using Geo = WgradGeo<CI, COUT, CO>;
     const size_t lds = (size_t)Geo::CO * kDztPitch * 2 + (size_t)Geo::CC * wg_plane(S) * 2 + Geo::red_bytes;
     if (lds > kLdsLimit) return false;
-    FMBYM_LAUNCH_LDS(kMWgrad, (k_wgrad<CI, COUT, CO>), dim3(nb, COUT / CO), dim3(256), lds, s, dz, in, part, S, tpb,
-                     tiles);
+    // input-channel chunks over blocks until the launch has kConvMinBlocks (a divisor of NCH)
+    int kz = 1;
+    while (kz * 2 <= Geo::NCH && Geo::NCH % (kz * 2) == 0 && nb * (COUT / CO) * kz < kConvMinBlocks) kz *= 2;
+    FMBYM_LAUNCH_LDS(kMWgrad, (k_wgrad<CI, COUT, CO>), dim3(nb, COUT / CO, kz), dim3(256), lds, s, dz, in, part, S,
+                     tpb, tiles);
     return true;
 }
 
