@@ -84,3 +84,40 @@ def segment_errors(gt, est, lengths=KITTI_LENGTHS_M, step: int = 10) -> dict:
         return dict(t_pct=None, r_deg_per_km=None, per_length=per, segments=0)
     return dict(t_pct=100.0 * float(np.mean(t_all)), r_deg_per_km=math.degrees(float(np.mean(r_all))) * 1000.0,
                 per_length=per, segments=len(t_all))
+
+
+def gate_outliers(rel, max_dtheta: float = math.radians(10.0), max_dt: float = 1.5, window: int = 5,
+                  max_run: int = 10):
+    """Replace pair poses that break a motion prior before chaining (an option:
+    the paper chains the search's poses as they are).
+
+    The prior of pair k is the component-wise median of the last ``window``
+    accepted pair poses (at the start, of the first ``window`` pair poses): the
+    vehicle's motion changes little between consecutive frames, while a pair
+    whose heading went to a spurious angular peak is tens of degrees off, its
+    translation with it.  A pair whose heading differs from the prior by more
+    than ``max_dtheta`` (rad) or whose translation differs by more than
+    ``max_dt`` (the pose's length unit) takes the prior's pose instead; after
+    ``max_run`` rejections in a row (2.5 s of scans at 4 Hz) the next pair is
+    accepted as it is and the prior starts again from it, so that a real change
+    of motion is followed.  Returns (gated poses [K - 1, 3],
+    rejected [K - 1] bool)."""
+    rel = np.asarray(rel, dtype=np.float64)
+    out = rel.copy()
+    rejected = np.zeros(len(rel), dtype=bool)
+    accepted = list(rel[:window])
+    run = 0
+    for k in range(len(rel)):
+        prior = np.median(np.asarray(accepted[-window:]), axis=0)
+        off = abs(_wrap(rel[k, 0] - prior[0])) > max_dtheta or math.hypot(*(rel[k, 1:] - prior[1:])) > max_dt
+        if off and run < max_run:
+            out[k] = prior
+            rejected[k] = True
+            run += 1
+            continue
+        if off:
+            accepted = [rel[k]]          # the motion changed: the prior starts again from here
+        elif k >= window:
+            accepted.append(rel[k])
+        run = 0
+    return out, rejected

@@ -51,6 +51,10 @@ def test_drive_odometry_matches_the_oracle():
           f"translation median {np.median(step_err):.3f} m; end point off by "
           f"{math.hypot(*(traj[-1, :2] - gt[-1, :2])):.2f} m after {len(gt)} frames; pairs within 2 bins "
           f"{(np.abs(est[:, 0] - rel[:, 0]) <= 2 * math.pi / kw['n_theta']).mean():.2f}", flush=True)
+    gated, rejected = odometry.gate_outliers(est)
+    eg = odometry.segment_errors(gt, odometry.chain(gated), lengths=(50, 100, 200))
+    print(f"with the outlier gate: {int(rejected.sum())} pairs replaced, drift {eg['t_pct']:.2f} % "
+          f"{eg['r_deg_per_km']:.1f} deg/km", flush=True)
     step = math.pi / kw["n_theta"]
     assert (np.abs(est[:, 0] - rel[:, 0]) <= 2 * step).mean() >= 0.85
     assert np.median(step_err) <= 2 * kw["delta_xy"]

@@ -79,3 +79,46 @@ def test_drive_pairs_follow_the_search_convention():
         est = O.search(scans[k], scans[k + 1], p)["pose"].numpy()
         assert abs(est[0] - rel[k, 0]) <= math.pi / 256, (k, est, rel[k])
         assert math.hypot(est[1] - rel[k, 1], est[2] - rel[k, 2]) <= 3 * 0.35, (k, est, rel[k])
+
+
+def test_outlier_gate_keeps_the_generated_motion():
+    """The generator turns by a damped random walk of at most a few degrees
+    per frame at 2-3 m per frame: no true pair pose breaks the gate."""
+    for name in ("drive256", "drive512"):
+        _, _, rel = synth.make_drive(name, scans=False)
+        gated, rejected = odometry.gate_outliers(rel)
+        assert not rejected.any()
+        np.testing.assert_array_equal(gated, rel)
+
+
+def test_outlier_gate_replaces_exactly_the_planted_outliers():
+    """Pairs sent to a spurious heading peak (tens of degrees off, their
+    translation metres off) are replaced, including the first pair and two in
+    a row; the gated trajectory's drift falls back near the true one's."""
+    _, gt, rel = synth.make_drive("drive512", scans=False)
+    bad = [0, 37, 38, 150, 260, 399]
+    est = rel.copy()
+    for j, k in enumerate(bad):
+        est[k, 0] += math.radians(25.0 if j % 2 == 0 else -40.0)
+        est[k, 1] += 4.0
+        est[k, 2] -= 3.0
+    gated, rejected = odometry.gate_outliers(est)
+    assert np.nonzero(rejected)[0].tolist() == bad
+    keep = np.setdiff1d(np.arange(len(rel)), bad)
+    np.testing.assert_array_equal(gated[keep], est[keep])
+    # a replaced pair takes the median of its neighbours' motion
+    assert np.abs(gated[bad, 0] - rel[bad, 0]).max() < math.radians(6.0)
+    assert np.hypot(*(gated[bad, 1:] - rel[bad, 1:]).T).max() < 1.0
+    raw = odometry.segment_errors(gt, odometry.chain(est))
+    fixed = odometry.segment_errors(gt, odometry.chain(gated))
+    assert fixed["t_pct"] < 0.2 * raw["t_pct"] and fixed["r_deg_per_km"] < 0.2 * raw["r_deg_per_km"]
+
+
+def test_outlier_gate_follows_a_real_change_of_motion():
+    """A step change of the motion lasting longer than max_run pairs is
+    rejected max_run times, then accepted and followed."""
+    rel = np.tile([0.0, -2.5, 0.0], (30, 1))
+    rel[10:, 0] = math.radians(15.0)
+    gated, rejected = odometry.gate_outliers(rel, max_run=3)
+    assert np.nonzero(rejected)[0].tolist() == [10, 11, 12]
+    np.testing.assert_array_equal(gated[13:], rel[13:])
