@@ -592,7 +592,7 @@ def drive_bench(args) -> int:
 
     cfg = workloads.DRIVE[args.workload]
     kw = workloads.search_kwargs(cfg["search"])
-    scans_np, gt, _ = synth.make_drive(cfg["drive"], split="bench")
+    scans_np, gt, rel_true = synth.make_drive(cfg["drive"], split="bench")
     dev = torch.device("cuda:0")
     S = torch.from_numpy(scans_np).to(dev)
     P = len(scans_np) - 1
@@ -614,6 +614,17 @@ def drive_bench(args) -> int:
     drift = odometry.segment_errors(gt, odometry.chain(rel))
     gated, rejected = odometry.gate_outliers(rel)
     drift_gated = odometry.segment_errors(gt, odometry.chain(gated))
+    # the same drive under the alternative readings of the scores (untimed)
+    readings = {}
+    for name, opt in (("hard_argmax", dict(hard_argmax=True)), ("logit_zscore", dict(zscore=True))):
+        sr = fmbym.Search(max_batch=P, **kw, **opt)
+        r = sr.forward(f, g, surfaces=False)["pose"].double().cpu().numpy()
+        torch.cuda.synchronize()
+        sr.close()
+        e = odometry.segment_errors(gt, odometry.chain(r))
+        t_err = np.hypot(*(r[:, 1:] - rel_true[:, 1:]).T)
+        readings[name] = {"t_pct": e["t_pct"], "r_deg_per_km": e["r_deg_per_km"],
+                          "pairs_t_err_over_1m": float((t_err > 1.0).mean())}
     pass_bytes = 92 * n * n * P
     res = {
         "metric": f"scan-pairs/sec, {n}^2 radar odometry (forward search over a drive's consecutive pairs), 1 GPU",
@@ -635,6 +646,8 @@ def drive_bench(args) -> int:
         # option beside the paper's chaining: pairs off the motion prior replaced
         "drift_gated": {"t_pct": drift_gated["t_pct"], "r_deg_per_km": drift_gated["r_deg_per_km"],
                         "segments": drift_gated["segments"], "rejected_pairs": int(rejected.sum())},
+        "drift_readings": readings,
+        "pairs_t_err_over_1m": float((np.hypot(*(rel[:, 1:] - rel_true[:, 1:]).T) > 1.0).mean()),
         "tuning": tuning,
     }
     if not args.no_cpu_baseline:
