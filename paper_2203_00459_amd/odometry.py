@@ -98,7 +98,7 @@ def gate_outliers(rel, max_dtheta: float = math.radians(10.0), max_dt: float = 1
     translation with it.  A pair whose heading differs from the prior by more
     than ``max_dtheta`` (rad) or whose translation differs by more than
     ``max_dt`` (the pose's length unit) takes the prior's pose instead; after
-    ``max_run`` rejections in a row (2.5 s of scans at 4 Hz) the next pair is
+    ``max_run`` rejections in a row (by default 10: 2.5 s of scans at 4 Hz) the next pair is
     accepted as it is and the prior starts again from it, so that a real change
     of motion is followed.  Returns (gated poses [K - 1, 3],
     rejected [K - 1] bool)."""

@@ -122,3 +122,13 @@ def test_outlier_gate_follows_a_real_change_of_motion():
     gated, rejected = odometry.gate_outliers(rel, max_run=3)
     assert np.nonzero(rejected)[0].tolist() == [10, 11, 12]
     np.testing.assert_array_equal(gated[13:], rel[13:])
+
+
+def test_outlier_gate_on_short_and_empty_lists():
+    """Fewer pairs than the prior's window, and none at all."""
+    gated, rejected = odometry.gate_outliers(np.zeros((0, 3)))
+    assert gated.shape == (0, 3) and rejected.shape == (0,)
+    rel = np.array([[0.0, -2.5, 0.0], [0.0, -2.4, 0.1], [math.radians(30.0), 2.0, 0.0]])
+    gated, rejected = odometry.gate_outliers(rel)
+    assert rejected.tolist() == [False, False, True]
+    np.testing.assert_array_equal(gated[2], np.median(rel, axis=0))
